@@ -1,0 +1,204 @@
+/*
+ * qmc.h -- C ABI of the MI355X particle-by-particle VMC library.
+ *
+ * The library runs the hot path of real-space variational Monte Carlo as
+ * the QMCPACK overview paper (arXiv:1802.06922) defines it: walkers are
+ * independent Markov chains sampling |Psi_T|^2 (section "Variational Monte
+ * Carlo"); each sweep moves every electron once, in order, with a Gaussian
+ * proposal and the Metropolis acceptance (section "Trial Moves", equations
+ * trans_prob_alle and accept_reject); Psi_T = D_up D_dn exp(J) (equation
+ * eq:msdj with one determinant) with orbitals from a periodic tricubic
+ * B-spline table (section "B-spline basis sets"), single-row inverse updates
+ * (section "Multi-Determinant Slater-Jastrow Form") and one- and two-body
+ * Jastrow factors (section "Jastrow factors"); the local energy is kinetic
+ * plus Ewald-summed Coulomb terms (section "Hamiltonian", equation
+ * vmc:electron_ham).
+ *
+ * Conventions for every call:
+ *  - Returns a qmc_status; never aborts.  qmc_last_error() gives a message.
+ *  - Host input arrays are read (and copied where kept) before the call
+ *    returns; the caller keeps ownership.  Device state belongs to the
+ *    library until qmc_destroy_system().  Output buffers belong to the caller.
+ *  - All device work is issued on the stream given at creation (NULL = the
+ *    default stream).  Calls that return host data synchronise that stream;
+ *    asynchronous device errors surface at the next synchronising call.
+ *  - One handle is driven by one host thread at a time; distinct handles may
+ *    be used concurrently.  Results depend only on (desc, table, seed,
+ *    walker count), never on other handles sharing the GPU.
+ *  - Positions are in bohr, stored wrapped into the cubic cell [0, L)^3.
+ *    Electrons 0..n_up-1 are spin up, n_up..n_up+n_dn-1 spin down.
+ */
+#ifndef QMC_H
+#define QMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qmc_system_s* qmc_system;   /* opaque; owned by the library */
+
+typedef enum {
+    QMC_OK = 0,
+    QMC_ERR_ARG = 1,       /* invalid argument or inconsistent sizes */
+    QMC_ERR_OOM = 2,       /* device memory (or the caller's arena) exhausted */
+    QMC_ERR_SINGULAR = 3,  /* a Slater matrix had a zero pivot */
+    QMC_ERR_DEVICE = 4,    /* a HIP runtime error */
+    QMC_ERR_STATE = 5,     /* call out of order (e.g. sweep before init_walkers) */
+    QMC_ERR_NUMERIC = 6    /* a non-finite local energy was produced (written as NaN) */
+} qmc_status;
+
+typedef enum { QMC_FP64 = 0, QMC_MIXED = 1 } qmc_precision;
+typedef enum { QMC_J_NONE = 0, QMC_J_PADE = 1, QMC_J_BSPLINE = 2 } qmc_jastrow_kind;
+typedef enum { QMC_H_KINETIC = 0, QMC_H_COULOMB_EWALD = 1 } qmc_hamiltonian;
+
+#define QMC_MAX_KNOTS 32     /* largest B-spline Jastrow M (free control points) */
+
+/*
+ * System description (section "Jastrow factors" for the radial functions;
+ * section "Hamiltonian" for the ions).  Copied by qmc_create_system().
+ *
+ *  n_up, n_dn     electrons per spin (n_up >= 1, n_dn >= 0, n_up+n_dn <= 1024)
+ *  L              cubic cell side (bohr)
+ *  n_ions, ion_pos[3*n_ions], ion_Z[n_ions]   host arrays; may be 0/NULL
+ *  precision      QMC_FP64: table, orbital values and inverse in FP64.
+ *                 QMC_MIXED: FP32 table, values, ratios and inverse; FP64
+ *                 positions, Jastrow, log-determinant and energy sums.
+ *  delay_rank     1 = Sherman-Morrison after every accepted move
+ *  recompute_period  sweeps between full FP64 inverse rebuilds (0 = never)
+ *  sigma          Gaussian proposal width (bohr); the transition probability
+ *                 has no drift, so it cancels in the acceptance
+ *  seed           key of the Philox4x32-10 streams; the numbers for electron
+ *                 i of walker w in sweep s depend only on (seed, w, s, i)
+ *  hamiltonian    QMC_H_KINETIC or QMC_H_COULOMB_EWALD
+ *  j2_kind        two-body radial function, used for every electron pair:
+ *                 PADE: j2_params = {a, b}, j2_n = 2, u = a r / (1 + b r),
+ *                 no cutoff (minimum-image distance).
+ *                 BSPLINE: j2_params = p_1..p_M (j2_n = M <= QMC_MAX_KNOTS),
+ *                 cutoff j2_rcut, u(r) = sum_m p_m B3(r M / rcut - m) with
+ *                 p_0 = p_2 - 2 (rcut / M) u'(0); u'(0) = j2_cusp_same for
+ *                 equal spins and j2_cusp_opp for opposite spins.
+ *  j1_kind        one-body (electron-ion) radial function, NONE or BSPLINE
+ *                 (j1_params = p_1..p_M, j1_rcut, cusp j1_cusp)
+ *  tie_guard      MIXED only: relative half-width of the band around each
+ *                 acceptance threshold inside which the decision is re-taken
+ *                 in FP64 (0 = library default 1e-3)
+ *  arena, arena_bytes  optional caller-owned device memory (e.g. from the
+ *                 PyTorch caching allocator).  If arena != NULL every device
+ *                 buffer of the handle is carved from it and nothing is
+ *                 allocated; size it with qmc_estimate_device_bytes().
+ */
+typedef struct {
+    int32_t n_up, n_dn;
+    double L;
+    int32_t n_ions;
+    const double* ion_pos;
+    const double* ion_Z;
+    int32_t precision;
+    int32_t delay_rank;
+    int32_t recompute_period;
+    double sigma;
+    uint64_t seed;
+    int32_t hamiltonian;
+    int32_t j2_kind;
+    const double* j2_params;
+    int32_t j2_n;
+    double j2_rcut;
+    double j2_cusp_same;
+    double j2_cusp_opp;
+    int32_t j1_kind;
+    const double* j1_params;
+    int32_t j1_n;
+    double j1_rcut;
+    double j1_cusp;
+    double tie_guard;
+    void* arena;
+    size_t arena_bytes;
+} qmc_system_desc;
+
+/* Create a handle.  hip_stream: a hipStream_t (e.g. PyTorch's current
+ * stream) or NULL.  Uses the device current at the call.  Errors: ARG for
+ * invalid sizes or parameters, DEVICE, OOM. */
+qmc_status qmc_create_system(const qmc_system_desc* desc, void* hip_stream, qmc_system* out);
+
+/* Upload the orbital table (section "B-spline basis sets": 64 coefficients
+ * per orbital per evaluation).  Layout [gx][gy][gz][n_orb], C order, the
+ * coefficient of knot (ix, iy, iz) multiplying the tensor product of uniform
+ * cubic B-splines centred on that knot; the grid is periodic with spacing
+ * L/gx, L/gy, L/gz.  dtype: 8 (double) or 4 (float).  coefs_on_device: 0 =
+ * host pointer, 1 = device pointer.  The data are copied (converted to the
+ * handle's precision).  Errors: ARG if n_orb != max(n_up, n_dn), a grid side
+ * < 4, or dtype not 4/8; OOM; DEVICE. */
+qmc_status qmc_load_spline_table(qmc_system s, int32_t gx, int32_t gy, int32_t gz, int32_t n_orb,
+                                 const void* coefs, int32_t dtype, int32_t coefs_on_device);
+
+/* Create n_walkers walkers (>= 1).  pos: host [n_walkers][N][3] or NULL;
+ * NULL draws uniform positions in the cell from the INIT stream of each
+ * walker.  Builds the Slater matrices, inverts them in FP64 (Gauss-Jordan
+ * with partial pivoting) and resets the sweep counter to 0.  Errors: STATE
+ * without a table; ARG; OOM; SINGULAR if any Slater matrix has a zero pivot
+ * (the walkers are then unusable until re-initialised). */
+qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos);
+
+/* Run n_sweeps particle-by-particle sweeps of every walker.  Each sweep
+ * proposes every electron once, in index order, and accepts with
+ * probability min(1, R^2 exp(2 dJ)), R the determinant ratio and dJ the
+ * Jastrow change.  n_accepted_out (nullable; non-NULL synchronises): total
+ * accepted moves over all walkers and these sweeps.  Errors: STATE before
+ * init_walkers; DEVICE. */
+qmc_status qmc_sweep(qmc_system s, int32_t n_sweeps, uint64_t* n_accepted_out);
+
+/* Local energy of every walker at its current configuration (section
+ * "Hamiltonian": E_L = sum_n Psi^-1 H_n Psi).  out[W][4] = (kinetic,
+ * electron-electron, electron-ion, ion-ion) in hartree; the Coulomb parts
+ * are Ewald sums with a uniform neutralising background where the charge
+ * does not cancel, each independent of the Ewald splitting.  out_on_device:
+ * 0 = host buffer (synchronises), 1 = device buffer (asynchronous).
+ * Errors: STATE; DEVICE; NUMERIC (host output only) if a value is not finite. */
+qmc_status qmc_measure_local_energy(qmc_system s, double* out, int32_t out_on_device);
+
+/* Copy walker state to host buffers (each nullable): pos[W][N][3];
+ * logabs_det[W][2] = log|D_up|, log|D_dn| accumulated as the sum of
+ * log|R| of the accepted moves since the last full inverse; sign[W][2]. */
+qmc_status qmc_get_walkers(qmc_system s, double* pos, double* logabs_det, int32_t* sign);
+
+/* Accept flags of the last sweep, host [W][N], 1 = accepted. */
+qmc_status qmc_get_accept_log(qmc_system s, uint8_t* bits);
+
+/* Rebuild every inverse from scratch in FP64 and reset log|D|.  drift_out
+ * (nullable, host [W][2]): accumulated log|D| minus the rebuilt one. */
+qmc_status qmc_recompute(qmc_system s, double* drift_out);
+
+/* Diagnostic: value, gradient (x, y, z) and Laplacian of every orbital at n
+ * host positions pos[n][3], written to host out[n][5][n_orb] in FP64. */
+qmc_status qmc_eval_spo_vgl(qmc_system s, int32_t n, const double* pos, double* out);
+
+/* Kernel timing: when enabled, every launch of each kernel class is
+ * bracketed by HIP events on the handle's stream.  Classes: 0 = orbital
+ * gather (proposal + spline VGL), 1 = move chain (ratio, Jastrow, accept,
+ * inverse update), 2 = measurement (kinetic + Ewald), 3 = inverse rebuild.
+ * qmc_kernel_timing synchronises and returns the summed milliseconds and the
+ * launch count since the last reset (reset = 1 clears them). */
+qmc_status qmc_set_timing(qmc_system s, int32_t enable);
+qmc_status qmc_kernel_timing(qmc_system s, int32_t kernel_class, double* total_ms, int64_t* launches,
+                             int32_t reset);
+
+/* Free every device buffer of the handle and the handle itself. */
+qmc_status qmc_destroy_system(qmc_system s);
+
+/* Message of the last error of s (NULL: of the last failed call on this
+ * thread).  Valid until the next call on the same handle/thread. */
+const char* qmc_last_error(qmc_system s);
+
+/* Device bytes a handle needs for desc, n_walkers walkers and a gx*gy*gz
+ * table (n_orb = max(n_up, n_dn)), including alignment; 0 for invalid input. */
+size_t qmc_estimate_device_bytes(const qmc_system_desc* desc, int32_t n_walkers, int32_t gx,
+                                 int32_t gy, int32_t gz);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QMC_H */

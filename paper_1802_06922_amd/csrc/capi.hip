@@ -1,0 +1,722 @@
+// capi.hip -- the C ABI (include/qmc.h): handle lifetime, device memory,
+// set-up tables and the launch sequence of each entry point.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qmc_kernels.hpp"
+
+using namespace qmc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// Device memory of a handle: either hipMalloc'd buffers or a bump region of
+// the caller's arena.  mark()/release_to() let the walker region be rebuilt.
+struct DeviceMemory {
+  char* arena = nullptr;
+  size_t arena_bytes = 0, used = 0;
+  struct Block { void* p; size_t mark; };
+  std::vector<Block> blocks;
+  hipError_t last = hipSuccess;
+
+  void* alloc(size_t bytes) {
+    bytes = align_up(bytes ? bytes : 1);
+    if (arena) {
+      if (used + bytes > arena_bytes) return nullptr;
+      void* p = arena + used;
+      blocks.push_back({p, used});
+      used += bytes;
+      return p;
+    }
+    void* p = nullptr;
+    last = hipMalloc(&p, bytes);
+    if (last != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+    blocks.push_back({p, used});
+    used += bytes;
+    return p;
+  }
+  size_t mark() const { return blocks.size(); }
+  void release_to(size_t m) {
+    while (blocks.size() > m) {
+      Block b = blocks.back();
+      blocks.pop_back();
+      if (!arena) (void)hipFree(b.p);
+      used = b.mark;
+    }
+  }
+};
+
+struct TimerClass {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> live, pool;
+  double ms = 0.0;
+  int64_t launches = 0;
+};
+
+size_t tsize_of(int precision) { return precision == QMC_MIXED ? sizeof(float) : sizeof(double); }
+
+int padded_stride(int n_orb, int precision) {
+  const int v = precision == QMC_MIXED ? 4 : 2;   // 16-byte vectors
+  return (n_orb + v - 1) / v * v;
+}
+
+}  // namespace
+
+struct qmc_system_s {
+  qmc_system_desc d{};
+  std::vector<double> ions4;             // [n_ions][4]
+  std::vector<double> j2p, j1p;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+  DeviceMemory mem;
+  size_t mark_sys = 0, mark_table = 0;
+  SysParams P{};
+  EwaldParams E{};
+  double* d_ions = nullptr;
+  double* d_gvec = nullptr;
+  double* d_sion = nullptr;
+  void* d_table = nullptr;
+  bool has_table = false, has_walkers = false;
+  uint32_t sweep_index = 0;
+  // walker buffers (untyped; T per precision)
+  double* pos = nullptr;
+  double* prop = nullptr;
+  void* vgl = nullptr;
+  uint8_t* cur = nullptr;
+  void* binv = nullptr;
+  double* logdet = nullptr;
+  int* sign = nullptr;
+  uint8_t* acc = nullptr;
+  uint32_t* nacc = nullptr;
+  int* status = nullptr;
+  double* scratch = nullptr;
+  double* drift = nullptr;
+  double* energy = nullptr;
+  bool timing = false;
+  TimerClass timers[4];
+};
+
+namespace {
+
+qmc_status fail(qmc_system s, qmc_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  if (s) s->err = buf;
+  return st;
+}
+
+#define HIP_TRY(s, expr)                                                                     \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail((s), QMC_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+  } while (0)
+
+template <typename T>
+Walkers<T> walkers_of(qmc_system s) {
+  Walkers<T> w;
+  w.pos = s->pos; w.prop = s->prop; w.vgl = static_cast<T*>(s->vgl); w.cur = s->cur;
+  w.binv = static_cast<T*>(s->binv); w.logdet = s->logdet; w.sign = s->sign; w.acc = s->acc;
+  w.nacc = s->nacc; w.status = s->status;
+  return w;
+}
+
+// Event-bracketed launch: f() issues the kernel on s->stream.
+template <typename F>
+hipError_t timed(qmc_system s, int cls, F&& f) {
+  if (!s->timing) return f();
+  TimerClass& tc = s->timers[cls];
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  if (!tc.pool.empty()) { ev = tc.pool.back(); tc.pool.pop_back(); }
+  else {
+    hipError_t e = hipEventCreate(&ev.first);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&ev.second);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = hipEventRecord(ev.first, s->stream);
+  if (e != hipSuccess) return e;
+  e = f();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(ev.second, s->stream);
+  tc.live.push_back(ev);
+  return e;
+}
+
+void build_radial(Radial& R, int kind, const double* p, int M, double rc, double cusp, double a, double b) {
+  std::memset(&R, 0, sizeof R);
+  R.kind = kind;
+  if (kind == QMC_J_PADE) { R.a = a; R.b = b; }
+  if (kind == QMC_J_BSPLINE) {
+    R.M = M;
+    R.rc = rc;
+    R.inv_delta = M / rc;
+    for (int m = 1; m <= M; ++m) R.p[m] = p[m - 1];
+    R.p[0] = R.p[2] - 2.0 * (rc / M) * cusp;   // u'(0) = (p_2 - p_0) / (2 rc / M)
+  }
+}
+
+// Ewald tables: splitting kappa = 4 / L, real space over the 27 nearest
+// images (every image closer than 1.5 L), reciprocal vectors of one half
+// space with G^2 / (4 kappa^2) <= 40.
+void ewald_setup(qmc_system s, std::vector<double>& gvec, std::vector<double>& sion) {
+  const double L = s->d.L, V = L * L * L;
+  const double kappa = 4.0 / L;
+  const double g0 = 2.0 * kPi / L;
+  const double gmax2 = 40.0 * 4.0 * kappa * kappa;
+  const int mmax = (int)std::ceil(std::sqrt(gmax2) / g0);
+  const int M = s->d.n_ions;
+  for (int a = 0; a <= mmax; ++a)
+    for (int b = -mmax; b <= mmax; ++b)
+      for (int c = -mmax; c <= mmax; ++c) {
+        if (a == 0 && (b < 0 || (b == 0 && c <= 0))) continue;   // one of each +-G pair
+        const double Gx = g0 * a, Gy = g0 * b, Gz = g0 * c;
+        const double G2 = Gx * Gx + Gy * Gy + Gz * Gz;
+        if (G2 > gmax2) continue;
+        gvec.push_back(Gx); gvec.push_back(Gy); gvec.push_back(Gz);
+        gvec.push_back(4.0 * kPi / V * std::exp(-G2 / (4.0 * kappa * kappa)) / G2);
+        double re = 0.0, im = 0.0;
+        for (int I = 0; I < M; ++I) {
+          const double ph = Gx * s->ions4[4 * I] + Gy * s->ions4[4 * I + 1] + Gz * s->ions4[4 * I + 2];
+          re += s->ions4[4 * I + 3] * std::cos(ph);
+          im += s->ions4[4 * I + 3] * std::sin(ph);
+        }
+        sion.push_back(re); sion.push_back(im);
+      }
+  // self-image sum: sum_{n != 0} erfc(kappa |n| L) / (|n| L)
+  double simg = 0.0;
+  for (int a = -2; a <= 2; ++a)
+    for (int b = -2; b <= 2; ++b)
+      for (int c = -2; c <= 2; ++c) {
+        if (!a && !b && !c) continue;
+        const double r = L * std::sqrt((double)(a * a + b * b + c * c));
+        simg += std::erfc(kappa * r) / r;
+      }
+  const double N = s->d.n_up + s->d.n_dn;
+  double Zt = 0.0, Z2 = 0.0;
+  for (int I = 0; I < M; ++I) { Zt += s->ions4[4 * I + 3]; Z2 += s->ions4[4 * I + 3] * s->ions4[4 * I + 3]; }
+  s->E.kappa = kappa;
+  s->E.rcut = 1.5 * L;
+  s->E.n_g = (int)(gvec.size() / 4);
+  s->E.c_ee = -kappa / std::sqrt(kPi) * N + 0.5 * N * simg - kPi * N * N / (2.0 * V * kappa * kappa);
+  s->E.c_ei = kPi * N * Zt / (V * kappa * kappa);
+  // ions alone: pairs over the 27 nearest images, reciprocal, self and background
+  double vii = 0.0;
+  for (int I = 0; I < M; ++I)
+    for (int J = 0; J < M; ++J) {
+      if (I == J) continue;
+      double d[3];
+      for (int k = 0; k < 3; ++k) {
+        const double x = s->ions4[4 * I + k] - s->ions4[4 * J + k];
+        d[k] = x - L * std::rint(x / L);
+      }
+      for (int a = -1; a <= 1; ++a)
+        for (int b = -1; b <= 1; ++b)
+          for (int c = -1; c <= 1; ++c) {
+            const double x = d[0] + a * L, y = d[1] + b * L, z = d[2] + c * L;
+            const double r = std::sqrt(x * x + y * y + z * z);
+            if (r < s->E.rcut) vii += 0.5 * s->ions4[4 * I + 3] * s->ions4[4 * J + 3] * std::erfc(kappa * r) / r;
+          }
+    }
+  for (size_t g = 0; g < sion.size() / 2; ++g)
+    vii += gvec[4 * g + 3] * (sion[2 * g] * sion[2 * g] + sion[2 * g + 1] * sion[2 * g + 1]);
+  vii += -kappa / std::sqrt(kPi) * Z2 + 0.5 * Z2 * simg - kPi * Zt * Zt / (2.0 * V * kappa * kappa);
+  s->E.v_ii = M ? vii : 0.0;
+}
+
+void free_walkers(qmc_system s) {
+  s->mem.release_to(s->mark_table);
+  s->has_walkers = false;
+  s->pos = s->prop = nullptr;
+  s->vgl = s->binv = nullptr;
+  s->cur = s->acc = nullptr;
+  s->logdet = s->scratch = s->drift = s->energy = nullptr;
+  s->sign = s->status = nullptr;
+  s->nacc = nullptr;
+}
+
+struct WalkerSizes {
+  size_t pos, prop, vgl, cur, binv, logdet, sign, acc, nacc, status, scratch, drift, energy;
+  size_t total() const {
+    return align_up(pos) + align_up(prop) + align_up(vgl) + align_up(cur) + align_up(binv) +
+           align_up(logdet) + align_up(sign) + align_up(acc) + align_up(nacc) + align_up(status) +
+           align_up(scratch) + align_up(drift) + align_up(energy);
+  }
+};
+
+WalkerSizes walker_sizes(int n_up, int n_dn, int precision, int W, int n_orb) {
+  const size_t N = (size_t)n_up + n_dn, S = padded_stride(n_orb, precision), ts = tsize_of(precision);
+  const size_t bs = (size_t)n_up * n_up + (size_t)n_dn * n_dn;
+  WalkerSizes z;
+  z.pos = W * N * 3 * sizeof(double);
+  z.prop = W * N * 4 * sizeof(double);
+  z.vgl = 2 * W * N * kComp * S * ts;
+  z.cur = W * N;
+  z.binv = W * bs * ts;
+  z.logdet = W * 2 * sizeof(double);
+  z.sign = W * 2 * sizeof(int);
+  z.acc = W * N;
+  z.nacc = W * sizeof(uint32_t);
+  z.status = W * sizeof(int);
+  z.scratch = W * bs * sizeof(double);
+  z.drift = W * 2 * sizeof(double);
+  z.energy = W * 4 * sizeof(double);
+  return z;
+}
+
+size_t system_bytes(const qmc_system_desc* d) {
+  // ions + Ewald tables (upper bound on the reciprocal list)
+  const double kappa_L = 4.0;
+  const int mmax = (int)std::ceil(std::sqrt(160.0) * kappa_L / (2.0 * kPi));
+  const size_t ng = (size_t)(mmax + 1) * (2 * mmax + 1) * (2 * mmax + 1);
+  return align_up((size_t)(d->n_ions > 0 ? d->n_ions : 1) * 4 * sizeof(double)) +
+         align_up(ng * 4 * sizeof(double)) + align_up(ng * 2 * sizeof(double));
+}
+
+qmc_status validate(const qmc_system_desc* d) {
+  if (!d) return fail(nullptr, QMC_ERR_ARG, "desc is NULL");
+  if (d->n_up < 1 || d->n_dn < 0 || d->n_up + d->n_dn > 1024)
+    return fail(nullptr, QMC_ERR_ARG, "need n_up >= 1, n_dn >= 0, n_up + n_dn <= 1024");
+  if (!(d->L > 0.0) || !std::isfinite(d->L)) return fail(nullptr, QMC_ERR_ARG, "L must be positive");
+  if (!(d->sigma > 0.0)) return fail(nullptr, QMC_ERR_ARG, "sigma must be positive");
+  if (d->precision != QMC_FP64 && d->precision != QMC_MIXED)
+    return fail(nullptr, QMC_ERR_ARG, "unknown precision %d", d->precision);
+  if (d->delay_rank != 1 && d->delay_rank != 0)
+    return fail(nullptr, QMC_ERR_ARG, "delay_rank %d: only 1 (Sherman-Morrison) is available", d->delay_rank);
+  if (d->recompute_period < 0) return fail(nullptr, QMC_ERR_ARG, "recompute_period must be >= 0");
+  if (d->hamiltonian != QMC_H_KINETIC && d->hamiltonian != QMC_H_COULOMB_EWALD)
+    return fail(nullptr, QMC_ERR_ARG, "unknown hamiltonian %d", d->hamiltonian);
+  if (d->n_ions < 0 || (d->n_ions > 0 && (!d->ion_pos || !d->ion_Z)))
+    return fail(nullptr, QMC_ERR_ARG, "n_ions > 0 needs ion_pos and ion_Z");
+  if (d->n_ions > 4096) return fail(nullptr, QMC_ERR_ARG, "at most 4096 ions");
+  auto check_j = [&](int kind, const double* p, int n, double rc, const char* nm) -> qmc_status {
+    if (kind == QMC_J_NONE) return QMC_OK;
+    if (kind == QMC_J_PADE) {
+      if (!p || n != 2) return fail(nullptr, QMC_ERR_ARG, "%s Pade needs params {a, b}", nm);
+      return QMC_OK;
+    }
+    if (kind == QMC_J_BSPLINE) {
+      if (!p || n < 2 || n > QMC_MAX_KNOTS)
+        return fail(nullptr, QMC_ERR_ARG, "%s B-spline needs 2..%d control points", nm, QMC_MAX_KNOTS);
+      if (!(rc > 0.0) || rc > 0.5 * d->L * (1.0 + 1e-12))
+        return fail(nullptr, QMC_ERR_ARG, "%s cutoff must be in (0, L/2]", nm);
+      return QMC_OK;
+    }
+    return fail(nullptr, QMC_ERR_ARG, "%s: unknown kind %d", nm, kind);
+  };
+  qmc_status st = check_j(d->j2_kind, d->j2_params, d->j2_n, d->j2_rcut, "j2");
+  if (st != QMC_OK) return st;
+  if (d->j1_kind == QMC_J_PADE) return fail(nullptr, QMC_ERR_ARG, "j1 supports NONE or BSPLINE");
+  st = check_j(d->j1_kind, d->j1_params, d->j1_n, d->j1_rcut, "j1");
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+qmc_status qmc_create_system(const qmc_system_desc* desc, void* hip_stream, qmc_system* out) {
+  if (!out) return fail(nullptr, QMC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  qmc_status st = validate(desc);
+  if (st != QMC_OK) return st;
+  qmc_system s = new (std::nothrow) qmc_system_s;
+  if (!s) return fail(nullptr, QMC_ERR_OOM, "host allocation failed");
+  s->d = *desc;
+  s->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return fail(nullptr, QMC_ERR_DEVICE, "no HIP device");
+  }
+  if (desc->arena) {
+    s->mem.arena = static_cast<char*>(desc->arena);
+    s->mem.arena_bytes = desc->arena_bytes;
+  }
+  const int M = desc->n_ions;
+  s->ions4.resize((size_t)(M > 0 ? M : 1) * 4, 0.0);
+  for (int I = 0; I < M; ++I) {
+    for (int k = 0; k < 3; ++k) {
+      const double x = desc->ion_pos[3 * I + k];
+      double y = x - desc->L * std::floor(x / desc->L);
+      if (y >= desc->L) y = 0.0;
+      s->ions4[4 * I + k] = y;
+    }
+    s->ions4[4 * I + 3] = desc->ion_Z[I];
+  }
+  // parameters copied into the handle
+  SysParams& P = s->P;
+  std::memset(&P, 0, sizeof P);
+  P.n_up = desc->n_up;
+  P.n_dn = desc->n_dn;
+  P.N = desc->n_up + desc->n_dn;
+  P.n_orb = desc->n_up > desc->n_dn ? desc->n_up : desc->n_dn;
+  P.S = padded_stride(P.n_orb, desc->precision);
+  P.n_ions = M;
+  P.bstride = desc->n_up * desc->n_up + desc->n_dn * desc->n_dn;
+  P.L = desc->L;
+  P.sigma = desc->sigma;
+  P.key0 = (uint32_t)desc->seed;
+  P.key1 = (uint32_t)(desc->seed >> 32);
+  const double* j2p = desc->j2_params;
+  build_radial(P.jas.same, desc->j2_kind, j2p, desc->j2_n, desc->j2_rcut, desc->j2_cusp_same,
+               j2p ? j2p[0] : 0.0, (j2p && desc->j2_n > 1) ? j2p[1] : 0.0);
+  build_radial(P.jas.opp, desc->j2_kind, j2p, desc->j2_n, desc->j2_rcut, desc->j2_cusp_opp,
+               j2p ? j2p[0] : 0.0, (j2p && desc->j2_n > 1) ? j2p[1] : 0.0);
+  build_radial(P.jas.ei, M > 0 ? desc->j1_kind : QMC_J_NONE, desc->j1_params, desc->j1_n,
+               desc->j1_rcut, desc->j1_cusp, 0.0, 0.0);
+  s->d.ion_pos = s->d.ion_Z = s->d.j2_params = s->d.j1_params = nullptr;
+  s->d.arena = nullptr;
+
+  s->d_ions = static_cast<double*>(s->mem.alloc(s->ions4.size() * sizeof(double)));
+  if (!s->d_ions) { qmc_destroy_system(s); return fail(nullptr, QMC_ERR_OOM, "device allocation (ions)"); }
+  if (hipMemcpyAsync(s->d_ions, s->ions4.data(), s->ions4.size() * sizeof(double), hipMemcpyHostToDevice,
+                     s->stream) != hipSuccess) {
+    qmc_destroy_system(s);
+    return fail(nullptr, QMC_ERR_DEVICE, "ion upload failed");
+  }
+  P.ions = s->d_ions;
+  s->E.enabled = desc->hamiltonian == QMC_H_COULOMB_EWALD;
+  if (s->E.enabled) {
+    std::vector<double> gvec, sion;
+    ewald_setup(s, gvec, sion);
+    s->d_gvec = static_cast<double*>(s->mem.alloc(gvec.size() * sizeof(double)));
+    s->d_sion = static_cast<double*>(s->mem.alloc(sion.size() * sizeof(double)));
+    if (!s->d_gvec || !s->d_sion) { qmc_destroy_system(s); return fail(nullptr, QMC_ERR_OOM, "device allocation (Ewald)"); }
+    if (hipMemcpyAsync(s->d_gvec, gvec.data(), gvec.size() * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync(s->d_sion, sion.data(), sion.size() * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess) {
+      qmc_destroy_system(s);
+      return fail(nullptr, QMC_ERR_DEVICE, "Ewald upload failed");
+    }
+    if (hipStreamSynchronize(s->stream) != hipSuccess) {
+      qmc_destroy_system(s);
+      return fail(nullptr, QMC_ERR_DEVICE, "stream synchronise failed");
+    }
+    s->E.gvec = s->d_gvec;
+    s->E.s_ion = s->d_sion;
+  } else if (hipStreamSynchronize(s->stream) != hipSuccess) {
+    qmc_destroy_system(s);
+    return fail(nullptr, QMC_ERR_DEVICE, "stream synchronise failed");
+  }
+  s->mark_sys = s->mem.mark();
+  s->mark_table = s->mark_sys;
+  *out = s;
+  return QMC_OK;
+}
+
+qmc_status qmc_load_spline_table(qmc_system s, int32_t gx, int32_t gy, int32_t gz, int32_t n_orb,
+                                 const void* coefs, int32_t dtype, int32_t coefs_on_device) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (n_orb != s->P.n_orb)
+    return fail(s, QMC_ERR_ARG, "n_orb %d must equal max(n_up, n_dn) = %d", n_orb, s->P.n_orb);
+  if (gx < 4 || gy < 4 || gz < 4 || (size_t)gx * gy * gz > (size_t)1 << 26)
+    return fail(s, QMC_ERR_ARG, "grid sides must be >= 4 (and the grid at most 2^26 points)");
+  if (dtype != 4 && dtype != 8) return fail(s, QMC_ERR_ARG, "dtype must be 4 or 8");
+  if (!coefs) return fail(s, QMC_ERR_ARG, "coefs is NULL");
+  HIP_TRY(s, hipSetDevice(s->device));
+  free_walkers(s);
+  s->mem.release_to(s->mark_sys);
+  s->has_table = false;
+  const size_t pts = (size_t)gx * gy * gz;
+  const int S = s->P.S;
+  const size_t ts = tsize_of(s->d.precision);
+  s->d_table = s->mem.alloc(pts * S * ts);
+  if (!s->d_table) return fail(s, QMC_ERR_OOM, "device allocation of the %zu-byte table failed", pts * S * ts);
+  // Convert/pad on the host: the padded orbital columns are zero.
+  const bool same = (size_t)dtype == ts && S == n_orb;
+  if (same) {
+    HIP_TRY(s, hipMemcpyAsync(s->d_table, coefs, pts * S * ts,
+                              coefs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+  } else {
+    std::vector<unsigned char> src;
+    const unsigned char* hs = static_cast<const unsigned char*>(coefs);
+    if (coefs_on_device) {
+      src.resize(pts * n_orb * dtype);
+      HIP_TRY(s, hipMemcpy(src.data(), coefs, src.size(), hipMemcpyDeviceToHost));
+      hs = src.data();
+    }
+    const size_t chunk = 1 << 16;   // points per staging chunk
+    std::vector<unsigned char> stage(chunk * S * ts);
+    for (size_t p0 = 0; p0 < pts; p0 += chunk) {
+      const size_t np = std::min(chunk, pts - p0);
+      std::memset(stage.data(), 0, np * S * ts);
+      for (size_t p = 0; p < np; ++p)
+        for (int j = 0; j < n_orb; ++j) {
+          const size_t si = (p0 + p) * n_orb + j;
+          const double v = dtype == 8 ? reinterpret_cast<const double*>(hs)[si]
+                                      : (double)reinterpret_cast<const float*>(hs)[si];
+          if (ts == 8) reinterpret_cast<double*>(stage.data())[p * S + j] = v;
+          else reinterpret_cast<float*>(stage.data())[p * S + j] = (float)v;
+        }
+      HIP_TRY(s, hipMemcpy(static_cast<char*>(s->d_table) + p0 * S * ts, stage.data(), np * S * ts,
+                           hipMemcpyHostToDevice));
+    }
+  }
+  s->P.gx = gx;
+  s->P.gy = gy;
+  s->P.gz = gz;
+  s->has_table = true;
+  s->mark_table = s->mem.mark();
+  return QMC_OK;
+}
+
+static qmc_status run_rebuild(qmc_system s, double* drift_dev) {
+  hipError_t e;
+  if (s->d.precision == QMC_MIXED)
+    e = timed(s, 3, [&] { return launch_rebuild<float>(s->P, walkers_of<float>(s), s->scratch, drift_dev, s->stream); });
+  else
+    e = timed(s, 3, [&] { return launch_rebuild<double>(s->P, walkers_of<double>(s), s->scratch, drift_dev, s->stream); });
+  if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "inverse rebuild launch: %s", hipGetErrorString(e));
+  return QMC_OK;
+}
+
+static qmc_status check_singular(qmc_system s) {
+  std::vector<int> st(s->P.W);
+  HIP_TRY(s, hipMemcpyAsync(st.data(), s->status, st.size() * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(s, hipStreamSynchronize(s->stream));
+  for (int w = 0; w < s->P.W; ++w)
+    if (st[w]) return fail(s, QMC_ERR_SINGULAR, "walker %d: singular Slater matrix (spin mask %d)", w, st[w]);
+  return QMC_OK;
+}
+
+qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (!s->has_table) return fail(s, QMC_ERR_STATE, "load the spline table before init_walkers");
+  if (n_walkers < 1 || n_walkers > (1 << 20)) return fail(s, QMC_ERR_ARG, "n_walkers must be in [1, 2^20]");
+  HIP_TRY(s, hipSetDevice(s->device));
+  free_walkers(s);
+  const int W = n_walkers;
+  const WalkerSizes z = walker_sizes(s->P.n_up, s->P.n_dn, s->d.precision, W, s->P.n_orb);
+  s->pos = static_cast<double*>(s->mem.alloc(z.pos));
+  s->prop = static_cast<double*>(s->mem.alloc(z.prop));
+  s->vgl = s->mem.alloc(z.vgl);
+  s->cur = static_cast<uint8_t*>(s->mem.alloc(z.cur));
+  s->binv = s->mem.alloc(z.binv);
+  s->logdet = static_cast<double*>(s->mem.alloc(z.logdet));
+  s->sign = static_cast<int*>(s->mem.alloc(z.sign));
+  s->acc = static_cast<uint8_t*>(s->mem.alloc(z.acc));
+  s->nacc = static_cast<uint32_t*>(s->mem.alloc(z.nacc));
+  s->status = static_cast<int*>(s->mem.alloc(z.status));
+  s->scratch = static_cast<double*>(s->mem.alloc(z.scratch));
+  s->drift = static_cast<double*>(s->mem.alloc(z.drift));
+  s->energy = static_cast<double*>(s->mem.alloc(z.energy));
+  if (!s->pos || !s->prop || !s->vgl || !s->cur || !s->binv || !s->logdet || !s->sign || !s->acc ||
+      !s->nacc || !s->status || !s->scratch || !s->drift || !s->energy) {
+    free_walkers(s);
+    return fail(s, QMC_ERR_OOM, "device allocation of %zu walker bytes failed", z.total());
+  }
+  s->P.W = W;
+  const size_t N = s->P.N;
+  if (pos) {
+    std::vector<double> wp((size_t)W * N * 3);
+    for (size_t q = 0; q < wp.size(); ++q) {
+      const double x = pos[q];
+      if (!std::isfinite(x)) { free_walkers(s); return fail(s, QMC_ERR_ARG, "non-finite position"); }
+      double y = x - s->d.L * std::floor(x / s->d.L);
+      wp[q] = (y >= s->d.L) ? 0.0 : y;
+    }
+    HIP_TRY(s, hipMemcpy(s->pos, wp.data(), wp.size() * sizeof(double), hipMemcpyHostToDevice));
+  } else {
+    HIP_TRY(s, launch_init_positions(s->P, s->pos, s->stream));
+  }
+  HIP_TRY(s, hipMemsetAsync(s->status, 0, z.status, s->stream));
+  HIP_TRY(s, hipMemsetAsync(s->acc, 0, z.acc, s->stream));
+  HIP_TRY(s, hipMemsetAsync(s->logdet, 0, z.logdet, s->stream));
+  hipError_t e;
+  if (s->d.precision == QMC_MIXED)
+    e = timed(s, 0, [&] { return launch_gather<float>(s->P, walkers_of<float>(s), static_cast<const float*>(s->d_table), 0, 1, s->stream); });
+  else
+    e = timed(s, 0, [&] { return launch_gather<double>(s->P, walkers_of<double>(s), static_cast<const double*>(s->d_table), 0, 1, s->stream); });
+  if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "orbital gather launch: %s", hipGetErrorString(e));
+  qmc_status st = run_rebuild(s, nullptr);
+  if (st != QMC_OK) return st;
+  st = check_singular(s);
+  s->sweep_index = 0;
+  s->has_walkers = (st == QMC_OK);
+  return st;
+}
+
+qmc_status qmc_sweep(qmc_system s, int32_t n_sweeps, uint64_t* n_accepted_out) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (!s->has_walkers) return fail(s, QMC_ERR_STATE, "init_walkers first");
+  if (n_sweeps < 0) return fail(s, QMC_ERR_ARG, "n_sweeps must be >= 0");
+  HIP_TRY(s, hipSetDevice(s->device));
+  uint64_t total = 0;
+  std::vector<uint32_t> na;
+  for (int it = 0; it < n_sweeps; ++it) {
+    const uint32_t sw = s->sweep_index;
+    hipError_t e;
+    if (s->d.precision == QMC_MIXED) {
+      e = timed(s, 0, [&] { return launch_gather<float>(s->P, walkers_of<float>(s), static_cast<const float*>(s->d_table), sw, 0, s->stream); });
+      if (e == hipSuccess) e = timed(s, 1, [&] { return launch_chain<float>(s->P, walkers_of<float>(s), sw, s->stream); });
+    } else {
+      e = timed(s, 0, [&] { return launch_gather<double>(s->P, walkers_of<double>(s), static_cast<const double*>(s->d_table), sw, 0, s->stream); });
+      if (e == hipSuccess) e = timed(s, 1, [&] { return launch_chain<double>(s->P, walkers_of<double>(s), sw, s->stream); });
+    }
+    if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "sweep launch: %s", hipGetErrorString(e));
+    s->sweep_index = sw + 1;
+    if (s->d.recompute_period > 0 && s->sweep_index % (uint32_t)s->d.recompute_period == 0) {
+      qmc_status st = run_rebuild(s, nullptr);
+      if (st != QMC_OK) return st;
+    }
+    if (n_accepted_out) {
+      na.resize(s->P.W);
+      HIP_TRY(s, hipMemcpyAsync(na.data(), s->nacc, na.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream));
+      HIP_TRY(s, hipStreamSynchronize(s->stream));
+      for (uint32_t v : na) total += v;
+    }
+  }
+  if (n_accepted_out) *n_accepted_out = total;
+  return QMC_OK;
+}
+
+qmc_status qmc_measure_local_energy(qmc_system s, double* out, int32_t out_on_device) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (!s->has_walkers) return fail(s, QMC_ERR_STATE, "init_walkers first");
+  if (!out) return fail(s, QMC_ERR_ARG, "out is NULL");
+  HIP_TRY(s, hipSetDevice(s->device));
+  double* dst = out_on_device ? out : s->energy;
+  hipError_t e;
+  if (s->d.precision == QMC_MIXED)
+    e = timed(s, 2, [&] { return launch_measure<float>(s->P, walkers_of<float>(s), s->E, dst, s->stream); });
+  else
+    e = timed(s, 2, [&] { return launch_measure<double>(s->P, walkers_of<double>(s), s->E, dst, s->stream); });
+  if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "measure launch: %s", hipGetErrorString(e));
+  if (out_on_device) return QMC_OK;
+  const size_t nb = (size_t)s->P.W * 4 * sizeof(double);
+  HIP_TRY(s, hipMemcpyAsync(out, s->energy, nb, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(s, hipStreamSynchronize(s->stream));
+  for (size_t q = 0; q < (size_t)s->P.W * 4; ++q)
+    if (!std::isfinite(out[q])) return fail(s, QMC_ERR_NUMERIC, "non-finite local energy (walker %zu)", q / 4);
+  return QMC_OK;
+}
+
+qmc_status qmc_get_walkers(qmc_system s, double* pos, double* logabs_det, int32_t* sign) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (!s->has_walkers) return fail(s, QMC_ERR_STATE, "init_walkers first");
+  HIP_TRY(s, hipSetDevice(s->device));
+  const size_t W = s->P.W, N = s->P.N;
+  if (pos) HIP_TRY(s, hipMemcpyAsync(pos, s->pos, W * N * 3 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  if (logabs_det) HIP_TRY(s, hipMemcpyAsync(logabs_det, s->logdet, W * 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  if (sign) HIP_TRY(s, hipMemcpyAsync(sign, s->sign, W * 2 * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(s, hipStreamSynchronize(s->stream));
+  return QMC_OK;
+}
+
+qmc_status qmc_get_accept_log(qmc_system s, uint8_t* bits) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (!s->has_walkers) return fail(s, QMC_ERR_STATE, "init_walkers first");
+  if (!bits) return fail(s, QMC_ERR_ARG, "bits is NULL");
+  HIP_TRY(s, hipSetDevice(s->device));
+  HIP_TRY(s, hipMemcpyAsync(bits, s->acc, (size_t)s->P.W * s->P.N, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(s, hipStreamSynchronize(s->stream));
+  return QMC_OK;
+}
+
+qmc_status qmc_recompute(qmc_system s, double* drift_out) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (!s->has_walkers) return fail(s, QMC_ERR_STATE, "init_walkers first");
+  HIP_TRY(s, hipSetDevice(s->device));
+  HIP_TRY(s, hipMemsetAsync(s->status, 0, (size_t)s->P.W * sizeof(int), s->stream));
+  qmc_status st = run_rebuild(s, s->drift);
+  if (st != QMC_OK) return st;
+  if (drift_out)
+    HIP_TRY(s, hipMemcpyAsync(drift_out, s->drift, (size_t)s->P.W * 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  return check_singular(s);
+}
+
+qmc_status qmc_eval_spo_vgl(qmc_system s, int32_t n, const double* pos, double* out) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (!s->has_table) return fail(s, QMC_ERR_STATE, "load the spline table first");
+  if (n < 0 || (n > 0 && (!pos || !out))) return fail(s, QMC_ERR_ARG, "bad arguments");
+  if (n == 0) return QMC_OK;
+  HIP_TRY(s, hipSetDevice(s->device));
+  double *dp = nullptr, *dout = nullptr;
+  const size_t ob = (size_t)n * kComp * s->P.n_orb * sizeof(double);
+  HIP_TRY(s, hipMalloc(&dp, (size_t)n * 3 * sizeof(double)));
+  hipError_t e = hipMalloc(&dout, ob);
+  if (e == hipSuccess) e = hipMemcpy(dp, pos, (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    if (s->d.precision == QMC_MIXED)
+      e = launch_eval_points<float>(s->P, static_cast<const float*>(s->d_table), dp, n, dout, s->stream);
+    else
+      e = launch_eval_points<double>(s->P, static_cast<const double*>(s->d_table), dp, n, dout, s->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e == hipSuccess) e = hipMemcpy(out, dout, ob, hipMemcpyDeviceToHost);
+  (void)hipFree(dp);
+  if (dout) (void)hipFree(dout);
+  if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "eval_spo_vgl: %s", hipGetErrorString(e));
+  return QMC_OK;
+}
+
+qmc_status qmc_set_timing(qmc_system s, int32_t enable) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  s->timing = enable != 0;
+  return QMC_OK;
+}
+
+qmc_status qmc_kernel_timing(qmc_system s, int32_t kernel_class, double* total_ms, int64_t* launches,
+                             int32_t reset) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (kernel_class < 0 || kernel_class > 3) return fail(s, QMC_ERR_ARG, "kernel_class must be 0..3");
+  HIP_TRY(s, hipSetDevice(s->device));
+  TimerClass& tc = s->timers[kernel_class];
+  if (!tc.live.empty()) HIP_TRY(s, hipEventSynchronize(tc.live.back().second));
+  for (auto& ev : tc.live) {
+    float ms = 0.f;
+    HIP_TRY(s, hipEventElapsedTime(&ms, ev.first, ev.second));
+    tc.ms += ms;
+    tc.launches += 1;
+    tc.pool.push_back(ev);
+  }
+  tc.live.clear();
+  if (total_ms) *total_ms = tc.ms;
+  if (launches) *launches = tc.launches;
+  if (reset) { tc.ms = 0.0; tc.launches = 0; }
+  return QMC_OK;
+}
+
+qmc_status qmc_destroy_system(qmc_system s) {
+  if (!s) return QMC_OK;
+  (void)hipSetDevice(s->device);
+  (void)hipStreamSynchronize(s->stream);
+  for (auto& tc : s->timers) {
+    for (auto& ev : tc.live) { (void)hipEventDestroy(ev.first); (void)hipEventDestroy(ev.second); }
+    for (auto& ev : tc.pool) { (void)hipEventDestroy(ev.first); (void)hipEventDestroy(ev.second); }
+  }
+  s->mem.release_to(0);
+  delete s;
+  return QMC_OK;
+}
+
+const char* qmc_last_error(qmc_system s) {
+  if (s) return s->err.c_str();
+  return g_last_error.c_str();
+}
+
+size_t qmc_estimate_device_bytes(const qmc_system_desc* desc, int32_t n_walkers, int32_t gx, int32_t gy,
+                                 int32_t gz) {
+  if (!desc || n_walkers < 1 || gx < 4 || gy < 4 || gz < 4) return 0;
+  if (desc->n_up < 1 || desc->n_dn < 0 || desc->n_up + desc->n_dn > 1024) return 0;
+  if (desc->precision != QMC_FP64 && desc->precision != QMC_MIXED) return 0;
+  const int n_orb = desc->n_up > desc->n_dn ? desc->n_up : desc->n_dn;
+  const size_t table = align_up((size_t)gx * gy * gz * padded_stride(n_orb, desc->precision) * tsize_of(desc->precision));
+  return system_bytes(desc) + table + walker_sizes(desc->n_up, desc->n_dn, desc->precision, n_walkers, n_orb).total();
+}
+
+}  // extern "C"

@@ -1,0 +1,186 @@
+// qmc_device.hpp -- parameter blocks and device helpers shared by the HIP
+// kernels of the particle-by-particle VMC library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/qmc.h"
+
+namespace qmc {
+
+constexpr int kBlock = 256;           // threads per workgroup (4 wave64)
+constexpr int kWaves = kBlock / 64;
+constexpr int kComp = 5;              // value, d/dx, d/dy, d/dz, Laplacian
+constexpr double kPi = 3.14159265358979323846;
+
+// Radial function of a Jastrow term (section "Jastrow factors").
+struct Radial {
+  int kind;          // QMC_J_NONE / PADE / BSPLINE
+  int M;             // B-spline: number of free control points
+  double a, b;       // Pade: u = a r / (1 + b r)
+  double rc;         // B-spline cutoff
+  double inv_delta;  // M / rc
+  // B-spline control points p_0..p_M followed by zeros, so that the four
+  // coefficients p_n..p_{n+3} of any interval n <= M-1 are addressable.
+  double p[QMC_MAX_KNOTS + 4];
+};
+
+struct Jastrow {
+  Radial same;   // electron pairs of equal spin
+  Radial opp;    // electron pairs of opposite spin
+  Radial ei;     // electron-ion
+};
+
+// Everything a kernel needs to know about a system, passed by value.
+struct SysParams {
+  int n_up, n_dn, N;      // electrons per spin, total
+  int n_orb, S;           // orbitals; padded orbital stride of table and value rows
+  int gx, gy, gz;         // spline grid
+  int W;                  // walkers
+  int n_ions;
+  int bstride;            // elements of one walker's two inverses
+  double L, sigma;
+  uint32_t key0, key1;    // Philox key (seed)
+  const double* ions;     // [n_ions][4] = x, y, z, Z
+  Jastrow jas;
+};
+
+// Device buffers of the walkers.  T is the orbital/inverse precision.
+template <typename T>
+struct Walkers {
+  double* pos;        // [W][N][3], wrapped into [0, L)
+  double* prop;       // [W][N][4]: proposed x, y, z and the acceptance uniform
+  T* vgl;             // [2][W][N][5][S]: value, gradient, Laplacian rows (two buffers)
+  uint8_t* cur;       // [W][N]: which vgl buffer holds electron i's current row
+  T* binv;            // [W][bstride]: B_up (n_up x n_up) then B_dn, B[l][k] = (A^-1)[l][k]
+  double* logdet;     // [W][2]
+  int* sign;          // [W][2]
+  uint8_t* acc;       // [W][N]: accept flags of the last sweep
+  uint32_t* nacc;     // [W]: accepted moves in the last launch
+  int* status;        // [W]: nonzero = singular matrix at the last rebuild
+};
+
+// ---------------------------------------------------------------------------
+// Counter-based random numbers: Philox4x32-10 (Salmon, Moraes, Dror and Shaw,
+// SC'11).  Counter (electron, sweep, walker, purpose << 16 | sub), key = seed.
+// ---------------------------------------------------------------------------
+enum Purpose : uint32_t { kInit = 1, kPropose = 2, kAccept = 3 };
+
+__device__ __forceinline__ void philox10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
+                                         uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t y0 = hi1 ^ c1 ^ k0, y2 = hi0 ^ c3 ^ k1;
+    c0 = y0; c1 = lo1; c2 = y2; c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+// Two doubles in [0,1) from the top 53 bits of each 64-bit half of a block.
+__device__ __forceinline__ void uniform_pair(const SysParams& P, uint32_t purpose, uint32_t sub,
+                                             uint32_t walker, uint32_t sweep, uint32_t elec,
+                                             double& u0, double& u1) {
+  uint32_t c0 = elec, c1 = sweep, c2 = walker, c3 = (purpose << 16) | sub;
+  philox10(c0, c1, c2, c3, P.key0, P.key1);
+  const uint64_t x0 = (uint64_t)c0 | ((uint64_t)c1 << 32);
+  const uint64_t x1 = (uint64_t)c2 | ((uint64_t)c3 << 32);
+  u0 = (double)(x0 >> 11) * 0x1.0p-53;
+  u1 = (double)(x1 >> 11) * 0x1.0p-53;
+}
+
+__device__ __forceinline__ double wrap_cell(double x, double L) {
+  double y = x - L * floor(x / L);
+  return (y >= L) ? 0.0 : y;
+}
+
+__device__ __forceinline__ double min_image(double d, double L) { return d - L * rint(d / L); }
+
+// Uniform cubic B-spline basis on one axis: for t = i0 + f the knots
+// i0-1 .. i0+2 carry weights w, first derivatives dw and second derivatives
+// d2w (already scaled by knots per bohr h).
+struct Axis {
+  int idx[4];
+  double w[4], dw[4], d2w[4];
+};
+
+__device__ __forceinline__ void axis_weights(double x, double L, int G, Axis& a) {
+  const double h = (double)G / L;
+  const double t = wrap_cell(x, L) * h;
+  const double fl = floor(t);
+  int i0 = (int)fl;
+  const double f = t - fl;
+  const double f2 = f * f, f3 = f2 * f, g = 1.0 - f;
+  a.w[0] = g * g * g * (1.0 / 6.0);
+  a.w[1] = (3.0 * f3 - 6.0 * f2 + 4.0) * (1.0 / 6.0);
+  a.w[2] = (-3.0 * f3 + 3.0 * f2 + 3.0 * f + 1.0) * (1.0 / 6.0);
+  a.w[3] = f3 * (1.0 / 6.0);
+  a.dw[0] = -0.5 * g * g * h;
+  a.dw[1] = (1.5 * f2 - 2.0 * f) * h;
+  a.dw[2] = (-1.5 * f2 + f + 0.5) * h;
+  a.dw[3] = 0.5 * f2 * h;
+  const double h2 = h * h;
+  a.d2w[0] = g * h2;
+  a.d2w[1] = (3.0 * f - 2.0) * h2;
+  a.d2w[2] = (1.0 - 3.0 * f) * h2;
+  a.d2w[3] = f * h2;
+  if (i0 >= G) i0 -= G;
+  i0 = i0 < 0 ? 0 : (i0 > G - 1 ? G - 1 : i0);   // never index outside the table
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    int j = i0 - 1 + m;
+    j = (j < 0) ? j + G : (j >= G ? j - G : j);
+    a.idx[m] = j;
+  }
+}
+
+// Radial Jastrow function value and first two derivatives.
+__device__ __forceinline__ void radial_eval(const Radial& R, double r, double& u, double& du,
+                                            double& d2u) {
+  if (R.kind == QMC_J_PADE) {
+    const double d = 1.0 + R.b * r, id = 1.0 / d;
+    u = R.a * r * id;
+    du = R.a * id * id;
+    d2u = -2.0 * R.a * R.b * id * id * id;
+  } else if (R.kind == QMC_J_BSPLINE && r < R.rc) {
+    const double t = r * R.inv_delta;
+    const double fl = floor(t);
+    const int n = (int)fl;
+    const double f = t - fl, f2 = f * f, f3 = f2 * f, g = 1.0 - f;
+    const double* p = R.p + n;
+    u = (g * g * g * p[0] + (3.0 * f3 - 6.0 * f2 + 4.0) * p[1] +
+         (-3.0 * f3 + 3.0 * f2 + 3.0 * f + 1.0) * p[2] + f3 * p[3]) * (1.0 / 6.0);
+    du = (-0.5 * g * g * p[0] + (1.5 * f2 - 2.0 * f) * p[1] + (-1.5 * f2 + f + 0.5) * p[2] +
+          0.5 * f2 * p[3]) * R.inv_delta;
+    d2u = (g * p[0] + (3.0 * f - 2.0) * p[1] + (1.0 - 3.0 * f) * p[2] + f * p[3]) *
+          (R.inv_delta * R.inv_delta);
+  } else {
+    u = 0.0; du = 0.0; d2u = 0.0;
+  }
+}
+
+__device__ __forceinline__ double radial_value(const Radial& R, double r) {
+  if (R.kind == QMC_J_PADE) return R.a * r / (1.0 + R.b * r);
+  if (R.kind == QMC_J_BSPLINE && r < R.rc) {
+    const double t = r * R.inv_delta;
+    const double fl = floor(t);
+    const int n = (int)fl;
+    const double f = t - fl, f2 = f * f, f3 = f2 * f, g = 1.0 - f;
+    const double* p = R.p + n;
+    return (g * g * g * p[0] + (3.0 * f3 - 6.0 * f2 + 4.0) * p[1] +
+            (-3.0 * f3 + 3.0 * f2 + 3.0 * f + 1.0) * p[2] + f3 * p[3]) * (1.0 / 6.0);
+  }
+  return 0.0;
+}
+
+// Wave64 sum of a double (xor butterfly: every lane gets the total).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+}  // namespace qmc

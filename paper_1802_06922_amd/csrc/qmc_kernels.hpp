@@ -1,0 +1,57 @@
+// qmc_kernels.hpp -- host-side launchers of the HIP kernels.  Each returns the
+// launch's hipError_t.  Template parameter T: double (FP64) or float (mixed).
+#pragma once
+
+#include "qmc_device.hpp"
+
+namespace qmc {
+
+// Ewald-sum constants of one system (splitting parameter kappa, reciprocal
+// vectors of one half space with their weights, the ions' structure factor).
+struct EwaldParams {
+  int enabled;
+  int n_g;
+  double kappa, rcut;
+  const double* gvec;    // [n_g][4]: Gx, Gy, Gz, (4 pi / V) exp(-G^2 / 4 kappa^2) / G^2
+  const double* s_ion;   // [n_g][2]: sum_I Z_I exp(i G.R_I)
+  double c_ee;           // electron self, self-image and background terms
+  double c_ei;           // electron-ion background cross term
+  double v_ii;           // ion-ion energy (constant)
+};
+
+// Orbital gather: for every (walker, electron), either draw the proposal of
+// `sweep` and evaluate all orbitals there (mode 0, written to the buffer that
+// does not hold the current row), or evaluate at the current position (mode 1,
+// written to buffer 0 and cur reset).
+template <typename T>
+hipError_t launch_gather(const SysParams& P, const Walkers<T>& Wk, const T* table, uint32_t sweep,
+                         int mode, hipStream_t st);
+
+// Diagnostic evaluation at arbitrary points: out[n][5][n_orb] (FP64).
+template <typename T>
+hipError_t launch_eval_points(const SysParams& P, const T* table, const double* pos, int n,
+                              double* out, hipStream_t st);
+
+// Sequential move chain of one sweep (one workgroup per walker).
+template <typename T>
+hipError_t launch_chain(const SysParams& P, const Walkers<T>& Wk, uint32_t sweep, hipStream_t st);
+
+// Initial positions from the INIT stream.
+hipError_t launch_init_positions(const SysParams& P, double* pos, hipStream_t st);
+
+// Full FP64 inverse of every Slater matrix from the current value rows
+// (Gauss-Jordan with partial pivoting); scratch: W * bstride doubles.
+// drift (nullable): receives log|D|_old - log|D|_new per [W][2].
+template <typename T>
+hipError_t launch_rebuild(const SysParams& P, const Walkers<T>& Wk, double* scratch, double* drift,
+                          hipStream_t st);
+
+// Local energy of every walker: out[W][4].
+template <typename T>
+hipError_t launch_measure(const SysParams& P, const Walkers<T>& Wk, const EwaldParams& E, double* out,
+                          hipStream_t st);
+
+// Size in bytes of the dynamic LDS the chain kernel needs for P.
+size_t chain_lds_bytes(const SysParams& P, size_t tsize, bool b_in_lds);
+
+}  // namespace qmc

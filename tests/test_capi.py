@@ -1,0 +1,77 @@
+"""Host-side checks of the C ABI library (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qmc.h")
+
+
+@pytest.fixture(scope="module")
+def libqmc():
+    from paper_1802_06922_amd import build as hipbuild
+    if not os.path.exists(hipbuild.LIB):
+        hipbuild.build()
+    return ctypes.CDLL(hipbuild.LIB)
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qmc_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ["qmc_create_system", "qmc_load_spline_table", "qmc_init_walkers", "qmc_sweep",
+                     "qmc_measure_local_energy"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(libqmc):
+    missing = [n for n in _declared() if not hasattr(libqmc, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_1802_06922_amd import qmc
+    assert sorted(qmc.EXPORTS) == _declared()
+
+
+def test_estimate_device_bytes_without_gpu(libqmc):
+    import numpy as np
+
+    import qmc_inputs as qi
+    from paper_1802_06922_amd import qmc
+    qmc.load_library()
+    wl = qi.heg14()
+    small = qmc.estimate_device_bytes(wl, 8)
+    big = qmc.estimate_device_bytes(wl, 800)
+    assert 0 < small < big
+    # table + walker buffers dominate: at least the FP64 table and two value buffers
+    S = 8
+    assert small >= 16 ** 3 * S * 8 + 2 * 8 * 14 * 5 * S * 8
+    keep = []
+    d = qmc.make_desc(wl, keep)
+    d.n_up = 0
+    assert libqmc.qmc_estimate_device_bytes(ctypes.byref(d), 8, 16, 16, 16) == 0
+    assert np.isfinite(small)
+
+
+def test_create_rejects_bad_descriptors_before_touching_the_device(libqmc):
+    import qmc_inputs as qi
+    from paper_1802_06922_amd import qmc
+    L = qmc.load_library()
+    wl = qi.solid128()
+    keep = []
+    bad = qmc.make_desc(wl, keep)
+    bad.j2_rcut = wl.L  # beyond the Wigner-Seitz radius L/2
+    h = ctypes.c_void_p()
+    assert L.qmc_create_system(ctypes.byref(bad), None, ctypes.byref(h)) == qmc.QMC_ERR_ARG
+    assert b"cutoff" in L.qmc_last_error(None)
+    bad = qmc.make_desc(wl, keep)
+    bad.sigma = 0.0
+    assert L.qmc_create_system(ctypes.byref(bad), None, ctypes.byref(h)) == qmc.QMC_ERR_ARG
+    assert L.qmc_create_system(None, None, ctypes.byref(h)) == qmc.QMC_ERR_ARG

@@ -1,0 +1,202 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bars (FP64 path): accept/reject decisions bit-exact; local energies within
+1e-10 relative (|E_gpu - E_orc| / max(|E_orc|, 1 hartree)); orbital values,
+gradients and Laplacians within 1e-12 of the oracle's (scaled by the row's
+magnitude).  Inputs come from the seeded generators in qmc_inputs; the
+random streams are the same Philox streams on both sides.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import qmc_inputs as qi
+
+pytestmark = pytest.mark.gpu
+
+E_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1802_06922_amd import qmc
+    qmc.load_library()
+    return qmc
+
+
+def _rel(a, b):
+    return np.abs(a - b) / np.maximum(np.abs(b), 1.0)
+
+
+def _run_gpu(gpu, wl, n_sweeps, n_walkers=None, sample=None):
+    s = gpu.System(wl, n_walkers=n_walkers)
+    bits, energies = [], []
+    for _ in range(n_sweeps):
+        s.sweep(1)
+        b = s.accept_log()
+        e = s.measure()
+        if sample is not None:
+            b, e = b[sample], e[sample]
+        bits.append(b)
+        energies.append(e)
+    pos, ld, sg = s.get_walkers()
+    s.close()
+    if sample is not None:
+        pos, ld, sg = pos[sample], ld[sample], sg[sample]
+    return np.stack(bits, 1), np.stack(energies, 1), pos, ld, sg
+
+
+def _compare_run(gpu, orc, wl, n_sweeps, walkers, n_walkers=None):
+    print(f"[parity] {wl.name}: walkers {list(walkers)[:6]}.. of {n_walkers or wl.n_walkers}, "
+          f"{n_sweeps} sweeps", flush=True)
+    sample = np.asarray(walkers)
+    b, e, pos, ld, sg = _run_gpu(gpu, wl, n_sweeps, n_walkers, sample)
+    ref = orc.OracleSystem(wl).run(sample, n_sweeps, measure_every=1)
+    assert np.array_equal(b, ref["accept"]), (
+        f"first differing move: {np.argwhere(b != ref['accept'])[:3]}")
+    rel = _rel(e, ref["energies"])
+    assert rel.max() < E_TOL, f"max rel energy error {rel.max():.3e}"
+    np.testing.assert_allclose(pos, ref["final_pos"], atol=1e-11)
+    np.testing.assert_allclose(ld, ref["logdet"], atol=1e-9)
+    assert np.array_equal(sg, ref["sign"])
+    return b, e
+
+
+def test_spline_vgl_matches_oracle(gpu, orc):
+    rng = np.random.default_rng(0)
+    cases = [qi.heg14(), qi.solid(10, 12, n_walkers=1, n_sweeps=1),     # 5 orbitals: ragged vectors
+             qi.solid(14, 9, n_walkers=1, n_sweeps=1, precision="fp64")]
+    for wl in cases:
+        print(f"[vgl] {wl.name}", flush=True)
+        s = gpu.System(wl, n_walkers=1)
+        pts = rng.uniform(0, wl.L, size=(97, 3))
+        pts[:5] = [[0, 0, 0], [wl.L * (1 - 1e-16), 0.1, 0.2], [1e-300, wl.L / 2, 1.0],
+                   [wl.L / wl.grid[0], 2 * wl.L / wl.grid[0], 0.0], [-0.3, wl.L + 0.2, 3.1 * wl.L]]
+        out = s.eval_spo_vgl(pts)
+        s.close()
+        osys = orc.OracleSystem(wl)
+        for p, o in zip(pts, out):
+            v, g, l = osys.spo_vgl(p)
+            ref = np.vstack([v, g, l])
+            scale = np.maximum(np.abs(ref).max(axis=0, keepdims=True), 1.0)
+            assert (np.abs(o - ref) / scale).max() < 1e-12
+
+
+def test_init_matches_oracle(gpu, orc):
+    wl = qi.solid(32, 16, n_walkers=6, n_sweeps=1)
+    s = gpu.System(wl)
+    pos, ld, sg = s.get_walkers()
+    s.close()
+    ref = orc.OracleSystem(wl).run(range(6), 0, measure_every=0)
+    np.testing.assert_allclose(pos, ref["final_pos"], atol=1e-13)
+    np.testing.assert_allclose(ld, ref["logdet_lu"], atol=1e-10)
+    assert np.array_equal(sg, ref["sign"])
+
+
+def test_heg14_full_trajectory(gpu, orc):
+    """The 14-electron gas (16^3 table, Pade J2, 8 walkers) over all 100 sweeps."""
+    wl = qi.heg14()
+    b, _ = _compare_run(gpu, orc, wl, wl.n_sweeps, range(wl.n_walkers))
+    assert 0.3 < b.mean() < 0.95
+
+
+def test_heg14_without_jastrow_kinetic_only(gpu, orc):
+    wl = qi.heg14(jastrow=False, hamiltonian="kinetic")
+    _compare_run(gpu, orc, wl, 20, range(8))
+
+
+def test_small_solid_trajectory_ragged(gpu, orc):
+    """Odd spin counts (9 up, 7 down: ragged rows, 9 orbitals), ions, both B-spline Jastrows."""
+    wl = qi.solid(18, 14, n_walkers=24, n_sweeps=1)
+    wl.n_up, wl.n_dn, wl.n_orb = 9, 7, 9
+    wl.coefs = qi.solid_table(9, 14, seed=3, dtype=np.float64)
+    _compare_run(gpu, orc, wl, 15, range(24))
+
+
+def test_solid128_sampled_walkers(gpu, orc):
+    """The 128-electron solid (48^3 FP64 table, 32 ions, 512 walkers): sampled walkers."""
+    wl = qi.solid128()
+    _compare_run(gpu, orc, wl, 4, [0, 255, 511])
+
+
+def test_recompute_drift_is_tiny(gpu, orc):
+    wl = qi.solid(64, 16, n_walkers=16, n_sweeps=1)
+    s = gpu.System(wl)
+    s.sweep(10)
+    drift = s.recompute()
+    pos, ld, _ = s.get_walkers()
+    e1 = s.measure()
+    s.close()
+    assert np.abs(drift).max() < 1e-9
+    osys = orc.OracleSystem(wl)
+    for w in range(0, 16, 5):
+        ref = osys.local_energy(pos[w])
+        assert _rel(e1[w], ref).max() < E_TOL
+
+
+def test_measure_at_given_positions(gpu, orc):
+    wl = qi.solid(32, 16, n_walkers=5, n_sweeps=1)
+    rng = np.random.default_rng(4)
+    pos = rng.uniform(-wl.L, 2 * wl.L, size=(5, wl.n_elec, 3))
+    s = gpu.System(wl, init_pos=pos)
+    e = s.measure()
+    s.close()
+    osys = orc.OracleSystem(wl)
+    for w in range(5):
+        assert _rel(e[w], osys.local_energy(pos[w])).max() < E_TOL
+
+
+def test_torch_arena_matches_own_allocations(gpu):
+    wl = qi.solid(32, 16, n_walkers=8, n_sweeps=1)
+    outs = []
+    for arena in (False, True):
+        s = gpu.System(wl, use_torch_arena=arena)
+        s.sweep(3)
+        outs.append((s.accept_log(), s.measure()))
+        s.close()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_repeatable_bitwise(gpu):
+    wl = qi.solid(32, 16, n_walkers=8, n_sweeps=1)
+    res = []
+    for _ in range(2):
+        s = gpu.System(wl)
+        s.sweep(3)
+        res.append((s.get_walkers()[0], s.measure()))
+        s.close()
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+
+
+def test_error_paths(gpu):
+    wl = qi.solid(8, 8, n_walkers=2, n_sweeps=1)
+    # two electrons of the same spin on the same point: zero determinant
+    pos = np.random.default_rng(1).uniform(0, wl.L, size=(2, 8, 3))
+    pos[1, 1] = pos[1, 0]
+    with pytest.raises(gpu.QMCError) as ei:
+        gpu.System(wl, init_pos=pos)
+    assert ei.value.status == gpu.QMC_ERR_SINGULAR
+    s = gpu.System(wl, init=False)
+    with pytest.raises(gpu.QMCError) as ei:
+        s.sweep(1)
+    assert ei.value.status == gpu.QMC_ERR_STATE
+    s.close()
+    bad = qi.solid(8, 8, n_walkers=2, n_sweeps=1)
+    bad.n_orb = 3
+    with pytest.raises(gpu.QMCError) as ei:
+        gpu.System(bad)
+    assert ei.value.status == gpu.QMC_ERR_ARG
+
+
+def test_acceptance_counter(gpu):
+    wl = qi.solid(16, 12, n_walkers=4, n_sweeps=1)
+    s = gpu.System(wl)
+    n = s.sweep(1, count_accepted=True)
+    bits = s.accept_log()
+    s.close()
+    assert n == int(bits.sum())
