@@ -85,6 +85,7 @@ struct qmc_system_s {
   double* d_ions = nullptr;
   double* d_gvec = nullptr;
   double* d_sion = nullptr;
+  int* d_segs = nullptr;
   void* d_table = nullptr;
   bool has_table = false, has_walkers = false;
   uint32_t sweep_index = 0;
@@ -170,33 +171,45 @@ void build_radial(Radial& R, int kind, const double* p, int M, double rc, double
   }
 }
 
-// Ewald tables: splitting kappa = 4 / L, real space over the 27 nearest
-// images (every image closer than 1.5 L), reciprocal vectors of one half
-// space with G^2 / (4 kappa^2) <= 40.
-void ewald_setup(qmc_system s, std::vector<double>& gvec, std::vector<double>& sion) {
+// Ewald tables (section "Long-Range Interactions").  Splitting kappa = 5.5 / L
+// with the real-space cutoff at one cell side L (erfc(5.5) ~ 7e-15), and every
+// reciprocal vector of one half space with G^2 / (4 kappa^2) <= 30, grouped in
+// segments of at most kEwaldSeg consecutive Gz of one (Gx, Gy) column.
+void ewald_setup(qmc_system s, std::vector<double>& gvec, std::vector<double>& sion,
+                 std::vector<int>& segs) {
   const double L = s->d.L, V = L * L * L;
-  const double kappa = 4.0 / L;
+  const double kappa = 5.5 / L;
   const double g0 = 2.0 * kPi / L;
-  const double gmax2 = 40.0 * 4.0 * kappa * kappa;
-  const int mmax = (int)std::ceil(std::sqrt(gmax2) / g0);
+  const double gmax2 = 30.0 * 4.0 * kappa * kappa;
+  const int m2max = (int)std::floor(gmax2 / (g0 * g0));
+  const int mmax = (int)std::floor(std::sqrt((double)m2max));
   const int M = s->d.n_ions;
   for (int a = 0; a <= mmax; ++a)
-    for (int b = -mmax; b <= mmax; ++b)
-      for (int c = -mmax; c <= mmax; ++c) {
-        if (a == 0 && (b < 0 || (b == 0 && c <= 0))) continue;   // one of each +-G pair
-        const double Gx = g0 * a, Gy = g0 * b, Gz = g0 * c;
-        const double G2 = Gx * Gx + Gy * Gy + Gz * Gz;
-        if (G2 > gmax2) continue;
-        gvec.push_back(Gx); gvec.push_back(Gy); gvec.push_back(Gz);
-        gvec.push_back(4.0 * kPi / V * std::exp(-G2 / (4.0 * kappa * kappa)) / G2);
-        double re = 0.0, im = 0.0;
-        for (int I = 0; I < M; ++I) {
-          const double ph = Gx * s->ions4[4 * I] + Gy * s->ions4[4 * I + 1] + Gz * s->ions4[4 * I + 2];
-          re += s->ions4[4 * I + 3] * std::cos(ph);
-          im += s->ions4[4 * I + 3] * std::sin(ph);
+    for (int b = -mmax; b <= mmax; ++b) {
+      if (a == 0 && b < 0) continue;                 // one of each +-G pair
+      const int rem = m2max - a * a - b * b;
+      if (rem < 0) continue;
+      const int cm = (int)std::floor(std::sqrt((double)rem));
+      const int lo = (a == 0 && b == 0) ? 1 : -cm;
+      for (int c0 = lo; c0 <= cm; c0 += kEwaldSeg) {
+        const int c1 = std::min(cm, c0 + kEwaldSeg - 1);
+        segs.push_back(a); segs.push_back(b); segs.push_back(c0); segs.push_back(c1);
+        segs.push_back((int)(gvec.size() / 4));
+        for (int c = c0; c <= c1; ++c) {
+          const double Gx = g0 * a, Gy = g0 * b, Gz = g0 * c;
+          const double G2 = Gx * Gx + Gy * Gy + Gz * Gz;
+          gvec.push_back(Gx); gvec.push_back(Gy); gvec.push_back(Gz);
+          gvec.push_back(4.0 * kPi / V * std::exp(-G2 / (4.0 * kappa * kappa)) / G2);
+          double re = 0.0, im = 0.0;
+          for (int I = 0; I < M; ++I) {
+            const double ph = Gx * s->ions4[4 * I] + Gy * s->ions4[4 * I + 1] + Gz * s->ions4[4 * I + 2];
+            re += s->ions4[4 * I + 3] * std::cos(ph);
+            im += s->ions4[4 * I + 3] * std::sin(ph);
+          }
+          sion.push_back(re); sion.push_back(im);
         }
-        sion.push_back(re); sion.push_back(im);
       }
+    }
   // self-image sum: sum_{n != 0} erfc(kappa |n| L) / (|n| L)
   double simg = 0.0;
   for (int a = -2; a <= 2; ++a)
@@ -210,11 +223,12 @@ void ewald_setup(qmc_system s, std::vector<double>& gvec, std::vector<double>& s
   double Zt = 0.0, Z2 = 0.0;
   for (int I = 0; I < M; ++I) { Zt += s->ions4[4 * I + 3]; Z2 += s->ions4[4 * I + 3] * s->ions4[4 * I + 3]; }
   s->E.kappa = kappa;
-  s->E.rcut = 1.5 * L;
+  s->E.rcut = L;
   s->E.n_g = (int)(gvec.size() / 4);
+  s->E.n_seg = (int)(segs.size() / 5);
   s->E.c_ee = -kappa / std::sqrt(kPi) * N + 0.5 * N * simg - kPi * N * N / (2.0 * V * kappa * kappa);
   s->E.c_ei = kPi * N * Zt / (V * kappa * kappa);
-  // ions alone: pairs over the 27 nearest images, reciprocal, self and background
+  // ions alone: pairs over every image closer than the cutoff, reciprocal, self and background
   double vii = 0.0;
   for (int I = 0; I < M; ++I)
     for (int J = 0; J < M; ++J) {
@@ -279,12 +293,13 @@ WalkerSizes walker_sizes(int n_up, int n_dn, int precision, int W, int n_orb) {
 }
 
 size_t system_bytes(const qmc_system_desc* d) {
-  // ions + Ewald tables (upper bound on the reciprocal list)
-  const double kappa_L = 4.0;
-  const int mmax = (int)std::ceil(std::sqrt(160.0) * kappa_L / (2.0 * kPi));
+  // ions + Ewald tables (upper bounds on the reciprocal list and its segments)
+  const int mmax = (int)std::ceil(std::sqrt(120.0) * 5.5 / (2.0 * kPi));
   const size_t ng = (size_t)(mmax + 1) * (2 * mmax + 1) * (2 * mmax + 1);
+  const size_t nseg = (size_t)(mmax + 1) * (2 * mmax + 1) * 3;
   return align_up((size_t)(d->n_ions > 0 ? d->n_ions : 1) * 4 * sizeof(double)) +
-         align_up(ng * 4 * sizeof(double)) + align_up(ng * 2 * sizeof(double));
+         align_up(ng * 4 * sizeof(double)) + align_up(ng * 2 * sizeof(double)) +
+         align_up(nseg * 5 * sizeof(int));
 }
 
 qmc_status validate(const qmc_system_desc* d) {
@@ -392,12 +407,15 @@ qmc_status qmc_create_system(const qmc_system_desc* desc, void* hip_stream, qmc_
   s->E.enabled = desc->hamiltonian == QMC_H_COULOMB_EWALD;
   if (s->E.enabled) {
     std::vector<double> gvec, sion;
-    ewald_setup(s, gvec, sion);
+    std::vector<int> segs;
+    ewald_setup(s, gvec, sion, segs);
     s->d_gvec = static_cast<double*>(s->mem.alloc(gvec.size() * sizeof(double)));
     s->d_sion = static_cast<double*>(s->mem.alloc(sion.size() * sizeof(double)));
-    if (!s->d_gvec || !s->d_sion) { qmc_destroy_system(s); return fail(nullptr, QMC_ERR_OOM, "device allocation (Ewald)"); }
+    s->d_segs = static_cast<int*>(s->mem.alloc(segs.size() * sizeof(int)));
+    if (!s->d_gvec || !s->d_sion || !s->d_segs) { qmc_destroy_system(s); return fail(nullptr, QMC_ERR_OOM, "device allocation (Ewald)"); }
     if (hipMemcpyAsync(s->d_gvec, gvec.data(), gvec.size() * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-        hipMemcpyAsync(s->d_sion, sion.data(), sion.size() * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess) {
+        hipMemcpyAsync(s->d_sion, sion.data(), sion.size() * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync(s->d_segs, segs.data(), segs.size() * sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess) {
       qmc_destroy_system(s);
       return fail(nullptr, QMC_ERR_DEVICE, "Ewald upload failed");
     }
@@ -407,6 +425,7 @@ qmc_status qmc_create_system(const qmc_system_desc* desc, void* hip_stream, qmc_
     }
     s->E.gvec = s->d_gvec;
     s->E.s_ion = s->d_sion;
+    s->E.segs = s->d_segs;
   } else if (hipStreamSynchronize(s->stream) != hipSuccess) {
     qmc_destroy_system(s);
     return fail(nullptr, QMC_ERR_DEVICE, "stream synchronise failed");

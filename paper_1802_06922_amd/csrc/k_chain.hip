@@ -11,51 +11,86 @@
 // "Multi-Determinant Slater-Jastrow Form"):
 //   B[l][m] -= B[l][k] (t_m - delta_mk) / R,   t_m = sum_j v_j B[j][m].
 //
-// One workgroup owns one walker for the whole sweep; the walker's positions
-// live in LDS, and so does the active spin's inverse whenever it fits.
+// One workgroup owns one walker for the whole sweep.  Positions, the spin
+// block's proposals and buffer flags, small ion sets, and the active spin's
+// inverse (whenever it fits) live in LDS.  The proposals' orbital rows do not
+// depend on the chain's decisions, so they stream through a two-chunk LDS
+// ring: the loads of chunk c+1 are issued when chunk c starts and have a whole
+// chunk of moves to arrive, hiding the HBM latency.
+#include <cstdlib>
+
 #include "qmc_kernels.hpp"
 
 namespace qmc {
 
-template <typename T>
+constexpr int kLdsIons = 256;     // ions staged in LDS up to this count
+
 struct ChainLayout {
-  // byte offsets inside the dynamic LDS block
-  size_t pos, red, v, col, t, b, total;
+  size_t pos, prop, ions, red, vbuf, col, t, cur, acc, b, total;
 };
 
-template <typename T>
-__host__ __device__ inline ChainLayout<T> chain_layout(int N, int nmax, int ldl, bool b_in_lds) {
-  ChainLayout<T> L;
+__host__ __device__ inline ChainLayout chain_layout(int N, int nmax, int n_ions, int ldl, size_t ts,
+                                                   bool b_in_lds, int rows_per_chunk) {
+  ChainLayout L;
   size_t o = 0;
   L.pos = o; o += sizeof(double) * 3 * N;
+  L.prop = o; o += sizeof(double) * 4 * nmax;
+  L.ions = o; o += (n_ions <= kLdsIons) ? sizeof(double) * 4 * n_ions : 0;
   L.red = o; o += sizeof(double) * 4 * kWaves;
   o = (o + 15) & ~size_t(15);
-  L.v = o; o += sizeof(T) * nmax;
-  L.col = o; o += sizeof(T) * nmax;
-  L.t = o; o += sizeof(T) * nmax;
+  L.vbuf = o; o += ts * (size_t)2 * rows_per_chunk * nmax;
   o = (o + 15) & ~size_t(15);
-  L.b = o; o += b_in_lds ? sizeof(T) * (size_t)nmax * ldl : 0;
+  L.col = o; o += ts * nmax;
+  o = (o + 15) & ~size_t(15);
+  L.t = o; o += ts * nmax;
+  o = (o + 15) & ~size_t(15);
+  L.cur = o; o += nmax;
+  L.acc = o; o += nmax;
+  o = (o + 15) & ~size_t(15);
+  L.b = o; o += b_in_lds ? ts * (size_t)nmax * ldl : 0;
   L.total = o;
   return L;
+}
+
+// Barrier between moves: LDS-only when the inverse lives in LDS (outstanding
+// row loads stay in flight), a full barrier when the inverse is in global memory.
+template <bool BLDS>
+__device__ __forceinline__ void block_sync() {
+  if (BLDS) sync_lds();
+  else __syncthreads();
+}
+
+__device__ __forceinline__ double min_image_inv(double d, double L, double invL) {
+  return d - L * rint(d * invL);
 }
 
 __device__ __forceinline__ double pair_u(const Jastrow& J, int kind, double r) {
   return kind == 0 ? radial_value(J.same, r) : (kind == 1 ? radial_value(J.opp, r) : radial_value(J.ei, r));
 }
 
-template <typename T, bool BLDS>
+// VPT = orbital values per thread per row (n <= 256 * VPT); a chunk holds
+// 16 / VPT rows, so the staging registers are always 16 values per thread.
+template <typename T, bool BLDS, int VPT>
 __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, uint32_t sweep, int ldl) {
+  constexpr int C = 16 / VPT;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ Jastrow sj;
   const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = P.N, nmax = P.n_up > P.n_dn ? P.n_up : P.n_dn;
-  const ChainLayout<T> lay = chain_layout<T>(N, nmax, ldl, BLDS);
+  const ChainLayout lay = chain_layout(N, nmax, P.n_ions, ldl, sizeof(T), BLDS, C);
   double* spos = reinterpret_cast<double*>(smem + lay.pos);
+  double* sprop = reinterpret_cast<double*>(smem + lay.prop);
+  const bool ions_lds = P.n_ions <= kLdsIons;
+  double* sion = reinterpret_cast<double*>(smem + lay.ions);
+  const double* ions = ions_lds ? sion : P.ions;
   double* red = reinterpret_cast<double*>(smem + lay.red);
-  T* sv = reinterpret_cast<T*>(smem + lay.v);
+  T* vbuf = reinterpret_cast<T*>(smem + lay.vbuf);
   T* scol = reinterpret_cast<T*>(smem + lay.col);
   T* st = reinterpret_cast<T*>(smem + lay.t);
+  uint8_t* scur = smem + lay.cur;
+  uint8_t* sacc = smem + lay.acc;
   T* sB = reinterpret_cast<T*>(smem + lay.b);
+  const double L = P.L, invL = 1.0 / P.L;
 
   {  // Jastrow parameters into LDS (indexed per lane below)
     const uint32_t* src = reinterpret_cast<const uint32_t*>(&P.jas);
@@ -63,16 +98,20 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, ui
     for (int q = tid; q < (int)(sizeof(Jastrow) / 4); q += kBlock) dst[q] = src[q];
   }
   for (int j = tid; j < 3 * N; j += kBlock) spos[j] = Wk.pos[(size_t)w * 3 * N + j];
-  double logd[2] = {Wk.logdet[2 * w], Wk.logdet[2 * w + 1]};
-  int sgn[2] = {Wk.sign[2 * w], Wk.sign[2 * w + 1]};
+  if (ions_lds)
+    for (int j = tid; j < 4 * P.n_ions; j += kBlock) sion[j] = P.ions[j];
   uint32_t nacc = 0;
   int parity = 0;
-  __syncthreads();
 
   for (int sp = 0; sp < 2; ++sp) {
     const int n = sp ? P.n_dn : P.n_up;
     const int off = sp ? P.n_up : 0;
     if (n == 0) continue;
+    const size_t item0 = (size_t)w * N + off;
+    double logd = Wk.logdet[2 * w + sp];
+    int sgn = Wk.sign[2 * w + sp];
+    for (int q = tid; q < 4 * n; q += kBlock) sprop[q] = Wk.prop[item0 * 4 + q];
+    for (int q = tid; q < n; q += kBlock) scur[q] = Wk.cur[item0 + q];
     T* Bg = Wk.binv + (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0);
     T* Bm;
     int ldb;
@@ -83,25 +122,56 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, ui
       }
       Bm = sB;
       ldb = ldl;
-      __syncthreads();
     } else {
       Bm = Bg;
       ldb = n;
     }
+    __syncthreads();
+    // column split of the accept-path product t = v^T B: tpc threads per column
+    int tpc = 1;
+    while (tpc < 8 && tpc * 2 * n <= kBlock) tpc *= 2;
+
+    // staging registers: this thread's elements of the next chunk's rows
+    T stage[C][VPT];
+    auto issue_chunk = [&](int c0) {
+#pragma unroll
+      for (int r = 0; r < C; ++r) {
+        const int kk = c0 + r;
+        if (kk < n) {
+          const T* vrow = Wk.vgl + ((size_t)(1 - scur[kk]) * P.W * N + item0 + kk) * kComp * P.S;
+#pragma unroll
+          for (int c = 0; c < VPT; ++c) {
+            const int j = tid + c * kBlock;
+            stage[r][c] = (j < n) ? vrow[j] : T(0);
+          }
+        }
+      }
+    };
+    issue_chunk(0);
     for (int k = 0; k < n; ++k) {
       const int i = off + k;
-      const size_t item = (size_t)w * N + i;
-      const double* pr = Wk.prop + item * 4;
-      const double rx = pr[0], ry = pr[1], rz = pr[2], u = pr[3];
-      const int cb = Wk.cur[item];
-      const T* vrow = Wk.vgl + ((size_t)(1 - cb) * P.W * N + item) * kComp * P.S;
+      const int kr = k % C;
+      T* vrow_l = vbuf + ((size_t)((k / C) & 1) * C + kr) * nmax;   // this move's row in LDS
+      if (kr == 0) {
+        // the staged chunk goes to its LDS slot, then the next chunk's loads start
+        T* slot = vbuf + (size_t)((k / C) & 1) * C * nmax;
+#pragma unroll
+        for (int r = 0; r < C; ++r)
+#pragma unroll
+          for (int c = 0; c < VPT; ++c) {
+            const int j = tid + c * kBlock;
+            if (j < n) slot[(size_t)r * nmax + j] = stage[r][c];
+          }
+        if (k + C < n) issue_chunk(k + C);
+      }
+      const double rx = sprop[4 * k], ry = sprop[4 * k + 1], rz = sprop[4 * k + 2], u = sprop[4 * k + 3];
 
-      // determinant ratio (partial sums) and orbital row into LDS
+      // determinant ratio (partial sums over this thread's own row elements)
       T rpart = T(0);
-      for (int j = tid; j < n; j += kBlock) {
-        const T vj = vrow[j];
-        sv[j] = vj;
-        rpart += vj * Bm[(size_t)j * ldb + k];
+#pragma unroll
+      for (int c = 0; c < VPT; ++c) {
+        const int j = tid + c * kBlock;
+        if (j < n) rpart += vrow_l[j] * Bm[(size_t)j * ldb + k];
       }
       // Jastrow change (partial sums)
       const double xo = spos[3 * i], yo = spos[3 * i + 1], zo = spos[3 * i + 2];
@@ -115,21 +185,23 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, ui
           cx = spos[3 * j]; cy = spos[3 * j + 1]; cz = spos[3 * j + 2];
           kind = ((j < P.n_up) == up_i) ? 0 : 1;
         } else {
-          const double* ion = P.ions + 4 * (j - N);
+          const double* ion = ions + 4 * (j - N);
           cx = ion[0]; cy = ion[1]; cz = ion[2];
           kind = 2;
         }
-        double dx = min_image(rx - cx, P.L), dy = min_image(ry - cy, P.L), dz = min_image(rz - cz, P.L);
+        double dx = min_image_inv(rx - cx, L, invL), dy = min_image_inv(ry - cy, L, invL);
+        double dz = min_image_inv(rz - cz, L, invL);
         const double r1 = sqrt(dx * dx + dy * dy + dz * dz);
-        dx = min_image(xo - cx, P.L); dy = min_image(yo - cy, P.L); dz = min_image(zo - cz, P.L);
+        dx = min_image_inv(xo - cx, L, invL); dy = min_image_inv(yo - cy, L, invL);
+        dz = min_image_inv(zo - cz, L, invL);
         const double r0 = sqrt(dx * dx + dy * dy + dz * dz);
         dj += pair_u(sj, kind, r1) - pair_u(sj, kind, r0);
       }
       // block reduction in a fixed order (bitwise repeatable)
-      const double ra = wave_sum((double)rpart), rb = wave_sum(dj);
+      const double ra = wave_sum_dpp((double)rpart), rb = wave_sum_dpp(dj);
       double* rr = red + parity * 2 * kWaves;
       if (lane == 0) { rr[wave] = ra; rr[kWaves + wave] = rb; }
-      __syncthreads();
+      block_sync<BLDS>();
       double Rd = 0.0, dJ = 0.0;
 #pragma unroll
       for (int q = 0; q < kWaves; ++q) { Rd += rr[q]; dJ += rr[kWaves + q]; }
@@ -138,48 +210,55 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, ui
       const bool accept = u < (double)R * (double)R * exp(2.0 * dJ);
 
       if (accept) {
-        for (int m = tid; m < n; m += kBlock) {
+        for (int q = tid; q < n * tpc; q += kBlock) {
+          const int m = q / tpc, part = q - m * tpc;
           T acc = T(0);
-          for (int l = 0; l < n; ++l) acc += sv[l] * Bm[(size_t)l * ldb + m];
-          st[m] = acc - (m == k ? T(1) : T(0));
-          scol[m] = Bm[(size_t)m * ldb + k];
+          for (int l = part; l < n; l += tpc) acc += vrow_l[l] * Bm[(size_t)l * ldb + m];
+          for (int o = tpc >> 1; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+          if (part == 0) {
+            st[m] = acc - (m == k ? T(1) : T(0));
+            scol[m] = Bm[(size_t)m * ldb + k];
+          }
         }
-        __syncthreads();
+        block_sync<BLDS>();
         const T invR = T(1) / R;
-        for (int l = tid / 64; l < n; l += kWaves) {
+        for (int l = wave; l < n; l += kWaves) {
           const T cl = scol[l] * invR;
           T* row = Bm + (size_t)l * ldb;
           for (int m = lane; m < n; m += 64) row[m] -= cl * st[m];
         }
         if (tid == 0) {
           spos[3 * i] = rx; spos[3 * i + 1] = ry; spos[3 * i + 2] = rz;
-          Wk.cur[item] = (uint8_t)(1 - cb);
-          Wk.acc[item] = 1;
+          scur[k] = (uint8_t)(1 - scur[k]);
+          sacc[k] = 1;
         }
         ++nacc;
-        logd[sp] += log(fabs((double)R));
-        if (R < T(0)) sgn[sp] = -sgn[sp];
-        __syncthreads();
+        logd += log(fabs((double)R));
+        if (R < T(0)) sgn = -sgn;
+        block_sync<BLDS>();
       } else if (tid == 0) {
-        Wk.acc[item] = 0;
+        sacc[k] = 0;
       }
+    }
+    __syncthreads();
+    for (int q = tid; q < n; q += kBlock) {
+      Wk.cur[item0 + q] = scur[q];
+      Wk.acc[item0 + q] = sacc[q];
+    }
+    if (tid == 0) {
+      Wk.logdet[2 * w + sp] = logd;
+      Wk.sign[2 * w + sp] = sgn;
     }
     if (BLDS) {
       for (int q = tid; q < n * n; q += kBlock) {
         const int l = q / n;
         Bg[q] = sB[l * ldl + (q - l * n)];
       }
-      __syncthreads();
     }
+    __syncthreads();
   }
   for (int j = tid; j < 3 * N; j += kBlock) Wk.pos[(size_t)w * 3 * N + j] = spos[j];
-  if (tid == 0) {
-    Wk.logdet[2 * w] = logd[0];
-    Wk.logdet[2 * w + 1] = logd[1];
-    Wk.sign[2 * w] = sgn[0];
-    Wk.sign[2 * w + 1] = sgn[1];
-    Wk.nacc[w] = nacc;
-  }
+  if (tid == 0) Wk.nacc[w] = nacc;
 }
 
 static int lds_budget() {
@@ -195,31 +274,50 @@ static int lds_budget() {
   return budget;
 }
 
+static int vpt_of(int nmax) { return nmax <= kBlock ? 1 : (nmax <= 2 * kBlock ? 2 : 4); }
+
 size_t chain_lds_bytes(const SysParams& P, size_t tsize, bool b_in_lds) {
   const int nmax = P.n_up > P.n_dn ? P.n_up : P.n_dn;
+  return chain_layout(P.N, nmax, P.n_ions, nmax | 1, tsize, b_in_lds, 16 / vpt_of(nmax)).total;
+}
+
+template <typename T, bool BLDS, int VPT>
+static hipError_t launch_chain_variant(const SysParams& P, const Walkers<T>& Wk, uint32_t sweep,
+                                       hipStream_t st, size_t bytes, int ldl) {
+  if (bytes > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chain<T, BLDS, VPT>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_chain<T, BLDS, VPT>), dim3(P.W), dim3(kBlock), bytes, st, P, Wk, sweep, ldl);
+  return hipGetLastError();
+}
+
+template <typename T, int VPT>
+static hipError_t launch_chain_vpt(const SysParams& P, const Walkers<T>& Wk, uint32_t sweep, hipStream_t st) {
+  const int nmax = P.n_up > P.n_dn ? P.n_up : P.n_dn;
   const int ldl = nmax | 1;
-  if (tsize == sizeof(double)) return chain_layout<double>(P.N, nmax, ldl, b_in_lds).total;
-  return chain_layout<float>(P.N, nmax, ldl, b_in_lds).total;
+  const size_t with_b = chain_layout(P.N, nmax, P.n_ions, ldl, sizeof(T), true, 16 / VPT).total;
+  const size_t without_b = chain_layout(P.N, nmax, P.n_ions, ldl, sizeof(T), false, 16 / VPT).total;
+  // QMC_CHAIN_GLOBAL_INVERSE=1 keeps the inverse in global memory even when it fits
+  // LDS (lets the tests cover the large-system path on small systems).
+  const char* fg = getenv("QMC_CHAIN_GLOBAL_INVERSE");
+  const bool force_global = fg && fg[0] == '1';
+  if (!force_global && with_b + sizeof(Jastrow) <= (size_t)lds_budget())
+    return launch_chain_variant<T, true, VPT>(P, Wk, sweep, st, with_b, ldl);
+  if (without_b + sizeof(Jastrow) > (size_t)lds_budget()) return hipErrorInvalidValue;
+  return launch_chain_variant<T, false, VPT>(P, Wk, sweep, st, without_b, ldl);
 }
 
 template <typename T>
 hipError_t launch_chain(const SysParams& P, const Walkers<T>& Wk, uint32_t sweep, hipStream_t st) {
   const int nmax = P.n_up > P.n_dn ? P.n_up : P.n_dn;
-  const int ldl = nmax | 1;
-  const size_t with_b = chain_layout<T>(P.N, nmax, ldl, true).total + sizeof(Jastrow);
-  if (with_b <= (size_t)lds_budget()) {
-    const size_t bytes = chain_layout<T>(P.N, nmax, ldl, true).total;
-    if (bytes > 65536) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chain<T, true>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL((k_chain<T, true>), dim3(P.W), dim3(kBlock), bytes, st, P, Wk, sweep, ldl);
-  } else {
-    const size_t bytes = chain_layout<T>(P.N, nmax, ldl, false).total;
-    hipLaunchKernelGGL((k_chain<T, false>), dim3(P.W), dim3(kBlock), bytes, st, P, Wk, sweep, ldl);
+  if (nmax > 4 * kBlock) return hipErrorInvalidValue;
+  switch (vpt_of(nmax)) {
+    case 1: return launch_chain_vpt<T, 1>(P, Wk, sweep, st);
+    case 2: return launch_chain_vpt<T, 2>(P, Wk, sweep, st);
+    default: return launch_chain_vpt<T, 4>(P, Wk, sweep, st);
   }
-  return hipGetLastError();
 }
 
 template hipError_t launch_chain<double>(const SysParams&, const Walkers<double>&, uint32_t, hipStream_t);

@@ -3,36 +3,67 @@
 // Section "Hamiltonian": E_L = sum_n Psi^-1 H_n Psi, collected once all
 // walkers have advanced one step.  For Psi = D_up D_dn exp(J):
 //   T_L = -1/2 sum_i [ lap_i D / D + 2 grad_i ln D . grad_i J + lap_i J + |grad_i J|^2 ]
-// with grad_i ln D = sum_l B[l][k] grad phi_l(r_i), lap_i D / D =
-// sum_l B[l][k] lap phi_l(r_i) taken from the cached value/gradient/Laplacian
-// row of each electron (no spline evaluation here), and the Jastrow
+// with grad_i ln D = sum_l B[l][k] grad phi_l(r_i) and lap_i D / D =
+// sum_l B[l][k] lap phi_l(r_i) taken from each electron's cached
+// value/gradient/Laplacian row (no spline evaluation here), and the Jastrow
 // derivatives summed over electron and ion partners (section "Jastrow
 // factors").  The Coulomb terms (section "Long-Range Interactions") are Ewald
-// sums: real-space pairs with erfc screening over the 27 nearest images, and
-// a half-space reciprocal sum of |S(G)|^2 with the ions' S(G) precomputed.
+// sums with splitting kappa: erfc-screened pairs over every image closer than
+// the cutoff (one cell side), and the half-space reciprocal sum
+// sum_G w(G) |S(G)|^2 with S(G) built segment by segment along Gz: one sincos
+// per (segment, electron) and a complex recurrence for the next Gz.
+//
+// One workgroup per walker; every phase spreads over all 256 threads and
+// combines partial sums in a fixed order (bitwise repeatable).
 #include "qmc_kernels.hpp"
 
 namespace qmc {
+
+constexpr int kSeg = kEwaldSeg;
 
 __device__ __forceinline__ const Radial& pick(const Jastrow& J, int kind) {
   return kind == 0 ? J.same : (kind == 1 ? J.opp : J.ei);
 }
 
-// sum over the 27 images (d already minimum-imaged) of erfc(kappa r) / r, r < rcut
+// sum of erfc(kappa r) / r over the images of d (minimum-imaged) with r < rcut <= L:
+// per axis only the shift toward the nearer neighbouring cell can qualify.
 __device__ __forceinline__ double screened_images(double dx, double dy, double dz, double L,
                                                   double kappa, double rcut2) {
+  const double sx = dx > 0.0 ? -L : L, sy = dy > 0.0 ? -L : L, sz = dz > 0.0 ? -L : L;
   double s = 0.0;
-  for (int a = -1; a <= 1; ++a)
-    for (int b = -1; b <= 1; ++b)
-      for (int c = -1; c <= 1; ++c) {
-        const double x = dx + a * L, y = dy + b * L, z = dz + c * L;
-        const double r2 = x * x + y * y + z * z;
-        if (r2 < rcut2) {
-          const double r = sqrt(r2);
-          s += erfc(kappa * r) / r;
-        }
-      }
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const double x = dx + ((m & 1) ? sx : 0.0);
+    const double y = dy + ((m & 2) ? sy : 0.0);
+    const double z = dz + ((m & 4) ? sz : 0.0);
+    const double r2 = x * x + y * y + z * z;
+    if (r2 < rcut2) {
+      const double r = sqrt(r2);
+      s += erfc(kappa * r) / r;
+    }
+  }
   return s;
+}
+
+struct MeasureLayout {
+  size_t pos, ez, gd, ld, gjp, ljp, total;
+  int parts;   // Jastrow partner split per electron
+};
+
+__host__ __device__ inline MeasureLayout measure_layout(int N) {
+  MeasureLayout L;
+  int parts = 1;
+  while (parts * 2 * N <= kBlock) parts *= 2;
+  L.parts = parts;
+  size_t o = 0;
+  L.pos = o; o += sizeof(double) * 3 * N;
+  L.ez = o; o += sizeof(double) * 2 * N;
+  L.gd = o; o += sizeof(double) * 3 * N;
+  L.ld = o; o += sizeof(double) * N;
+  L.gjp = o; o += sizeof(double) * 3 * (size_t)N * parts;
+  L.ljp = o; o += sizeof(double) * (size_t)N * parts;
+  L.total = o;
+  return L;
 }
 
 template <typename T>
@@ -40,10 +71,16 @@ __global__ __launch_bounds__(kBlock) void k_measure(SysParams P, Walkers<T> Wk, 
                                                     double* __restrict__ out) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ Jastrow sj;
-  __shared__ double red[3 * kWaves];
+  __shared__ double red[5 * kWaves];
   const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = P.N;
-  double* spos = reinterpret_cast<double*>(smem);
+  const MeasureLayout lay = measure_layout(N);
+  double* spos = reinterpret_cast<double*>(smem + lay.pos);
+  double* sez = reinterpret_cast<double*>(smem + lay.ez);
+  double* sgd = reinterpret_cast<double*>(smem + lay.gd);
+  double* sld = reinterpret_cast<double*>(smem + lay.ld);
+  double* sgj = reinterpret_cast<double*>(smem + lay.gjp);
+  double* slj = reinterpret_cast<double*>(smem + lay.ljp);
   {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(&P.jas);
     uint32_t* dst = reinterpret_cast<uint32_t*>(&sj);
@@ -51,36 +88,51 @@ __global__ __launch_bounds__(kBlock) void k_measure(SysParams P, Walkers<T> Wk, 
   }
   for (int j = tid; j < 3 * N; j += kBlock) spos[j] = Wk.pos[(size_t)w * 3 * N + j];
   __syncthreads();
+  const double g0 = 2.0 * kPi / P.L;
+  if (E.enabled)
+    for (int i = tid; i < N; i += kBlock) {
+      double s, c;
+      sincos(g0 * spos[3 * i + 2], &s, &c);
+      sez[2 * i] = c;
+      sez[2 * i + 1] = s;
+    }
 
-  double tkin = 0.0, vee = 0.0, vei = 0.0;
-  const double rcut2 = E.rcut * E.rcut;
-  for (int i = tid; i < N; i += kBlock) {
+  // (1) determinant part: one wave per electron, lanes over orbitals (coalesced rows)
+  for (int i = wave; i < N; i += kWaves) {
     const int sp = i < P.n_up ? 0 : 1;
     const int n = sp ? P.n_dn : P.n_up, k = i - (sp ? P.n_up : 0);
     const size_t item = (size_t)w * N + i;
     const T* row = Wk.vgl + ((size_t)Wk.cur[item] * P.W * N + item) * kComp * P.S;
     const T* B = Wk.binv + (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0);
-    double gD[3] = {0.0, 0.0, 0.0}, lD = 0.0;
-    for (int l = 0; l < n; ++l) {
+    double gx = 0.0, gy = 0.0, gz = 0.0, l2 = 0.0;
+    for (int l = lane; l < n; l += 64) {
       const double b = (double)B[(size_t)l * n + k];
-      gD[0] += b * (double)row[P.S + l];
-      gD[1] += b * (double)row[2 * P.S + l];
-      gD[2] += b * (double)row[3 * P.S + l];
-      lD += b * (double)row[4 * P.S + l];
+      gx += b * (double)row[P.S + l];
+      gy += b * (double)row[2 * P.S + l];
+      gz += b * (double)row[3 * P.S + l];
+      l2 += b * (double)row[4 * P.S + l];
     }
+    gx = wave_sum_dpp(gx); gy = wave_sum_dpp(gy); gz = wave_sum_dpp(gz); l2 = wave_sum_dpp(l2);
+    if (lane == 0) { sgd[3 * i] = gx; sgd[3 * i + 1] = gy; sgd[3 * i + 2] = gz; sld[i] = l2; }
+  }
+
+  // (2) Jastrow gradient and Laplacian: (electron, part) items, partners j = part (mod parts)
+  const int parts = lay.parts;
+  for (int q = tid; q < N * parts; q += kBlock) {
+    const int i = q % N, part = q / N;
     const double xi = spos[3 * i], yi = spos[3 * i + 1], zi = spos[3 * i + 2];
     const bool up_i = i < P.n_up;
-    double gJ[3] = {0.0, 0.0, 0.0}, lJ = 0.0, ee = 0.0, ei = 0.0;
-    for (int j = 0; j < N + P.n_ions; ++j) {
+    double g[3] = {0.0, 0.0, 0.0}, lj = 0.0;
+    for (int j = part; j < N + P.n_ions; j += parts) {
       if (j == i) continue;
-      double cx, cy, cz, q = 0.0;
+      double cx, cy, cz;
       int kind;
       if (j < N) {
         cx = spos[3 * j]; cy = spos[3 * j + 1]; cz = spos[3 * j + 2];
         kind = ((j < P.n_up) == up_i) ? 0 : 1;
       } else {
         const double* ion = P.ions + 4 * (j - N);
-        cx = ion[0]; cy = ion[1]; cz = ion[2]; q = ion[3];
+        cx = ion[0]; cy = ion[1]; cz = ion[2];
         kind = 2;
       }
       const double dx = min_image(xi - cx, P.L), dy = min_image(yi - cy, P.L), dz = min_image(zi - cz, P.L);
@@ -88,51 +140,115 @@ __global__ __launch_bounds__(kBlock) void k_measure(SysParams P, Walkers<T> Wk, 
       double u, du, d2u;
       radial_eval(pick(sj, kind), r, u, du, d2u);
       const double f = du / r;
-      gJ[0] += f * dx; gJ[1] += f * dy; gJ[2] += f * dz;
-      lJ += d2u + 2.0 * f;
-      if (E.enabled) {
-        const double s = screened_images(dx, dy, dz, P.L, E.kappa, rcut2);
-        if (j < N) ee += 0.5 * s;
-        else ei -= q * s;
-      }
+      g[0] += f * dx; g[1] += f * dy; g[2] += f * dz;
+      lj += d2u + 2.0 * f;
     }
-    const double dot = gD[0] * gJ[0] + gD[1] * gJ[1] + gD[2] * gJ[2];
-    const double gJ2 = gJ[0] * gJ[0] + gJ[1] * gJ[1] + gJ[2] * gJ[2];
-    tkin += -0.5 * (lD + 2.0 * dot + lJ + gJ2);
-    vee += ee;
-    vei += ei;
+    double* gp = sgj + 3 * ((size_t)part * N + i);
+    gp[0] = g[0]; gp[1] = g[1]; gp[2] = g[2];
+    slj[(size_t)part * N + i] = lj;
   }
+
+  double vee = 0.0, vei = 0.0, vee_k = 0.0, vei_k = 0.0;
   if (E.enabled) {
-    for (int g = tid; g < E.n_g; g += kBlock) {
-      const double Gx = E.gvec[4 * g], Gy = E.gvec[4 * g + 1], Gz = E.gvec[4 * g + 2], wg = E.gvec[4 * g + 3];
-      double re = 0.0, im = 0.0;
+    const double rcut2 = E.rcut * E.rcut;
+    // (3a) electron pairs, each once: j = i + d (mod N), d = 1..(N-1)/2, and d = N/2 for i < N/2
+    const int D = (N - 1) / 2;
+    const int n_pairs = N * D + ((N % 2 == 0) ? N / 2 : 0);
+    for (int q = tid; q < n_pairs; q += kBlock) {
+      int i, j;
+      if (q < N * D) { i = q % N; j = i + q / N + 1; if (j >= N) j -= N; }
+      else { i = q - N * D; j = i + N / 2; }
+      const double dx = min_image(spos[3 * i] - spos[3 * j], P.L);
+      const double dy = min_image(spos[3 * i + 1] - spos[3 * j + 1], P.L);
+      const double dz = min_image(spos[3 * i + 2] - spos[3 * j + 2], P.L);
+      vee += screened_images(dx, dy, dz, P.L, E.kappa, rcut2);
+    }
+    // (3b) electron-ion pairs
+    for (int q = tid; q < N * P.n_ions; q += kBlock) {
+      const int i = q % N, I = q / N;
+      const double* ion = P.ions + 4 * I;
+      const double dx = min_image(spos[3 * i] - ion[0], P.L);
+      const double dy = min_image(spos[3 * i + 1] - ion[1], P.L);
+      const double dz = min_image(spos[3 * i + 2] - ion[2], P.L);
+      vei -= ion[3] * screened_images(dx, dy, dz, P.L, E.kappa, rcut2);
+    }
+    // (3c) reciprocal space: one item per segment of at most kSeg vectors of one
+    // (Gx, Gy) column; S(G) over all electrons, then w(G) |S|^2 and the cross term.
+    for (int q = tid; q < E.n_seg; q += kBlock) {
+      const int* seg = E.segs + 5 * q;
+      const int mx = seg[0], my = seg[1], lo = seg[2], cnt = seg[3] - seg[2] + 1, goff = seg[4];
+      double sr[kSeg], si[kSeg];
+#pragma unroll
+      for (int m = 0; m < kSeg; ++m) { sr[m] = 0.0; si[m] = 0.0; }
       for (int i = 0; i < N; ++i) {
-        double s, c;
-        sincos(Gx * spos[3 * i] + Gy * spos[3 * i + 1] + Gz * spos[3 * i + 2], &s, &c);
-        re -= c;   // electron charge -1
-        im -= s;
+        double br, bi;
+        sincos(g0 * (mx * spos[3 * i] + my * spos[3 * i + 1] + lo * spos[3 * i + 2]), &bi, &br);
+        const double er = sez[2 * i], ei = sez[2 * i + 1];
+#pragma unroll
+        for (int m = 0; m < kSeg; ++m) {
+          sr[m] += br;
+          si[m] += bi;
+          const double t = br * er - bi * ei;
+          bi = br * ei + bi * er;
+          br = t;
+        }
       }
-      vee += wg * (re * re + im * im);
-      vei += wg * 2.0 * (re * E.s_ion[2 * g] + im * E.s_ion[2 * g + 1]);
+#pragma unroll
+      for (int m = 0; m < kSeg; ++m) {
+        if (m < cnt) {
+          const double* gv = E.gvec + 4 * (goff + m);
+          const double re = -sr[m], im = -si[m];   // electron charge -1
+          vee_k += gv[3] * (re * re + im * im);
+          vei_k += gv[3] * 2.0 * (re * E.s_ion[2 * (goff + m)] + im * E.s_ion[2 * (goff + m) + 1]);
+        }
+      }
     }
   }
-  const double a = wave_sum(tkin), b = wave_sum(vee), c = wave_sum(vei);
-  if (lane == 0) { red[wave] = a; red[kWaves + wave] = b; red[2 * kWaves + wave] = c; }
+  __syncthreads();
+
+  // (4) per-electron kinetic term from (1) and (2)
+  double tkin = 0.0;
+  for (int i = tid; i < N; i += kBlock) {
+    double g[3] = {0.0, 0.0, 0.0}, lj = 0.0;
+    for (int part = 0; part < parts; ++part) {
+      const double* gp = sgj + 3 * ((size_t)part * N + i);
+      g[0] += gp[0]; g[1] += gp[1]; g[2] += gp[2];
+      lj += slj[(size_t)part * N + i];
+    }
+    const double dot = sgd[3 * i] * g[0] + sgd[3 * i + 1] * g[1] + sgd[3 * i + 2] * g[2];
+    tkin += -0.5 * (sld[i] + 2.0 * dot + lj + g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  }
+  const double a = wave_sum_dpp(tkin), b = wave_sum_dpp(vee), c = wave_sum_dpp(vei);
+  const double d = wave_sum_dpp(vee_k), e = wave_sum_dpp(vei_k);
+  if (lane == 0) {
+    red[wave] = a; red[kWaves + wave] = b; red[2 * kWaves + wave] = c;
+    red[3 * kWaves + wave] = d; red[4 * kWaves + wave] = e;
+  }
   __syncthreads();
   if (tid == 0) {
-    double t = 0.0, x = 0.0, y = 0.0;
-    for (int q = 0; q < kWaves; ++q) { t += red[q]; x += red[kWaves + q]; y += red[2 * kWaves + q]; }
+    double t = 0.0, x = 0.0, y = 0.0, xk = 0.0, yk = 0.0;
+    for (int q = 0; q < kWaves; ++q) {
+      t += red[q]; x += red[kWaves + q]; y += red[2 * kWaves + q];
+      xk += red[3 * kWaves + q]; yk += red[4 * kWaves + q];
+    }
     out[4 * w + 0] = t;
-    out[4 * w + 1] = E.enabled ? x + E.c_ee : 0.0;
-    out[4 * w + 2] = E.enabled ? y + E.c_ei : 0.0;
+    out[4 * w + 1] = E.enabled ? (x + xk) + E.c_ee : 0.0;
+    out[4 * w + 2] = E.enabled ? (y + yk) + E.c_ei : 0.0;
     out[4 * w + 3] = E.enabled ? E.v_ii : 0.0;
   }
 }
 
+size_t measure_lds_bytes(const SysParams& P) { return measure_layout(P.N).total; }
+
 template <typename T>
 hipError_t launch_measure(const SysParams& P, const Walkers<T>& Wk, const EwaldParams& E, double* out,
                           hipStream_t st) {
-  const size_t bytes = sizeof(double) * 3 * (size_t)P.N;
+  const size_t bytes = measure_layout(P.N).total;
+  if (bytes > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_measure<T>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_measure<T>, dim3(P.W), dim3(kBlock), bytes, st, P, Wk, E, out);
   return hipGetLastError();
 }

@@ -183,4 +183,40 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// One DPP step: v + (the value of the lane selected by ctrl), for the rows in
+// row_mask (other rows add zero).  Works on the two 32-bit halves of a double.
+template <int ctrl, int row_mask>
+__device__ __forceinline__ double dpp_add(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, ctrl, row_mask, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), ctrl, row_mask, 0xF, false);
+  return v + __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Wave64 sum through the data-parallel-primitive lane network (no LDS round
+// trips): pairs, quads, half rows and rows of 16, then the two row
+// broadcasts carry the partial sums up to lane 63, read back as a uniform
+// value.  All 64 lanes must be active.  The summation order is fixed.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v = dpp_add<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  v = dpp_add<0x141, 0xF>(v);   // row_half_mirror
+  v = dpp_add<0x140, 0xF>(v);   // row_mirror
+  v = dpp_add<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Workgroup barrier that orders LDS only: outstanding global loads (e.g. a
+// prefetch) stay in flight across it.  Use __syncthreads() where global
+// memory written by one wave is read by another.
+__device__ __forceinline__ void sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 }  // namespace qmc

@@ -8,12 +8,15 @@ namespace qmc {
 
 // Ewald-sum constants of one system (splitting parameter kappa, reciprocal
 // vectors of one half space with their weights, the ions' structure factor).
+constexpr int kEwaldSeg = 10;   // reciprocal vectors per segment of a (Gx, Gy) column
+
 struct EwaldParams {
   int enabled;
-  int n_g;
+  int n_g, n_seg;
   double kappa, rcut;
   const double* gvec;    // [n_g][4]: Gx, Gy, Gz, (4 pi / V) exp(-G^2 / 4 kappa^2) / G^2
   const double* s_ion;   // [n_g][2]: sum_I Z_I exp(i G.R_I)
+  const int* segs;       // [n_seg][5]: mx, my, mz_lo, mz_hi, index of the first vector in gvec
   double c_ee;           // electron self, self-image and background terms
   double c_ei;           // electron-ion background cross term
   double v_ii;           // ion-ion energy (constant)

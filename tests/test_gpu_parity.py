@@ -200,3 +200,19 @@ def test_acceptance_counter(gpu):
     bits = s.accept_log()
     s.close()
     assert n == int(bits.sum())
+
+
+def test_global_memory_inverse_path(gpu, orc, monkeypatch):
+    """The chain with the inverse kept in global memory (the path of large spin blocks)."""
+    monkeypatch.setenv("QMC_CHAIN_GLOBAL_INVERSE", "1")
+    wl = qi.solid(40, 16, n_walkers=12, n_sweeps=1)
+    _compare_run(gpu, orc, wl, 6, range(12))
+
+
+def test_many_ions_and_odd_sizes(gpu, orc):
+    """More ions than fit the chain's LDS staging (read from global memory), 3 up / 2 down."""
+    wl = qi.solid(20, 10, n_walkers=4, n_sweeps=1, ions_per_elec=14.0, Z=0.5)
+    wl.n_up, wl.n_dn, wl.n_orb = 3, 2, 3
+    wl.coefs = qi.solid_table(3, 10, seed=5, dtype=np.float64)
+    assert wl.n_ions > 256
+    _compare_run(gpu, orc, wl, 5, range(4))
