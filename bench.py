@@ -80,6 +80,8 @@ def main(argv=None) -> int:
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="solid128", help="solid128 | heg14 | mixed384")
+    ap.add_argument("--delay", type=int, default=None,
+                    help="delay rank K (1 = Sherman-Morrison; 4..64 = delayed updates)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args(argv)
@@ -99,6 +101,8 @@ def main(argv=None) -> int:
         return 2
     torch.cuda.set_device(0)
     wl = qi.WORKLOADS[args.workload]()
+    if args.delay is not None:
+        wl.delay_rank = args.delay
     print(f"[bench] building {wl.name}", file=sys.stderr, flush=True)
     s = System(wl)
     W, N = s.W, wl.n_elec

@@ -66,7 +66,11 @@ typedef enum { QMC_H_KINETIC = 0, QMC_H_COULOMB_EWALD = 1 } qmc_hamiltonian;
  *  precision      QMC_FP64: table, orbital values and inverse in FP64.
  *                 QMC_MIXED: FP32 table, values, ratios and inverse; FP64
  *                 positions, Jastrow, log-determinant and energy sums.
- *  delay_rank     1 = Sherman-Morrison after every accepted move
+ *  delay_rank     1 (or 0) = Sherman-Morrison after every accepted move;
+ *                 K = 4, 8, 16, 32 or 64 = delayed update (section "Multi-
+ *                 Determinant Slater-Jastrow Form"): windows of K moves share
+ *                 one inverse, ratios come from Y = V B0 by Schur complements
+ *                 and accepted rows are applied by one rank-m product per window
  *  recompute_period  sweeps between full FP64 inverse rebuilds (0 = never)
  *  sigma          Gaussian proposal width (bohr); the transition probability
  *                 has no drift, so it cancels in the acceptance
@@ -166,6 +170,11 @@ qmc_status qmc_get_walkers(qmc_system s, double* pos, double* logabs_det, int32_
 
 /* Accept flags of the last sweep, host [W][N], 1 = accepted. */
 qmc_status qmc_get_accept_log(qmc_system s, uint8_t* bits);
+
+/* Counters since qmc_init_walkers (each nullable): redecided = moves whose
+ * acceptance fell inside the mixed-precision guard band and was decided again
+ * from an FP64 ratio; sweeps = sweeps run.  Synchronises. */
+qmc_status qmc_get_counters(qmc_system s, uint64_t* redecided, uint64_t* sweeps);
 
 /* Rebuild every inverse from scratch in FP64 and reset log|D|.  drift_out
  * (nullable, host [W][2]): accumulated log|D| minus the rebuilt one. */

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -100,10 +101,13 @@ struct qmc_system_s {
   uint8_t* acc = nullptr;
   uint32_t* nacc = nullptr;
   int* status = nullptr;
+  double* val64 = nullptr;
+  uint32_t* nguard = nullptr;
   double* scratch = nullptr;
   double* drift = nullptr;
   double* energy = nullptr;
   bool timing = false;
+  int use_mfma = 1;   // delayed-update products on the matrix cores (QMC_DELAYED_VALU=1: vector ALU)
   TimerClass timers[4];
 };
 
@@ -132,7 +136,7 @@ Walkers<T> walkers_of(qmc_system s) {
   Walkers<T> w;
   w.pos = s->pos; w.prop = s->prop; w.vgl = static_cast<T*>(s->vgl); w.cur = s->cur;
   w.binv = static_cast<T*>(s->binv); w.logdet = s->logdet; w.sign = s->sign; w.acc = s->acc;
-  w.nacc = s->nacc; w.status = s->status;
+  w.nacc = s->nacc; w.status = s->status; w.val64 = s->val64; w.nguard = s->nguard;
   return w;
 }
 
@@ -261,14 +265,16 @@ void free_walkers(qmc_system s) {
   s->logdet = s->scratch = s->drift = s->energy = nullptr;
   s->sign = s->status = nullptr;
   s->nacc = nullptr;
+  s->val64 = nullptr;
+  s->nguard = nullptr;
 }
 
 struct WalkerSizes {
-  size_t pos, prop, vgl, cur, binv, logdet, sign, acc, nacc, status, scratch, drift, energy;
+  size_t pos, prop, vgl, cur, binv, logdet, sign, acc, nacc, status, scratch, drift, energy, val64, nguard;
   size_t total() const {
     return align_up(pos) + align_up(prop) + align_up(vgl) + align_up(cur) + align_up(binv) +
            align_up(logdet) + align_up(sign) + align_up(acc) + align_up(nacc) + align_up(status) +
-           align_up(scratch) + align_up(drift) + align_up(energy);
+           align_up(scratch) + align_up(drift) + align_up(energy) + align_up(val64) + align_up(nguard);
   }
 };
 
@@ -289,6 +295,8 @@ WalkerSizes walker_sizes(int n_up, int n_dn, int precision, int W, int n_orb) {
   z.scratch = W * bs * sizeof(double);
   z.drift = W * 2 * sizeof(double);
   z.energy = W * 4 * sizeof(double);
+  z.val64 = precision == QMC_MIXED ? 2 * W * N * S * sizeof(double) : 0;
+  z.nguard = W * sizeof(uint32_t);
   return z;
 }
 
@@ -310,8 +318,10 @@ qmc_status validate(const qmc_system_desc* d) {
   if (!(d->sigma > 0.0)) return fail(nullptr, QMC_ERR_ARG, "sigma must be positive");
   if (d->precision != QMC_FP64 && d->precision != QMC_MIXED)
     return fail(nullptr, QMC_ERR_ARG, "unknown precision %d", d->precision);
-  if (d->delay_rank != 1 && d->delay_rank != 0)
-    return fail(nullptr, QMC_ERR_ARG, "delay_rank %d: only 1 (Sherman-Morrison) is available", d->delay_rank);
+  if (d->delay_rank < 0 || d->delay_rank == 2 || d->delay_rank == 3 || d->delay_rank > 64 ||
+      (d->delay_rank > 1 && (d->delay_rank & (d->delay_rank - 1))))
+    return fail(nullptr, QMC_ERR_ARG, "delay_rank %d: use 1 (Sherman-Morrison) or a power of two in [4, 64]",
+                d->delay_rank);
   if (d->recompute_period < 0) return fail(nullptr, QMC_ERR_ARG, "recompute_period must be >= 0");
   if (d->hamiltonian != QMC_H_KINETIC && d->hamiltonian != QMC_H_COULOMB_EWALD)
     return fail(nullptr, QMC_ERR_ARG, "unknown hamiltonian %d", d->hamiltonian);
@@ -352,6 +362,11 @@ qmc_status qmc_create_system(const qmc_system_desc* desc, void* hip_stream, qmc_
   qmc_system s = new (std::nothrow) qmc_system_s;
   if (!s) return fail(nullptr, QMC_ERR_OOM, "host allocation failed");
   s->d = *desc;
+  if (s->d.delay_rank == 0) s->d.delay_rank = 1;
+  {
+    const char* v = getenv("QMC_DELAYED_VALU");
+    s->use_mfma = !(v && v[0] == '1');
+  }
   s->stream = static_cast<hipStream_t>(hip_stream);
   if (hipGetDevice(&s->device) != hipSuccess) {
     delete s;
@@ -384,6 +399,7 @@ qmc_status qmc_create_system(const qmc_system_desc* desc, void* hip_stream, qmc_
   P.bstride = desc->n_up * desc->n_up + desc->n_dn * desc->n_dn;
   P.L = desc->L;
   P.sigma = desc->sigma;
+  P.tie_guard = desc->tie_guard > 0.0 ? desc->tie_guard : 1e-3;
   P.key0 = (uint32_t)desc->seed;
   P.key1 = (uint32_t)(desc->seed >> 32);
   const double* j2p = desc->j2_params;
@@ -533,8 +549,11 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
   s->scratch = static_cast<double*>(s->mem.alloc(z.scratch));
   s->drift = static_cast<double*>(s->mem.alloc(z.drift));
   s->energy = static_cast<double*>(s->mem.alloc(z.energy));
+  s->nguard = static_cast<uint32_t*>(s->mem.alloc(z.nguard));
+  if (s->d.precision == QMC_MIXED) s->val64 = static_cast<double*>(s->mem.alloc(z.val64));
   if (!s->pos || !s->prop || !s->vgl || !s->cur || !s->binv || !s->logdet || !s->sign || !s->acc ||
-      !s->nacc || !s->status || !s->scratch || !s->drift || !s->energy) {
+      !s->nacc || !s->status || !s->scratch || !s->drift || !s->energy || !s->nguard ||
+      (s->d.precision == QMC_MIXED && !s->val64)) {
     free_walkers(s);
     return fail(s, QMC_ERR_OOM, "device allocation of %zu walker bytes failed", z.total());
   }
@@ -553,6 +572,7 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
     HIP_TRY(s, launch_init_positions(s->P, s->pos, s->stream));
   }
   HIP_TRY(s, hipMemsetAsync(s->status, 0, z.status, s->stream));
+  HIP_TRY(s, hipMemsetAsync(s->nguard, 0, z.nguard, s->stream));
   HIP_TRY(s, hipMemsetAsync(s->acc, 0, z.acc, s->stream));
   HIP_TRY(s, hipMemsetAsync(s->logdet, 0, z.logdet, s->stream));
   hipError_t e;
@@ -579,12 +599,22 @@ qmc_status qmc_sweep(qmc_system s, int32_t n_sweeps, uint64_t* n_accepted_out) {
   for (int it = 0; it < n_sweeps; ++it) {
     const uint32_t sw = s->sweep_index;
     hipError_t e;
+    const int K = s->d.delay_rank;
+    const int mfma = s->use_mfma;
     if (s->d.precision == QMC_MIXED) {
       e = timed(s, 0, [&] { return launch_gather<float>(s->P, walkers_of<float>(s), static_cast<const float*>(s->d_table), sw, 0, s->stream); });
-      if (e == hipSuccess) e = timed(s, 1, [&] { return launch_chain<float>(s->P, walkers_of<float>(s), sw, s->stream); });
+      if (e == hipSuccess)
+        e = timed(s, 1, [&] {
+          return K > 1 ? launch_chain_delayed<float>(s->P, walkers_of<float>(s), sw, K, mfma, s->stream)
+                       : launch_chain<float>(s->P, walkers_of<float>(s), sw, s->stream);
+        });
     } else {
       e = timed(s, 0, [&] { return launch_gather<double>(s->P, walkers_of<double>(s), static_cast<const double*>(s->d_table), sw, 0, s->stream); });
-      if (e == hipSuccess) e = timed(s, 1, [&] { return launch_chain<double>(s->P, walkers_of<double>(s), sw, s->stream); });
+      if (e == hipSuccess)
+        e = timed(s, 1, [&] {
+          return K > 1 ? launch_chain_delayed<double>(s->P, walkers_of<double>(s), sw, K, mfma, s->stream)
+                       : launch_chain<double>(s->P, walkers_of<double>(s), sw, s->stream);
+        });
     }
     if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "sweep launch: %s", hipGetErrorString(e));
     s->sweep_index = sw + 1;
@@ -643,6 +673,22 @@ qmc_status qmc_get_accept_log(qmc_system s, uint8_t* bits) {
   HIP_TRY(s, hipSetDevice(s->device));
   HIP_TRY(s, hipMemcpyAsync(bits, s->acc, (size_t)s->P.W * s->P.N, hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(s, hipStreamSynchronize(s->stream));
+  return QMC_OK;
+}
+
+qmc_status qmc_get_counters(qmc_system s, uint64_t* redecided, uint64_t* sweeps) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (!s->has_walkers) return fail(s, QMC_ERR_STATE, "init_walkers first");
+  HIP_TRY(s, hipSetDevice(s->device));
+  if (redecided) {
+    std::vector<uint32_t> g(s->P.W);
+    HIP_TRY(s, hipMemcpyAsync(g.data(), s->nguard, g.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    uint64_t t = 0;
+    for (uint32_t v : g) t += v;
+    *redecided = t;
+  }
+  if (sweeps) *sweeps = s->sweep_index;
   return QMC_OK;
 }
 

@@ -19,6 +19,7 @@
 // chunk of moves to arrive, hiding the HBM latency.
 #include <cstdlib>
 
+#include "qmc_guard.hpp"
 #include "qmc_kernels.hpp"
 
 namespace qmc {
@@ -26,7 +27,7 @@ namespace qmc {
 constexpr int kLdsIons = 256;     // ions staged in LDS up to this count
 
 struct ChainLayout {
-  size_t pos, prop, ions, red, vbuf, col, t, cur, acc, b, total;
+  size_t pos, prop, ions, red, vbuf, col, t, cur, acc, gx, gr, b, total;
 };
 
 __host__ __device__ inline ChainLayout chain_layout(int N, int nmax, int n_ions, int ldl, size_t ts,
@@ -36,7 +37,7 @@ __host__ __device__ inline ChainLayout chain_layout(int N, int nmax, int n_ions,
   L.pos = o; o += sizeof(double) * 3 * N;
   L.prop = o; o += sizeof(double) * 4 * nmax;
   L.ions = o; o += (n_ions <= kLdsIons) ? sizeof(double) * 4 * n_ions : 0;
-  L.red = o; o += sizeof(double) * 4 * kWaves;
+  L.red = o; o += sizeof(double) * 5 * kWaves;
   o = (o + 15) & ~size_t(15);
   L.vbuf = o; o += ts * (size_t)2 * rows_per_chunk * nmax;
   o = (o + 15) & ~size_t(15);
@@ -47,6 +48,8 @@ __host__ __device__ inline ChainLayout chain_layout(int N, int nmax, int n_ions,
   L.cur = o; o += nmax;
   L.acc = o; o += nmax;
   o = (o + 15) & ~size_t(15);
+  L.gx = o; o += (ts == 4) ? sizeof(double) * nmax : 0;   // FP64 re-decision scratch (mixed)
+  L.gr = o; o += (ts == 4) ? sizeof(double) * nmax : 0;
   L.b = o; o += b_in_lds ? ts * (size_t)nmax * ldl : 0;
   L.total = o;
   return L;
@@ -89,6 +92,8 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, ui
   T* st = reinterpret_cast<T*>(smem + lay.t);
   uint8_t* scur = smem + lay.cur;
   uint8_t* sacc = smem + lay.acc;
+  double* sgx = reinterpret_cast<double*>(smem + lay.gx);
+  double* sgr = reinterpret_cast<double*>(smem + lay.gr);
   T* sB = reinterpret_cast<T*>(smem + lay.b);
   const double L = P.L, invL = 1.0 / P.L;
 
@@ -100,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, ui
   for (int j = tid; j < 3 * N; j += kBlock) spos[j] = Wk.pos[(size_t)w * 3 * N + j];
   if (ions_lds)
     for (int j = tid; j < 4 * P.n_ions; j += kBlock) sion[j] = P.ions[j];
-  uint32_t nacc = 0;
+  uint32_t nacc = 0, nguard = 0;
   int parity = 0;
 
   for (int sp = 0; sp < 2; ++sp) {
@@ -207,7 +212,19 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, ui
       for (int q = 0; q < kWaves; ++q) { Rd += rr[q]; dJ += rr[kWaves + q]; }
       parity ^= 1;
       const T R = (T)Rd;
-      const bool accept = u < (double)R * (double)R * exp(2.0 * dJ);
+      const double ej = exp(2.0 * dJ);
+      const double p32 = (double)R * (double)R * ej;
+      double Rlog = (double)R;
+      bool accept;
+      if (sizeof(T) == 4 && fabs(u - p32) <= P.tie_guard * p32) {
+        // near tie in FP32: decide again with an FP64 ratio (uniform branch)
+        const double* v64 = Wk.val64 + ((size_t)(1 - scur[k]) * P.W * N + item0 + k) * P.S;
+        Rlog = refined_ratio<T>(P, Wk, Bm, ldb, n, item0, scur, v64, k, sgx, sgr, red + 2 * 2 * kWaves, tid);
+        accept = u < Rlog * Rlog * ej;
+        ++nguard;
+      } else {
+        accept = u < p32;
+      }
 
       if (accept) {
         for (int q = tid; q < n * tpc; q += kBlock) {
@@ -233,8 +250,8 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, ui
           sacc[k] = 1;
         }
         ++nacc;
-        logd += log(fabs((double)R));
-        if (R < T(0)) sgn = -sgn;
+        logd += log(fabs(Rlog));
+        if (Rlog < 0.0) sgn = -sgn;
         block_sync<BLDS>();
       } else if (tid == 0) {
         sacc[k] = 0;
@@ -258,7 +275,10 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, ui
     __syncthreads();
   }
   for (int j = tid; j < 3 * N; j += kBlock) Wk.pos[(size_t)w * 3 * N + j] = spos[j];
-  if (tid == 0) Wk.nacc[w] = nacc;
+  if (tid == 0) {
+    Wk.nacc[w] = nacc;
+    Wk.nguard[w] += nguard;
+  }
 }
 
 static int lds_budget() {

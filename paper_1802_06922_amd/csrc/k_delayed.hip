@@ -1,0 +1,550 @@
+// k_delayed.hip -- the move chain with rank-K delayed inverse updates.
+//
+// Section "Multi-Determinant Slater-Jastrow Form" names two ways of keeping
+// the inverse current: single-row Sherman-Morrison updates and a delayed
+// update that defers accepted row changes and applies them with
+// matrix-matrix products (section "Performance and Parallel Scaling").  This
+// kernel implements the delayed form in its Woodbury algebra, organised
+// around the fact that every proposal row of a sweep is already known when
+// the chain runs (the gather kernel evaluated them all).
+//
+// Window of K consecutive moves of one spin block, inverse B0 at its start,
+// proposal rows v_q (q = 0..K-1, electron p = k0 + q):
+//   Y = V B0                       (K x n: one matrix product per window)
+// After m accepted moves (electrons P = p_1..p_m, window slots Q), with
+//   C = Y[Q, P]   (m x m; the Woodbury capacitance I + Delta B0 E_P)
+// the ratio of the next proposal (slot q, electron p) is the Schur complement
+//   R = Y[q][p] - Y[q, P] C^-1 Y[Q, p]
+// and acceptance borders C^-1 by one row and column.  At the window end the
+// inverse becomes
+//   B = B0 - B0[:, P] C^-1 (Y[Q, :] - E_P^T)      (rank-m product)
+// which equals m successive Sherman-Morrison updates in exact arithmetic.
+//
+// The Jastrow change splits the same way: partners outside the window do not
+// move during it, so their terms are summed for all K moves at once; only the
+// K x K in-window terms depend on earlier decisions of the window, and both of
+// their possible values are precomputed.
+//
+// Per window: a parallel phase (window rows, Jastrow sums, Y on the matrix
+// cores), a sequential phase in one wave (O(m^2 + K) per move, no workgroup
+// barriers), and the flush product on the matrix cores.
+#include <cstdlib>
+
+#include "qmc_guard.hpp"
+#include "qmc_kernels.hpp"
+
+namespace qmc {
+
+constexpr int kMaxWindow = 64;
+constexpr int kLdsIonsD = 256;
+
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+struct DLayout {
+  size_t pos, prop, ions, red, gold, gdiff, cur, acc, plist, qlist, vec, cinv, vwin, ywin, zwin, gx, gr, grow, b,
+      total;
+};
+
+__host__ __device__ inline int round16(int x) { return (x + 15) & ~15; }
+
+__host__ __device__ inline DLayout dlayout(int N, int nmax, int n_ions, int ldl, size_t ts, bool b_in_lds,
+                                           int K) {
+  DLayout L;
+  const int nP = round16(nmax);
+  size_t o = 0;
+  auto al = [&](size_t a) { o = (o + a - 1) & ~(a - 1); };
+  L.pos = o; o += sizeof(double) * 3 * N;
+  L.prop = o; o += sizeof(double) * 4 * nmax;
+  L.ions = o; o += (n_ions <= kLdsIonsD) ? sizeof(double) * 4 * n_ions : 0;
+  L.red = o; o += sizeof(double) * kBlock;
+  L.gold = o; o += sizeof(double) * K * K;
+  L.gdiff = o; o += sizeof(double) * K * K;
+  L.cur = o; o += nmax;
+  L.acc = o; o += nmax;
+  al(16);
+  L.plist = o; o += sizeof(int) * K;
+  L.qlist = o; o += sizeof(int) * K;
+  al(16);
+  L.vec = o; o += ts * 4 * kMaxWindow;
+  al(16);
+  L.cinv = o; o += ts * K * K;
+  al(16);
+  L.vwin = o; o += ts * (size_t)K * nP;    // also holds U = B0[:, P] (n x K) during the flush
+  al(16);
+  L.ywin = o; o += ts * (size_t)K * nP;
+  al(16);
+  L.zwin = o; o += ts * (size_t)K * nP;
+  al(16);
+  L.gx = o; o += (ts == 4) ? sizeof(double) * nmax : 0;   // FP64 re-decision scratch (mixed)
+  L.gr = o; o += (ts == 4) ? sizeof(double) * nmax : 0;
+  L.grow = o; o += (ts == 4) ? ts * (size_t)nP : 0;        // the re-decided move's row
+  al(16);
+  L.b = o; o += b_in_lds ? ts * (size_t)nmax * ldl : 0;
+  L.total = o;
+  return L;
+}
+
+template <bool BLDS>
+__device__ __forceinline__ void dsync() {
+  if (BLDS) sync_lds();
+  else __syncthreads();
+}
+
+// Orders this wave's LDS writes before its later LDS reads (lanes read what
+// other lanes of the same wave wrote).
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double ju(const Jastrow& J, int kind, double r) {
+  return kind == 0 ? radial_value(J.same, r) : (kind == 1 ? radial_value(J.opp, r) : radial_value(J.ei, r));
+}
+
+__device__ __forceinline__ double dist(double ax, double ay, double az, double bx, double by, double bz,
+                                       double L, double invL) {
+  double dx = ax - bx, dy = ay - by, dz = az - bz;
+  dx -= L * rint(dx * invL);
+  dy -= L * rint(dy * invL);
+  dz -= L * rint(dz * invL);
+  return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+// Y[q][c] = sum_l V[q][l] B[l][c] for q < Kw, c < n (all threads of the block).
+template <typename T, bool MF>
+__device__ __forceinline__ void gemm_window(const T* V, const T* B, int ldb, T* Y, int Kw, int n, int nP,
+                                            int tid) {
+  if (MF) {
+    const int lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int tq = (Kw + 15) >> 4, tc = (n + 15) >> 4;
+    for (int t = wave; t < tq * tc; t += kWaves) {
+      const int q0 = (t / tc) * 16, c0 = (t % tc) * 16;
+      typename Mfma<T>::v4 acc = {T(0), T(0), T(0), T(0)};
+      const int qa = q0 + li, cb = c0 + li;
+      for (int l0 = 0; l0 < n; l0 += 4) {
+        const int l = l0 + lk;
+        const T a = (qa < Kw && l < n) ? V[(size_t)qa * nP + l] : T(0);
+        const T b = (l < n && cb < n) ? B[(size_t)l * ldb + cb] : T(0);
+        acc = Mfma<T>::mma(a, b, acc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = q0 + 4 * lk + r;
+        if (q < Kw && cb < n) Y[(size_t)q * nP + cb] = acc[r];
+      }
+    }
+  } else {
+    for (int idx = tid; idx < Kw * n; idx += kBlock) {
+      const int q = idx / n, c = idx - q * n;
+      T acc = T(0);
+      for (int l = 0; l < n; ++l) acc += V[(size_t)q * nP + l] * B[(size_t)l * ldb + c];
+      Y[(size_t)q * nP + c] = acc;
+    }
+  }
+}
+
+// B[l][c] -= sum_r U[l][r] Z[r][c] for l, c < n, r < mP (U, Z zero-padded to mP).
+template <typename T, bool MF>
+__device__ __forceinline__ void gemm_flush(T* B, int ldb, const T* U, int ldu, const T* Z, int nP, int n,
+                                           int mP, int tid) {
+  if (MF) {
+    const int lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int tt = (n + 15) >> 4;
+    for (int t = wave; t < tt * tt; t += kWaves) {
+      const int l0 = (t / tt) * 16, c0 = (t % tt) * 16;
+      typename Mfma<T>::v4 acc = {T(0), T(0), T(0), T(0)};
+      const int la = l0 + li, cb = c0 + li;
+      for (int r0 = 0; r0 < mP; r0 += 4) {
+        const int r = r0 + lk;
+        const T a = (la < n) ? U[(size_t)la * ldu + r] : T(0);
+        const T b = (cb < n) ? Z[(size_t)r * nP + cb] : T(0);
+        acc = Mfma<T>::mma(a, b, acc);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int l = l0 + 4 * lk + q;
+        if (l < n && cb < n) B[(size_t)l * ldb + cb] -= acc[q];
+      }
+    }
+  } else {
+    for (int idx = tid; idx < n * n; idx += kBlock) {
+      const int l = idx / n, c = idx - l * n;
+      T acc = T(0);
+      for (int r = 0; r < mP; ++r) acc += U[(size_t)l * ldu + r] * Z[(size_t)r * nP + c];
+      B[(size_t)l * ldb + c] -= acc;
+    }
+  }
+}
+
+template <typename T, bool BLDS, bool MF>
+__global__ __launch_bounds__(kBlock) void k_chain_delayed(SysParams P, Walkers<T> Wk, uint32_t sweep, int K,
+                                                          int ldl) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ Jastrow sj;
+  __shared__ int sm_m, sm_stop;
+  __shared__ double sm_dj;
+  const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int N = P.N, nmax = P.n_up > P.n_dn ? P.n_up : P.n_dn, nP = round16(nmax);
+  const DLayout lay = dlayout(N, nmax, P.n_ions, ldl, sizeof(T), BLDS, K);
+  double* spos = reinterpret_cast<double*>(smem + lay.pos);
+  double* sprop = reinterpret_cast<double*>(smem + lay.prop);
+  const bool ions_lds = P.n_ions <= kLdsIonsD;
+  double* sion = reinterpret_cast<double*>(smem + lay.ions);
+  const double* ions = ions_lds ? sion : P.ions;
+  double* red = reinterpret_cast<double*>(smem + lay.red);
+  double* gold = reinterpret_cast<double*>(smem + lay.gold);
+  double* gdiff = reinterpret_cast<double*>(smem + lay.gdiff);
+  uint8_t* scur = smem + lay.cur;
+  uint8_t* sacc = smem + lay.acc;
+  int* plist = reinterpret_cast<int*>(smem + lay.plist);
+  int* qlist = reinterpret_cast<int*>(smem + lay.qlist);
+  T* sa = reinterpret_cast<T*>(smem + lay.vec);
+  T* sb = sa + kMaxWindow;
+  T* sx = sb + kMaxWindow;
+  T* sy = sx + kMaxWindow;
+  T* cinv = reinterpret_cast<T*>(smem + lay.cinv);
+  T* vwin = reinterpret_cast<T*>(smem + lay.vwin);
+  T* ubuf = vwin;
+  T* ywin = reinterpret_cast<T*>(smem + lay.ywin);
+  T* zwin = reinterpret_cast<T*>(smem + lay.zwin);
+  double* sgx = reinterpret_cast<double*>(smem + lay.gx);
+  double* sgr = reinterpret_cast<double*>(smem + lay.gr);
+  T* sgrow = reinterpret_cast<T*>(smem + lay.grow);
+  T* sB = reinterpret_cast<T*>(smem + lay.b);
+  const double L = P.L, invL = 1.0 / P.L;
+  const int tpq = kBlock / K;   // threads per window slot in the Jastrow sums
+
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(&P.jas);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&sj);
+    for (int q = tid; q < (int)(sizeof(Jastrow) / 4); q += kBlock) dst[q] = src[q];
+  }
+  for (int j = tid; j < 3 * N; j += kBlock) spos[j] = Wk.pos[(size_t)w * 3 * N + j];
+  if (ions_lds)
+    for (int j = tid; j < 4 * P.n_ions; j += kBlock) sion[j] = P.ions[j];
+  uint32_t nacc = 0, nguard = 0;
+
+  for (int sp = 0; sp < 2; ++sp) {
+    const int n = sp ? P.n_dn : P.n_up;
+    const int off = sp ? P.n_up : 0;
+    if (n == 0) continue;
+    const size_t item0 = (size_t)w * N + off;
+    double logd = Wk.logdet[2 * w + sp];
+    int sgn = Wk.sign[2 * w + sp];
+    for (int q = tid; q < 4 * n; q += kBlock) sprop[q] = Wk.prop[item0 * 4 + q];
+    for (int q = tid; q < n; q += kBlock) scur[q] = Wk.cur[item0 + q];
+    T* Bg = Wk.binv + (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0);
+    T* Bm;
+    int ldb;
+    if (BLDS) {
+      for (int q = tid; q < n * n; q += kBlock) {
+        const int l = q / n;
+        sB[l * ldl + (q - l * n)] = Bg[q];
+      }
+      Bm = sB;
+      ldb = ldl;
+    } else {
+      Bm = Bg;
+      ldb = n;
+    }
+    const bool up_block = sp == 0;
+
+    for (int k0 = 0; k0 < n;) {
+      const int Kw = (n - k0) < K ? (n - k0) : K;
+      // (A1) the window's proposal rows
+      for (int idx = tid; idx < Kw * n; idx += kBlock) {
+        const int q = idx / n, l = idx - q * n;
+        const size_t it = item0 + k0 + q;
+        vwin[(size_t)q * nP + l] = Wk.vgl[((size_t)(1 - scur[k0 + q]) * P.W * N + it) * kComp * P.S + l];
+      }
+      __syncthreads();
+      // (A2) Jastrow: fixed partners (outside the window) per slot, and in-window pair terms
+      {
+        const int q = tid / tpq, s = tid - q * tpq;
+        double part = 0.0;
+        if (q < Kw) {
+          const int kq = k0 + q, iq = off + kq;
+          const double px = sprop[4 * kq], py = sprop[4 * kq + 1], pz = sprop[4 * kq + 2];
+          const double ox = spos[3 * iq], oy = spos[3 * iq + 1], oz = spos[3 * iq + 2];
+          const int w0 = off + k0, w1 = off + k0 + Kw;
+          for (int j = s; j < N + P.n_ions; j += tpq) {
+            if (j >= w0 && j < w1) continue;
+            double cx, cy, cz;
+            int kind;
+            if (j < N) {
+              cx = spos[3 * j]; cy = spos[3 * j + 1]; cz = spos[3 * j + 2];
+              kind = ((j < P.n_up) == up_block) ? 0 : 1;
+            } else {
+              const double* ion = ions + 4 * (j - N);
+              cx = ion[0]; cy = ion[1]; cz = ion[2];
+              kind = 2;
+            }
+            part += ju(sj, kind, dist(px, py, pz, cx, cy, cz, L, invL)) -
+                    ju(sj, kind, dist(ox, oy, oz, cx, cy, cz, L, invL));
+          }
+        }
+        red[tid] = part;
+      }
+      for (int idx = tid; idx < Kw * Kw; idx += kBlock) {
+        const int q = idx / Kw, q2 = idx - q * Kw;
+        if (q == q2) continue;
+        const int kq = k0 + q, k2 = k0 + q2, iq = off + kq, i2 = off + k2;
+        const double px = sprop[4 * kq], py = sprop[4 * kq + 1], pz = sprop[4 * kq + 2];
+        const double ox = spos[3 * iq], oy = spos[3 * iq + 1], oz = spos[3 * iq + 2];
+        const double cx = spos[3 * i2], cy = spos[3 * i2 + 1], cz = spos[3 * i2 + 2];
+        const double g_old = ju(sj, 0, dist(px, py, pz, cx, cy, cz, L, invL)) -
+                             ju(sj, 0, dist(ox, oy, oz, cx, cy, cz, L, invL));
+        gold[q * K + q2] = g_old;
+        if (q2 < q) {
+          const double nx = sprop[4 * k2], ny = sprop[4 * k2 + 1], nz = sprop[4 * k2 + 2];
+          const double g_new = ju(sj, 0, dist(px, py, pz, nx, ny, nz, L, invL)) -
+                               ju(sj, 0, dist(ox, oy, oz, nx, ny, nz, L, invL));
+          gdiff[q * K + q2] = g_new - g_old;
+        }
+      }
+      // (A3) Y = V B0
+      gemm_window<T, MF>(vwin, Bm, ldb, ywin, Kw, n, nP, tid);
+      __syncthreads();
+
+      // (B) the moves of the window, in order, by one wave
+      if (wave == 0) {
+        if (lane == 0) sm_stop = -1;
+        double Fq = 0.0;
+        if (lane < Kw)
+          for (int s = 0; s < tpq; ++s) Fq += red[lane * tpq + s];
+        int m = 0;
+        for (int q = 0; q < Kw; ++q) {
+          const int kq = k0 + q, iq = off + kq;
+          T al = T(0), xr = T(0);
+          if (lane < m) {
+            al = ywin[(size_t)q * nP + plist[lane]];
+            sb[lane] = ywin[(size_t)qlist[lane] * nP + kq];
+            sa[lane] = al;
+          }
+          wave_sync_lds();
+          if (lane < m)
+            for (int l = 0; l < m; ++l) xr += cinv[lane * K + l] * sb[l];
+          const double corr = wave_sum_dpp((double)(al * xr));
+          const T R = ywin[(size_t)q * nP + kq] - (T)corr;
+          double jt = 0.0;
+          if (lane < Kw && lane != q) {
+            jt = gold[q * K + lane];
+            if (lane < q && sacc[k0 + lane]) jt += gdiff[q * K + lane];
+          }
+          const double dJ = readlane_d(Fq, q) + wave_sum_dpp(jt);
+          const double u = sprop[4 * kq + 3];
+          const double p32 = (double)R * (double)R * exp(2.0 * dJ);
+          if (sizeof(T) == 4 && fabs(u - p32) <= P.tie_guard * p32) {
+            // near tie in FP32: end the window here; the move is re-decided in FP64 below
+            if (lane == 0) { sm_stop = q; sm_dj = dJ; }
+            break;
+          }
+          const bool accept = u < p32;
+          if (accept) {
+            T yc = T(0);
+            if (lane < m)
+              for (int l = 0; l < m; ++l) yc += sa[l] * cinv[l * K + lane];
+            if (lane < m) { sx[lane] = xr; sy[lane] = yc; }
+            wave_sync_lds();
+            const T invR = T(1) / R;
+            if (lane < m) {
+              for (int c = 0; c < m; ++c) cinv[lane * K + c] += xr * sy[c] * invR;
+              cinv[lane * K + m] = -xr * invR;
+            } else if (lane == m) {
+              for (int c = 0; c < m; ++c) cinv[m * K + c] = -sy[c] * invR;
+              cinv[m * K + m] = invR;
+            }
+            if (lane == 0) {
+              plist[m] = kq;
+              qlist[m] = q;
+              spos[3 * iq] = sprop[4 * kq];
+              spos[3 * iq + 1] = sprop[4 * kq + 1];
+              spos[3 * iq + 2] = sprop[4 * kq + 2];
+              scur[kq] = (uint8_t)(1 - scur[kq]);
+              sacc[kq] = 1;
+            }
+            ++m;
+            ++nacc;
+            logd += log(fabs((double)R));
+            if (R < T(0)) sgn = -sgn;
+          } else if (lane == 0) {
+            sacc[kq] = 0;
+          }
+          wave_sync_lds();
+        }
+        if (lane == 0) sm_m = m;
+      }
+      __syncthreads();
+
+      // (C) flush: B = B0 - B0[:, P] C^-1 (Y[Q, :] - E_P^T)
+      const int m = sm_m;
+      if (m > 0) {
+        const int mP = (m + 3) & ~3;
+        for (int idx = tid; idx < n * mP; idx += kBlock) {
+          const int l = idx / mP, r = idx - l * mP;
+          ubuf[(size_t)l * K + r] = (r < m) ? Bm[(size_t)l * ldb + plist[r]] : T(0);
+        }
+        for (int idx = tid; idx < mP * n; idx += kBlock) {
+          const int r = idx / n, c = idx - r * n;
+          T acc = T(0);
+          if (r < m)
+            for (int l = 0; l < m; ++l)
+              acc += cinv[r * K + l] * (ywin[(size_t)qlist[l] * nP + c] - (c == plist[l] ? T(1) : T(0)));
+          zwin[(size_t)r * nP + c] = acc;
+        }
+        __syncthreads();
+        gemm_flush<T, MF>(Bm, ldb, ubuf, K, zwin, nP, n, mP, tid);
+        __syncthreads();
+      }
+      // (D) a move stopped at a near tie (mixed precision): FP64 decision against the
+      // now current inverse, Sherman-Morrison update if accepted
+      const int stop = sm_stop;
+      if (stop >= 0) {
+        const int kq = k0 + stop, iq = off + kq;
+        const size_t it = item0 + kq;
+        const T* vg = Wk.vgl + ((size_t)(1 - scur[kq]) * P.W * N + it) * kComp * P.S;
+        for (int l = tid; l < n; l += kBlock) sgrow[l] = vg[l];
+        const double* v64 = Wk.val64 + ((size_t)(1 - scur[kq]) * P.W * N + it) * P.S;
+        const double R64 = refined_ratio<T>(P, Wk, Bm, ldb, n, item0, scur, v64, kq, sgx, sgr, red, tid);
+        const double dJ = sm_dj;
+        const double u = sprop[4 * kq + 3];
+        ++nguard;
+        if (u < R64 * R64 * exp(2.0 * dJ)) {
+          // t = v^T B (FP32), column kq saved, then B -= B[:, kq] (t - e_kq) / t_kq
+          T* st = ywin;              // free after the flush
+          T* scol = zwin;
+          for (int m = tid; m < n; m += kBlock) {
+            T acc = T(0);
+            for (int l = 0; l < n; ++l) acc += sgrow[l] * Bm[(size_t)l * ldb + m];
+            st[m] = acc;
+            scol[m] = Bm[(size_t)m * ldb + kq];
+          }
+          __syncthreads();
+          const T invR = T(1) / st[kq];
+          __syncthreads();
+          for (int idx = tid; idx < n * n; idx += kBlock) {
+            const int l = idx / n, m = idx - l * n;
+            Bm[(size_t)l * ldb + m] -= scol[l] * invR * (st[m] - (m == kq ? T(1) : T(0)));
+          }
+          if (tid == 0) {
+            spos[3 * iq] = sprop[4 * kq];
+            spos[3 * iq + 1] = sprop[4 * kq + 1];
+            spos[3 * iq + 2] = sprop[4 * kq + 2];
+            scur[kq] = (uint8_t)(1 - scur[kq]);
+            sacc[kq] = 1;
+          }
+          ++nacc;
+          logd += log(fabs(R64));
+          if (R64 < 0.0) sgn = -sgn;
+        } else if (tid == 0) {
+          sacc[kq] = 0;
+        }
+        __syncthreads();
+        k0 = kq + 1;
+      } else {
+        k0 += Kw;
+      }
+    }
+    __syncthreads();
+    for (int q = tid; q < n; q += kBlock) {
+      Wk.cur[item0 + q] = scur[q];
+      Wk.acc[item0 + q] = sacc[q];
+    }
+    if (tid == 0) {
+      Wk.logdet[2 * w + sp] = logd;
+      Wk.sign[2 * w + sp] = sgn;
+    }
+    if (BLDS) {
+      for (int q = tid; q < n * n; q += kBlock) {
+        const int l = q / n;
+        Bg[q] = sB[l * ldl + (q - l * n)];
+      }
+    }
+    __syncthreads();
+  }
+  for (int j = tid; j < 3 * N; j += kBlock) Wk.pos[(size_t)w * 3 * N + j] = spos[j];
+  if (tid == 0) {
+    Wk.nacc[w] = nacc;
+    Wk.nguard[w] += nguard;
+  }
+}
+
+static int lds_budget_d() {
+  static int budget = -1;
+  if (budget < 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+      budget = v;
+    else
+      budget = 65536;
+  }
+  return budget;
+}
+
+template <typename T, bool BLDS, bool MF>
+static hipError_t launch_delayed_variant(const SysParams& P, const Walkers<T>& Wk, uint32_t sweep, int K,
+                                         hipStream_t st, size_t bytes, int ldl) {
+  if (bytes > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chain_delayed<T, BLDS, MF>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_chain_delayed<T, BLDS, MF>), dim3(P.W), dim3(kBlock), bytes, st, P, Wk, sweep, K, ldl);
+  return hipGetLastError();
+}
+
+size_t delayed_lds_bytes(const SysParams& P, size_t tsize, bool b_in_lds, int K) {
+  const int nmax = P.n_up > P.n_dn ? P.n_up : P.n_dn;
+  return dlayout(P.N, nmax, P.n_ions, nmax | 1, tsize, b_in_lds, K).total;
+}
+
+template <typename T>
+hipError_t launch_chain_delayed(const SysParams& P, const Walkers<T>& Wk, uint32_t sweep, int K, int use_mfma,
+                                hipStream_t st) {
+  // K >= 4 keeps the flush's padded rank (a multiple of 4) within the K-wide buffers
+  if (K < 4 || K > kMaxWindow || (K & (K - 1))) return hipErrorInvalidValue;
+  const int nmax = P.n_up > P.n_dn ? P.n_up : P.n_dn;
+  const int ldl = nmax | 1;
+  const size_t with_b = dlayout(P.N, nmax, P.n_ions, ldl, sizeof(T), true, K).total + sizeof(Jastrow);
+  const size_t without_b = dlayout(P.N, nmax, P.n_ions, ldl, sizeof(T), false, K).total + sizeof(Jastrow);
+  const char* fg = getenv("QMC_CHAIN_GLOBAL_INVERSE");
+  const bool force_global = fg && fg[0] == '1';
+  const size_t budget = (size_t)lds_budget_d();
+  if (!force_global && with_b <= budget) {
+    const size_t bytes = with_b - sizeof(Jastrow);
+    return use_mfma ? launch_delayed_variant<T, true, true>(P, Wk, sweep, K, st, bytes, ldl)
+                    : launch_delayed_variant<T, true, false>(P, Wk, sweep, K, st, bytes, ldl);
+  }
+  if (without_b > budget) return hipErrorInvalidValue;
+  const size_t bytes = without_b - sizeof(Jastrow);
+  return use_mfma ? launch_delayed_variant<T, false, true>(P, Wk, sweep, K, st, bytes, ldl)
+                  : launch_delayed_variant<T, false, false>(P, Wk, sweep, K, st, bytes, ldl);
+}
+
+template hipError_t launch_chain_delayed<double>(const SysParams&, const Walkers<double>&, uint32_t, int, int,
+                                                 hipStream_t);
+template hipError_t launch_chain_delayed<float>(const SysParams&, const Walkers<float>&, uint32_t, int, int,
+                                                hipStream_t);
+
+}  // namespace qmc

@@ -134,12 +134,17 @@ __global__ __launch_bounds__(kBlock) void k_gather(SysParams P, Walkers<T> Wk,
   axis_weights(r[1], P.L, P.gy, ay);
   axis_weights(r[2], P.L, P.gz, az);
   T* out = Wk.vgl + ((size_t)buf * P.W * P.N + (size_t)item) * kComp * P.S;
+  double* out64 = Wk.val64 ? Wk.val64 + ((size_t)buf * P.W * P.N + (size_t)item) * P.S : nullptr;
   const int nvec = P.S / V;
   for (int q = lane; q < nvec; q += tpi) {
     double acc[kComp][V];
     spline_vgl_vec<T>(table, P, ax, ay, az, q, acc);
 #pragma unroll
     for (int c = 0; c < kComp; ++c) store_vec<T>(out + (size_t)c * P.S + (size_t)q * V, acc[c]);
+    if (out64) {   // mixed precision keeps the FP64 values for re-decisions and rebuilds
+#pragma unroll
+      for (int e = 0; e < V; ++e) out64[(size_t)q * V + e] = acc[0][e];
+    }
   }
 }
 

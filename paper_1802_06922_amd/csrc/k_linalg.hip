@@ -42,7 +42,8 @@ __global__ __launch_bounds__(kBlock) void k_rebuild(SysParams P, Walkers<T> Wk, 
     const int k = q / n, l = q - k * n;
     const size_t item = (size_t)w * N + off + k;
     const int cb = Wk.cur[item];
-    a[q] = (double)Wk.vgl[((size_t)cb * P.W * N + item) * kComp * P.S + l];
+    a[q] = Wk.val64 ? Wk.val64[((size_t)cb * P.W * N + item) * P.S + l]
+                    : (double)Wk.vgl[((size_t)cb * P.W * N + item) * kComp * P.S + l];
     amax = fmax(amax, fabs(a[q]));
   }
 #pragma unroll

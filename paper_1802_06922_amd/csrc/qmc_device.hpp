@@ -41,6 +41,7 @@ struct SysParams {
   int n_ions;
   int bstride;            // elements of one walker's two inverses
   double L, sigma;
+  double tie_guard;       // mixed precision: relative half-width of the FP64 re-decision band
   uint32_t key0, key1;    // Philox key (seed)
   const double* ions;     // [n_ions][4] = x, y, z, Z
   Jastrow jas;
@@ -59,6 +60,8 @@ struct Walkers {
   uint8_t* acc;       // [W][N]: accept flags of the last sweep
   uint32_t* nacc;     // [W]: accepted moves in the last launch
   int* status;        // [W]: nonzero = singular matrix at the last rebuild
+  double* val64;      // [2][W][N][S]: FP64 orbital values (mixed precision only, else null)
+  uint32_t* nguard;   // [W]: moves re-decided in FP64 (cumulative; mixed precision)
 };
 
 // ---------------------------------------------------------------------------

@@ -39,6 +39,14 @@ hipError_t launch_eval_points(const SysParams& P, const T* table, const double* 
 template <typename T>
 hipError_t launch_chain(const SysParams& P, const Walkers<T>& Wk, uint32_t sweep, hipStream_t st);
 
+// Move chain with rank-K delayed updates (K a power of two, 4..64): per window
+// of K moves one product Y = V B0, Schur-complement ratios, one rank-m flush.
+// use_mfma selects matrix-core products (else vector ALU).
+template <typename T>
+hipError_t launch_chain_delayed(const SysParams& P, const Walkers<T>& Wk, uint32_t sweep, int K, int use_mfma,
+                                hipStream_t st);
+size_t delayed_lds_bytes(const SysParams& P, size_t tsize, bool b_in_lds, int K);
+
 // Initial positions from the INIT stream.
 hipError_t launch_init_positions(const SysParams& P, double* pos, hipStream_t st);
 

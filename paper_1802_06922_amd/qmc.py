@@ -24,7 +24,7 @@ KERNEL_GATHER, KERNEL_CHAIN, KERNEL_MEASURE, KERNEL_REBUILD = 0, 1, 2, 3
 
 EXPORTS = [
     "qmc_create_system", "qmc_load_spline_table", "qmc_init_walkers", "qmc_sweep",
-    "qmc_measure_local_energy", "qmc_get_walkers", "qmc_get_accept_log", "qmc_recompute",
+    "qmc_measure_local_energy", "qmc_get_walkers", "qmc_get_accept_log", "qmc_get_counters", "qmc_recompute",
     "qmc_eval_spo_vgl", "qmc_set_timing", "qmc_kernel_timing", "qmc_destroy_system",
     "qmc_last_error", "qmc_estimate_device_bytes",
 ]
@@ -70,6 +70,7 @@ def load_library():
     L.qmc_measure_local_energy.argtypes = [vp, vp, C.c_int32]
     L.qmc_get_walkers.argtypes = [vp, dp, dp, C.POINTER(C.c_int32)]
     L.qmc_get_accept_log.argtypes = [vp, C.POINTER(C.c_uint8)]
+    L.qmc_get_counters.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
     L.qmc_recompute.argtypes = [vp, dp]
     L.qmc_eval_spo_vgl.argtypes = [vp, C.c_int32, dp, dp]
     L.qmc_set_timing.argtypes = [vp, C.c_int32]
@@ -230,6 +231,12 @@ class System:
         bits = np.zeros((self.W, self.wl.n_elec), dtype=np.uint8)
         self._check(self.L.qmc_get_accept_log(self.h, bits.ctypes.data_as(C.POINTER(C.c_uint8))))
         return bits
+
+    def counters(self):
+        """(moves re-decided in FP64, sweeps run) since init_walkers."""
+        a, b = C.c_uint64(0), C.c_uint64(0)
+        self._check(self.L.qmc_get_counters(self.h, C.byref(a), C.byref(b)))
+        return int(a.value), int(b.value)
 
     def recompute(self) -> np.ndarray:
         drift = np.zeros((self.W, 2))

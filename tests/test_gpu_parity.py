@@ -216,3 +216,89 @@ def test_many_ions_and_odd_sizes(gpu, orc):
     wl.coefs = qi.solid_table(3, 10, seed=5, dtype=np.float64)
     assert wl.n_ions > 256
     _compare_run(gpu, orc, wl, 5, range(4))
+
+
+@pytest.mark.parametrize("K,case", [(4, "heg14"), (8, "ragged"), (16, "solid128"), (64, "solid128")])
+def test_delayed_update_trajectories(gpu, orc, K, case):
+    """Rank-K delayed updates (Schur-complement ratios, one rank-m flush per window) against
+    the oracle's Sherman-Morrison chain: same decisions, same energies."""
+    if case == "heg14":
+        wl, walkers, sweeps = qi.heg14(), range(8), 30
+    elif case == "ragged":
+        wl = qi.solid(18, 14, n_walkers=24, n_sweeps=1)
+        wl.n_up, wl.n_dn, wl.n_orb = 9, 7, 9
+        wl.coefs = qi.solid_table(9, 14, seed=3, dtype=np.float64)
+        walkers, sweeps = range(24), 10
+    else:
+        wl, walkers, sweeps = qi.solid128(), [0, 255, 511], 3
+    wl.delay_rank = K
+    _compare_run(gpu, orc, wl, sweeps, walkers)
+
+
+@pytest.mark.parametrize("engine", ["valu", "global"])
+def test_delayed_update_variants(gpu, orc, monkeypatch, engine):
+    """The vector-ALU products and the global-memory inverse variant of the delayed chain."""
+    if engine == "valu":
+        monkeypatch.setenv("QMC_DELAYED_VALU", "1")
+    else:
+        monkeypatch.setenv("QMC_CHAIN_GLOBAL_INVERSE", "1")
+    wl = qi.solid(40, 16, n_walkers=12, n_sweeps=1)
+    wl.delay_rank = 8
+    _compare_run(gpu, orc, wl, 6, range(12))
+
+
+def test_delayed_rank_validation(gpu):
+    wl = qi.solid(16, 8, n_walkers=2, n_sweeps=1)
+    for bad in (2, 3, 12, 128):
+        wl.delay_rank = bad
+        with pytest.raises(gpu.QMCError) as ei:
+            gpu.System(wl)
+        assert ei.value.status == gpu.QMC_ERR_ARG
+
+
+MIXED_TOL = 1e-5
+
+
+def _compare_mixed(gpu, orc, wl, n_sweeps, walkers, tie_guard=0.0):
+    """Mixed precision against the FP64 oracle on the same FP32-valued table: decisions
+    bit-exact, local energies within 1e-5 relative."""
+    print(f"[mixed] {wl.name} K={wl.delay_rank}: walkers {list(walkers)[:6]}, {n_sweeps} sweeps", flush=True)
+    sample = np.asarray(walkers)
+    s = gpu.System(wl, tie_guard=tie_guard)
+    bits, energies = [], []
+    for _ in range(n_sweeps):
+        s.sweep(1)
+        bits.append(s.accept_log()[sample])
+        energies.append(s.measure()[sample])
+    redecided, _ = s.counters()
+    s.close()
+    b, e = np.stack(bits, 1), np.stack(energies, 1)
+    ref = orc.OracleSystem(wl).run(sample, n_sweeps, measure_every=1)
+    assert np.array_equal(b, ref["accept"]), f"decisions differ at {np.argwhere(b != ref['accept'])[:3]}"
+    rel = _rel(e, ref["energies"])
+    print(f"[mixed] max rel energy error {rel.max():.2e}, median {np.median(rel):.2e}, "
+          f"re-decided {redecided} of {b.size * (wl.n_walkers // len(sample))} moves", flush=True)
+    assert rel.max() < MIXED_TOL
+    return redecided
+
+
+@pytest.mark.parametrize("K", [1, 8])
+def test_mixed_precision_small(gpu, orc, K):
+    wl = qi.solid(48, 16, n_walkers=16, n_sweeps=1, precision="mixed", table_dtype=np.float32,
+                  delay_rank=K, recompute_period=4)
+    _compare_mixed(gpu, orc, wl, 10, range(16))
+
+
+def test_mixed_precision_guard_is_exercised(gpu, orc):
+    """A wide guard band forces many FP64 re-decisions (both chains)."""
+    for K in (1, 16):
+        wl = qi.solid(32, 12, n_walkers=8, n_sweeps=1, precision="mixed", table_dtype=np.float32,
+                      delay_rank=K, recompute_period=3)
+        n = _compare_mixed(gpu, orc, wl, 6, range(8), tie_guard=0.5)
+        assert n > 50
+
+
+def test_mixed384_sampled_walkers(gpu, orc):
+    """The 384-electron mixed-precision system (FP32 64^3 table, rank-32 delay, 1024 walkers)."""
+    wl = qi.mixed384()
+    _compare_mixed(gpu, orc, wl, 2, [0, 1023])
