@@ -194,6 +194,48 @@ qmc_status qmc_set_timing(qmc_system s, int32_t enable);
 qmc_status qmc_kernel_timing(qmc_system s, int32_t kernel_class, double* total_ms, int64_t* launches,
                              int32_t reset);
 
+/* Change the delay rank between sweeps (1, or 4..64 a power of two).  Windows
+ * never span sweeps, so any rank is valid at a sweep boundary. */
+qmc_status qmc_set_delay_rank(qmc_system s, int32_t delay_rank);
+
+/* Autotuner: runs trial_sweeps sweeps (>= 2; the first is not timed) with each
+ * candidate delay rank, times the move-chain kernel with HIP events, keeps the
+ * fastest and writes it to best_rank (best_ms: its mean chain milliseconds per
+ * sweep; both nullable).  The trial sweeps are ordinary sweeps of the chain. */
+qmc_status qmc_autotune_delay(qmc_system s, const int32_t* ranks, int32_t n_ranks, int32_t trial_sweeps,
+                              int32_t* best_rank, double* best_ms);
+
+/* Local energies of the last measurement (qmc_measure_local_energy or a batch
+ * sweep with measurement), host out[W][4].  Synchronises. */
+qmc_status qmc_get_last_energies(qmc_system s, double* out);
+
+/* ---- Batches: several systems advanced by fused launches -------------------
+ * The walkers of all systems of a batch (any sizes, one precision, delay rank
+ * >= 4, initialised) are advanced by one orbital-gather launch, one delayed-
+ * chain launch per LDS class and one measurement launch per sweep.  Each
+ * system's results are identical to advancing it alone.  All launches go to
+ * the batch's stream; do not drive a member system through another stream
+ * while the batch is in use.  The batch does not own the systems; re-create it
+ * after re-initialising or destroying a member. */
+typedef struct qmc_batch_s* qmc_batch;
+
+qmc_status qmc_batch_create(const qmc_system* systems, int32_t n_systems, void* hip_stream, qmc_batch* out);
+
+/* n_sweeps sweeps of every member; measure != 0 also measures every member's
+ * local energies after each sweep (read them with qmc_get_last_energies).
+ * Member systems' periodic FP64 rebuilds run between sweeps as configured. */
+qmc_status qmc_batch_sweep(qmc_batch b, int32_t n_sweeps, int32_t measure);
+
+/* use_graph != 0: capture one sweep (all its launches) as a HIP graph on first
+ * use and replay it for every later sweep. */
+qmc_status qmc_batch_set_graph(qmc_batch b, int32_t use_graph);
+
+/* Summed milliseconds and count of batch sweeps (HIP events around each
+ * sweep, including its measurement) since the last reset; synchronises. */
+qmc_status qmc_batch_timing(qmc_batch b, double* total_ms, int64_t* sweeps, int32_t reset);
+
+qmc_status qmc_batch_destroy(qmc_batch b);
+
 /* Free every device buffer of the handle and the handle itself. */
 qmc_status qmc_destroy_system(qmc_system s);
 

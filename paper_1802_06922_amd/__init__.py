@@ -3,8 +3,8 @@
 The compute path is the HIP library ``_lib/libqmc.so`` (C ABI in ``include/qmc.h``);
 ``qmc`` is its ctypes binding.
 """
-from .qmc import (QMCError, System, estimate_device_bytes, load_library, KERNEL_GATHER,  # noqa: F401
+from .qmc import (Batch, QMCError, System, estimate_device_bytes, load_library, KERNEL_GATHER,  # noqa: F401
                   KERNEL_CHAIN, KERNEL_MEASURE, KERNEL_REBUILD)
 
-__all__ = ["QMCError", "System", "estimate_device_bytes", "load_library", "KERNEL_GATHER",
+__all__ = ["Batch", "QMCError", "System", "estimate_device_bytes", "load_library", "KERNEL_GATHER",
            "KERNEL_CHAIN", "KERNEL_MEASURE", "KERNEL_REBUILD"]

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -103,6 +104,7 @@ struct qmc_system_s {
   int* status = nullptr;
   double* val64 = nullptr;
   uint32_t* nguard = nullptr;
+  uint32_t* sweep_ctr = nullptr;
   double* scratch = nullptr;
   double* drift = nullptr;
   double* energy = nullptr;
@@ -136,7 +138,7 @@ Walkers<T> walkers_of(qmc_system s) {
   Walkers<T> w;
   w.pos = s->pos; w.prop = s->prop; w.vgl = static_cast<T*>(s->vgl); w.cur = s->cur;
   w.binv = static_cast<T*>(s->binv); w.logdet = s->logdet; w.sign = s->sign; w.acc = s->acc;
-  w.nacc = s->nacc; w.status = s->status; w.val64 = s->val64; w.nguard = s->nguard;
+  w.nacc = s->nacc; w.status = s->status; w.val64 = s->val64; w.nguard = s->nguard; w.sweep_ctr = s->sweep_ctr;
   return w;
 }
 
@@ -267,14 +269,16 @@ void free_walkers(qmc_system s) {
   s->nacc = nullptr;
   s->val64 = nullptr;
   s->nguard = nullptr;
+  s->sweep_ctr = nullptr;
 }
 
 struct WalkerSizes {
-  size_t pos, prop, vgl, cur, binv, logdet, sign, acc, nacc, status, scratch, drift, energy, val64, nguard;
+  size_t pos, prop, vgl, cur, binv, logdet, sign, acc, nacc, status, scratch, drift, energy, val64, nguard, sweep;
   size_t total() const {
     return align_up(pos) + align_up(prop) + align_up(vgl) + align_up(cur) + align_up(binv) +
            align_up(logdet) + align_up(sign) + align_up(acc) + align_up(nacc) + align_up(status) +
-           align_up(scratch) + align_up(drift) + align_up(energy) + align_up(val64) + align_up(nguard);
+           align_up(scratch) + align_up(drift) + align_up(energy) + align_up(val64) + align_up(nguard) +
+           align_up(sweep);
   }
 };
 
@@ -297,6 +301,7 @@ WalkerSizes walker_sizes(int n_up, int n_dn, int precision, int W, int n_orb) {
   z.energy = W * 4 * sizeof(double);
   z.val64 = precision == QMC_MIXED ? 2 * W * N * S * sizeof(double) : 0;
   z.nguard = W * sizeof(uint32_t);
+  z.sweep = sizeof(uint32_t);
   return z;
 }
 
@@ -310,6 +315,8 @@ size_t system_bytes(const qmc_system_desc* d) {
          align_up(nseg * 5 * sizeof(int));
 }
 
+bool valid_rank(int K) { return K == 0 || K == 1 || (K >= 4 && K <= 64 && !(K & (K - 1))); }
+
 qmc_status validate(const qmc_system_desc* d) {
   if (!d) return fail(nullptr, QMC_ERR_ARG, "desc is NULL");
   if (d->n_up < 1 || d->n_dn < 0 || d->n_up + d->n_dn > 1024)
@@ -318,8 +325,7 @@ qmc_status validate(const qmc_system_desc* d) {
   if (!(d->sigma > 0.0)) return fail(nullptr, QMC_ERR_ARG, "sigma must be positive");
   if (d->precision != QMC_FP64 && d->precision != QMC_MIXED)
     return fail(nullptr, QMC_ERR_ARG, "unknown precision %d", d->precision);
-  if (d->delay_rank < 0 || d->delay_rank == 2 || d->delay_rank == 3 || d->delay_rank > 64 ||
-      (d->delay_rank > 1 && (d->delay_rank & (d->delay_rank - 1))))
+  if (!valid_rank(d->delay_rank))
     return fail(nullptr, QMC_ERR_ARG, "delay_rank %d: use 1 (Sherman-Morrison) or a power of two in [4, 64]",
                 d->delay_rank);
   if (d->recompute_period < 0) return fail(nullptr, QMC_ERR_ARG, "recompute_period must be >= 0");
@@ -409,6 +415,11 @@ qmc_status qmc_create_system(const qmc_system_desc* desc, void* hip_stream, qmc_
                j2p ? j2p[0] : 0.0, (j2p && desc->j2_n > 1) ? j2p[1] : 0.0);
   build_radial(P.jas.ei, M > 0 ? desc->j1_kind : QMC_J_NONE, desc->j1_params, desc->j1_n,
                desc->j1_rcut, desc->j1_cusp, 0.0, 0.0);
+  if (s->d.delay_rank > 1 && !delayed_feasible(P, tsize_of(desc->precision), s->d.delay_rank)) {
+    delete s;
+    return fail(nullptr, QMC_ERR_ARG, "delay_rank %d does not fit one workgroup's LDS for this system",
+                desc->delay_rank);
+  }
   s->d.ion_pos = s->d.ion_Z = s->d.j2_params = s->d.j1_params = nullptr;
   s->d.arena = nullptr;
 
@@ -550,9 +561,10 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
   s->drift = static_cast<double*>(s->mem.alloc(z.drift));
   s->energy = static_cast<double*>(s->mem.alloc(z.energy));
   s->nguard = static_cast<uint32_t*>(s->mem.alloc(z.nguard));
+  s->sweep_ctr = static_cast<uint32_t*>(s->mem.alloc(z.sweep));
   if (s->d.precision == QMC_MIXED) s->val64 = static_cast<double*>(s->mem.alloc(z.val64));
   if (!s->pos || !s->prop || !s->vgl || !s->cur || !s->binv || !s->logdet || !s->sign || !s->acc ||
-      !s->nacc || !s->status || !s->scratch || !s->drift || !s->energy || !s->nguard ||
+      !s->nacc || !s->status || !s->scratch || !s->drift || !s->energy || !s->nguard || !s->sweep_ctr ||
       (s->d.precision == QMC_MIXED && !s->val64)) {
     free_walkers(s);
     return fail(s, QMC_ERR_OOM, "device allocation of %zu walker bytes failed", z.total());
@@ -573,13 +585,14 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
   }
   HIP_TRY(s, hipMemsetAsync(s->status, 0, z.status, s->stream));
   HIP_TRY(s, hipMemsetAsync(s->nguard, 0, z.nguard, s->stream));
+  HIP_TRY(s, hipMemsetAsync(s->sweep_ctr, 0, z.sweep, s->stream));
   HIP_TRY(s, hipMemsetAsync(s->acc, 0, z.acc, s->stream));
   HIP_TRY(s, hipMemsetAsync(s->logdet, 0, z.logdet, s->stream));
   hipError_t e;
   if (s->d.precision == QMC_MIXED)
-    e = timed(s, 0, [&] { return launch_gather<float>(s->P, walkers_of<float>(s), static_cast<const float*>(s->d_table), 0, 1, s->stream); });
+    e = timed(s, 0, [&] { return launch_gather<float>(s->P, walkers_of<float>(s), static_cast<const float*>(s->d_table), 1, s->stream); });
   else
-    e = timed(s, 0, [&] { return launch_gather<double>(s->P, walkers_of<double>(s), static_cast<const double*>(s->d_table), 0, 1, s->stream); });
+    e = timed(s, 0, [&] { return launch_gather<double>(s->P, walkers_of<double>(s), static_cast<const double*>(s->d_table), 1, s->stream); });
   if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "orbital gather launch: %s", hipGetErrorString(e));
   qmc_status st = run_rebuild(s, nullptr);
   if (st != QMC_OK) return st;
@@ -602,18 +615,18 @@ qmc_status qmc_sweep(qmc_system s, int32_t n_sweeps, uint64_t* n_accepted_out) {
     const int K = s->d.delay_rank;
     const int mfma = s->use_mfma;
     if (s->d.precision == QMC_MIXED) {
-      e = timed(s, 0, [&] { return launch_gather<float>(s->P, walkers_of<float>(s), static_cast<const float*>(s->d_table), sw, 0, s->stream); });
+      e = timed(s, 0, [&] { return launch_gather<float>(s->P, walkers_of<float>(s), static_cast<const float*>(s->d_table), 0, s->stream); });
       if (e == hipSuccess)
         e = timed(s, 1, [&] {
-          return K > 1 ? launch_chain_delayed<float>(s->P, walkers_of<float>(s), sw, K, mfma, s->stream)
-                       : launch_chain<float>(s->P, walkers_of<float>(s), sw, s->stream);
+          return K > 1 ? launch_chain_delayed<float>(s->P, walkers_of<float>(s), K, mfma, s->stream)
+                       : launch_chain<float>(s->P, walkers_of<float>(s), s->stream);
         });
     } else {
-      e = timed(s, 0, [&] { return launch_gather<double>(s->P, walkers_of<double>(s), static_cast<const double*>(s->d_table), sw, 0, s->stream); });
+      e = timed(s, 0, [&] { return launch_gather<double>(s->P, walkers_of<double>(s), static_cast<const double*>(s->d_table), 0, s->stream); });
       if (e == hipSuccess)
         e = timed(s, 1, [&] {
-          return K > 1 ? launch_chain_delayed<double>(s->P, walkers_of<double>(s), sw, K, mfma, s->stream)
-                       : launch_chain<double>(s->P, walkers_of<double>(s), sw, s->stream);
+          return K > 1 ? launch_chain_delayed<double>(s->P, walkers_of<double>(s), K, mfma, s->stream)
+                       : launch_chain<double>(s->P, walkers_of<double>(s), s->stream);
         });
     }
     if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "sweep launch: %s", hipGetErrorString(e));
@@ -756,6 +769,68 @@ qmc_status qmc_kernel_timing(qmc_system s, int32_t kernel_class, double* total_m
   return QMC_OK;
 }
 
+qmc_status qmc_set_delay_rank(qmc_system s, int32_t delay_rank) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (!valid_rank(delay_rank))
+    return fail(s, QMC_ERR_ARG, "delay_rank %d: use 1 or a power of two in [4, 64]", delay_rank);
+  if (delay_rank > 1 && !delayed_feasible(s->P, tsize_of(s->d.precision), delay_rank))
+    return fail(s, QMC_ERR_ARG, "delay_rank %d does not fit one workgroup's LDS for this system", delay_rank);
+  s->d.delay_rank = delay_rank == 0 ? 1 : delay_rank;
+  return QMC_OK;
+}
+
+qmc_status qmc_autotune_delay(qmc_system s, const int32_t* ranks, int32_t n_ranks, int32_t trial_sweeps,
+                              int32_t* best_rank, double* best_ms) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (!s->has_walkers) return fail(s, QMC_ERR_STATE, "init_walkers first");
+  if (!ranks || n_ranks < 1 || trial_sweeps < 2) return fail(s, QMC_ERR_ARG, "need candidates and >= 2 trial sweeps");
+  for (int i = 0; i < n_ranks; ++i)
+    if (!valid_rank(ranks[i])) return fail(s, QMC_ERR_ARG, "candidate delay rank %d is not valid", ranks[i]);
+  const size_t ts = tsize_of(s->d.precision);
+  const bool timing_was = s->timing;
+  const int rank_was = s->d.delay_rank;
+  s->timing = true;
+  int best = -1;
+  double best_t = 0.0;
+  for (int i = 0; i < n_ranks; ++i) {
+    if (ranks[i] > 1 && !delayed_feasible(s->P, ts, ranks[i])) continue;   // does not fit the LDS
+    s->d.delay_rank = ranks[i] == 0 ? 1 : ranks[i];
+    qmc_status st = qmc_sweep(s, 1, nullptr);   // untimed: first use of this variant
+    double ms = 0.0;
+    int64_t cnt = 0;
+    if (st == QMC_OK) st = qmc_kernel_timing(s, 1, nullptr, nullptr, 1);
+    if (st == QMC_OK) st = qmc_sweep(s, trial_sweeps - 1, nullptr);
+    if (st == QMC_OK) st = qmc_kernel_timing(s, 1, &ms, &cnt, 1);
+    if (st != QMC_OK) {
+      s->timing = timing_was;
+      s->d.delay_rank = rank_was;
+      return st;
+    }
+    const double per = ms / (double)(cnt > 0 ? cnt : 1);
+    if (best < 0 || per < best_t) { best = s->d.delay_rank; best_t = per; }
+  }
+  if (best < 0) {
+    s->d.delay_rank = rank_was;
+    s->timing = timing_was;
+    return fail(s, QMC_ERR_ARG, "no candidate delay rank fits this system");
+  }
+  s->d.delay_rank = best;
+  s->timing = timing_was;
+  if (best_rank) *best_rank = best;
+  if (best_ms) *best_ms = best_t;
+  return QMC_OK;
+}
+
+qmc_status qmc_get_last_energies(qmc_system s, double* out) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (!s->has_walkers) return fail(s, QMC_ERR_STATE, "init_walkers first");
+  if (!out) return fail(s, QMC_ERR_ARG, "out is NULL");
+  HIP_TRY(s, hipSetDevice(s->device));
+  HIP_TRY(s, hipMemcpyAsync(out, s->energy, (size_t)s->P.W * 4 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(s, hipStreamSynchronize(s->stream));
+  return QMC_OK;
+}
+
 qmc_status qmc_destroy_system(qmc_system s) {
   if (!s) return QMC_OK;
   (void)hipSetDevice(s->device);
@@ -766,6 +841,247 @@ qmc_status qmc_destroy_system(qmc_system s) {
   }
   s->mem.release_to(0);
   delete s;
+  return QMC_OK;
+}
+
+}  // extern "C"
+
+struct qmc_batch_s {
+  std::vector<qmc_system> sys;
+  hipStream_t stream = nullptr;
+  int device = 0, precision = 0;
+  std::string err;
+  void* d_sysdev = nullptr;
+  int2* d_maps = nullptr;
+  int2 *gmap = nullptr, *clmap = nullptr, *cgmap = nullptr, *mmap = nullptr;
+  int n_g = 0, n_cl = 0, n_cg = 0, n_m = 0;
+  size_t lds_cl = 0, lds_cg = 0, lds_m = 0;
+  int use_mfma = 1;
+  bool use_graph = false;
+  hipGraphExec_t gexec = nullptr;
+  int graph_measure = -1;
+  TimerClass timer;
+};
+
+namespace {
+
+qmc_status bfail(qmc_batch b, qmc_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  if (b) b->err = buf;
+  return st;
+}
+
+#define BHIP_TRY(b, expr)                                                                    \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return bfail((b), QMC_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+  } while (0)
+
+int max_lds_per_block() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+    return v;
+  return 65536;
+}
+
+template <typename T>
+qmc_status batch_build(qmc_batch b) {
+  const int n = (int)b->sys.size();
+  const int V = sizeof(T) == sizeof(double) ? 2 : 4;
+  const size_t budget = (size_t)max_lds_per_block();
+  std::vector<SysDev<T>> sd(n);
+  std::vector<int2> g, cl, cg, m;
+  for (int i = 0; i < n; ++i) {
+    qmc_system s = b->sys[i];
+    SysDev<T>& d = sd[i];
+    std::memset(&d, 0, sizeof d);
+    d.P = s->P;
+    d.W = walkers_of<T>(s);
+    d.E = s->E;
+    d.table = static_cast<const T*>(s->d_table);
+    d.eout = s->energy;
+    d.K = s->d.delay_rank;
+    const int nmax = s->P.n_up > s->P.n_dn ? s->P.n_up : s->P.n_dn;
+    d.ldl = nmax | 1;
+    d.tpi_log2 = gather_tpi_log2(s->P.S / V);
+    const long items = (long)s->P.W * s->P.N;
+    const long per_block = kBlock >> d.tpi_log2;
+    for (long it = 0; it < items; it += per_block) g.push_back(make_int2(i, (int)it));
+    const size_t extra = sizeof(Jastrow) + sizeof(SysDev<T>);
+    const size_t bl = delayed_lds_bytes(s->P, sizeof(T), true, d.K);
+    const size_t gl = delayed_lds_bytes(s->P, sizeof(T), false, d.K);
+    const bool in_lds = bl + extra <= budget;
+    if (!in_lds && gl + extra > budget)
+      return bfail(b, QMC_ERR_ARG, "system %d does not fit the batched chain's LDS", i);
+    for (int w = 0; w < s->P.W; ++w) {
+      (in_lds ? cl : cg).push_back(make_int2(i, w));
+      m.push_back(make_int2(i, w));
+    }
+    if (in_lds) b->lds_cl = std::max(b->lds_cl, bl);
+    else b->lds_cg = std::max(b->lds_cg, gl);
+    b->lds_m = std::max(b->lds_m, measure_lds_bytes(s->P));
+  }
+  BHIP_TRY(b, hipMalloc(&b->d_sysdev, sizeof(SysDev<T>) * n));
+  const size_t nm = g.size() + cl.size() + cg.size() + m.size();
+  BHIP_TRY(b, hipMalloc(reinterpret_cast<void**>(&b->d_maps), sizeof(int2) * nm));
+  b->gmap = b->d_maps;
+  b->clmap = b->gmap + g.size();
+  b->cgmap = b->clmap + cl.size();
+  b->mmap = b->cgmap + cg.size();
+  b->n_g = (int)g.size(); b->n_cl = (int)cl.size(); b->n_cg = (int)cg.size(); b->n_m = (int)m.size();
+  std::vector<int2> all;
+  all.reserve(nm);
+  all.insert(all.end(), g.begin(), g.end());
+  all.insert(all.end(), cl.begin(), cl.end());
+  all.insert(all.end(), cg.begin(), cg.end());
+  all.insert(all.end(), m.begin(), m.end());
+  BHIP_TRY(b, hipMemcpy(b->d_sysdev, sd.data(), sizeof(SysDev<T>) * n, hipMemcpyHostToDevice));
+  BHIP_TRY(b, hipMemcpy(b->d_maps, all.data(), sizeof(int2) * nm, hipMemcpyHostToDevice));
+  return QMC_OK;
+}
+
+template <typename T>
+hipError_t batch_launch(qmc_batch b, int measure) {
+  const SysDev<T>* sd = static_cast<const SysDev<T>*>(b->d_sysdev);
+  hipError_t e = launch_gather_batched<T>(sd, b->gmap, b->n_g, b->stream);
+  if (e == hipSuccess)
+    e = launch_chain_delayed_batched<T>(sd, b->clmap, b->n_cl, true, b->use_mfma, b->lds_cl, b->stream);
+  if (e == hipSuccess)
+    e = launch_chain_delayed_batched<T>(sd, b->cgmap, b->n_cg, false, b->use_mfma, b->lds_cg, b->stream);
+  if (e == hipSuccess && measure) e = launch_measure_batched<T>(sd, b->mmap, b->n_m, b->lds_m, b->stream);
+  return e;
+}
+
+hipError_t batch_launch_any(qmc_batch b, int measure) {
+  return b->precision == QMC_MIXED ? batch_launch<float>(b, measure) : batch_launch<double>(b, measure);
+}
+
+}  // namespace
+
+extern "C" {
+
+qmc_status qmc_batch_create(const qmc_system* systems, int32_t n_systems, void* hip_stream, qmc_batch* out) {
+  if (!out) return bfail(nullptr, QMC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!systems || n_systems < 1) return bfail(nullptr, QMC_ERR_ARG, "need at least one system");
+  qmc_batch b = new (std::nothrow) qmc_batch_s;
+  if (!b) return bfail(nullptr, QMC_ERR_OOM, "host allocation failed");
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  for (int i = 0; i < n_systems; ++i) {
+    qmc_system s = systems[i];
+    if (!s || !s->has_walkers) { delete b; return bfail(nullptr, QMC_ERR_STATE, "system %d is not initialised", i); }
+    if (i == 0) { b->device = s->device; b->precision = s->d.precision; b->use_mfma = s->use_mfma; }
+    if (s->device != b->device || s->d.precision != b->precision) {
+      delete b;
+      return bfail(nullptr, QMC_ERR_ARG, "systems of a batch share the device and the precision");
+    }
+    if (s->d.delay_rank < 4) {
+      delete b;
+      return bfail(nullptr, QMC_ERR_ARG, "system %d: batches run the delayed chain (delay rank >= 4)", i);
+    }
+    b->sys.push_back(s);
+  }
+  if (hipSetDevice(b->device) != hipSuccess) { delete b; return bfail(nullptr, QMC_ERR_DEVICE, "hipSetDevice failed"); }
+  for (qmc_system s : b->sys)
+    if (hipStreamSynchronize(s->stream) != hipSuccess) { delete b; return bfail(nullptr, QMC_ERR_DEVICE, "member stream sync failed"); }
+  qmc_status st = b->precision == QMC_MIXED ? batch_build<float>(b) : batch_build<double>(b);
+  if (st != QMC_OK) {
+    qmc_batch_destroy(b);
+    return st;
+  }
+  *out = b;
+  return QMC_OK;
+}
+
+qmc_status qmc_batch_set_graph(qmc_batch b, int32_t use_graph) {
+  if (!b) return bfail(nullptr, QMC_ERR_ARG, "batch is NULL");
+  if (use_graph && b->stream == nullptr)
+    return bfail(b, QMC_ERR_ARG, "graph capture needs a non-default stream");
+  b->use_graph = use_graph != 0;
+  return QMC_OK;
+}
+
+qmc_status qmc_batch_sweep(qmc_batch b, int32_t n_sweeps, int32_t measure) {
+  if (!b) return bfail(nullptr, QMC_ERR_ARG, "batch is NULL");
+  if (n_sweeps < 0) return bfail(b, QMC_ERR_ARG, "n_sweeps must be >= 0");
+  BHIP_TRY(b, hipSetDevice(b->device));
+  measure = measure ? 1 : 0;
+  if (b->use_graph && (!b->gexec || b->graph_measure != measure)) {
+    if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+    hipGraph_t graph = nullptr;
+    BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
+    const hipError_t e = batch_launch_any(b, measure);
+    const hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return bfail(b, QMC_ERR_DEVICE, "sweep capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    const hipError_t e3 = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) { b->gexec = nullptr; return bfail(b, QMC_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(e3)); }
+    b->graph_measure = measure;
+  }
+  for (int it = 0; it < n_sweeps; ++it) {
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    if (!b->timer.pool.empty()) { ev = b->timer.pool.back(); b->timer.pool.pop_back(); }
+    else {
+      BHIP_TRY(b, hipEventCreate(&ev.first));
+      BHIP_TRY(b, hipEventCreate(&ev.second));
+    }
+    BHIP_TRY(b, hipEventRecord(ev.first, b->stream));
+    if (b->use_graph) BHIP_TRY(b, hipGraphLaunch(b->gexec, b->stream));
+    else BHIP_TRY(b, batch_launch_any(b, measure));
+    BHIP_TRY(b, hipEventRecord(ev.second, b->stream));
+    b->timer.live.push_back(ev);
+    for (qmc_system s : b->sys) {
+      s->sweep_index += 1;
+      if (s->d.recompute_period > 0 && s->sweep_index % (uint32_t)s->d.recompute_period == 0) {
+        const hipError_t e = s->d.precision == QMC_MIXED
+            ? launch_rebuild<float>(s->P, walkers_of<float>(s), s->scratch, nullptr, b->stream)
+            : launch_rebuild<double>(s->P, walkers_of<double>(s), s->scratch, nullptr, b->stream);
+        if (e != hipSuccess) return bfail(b, QMC_ERR_DEVICE, "rebuild launch: %s", hipGetErrorString(e));
+      }
+    }
+  }
+  return QMC_OK;
+}
+
+qmc_status qmc_batch_timing(qmc_batch b, double* total_ms, int64_t* sweeps, int32_t reset) {
+  if (!b) return bfail(nullptr, QMC_ERR_ARG, "batch is NULL");
+  BHIP_TRY(b, hipSetDevice(b->device));
+  TimerClass& tc = b->timer;
+  if (!tc.live.empty()) BHIP_TRY(b, hipEventSynchronize(tc.live.back().second));
+  for (auto& ev : tc.live) {
+    float ms = 0.f;
+    BHIP_TRY(b, hipEventElapsedTime(&ms, ev.first, ev.second));
+    tc.ms += ms;
+    tc.launches += 1;
+    tc.pool.push_back(ev);
+  }
+  tc.live.clear();
+  if (total_ms) *total_ms = tc.ms;
+  if (sweeps) *sweeps = tc.launches;
+  if (reset) { tc.ms = 0.0; tc.launches = 0; }
+  return QMC_OK;
+}
+
+qmc_status qmc_batch_destroy(qmc_batch b) {
+  if (!b) return QMC_OK;
+  (void)hipSetDevice(b->device);
+  (void)hipStreamSynchronize(b->stream);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  for (auto& ev : b->timer.live) { (void)hipEventDestroy(ev.first); (void)hipEventDestroy(ev.second); }
+  for (auto& ev : b->timer.pool) { (void)hipEventDestroy(ev.first); (void)hipEventDestroy(ev.second); }
+  if (b->d_sysdev) (void)hipFree(b->d_sysdev);
+  if (b->d_maps) (void)hipFree(b->d_maps);
+  delete b;
   return QMC_OK;
 }
 

@@ -74,7 +74,7 @@ __device__ __forceinline__ double pair_u(const Jastrow& J, int kind, double r) {
 // VPT = orbital values per thread per row (n <= 256 * VPT); a chunk holds
 // 16 / VPT rows, so the staging registers are always 16 values per thread.
 template <typename T, bool BLDS, int VPT>
-__global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, uint32_t sweep, int ldl) {
+__global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, int ldl) {
   constexpr int C = 16 / VPT;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ Jastrow sj;
@@ -278,6 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, ui
   if (tid == 0) {
     Wk.nacc[w] = nacc;
     Wk.nguard[w] += nguard;
+    if (w == 0) *Wk.sweep_ctr += 1u;   // read by the next sweep's gather
   }
 }
 
@@ -302,19 +303,19 @@ size_t chain_lds_bytes(const SysParams& P, size_t tsize, bool b_in_lds) {
 }
 
 template <typename T, bool BLDS, int VPT>
-static hipError_t launch_chain_variant(const SysParams& P, const Walkers<T>& Wk, uint32_t sweep,
-                                       hipStream_t st, size_t bytes, int ldl) {
+static hipError_t launch_chain_variant(const SysParams& P, const Walkers<T>& Wk, hipStream_t st,
+                                       size_t bytes, int ldl) {
   if (bytes > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chain<T, BLDS, VPT>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_chain<T, BLDS, VPT>), dim3(P.W), dim3(kBlock), bytes, st, P, Wk, sweep, ldl);
+  hipLaunchKernelGGL((k_chain<T, BLDS, VPT>), dim3(P.W), dim3(kBlock), bytes, st, P, Wk, ldl);
   return hipGetLastError();
 }
 
 template <typename T, int VPT>
-static hipError_t launch_chain_vpt(const SysParams& P, const Walkers<T>& Wk, uint32_t sweep, hipStream_t st) {
+static hipError_t launch_chain_vpt(const SysParams& P, const Walkers<T>& Wk, hipStream_t st) {
   const int nmax = P.n_up > P.n_dn ? P.n_up : P.n_dn;
   const int ldl = nmax | 1;
   const size_t with_b = chain_layout(P.N, nmax, P.n_ions, ldl, sizeof(T), true, 16 / VPT).total;
@@ -324,23 +325,23 @@ static hipError_t launch_chain_vpt(const SysParams& P, const Walkers<T>& Wk, uin
   const char* fg = getenv("QMC_CHAIN_GLOBAL_INVERSE");
   const bool force_global = fg && fg[0] == '1';
   if (!force_global && with_b + sizeof(Jastrow) <= (size_t)lds_budget())
-    return launch_chain_variant<T, true, VPT>(P, Wk, sweep, st, with_b, ldl);
+    return launch_chain_variant<T, true, VPT>(P, Wk, st, with_b, ldl);
   if (without_b + sizeof(Jastrow) > (size_t)lds_budget()) return hipErrorInvalidValue;
-  return launch_chain_variant<T, false, VPT>(P, Wk, sweep, st, without_b, ldl);
+  return launch_chain_variant<T, false, VPT>(P, Wk, st, without_b, ldl);
 }
 
 template <typename T>
-hipError_t launch_chain(const SysParams& P, const Walkers<T>& Wk, uint32_t sweep, hipStream_t st) {
+hipError_t launch_chain(const SysParams& P, const Walkers<T>& Wk, hipStream_t st) {
   const int nmax = P.n_up > P.n_dn ? P.n_up : P.n_dn;
   if (nmax > 4 * kBlock) return hipErrorInvalidValue;
   switch (vpt_of(nmax)) {
-    case 1: return launch_chain_vpt<T, 1>(P, Wk, sweep, st);
-    case 2: return launch_chain_vpt<T, 2>(P, Wk, sweep, st);
-    default: return launch_chain_vpt<T, 4>(P, Wk, sweep, st);
+    case 1: return launch_chain_vpt<T, 1>(P, Wk, st);
+    case 2: return launch_chain_vpt<T, 2>(P, Wk, st);
+    default: return launch_chain_vpt<T, 4>(P, Wk, st);
   }
 }
 
-template hipError_t launch_chain<double>(const SysParams&, const Walkers<double>&, uint32_t, hipStream_t);
-template hipError_t launch_chain<float>(const SysParams&, const Walkers<float>&, uint32_t, hipStream_t);
+template hipError_t launch_chain<double>(const SysParams&, const Walkers<double>&, hipStream_t);
+template hipError_t launch_chain<float>(const SysParams&, const Walkers<float>&, hipStream_t);
 
 }  // namespace qmc

@@ -38,18 +38,23 @@ namespace qmc {
 constexpr int kMaxWindow = 64;
 constexpr int kLdsIonsD = 256;
 
+// 16x16x4 matrix-core products.  Operands: lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16]; result register r of lane l holds D[row(l, r)][l % 16],
+// where the row mapping differs between the FP32 and FP64 instructions.
 template <typename T> struct Mfma;
 template <> struct Mfma<double> {
   typedef double v4 __attribute__((ext_vector_type(4)));
   static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
 };
 template <> struct Mfma<float> {
   typedef float v4 __attribute__((ext_vector_type(4)));
   static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
 struct DLayout {
@@ -81,11 +86,12 @@ __host__ __device__ inline DLayout dlayout(int N, int nmax, int n_ions, int ldl,
   al(16);
   L.cinv = o; o += ts * K * K;
   al(16);
-  L.vwin = o; o += ts * (size_t)K * nP;    // also holds U = B0[:, P] (n x K) during the flush
-  al(16);
+  // Window rows V (dead after Y = V B0) share storage with the flush's Z, and the
+  // flush's U = B0[:, P] reuses Y's storage once Z has been formed.
   L.ywin = o; o += ts * (size_t)K * nP;
   al(16);
   L.zwin = o; o += ts * (size_t)K * nP;
+  L.vwin = L.zwin;
   al(16);
   L.gx = o; o += (ts == 4) ? sizeof(double) * nmax : 0;   // FP64 re-decision scratch (mixed)
   L.gr = o; o += (ts == 4) ? sizeof(double) * nmax : 0;
@@ -149,7 +155,7 @@ __device__ __forceinline__ void gemm_window(const T* V, const T* B, int ldb, T* 
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int q = q0 + 4 * lk + r;
+        const int q = q0 + Mfma<T>::row(lane, r);
         if (q < Kw && cb < n) Y[(size_t)q * nP + cb] = acc[r];
       }
     }
@@ -182,7 +188,7 @@ __device__ __forceinline__ void gemm_flush(T* B, int ldb, const T* U, int ldu, c
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int l = l0 + 4 * lk + q;
+        const int l = l0 + Mfma<T>::row(lane, q);
         if (l < n && cb < n) B[(size_t)l * ldb + cb] -= acc[q];
       }
     }
@@ -197,13 +203,13 @@ __device__ __forceinline__ void gemm_flush(T* B, int ldb, const T* U, int ldu, c
 }
 
 template <typename T, bool BLDS, bool MF>
-__global__ __launch_bounds__(kBlock) void k_chain_delayed(SysParams P, Walkers<T> Wk, uint32_t sweep, int K,
-                                                          int ldl) {
+__device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const Walkers<T>& Wk, int w, int K,
+                                                     int ldl) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ Jastrow sj;
   __shared__ int sm_m, sm_stop;
   __shared__ double sm_dj;
-  const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = P.N, nmax = P.n_up > P.n_dn ? P.n_up : P.n_dn, nP = round16(nmax);
   const DLayout lay = dlayout(N, nmax, P.n_ions, ldl, sizeof(T), BLDS, K);
   double* spos = reinterpret_cast<double*>(smem + lay.pos);
@@ -224,8 +230,8 @@ __global__ __launch_bounds__(kBlock) void k_chain_delayed(SysParams P, Walkers<T
   T* sy = sx + kMaxWindow;
   T* cinv = reinterpret_cast<T*>(smem + lay.cinv);
   T* vwin = reinterpret_cast<T*>(smem + lay.vwin);
-  T* ubuf = vwin;
   T* ywin = reinterpret_cast<T*>(smem + lay.ywin);
+  T* ubuf = ywin;
   T* zwin = reinterpret_cast<T*>(smem + lay.zwin);
   double* sgx = reinterpret_cast<double*>(smem + lay.gx);
   double* sgr = reinterpret_cast<double*>(smem + lay.gr);
@@ -268,6 +274,7 @@ __global__ __launch_bounds__(kBlock) void k_chain_delayed(SysParams P, Walkers<T
       ldb = n;
     }
     const bool up_block = sp == 0;
+    __syncthreads();   // the block's proposals, buffer flags and inverse are staged before any use
 
     for (int k0 = 0; k0 < n;) {
       const int Kw = (n - k0) < K ? (n - k0) : K;
@@ -400,10 +407,6 @@ __global__ __launch_bounds__(kBlock) void k_chain_delayed(SysParams P, Walkers<T
       const int m = sm_m;
       if (m > 0) {
         const int mP = (m + 3) & ~3;
-        for (int idx = tid; idx < n * mP; idx += kBlock) {
-          const int l = idx / mP, r = idx - l * mP;
-          ubuf[(size_t)l * K + r] = (r < m) ? Bm[(size_t)l * ldb + plist[r]] : T(0);
-        }
         for (int idx = tid; idx < mP * n; idx += kBlock) {
           const int r = idx / n, c = idx - r * n;
           T acc = T(0);
@@ -411,6 +414,11 @@ __global__ __launch_bounds__(kBlock) void k_chain_delayed(SysParams P, Walkers<T
             for (int l = 0; l < m; ++l)
               acc += cinv[r * K + l] * (ywin[(size_t)qlist[l] * nP + c] - (c == plist[l] ? T(1) : T(0)));
           zwin[(size_t)r * nP + c] = acc;
+        }
+        __syncthreads();   // Y is dead from here: U takes its storage
+        for (int idx = tid; idx < n * mP; idx += kBlock) {
+          const int l = idx / mP, r = idx - l * mP;
+          ubuf[(size_t)l * K + r] = (r < m) ? Bm[(size_t)l * ldb + plist[r]] : T(0);
         }
         __syncthreads();
         gemm_flush<T, MF>(Bm, ldb, ubuf, K, zwin, nP, n, mP, tid);
@@ -486,7 +494,28 @@ __global__ __launch_bounds__(kBlock) void k_chain_delayed(SysParams P, Walkers<T
   if (tid == 0) {
     Wk.nacc[w] = nacc;
     Wk.nguard[w] += nguard;
+    if (w == 0) *Wk.sweep_ctr += 1u;   // read by the next sweep's gather
   }
+}
+
+template <typename T, bool BLDS, bool MF>
+__global__ __launch_bounds__(kBlock) void k_chain_delayed(SysParams P, Walkers<T> Wk, int K, int ldl) {
+  chain_delayed_walker<T, BLDS, MF>(P, Wk, blockIdx.x, K, ldl);
+}
+
+// Several systems in one launch: block b is walker bmap[b].y of system bmap[b].x.
+template <typename T, bool BLDS, bool MF>
+__global__ __launch_bounds__(kBlock) void k_chain_delayed_batched(const SysDev<T>* __restrict__ sd,
+                                                                  const int2* __restrict__ bmap) {
+  __shared__ SysDev<T> s;
+  const int2 m = bmap[blockIdx.x];
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(sd + m.x);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&s);
+    for (int q = threadIdx.x; q < (int)(sizeof(SysDev<T>) / 4); q += kBlock) dst[q] = src[q];
+  }
+  __syncthreads();
+  chain_delayed_walker<T, BLDS, MF>(s.P, s.W, m.y, s.K, s.ldl);
 }
 
 static int lds_budget_d() {
@@ -503,15 +532,21 @@ static int lds_budget_d() {
 }
 
 template <typename T, bool BLDS, bool MF>
-static hipError_t launch_delayed_variant(const SysParams& P, const Walkers<T>& Wk, uint32_t sweep, int K,
-                                         hipStream_t st, size_t bytes, int ldl) {
+static hipError_t launch_delayed_variant(const SysParams& P, const Walkers<T>& Wk, int K, hipStream_t st,
+                                         size_t bytes, int ldl) {
   if (bytes > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chain_delayed<T, BLDS, MF>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_chain_delayed<T, BLDS, MF>), dim3(P.W), dim3(kBlock), bytes, st, P, Wk, sweep, K, ldl);
+  hipLaunchKernelGGL((k_chain_delayed<T, BLDS, MF>), dim3(P.W), dim3(kBlock), bytes, st, P, Wk, K, ldl);
   return hipGetLastError();
+}
+
+bool delayed_feasible(const SysParams& P, size_t tsize, int K) {
+  const int nmax = P.n_up > P.n_dn ? P.n_up : P.n_dn;
+  return dlayout(P.N, nmax, P.n_ions, nmax | 1, tsize, false, K).total + sizeof(Jastrow) +
+             sizeof(SysDev<double>) <= (size_t)lds_budget_d();
 }
 
 size_t delayed_lds_bytes(const SysParams& P, size_t tsize, bool b_in_lds, int K) {
@@ -520,8 +555,7 @@ size_t delayed_lds_bytes(const SysParams& P, size_t tsize, bool b_in_lds, int K)
 }
 
 template <typename T>
-hipError_t launch_chain_delayed(const SysParams& P, const Walkers<T>& Wk, uint32_t sweep, int K, int use_mfma,
-                                hipStream_t st) {
+hipError_t launch_chain_delayed(const SysParams& P, const Walkers<T>& Wk, int K, int use_mfma, hipStream_t st) {
   // K >= 4 keeps the flush's padded rank (a multiple of 4) within the K-wide buffers
   if (K < 4 || K > kMaxWindow || (K & (K - 1))) return hipErrorInvalidValue;
   const int nmax = P.n_up > P.n_dn ? P.n_up : P.n_dn;
@@ -533,18 +567,44 @@ hipError_t launch_chain_delayed(const SysParams& P, const Walkers<T>& Wk, uint32
   const size_t budget = (size_t)lds_budget_d();
   if (!force_global && with_b <= budget) {
     const size_t bytes = with_b - sizeof(Jastrow);
-    return use_mfma ? launch_delayed_variant<T, true, true>(P, Wk, sweep, K, st, bytes, ldl)
-                    : launch_delayed_variant<T, true, false>(P, Wk, sweep, K, st, bytes, ldl);
+    return use_mfma ? launch_delayed_variant<T, true, true>(P, Wk, K, st, bytes, ldl)
+                    : launch_delayed_variant<T, true, false>(P, Wk, K, st, bytes, ldl);
   }
   if (without_b > budget) return hipErrorInvalidValue;
   const size_t bytes = without_b - sizeof(Jastrow);
-  return use_mfma ? launch_delayed_variant<T, false, true>(P, Wk, sweep, K, st, bytes, ldl)
-                  : launch_delayed_variant<T, false, false>(P, Wk, sweep, K, st, bytes, ldl);
+  return use_mfma ? launch_delayed_variant<T, false, true>(P, Wk, K, st, bytes, ldl)
+                  : launch_delayed_variant<T, false, false>(P, Wk, K, st, bytes, ldl);
 }
 
-template hipError_t launch_chain_delayed<double>(const SysParams&, const Walkers<double>&, uint32_t, int, int,
-                                                 hipStream_t);
-template hipError_t launch_chain_delayed<float>(const SysParams&, const Walkers<float>&, uint32_t, int, int,
-                                                hipStream_t);
+template <typename T, bool BLDS, bool MF>
+static hipError_t launch_delayed_batched_variant(const SysDev<T>* sd, const int2* bmap, int n_blocks, size_t lds,
+                                                 hipStream_t st) {
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chain_delayed_batched<T, BLDS, MF>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_chain_delayed_batched<T, BLDS, MF>), dim3(n_blocks), dim3(kBlock), lds, st, sd, bmap);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_chain_delayed_batched(const SysDev<T>* sd, const int2* bmap, int n_blocks, bool b_in_lds,
+                                        int use_mfma, size_t lds, hipStream_t st) {
+  if (n_blocks <= 0) return hipSuccess;
+  if (lds + sizeof(Jastrow) + sizeof(SysDev<T>) > (size_t)lds_budget_d()) return hipErrorInvalidValue;
+  if (b_in_lds)
+    return use_mfma ? launch_delayed_batched_variant<T, true, true>(sd, bmap, n_blocks, lds, st)
+                    : launch_delayed_batched_variant<T, true, false>(sd, bmap, n_blocks, lds, st);
+  return use_mfma ? launch_delayed_batched_variant<T, false, true>(sd, bmap, n_blocks, lds, st)
+                  : launch_delayed_batched_variant<T, false, false>(sd, bmap, n_blocks, lds, st);
+}
+
+template hipError_t launch_chain_delayed<double>(const SysParams&, const Walkers<double>&, int, int, hipStream_t);
+template hipError_t launch_chain_delayed<float>(const SysParams&, const Walkers<float>&, int, int, hipStream_t);
+template hipError_t launch_chain_delayed_batched<double>(const SysDev<double>*, const int2*, int, bool, int, size_t,
+                                                         hipStream_t);
+template hipError_t launch_chain_delayed_batched<float>(const SysDev<float>*, const int2*, int, bool, int, size_t,
+                                                        hipStream_t);
 
 }  // namespace qmc

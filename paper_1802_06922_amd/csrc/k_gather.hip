@@ -94,14 +94,12 @@ __device__ __forceinline__ void spline_vgl_vec(const T* __restrict__ table, cons
 
 // One item = one (walker, electron); tpi = 1 << tpi_log2 lanes per item.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_gather(SysParams P, Walkers<T> Wk,
-                                                   const T* __restrict__ table, uint32_t sweep,
-                                                   int mode, int tpi_log2) {
+__device__ __forceinline__ void gather_item(const SysParams& P, const Walkers<T>& Wk,
+                                            const T* __restrict__ table, int mode, long item, int lane,
+                                            int tpi) {
   constexpr int V = VecOf<T>::V;
-  const int tpi = 1 << tpi_log2;
-  const int lane = threadIdx.x & (tpi - 1);
-  const long item = (long)blockIdx.x * (kBlock >> tpi_log2) + (threadIdx.x >> tpi_log2);
   if (item >= (long)P.W * P.N) return;
+  const uint32_t sweep = mode == 0 ? *Wk.sweep_ctr : 0u;
   const int w = (int)(item / P.N), i = (int)(item % P.N);
   const double* p0 = Wk.pos + item * 3;
   double r[3];
@@ -149,6 +147,30 @@ __global__ __launch_bounds__(kBlock) void k_gather(SysParams P, Walkers<T> Wk,
 }
 
 template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gather(SysParams P, Walkers<T> Wk, const T* __restrict__ table,
+                                                   int mode, int tpi_log2) {
+  const long item = (long)blockIdx.x * (kBlock >> tpi_log2) + (threadIdx.x >> tpi_log2);
+  gather_item<T>(P, Wk, table, mode, item, threadIdx.x & ((1 << tpi_log2) - 1), 1 << tpi_log2);
+}
+
+// Several systems in one launch: block b works on items bmap[b].y .. of system bmap[b].x.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gather_batched(const SysDev<T>* __restrict__ sd,
+                                                           const int2* __restrict__ bmap) {
+  __shared__ SysDev<T> s;
+  const int2 m = bmap[blockIdx.x];
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(sd + m.x);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&s);
+    for (int q = threadIdx.x; q < (int)(sizeof(SysDev<T>) / 4); q += kBlock) dst[q] = src[q];
+  }
+  __syncthreads();
+  const int tl = s.tpi_log2;
+  const long item = (long)m.y + (threadIdx.x >> tl);
+  gather_item<T>(s.P, s.W, s.table, 0, item, threadIdx.x & ((1 << tl) - 1), 1 << tl);
+}
+
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_eval_points(SysParams P, const T* __restrict__ table,
                                                         const double* __restrict__ pos, int n,
                                                         double* __restrict__ out) {
@@ -182,22 +204,32 @@ __global__ __launch_bounds__(kBlock) void k_init_positions(SysParams P, double* 
   pos[item * 3 + 2] = wrap_cell(P.L * b0, P.L);
 }
 
-static int gather_tpi_log2(int nvec) {
+int gather_tpi_log2(int nvec) {
   int l = 0;
   while ((1 << l) < nvec && l < 6) ++l;
   return l;
 }
 
 template <typename T>
-hipError_t launch_gather(const SysParams& P, const Walkers<T>& Wk, const T* table, uint32_t sweep,
-                         int mode, hipStream_t st) {
+hipError_t launch_gather(const SysParams& P, const Walkers<T>& Wk, const T* table, int mode, hipStream_t st) {
   const int nvec = P.S / VecOf<T>::V;
   const int tl = gather_tpi_log2(nvec);
   const long items = (long)P.W * P.N;
   const long per_block = kBlock >> tl;
   const unsigned blocks = (unsigned)((items + per_block - 1) / per_block);
-  hipLaunchKernelGGL(k_gather<T>, dim3(blocks), dim3(kBlock), 0, st, P, Wk, table, sweep, mode, tl);
+  hipLaunchKernelGGL(k_gather<T>, dim3(blocks), dim3(kBlock), 0, st, P, Wk, table, mode, tl);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gather_batched(const SysDev<T>* sd, const int2* bmap, int n_blocks, hipStream_t st) {
+  if (n_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_batched<T>, dim3(n_blocks), dim3(kBlock), 0, st, sd, bmap);
+  return hipGetLastError();
+}
+
+int gather_items_per_block(int S, size_t tsize) {
+  return kBlock >> gather_tpi_log2(S / (tsize == sizeof(double) ? 2 : 4));
 }
 
 template <typename T>
@@ -217,10 +249,12 @@ hipError_t launch_init_positions(const SysParams& P, double* pos, hipStream_t st
   return hipGetLastError();
 }
 
-template hipError_t launch_gather<double>(const SysParams&, const Walkers<double>&, const double*,
-                                          uint32_t, int, hipStream_t);
-template hipError_t launch_gather<float>(const SysParams&, const Walkers<float>&, const float*,
-                                         uint32_t, int, hipStream_t);
+template hipError_t launch_gather<double>(const SysParams&, const Walkers<double>&, const double*, int,
+                                          hipStream_t);
+template hipError_t launch_gather<float>(const SysParams&, const Walkers<float>&, const float*, int,
+                                         hipStream_t);
+template hipError_t launch_gather_batched<double>(const SysDev<double>*, const int2*, int, hipStream_t);
+template hipError_t launch_gather_batched<float>(const SysDev<float>*, const int2*, int, hipStream_t);
 template hipError_t launch_eval_points<double>(const SysParams&, const double*, const double*, int,
                                                double*, hipStream_t);
 template hipError_t launch_eval_points<float>(const SysParams&, const float*, const double*, int,

@@ -67,12 +67,12 @@ __host__ __device__ inline MeasureLayout measure_layout(int N) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_measure(SysParams P, Walkers<T> Wk, EwaldParams E,
-                                                    double* __restrict__ out) {
+__device__ __forceinline__ void measure_walker(const SysParams& P, const Walkers<T>& Wk, const EwaldParams& E,
+                                               double* __restrict__ out, int w) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ Jastrow sj;
   __shared__ double red[5 * kWaves];
-  const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = P.N;
   const MeasureLayout lay = measure_layout(N);
   double* spos = reinterpret_cast<double*>(smem + lay.pos);
@@ -238,7 +238,43 @@ __global__ __launch_bounds__(kBlock) void k_measure(SysParams P, Walkers<T> Wk, 
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_measure(SysParams P, Walkers<T> Wk, EwaldParams E,
+                                                    double* __restrict__ out) {
+  measure_walker<T>(P, Wk, E, out, blockIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_measure_batched(const SysDev<T>* __restrict__ sd,
+                                                            const int2* __restrict__ bmap) {
+  __shared__ SysDev<T> s;
+  const int2 m = bmap[blockIdx.x];
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(sd + m.x);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&s);
+    for (int q = threadIdx.x; q < (int)(sizeof(SysDev<T>) / 4); q += kBlock) dst[q] = src[q];
+  }
+  __syncthreads();
+  measure_walker<T>(s.P, s.W, s.E, s.eout, m.y);
+}
+
 size_t measure_lds_bytes(const SysParams& P) { return measure_layout(P.N).total; }
+
+template <typename T>
+hipError_t launch_measure_batched(const SysDev<T>* sd, const int2* bmap, int n_blocks, size_t lds,
+                                  hipStream_t st) {
+  if (n_blocks <= 0) return hipSuccess;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_measure_batched<T>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_measure_batched<T>, dim3(n_blocks), dim3(kBlock), lds, st, sd, bmap);
+  return hipGetLastError();
+}
+
+template hipError_t launch_measure_batched<double>(const SysDev<double>*, const int2*, int, size_t, hipStream_t);
+template hipError_t launch_measure_batched<float>(const SysDev<float>*, const int2*, int, size_t, hipStream_t);
 
 template <typename T>
 hipError_t launch_measure(const SysParams& P, const Walkers<T>& Wk, const EwaldParams& E, double* out,

@@ -62,6 +62,7 @@ struct Walkers {
   int* status;        // [W]: nonzero = singular matrix at the last rebuild
   double* val64;      // [2][W][N][S]: FP64 orbital values (mixed precision only, else null)
   uint32_t* nguard;   // [W]: moves re-decided in FP64 (cumulative; mixed precision)
+  uint32_t* sweep_ctr;  // index of the next sweep (device side, so captured sweeps replay correctly)
 };
 
 // ---------------------------------------------------------------------------

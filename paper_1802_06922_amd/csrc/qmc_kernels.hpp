@@ -22,13 +22,31 @@ struct EwaldParams {
   double v_ii;           // ion-ion energy (constant)
 };
 
-// Orbital gather: for every (walker, electron), either draw the proposal of
-// `sweep` and evaluate all orbitals there (mode 0, written to the buffer that
-// does not hold the current row), or evaluate at the current position (mode 1,
-// written to buffer 0 and cur reset).
+// One system of a batched launch (copied to LDS by each block).
 template <typename T>
-hipError_t launch_gather(const SysParams& P, const Walkers<T>& Wk, const T* table, uint32_t sweep,
-                         int mode, hipStream_t st);
+struct SysDev {
+  SysParams P;
+  Walkers<T> W;
+  EwaldParams E;
+  const T* table;
+  double* eout;      // [W][4] local energies
+  int K;             // delay rank of the chain
+  int ldl;           // LDS row stride of the inverse
+  int tpi_log2;      // gather lanes per proposal (log2)
+  int pad;
+};
+
+// Orbital gather: for every (walker, electron), either draw the proposal of
+// the sweep in *Wk.sweep_ctr and evaluate all orbitals there (mode 0, written
+// to the buffer that does not hold the current row), or evaluate at the
+// current position (mode 1, written to buffer 0 and cur reset).
+template <typename T>
+hipError_t launch_gather(const SysParams& P, const Walkers<T>& Wk, const T* table, int mode, hipStream_t st);
+// Several systems' proposals in one launch; bmap[b] = (system, first item of block b).
+template <typename T>
+hipError_t launch_gather_batched(const SysDev<T>* sd, const int2* bmap, int n_blocks, hipStream_t st);
+int gather_tpi_log2(int nvec);
+int gather_items_per_block(int S, size_t tsize);
 
 // Diagnostic evaluation at arbitrary points: out[n][5][n_orb] (FP64).
 template <typename T>
@@ -37,15 +55,21 @@ hipError_t launch_eval_points(const SysParams& P, const T* table, const double* 
 
 // Sequential move chain of one sweep (one workgroup per walker).
 template <typename T>
-hipError_t launch_chain(const SysParams& P, const Walkers<T>& Wk, uint32_t sweep, hipStream_t st);
+hipError_t launch_chain(const SysParams& P, const Walkers<T>& Wk, hipStream_t st);
 
 // Move chain with rank-K delayed updates (K a power of two, 4..64): per window
 // of K moves one product Y = V B0, Schur-complement ratios, one rank-m flush.
 // use_mfma selects matrix-core products (else vector ALU).
 template <typename T>
-hipError_t launch_chain_delayed(const SysParams& P, const Walkers<T>& Wk, uint32_t sweep, int K, int use_mfma,
-                                hipStream_t st);
+hipError_t launch_chain_delayed(const SysParams& P, const Walkers<T>& Wk, int K, int use_mfma, hipStream_t st);
 size_t delayed_lds_bytes(const SysParams& P, size_t tsize, bool b_in_lds, int K);
+// Whether rank K fits the LDS of one workgroup (single or batched launch) for P.
+bool delayed_feasible(const SysParams& P, size_t tsize, int K);
+// Batched delayed chain over the systems' walkers; bmap[b] = (system, walker).
+// b_in_lds must hold for every system of the launch; lds = dynamic LDS bytes (max).
+template <typename T>
+hipError_t launch_chain_delayed_batched(const SysDev<T>* sd, const int2* bmap, int n_blocks, bool b_in_lds,
+                                        int use_mfma, size_t lds, hipStream_t st);
 
 // Initial positions from the INIT stream.
 hipError_t launch_init_positions(const SysParams& P, double* pos, hipStream_t st);
@@ -61,6 +85,11 @@ hipError_t launch_rebuild(const SysParams& P, const Walkers<T>& Wk, double* scra
 template <typename T>
 hipError_t launch_measure(const SysParams& P, const Walkers<T>& Wk, const EwaldParams& E, double* out,
                           hipStream_t st);
+// Batched measurement; bmap[b] = (system, walker); lds = dynamic LDS bytes (max over systems).
+template <typename T>
+hipError_t launch_measure_batched(const SysDev<T>* sd, const int2* bmap, int n_blocks, size_t lds,
+                                  hipStream_t st);
+size_t measure_lds_bytes(const SysParams& P);
 
 // Size in bytes of the dynamic LDS the chain kernel needs for P.
 size_t chain_lds_bytes(const SysParams& P, size_t tsize, bool b_in_lds);

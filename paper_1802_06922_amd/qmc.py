@@ -26,7 +26,9 @@ EXPORTS = [
     "qmc_create_system", "qmc_load_spline_table", "qmc_init_walkers", "qmc_sweep",
     "qmc_measure_local_energy", "qmc_get_walkers", "qmc_get_accept_log", "qmc_get_counters", "qmc_recompute",
     "qmc_eval_spo_vgl", "qmc_set_timing", "qmc_kernel_timing", "qmc_destroy_system",
-    "qmc_last_error", "qmc_estimate_device_bytes",
+    "qmc_last_error", "qmc_estimate_device_bytes", "qmc_set_delay_rank", "qmc_autotune_delay",
+    "qmc_get_last_energies", "qmc_batch_create", "qmc_batch_sweep", "qmc_batch_set_graph",
+    "qmc_batch_timing", "qmc_batch_destroy",
 ]
 
 
@@ -80,6 +82,15 @@ def load_library():
     L.qmc_last_error.restype = C.c_char_p
     L.qmc_estimate_device_bytes.argtypes = [C.POINTER(Desc), C.c_int32, C.c_int32, C.c_int32, C.c_int32]
     L.qmc_estimate_device_bytes.restype = C.c_size_t
+    ip = C.POINTER(C.c_int32)
+    L.qmc_set_delay_rank.argtypes = [vp, C.c_int32]
+    L.qmc_autotune_delay.argtypes = [vp, ip, C.c_int32, C.c_int32, ip, dp]
+    L.qmc_get_last_energies.argtypes = [vp, dp]
+    L.qmc_batch_create.argtypes = [C.POINTER(vp), C.c_int32, vp, C.POINTER(vp)]
+    L.qmc_batch_sweep.argtypes = [vp, C.c_int32, C.c_int32]
+    L.qmc_batch_set_graph.argtypes = [vp, C.c_int32]
+    L.qmc_batch_timing.argtypes = [vp, dp, C.POINTER(C.c_int64), C.c_int32]
+    L.qmc_batch_destroy.argtypes = [vp]
     for name in EXPORTS:
         if name not in ("qmc_last_error", "qmc_estimate_device_bytes"):
             getattr(L, name).restype = st
@@ -249,6 +260,24 @@ class System:
         self._check(self.L.qmc_eval_spo_vgl(self.h, pos.shape[0], _dp(pos), _dp(out)))
         return out
 
+    def set_delay_rank(self, K: int):
+        self._check(self.L.qmc_set_delay_rank(self.h, int(K)))
+
+    def autotune_delay(self, ranks=(8, 16, 32, 64), trial_sweeps: int = 3):
+        """Time the move chain with each delay rank (trial sweeps are ordinary sweeps); keep the best."""
+        arr = (C.c_int32 * len(ranks))(*ranks)
+        best = C.c_int32(0)
+        ms = C.c_double(0.0)
+        self._check(self.L.qmc_autotune_delay(self.h, arr, len(ranks), int(trial_sweeps), C.byref(best),
+                                              C.byref(ms)))
+        self.wl.delay_rank = int(best.value)
+        return int(best.value), float(ms.value)
+
+    def last_energies(self) -> np.ndarray:
+        e = np.zeros((self.W, 4))
+        self._check(self.L.qmc_get_last_energies(self.h, _dp(e)))
+        return e
+
     def set_timing(self, on: bool = True):
         self._check(self.L.qmc_set_timing(self.h, int(bool(on))))
 
@@ -264,3 +293,47 @@ def estimate_device_bytes(wl, n_walkers: int) -> int:
     d = make_desc(wl, keep)
     g = wl.grid
     return int(load_library().qmc_estimate_device_bytes(C.byref(d), n_walkers, g[0], g[1], g[2]))
+
+
+class Batch:
+    """Several initialised systems advanced by fused launches (see qmc_batch_* in include/qmc.h)."""
+
+    def __init__(self, systems, stream=None, graph: bool = False):
+        import torch
+        self.L = load_library()
+        self.systems = list(systems)
+        if stream is None:
+            stream = torch.cuda.Stream() if graph else torch.cuda.current_stream()
+        self.stream = stream
+        hs = (C.c_void_p * len(self.systems))(*[s.h.value for s in self.systems])
+        b = C.c_void_p()
+        st = self.L.qmc_batch_create(hs, len(self.systems), C.c_void_p(stream.cuda_stream), C.byref(b))
+        if st != QMC_OK:
+            raise QMCError(st, self.L.qmc_last_error(None).decode())
+        self.b = b
+        if graph:
+            self._check(self.L.qmc_batch_set_graph(self.b, 1))
+
+    def _check(self, st):
+        if st != QMC_OK:
+            raise QMCError(st, self.L.qmc_last_error(None).decode())
+
+    def sweep(self, n: int = 1, measure: bool = False):
+        self._check(self.L.qmc_batch_sweep(self.b, int(n), int(bool(measure))))
+
+    def timing(self, reset: bool = False):
+        ms = C.c_double(0.0)
+        n = C.c_int64(0)
+        self._check(self.L.qmc_batch_timing(self.b, C.byref(ms), C.byref(n), int(reset)))
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "b", None):
+            self.L.qmc_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,91 @@
+"""GPU: batched systems (fused launches, graph replay) and the delay-rank autotuner."""
+import numpy as np
+import pytest
+
+import qmc_inputs as qi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1802_06922_amd import qmc
+    qmc.load_library()
+    return qmc
+
+
+def _systems():
+    """Uneven mixed-precision systems (the last one too large to keep its inverse in LDS)."""
+    spec = [(16, 10, 8, 8), (40, 14, 12, 16), (72, 16, 6, 32), (400, 24, 2, 32)]
+    out = []
+    for i, (n, g, w, K) in enumerate(spec):
+        out.append(qi.solid(n, g, n_walkers=w, n_sweeps=1, precision="mixed", table_dtype=np.float32,
+                            delay_rank=K, recompute_period=3, seed=i, name=f"batch{n}"))
+    return out
+
+
+def _alone(gpu, wl, sweeps):
+    s = gpu.System(wl)
+    bits, e = [], []
+    for _ in range(sweeps):
+        s.sweep(1)
+        bits.append(s.accept_log())
+        e.append(s.measure())
+    s.close()
+    return np.stack(bits), np.stack(e)
+
+
+def test_batch_equals_each_system_alone(gpu):
+    sweeps = 5
+    wls = _systems()
+    ref = [_alone(gpu, wl, sweeps) for wl in wls]
+    systems = [gpu.System(wl) for wl in wls]
+    batch = gpu.Batch(systems)
+    for it in range(sweeps):
+        batch.sweep(1, measure=True)
+        for k, s in enumerate(systems):
+            print(f"[batch] sweep {it} system {k}", flush=True)
+            assert np.array_equal(s.accept_log(), ref[k][0][it])
+            assert np.array_equal(s.last_energies(), ref[k][1][it])
+    batch.close()
+    for s in systems:
+        s.close()
+
+
+def test_batch_graph_replay_equals_eager(gpu):
+    sweeps = 6
+    wls = _systems()[:3]
+    outs = []
+    for graph in (False, True):
+        systems = [gpu.System(wl) for wl in wls]
+        batch = gpu.Batch(systems, graph=graph)
+        res = []
+        for it in range(sweeps):
+            batch.sweep(1, measure=True)
+            res.append([(s.accept_log(), s.last_energies()) for s in systems])
+        batch.close()
+        for s in systems:
+            s.close()
+        outs.append(res)
+    for it in range(sweeps):
+        for k in range(len(wls)):
+            assert np.array_equal(outs[0][it][k][0], outs[1][it][k][0])
+            assert np.array_equal(outs[0][it][k][1], outs[1][it][k][1])
+
+
+def test_autotune_keeps_the_chain_exact(gpu, orc):
+    wl = qi.solid(48, 16, n_walkers=8, n_sweeps=1, delay_rank=8)
+    s = gpu.System(wl)
+    best, ms = s.autotune_delay(ranks=(4, 8, 16, 64), trial_sweeps=2)
+    assert best in (4, 8, 16, 64) and ms > 0
+    s.sweep(1)
+    pos, ld, _ = s.get_walkers()
+    bits = s.accept_log()
+    s.close()
+    ref = orc.OracleSystem(wl).run(range(8), 9, measure_every=0)
+    assert np.array_equal(bits, ref["accept"][:, -1])
+    np.testing.assert_allclose(pos, ref["final_pos"], atol=1e-11)
+    np.testing.assert_allclose(ld, ref["logdet"], atol=1e-9)
