@@ -243,6 +243,14 @@ qmc_status qmc_destroy_system(qmc_system s);
  * thread).  Valid until the next call on the same handle/thread. */
 const char* qmc_last_error(qmc_system s);
 
+/* Largest delay rank (64, 32, 16, 8 or 4) whose delayed-update chain fits
+ * one workgroup's LDS for desc's electron and ion counts and precision (the
+ * window of the delayed update of section "Performance and Parallel Scaling"
+ * grows as K*N); 1 when none fits
+ * (Sherman-Morrison only), 0 for an invalid descriptor.  Host-only: needs no
+ * handle; reads the current device's LDS size when a device is present. */
+int32_t qmc_max_delay_rank(const qmc_system_desc* desc);
+
 /* Device bytes a handle needs for desc, n_walkers walkers and a gx*gy*gz
  * table (n_orb = max(n_up, n_dn)), including alignment; 0 for invalid input. */
 size_t qmc_estimate_device_bytes(const qmc_system_desc* desc, int32_t n_walkers, int32_t gx,

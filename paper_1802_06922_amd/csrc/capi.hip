@@ -1090,6 +1090,19 @@ const char* qmc_last_error(qmc_system s) {
   return g_last_error.c_str();
 }
 
+int32_t qmc_max_delay_rank(const qmc_system_desc* desc) {
+  if (validate(desc) != QMC_OK) return 0;
+  SysParams P;
+  std::memset(&P, 0, sizeof P);
+  P.n_up = desc->n_up;
+  P.n_dn = desc->n_dn;
+  P.N = desc->n_up + desc->n_dn;
+  P.n_ions = desc->n_ions;
+  for (int K = 64; K >= 4; K >>= 1)
+    if (delayed_feasible(P, tsize_of(desc->precision), K)) return K;
+  return 1;
+}
+
 size_t qmc_estimate_device_bytes(const qmc_system_desc* desc, int32_t n_walkers, int32_t gx, int32_t gy,
                                  int32_t gz) {
   if (!desc || n_walkers < 1 || gx < 4 || gy < 4 || gz < 4) return 0;

@@ -526,7 +526,7 @@ static int lds_budget_d() {
         hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
       budget = v;
     else
-      budget = 65536;
+      budget = 163840;   // gfx950: 160 KiB of LDS per workgroup
   }
   return budget;
 }

@@ -28,7 +28,7 @@ EXPORTS = [
     "qmc_eval_spo_vgl", "qmc_set_timing", "qmc_kernel_timing", "qmc_destroy_system",
     "qmc_last_error", "qmc_estimate_device_bytes", "qmc_set_delay_rank", "qmc_autotune_delay",
     "qmc_get_last_energies", "qmc_batch_create", "qmc_batch_sweep", "qmc_batch_set_graph",
-    "qmc_batch_timing", "qmc_batch_destroy",
+    "qmc_batch_timing", "qmc_batch_destroy", "qmc_max_delay_rank",
 ]
 
 
@@ -91,8 +91,10 @@ def load_library():
     L.qmc_batch_set_graph.argtypes = [vp, C.c_int32]
     L.qmc_batch_timing.argtypes = [vp, dp, C.POINTER(C.c_int64), C.c_int32]
     L.qmc_batch_destroy.argtypes = [vp]
+    L.qmc_max_delay_rank.argtypes = [C.POINTER(Desc)]
+    L.qmc_max_delay_rank.restype = C.c_int32
     for name in EXPORTS:
-        if name not in ("qmc_last_error", "qmc_estimate_device_bytes"):
+        if name not in ("qmc_last_error", "qmc_estimate_device_bytes", "qmc_max_delay_rank"):
             getattr(L, name).restype = st
     _lib = L
     return L
@@ -293,6 +295,15 @@ def estimate_device_bytes(wl, n_walkers: int) -> int:
     d = make_desc(wl, keep)
     g = wl.grid
     return int(load_library().qmc_estimate_device_bytes(C.byref(d), n_walkers, g[0], g[1], g[2]))
+
+
+def max_delay_rank(wl) -> int:
+    """Largest delay rank whose chain fits one workgroup's LDS (1: Sherman-Morrison only)."""
+    keep: list = []
+    k = int(load_library().qmc_max_delay_rank(C.byref(make_desc(wl, keep))))
+    if k == 0:
+        raise QMCError(QMC_ERR_ARG, "qmc_max_delay_rank rejected the descriptor")
+    return k
 
 
 class Batch:

@@ -1,0 +1,169 @@
+"""Serving loop: continuous batching of VMC requests on one GPU.
+
+Requests (each a VMC run with its own system, table, walker count and sweep
+count) arrive on a trace.  A request is admitted as soon as its device memory
+(``qmc_estimate_device_bytes``) fits the HBM budget next to the requests
+already resident; its walkers, inverses and table then stay on the GPU until
+it finishes.  Every iteration advances all resident requests by one sweep
+with one fused batch launch (``qmc_batch_*``), so requests that arrive while
+others run join at the next sweep boundary and their work overlaps on the
+device.  A request's results do not depend on which other requests share the
+GPU: every walker runs the same per-walker arithmetic in any batch.
+
+Per-sweep latency of a request = GPU time of the batch sweep that advanced it
+(HIP events around each sweep); p50/p99 are pooled over all (request, sweep)
+pairs.  Host work between sweeps (admission, batch rebuild) is outside those
+events and shows up in the wall-clock throughput instead.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import dataclasses
+import time
+from collections import deque
+from typing import Optional
+
+import numpy as np
+
+from . import qmc
+
+
+def delay_rank_for(wl, cap: int = 32) -> int:
+    """Delay rank of a request: the largest one (at most ``cap``) whose chain fits one workgroup's
+    LDS.  It depends on the system only, so a request computes the same alone and in any mix."""
+    return min(cap, qmc.max_delay_rank(wl))
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival_s: float
+    wl: object
+    n_sweeps: int
+    est_bytes: int = 0
+    system: Optional[object] = None
+    done_sweeps: int = 0
+    admitted_s: float = 0.0
+    finished_s: float = 0.0
+    latencies_ms: list = dataclasses.field(default_factory=list)
+    energy: Optional[np.ndarray] = None
+    final_pos: Optional[np.ndarray] = None
+
+
+class Server:
+    def __init__(self, hbm_budget_bytes: Optional[int] = None, reserve_bytes: int = 8 << 30,
+                 graph: bool = False):
+        import torch
+        self.torch = torch
+        free, total = torch.cuda.mem_get_info()
+        budget = free - reserve_bytes
+        if hbm_budget_bytes is not None:
+            budget = min(budget, hbm_budget_bytes)
+        self.budget = max(0, int(budget))
+        self.graph = graph
+        self.stream = torch.cuda.Stream()
+
+    def run(self, requests, time_scale: float = 1.0, log=None):
+        """Serve ``requests`` (list of Request, arrival times in seconds); returns a stats dict."""
+        torch = self.torch
+        pending = deque(sorted(requests, key=lambda r: r.arrival_s))
+        queue: deque = deque()
+        active: list = []
+        finished: list = []
+        used = 0
+        batch = None
+        dirty = True
+        n_sweep_iters = 0
+        t0 = time.perf_counter()
+        with torch.cuda.stream(self.stream):
+            while pending or queue or active:
+                now = time.perf_counter() - t0
+                while pending and pending[0].arrival_s * time_scale <= now:
+                    queue.append(pending.popleft())
+                while queue:   # admission by device memory (first come, first served)
+                    r = queue[0]
+                    if r.est_bytes > self.budget:
+                        raise qmc.QMCError(qmc.QMC_ERR_OOM, f"request {r.rid} needs {r.est_bytes} bytes, "
+                                           f"more than the whole budget {self.budget}")
+                    if used + r.est_bytes > self.budget:
+                        break
+                    queue.popleft()
+                    r.system = qmc.System(r.wl, stream=self.stream)
+                    r.admitted_s = time.perf_counter() - t0
+                    used += r.est_bytes
+                    active.append(r)
+                    dirty = True
+                    if log:
+                        log(f"[serve] t={r.admitted_s:.3f}s admit {r.rid} N={r.wl.n_elec} W={r.wl.n_walkers} "
+                            f"sweeps={r.n_sweeps} ({len(active)} resident)")
+                if not active:
+                    if pending:
+                        time.sleep(max(0.0, pending[0].arrival_s * time_scale - (time.perf_counter() - t0)))
+                    continue
+                if dirty:
+                    if batch is not None:
+                        batch.close()
+                    batch = qmc.Batch([r.system for r in active], stream=self.stream, graph=self.graph)
+                    dirty = False
+                batch.sweep(1, measure=True)
+                ms, _ = batch.timing(reset=True)     # synchronises: this sweep's GPU time
+                n_sweep_iters += 1
+                still = []
+                for r in active:
+                    r.latencies_ms.append(ms)
+                    r.done_sweeps += 1
+                    if r.done_sweeps >= r.n_sweeps:
+                        r.energy = r.system.last_energies()
+                        r.final_pos = r.system.get_walkers()[0]
+                        r.finished_s = time.perf_counter() - t0
+                        r.system.close()
+                        r.system = None
+                        used -= r.est_bytes
+                        finished.append(r)
+                        dirty = True
+                    else:
+                        still.append(r)
+                active = still
+        if batch is not None:
+            batch.close()
+        wall = time.perf_counter() - t0
+        lat = np.array([x for r in finished for x in r.latencies_ms])
+        moves = sum(r.wl.n_walkers * r.wl.n_elec * r.n_sweeps for r in finished)
+        return {
+            "requests": len(finished),
+            "wall_s": wall,
+            "moves": moves,
+            "moves_per_s": moves / wall if wall > 0 else 0.0,
+            "gpu_sweep_ms_total": float(lat.sum()) if lat.size else 0.0,
+            "sweep_iterations": n_sweep_iters,
+            "p50_sweep_ms": float(np.percentile(lat, 50)) if lat.size else None,
+            "p99_sweep_ms": float(np.percentile(lat, 99)) if lat.size else None,
+            "mean_queue_s": float(np.mean([r.admitted_s - r.arrival_s * time_scale for r in finished])),
+            "finished": finished,
+        }
+
+
+def build_requests(trace, sweep_scale: float = 1.0, max_workers: int = 8, log=None):
+    """Requests for a trace of ``qmc_inputs.served_trace`` entries: each its own solid-like FP32
+    system (mixed precision), table seeded by the request id; tables are generated on the host
+    before serving starts."""
+    import qmc_inputs as qi
+
+    def make(e):
+        wl = qi.solid(e["n_elec"], e["grid"], n_walkers=e["n_walkers"], n_sweeps=1, precision="mixed",
+                      table_dtype=np.float32, delay_rank=16, recompute_period=64, seed=e["seed"],
+                      name=f"req{e['id']}")
+        wl.delay_rank = delay_rank_for(wl)
+        n = max(1, int(round(e["n_sweeps"] * sweep_scale)))
+        r = Request(rid=e["id"], arrival_s=e["arrival_s"], wl=wl, n_sweeps=n)
+        r.est_bytes = qmc.estimate_device_bytes(wl, wl.n_walkers)
+        if log:
+            log(f"[serve] request {r.rid}: N={wl.n_elec} grid={e['grid']} W={wl.n_walkers} "
+                f"sweeps={n} K={wl.delay_rank} {r.est_bytes / 2**30:.2f} GiB")
+        return r
+
+    with cf.ThreadPoolExecutor(max_workers=max_workers) as ex:
+        reqs = list(ex.map(make, trace))
+    if log:
+        log(f"[serve] built {len(reqs)} requests")
+    return reqs

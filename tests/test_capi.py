@@ -75,3 +75,25 @@ def test_create_rejects_bad_descriptors_before_touching_the_device(libqmc):
     bad.sigma = 0.0
     assert L.qmc_create_system(ctypes.byref(bad), None, ctypes.byref(h)) == qmc.QMC_ERR_ARG
     assert L.qmc_create_system(None, None, ctypes.byref(h)) == qmc.QMC_ERR_ARG
+
+
+def test_max_delay_rank_is_host_only_and_monotone(libqmc):
+    import qmc_inputs as qi
+    from paper_1802_06922_amd import qmc
+    qmc.load_library()
+    ranks = []
+    for n in (16, 64, 128, 256, 512, 1024):
+        wl = qi.solid(n, 8, n_walkers=1, n_sweeps=1, precision="mixed", table_dtype=qi.np.float32)
+        k = qmc.max_delay_rank(wl)
+        assert k in (1, 4, 8, 16, 32, 64)
+        ranks.append(k)
+    # the window grows with N: the largest feasible rank never grows with the system
+    assert ranks == sorted(ranks, reverse=True)
+    assert ranks[0] == 64 and ranks[-1] < 64
+    # FP64 windows take twice the LDS of FP32 ones
+    wl64 = qi.solid(512, 8, n_walkers=1, n_sweeps=1, precision="fp64")
+    assert qmc.max_delay_rank(wl64) <= ranks[4]
+    keep = []
+    d = qmc.make_desc(qi.heg14(), keep)
+    d.n_up = 0
+    assert libqmc.qmc_max_delay_rank(ctypes.byref(d)) == 0

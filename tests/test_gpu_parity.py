@@ -218,7 +218,8 @@ def test_many_ions_and_odd_sizes(gpu, orc):
     _compare_run(gpu, orc, wl, 5, range(4))
 
 
-@pytest.mark.parametrize("K,case", [(4, "heg14"), (8, "ragged"), (16, "solid128"), (64, "solid128")])
+@pytest.mark.parametrize("K,case", [(4, "heg14"), (8, "ragged"), (16, "solid128"), (32, "solid128"),
+                                    (64, "solid64")])
 def test_delayed_update_trajectories(gpu, orc, K, case):
     """Rank-K delayed updates (Schur-complement ratios, one rank-m flush per window) against
     the oracle's Sherman-Morrison chain: same decisions, same energies."""
@@ -229,6 +230,8 @@ def test_delayed_update_trajectories(gpu, orc, K, case):
         wl.n_up, wl.n_dn, wl.n_orb = 9, 7, 9
         wl.coefs = qi.solid_table(9, 14, seed=3, dtype=np.float64)
         walkers, sweeps = range(24), 10
+    elif case == "solid64":
+        wl, walkers, sweeps = qi.solid(64, 20, n_walkers=16, n_sweeps=1), range(16), 4
     else:
         wl, walkers, sweeps = qi.solid128(), [0, 255, 511], 3
     wl.delay_rank = K

@@ -1,0 +1,48 @@
+"""GPU: the serving loop (continuous batching under a memory budget) gives each request the
+results it gets alone."""
+import numpy as np
+import pytest
+
+import qmc_inputs as qi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1802_06922_amd import qmc
+    qmc.load_library()
+    return qmc
+
+
+def test_served_requests_match_alone(gpu):
+    from paper_1802_06922_amd import serve
+    spec = [(24, 12, 6, 4), (48, 14, 10, 7), (16, 10, 4, 3), (96, 16, 8, 5)]   # (N, grid, W, sweeps)
+    reqs = []
+    for i, (n, g, w, sw) in enumerate(spec):
+        wl = qi.solid(n, g, n_walkers=w, n_sweeps=1, precision="mixed", table_dtype=np.float32,
+                      recompute_period=2, seed=10 + i, name=f"req{i}")
+        wl.delay_rank = serve.delay_rank_for(wl, cap=16)
+        r = serve.Request(rid=i, arrival_s=0.0, wl=wl, n_sweeps=sw)
+        r.est_bytes = gpu.estimate_device_bytes(wl, w)
+        reqs.append(r)
+    # a budget holding about two requests at once: later ones join mid-run as others finish
+    budget = int(sorted(r.est_bytes for r in reqs)[-1] + sorted(r.est_bytes for r in reqs)[-2] + 1)
+    srv = serve.Server(hbm_budget_bytes=budget, reserve_bytes=0)
+    st = srv.run(reqs, time_scale=0.0, log=lambda m: print(m, flush=True))
+    assert st["requests"] == len(spec)
+    assert st["sweep_iterations"] < sum(s[3] for s in spec)   # requests shared sweeps
+    for r in st["finished"]:
+        print(f"[serve] compare request {r.rid}", flush=True)
+        s = gpu.System(r.wl)
+        for _ in range(r.n_sweeps):
+            s.sweep(1)
+            e = s.measure()
+        pos = s.get_walkers()[0]
+        s.close()
+        assert np.array_equal(e, r.energy)
+        assert np.array_equal(pos, r.final_pos)
+        assert len(r.latencies_ms) == r.n_sweeps and min(r.latencies_ms) > 0
