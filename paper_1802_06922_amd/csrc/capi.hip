@@ -858,8 +858,7 @@ struct qmc_batch_s {
   size_t lds_cl = 0, lds_cg = 0, lds_m = 0;
   int use_mfma = 1;
   bool use_graph = false;
-  hipGraphExec_t gexec = nullptr;
-  int graph_measure = -1;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
   TimerClass timer;
 };
 
@@ -947,20 +946,24 @@ qmc_status batch_build(qmc_batch b) {
   return QMC_OK;
 }
 
+// One sweep of every member (gather, chain launches) and, if measure, the fused measurement.
 template <typename T>
-hipError_t batch_launch(qmc_batch b, int measure) {
+hipError_t batch_launch(qmc_batch b, int sweep, int measure) {
   const SysDev<T>* sd = static_cast<const SysDev<T>*>(b->d_sysdev);
-  hipError_t e = launch_gather_batched<T>(sd, b->gmap, b->n_g, b->stream);
-  if (e == hipSuccess)
-    e = launch_chain_delayed_batched<T>(sd, b->clmap, b->n_cl, true, b->use_mfma, b->lds_cl, b->stream);
-  if (e == hipSuccess)
-    e = launch_chain_delayed_batched<T>(sd, b->cgmap, b->n_cg, false, b->use_mfma, b->lds_cg, b->stream);
+  hipError_t e = hipSuccess;
+  if (sweep) {
+    e = launch_gather_batched<T>(sd, b->gmap, b->n_g, b->stream);
+    if (e == hipSuccess)
+      e = launch_chain_delayed_batched<T>(sd, b->clmap, b->n_cl, true, b->use_mfma, b->lds_cl, b->stream);
+    if (e == hipSuccess)
+      e = launch_chain_delayed_batched<T>(sd, b->cgmap, b->n_cg, false, b->use_mfma, b->lds_cg, b->stream);
+  }
   if (e == hipSuccess && measure) e = launch_measure_batched<T>(sd, b->mmap, b->n_m, b->lds_m, b->stream);
   return e;
 }
 
-hipError_t batch_launch_any(qmc_batch b, int measure) {
-  return b->precision == QMC_MIXED ? batch_launch<float>(b, measure) : batch_launch<double>(b, measure);
+hipError_t batch_launch_any(qmc_batch b, int sweep, int measure) {
+  return b->precision == QMC_MIXED ? batch_launch<float>(b, sweep, measure) : batch_launch<double>(b, sweep, measure);
 }
 
 }  // namespace
@@ -1013,21 +1016,25 @@ qmc_status qmc_batch_sweep(qmc_batch b, int32_t n_sweeps, int32_t measure) {
   if (n_sweeps < 0) return bfail(b, QMC_ERR_ARG, "n_sweeps must be >= 0");
   BHIP_TRY(b, hipSetDevice(b->device));
   measure = measure ? 1 : 0;
-  if (b->use_graph && (!b->gexec || b->graph_measure != measure)) {
-    if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+  // gexec[v]: captured sweep (v = 0) or sweep + measurement (v = 1), made on first use
+  auto graph_for = [&](int v) -> qmc_status {
+    if (b->gexec[v]) return QMC_OK;
     hipGraph_t graph = nullptr;
     BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
-    const hipError_t e = batch_launch_any(b, measure);
+    const hipError_t e = batch_launch_any(b, 1, v);
     const hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
     if (e != hipSuccess || e2 != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
       return bfail(b, QMC_ERR_DEVICE, "sweep capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
     }
-    const hipError_t e3 = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+    const hipError_t e3 = hipGraphInstantiate(&b->gexec[v], graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
-    if (e3 != hipSuccess) { b->gexec = nullptr; return bfail(b, QMC_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(e3)); }
-    b->graph_measure = measure;
-  }
+    if (e3 != hipSuccess) {
+      b->gexec[v] = nullptr;
+      return bfail(b, QMC_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(e3));
+    }
+    return QMC_OK;
+  };
   for (int it = 0; it < n_sweeps; ++it) {
     std::pair<hipEvent_t, hipEvent_t> ev;
     if (!b->timer.pool.empty()) { ev = b->timer.pool.back(); b->timer.pool.pop_back(); }
@@ -1035,11 +1042,22 @@ qmc_status qmc_batch_sweep(qmc_batch b, int32_t n_sweeps, int32_t measure) {
       BHIP_TRY(b, hipEventCreate(&ev.first));
       BHIP_TRY(b, hipEventCreate(&ev.second));
     }
+    // members whose periodic FP64 rebuild falls after this sweep: as in qmc_sweep, the rebuild
+    // precedes the measurement, so the sweep runs without it and the measurement follows eagerly
+    bool due = false;
+    for (qmc_system s : b->sys)
+      due |= s->d.recompute_period > 0 && (s->sweep_index + 1) % (uint32_t)s->d.recompute_period == 0;
+    const int fused_measure = measure && !due;
+    if (b->use_graph) {
+      const qmc_status st = graph_for(fused_measure);
+      if (st != QMC_OK) return st;
+    }
     BHIP_TRY(b, hipEventRecord(ev.first, b->stream));
-    if (b->use_graph) BHIP_TRY(b, hipGraphLaunch(b->gexec, b->stream));
-    else BHIP_TRY(b, batch_launch_any(b, measure));
-    BHIP_TRY(b, hipEventRecord(ev.second, b->stream));
-    b->timer.live.push_back(ev);
+    if (b->use_graph) {
+      BHIP_TRY(b, hipGraphLaunch(b->gexec[fused_measure], b->stream));
+    } else {
+      BHIP_TRY(b, batch_launch_any(b, 1, fused_measure));
+    }
     for (qmc_system s : b->sys) {
       s->sweep_index += 1;
       if (s->d.recompute_period > 0 && s->sweep_index % (uint32_t)s->d.recompute_period == 0) {
@@ -1049,6 +1067,9 @@ qmc_status qmc_batch_sweep(qmc_batch b, int32_t n_sweeps, int32_t measure) {
         if (e != hipSuccess) return bfail(b, QMC_ERR_DEVICE, "rebuild launch: %s", hipGetErrorString(e));
       }
     }
+    if (measure && due) BHIP_TRY(b, batch_launch_any(b, 0, 1));
+    BHIP_TRY(b, hipEventRecord(ev.second, b->stream));
+    b->timer.live.push_back(ev);
   }
   return QMC_OK;
 }
@@ -1076,7 +1097,8 @@ qmc_status qmc_batch_destroy(qmc_batch b) {
   if (!b) return QMC_OK;
   (void)hipSetDevice(b->device);
   (void)hipStreamSynchronize(b->stream);
-  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  for (hipGraphExec_t g : b->gexec)
+    if (g) (void)hipGraphExecDestroy(g);
   for (auto& ev : b->timer.live) { (void)hipEventDestroy(ev.first); (void)hipEventDestroy(ev.second); }
   for (auto& ev : b->timer.pool) { (void)hipEventDestroy(ev.first); (void)hipEventDestroy(ev.second); }
   if (b->d_sysdev) (void)hipFree(b->d_sysdev);
