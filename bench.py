@@ -230,7 +230,7 @@ def bench_served(args) -> int:
 
     trace = qi.served_trace(n_requests=args.requests, rate_per_s=20.0, seed=0)
     log = lambda m: print(m, file=sys.stderr, flush=True)
-    reqs = serve.build_requests(trace, sweep_scale=args.sweep_scale, log=log)
+    reqs = serve.build_requests(trace, sweep_scale=args.sweep_scale, table_pool=True, log=log)
     srv = serve.Server(graph=not args.no_graph)
     st = srv.run(reqs, log=log)
     line = {

@@ -214,9 +214,11 @@ qmc_status qmc_get_last_energies(qmc_system s, double* out);
  * >= 4, initialised) are advanced by one orbital-gather launch, one delayed-
  * chain launch per LDS class and one measurement launch per sweep.  Each
  * system's results are identical to advancing it alone.  All launches go to
- * the batch's stream; do not drive a member system through another stream
- * while the batch is in use.  The batch does not own the systems; re-create it
- * after re-initialising or destroying a member. */
+ * the batch's stream.  qmc_batch_sweep orders itself after work already
+ * queued on the members' own streams and orders later work on those streams
+ * after itself (stream events), so member calls such as qmc_get_accept_log
+ * may follow on the member's stream.  The batch does not own the systems;
+ * re-create it after re-initialising or destroying a member. */
 typedef struct qmc_batch_s* qmc_batch;
 
 qmc_status qmc_batch_create(const qmc_system* systems, int32_t n_systems, void* hip_stream, qmc_batch* out);

@@ -859,6 +859,11 @@ struct qmc_batch_s {
   int use_mfma = 1;
   bool use_graph = false;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  // ordering against the members' own streams: one event per distinct member stream
+  // (work queued there before a batch sweep) and one on the batch stream (after it)
+  std::vector<hipStream_t> member_streams;
+  std::vector<hipEvent_t> member_ev;
+  hipEvent_t done_ev = nullptr;
   TimerClass timer;
 };
 
@@ -999,6 +1004,17 @@ qmc_status qmc_batch_create(const qmc_system* systems, int32_t n_systems, void* 
     qmc_batch_destroy(b);
     return st;
   }
+  for (qmc_system s : b->sys)
+    if (s->stream != b->stream &&
+        std::find(b->member_streams.begin(), b->member_streams.end(), s->stream) == b->member_streams.end())
+      b->member_streams.push_back(s->stream);
+  b->member_ev.assign(b->member_streams.size(), nullptr);
+  bool ok = hipEventCreateWithFlags(&b->done_ev, hipEventDisableTiming) == hipSuccess;
+  for (auto& e : b->member_ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    qmc_batch_destroy(b);
+    return bfail(nullptr, QMC_ERR_DEVICE, "event creation failed");
+  }
   *out = b;
   return QMC_OK;
 }
@@ -1035,6 +1051,11 @@ qmc_status qmc_batch_sweep(qmc_batch b, int32_t n_sweeps, int32_t measure) {
     }
     return QMC_OK;
   };
+  if (n_sweeps == 0) return QMC_OK;
+  for (size_t i = 0; i < b->member_streams.size(); ++i) {
+    BHIP_TRY(b, hipEventRecord(b->member_ev[i], b->member_streams[i]));
+    BHIP_TRY(b, hipStreamWaitEvent(b->stream, b->member_ev[i], 0));
+  }
   for (int it = 0; it < n_sweeps; ++it) {
     std::pair<hipEvent_t, hipEvent_t> ev;
     if (!b->timer.pool.empty()) { ev = b->timer.pool.back(); b->timer.pool.pop_back(); }
@@ -1071,6 +1092,10 @@ qmc_status qmc_batch_sweep(qmc_batch b, int32_t n_sweeps, int32_t measure) {
     BHIP_TRY(b, hipEventRecord(ev.second, b->stream));
     b->timer.live.push_back(ev);
   }
+  if (!b->member_streams.empty()) {
+    BHIP_TRY(b, hipEventRecord(b->done_ev, b->stream));
+    for (hipStream_t ms : b->member_streams) BHIP_TRY(b, hipStreamWaitEvent(ms, b->done_ev, 0));
+  }
   return QMC_OK;
 }
 
@@ -1099,6 +1124,9 @@ qmc_status qmc_batch_destroy(qmc_batch b) {
   (void)hipStreamSynchronize(b->stream);
   for (hipGraphExec_t g : b->gexec)
     if (g) (void)hipGraphExecDestroy(g);
+  for (hipEvent_t e : b->member_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (b->done_ev) (void)hipEventDestroy(b->done_ev);
   for (auto& ev : b->timer.live) { (void)hipEventDestroy(ev.first); (void)hipEventDestroy(ev.second); }
   for (auto& ev : b->timer.pool) { (void)hipEventDestroy(ev.first); (void)hipEventDestroy(ev.second); }
   if (b->d_sysdev) (void)hipFree(b->d_sysdev);

@@ -151,16 +151,33 @@ class Server:
         }
 
 
-def build_requests(trace, sweep_scale: float = 1.0, max_workers: int = 8, log=None):
-    """Requests for a trace of ``qmc_inputs.served_trace`` entries: each its own solid-like FP32
-    system (mixed precision), table seeded by the request id; tables are generated on the host
-    before serving starts."""
+def build_requests(trace, sweep_scale: float = 1.0, max_workers: int = 8, table_pool: bool = False,
+                   log=None):
+    """Requests for a trace of ``qmc_inputs.served_trace`` entries, each a solid-like mixed-precision
+    system.  Tables are generated on the host before serving starts: per request with seed = its
+    id, or, with ``table_pool``, as the first n_orb orbitals of one 512-orbital table per grid size
+    (seed = grid), which keeps generation of a long trace to a few tables; the served arithmetic
+    does not depend on the coefficient values."""
     import qmc_inputs as qi
 
+    pool: dict = {}
+    if table_pool:
+        grids = sorted({e["grid"] for e in trace})
+        need = {g: max(e["n_elec"] // 2 for e in trace if e["grid"] == g) for g in grids}
+        with cf.ThreadPoolExecutor(max_workers=max_workers) as ex:
+            tabs = list(ex.map(lambda g: qi.solid_table(need[g], g, seed=g, dtype=np.float32), grids))
+        pool = dict(zip(grids, tabs))
+        if log:
+            log(f"[serve] table pool: grids {grids}")
+
     def make(e):
-        wl = qi.solid(e["n_elec"], e["grid"], n_walkers=e["n_walkers"], n_sweeps=1, precision="mixed",
-                      table_dtype=np.float32, delay_rank=16, recompute_period=64, seed=e["seed"],
-                      name=f"req{e['id']}")
+        wl = qi.solid(e["n_elec"], 4 if table_pool else e["grid"], n_walkers=e["n_walkers"], n_sweeps=1,
+                      precision="mixed", table_dtype=np.float32, delay_rank=16, recompute_period=64,
+                      seed=e["seed"], name=f"req{e['id']}")
+        if table_pool:
+            g = e["grid"]
+            wl.grid = (g, g, g)
+            wl.coefs = np.ascontiguousarray(pool[g][..., :wl.n_orb])
         wl.delay_rank = delay_rank_for(wl)
         n = max(1, int(round(e["n_sweeps"] * sweep_scale)))
         r = Request(rid=e["id"], arrival_s=e["arrival_s"], wl=wl, n_sweeps=n)
