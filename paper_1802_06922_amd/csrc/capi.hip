@@ -298,7 +298,7 @@ WalkerSizes walker_sizes(int n_up, int n_dn, int precision, int W, int n_orb) {
   z.status = W * sizeof(int);
   z.scratch = W * bs * sizeof(double);
   z.drift = W * 2 * sizeof(double);
-  z.energy = W * 4 * sizeof(double);
+  z.energy = W * (4 + kMaxMeasureParts * 5) * sizeof(double);   // energies, then measurement partials
   z.val64 = precision == QMC_MIXED ? 2 * W * N * S * sizeof(double) : 0;
   z.nguard = W * sizeof(uint32_t);
   z.sweep = sizeof(uint32_t);
@@ -654,9 +654,9 @@ qmc_status qmc_measure_local_energy(qmc_system s, double* out, int32_t out_on_de
   double* dst = out_on_device ? out : s->energy;
   hipError_t e;
   if (s->d.precision == QMC_MIXED)
-    e = timed(s, 2, [&] { return launch_measure<float>(s->P, walkers_of<float>(s), s->E, dst, s->stream); });
+    e = timed(s, 2, [&] { return launch_measure<float>(s->P, walkers_of<float>(s), s->E, s->energy + 4 * (size_t)s->P.W, dst, s->stream); });
   else
-    e = timed(s, 2, [&] { return launch_measure<double>(s->P, walkers_of<double>(s), s->E, dst, s->stream); });
+    e = timed(s, 2, [&] { return launch_measure<double>(s->P, walkers_of<double>(s), s->E, s->energy + 4 * (size_t)s->P.W, dst, s->stream); });
   if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "measure launch: %s", hipGetErrorString(e));
   if (out_on_device) return QMC_OK;
   const size_t nb = (size_t)s->P.W * 4 * sizeof(double);
@@ -853,8 +853,8 @@ struct qmc_batch_s {
   std::string err;
   void* d_sysdev = nullptr;
   int2* d_maps = nullptr;
-  int2 *gmap = nullptr, *clmap = nullptr, *cgmap = nullptr, *mmap = nullptr;
-  int n_g = 0, n_cl = 0, n_cg = 0, n_m = 0;
+  int2 *gmap = nullptr, *clmap = nullptr, *cgmap = nullptr, *mmap = nullptr, *fmap = nullptr;
+  int n_g = 0, n_cl = 0, n_cg = 0, n_m = 0, n_f = 0;
   size_t lds_cl = 0, lds_cg = 0, lds_m = 0;
   int use_mfma = 1;
   bool use_graph = false;
@@ -901,7 +901,7 @@ qmc_status batch_build(qmc_batch b) {
   const int V = sizeof(T) == sizeof(double) ? 2 : 4;
   const size_t budget = (size_t)max_lds_per_block();
   std::vector<SysDev<T>> sd(n);
-  std::vector<int2> g, cl, cg, m;
+  std::vector<int2> g, cl, cg, m, f;
   for (int i = 0; i < n; ++i) {
     qmc_system s = b->sys[i];
     SysDev<T>& d = sd[i];
@@ -911,6 +911,8 @@ qmc_status batch_build(qmc_batch b) {
     d.E = s->E;
     d.table = static_cast<const T*>(s->d_table);
     d.eout = s->energy;
+    d.mpart = s->energy + 4 * (size_t)s->P.W;
+    d.np = measure_parts(s->P.W);
     d.K = s->d.delay_rank;
     const int nmax = s->P.n_up > s->P.n_dn ? s->P.n_up : s->P.n_dn;
     d.ldl = nmax | 1;
@@ -926,26 +928,30 @@ qmc_status batch_build(qmc_batch b) {
       return bfail(b, QMC_ERR_ARG, "system %d does not fit the batched chain's LDS", i);
     for (int w = 0; w < s->P.W; ++w) {
       (in_lds ? cl : cg).push_back(make_int2(i, w));
-      m.push_back(make_int2(i, w));
+      f.push_back(make_int2(i, w));
+      for (int p = 0; p < d.np; ++p) m.push_back(make_int2(i, w * d.np + p));
     }
     if (in_lds) b->lds_cl = std::max(b->lds_cl, bl);
     else b->lds_cg = std::max(b->lds_cg, gl);
-    b->lds_m = std::max(b->lds_m, measure_lds_bytes(s->P));
+    b->lds_m = std::max(b->lds_m, measure_lds_bytes(s->P, d.np));
   }
   BHIP_TRY(b, hipMalloc(&b->d_sysdev, sizeof(SysDev<T>) * n));
-  const size_t nm = g.size() + cl.size() + cg.size() + m.size();
+  const size_t nm = g.size() + cl.size() + cg.size() + m.size() + f.size();
   BHIP_TRY(b, hipMalloc(reinterpret_cast<void**>(&b->d_maps), sizeof(int2) * nm));
   b->gmap = b->d_maps;
   b->clmap = b->gmap + g.size();
   b->cgmap = b->clmap + cl.size();
   b->mmap = b->cgmap + cg.size();
+  b->fmap = b->mmap + m.size();
   b->n_g = (int)g.size(); b->n_cl = (int)cl.size(); b->n_cg = (int)cg.size(); b->n_m = (int)m.size();
+  b->n_f = (int)f.size();
   std::vector<int2> all;
   all.reserve(nm);
   all.insert(all.end(), g.begin(), g.end());
   all.insert(all.end(), cl.begin(), cl.end());
   all.insert(all.end(), cg.begin(), cg.end());
   all.insert(all.end(), m.begin(), m.end());
+  all.insert(all.end(), f.begin(), f.end());
   BHIP_TRY(b, hipMemcpy(b->d_sysdev, sd.data(), sizeof(SysDev<T>) * n, hipMemcpyHostToDevice));
   BHIP_TRY(b, hipMemcpy(b->d_maps, all.data(), sizeof(int2) * nm, hipMemcpyHostToDevice));
   return QMC_OK;
@@ -963,7 +969,7 @@ hipError_t batch_launch(qmc_batch b, int sweep, int measure) {
     if (e == hipSuccess)
       e = launch_chain_delayed_batched<T>(sd, b->cgmap, b->n_cg, false, b->use_mfma, b->lds_cg, b->stream);
   }
-  if (e == hipSuccess && measure) e = launch_measure_batched<T>(sd, b->mmap, b->n_m, b->lds_m, b->stream);
+  if (e == hipSuccess && measure) e = launch_measure_batched<T>(sd, b->mmap, b->n_m, b->fmap, b->n_f, b->lds_m, b->stream);
   return e;
 }
 

@@ -13,8 +13,8 @@
 // sum_G w(G) |S(G)|^2 with S(G) built segment by segment along Gz: one sincos
 // per (segment, electron) and a complex recurrence for the next Gz.
 //
-// One workgroup per walker; every phase spreads over all 256 threads and
-// combines partial sums in a fixed order (bitwise repeatable).
+// Several workgroups per walker (see measure_part); every phase spreads over
+// all threads and combines partial sums in a fixed order (bitwise repeatable).
 #include "qmc_kernels.hpp"
 
 namespace qmc {
@@ -45,36 +45,47 @@ __device__ __forceinline__ double screened_images(double dx, double dy, double d
   return s;
 }
 
+// Every walker's local energy is computed by np workgroups (parts): part p
+// takes the kinetic terms of electrons i = p (mod np) and every np-th pair,
+// ion pair and reciprocal segment; it writes five partial sums, and a second
+// kernel adds the parts of a walker in a fixed order.  Spreading a walker
+// over several workgroups keeps enough waves in flight to hide the latency of
+// the FP64 transcendental sequences (erfc, sincos) that dominate here.
+constexpr int kPartSums = 5;   // kinetic, e-e real space, e-I real space, e-e reciprocal, e-I reciprocal
+
 struct MeasureLayout {
   size_t pos, ez, gd, ld, gjp, ljp, total;
+  int nloc;    // electrons per part (upper bound)
   int parts;   // Jastrow partner split per electron
 };
 
-__host__ __device__ inline MeasureLayout measure_layout(int N) {
+__host__ __device__ inline MeasureLayout measure_layout(int N, int np) {
   MeasureLayout L;
+  L.nloc = (N + np - 1) / np;
   int parts = 1;
-  while (parts * 2 * N <= kBlock) parts *= 2;
+  while (parts * 2 * L.nloc <= kBlock) parts *= 2;
   L.parts = parts;
   size_t o = 0;
   L.pos = o; o += sizeof(double) * 3 * N;
   L.ez = o; o += sizeof(double) * 2 * N;
-  L.gd = o; o += sizeof(double) * 3 * N;
-  L.ld = o; o += sizeof(double) * N;
-  L.gjp = o; o += sizeof(double) * 3 * (size_t)N * parts;
-  L.ljp = o; o += sizeof(double) * (size_t)N * parts;
+  L.gd = o; o += sizeof(double) * 3 * L.nloc;
+  L.ld = o; o += sizeof(double) * L.nloc;
+  L.gjp = o; o += sizeof(double) * 3 * (size_t)L.nloc * parts;
+  L.ljp = o; o += sizeof(double) * (size_t)L.nloc * parts;
   L.total = o;
   return L;
 }
 
 template <typename T>
-__device__ __forceinline__ void measure_walker(const SysParams& P, const Walkers<T>& Wk, const EwaldParams& E,
-                                               double* __restrict__ out, int w) {
+__device__ __forceinline__ void measure_part(const SysParams& P, const Walkers<T>& Wk, const EwaldParams& E,
+                                             double* __restrict__ partial, int w, int p, int np) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ Jastrow sj;
-  __shared__ double red[5 * kWaves];
+  __shared__ double red[kPartSums * kWaves];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = P.N;
-  const MeasureLayout lay = measure_layout(N);
+  const MeasureLayout lay = measure_layout(N, np);
+  const int nloc = lay.nloc;
   double* spos = reinterpret_cast<double*>(smem + lay.pos);
   double* sez = reinterpret_cast<double*>(smem + lay.ez);
   double* sgd = reinterpret_cast<double*>(smem + lay.gd);
@@ -97,8 +108,10 @@ __device__ __forceinline__ void measure_walker(const SysParams& P, const Walkers
       sez[2 * i + 1] = s;
     }
 
-  // (1) determinant part: one wave per electron, lanes over orbitals (coalesced rows)
-  for (int i = wave; i < N; i += kWaves) {
+  // (1) determinant part of this part's electrons: one wave per electron, lanes over orbitals
+  for (int li = wave; li < nloc; li += kWaves) {
+    const int i = p + li * np;
+    if (i >= N) break;
     const int sp = i < P.n_up ? 0 : 1;
     const int n = sp ? P.n_dn : P.n_up, k = i - (sp ? P.n_up : 0);
     const size_t item = (size_t)w * N + i;
@@ -113,13 +126,14 @@ __device__ __forceinline__ void measure_walker(const SysParams& P, const Walkers
       l2 += b * (double)row[4 * P.S + l];
     }
     gx = wave_sum_dpp(gx); gy = wave_sum_dpp(gy); gz = wave_sum_dpp(gz); l2 = wave_sum_dpp(l2);
-    if (lane == 0) { sgd[3 * i] = gx; sgd[3 * i + 1] = gy; sgd[3 * i + 2] = gz; sld[i] = l2; }
+    if (lane == 0) { sgd[3 * li] = gx; sgd[3 * li + 1] = gy; sgd[3 * li + 2] = gz; sld[li] = l2; }
   }
 
   // (2) Jastrow gradient and Laplacian: (electron, part) items, partners j = part (mod parts)
   const int parts = lay.parts;
-  for (int q = tid; q < N * parts; q += kBlock) {
-    const int i = q % N, part = q / N;
+  for (int q = tid; q < nloc * parts; q += kBlock) {
+    const int li = q % nloc, part = q / nloc, i = p + li * np;
+    if (i >= N) continue;
     const double xi = spos[3 * i], yi = spos[3 * i + 1], zi = spos[3 * i + 2];
     const bool up_i = i < P.n_up;
     double g[3] = {0.0, 0.0, 0.0}, lj = 0.0;
@@ -143,18 +157,20 @@ __device__ __forceinline__ void measure_walker(const SysParams& P, const Walkers
       g[0] += f * dx; g[1] += f * dy; g[2] += f * dz;
       lj += d2u + 2.0 * f;
     }
-    double* gp = sgj + 3 * ((size_t)part * N + i);
+    double* gp = sgj + 3 * ((size_t)part * nloc + li);
     gp[0] = g[0]; gp[1] = g[1]; gp[2] = g[2];
-    slj[(size_t)part * N + i] = lj;
+    slj[(size_t)part * nloc + li] = lj;
   }
 
+  // (3) Coulomb terms: every np-th item of each list, items q = p + np * (tid + kBlock * r)
   double vee = 0.0, vei = 0.0, vee_k = 0.0, vei_k = 0.0;
   if (E.enabled) {
     const double rcut2 = E.rcut * E.rcut;
+    const int stride = np * kBlock;
     // (3a) electron pairs, each once: j = i + d (mod N), d = 1..(N-1)/2, and d = N/2 for i < N/2
     const int D = (N - 1) / 2;
     const int n_pairs = N * D + ((N % 2 == 0) ? N / 2 : 0);
-    for (int q = tid; q < n_pairs; q += kBlock) {
+    for (int q = p + np * tid; q < n_pairs; q += stride) {
       int i, j;
       if (q < N * D) { i = q % N; j = i + q / N + 1; if (j >= N) j -= N; }
       else { i = q - N * D; j = i + N / 2; }
@@ -164,7 +180,7 @@ __device__ __forceinline__ void measure_walker(const SysParams& P, const Walkers
       vee += screened_images(dx, dy, dz, P.L, E.kappa, rcut2);
     }
     // (3b) electron-ion pairs
-    for (int q = tid; q < N * P.n_ions; q += kBlock) {
+    for (int q = p + np * tid; q < N * P.n_ions; q += stride) {
       const int i = q % N, I = q / N;
       const double* ion = P.ions + 4 * I;
       const double dx = min_image(spos[3 * i] - ion[0], P.L);
@@ -174,7 +190,7 @@ __device__ __forceinline__ void measure_walker(const SysParams& P, const Walkers
     }
     // (3c) reciprocal space: one item per segment of at most kSeg vectors of one
     // (Gx, Gy) column; S(G) over all electrons, then w(G) |S|^2 and the cross term.
-    for (int q = tid; q < E.n_seg; q += kBlock) {
+    for (int q = p + np * tid; q < E.n_seg; q += stride) {
       const int* seg = E.segs + 5 * q;
       const int mx = seg[0], my = seg[1], lo = seg[2], cnt = seg[3] - seg[2] + 1, goff = seg[4];
       double sr[kSeg], si[kSeg];
@@ -208,15 +224,16 @@ __device__ __forceinline__ void measure_walker(const SysParams& P, const Walkers
 
   // (4) per-electron kinetic term from (1) and (2)
   double tkin = 0.0;
-  for (int i = tid; i < N; i += kBlock) {
+  for (int li = tid; li < nloc; li += kBlock) {
+    if (p + li * np >= N) break;
     double g[3] = {0.0, 0.0, 0.0}, lj = 0.0;
     for (int part = 0; part < parts; ++part) {
-      const double* gp = sgj + 3 * ((size_t)part * N + i);
+      const double* gp = sgj + 3 * ((size_t)part * nloc + li);
       g[0] += gp[0]; g[1] += gp[1]; g[2] += gp[2];
-      lj += slj[(size_t)part * N + i];
+      lj += slj[(size_t)part * nloc + li];
     }
-    const double dot = sgd[3 * i] * g[0] + sgd[3 * i + 1] * g[1] + sgd[3 * i + 2] * g[2];
-    tkin += -0.5 * (sld[i] + 2.0 * dot + lj + g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    const double dot = sgd[3 * li] * g[0] + sgd[3 * li + 1] * g[1] + sgd[3 * li + 2] * g[2];
+    tkin += -0.5 * (sld[li] + 2.0 * dot + lj + g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
   }
   const double a = wave_sum_dpp(tkin), b = wave_sum_dpp(vee), c = wave_sum_dpp(vei);
   const double d = wave_sum_dpp(vee_k), e = wave_sum_dpp(vei_k);
@@ -225,25 +242,40 @@ __device__ __forceinline__ void measure_walker(const SysParams& P, const Walkers
     red[3 * kWaves + wave] = d; red[4 * kWaves + wave] = e;
   }
   __syncthreads();
-  if (tid == 0) {
-    double t = 0.0, x = 0.0, y = 0.0, xk = 0.0, yk = 0.0;
-    for (int q = 0; q < kWaves; ++q) {
-      t += red[q]; x += red[kWaves + q]; y += red[2 * kWaves + q];
-      xk += red[3 * kWaves + q]; yk += red[4 * kWaves + q];
-    }
-    out[4 * w + 0] = t;
-    out[4 * w + 1] = E.enabled ? (x + xk) + E.c_ee : 0.0;
-    out[4 * w + 2] = E.enabled ? (y + yk) + E.c_ei : 0.0;
-    out[4 * w + 3] = E.enabled ? E.v_ii : 0.0;
+  if (tid < kPartSums) {
+    double t = 0.0;
+    for (int q = 0; q < kWaves; ++q) t += red[tid * kWaves + q];
+    partial[((size_t)w * np + p) * kPartSums + tid] = t;
   }
+}
+
+// out[w] = (T, V_ee, V_eI, V_II) from the parts' partial sums, added in part order.
+__device__ __forceinline__ void measure_finish(const EwaldParams& E, const double* __restrict__ partial,
+                                               double* __restrict__ out, int w, int np) {
+  double t = 0.0, x = 0.0, y = 0.0, xk = 0.0, yk = 0.0;
+  for (int p = 0; p < np; ++p) {
+    const double* q = partial + ((size_t)w * np + p) * kPartSums;
+    t += q[0]; x += q[1]; y += q[2]; xk += q[3]; yk += q[4];
+  }
+  out[4 * w + 0] = t;
+  out[4 * w + 1] = E.enabled ? (x + xk) + E.c_ee : 0.0;
+  out[4 * w + 2] = E.enabled ? (y + yk) + E.c_ei : 0.0;
+  out[4 * w + 3] = E.enabled ? E.v_ii : 0.0;
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_measure(SysParams P, Walkers<T> Wk, EwaldParams E,
-                                                    double* __restrict__ out) {
-  measure_walker<T>(P, Wk, E, out, blockIdx.x);
+                                                    double* __restrict__ partial, int np) {
+  measure_part<T>(P, Wk, E, partial, blockIdx.x / np, blockIdx.x % np, np);
 }
 
+__global__ __launch_bounds__(kBlock) void k_measure_finish(EwaldParams E, const double* __restrict__ partial,
+                                                           double* __restrict__ out, int W, int np) {
+  const int w = blockIdx.x * kBlock + threadIdx.x;
+  if (w < W) measure_finish(E, partial, out, w, np);
+}
+
+// Batched: block b computes part bmap[b].y % np of walker bmap[b].y / np of system bmap[b].x.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_measure_batched(const SysDev<T>* __restrict__ sd,
                                                             const int2* __restrict__ bmap) {
@@ -255,14 +287,32 @@ __global__ __launch_bounds__(kBlock) void k_measure_batched(const SysDev<T>* __r
     for (int q = threadIdx.x; q < (int)(sizeof(SysDev<T>) / 4); q += kBlock) dst[q] = src[q];
   }
   __syncthreads();
-  measure_walker<T>(s.P, s.W, s.E, s.eout, m.y);
+  measure_part<T>(s.P, s.W, s.E, s.mpart, m.y / s.np, m.y % s.np, s.np);
 }
 
-size_t measure_lds_bytes(const SysParams& P) { return measure_layout(P.N).total; }
+// Batched finish: thread t handles (system, walker) fmap[t].
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_measure_finish_batched(const SysDev<T>* __restrict__ sd,
+                                                                   const int2* __restrict__ fmap, int n) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n) return;
+  const int2 m = fmap[t];
+  const SysDev<T>& s = sd[m.x];
+  measure_finish(s.E, s.mpart, s.eout, m.y, s.np);
+}
+
+int measure_parts(int W) {
+  // aim at about eight workgroups per compute unit over the whole launch
+  int np = 1;
+  while (np < 8 && (long)W * np < 2048) np *= 2;
+  return np;
+}
+
+size_t measure_lds_bytes(const SysParams& P, int np) { return measure_layout(P.N, np).total; }
 
 template <typename T>
-hipError_t launch_measure_batched(const SysDev<T>* sd, const int2* bmap, int n_blocks, size_t lds,
-                                  hipStream_t st) {
+hipError_t launch_measure_batched(const SysDev<T>* sd, const int2* bmap, int n_blocks, const int2* fmap,
+                                  int n_walkers, size_t lds, hipStream_t st) {
   if (n_blocks <= 0) return hipSuccess;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_measure_batched<T>),
@@ -270,28 +320,39 @@ hipError_t launch_measure_batched(const SysDev<T>* sd, const int2* bmap, int n_b
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_measure_batched<T>, dim3(n_blocks), dim3(kBlock), lds, st, sd, bmap);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_measure_finish_batched<T>, dim3((n_walkers + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
+                     sd, fmap, n_walkers);
   return hipGetLastError();
 }
 
-template hipError_t launch_measure_batched<double>(const SysDev<double>*, const int2*, int, size_t, hipStream_t);
-template hipError_t launch_measure_batched<float>(const SysDev<float>*, const int2*, int, size_t, hipStream_t);
+template hipError_t launch_measure_batched<double>(const SysDev<double>*, const int2*, int, const int2*, int,
+                                                   size_t, hipStream_t);
+template hipError_t launch_measure_batched<float>(const SysDev<float>*, const int2*, int, const int2*, int,
+                                                  size_t, hipStream_t);
 
 template <typename T>
-hipError_t launch_measure(const SysParams& P, const Walkers<T>& Wk, const EwaldParams& E, double* out,
-                          hipStream_t st) {
-  const size_t bytes = measure_layout(P.N).total;
+hipError_t launch_measure(const SysParams& P, const Walkers<T>& Wk, const EwaldParams& E, double* partial,
+                          double* out, hipStream_t st) {
+  const int np = measure_parts(P.W);
+  const size_t bytes = measure_layout(P.N, np).total;
   if (bytes > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_measure<T>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_measure<T>, dim3(P.W), dim3(kBlock), bytes, st, P, Wk, E, out);
+  hipLaunchKernelGGL(k_measure<T>, dim3(P.W * np), dim3(kBlock), bytes, st, P, Wk, E, partial, np);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_measure_finish, dim3((P.W + kBlock - 1) / kBlock), dim3(kBlock), 0, st, E, partial, out,
+                     P.W, np);
   return hipGetLastError();
 }
 
-template hipError_t launch_measure<double>(const SysParams&, const Walkers<double>&, const EwaldParams&,
+template hipError_t launch_measure<double>(const SysParams&, const Walkers<double>&, const EwaldParams&, double*,
                                            double*, hipStream_t);
-template hipError_t launch_measure<float>(const SysParams&, const Walkers<float>&, const EwaldParams&,
+template hipError_t launch_measure<float>(const SysParams&, const Walkers<float>&, const EwaldParams&, double*,
                                           double*, hipStream_t);
 
 }  // namespace qmc

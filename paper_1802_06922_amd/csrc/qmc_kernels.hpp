@@ -30,10 +30,11 @@ struct SysDev {
   EwaldParams E;
   const T* table;
   double* eout;      // [W][4] local energies
+  double* mpart;     // [W][np][5] partial sums of the measurement
   int K;             // delay rank of the chain
   int ldl;           // LDS row stride of the inverse
   int tpi_log2;      // gather lanes per proposal (log2)
-  int pad;
+  int np;            // workgroups per walker in the measurement
 };
 
 // Orbital gather: for every (walker, electron), either draw the proposal of
@@ -81,15 +82,19 @@ template <typename T>
 hipError_t launch_rebuild(const SysParams& P, const Walkers<T>& Wk, double* scratch, double* drift,
                           hipStream_t st);
 
-// Local energy of every walker: out[W][4].
+// Local energy of every walker: out[W][4]; partial: W * kMaxMeasureParts * 5 doubles of scratch.
+constexpr int kMaxMeasureParts = 8;
 template <typename T>
-hipError_t launch_measure(const SysParams& P, const Walkers<T>& Wk, const EwaldParams& E, double* out,
-                          hipStream_t st);
-// Batched measurement; bmap[b] = (system, walker); lds = dynamic LDS bytes (max over systems).
+hipError_t launch_measure(const SysParams& P, const Walkers<T>& Wk, const EwaldParams& E, double* partial,
+                          double* out, hipStream_t st);
+// Workgroups per walker the measurement uses for W walkers (a power of two, at most kMaxMeasureParts).
+int measure_parts(int W);
+// Batched measurement: bmap[b] = (system, walker * np + part) per workgroup, then fmap[t] =
+// (system, walker) for the n_walkers sums; lds = dynamic LDS bytes (max over systems).
 template <typename T>
-hipError_t launch_measure_batched(const SysDev<T>* sd, const int2* bmap, int n_blocks, size_t lds,
-                                  hipStream_t st);
-size_t measure_lds_bytes(const SysParams& P);
+hipError_t launch_measure_batched(const SysDev<T>* sd, const int2* bmap, int n_blocks, const int2* fmap,
+                                  int n_walkers, size_t lds, hipStream_t st);
+size_t measure_lds_bytes(const SysParams& P, int np);
 
 // Size in bytes of the dynamic LDS the chain kernel needs for P.
 size_t chain_lds_bytes(const SysParams& P, size_t tsize, bool b_in_lds);
