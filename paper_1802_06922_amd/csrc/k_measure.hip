@@ -51,6 +51,12 @@ __device__ __forceinline__ double screened_images(double dx, double dy, double d
 // kernel adds the parts of a walker in a fixed order.  Spreading a walker
 // over several workgroups keeps enough waves in flight to hide the latency of
 // the FP64 transcendental sequences (erfc, sincos) that dominate here.
+// Sum over the four lanes of a lane quad (all four active), the same in each lane.
+__device__ __forceinline__ double quad_sum(double v) {
+  v = dpp_add<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  return dpp_add<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+}
+
 constexpr int kPartSums = 5;   // kinetic, e-e real space, e-I real space, e-e reciprocal, e-I reciprocal
 
 struct MeasureLayout {
@@ -188,15 +194,19 @@ __device__ __forceinline__ void measure_part(const SysParams& P, const Walkers<T
       const double dz = min_image(spos[3 * i + 2] - ion[2], P.L);
       vei -= ion[3] * screened_images(dx, dy, dz, P.L, E.kappa, rcut2);
     }
-    // (3c) reciprocal space: one item per segment of at most kSeg vectors of one
-    // (Gx, Gy) column; S(G) over all electrons, then w(G) |S|^2 and the cross term.
-    for (int q = p + np * tid; q < E.n_seg; q += stride) {
+    // (3c) reciprocal space: items (segment, quarter of the electrons) in lane quads; a
+    // segment holds at most kSeg vectors of one (Gx, Gy) column.  Each lane sums e^{iG.r}
+    // over its quarter (one sincos per electron, then the Gz recurrence), the quad adds its
+    // four partial structure factors, and the quad's first lane adds w(G) |S|^2 and the
+    // cross term with the ions.  Quads are active or idle as a whole.
+    for (int u = tid; p + np * (u >> 2) < E.n_seg; u += kBlock) {
+      const int q = p + np * (u >> 2), c4 = u & 3;
       const int* seg = E.segs + 5 * q;
       const int mx = seg[0], my = seg[1], lo = seg[2], cnt = seg[3] - seg[2] + 1, goff = seg[4];
       double sr[kSeg], si[kSeg];
 #pragma unroll
       for (int m = 0; m < kSeg; ++m) { sr[m] = 0.0; si[m] = 0.0; }
-      for (int i = 0; i < N; ++i) {
+      for (int i = c4; i < N; i += 4) {
         double br, bi;
         sincos(g0 * (mx * spos[3 * i] + my * spos[3 * i + 1] + lo * spos[3 * i + 2]), &bi, &br);
         const double er = sez[2 * i], ei = sez[2 * i + 1];
@@ -211,11 +221,18 @@ __device__ __forceinline__ void measure_part(const SysParams& P, const Walkers<T
       }
 #pragma unroll
       for (int m = 0; m < kSeg; ++m) {
-        if (m < cnt) {
-          const double* gv = E.gvec + 4 * (goff + m);
-          const double re = -sr[m], im = -si[m];   // electron charge -1
-          vee_k += gv[3] * (re * re + im * im);
-          vei_k += gv[3] * 2.0 * (re * E.s_ion[2 * (goff + m)] + im * E.s_ion[2 * (goff + m) + 1]);
+        sr[m] = quad_sum(sr[m]);
+        si[m] = quad_sum(si[m]);
+      }
+      if (c4 == 0) {
+#pragma unroll
+        for (int m = 0; m < kSeg; ++m) {
+          if (m < cnt) {
+            const double* gv = E.gvec + 4 * (goff + m);
+            const double re = -sr[m], im = -si[m];   // electron charge -1
+            vee_k += gv[3] * (re * re + im * im);
+            vei_k += gv[3] * 2.0 * (re * E.s_ion[2 * (goff + m)] + im * E.s_ion[2 * (goff + m) + 1]);
+          }
         }
       }
     }
