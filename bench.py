@@ -41,15 +41,12 @@ def describe(wl) -> str:
 def measured_traffic(wl):
     """HBM bytes per gather launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE runs,
     scaled by a plain copy's counter readings; None once the kernel source has changed."""
-    import hashlib
+    from paper_1802_06922_amd.profiling import source_hash
     path = os.path.join(ROOT, "profiles", f"gather_traffic_{wl.name}.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    m = hashlib.sha256()
-    for p in d["source_files"]:
-        m.update(open(os.path.join(ROOT, p), "rb").read())
-    if m.hexdigest()[:16] != d["source_sha256_16"]:
+    if source_hash(d["source_files"]) != d["source_sha256_16"]:
         return None
     return d["traffic_bytes_per_dispatch"]
 
@@ -82,9 +79,10 @@ def main(argv=None) -> int:
     ap.add_argument("--workload", default="solid128", help="solid128 | heg14 | mixed384")
     ap.add_argument("--delay", type=int, default=None,
                     help="delay rank K (1 = Sherman-Morrison; 4..64 = delayed updates)")
-    ap.add_argument("--mode", default="single", choices=["single", "batched", "served"],
+    ap.add_argument("--mode", default="single", choices=["single", "batched", "served", "copy"],
                     help="single: one system (default); batched: the four uneven systems in fused "
-                         "launches; served: a Poisson request stream with continuous batching")
+                         "launches; served: a Poisson request stream with continuous batching; copy: "
+                         "a plain 1 GiB device copy (x3), the reference for HBM counter readings")
     ap.add_argument("--requests", type=int, default=24, help="served: requests of the trace")
     ap.add_argument("--sweep-scale", type=float, default=0.1, help="served: scale of each request's sweeps")
     ap.add_argument("--no-graph", action="store_true", help="batched/served: no HIP graph replay")
@@ -110,6 +108,8 @@ def main(argv=None) -> int:
         return bench_batched(args)
     if args.mode == "served":
         return bench_served(args)
+    if args.mode == "copy":
+        return copy_reference()
     wl = qi.WORKLOADS[args.workload]()
     if args.delay is not None:
         wl.delay_rank = args.delay
@@ -173,6 +173,19 @@ def main(argv=None) -> int:
         print("[bench] CPU baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(line), flush=True)
+    return 0
+
+
+def copy_reference() -> int:
+    """A plain device copy of known size: each of the three copies reads and writes 1 GiB."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "copy", "bytes_per_copy": n * 4, "copies": 3}), flush=True)
     return 0
 
 
