@@ -158,8 +158,11 @@ qmc_status qmc_sweep(qmc_system s, int32_t n_sweeps, uint64_t* n_accepted_out);
  * "Hamiltonian": E_L = sum_n Psi^-1 H_n Psi).  out[W][4] = (kinetic,
  * electron-electron, electron-ion, ion-ion) in hartree; the Coulomb parts
  * are Ewald sums with a uniform neutralising background where the charge
- * does not cancel, each independent of the Ewald splitting.  out_on_device:
- * 0 = host buffer (synchronises), 1 = device buffer (asynchronous).
+ * does not cancel, each independent of the Ewald splitting.  MIXED: the
+ * kinetic part reads an inverse refined by one FP64 correction step
+ * X = B + B (I - A B) against the FP64 Slater matrix A (the FP32 inverse
+ * itself is left as the chain keeps it).  out_on_device: 0 = host buffer
+ * (synchronises), 1 = device buffer (asynchronous).
  * Errors: STATE; DEVICE; NUMERIC (host output only) if a value is not finite. */
 qmc_status qmc_measure_local_energy(qmc_system s, double* out, int32_t out_on_device);
 

@@ -103,6 +103,7 @@ struct qmc_system_s {
   uint32_t* nacc = nullptr;
   int* status = nullptr;
   double* val64 = nullptr;
+  void* xinv = nullptr;      // FP64-refined inverse read by the measurement (mixed precision)
   uint32_t* nguard = nullptr;
   uint32_t* sweep_ctr = nullptr;
   double* scratch = nullptr;
@@ -139,6 +140,7 @@ Walkers<T> walkers_of(qmc_system s) {
   w.pos = s->pos; w.prop = s->prop; w.vgl = static_cast<T*>(s->vgl); w.cur = s->cur;
   w.binv = static_cast<T*>(s->binv); w.logdet = s->logdet; w.sign = s->sign; w.acc = s->acc;
   w.nacc = s->nacc; w.status = s->status; w.val64 = s->val64; w.nguard = s->nguard; w.sweep_ctr = s->sweep_ctr;
+  w.xinv = static_cast<T*>(s->xinv);
   return w;
 }
 
@@ -268,17 +270,19 @@ void free_walkers(qmc_system s) {
   s->sign = s->status = nullptr;
   s->nacc = nullptr;
   s->val64 = nullptr;
+  s->xinv = nullptr;
   s->nguard = nullptr;
   s->sweep_ctr = nullptr;
 }
 
 struct WalkerSizes {
-  size_t pos, prop, vgl, cur, binv, logdet, sign, acc, nacc, status, scratch, drift, energy, val64, nguard, sweep;
+  size_t pos, prop, vgl, cur, binv, logdet, sign, acc, nacc, status, scratch, drift, energy, val64, nguard, sweep,
+      xinv;
   size_t total() const {
     return align_up(pos) + align_up(prop) + align_up(vgl) + align_up(cur) + align_up(binv) +
            align_up(logdet) + align_up(sign) + align_up(acc) + align_up(nacc) + align_up(status) +
            align_up(scratch) + align_up(drift) + align_up(energy) + align_up(val64) + align_up(nguard) +
-           align_up(sweep);
+           align_up(sweep) + align_up(xinv);
   }
 };
 
@@ -300,6 +304,7 @@ WalkerSizes walker_sizes(int n_up, int n_dn, int precision, int W, int n_orb) {
   z.drift = W * 2 * sizeof(double);
   z.energy = W * (4 + kMaxMeasureParts * 5) * sizeof(double);   // energies, then measurement partials
   z.val64 = precision == QMC_MIXED ? 2 * W * N * S * sizeof(double) : 0;
+  z.xinv = precision == QMC_MIXED ? W * bs * ts : 0;
   z.nguard = W * sizeof(uint32_t);
   z.sweep = sizeof(uint32_t);
   return z;
@@ -562,10 +567,13 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
   s->energy = static_cast<double*>(s->mem.alloc(z.energy));
   s->nguard = static_cast<uint32_t*>(s->mem.alloc(z.nguard));
   s->sweep_ctr = static_cast<uint32_t*>(s->mem.alloc(z.sweep));
-  if (s->d.precision == QMC_MIXED) s->val64 = static_cast<double*>(s->mem.alloc(z.val64));
+  if (s->d.precision == QMC_MIXED) {
+    s->val64 = static_cast<double*>(s->mem.alloc(z.val64));
+    s->xinv = s->mem.alloc(z.xinv);
+  }
   if (!s->pos || !s->prop || !s->vgl || !s->cur || !s->binv || !s->logdet || !s->sign || !s->acc ||
       !s->nacc || !s->status || !s->scratch || !s->drift || !s->energy || !s->nguard || !s->sweep_ctr ||
-      (s->d.precision == QMC_MIXED && !s->val64)) {
+      (s->d.precision == QMC_MIXED && (!s->val64 || !s->xinv))) {
     free_walkers(s);
     return fail(s, QMC_ERR_OOM, "device allocation of %zu walker bytes failed", z.total());
   }
@@ -654,7 +662,12 @@ qmc_status qmc_measure_local_energy(qmc_system s, double* out, int32_t out_on_de
   double* dst = out_on_device ? out : s->energy;
   hipError_t e;
   if (s->d.precision == QMC_MIXED)
-    e = timed(s, 2, [&] { return launch_measure<float>(s->P, walkers_of<float>(s), s->E, s->energy + 4 * (size_t)s->P.W, dst, s->stream); });
+    e = timed(s, 2, [&] {
+      const hipError_t er = launch_refine<float>(s->P, walkers_of<float>(s), s->scratch, s->stream);
+      return er != hipSuccess ? er
+                              : launch_measure<float>(s->P, walkers_of<float>(s), s->E, s->energy + 4 * (size_t)s->P.W,
+                                                      dst, s->stream);
+    });
   else
     e = timed(s, 2, [&] { return launch_measure<double>(s->P, walkers_of<double>(s), s->E, s->energy + 4 * (size_t)s->P.W, dst, s->stream); });
   if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "measure launch: %s", hipGetErrorString(e));
@@ -913,6 +926,7 @@ qmc_status batch_build(qmc_batch b) {
     d.eout = s->energy;
     d.mpart = s->energy + 4 * (size_t)s->P.W;
     d.np = measure_parts(s->P.W);
+    d.scratch = s->scratch;
     d.K = s->d.delay_rank;
     const int nmax = s->P.n_up > s->P.n_dn ? s->P.n_up : s->P.n_dn;
     d.ldl = nmax | 1;
@@ -969,6 +983,8 @@ hipError_t batch_launch(qmc_batch b, int sweep, int measure) {
     if (e == hipSuccess)
       e = launch_chain_delayed_batched<T>(sd, b->cgmap, b->n_cg, false, b->use_mfma, b->lds_cg, b->stream);
   }
+  if (e == hipSuccess && measure && b->precision == QMC_MIXED)
+    e = launch_refine_batched<float>(reinterpret_cast<const SysDev<float>*>(sd), b->fmap, b->n_f, b->stream);
   if (e == hipSuccess && measure) e = launch_measure_batched<T>(sd, b->mmap, b->n_m, b->fmap, b->n_f, b->lds_m, b->stream);
   return e;
 }

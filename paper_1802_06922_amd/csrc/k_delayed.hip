@@ -38,25 +38,6 @@ namespace qmc {
 constexpr int kMaxWindow = 64;
 constexpr int kLdsIonsD = 256;
 
-// 16x16x4 matrix-core products.  Operands: lane l holds A[l % 16][l / 16] and
-// B[l / 16][l % 16]; result register r of lane l holds D[row(l, r)][l % 16],
-// where the row mapping differs between the FP32 and FP64 instructions.
-template <typename T> struct Mfma;
-template <> struct Mfma<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
-};
-template <> struct Mfma<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
-};
-
 struct DLayout {
   size_t pos, prop, ions, red, gold, gdiff, cur, acc, plist, qlist, vec, cinv, vwin, ywin, zwin, gx, gr, grow, b,
       total;

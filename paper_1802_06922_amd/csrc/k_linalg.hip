@@ -128,6 +128,141 @@ __global__ __launch_bounds__(kBlock) void k_rebuild(SysParams P, Walkers<T> Wk, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP64 refinement of the FP32 inverses before a measurement (mixed precision).
+//
+// Between full rebuilds the FP32 rank-one and delayed updates let B drift from
+// A^-1 by a few FP32 units times the conditioning of A; the kinetic energy sums
+// B[l][k] times orbital Laplacians with heavy cancellation, so that drift can
+// reach 1e-4 of the energy.  One correction step X = B + B (I - A B), with the
+// FP64 Slater matrix A and all products in FP64, squares the relative error of
+// the inverse.  Both products run on the FP64 matrix cores in 64 x 64 output
+// tiles staged through LDS; the residual I - A B goes to an FP64 scratch
+// matrix, X to the buffer the measurement reads (binv itself is not changed,
+// so a measurement never alters the chain).
+// ---------------------------------------------------------------------------
+constexpr int kTile = 64, kChunk = 16;
+constexpr int kLs = kChunk + 1;    // padded LDS row strides (fewer bank conflicts)
+constexpr int kRs = kTile + 2;
+
+// C[i][k] = sum_l Lf(i, l) Rf(l, k) for i, k < n; epi(i, k, C[i][k]) stores each
+// result.  All threads of the block call it; each wave owns a 32 x 32 quadrant.
+template <typename LF, typename RF, typename EF>
+__device__ __forceinline__ void gemm64(int n, LF Lf, RF Rf, EF epi, double* sL, double* sR) {
+  typedef Mfma<double> M;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int nt = (n + kTile - 1) / kTile;
+  for (int t = 0; t < nt * nt; ++t) {
+    const int i0 = (t / nt) * kTile, k0 = (t % nt) * kTile;
+    M::v4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = M::v4{0.0, 0.0, 0.0, 0.0};
+    for (int l0 = 0; l0 < n; l0 += kChunk) {
+      for (int q = tid; q < kTile * kChunk; q += kBlock) {
+        const int r = q / kChunk, c = q % kChunk;          // left panel: row r, column c
+        const int i = i0 + r, l = l0 + c;
+        sL[r * kLs + c] = (i < n && l < n) ? Lf(i, l) : 0.0;
+        const int rr = q / kTile, cc = q % kTile;          // right panel: row rr, column cc
+        const int l2 = l0 + rr, k = k0 + cc;
+        sR[rr * kRs + cc] = (l2 < n && k < n) ? Rf(l2, k) : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < kChunk; kk += 4) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const double av = sL[(wr + 16 * a + li) * kLs + kk + lk];
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            const double bv = sR[(kk + lk) * kRs + wc + 16 * b + li];
+            acc[a][b] = M::mma(av, bv, acc[a][b]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + wr + 16 * a + M::row(lane, r), k = k0 + wc + 16 * b + li;
+          if (i < n && k < n) epi(i, k, acc[a][b][r]);
+        }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void refine_spin(const SysParams& P, const Walkers<T>& Wk, double* scratch, int w,
+                                            int sp) {
+  __shared__ double sL[kTile * kLs];
+  __shared__ double sR[kChunk * kRs];
+  __shared__ const double* arow[kMaxSpin];
+  const int n = sp ? P.n_dn : P.n_up, off = sp ? P.n_up : 0;
+  if (n == 0) return;
+  const int N = P.N;
+  const size_t boff = (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0);
+  const T* B = Wk.binv + boff;
+  T* X = Wk.xinv + boff;
+  double* E = scratch + boff;
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    const size_t item = (size_t)w * N + off + i;
+    arow[i] = Wk.val64 + ((size_t)Wk.cur[item] * P.W * N + item) * P.S;
+  }
+  __syncthreads();
+  // E = I - A B
+  gemm64(n, [&](int i, int l) { return arow[i][l]; },
+         [&](int l, int k) { return (double)B[(size_t)l * n + k]; },
+         [&](int i, int k, double c) { E[(size_t)i * n + k] = (i == k ? 1.0 : 0.0) - c; }, sL, sR);
+  __syncthreads();   // E (global) complete before it is read
+  // X = B + B E
+  gemm64(n, [&](int i, int l) { return (double)B[(size_t)i * n + l]; },
+         [&](int l, int k) { return E[(size_t)l * n + k]; },
+         [&](int i, int k, double c) { X[(size_t)i * n + k] = (T)((double)B[(size_t)i * n + k] + c); }, sL, sR);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_refine(SysParams P, Walkers<T> Wk, double* scratch) {
+  refine_spin<T>(P, Wk, scratch, blockIdx.x >> 1, blockIdx.x & 1);
+}
+
+// Batched: block b refines spin b & 1 of (system, walker) fmap[b >> 1].
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_refine_batched(const SysDev<T>* __restrict__ sd,
+                                                           const int2* __restrict__ fmap) {
+  __shared__ SysDev<T> s;
+  const int2 m = fmap[blockIdx.x >> 1];
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(sd + m.x);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&s);
+    for (int q = threadIdx.x; q < (int)(sizeof(SysDev<T>) / 4); q += kBlock) dst[q] = src[q];
+  }
+  __syncthreads();
+  refine_spin<T>(s.P, s.W, s.scratch, m.y, blockIdx.x & 1);
+}
+
+template <typename T>
+hipError_t launch_refine(const SysParams& P, const Walkers<T>& Wk, double* scratch, hipStream_t st) {
+  if (P.n_up > kMaxSpin || P.n_dn > kMaxSpin || !Wk.val64 || !Wk.xinv) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_refine<T>, dim3(2 * P.W), dim3(kBlock), 0, st, P, Wk, scratch);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_refine_batched(const SysDev<T>* sd, const int2* fmap, int n_walkers, hipStream_t st) {
+  if (n_walkers <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_refine_batched<T>, dim3(2 * n_walkers), dim3(kBlock), 0, st, sd, fmap);
+  return hipGetLastError();
+}
+
+template hipError_t launch_refine<float>(const SysParams&, const Walkers<float>&, double*, hipStream_t);
+template hipError_t launch_refine_batched<float>(const SysDev<float>*, const int2*, int, hipStream_t);
+
 template <typename T>
 hipError_t launch_rebuild(const SysParams& P, const Walkers<T>& Wk, double* scratch, double* drift,
                           hipStream_t st) {

@@ -122,7 +122,7 @@ __device__ __forceinline__ void measure_part(const SysParams& P, const Walkers<T
     const int n = sp ? P.n_dn : P.n_up, k = i - (sp ? P.n_up : 0);
     const size_t item = (size_t)w * N + i;
     const T* row = Wk.vgl + ((size_t)Wk.cur[item] * P.W * N + item) * kComp * P.S;
-    const T* B = Wk.binv + (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0);
+    const T* B = (Wk.xinv ? Wk.xinv : Wk.binv) + (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0);
     double gx = 0.0, gy = 0.0, gz = 0.0, l2 = 0.0;
     for (int l = lane; l < n; l += 64) {
       const double b = (double)B[(size_t)l * n + k];

@@ -63,6 +63,7 @@ struct Walkers {
   double* val64;      // [2][W][N][S]: FP64 orbital values (mixed precision only, else null)
   uint32_t* nguard;   // [W]: moves re-decided in FP64 (cumulative; mixed precision)
   uint32_t* sweep_ctr;  // index of the next sweep (device side, so captured sweeps replay correctly)
+  T* xinv;            // [W][bstride]: FP64-refined copy of binv the measurement reads (mixed only, else null)
 };
 
 // ---------------------------------------------------------------------------
@@ -213,6 +214,25 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+
+// 16x16x4 matrix-core products.  Operands: lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16]; result register r of lane l holds D[row(l, r)][l % 16],
+// where the row mapping differs between the FP32 and FP64 instructions.
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+template <> struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
 
 // Workgroup barrier that orders LDS only: outstanding global loads (e.g. a
 // prefetch) stay in flight across it.  Use __syncthreads() where global

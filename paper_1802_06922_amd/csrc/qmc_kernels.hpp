@@ -35,6 +35,7 @@ struct SysDev {
   int ldl;           // LDS row stride of the inverse
   int tpi_log2;      // gather lanes per proposal (log2)
   int np;            // workgroups per walker in the measurement
+  double* scratch;   // [W][bstride] FP64 scratch (rebuild, refinement)
 };
 
 // Orbital gather: for every (walker, electron), either draw the proposal of
@@ -81,6 +82,14 @@ hipError_t launch_init_positions(const SysParams& P, double* pos, hipStream_t st
 template <typename T>
 hipError_t launch_rebuild(const SysParams& P, const Walkers<T>& Wk, double* scratch, double* drift,
                           hipStream_t st);
+
+// Mixed precision: Wk.xinv = B + B (I - A B) with the FP64 Slater matrix A (from val64) and
+// FP64 products, the inverse the measurement reads; scratch: W * bstride doubles.
+template <typename T>
+hipError_t launch_refine(const SysParams& P, const Walkers<T>& Wk, double* scratch, hipStream_t st);
+// Batched refinement of every (system, walker) of fmap, both spins.
+template <typename T>
+hipError_t launch_refine_batched(const SysDev<T>* sd, const int2* fmap, int n_walkers, hipStream_t st);
 
 // Local energy of every walker: out[W][4]; partial: W * kMaxMeasureParts * 5 doubles of scratch.
 constexpr int kMaxMeasureParts = 8;
