@@ -279,7 +279,8 @@ def _compare_mixed(gpu, orc, wl, n_sweeps, walkers, tie_guard=0.0):
     ref = orc.OracleSystem(wl).run(sample, n_sweeps, measure_every=1)
     assert np.array_equal(b, ref["accept"]), f"decisions differ at {np.argwhere(b != ref['accept'])[:3]}"
     rel = _rel(e, ref["energies"])
-    print(f"[mixed] max rel energy error {rel.max():.2e}, median {np.median(rel):.2e}, "
+    print(f"[mixed] rel energy error max {rel.max():.2e}, p99 {np.percentile(rel, 99):.2e}, "
+          f"median {np.median(rel):.2e}, "
           f"re-decided {redecided} of {b.size * (wl.n_walkers // len(sample))} moves", flush=True)
     assert rel.max() < MIXED_TOL
     return redecided
