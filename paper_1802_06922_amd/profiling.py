@@ -8,8 +8,8 @@
             <copy_fetch.csv> <copy_write.csv> <copy_bytes> <command>...
         JSON record of a kernel's HBM traffic per dispatch: FETCH_SIZE and WRITE_SIZE (KiB) of
         the kernel, each scaled by the reading of the same counter for a plain device copy of
-        copy_bytes bytes (``bench.py --mode copy``), with a hash of the kernel's sources so the
-        record is ignored once they change.
+        copy_bytes bytes per copy dispatch (``bench.py --mode copy``: 1 GiB each), with a hash of
+        the kernel's sources so the record is ignored once they change.
 """
 from __future__ import annotations
 
