@@ -88,6 +88,7 @@ struct qmc_system_s {
   double* d_gvec = nullptr;
   double* d_sion = nullptr;
   int* d_segs = nullptr;
+  double* d_htab = nullptr;
   void* d_table = nullptr;
   bool has_table = false, has_walkers = false;
   uint32_t sweep_index = 0;
@@ -183,6 +184,37 @@ void build_radial(Radial& R, int kind, const double* p, int M, double rc, double
 // with the real-space cutoff at one cell side L (erfc(5.5) ~ 7e-15), and every
 // reciprocal vector of one half space with G^2 / (4 kappa^2) <= 30, grouped in
 // segments of at most kEwaldSeg consecutive Gz of one (Gx, Gy) column.
+// H(x) = erf(sqrt x) / sqrt x (its series near 0), for the real-space table.
+double erf_over_sqrt(double x) {
+  if (x < 1e-10) return 2.0 / std::sqrt(kPi) * (1.0 - x / 3.0);
+  const double r = std::sqrt(x);
+  return std::erf(r) / r;
+}
+
+// Coefficients of H on each interval: Chebyshev interpolation at kHDeg + 1 Chebyshev
+// points of the interval, rewritten in powers of the interval's scaled variable u.
+void h_table(std::vector<double>& tab) {
+  constexpr int D = kHDeg, M = kHDeg + 1;
+  double T[M][M] = {};   // T[j][m]: coefficient of u^m in the Chebyshev polynomial T_j
+  T[0][0] = 1.0;
+  if (D >= 1) T[1][1] = 1.0;
+  for (int j = 2; j <= D; ++j)
+    for (int m = 0; m <= D; ++m) T[j][m] = (m > 0 ? 2.0 * T[j - 1][m - 1] : 0.0) - T[j - 2][m];
+  tab.assign(kHTab, 0.0);
+  for (int i = 0; i < kHInt; ++i) {
+    const double xc = (i + 0.5) * kHW;
+    double f[M], a[M];
+    for (int k = 0; k < M; ++k) f[k] = erf_over_sqrt(xc + 0.5 * kHW * std::cos(kPi * (k + 0.5) / M));
+    for (int j = 0; j < M; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < M; ++k) acc += f[k] * std::cos(j * kPi * (k + 0.5) / M);
+      a[j] = (j == 0 ? 1.0 : 2.0) * acc / M;
+    }
+    for (int j = 0; j < M; ++j)
+      for (int m = 0; m <= D; ++m) tab[(size_t)i * M + m] += a[j] * T[j][m];
+  }
+}
+
 void ewald_setup(qmc_system s, std::vector<double>& gvec, std::vector<double>& sion,
                  std::vector<int>& segs) {
   const double L = s->d.L, V = L * L * L;
@@ -317,7 +349,7 @@ size_t system_bytes(const qmc_system_desc* d) {
   const size_t nseg = (size_t)(mmax + 1) * (2 * mmax + 1) * 3;
   return align_up((size_t)(d->n_ions > 0 ? d->n_ions : 1) * 4 * sizeof(double)) +
          align_up(ng * 4 * sizeof(double)) + align_up(ng * 2 * sizeof(double)) +
-         align_up(nseg * 5 * sizeof(int));
+         align_up(nseg * 5 * sizeof(int)) + align_up(kHTab * sizeof(double));
 }
 
 bool valid_rank(int K) { return K == 0 || K == 1 || (K >= 4 && K <= 64 && !(K & (K - 1))); }
@@ -438,16 +470,22 @@ qmc_status qmc_create_system(const qmc_system_desc* desc, void* hip_stream, qmc_
   P.ions = s->d_ions;
   s->E.enabled = desc->hamiltonian == QMC_H_COULOMB_EWALD;
   if (s->E.enabled) {
-    std::vector<double> gvec, sion;
+    std::vector<double> gvec, sion, htab;
     std::vector<int> segs;
     ewald_setup(s, gvec, sion, segs);
+    h_table(htab);
     s->d_gvec = static_cast<double*>(s->mem.alloc(gvec.size() * sizeof(double)));
     s->d_sion = static_cast<double*>(s->mem.alloc(sion.size() * sizeof(double)));
     s->d_segs = static_cast<int*>(s->mem.alloc(segs.size() * sizeof(int)));
-    if (!s->d_gvec || !s->d_sion || !s->d_segs) { qmc_destroy_system(s); return fail(nullptr, QMC_ERR_OOM, "device allocation (Ewald)"); }
+    s->d_htab = static_cast<double*>(s->mem.alloc(htab.size() * sizeof(double)));
+    if (!s->d_gvec || !s->d_sion || !s->d_segs || !s->d_htab) {
+      qmc_destroy_system(s);
+      return fail(nullptr, QMC_ERR_OOM, "device allocation (Ewald)");
+    }
     if (hipMemcpyAsync(s->d_gvec, gvec.data(), gvec.size() * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
         hipMemcpyAsync(s->d_sion, sion.data(), sion.size() * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-        hipMemcpyAsync(s->d_segs, segs.data(), segs.size() * sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess) {
+        hipMemcpyAsync(s->d_segs, segs.data(), segs.size() * sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync(s->d_htab, htab.data(), htab.size() * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess) {
       qmc_destroy_system(s);
       return fail(nullptr, QMC_ERR_DEVICE, "Ewald upload failed");
     }
@@ -458,6 +496,7 @@ qmc_status qmc_create_system(const qmc_system_desc* desc, void* hip_stream, qmc_
     s->E.gvec = s->d_gvec;
     s->E.s_ion = s->d_sion;
     s->E.segs = s->d_segs;
+    s->E.htab = s->d_htab;
   } else if (hipStreamSynchronize(s->stream) != hipSuccess) {
     qmc_destroy_system(s);
     return fail(nullptr, QMC_ERR_DEVICE, "stream synchronise failed");

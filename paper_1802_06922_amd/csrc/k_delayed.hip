@@ -39,7 +39,7 @@ constexpr int kMaxWindow = 64;
 constexpr int kLdsIonsD = 256;
 
 struct DLayout {
-  size_t pos, prop, ions, red, gold, gdiff, cur, acc, plist, qlist, vec, cinv, vwin, ywin, zwin, gx, gr, grow, b,
+  size_t pos, prop, ions, red, gold, gdiff, cur, acc, plist, qlist, vwin, ywin, zwin, gx, gr, grow, b,
       total;
 };
 
@@ -62,10 +62,6 @@ __host__ __device__ inline DLayout dlayout(int N, int nmax, int n_ions, int ldl,
   al(16);
   L.plist = o; o += sizeof(int) * K;
   L.qlist = o; o += sizeof(int) * K;
-  al(16);
-  L.vec = o; o += ts * 4 * kMaxWindow;
-  al(16);
-  L.cinv = o; o += ts * K * K;
   al(16);
   // Window rows V (dead after Y = V B0) share storage with the flush's Z, and the
   // flush's U = B0[:, P] reuses Y's storage once Z has been formed.
@@ -117,27 +113,54 @@ __device__ __forceinline__ double dist(double ax, double ay, double az, double b
   return sqrt(dx * dx + dy * dy + dz * dz);
 }
 
+// Matrix-core tiles of a wave are processed in groups of kGroup: their operand
+// loads are issued together, so that when B lives in global memory a wave has
+// several loads in flight instead of one round trip per 16 x 16 x 4 step.
+// Four tiles for FP32; two for FP64, whose operands take twice the registers.
+template <typename T> struct Group { static constexpr int n = sizeof(T) == 4 ? 4 : 2; };
+
 // Y[q][c] = sum_l V[q][l] B[l][c] for q < Kw, c < n (all threads of the block).
 template <typename T, bool MF>
 __device__ __forceinline__ void gemm_window(const T* V, const T* B, int ldb, T* Y, int Kw, int n, int nP,
                                             int tid) {
   if (MF) {
+    typedef Mfma<T> M;
+    constexpr int kGroup = Group<T>::n;
     const int lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
-    const int tq = (Kw + 15) >> 4, tc = (n + 15) >> 4;
-    for (int t = wave; t < tq * tc; t += kWaves) {
-      const int q0 = (t / tc) * 16, c0 = (t % tc) * 16;
-      typename Mfma<T>::v4 acc = {T(0), T(0), T(0), T(0)};
-      const int qa = q0 + li, cb = c0 + li;
+    const int tq = (Kw + 15) >> 4, tc = (n + 15) >> 4, nt = tq * tc;
+    // wave w takes tiles w, w + kWaves, ... in groups of kGroup
+    for (int g0 = wave; g0 < nt; g0 += kWaves * kGroup) {
+      typename M::v4 acc[kGroup];
+      int qa[kGroup], cb[kGroup];
+#pragma unroll
+      for (int j = 0; j < kGroup; ++j) {
+        const int t = g0 + j * kWaves;
+        acc[j] = typename M::v4{T(0), T(0), T(0), T(0)};
+        qa[j] = t < nt ? (t / tc) * 16 + li : Kw;    // rows beyond Kw and columns beyond n read zero
+        cb[j] = t < nt ? (t % tc) * 16 + li : n;
+      }
+#pragma unroll 2
       for (int l0 = 0; l0 < n; l0 += 4) {
         const int l = l0 + lk;
-        const T a = (qa < Kw && l < n) ? V[(size_t)qa * nP + l] : T(0);
-        const T b = (l < n && cb < n) ? B[(size_t)l * ldb + cb] : T(0);
-        acc = Mfma<T>::mma(a, b, acc);
+        T a[kGroup], b[kGroup];
+#pragma unroll
+        for (int j = 0; j < kGroup; ++j) {
+          a[j] = (qa[j] < Kw && l < n) ? V[(size_t)qa[j] * nP + l] : T(0);
+          b[j] = (l < n && cb[j] < n) ? B[(size_t)l * ldb + cb[j]] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < kGroup; ++j) acc[j] = M::mma(a[j], b[j], acc[j]);
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int q = q0 + Mfma<T>::row(lane, r);
-        if (q < Kw && cb < n) Y[(size_t)q * nP + cb] = acc[r];
+      for (int j = 0; j < kGroup; ++j) {
+        const int t = g0 + j * kWaves;
+        if (t >= nt) continue;
+        const int q0 = (t / tc) * 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int q = q0 + M::row(lane, r);
+          if (q < Kw && cb[j] < n) Y[(size_t)q * nP + cb[j]] = acc[j][r];
+        }
       }
     }
   } else {
@@ -155,23 +178,45 @@ template <typename T, bool MF>
 __device__ __forceinline__ void gemm_flush(T* B, int ldb, const T* U, int ldu, const T* Z, int nP, int n,
                                            int mP, int tid) {
   if (MF) {
+    typedef Mfma<T> M;
+    constexpr int kGroup = Group<T>::n;
     const int lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
-    const int tt = (n + 15) >> 4;
-    for (int t = wave; t < tt * tt; t += kWaves) {
-      const int l0 = (t / tt) * 16, c0 = (t % tt) * 16;
-      typename Mfma<T>::v4 acc = {T(0), T(0), T(0), T(0)};
-      const int la = l0 + li, cb = c0 + li;
+    const int tt = (n + 15) >> 4, nt = tt * tt;
+    for (int g0 = wave; g0 < nt; g0 += kWaves * kGroup) {
+      // the old values of the group's tiles are loaded first; they arrive while the products run
+      T old[kGroup][4];
+      int lrow[kGroup], cb[kGroup];
+#pragma unroll
+      for (int j = 0; j < kGroup; ++j) {
+        const int t = g0 + j * kWaves;
+        lrow[j] = t < nt ? (t / tt) * 16 : n;
+        cb[j] = t < nt ? (t % tt) * 16 + li : n;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int l = lrow[j] + M::row(lane, r);
+          old[j][r] = (l < n && cb[j] < n) ? B[(size_t)l * ldb + cb[j]] : T(0);
+        }
+      }
+      typename M::v4 acc[kGroup];
+#pragma unroll
+      for (int j = 0; j < kGroup; ++j) acc[j] = typename M::v4{T(0), T(0), T(0), T(0)};
       for (int r0 = 0; r0 < mP; r0 += 4) {
         const int r = r0 + lk;
-        const T a = (la < n) ? U[(size_t)la * ldu + r] : T(0);
-        const T b = (cb < n) ? Z[(size_t)r * nP + cb] : T(0);
-        acc = Mfma<T>::mma(a, b, acc);
+#pragma unroll
+        for (int j = 0; j < kGroup; ++j) {
+          const int la = lrow[j] + li;
+          const T a = (la < n) ? U[(size_t)la * ldu + r] : T(0);
+          const T b = (cb[j] < n) ? Z[(size_t)r * nP + cb[j]] : T(0);
+          acc[j] = M::mma(a, b, acc[j]);
+        }
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int l = l0 + Mfma<T>::row(lane, q);
-        if (l < n && cb < n) B[(size_t)l * ldb + cb] -= acc[q];
-      }
+      for (int j = 0; j < kGroup; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int l = lrow[j] + M::row(lane, r);
+          if (l < n && cb[j] < n) B[(size_t)l * ldb + cb[j]] = old[j][r] - acc[j][r];
+        }
     }
   } else {
     for (int idx = tid; idx < n * n; idx += kBlock) {
@@ -205,11 +250,7 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
   uint8_t* sacc = smem + lay.acc;
   int* plist = reinterpret_cast<int*>(smem + lay.plist);
   int* qlist = reinterpret_cast<int*>(smem + lay.qlist);
-  T* sa = reinterpret_cast<T*>(smem + lay.vec);
-  T* sb = sa + kMaxWindow;
-  T* sx = sb + kMaxWindow;
-  T* sy = sx + kMaxWindow;
-  T* cinv = reinterpret_cast<T*>(smem + lay.cinv);
+  T* yk = reinterpret_cast<T*>(smem + lay.gold);   // (B): the window block, in the storage of gold
   T* vwin = reinterpret_cast<T*>(smem + lay.vwin);
   T* ywin = reinterpret_cast<T*>(smem + lay.ywin);
   T* ubuf = ywin;
@@ -314,53 +355,54 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
       gemm_window<T, MF>(vwin, Bm, ldb, ywin, Kw, n, nP, tid);
       __syncthreads();
 
-      // (B) the moves of the window, in order, by one wave
+      // (B) the moves of the window, in order, by one wave.  Lane q keeps move q's Jastrow
+      // change (partners at their positions before the window, in-window partners too) and
+      // row q of the window block yk = Y[:, k0 .. k0 + Kw).  An accepted move q eliminates
+      // its column from the later rows (the Sherman-Morrison update restricted to the
+      // window's own columns), so each ratio is read, not recomputed: R_q = yk[q][q].
       if (wave == 0) {
         if (lane == 0) sm_stop = -1;
         double Fq = 0.0;
-        if (lane < Kw)
+        if (lane < Kw) {
           for (int s = 0; s < tpq; ++s) Fq += red[lane * tpq + s];
+          for (int j = 0; j < Kw; ++j)
+            if (j != lane) Fq += gold[lane * K + j];
+        }
+        wave_sync_lds();   // gold is consumed: its storage takes yk
+        if (lane < Kw)
+          for (int j = 0; j < Kw; ++j) yk[lane * K + j] = ywin[(size_t)lane * nP + k0 + j];
+        wave_sync_lds();
         int m = 0;
         for (int q = 0; q < Kw; ++q) {
           const int kq = k0 + q, iq = off + kq;
-          T al = T(0), xr = T(0);
-          if (lane < m) {
-            al = ywin[(size_t)q * nP + plist[lane]];
-            sb[lane] = ywin[(size_t)qlist[lane] * nP + kq];
-            sa[lane] = al;
-          }
-          wave_sync_lds();
-          if (lane < m)
-            for (int l = 0; l < m; ++l) xr += cinv[lane * K + l] * sb[l];
-          const double corr = wave_sum_dpp((double)(al * xr));
-          const T R = ywin[(size_t)q * nP + kq] - (T)corr;
-          double jt = 0.0;
-          if (lane < Kw && lane != q) {
-            jt = gold[q * K + lane];
-            if (lane < q && sacc[k0 + lane]) jt += gdiff[q * K + lane];
-          }
-          const double dJ = readlane_d(Fq, q) + wave_sum_dpp(jt);
+          const T R = yk[q * K + q];
+          const double dJ = readlane_d(Fq, q);
           const double u = sprop[4 * kq + 3];
-          const double p32 = (double)R * (double)R * exp(2.0 * dJ);
+          // mixed precision: an FP32 exponential is well inside the guard band
+          const double ex = sizeof(T) == 4 ? (double)__expf((float)(2.0 * dJ)) : exp(2.0 * dJ);
+          const double p32 = (double)R * (double)R * ex;
           if (sizeof(T) == 4 && fabs(u - p32) <= P.tie_guard * p32) {
             // near tie in FP32: end the window here; the move is re-decided in FP64 below
             if (lane == 0) { sm_stop = q; sm_dj = dJ; }
             break;
           }
-          const bool accept = u < p32;
-          if (accept) {
-            T yc = T(0);
-            if (lane < m)
-              for (int l = 0; l < m; ++l) yc += sa[l] * cinv[l * K + lane];
-            if (lane < m) { sx[lane] = xr; sy[lane] = yc; }
-            wave_sync_lds();
-            const T invR = T(1) / R;
-            if (lane < m) {
-              for (int c = 0; c < m; ++c) cinv[lane * K + c] += xr * sy[c] * invR;
-              cinv[lane * K + m] = -xr * invR;
-            } else if (lane == m) {
-              for (int c = 0; c < m; ++c) cinv[m * K + c] = -sy[c] * invR;
-              cinv[m * K + m] = invR;
+          if (u < p32) {
+            if (lane > q && lane < Kw) {
+              const T f = yk[lane * K + q] / R;
+              // eight columns at a time: all loads before the stores, so they overlap
+              for (int j0 = q + 1; j0 < Kw; j0 += 8) {
+                T pv[8], rv[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                  const int j = j0 + e;
+                  pv[e] = j < Kw ? yk[q * K + j] : T(0);
+                  rv[e] = j < Kw ? yk[lane * K + j] : T(0);
+                }
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                  if (j0 + e < Kw) yk[lane * K + j0 + e] = rv[e] - f * pv[e];
+              }
+              Fq += gdiff[lane * K + q];
             }
             if (lane == 0) {
               plist[m] = kq;
@@ -384,10 +426,32 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
       }
       __syncthreads();
 
-      // (C) flush: B = B0 - B0[:, P] C^-1 (Y[Q, :] - E_P^T)
+      // (C) flush: B = B0 - B0[:, P] C^-1 (Y[Q, :] - E_P^T), C = Y[Q, P].  C^-1 by
+      // Gauss-Jordan elimination without pivoting over the whole workgroup (its pivots are
+      // the accepted ratios, all nonzero), each step from one buffer into the other; the
+      // storage of gold and gdiff is free after (B).
       const int m = sm_m;
       if (m > 0) {
         const int mP = (m + 3) & ~3;
+        T* ga = reinterpret_cast<T*>(smem + lay.gold);
+        T* gb = reinterpret_cast<T*>(smem + lay.gdiff);
+        for (int idx = tid; idx < m * m; idx += kBlock) {
+          const int a = idx / m, b = idx - a * m;
+          ga[a * K + b] = ywin[(size_t)qlist[a] * nP + plist[b]];
+        }
+        __syncthreads();
+        for (int pv = 0; pv < m; ++pv) {
+          const T inv = T(1) / ga[pv * K + pv];
+          for (int idx = tid; idx < m * m; idx += kBlock) {
+            const int i = idx / m, j = idx - i * m;
+            const T aip = ga[i * K + pv], apj = ga[pv * K + j];
+            gb[i * K + j] = i == pv ? (j == pv ? inv : apj * inv)
+                                    : (j == pv ? -aip * inv : ga[i * K + j] - aip * apj * inv);
+          }
+          __syncthreads();
+          T* t = ga; ga = gb; gb = t;
+        }
+        const T* cinv = ga;
         for (int idx = tid; idx < mP * n; idx += kBlock) {
           const int r = idx / n, c = idx - r * n;
           T acc = T(0);

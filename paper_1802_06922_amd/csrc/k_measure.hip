@@ -25,10 +25,23 @@ __device__ __forceinline__ const Radial& pick(const Jastrow& J, int kind) {
   return kind == 0 ? J.same : (kind == 1 ? J.opp : J.ei);
 }
 
+// erfc(kappa r) / r = 1 / r - kappa H(kappa^2 r^2) for r^2 < rcut^2, H from its table.
+__device__ __forceinline__ double screened(double r2, double kappa, const double* __restrict__ htab) {
+  const double ri = rsqrt(r2);
+  const double x = kappa * kappa * r2;
+  const int i = (int)(x * (1.0 / kHW));
+  const double u = (x - (i + 0.5) * kHW) * (2.0 / kHW);
+  const double* c = htab + i * (kHDeg + 1);
+  double h = c[kHDeg];
+#pragma unroll
+  for (int m = kHDeg - 1; m >= 0; --m) h = h * u + c[m];
+  return ri - kappa * h;
+}
+
 // sum of erfc(kappa r) / r over the images of d (minimum-imaged) with r < rcut <= L:
 // per axis only the shift toward the nearer neighbouring cell can qualify.
 __device__ __forceinline__ double screened_images(double dx, double dy, double dz, double L,
-                                                  double kappa, double rcut2) {
+                                                  double kappa, double rcut2, const double* htab) {
   const double sx = dx > 0.0 ? -L : L, sy = dy > 0.0 ? -L : L, sz = dz > 0.0 ? -L : L;
   double s = 0.0;
 #pragma unroll
@@ -37,16 +50,19 @@ __device__ __forceinline__ double screened_images(double dx, double dy, double d
     const double y = dy + ((m & 2) ? sy : 0.0);
     const double z = dz + ((m & 4) ? sz : 0.0);
     const double r2 = x * x + y * y + z * z;
-    if (r2 < rcut2) {
-      const double r = sqrt(r2);
-      s += erfc(kappa * r) / r;
-    }
+    if (r2 < rcut2) s += screened(r2, kappa, htab);
   }
   return s;
 }
 
+struct MeasureLayout {
+  size_t pos, ez, gd, ld, gjp, ljp, htab, total;
+  int nloc;    // electrons per part (upper bound)
+  int parts;   // Jastrow partner split per electron
+};
+
 // Every walker's local energy is computed by np workgroups (parts): part p
-// takes the kinetic terms of electrons i = p (mod np) and every np-th pair,
+// takes the kinetic terms of electrons p nloc .. (p + 1) nloc - 1 and every np-th pair,
 // ion pair and reciprocal segment; it writes five partial sums, and a second
 // kernel adds the parts of a walker in a fixed order.  Spreading a walker
 // over several workgroups keeps enough waves in flight to hide the latency of
@@ -59,17 +75,14 @@ __device__ __forceinline__ double quad_sum(double v) {
 
 constexpr int kPartSums = 5;   // kinetic, e-e real space, e-I real space, e-e reciprocal, e-I reciprocal
 
-struct MeasureLayout {
-  size_t pos, ez, gd, ld, gjp, ljp, total;
-  int nloc;    // electrons per part (upper bound)
-  int parts;   // Jastrow partner split per electron
-};
 
 __host__ __device__ inline MeasureLayout measure_layout(int N, int np) {
   MeasureLayout L;
   L.nloc = (N + np - 1) / np;
+  // partners split so that the (electron, part) items fill the workgroup about four times
+  // over, with at most 1024 items (their partial sums are kept in LDS)
   int parts = 1;
-  while (parts * 2 * L.nloc <= kBlock) parts *= 2;
+  while (parts * L.nloc < 4 * kBlock && parts * 2 * L.nloc <= 1024 && parts * 2 <= N) parts *= 2;
   L.parts = parts;
   size_t o = 0;
   L.pos = o; o += sizeof(double) * 3 * N;
@@ -78,6 +91,7 @@ __host__ __device__ inline MeasureLayout measure_layout(int N, int np) {
   L.ld = o; o += sizeof(double) * L.nloc;
   L.gjp = o; o += sizeof(double) * 3 * (size_t)L.nloc * parts;
   L.ljp = o; o += sizeof(double) * (size_t)L.nloc * parts;
+  L.htab = o; o += sizeof(double) * kHTab;
   L.total = o;
   return L;
 }
@@ -103,9 +117,12 @@ __device__ __forceinline__ void measure_part(const SysParams& P, const Walkers<T
     uint32_t* dst = reinterpret_cast<uint32_t*>(&sj);
     for (int q = tid; q < (int)(sizeof(Jastrow) / 4); q += kBlock) dst[q] = src[q];
   }
+  double* shtab = reinterpret_cast<double*>(smem + lay.htab);
   for (int j = tid; j < 3 * N; j += kBlock) spos[j] = Wk.pos[(size_t)w * 3 * N + j];
+  if (E.enabled)
+    for (int j = tid; j < kHTab; j += kBlock) shtab[j] = E.htab[j];
   __syncthreads();
-  const double g0 = 2.0 * kPi / P.L;
+  const double g0 = 2.0 * kPi / P.L, invL = 1.0 / P.L;
   if (E.enabled)
     for (int i = tid; i < N; i += kBlock) {
       double s, c;
@@ -114,55 +131,56 @@ __device__ __forceinline__ void measure_part(const SysParams& P, const Walkers<T
       sez[2 * i + 1] = s;
     }
 
-  // (1) determinant part of this part's electrons: one wave per electron, lanes over orbitals
-  for (int li = wave; li < nloc; li += kWaves) {
-    const int i = p + li * np;
+  // (1) determinant part of this part's electrons i = p nloc + li, one thread per electron:
+  // column k of the inverse is read across the threads of consecutive electrons (coalesced),
+  // each thread walking its own value/gradient/Laplacian row
+  for (int li = tid; li < nloc; li += kBlock) {
+    const int i = p * nloc + li;
     if (i >= N) break;
     const int sp = i < P.n_up ? 0 : 1;
     const int n = sp ? P.n_dn : P.n_up, k = i - (sp ? P.n_up : 0);
     const size_t item = (size_t)w * N + i;
     const T* row = Wk.vgl + ((size_t)Wk.cur[item] * P.W * N + item) * kComp * P.S;
-    const T* B = (Wk.xinv ? Wk.xinv : Wk.binv) + (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0);
+    const T* B = (Wk.xinv ? Wk.xinv : Wk.binv) + (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0) + k;
     double gx = 0.0, gy = 0.0, gz = 0.0, l2 = 0.0;
-    for (int l = lane; l < n; l += 64) {
-      const double b = (double)B[(size_t)l * n + k];
+#pragma unroll 4
+    for (int l = 0; l < n; ++l) {
+      const double b = (double)B[(size_t)l * n];
       gx += b * (double)row[P.S + l];
       gy += b * (double)row[2 * P.S + l];
       gz += b * (double)row[3 * P.S + l];
       l2 += b * (double)row[4 * P.S + l];
     }
-    gx = wave_sum_dpp(gx); gy = wave_sum_dpp(gy); gz = wave_sum_dpp(gz); l2 = wave_sum_dpp(l2);
-    if (lane == 0) { sgd[3 * li] = gx; sgd[3 * li + 1] = gy; sgd[3 * li + 2] = gz; sld[li] = l2; }
+    sgd[3 * li] = gx; sgd[3 * li + 1] = gy; sgd[3 * li + 2] = gz; sld[li] = l2;
   }
 
   // (2) Jastrow gradient and Laplacian: (electron, part) items, partners j = part (mod parts)
   const int parts = lay.parts;
   for (int q = tid; q < nloc * parts; q += kBlock) {
-    const int li = q % nloc, part = q / nloc, i = p + li * np;
+    const int li = q % nloc, part = q / nloc, i = p * nloc + li;
     if (i >= N) continue;
     const double xi = spos[3 * i], yi = spos[3 * i + 1], zi = spos[3 * i + 2];
     const bool up_i = i < P.n_up;
     double g[3] = {0.0, 0.0, 0.0}, lj = 0.0;
-    for (int j = part; j < N + P.n_ions; j += parts) {
-      if (j == i) continue;
-      double cx, cy, cz;
-      int kind;
-      if (j < N) {
-        cx = spos[3 * j]; cy = spos[3 * j + 1]; cz = spos[3 * j + 2];
-        kind = ((j < P.n_up) == up_i) ? 0 : 1;
-      } else {
-        const double* ion = P.ions + 4 * (j - N);
-        cx = ion[0]; cy = ion[1]; cz = ion[2];
-        kind = 2;
+    // partners j = part (mod parts) in three ranges, each with its own radial function:
+    // same-spin electrons, opposite-spin electrons, ions
+    auto range = [&](const Radial& R, int lo, int hi, const double* c, int stride) {
+      for (int j = lo + ((part - lo) % parts + parts) % parts; j < hi; j += parts) {
+        const double* cj = c + (size_t)stride * j;
+        const double dx = min_image(xi - cj[0], P.L, invL), dy = min_image(yi - cj[1], P.L, invL);
+        const double dz = min_image(zi - cj[2], P.L, invL);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double ri = rsqrt(r2), r = r2 * ri;
+        double u, du, d2u;
+        radial_eval(R, r, u, du, d2u);
+        const double f = j == i ? 0.0 : du * ri;   // no self term
+        g[0] += f * dx; g[1] += f * dy; g[2] += f * dz;
+        lj += j == i ? 0.0 : d2u + 2.0 * f;
       }
-      const double dx = min_image(xi - cx, P.L), dy = min_image(yi - cy, P.L), dz = min_image(zi - cz, P.L);
-      const double r = sqrt(dx * dx + dy * dy + dz * dz);
-      double u, du, d2u;
-      radial_eval(pick(sj, kind), r, u, du, d2u);
-      const double f = du / r;
-      g[0] += f * dx; g[1] += f * dy; g[2] += f * dz;
-      lj += d2u + 2.0 * f;
-    }
+    };
+    range(up_i ? sj.same : sj.opp, 0, P.n_up, spos, 3);
+    range(up_i ? sj.opp : sj.same, P.n_up, N, spos, 3);
+    if (P.n_ions > 0) range(sj.ei, N, N + P.n_ions, P.ions - 4 * (size_t)N, 4);
     double* gp = sgj + 3 * ((size_t)part * nloc + li);
     gp[0] = g[0]; gp[1] = g[1]; gp[2] = g[2];
     slj[(size_t)part * nloc + li] = lj;
@@ -180,19 +198,19 @@ __device__ __forceinline__ void measure_part(const SysParams& P, const Walkers<T
       int i, j;
       if (q < N * D) { i = q % N; j = i + q / N + 1; if (j >= N) j -= N; }
       else { i = q - N * D; j = i + N / 2; }
-      const double dx = min_image(spos[3 * i] - spos[3 * j], P.L);
-      const double dy = min_image(spos[3 * i + 1] - spos[3 * j + 1], P.L);
-      const double dz = min_image(spos[3 * i + 2] - spos[3 * j + 2], P.L);
-      vee += screened_images(dx, dy, dz, P.L, E.kappa, rcut2);
+      const double dx = min_image(spos[3 * i] - spos[3 * j], P.L, invL);
+      const double dy = min_image(spos[3 * i + 1] - spos[3 * j + 1], P.L, invL);
+      const double dz = min_image(spos[3 * i + 2] - spos[3 * j + 2], P.L, invL);
+      vee += screened_images(dx, dy, dz, P.L, E.kappa, rcut2, shtab);
     }
     // (3b) electron-ion pairs
     for (int q = p + np * tid; q < N * P.n_ions; q += stride) {
       const int i = q % N, I = q / N;
       const double* ion = P.ions + 4 * I;
-      const double dx = min_image(spos[3 * i] - ion[0], P.L);
-      const double dy = min_image(spos[3 * i + 1] - ion[1], P.L);
-      const double dz = min_image(spos[3 * i + 2] - ion[2], P.L);
-      vei -= ion[3] * screened_images(dx, dy, dz, P.L, E.kappa, rcut2);
+      const double dx = min_image(spos[3 * i] - ion[0], P.L, invL);
+      const double dy = min_image(spos[3 * i + 1] - ion[1], P.L, invL);
+      const double dz = min_image(spos[3 * i + 2] - ion[2], P.L, invL);
+      vei -= ion[3] * screened_images(dx, dy, dz, P.L, E.kappa, rcut2, shtab);
     }
     // (3c) reciprocal space: items (segment, quarter of the electrons) in lane quads; a
     // segment holds at most kSeg vectors of one (Gx, Gy) column.  Each lane sums e^{iG.r}
@@ -242,7 +260,7 @@ __device__ __forceinline__ void measure_part(const SysParams& P, const Walkers<T
   // (4) per-electron kinetic term from (1) and (2)
   double tkin = 0.0;
   for (int li = tid; li < nloc; li += kBlock) {
-    if (p + li * np >= N) break;
+    if (p * nloc + li >= N) break;
     double g[3] = {0.0, 0.0, 0.0}, lj = 0.0;
     for (int part = 0; part < parts; ++part) {
       const double* gp = sgj + 3 * ((size_t)part * nloc + li);

@@ -103,6 +103,8 @@ __device__ __forceinline__ double wrap_cell(double x, double L) {
 }
 
 __device__ __forceinline__ double min_image(double d, double L) { return d - L * rint(d / L); }
+// The same with the reciprocal of L precomputed (no division).
+__device__ __forceinline__ double min_image(double d, double L, double invL) { return d - L * rint(d * invL); }
 
 // Uniform cubic B-spline basis on one axis: for t = i0 + f the knots
 // i0-1 .. i0+2 carry weights w, first derivatives dw and second derivatives
@@ -143,6 +145,11 @@ __device__ __forceinline__ void axis_weights(double x, double L, int G, Axis& a)
 }
 
 // Radial Jastrow function value and first two derivatives.
+// Cubic B-spline radial function on the knot interval holding t = r / delta: the four
+// coefficients p[n..n+3] (n = floor t) give the interval's polynomial in f = t - n,
+//   c0 = (p0 + 4 p1 + p2) / 6, c1 = (p2 - p0) / 2, c2 = (p0 - 2 p1 + p2) / 2,
+//   c3 = (p3 - p0) / 6 + (p1 - p2) / 2,
+// the expansion of the uniform cubic B-spline weights, evaluated by Horner's rule.
 __device__ __forceinline__ void radial_eval(const Radial& R, double r, double& u, double& du,
                                             double& d2u) {
   if (R.kind == QMC_J_PADE) {
@@ -150,18 +157,19 @@ __device__ __forceinline__ void radial_eval(const Radial& R, double r, double& u
     u = R.a * r * id;
     du = R.a * id * id;
     d2u = -2.0 * R.a * R.b * id * id * id;
-  } else if (R.kind == QMC_J_BSPLINE && r < R.rc) {
-    const double t = r * R.inv_delta;
+  } else if (R.kind == QMC_J_BSPLINE) {
+    // branch-free in r: beyond the cutoff the first interval is evaluated and weighted zero
+    const bool in = r < R.rc;
+    const double t = in ? r * R.inv_delta : 0.0;
     const double fl = floor(t);
-    const int n = (int)fl;
-    const double f = t - fl, f2 = f * f, f3 = f2 * f, g = 1.0 - f;
-    const double* p = R.p + n;
-    u = (g * g * g * p[0] + (3.0 * f3 - 6.0 * f2 + 4.0) * p[1] +
-         (-3.0 * f3 + 3.0 * f2 + 3.0 * f + 1.0) * p[2] + f3 * p[3]) * (1.0 / 6.0);
-    du = (-0.5 * g * g * p[0] + (1.5 * f2 - 2.0 * f) * p[1] + (-1.5 * f2 + f + 0.5) * p[2] +
-          0.5 * f2 * p[3]) * R.inv_delta;
-    d2u = (g * p[0] + (3.0 * f - 2.0) * p[1] + (1.0 - 3.0 * f) * p[2] + f * p[3]) *
-          (R.inv_delta * R.inv_delta);
+    const double* p = R.p + (int)fl;
+    const double f = t - fl;
+    const double p0 = p[0], p1 = p[1], p2 = p[2], p3 = p[3];
+    const double c0 = (p0 + 4.0 * p1 + p2) * (1.0 / 6.0), c1 = 0.5 * (p2 - p0);
+    const double c2 = 0.5 * (p0 + p2) - p1, c3 = (p3 - p0) * (1.0 / 6.0) + 0.5 * (p1 - p2);
+    u = in ? c0 + f * (c1 + f * (c2 + f * c3)) : 0.0;
+    du = in ? (c1 + f * (2.0 * c2 + 3.0 * f * c3)) * R.inv_delta : 0.0;
+    d2u = in ? (2.0 * c2 + 6.0 * f * c3) * (R.inv_delta * R.inv_delta) : 0.0;
   } else {
     u = 0.0; du = 0.0; d2u = 0.0;
   }
@@ -169,14 +177,16 @@ __device__ __forceinline__ void radial_eval(const Radial& R, double r, double& u
 
 __device__ __forceinline__ double radial_value(const Radial& R, double r) {
   if (R.kind == QMC_J_PADE) return R.a * r / (1.0 + R.b * r);
-  if (R.kind == QMC_J_BSPLINE && r < R.rc) {
-    const double t = r * R.inv_delta;
+  if (R.kind == QMC_J_BSPLINE) {
+    const bool in = r < R.rc;
+    const double t = in ? r * R.inv_delta : 0.0;
     const double fl = floor(t);
-    const int n = (int)fl;
-    const double f = t - fl, f2 = f * f, f3 = f2 * f, g = 1.0 - f;
-    const double* p = R.p + n;
-    return (g * g * g * p[0] + (3.0 * f3 - 6.0 * f2 + 4.0) * p[1] +
-            (-3.0 * f3 + 3.0 * f2 + 3.0 * f + 1.0) * p[2] + f3 * p[3]) * (1.0 / 6.0);
+    const double* p = R.p + (int)fl;
+    const double f = t - fl;
+    const double p0 = p[0], p1 = p[1], p2 = p[2], p3 = p[3];
+    const double c0 = (p0 + 4.0 * p1 + p2) * (1.0 / 6.0), c1 = 0.5 * (p2 - p0);
+    const double c2 = 0.5 * (p0 + p2) - p1, c3 = (p3 - p0) * (1.0 / 6.0) + 0.5 * (p1 - p2);
+    return in ? c0 + f * (c1 + f * (c2 + f * c3)) : 0.0;
   }
   return 0.0;
 }

@@ -10,6 +10,14 @@ namespace qmc {
 // vectors of one half space with their weights, the ions' structure factor).
 constexpr int kEwaldSeg = 10;   // reciprocal vectors per segment of a (Gx, Gy) column
 
+// Real-space Ewald term erfc(kappa r) / r = 1 / r - kappa H(kappa^2 r^2) with the entire
+// function H(x) = erf(sqrt x) / sqrt x, tabulated on [0, (kappa rcut)^2] = [0, 5.5^2] as
+// degree-kHDeg polynomials in u = (x - x_c) / (kHW / 2) on intervals of width kHW.
+constexpr int kHDeg = 7;
+constexpr double kHW = 0.25;
+constexpr int kHInt = 122;                     // covers x < 30.5
+constexpr int kHTab = kHInt * (kHDeg + 1);    // doubles
+
 struct EwaldParams {
   int enabled;
   int n_g, n_seg;
@@ -17,6 +25,7 @@ struct EwaldParams {
   const double* gvec;    // [n_g][4]: Gx, Gy, Gz, (4 pi / V) exp(-G^2 / 4 kappa^2) / G^2
   const double* s_ion;   // [n_g][2]: sum_I Z_I exp(i G.R_I)
   const int* segs;       // [n_seg][5]: mx, my, mz_lo, mz_hi, index of the first vector in gvec
+  const double* htab;    // [kHInt][kHDeg + 1]: polynomial coefficients of H, lowest degree first
   double c_ee;           // electron self, self-image and background terms
   double c_ei;           // electron-ion background cross term
   double v_ii;           // ion-ion energy (constant)

@@ -60,6 +60,9 @@ def load_library():
     global _lib
     if _lib is not None:
         return _lib
+    # PyTorch's HIP runtime must be the one the library binds to (one runtime per process),
+    # so torch is loaded before the library.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                            "or python paper_1802_06922_amd/build.py")
