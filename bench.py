@@ -61,7 +61,7 @@ def cpu_baseline(wl, target_s: float = 12.0):
     t0 = time.perf_counter()
     osys.run(ids, 1, measure_every=1, bits=False, threads=threads)
     t1 = time.perf_counter() - t0
-    sweeps = max(1, min(50, int(target_s / max(t1, 1e-3))))
+    sweeps = max(1, min(400, int(target_s / max(t1, 1e-3))))
     t0 = time.perf_counter()
     osys.run(ids, sweeps, measure_every=1, bits=False, threads=threads)
     dt = time.perf_counter() - t0
@@ -78,7 +78,8 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="solid128", help="solid128 | heg14 | mixed384")
     ap.add_argument("--delay", type=int, default=None,
-                    help="delay rank K (1 = Sherman-Morrison; 4..64 = delayed updates)")
+                    help="delay rank K (1 = Sherman-Morrison; 4..64 = delayed updates); "
+                         "default: autotuned before the timed region")
     ap.add_argument("--mode", default="single", choices=["single", "batched", "served", "copy"],
                     help="single: one system (default); batched: the four uneven systems in fused "
                          "launches; served: a Poisson request stream with continuous batching; copy: "
@@ -87,6 +88,8 @@ def main(argv=None) -> int:
     ap.add_argument("--sweep-scale", type=float, default=0.1, help="served: scale of each request's sweeps")
     ap.add_argument("--no-graph", action="store_true", help="batched/served: no HIP graph replay")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the mixed-vs-FP64 comparison on the 384-electron system")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args(argv)
     if args.gpus != 1:
@@ -98,8 +101,6 @@ def main(argv=None) -> int:
     import torch
 
     import qmc_inputs as qi
-    from paper_1802_06922_amd import KERNEL_CHAIN, KERNEL_GATHER, KERNEL_MEASURE, System
-
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
@@ -111,23 +112,76 @@ def main(argv=None) -> int:
     if args.mode == "copy":
         return copy_reference()
     wl = qi.WORKLOADS[args.workload]()
-    if args.delay is not None:
-        wl.delay_rank = args.delay
+    r = run_single(wl, args.steps, args.warmup, args.delay)
+    W, N = r["walkers"], wl.n_elec
+    kt = r["kt"]
+    b = wl.coefs.dtype.itemsize
+    bytes_per_move = 64 * wl.n_orb * b
+    g_ms, g_n = kt["gather"]
+    avg_gather_s = g_ms / max(g_n, 1) / 1e3
+    achieved = bytes_per_move * W * N / avg_gather_s / 1e9
+    line = {
+        "metric": METRIC,
+        "value": r["value"],
+        "unit": "electron-moves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if wl.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": describe(wl), "walkers": W, "electrons": N, "orbitals": wl.n_orb,
+                   "grid": list(wl.grid), "delay_rank": r["delay_rank"],
+                   "step": "1 sweep (N moves per walker) + local energy"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(wl),
+                     "kernel": "k_gather (proposal + tricubic B-spline VGL of every orbital)",
+                     "bytes_per_launch": bytes_per_move * W * N,
+                     "avg_launch_ms": avg_gather_s * 1e3},
+        "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
+        "sweep_only_moves_per_s": r["sweep_only_moves_per_s"],
+        "mean_local_energy": r["mean_local_energy"],
+    }
+    if not args.no_compare:
+        line["mixed_vs_fp64"] = compare_precisions(args)
+    if not args.no_cpu_baseline:
+        print("[bench] CPU baseline (oracle)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def run_single(wl, steps: int, warmup: int, delay, quiet: bool = False):
+    """Steps of (sweep + local energy) of one system; the delay rank is autotuned when not given
+    (the trial sweeps are ordinary sweeps, before the timed region)."""
+    import torch
+
+    from paper_1802_06922_amd import KERNEL_CHAIN, KERNEL_GATHER, KERNEL_MEASURE, System
+    if delay is not None:
+        wl.delay_rank = delay
     print(f"[bench] building {wl.name}", file=sys.stderr, flush=True)
     s = System(wl)
+    if delay is None:
+        K, _ = s.autotune_delay(ranks=(1, 8, 16, 32, 64), trial_sweeps=3)
+        print(f"[bench] {wl.name}: delay rank {K} (autotuned)", file=sys.stderr, flush=True)
+    else:
+        K = delay
     W, N = s.W, wl.n_elec
     energies = torch.empty((W, 4), dtype=torch.float64, device="cuda")
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         s.sweep(1)
         s.measure(out=energies)
     torch.cuda.synchronize()
     s.set_timing(True)
     for k in (KERNEL_GATHER, KERNEL_CHAIN, KERNEL_MEASURE):
         s.kernel_timing(k, reset=True)
-    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    print(f"[bench] {wl.name}: timing {steps} steps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         s.sweep(1)
         s.measure(out=energies)
     torch.cuda.synchronize()
@@ -136,44 +190,32 @@ def main(argv=None) -> int:
           (("gather", KERNEL_GATHER), ("chain", KERNEL_CHAIN), ("measure", KERNEL_MEASURE))}
     e_host = energies.cpu().numpy()
     s.close()
+    moves = W * N * steps
+    sweep_ms = (kt["gather"][0] + kt["chain"][0]) / steps
+    return {"value": moves / dt, "ms_per_step": dt / steps * 1e3, "kt": kt, "walkers": W,
+            "delay_rank": K, "sweep_only_moves_per_s": moves / (sweep_ms * steps / 1e3) if sweep_ms > 0 else None,
+            "mean_local_energy": float(e_host.sum(axis=1).mean())}
 
-    moves = W * N * args.steps
-    value = moves / dt
-    b = wl.coefs.dtype.itemsize
-    bytes_per_move = 64 * wl.n_orb * b
-    g_ms, g_n = kt["gather"]
-    avg_gather_s = g_ms / max(g_n, 1) / 1e3
-    achieved = bytes_per_move * W * N / avg_gather_s / 1e9
-    sweep_ms = (kt["gather"][0] + kt["chain"][0]) / args.steps
-    line = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "electron-moves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if wl.precision == "fp64" else "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": describe(wl), "walkers": W, "electrons": N, "orbitals": wl.n_orb,
-                   "grid": list(wl.grid), "step": "1 sweep (N moves per walker) + local energy"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(wl),
-                     "kernel": "k_gather (proposal + tricubic B-spline VGL of every orbital)",
-                     "bytes_per_launch": bytes_per_move * W * N,
-                     "avg_launch_ms": avg_gather_s * 1e3},
-        "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
-        "sweep_only_moves_per_s": moves / (sweep_ms * args.steps / 1e3) if sweep_ms > 0 else None,
-        "mean_local_energy": float(e_host.sum(axis=1).mean()),
-    }
-    if not args.no_cpu_baseline:
-        print("[bench] CPU baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
-    print(json.dumps(line), flush=True)
-    return 0
+
+def compare_precisions(args):
+    """The 384-electron system in mixed precision and in FP64 (the same FP32-valued table stored
+    in FP64, FP64 inverse updates, no guard), each with its autotuned delay rank."""
+    import dataclasses
+
+    import numpy as np
+
+    import qmc_inputs as qi
+    steps = max(3, args.steps // 6)
+    mixed = qi.mixed384()
+    fp64 = dataclasses.replace(mixed, precision="fp64", coefs=mixed.coefs.astype(np.float64),
+                               recompute_period=0, name="solid384_fp64")
+    out = {"workload": "384 electrons, 192 orbitals, 64^3 table, 96 ions, 1024 walkers"}
+    for tag, wl in (("mixed", mixed), ("fp64", fp64)):
+        r = run_single(wl, steps, 1, None)
+        out[tag] = {"moves_per_s": r["value"], "ms_per_step": r["ms_per_step"], "delay_rank": r["delay_rank"],
+                    "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in r["kt"].items()}}
+    out["mixed_over_fp64"] = out["mixed"]["moves_per_s"] / out["fp64"]["moves_per_s"]
+    return out
 
 
 def copy_reference() -> int:

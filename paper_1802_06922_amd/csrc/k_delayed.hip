@@ -261,6 +261,9 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
   T* sB = reinterpret_cast<T*>(smem + lay.b);
   const double L = P.L, invL = 1.0 / P.L;
   const int tpq = kBlock / K;   // threads per window slot in the Jastrow sums
+  // the wave that runs the moves in sequence rotates with the workgroup index, so that the
+  // sequential phases of workgroups sharing a compute unit fall on different SIMDs
+  const int seq_wave = (int)(blockIdx.x & (kWaves - 1)), seq_tid = seq_wave * 64;
 
   {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(&P.jas);
@@ -360,7 +363,7 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
       // row q of the window block yk = Y[:, k0 .. k0 + Kw).  An accepted move q eliminates
       // its column from the later rows (the Sherman-Morrison update restricted to the
       // window's own columns), so each ratio is read, not recomputed: R_q = yk[q][q].
-      if (wave == 0) {
+      if (wave == seq_wave) {
         if (lane == 0) sm_stop = -1;
         double Fq = 0.0;
         if (lane < Kw) {
@@ -523,7 +526,7 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
       Wk.cur[item0 + q] = scur[q];
       Wk.acc[item0 + q] = sacc[q];
     }
-    if (tid == 0) {
+    if (tid == seq_tid) {   // the sequential wave holds the complete log|D|, sign and counts
       Wk.logdet[2 * w + sp] = logd;
       Wk.sign[2 * w + sp] = sgn;
     }
@@ -536,7 +539,7 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
     __syncthreads();
   }
   for (int j = tid; j < 3 * N; j += kBlock) Wk.pos[(size_t)w * 3 * N + j] = spos[j];
-  if (tid == 0) {
+  if (tid == seq_tid) {
     Wk.nacc[w] = nacc;
     Wk.nguard[w] += nguard;
     if (w == 0) *Wk.sweep_ctr += 1u;   // read by the next sweep's gather

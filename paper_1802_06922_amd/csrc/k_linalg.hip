@@ -141,12 +141,15 @@ __global__ __launch_bounds__(kBlock) void k_rebuild(SysParams P, Walkers<T> Wk, 
 // matrix, X to the buffer the measurement reads (binv itself is not changed,
 // so a measurement never alters the chain).
 // ---------------------------------------------------------------------------
-constexpr int kTile = 64, kChunk = 16;
+constexpr int kTile = 64, kChunk = 32;
 constexpr int kLs = kChunk + 1;    // padded LDS row strides (fewer bank conflicts)
 constexpr int kRs = kTile + 2;
+constexpr int kPerThread = kTile * kChunk / kBlock;   // panel entries each thread stages
 
 // C[i][k] = sum_l Lf(i, l) Rf(l, k) for i, k < n; epi(i, k, C[i][k]) stores each
-// result.  All threads of the block call it; each wave owns a 32 x 32 quadrant.
+// result.  All threads of the block call it; each wave owns a 32 x 32 quadrant of a
+// 64 x 64 output tile.  The panels of the next k-chunk are loaded into registers while
+// the matrix cores work on the current chunk from LDS.
 template <typename LF, typename RF, typename EF>
 __device__ __forceinline__ void gemm64(int n, LF Lf, RF Rf, EF epi, double* sL, double* sR) {
   typedef Mfma<double> M;
@@ -154,6 +157,7 @@ __device__ __forceinline__ void gemm64(int n, LF Lf, RF Rf, EF epi, double* sL, 
   const int li = lane & 15, lk = lane >> 4;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int nt = (n + kTile - 1) / kTile;
+  const int nc = (n + kChunk - 1) / kChunk;
   for (int t = 0; t < nt * nt; ++t) {
     const int i0 = (t / nt) * kTile, k0 = (t % nt) * kTile;
     M::v4 acc[2][2];
@@ -161,16 +165,29 @@ __device__ __forceinline__ void gemm64(int n, LF Lf, RF Rf, EF epi, double* sL, 
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b) acc[a][b] = M::v4{0.0, 0.0, 0.0, 0.0};
-    for (int l0 = 0; l0 < n; l0 += kChunk) {
-      for (int q = tid; q < kTile * kChunk; q += kBlock) {
+    double rl[kPerThread], rr[kPerThread];
+    auto fetch = [&](int l0) {
+#pragma unroll
+      for (int e = 0; e < kPerThread; ++e) {
+        const int q = tid + e * kBlock;
         const int r = q / kChunk, c = q % kChunk;          // left panel: row r, column c
         const int i = i0 + r, l = l0 + c;
-        sL[r * kLs + c] = (i < n && l < n) ? Lf(i, l) : 0.0;
-        const int rr = q / kTile, cc = q % kTile;          // right panel: row rr, column cc
-        const int l2 = l0 + rr, k = k0 + cc;
-        sR[rr * kRs + cc] = (l2 < n && k < n) ? Rf(l2, k) : 0.0;
+        rl[e] = (i < n && l < n) ? Lf(i, l) : 0.0;
+        const int rr2 = q / kTile, cc = q % kTile;         // right panel: row rr2, column cc
+        const int l2 = l0 + rr2, k = k0 + cc;
+        rr[e] = (l2 < n && k < n) ? Rf(l2, k) : 0.0;
+      }
+    };
+    fetch(0);
+    for (int ch = 0; ch < nc; ++ch) {
+#pragma unroll
+      for (int e = 0; e < kPerThread; ++e) {
+        const int q = tid + e * kBlock;
+        sL[(q / kChunk) * kLs + q % kChunk] = rl[e];
+        sR[(q / kTile) * kRs + q % kTile] = rr[e];
       }
       __syncthreads();
+      if (ch + 1 < nc) fetch((ch + 1) * kChunk);   // in flight during the products below
 #pragma unroll
       for (int kk = 0; kk < kChunk; kk += 4) {
 #pragma unroll
