@@ -54,8 +54,12 @@ class Request:
 
 
 class Server:
+    """Continuous batching on one GPU.  Admitted requests are prepared (device allocation, table
+    upload, walker initialisation) by host threads on their own stream while the resident
+    requests keep sweeping; a prepared request joins the batch at the next sweep boundary."""
+
     def __init__(self, hbm_budget_bytes: Optional[int] = None, reserve_bytes: int = 8 << 30,
-                 graph: bool = False):
+                 graph: bool = False, prep_threads: int = 2):
         import torch
         self.torch = torch
         free, total = torch.cuda.mem_get_info()
@@ -65,21 +69,30 @@ class Server:
         self.budget = max(0, int(budget))
         self.graph = graph
         self.stream = torch.cuda.Stream()
+        self.prep_threads = prep_threads
 
     def run(self, requests, time_scale: float = 1.0, log=None):
         """Serve ``requests`` (list of Request, arrival times in seconds); returns a stats dict."""
         torch = self.torch
         pending = deque(sorted(requests, key=lambda r: r.arrival_s))
         queue: deque = deque()
+        preparing: list = []
         active: list = []
         finished: list = []
         used = 0
         batch = None
         dirty = True
         n_sweep_iters = 0
+        prep_streams = [torch.cuda.Stream() for _ in range(self.prep_threads)]
         t0 = time.perf_counter()
-        with torch.cuda.stream(self.stream):
-            while pending or queue or active:
+
+        def prepare(r, k):
+            with torch.cuda.stream(prep_streams[k]):
+                return qmc.System(r.wl, stream=prep_streams[k])
+
+        with cf.ThreadPoolExecutor(max_workers=self.prep_threads) as pool, torch.cuda.stream(self.stream):
+            n_sub = 0
+            while pending or queue or preparing or active:
                 now = time.perf_counter() - t0
                 while pending and pending[0].arrival_s * time_scale <= now:
                     queue.append(pending.popleft())
@@ -91,17 +104,29 @@ class Server:
                     if used + r.est_bytes > self.budget:
                         break
                     queue.popleft()
-                    r.system = qmc.System(r.wl, stream=self.stream)
-                    r.admitted_s = time.perf_counter() - t0
-                    r.last_done_s = r.admitted_s
                     used += r.est_bytes
-                    active.append(r)
-                    dirty = True
-                    if log:
-                        log(f"[serve] t={r.admitted_s:.3f}s admit {r.rid} N={r.wl.n_elec} W={r.wl.n_walkers} "
-                            f"sweeps={r.n_sweeps} ({len(active)} resident)")
+                    preparing.append((r, pool.submit(prepare, r, n_sub % self.prep_threads)))
+                    n_sub += 1
+                # prepared requests join at this sweep boundary (and the loop waits for one
+                # when nothing else can run)
+                if preparing and not active:
+                    cf.wait([f for _, f in preparing], return_when=cf.FIRST_COMPLETED)
+                still_prep = []
+                for r, f in preparing:
+                    if f.done():
+                        r.system = f.result()
+                        r.admitted_s = time.perf_counter() - t0
+                        r.last_done_s = r.admitted_s
+                        active.append(r)
+                        dirty = True
+                        if log:
+                            log(f"[serve] t={r.admitted_s:.3f}s admit {r.rid} N={r.wl.n_elec} "
+                                f"W={r.wl.n_walkers} sweeps={r.n_sweeps} ({len(active)} resident)")
+                    else:
+                        still_prep.append((r, f))
+                preparing = still_prep
                 if not active:
-                    if pending:
+                    if pending and not queue and not preparing:
                         time.sleep(max(0.0, pending[0].arrival_s * time_scale - (time.perf_counter() - t0)))
                     continue
                 if dirty:
