@@ -143,10 +143,14 @@ __device__ __forceinline__ void gemm_window(const T* V, const T* B, int ldb, T* 
       for (int l0 = 0; l0 < n; l0 += 4) {
         const int l = l0 + lk;
         T a[kGroup], b[kGroup];
+        // unconditional loads from clamped indices (in bounds), out-of-range entries zeroed
+        const int lc = l < n ? l : n - 1;
 #pragma unroll
         for (int j = 0; j < kGroup; ++j) {
-          a[j] = (qa[j] < Kw && l < n) ? V[(size_t)qa[j] * nP + l] : T(0);
-          b[j] = (l < n && cb[j] < n) ? B[(size_t)l * ldb + cb[j]] : T(0);
+          const T av = V[(size_t)(qa[j] < Kw ? qa[j] : Kw - 1) * nP + lc];
+          const T bv = B[(size_t)lc * ldb + (cb[j] < n ? cb[j] : n - 1)];
+          a[j] = (qa[j] < Kw && l < n) ? av : T(0);
+          b[j] = (l < n && cb[j] < n) ? bv : T(0);
         }
 #pragma unroll
         for (int j = 0; j < kGroup; ++j) acc[j] = M::mma(a[j], b[j], acc[j]);
@@ -194,7 +198,8 @@ __device__ __forceinline__ void gemm_flush(T* B, int ldb, const T* U, int ldu, c
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int l = lrow[j] + M::row(lane, r);
-          old[j][r] = (l < n && cb[j] < n) ? B[(size_t)l * ldb + cb[j]] : T(0);
+          const T v = B[(size_t)(l < n ? l : n - 1) * ldb + (cb[j] < n ? cb[j] : n - 1)];
+          old[j][r] = (l < n && cb[j] < n) ? v : T(0);
         }
       }
       typename M::v4 acc[kGroup];
@@ -205,9 +210,9 @@ __device__ __forceinline__ void gemm_flush(T* B, int ldb, const T* U, int ldu, c
 #pragma unroll
         for (int j = 0; j < kGroup; ++j) {
           const int la = lrow[j] + li;
-          const T a = (la < n) ? U[(size_t)la * ldu + r] : T(0);
-          const T b = (cb[j] < n) ? Z[(size_t)r * nP + cb[j]] : T(0);
-          acc[j] = M::mma(a, b, acc[j]);
+          const T av = U[(size_t)(la < n ? la : n - 1) * ldu + r];
+          const T bv = Z[(size_t)r * nP + (cb[j] < n ? cb[j] : n - 1)];
+          acc[j] = M::mma(la < n ? av : T(0), cb[j] < n ? bv : T(0), acc[j]);
         }
       }
 #pragma unroll
@@ -368,8 +373,10 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
         double Fq = 0.0;
         if (lane < Kw) {
           for (int s = 0; s < tpq; ++s) Fq += red[lane * tpq + s];
-          for (int j = 0; j < Kw; ++j)
-            if (j != lane) Fq += gold[lane * K + j];
+          for (int j = 0; j < Kw; ++j) {
+            const double gj = gold[lane * K + j];
+            Fq += j != lane ? gj : 0.0;
+          }
         }
         wave_sync_lds();   // gold is consumed: its storage takes yk
         if (lane < Kw)
@@ -392,14 +399,16 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
           if (u < p32) {
             if (lane > q && lane < Kw) {
               const T f = yk[lane * K + q] / R;
-              // eight columns at a time: all loads before the stores, so they overlap
+              // eight columns at a time: all loads before the stores, so they overlap.  The
+              // loads are unconditional (a guarded load becomes a branch of its own): columns
+              // past Kw read at most 7 entries beyond the row, inside the LDS block that
+              // follows yk, and are never stored.
               for (int j0 = q + 1; j0 < Kw; j0 += 8) {
                 T pv[8], rv[8];
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                  const int j = j0 + e;
-                  pv[e] = j < Kw ? yk[q * K + j] : T(0);
-                  rv[e] = j < Kw ? yk[lane * K + j] : T(0);
+                  pv[e] = yk[q * K + j0 + e];
+                  rv[e] = yk[lane * K + j0 + e];
                 }
 #pragma unroll
                 for (int e = 0; e < 8; ++e)

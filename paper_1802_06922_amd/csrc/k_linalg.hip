@@ -171,11 +171,14 @@ __device__ __forceinline__ void gemm64(int n, LF Lf, RF Rf, EF epi, double* sL, 
       for (int e = 0; e < kPerThread; ++e) {
         const int q = tid + e * kBlock;
         const int r = q / kChunk, c = q % kChunk;          // left panel: row r, column c
+        // unconditional loads from clamped indices, out-of-range entries zeroed
         const int i = i0 + r, l = l0 + c;
-        rl[e] = (i < n && l < n) ? Lf(i, l) : 0.0;
+        const double vl = Lf(i < n ? i : n - 1, l < n ? l : n - 1);
+        rl[e] = (i < n && l < n) ? vl : 0.0;
         const int rr2 = q / kTile, cc = q % kTile;         // right panel: row rr2, column cc
         const int l2 = l0 + rr2, k = k0 + cc;
-        rr[e] = (l2 < n && k < n) ? Rf(l2, k) : 0.0;
+        const double vr = Rf(l2 < n ? l2 : n - 1, k < n ? k : n - 1);
+        rr[e] = (l2 < n && k < n) ? vr : 0.0;
       }
     };
     fetch(0);
