@@ -135,6 +135,7 @@ def main(argv=None) -> int:
         "data": "synthetic",
         "config": {"workload": describe(wl), "walkers": W, "electrons": N, "orbitals": wl.n_orb,
                    "grid": list(wl.grid), "delay_rank": r["delay_rank"],
+                   "gather_lanes_log2": r["gather_lanes_log2"],
                    "step": "1 sweep (N moves per walker) + local energy"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(wl),
@@ -164,9 +165,11 @@ def run_single(wl, steps: int, warmup: int, delay, quiet: bool = False):
         wl.delay_rank = delay
     print(f"[bench] building {wl.name}", file=sys.stderr, flush=True)
     s = System(wl)
+    lanes_log2, _ = s.autotune_gather(trial_sweeps=3)
     if delay is None:
         K, _ = s.autotune_delay(ranks=(1, 8, 16, 32, 64), trial_sweeps=3)
-        print(f"[bench] {wl.name}: delay rank {K} (autotuned)", file=sys.stderr, flush=True)
+        print(f"[bench] {wl.name}: delay rank {K}, gather lanes 2^{lanes_log2} (autotuned)",
+              file=sys.stderr, flush=True)
     else:
         K = delay
     W, N = s.W, wl.n_elec
@@ -189,12 +192,13 @@ def run_single(wl, steps: int, warmup: int, delay, quiet: bool = False):
     kt = {name: s.kernel_timing(k) for name, k in
           (("gather", KERNEL_GATHER), ("chain", KERNEL_CHAIN), ("measure", KERNEL_MEASURE))}
     e_host = energies.cpu().numpy()
+    pos_host = s.get_walkers()[0]
     s.close()
     moves = W * N * steps
     sweep_ms = (kt["gather"][0] + kt["chain"][0]) / steps
     return {"value": moves / dt, "ms_per_step": dt / steps * 1e3, "kt": kt, "walkers": W,
-            "delay_rank": K, "sweep_only_moves_per_s": moves / (sweep_ms * steps / 1e3) if sweep_ms > 0 else None,
-            "mean_local_energy": float(e_host.sum(axis=1).mean())}
+            "delay_rank": K, "gather_lanes_log2": lanes_log2, "sweep_only_moves_per_s": moves / (sweep_ms * steps / 1e3) if sweep_ms > 0 else None,
+            "mean_local_energy": float(e_host.sum(axis=1).mean()), "energies": e_host, "positions": pos_host}
 
 
 def compare_precisions(args):
@@ -210,11 +214,21 @@ def compare_precisions(args):
     fp64 = dataclasses.replace(mixed, precision="fp64", coefs=mixed.coefs.astype(np.float64),
                                recompute_period=0, name="solid384_fp64")
     out = {"workload": "384 electrons, 192 orbitals, 64^3 table, 96 ions, 1024 walkers"}
+    runs = {}
     for tag, wl in (("mixed", mixed), ("fp64", fp64)):
         r = run_single(wl, steps, 1, None)
+        runs[tag] = r
         out[tag] = {"moves_per_s": r["value"], "ms_per_step": r["ms_per_step"], "delay_rank": r["delay_rank"],
                     "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in r["kt"].items()}}
     out["mixed_over_fp64"] = out["mixed"]["moves_per_s"] / out["fp64"]["moves_per_s"]
+    # both ran the same number of sweeps from the same start; the mixed path takes the FP64
+    # decisions, so the walkers coincide and the last local energies compare one to one
+    same = bool(np.array_equal(runs["mixed"]["positions"], runs["fp64"]["positions"]))
+    em, ef = runs["mixed"]["energies"], runs["fp64"]["energies"]
+    rel = np.abs(em - ef) / np.maximum(np.abs(ef), 1.0)
+    out["mixed_energy_error_vs_fp64"] = {
+        "same_walker_positions": same, "components": "kinetic, e-e, e-I, I-I per walker",
+        "max": float(rel.max()), "p99": float(np.percentile(rel, 99)), "median": float(np.median(rel))}
     return out
 
 
@@ -244,8 +258,10 @@ def bench_batched(args) -> int:
     for wl in wls:
         print(f"[bench] building {wl.name}", file=sys.stderr, flush=True)
         s = System(wl)
+        tl, gms = s.autotune_gather(trial_sweeps=3)
         K, ms = s.autotune_delay(ranks=(8, 16, 32, 64), trial_sweeps=3)
-        tuned.append({"system": wl.name, "delay_rank": K, "chain_ms": ms})
+        tuned.append({"system": wl.name, "delay_rank": K, "chain_ms": ms, "gather_lanes_log2": tl,
+                      "gather_ms": gms})
         systems.append(s)
     b = Batch(systems, graph=not args.no_graph)
     for _ in range(args.warmup):

@@ -201,6 +201,15 @@ qmc_status qmc_kernel_timing(qmc_system s, int32_t kernel_class, double* total_m
  * never span sweeps, so any rank is valid at a sweep boundary. */
 qmc_status qmc_set_delay_rank(qmc_system s, int32_t delay_rank);
 
+/* Gather autotuner: times the orbital gather (section "B-spline basis sets")
+ * with 1/2, 1, 2 and 4 times the default number of lanes per proposal (lanes
+ * split a proposal's orbitals, never a sum, so every width gives the same
+ * rows bit for bit), trial_sweeps (>= 2; the first untimed) ordinary sweeps
+ * each, and keeps the fastest for later sweeps and batches.  best_lanes_log2,
+ * best_ms (nullable): the chosen width (log2 lanes) and its mean gather
+ * milliseconds.  Errors: STATE before init_walkers or without a table. */
+qmc_status qmc_autotune_gather(qmc_system s, int32_t trial_sweeps, int32_t* best_lanes_log2, double* best_ms);
+
 /* Autotuner: runs trial_sweeps sweeps (>= 2; the first is not timed) with each
  * candidate delay rank, times the move-chain kernel with HIP events, keeps the
  * fastest and writes it to best_rank (best_ms: its mean chain milliseconds per

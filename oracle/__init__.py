@@ -47,7 +47,9 @@ def lib():
         L.orc_gauss3.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, dp]
         L.orc_accept_uniform.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32]
         L.orc_accept_uniform.restype = C.c_double
-        L.orc_init_position.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_double, dp]
+        L.orc_init_position.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_double, dp]
+        L.orc_fp32_inverse_residual.argtypes = [C.c_int, dp, dp]
+        L.orc_fp32_inverse_residual.restype = C.c_double
         L.orc_spo_vgl.argtypes = [C.c_void_p, dp, dp, dp, dp]
         L.orc_radial.argtypes = [C.c_void_p, C.c_int, C.c_double, dp]
         L.orc_inverse.argtypes = [C.c_int, dp, dp, dp, ip]
@@ -229,9 +231,9 @@ def accept_uniform(seed, walker, sweep, electron):
     return lib().orc_accept_uniform(seed, walker, sweep, electron)
 
 
-def init_position(seed, walker, electron, L):
+def init_position(seed, walker, electron, L, attempt=0):
     r = np.zeros(3)
-    lib().orc_init_position(seed, walker, electron, L, _dp(r))
+    lib().orc_init_position(seed, walker, electron, attempt, L, _dp(r))
     return r
 
 
@@ -273,3 +275,14 @@ def ewald(pos, q, L, kappa=0.0):
 
 def max_threads():
     return lib().orc_max_threads()
+
+
+def fp32_inverse_residual(A, B):
+    """max |I - A fl32(B)| in double (the oracle's acceptance test for initial configurations)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    return lib().orc_fp32_inverse_residual(A.shape[0], _dp(A), _dp(B))
+
+
+INIT_ATTEMPTS = 16
+INIT_RESIDUAL = 1e-5

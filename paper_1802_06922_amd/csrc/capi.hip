@@ -105,6 +105,7 @@ struct qmc_system_s {
   int* status = nullptr;
   double* val64 = nullptr;
   void* xinv = nullptr;      // FP64-refined inverse read by the measurement (mixed precision)
+  int gather_lanes_log2 = -1;   // lanes per proposal in the gather (log2); -1 = default
   uint32_t* nguard = nullptr;
   uint32_t* sweep_ctr = nullptr;
   double* scratch = nullptr;
@@ -627,23 +628,50 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
       wp[q] = (y >= s->d.L) ? 0.0 : y;
     }
     HIP_TRY(s, hipMemcpy(s->pos, wp.data(), wp.size() * sizeof(double), hipMemcpyHostToDevice));
-  } else {
-    HIP_TRY(s, launch_init_positions(s->P, s->pos, s->stream));
   }
-  HIP_TRY(s, hipMemsetAsync(s->status, 0, z.status, s->stream));
   HIP_TRY(s, hipMemsetAsync(s->nguard, 0, z.nguard, s->stream));
   HIP_TRY(s, hipMemsetAsync(s->sweep_ctr, 0, z.sweep, s->stream));
   HIP_TRY(s, hipMemsetAsync(s->acc, 0, z.acc, s->stream));
-  HIP_TRY(s, hipMemsetAsync(s->logdet, 0, z.logdet, s->stream));
-  hipError_t e;
-  if (s->d.precision == QMC_MIXED)
-    e = timed(s, 0, [&] { return launch_gather<float>(s->P, walkers_of<float>(s), static_cast<const float*>(s->d_table), 1, s->stream); });
-  else
-    e = timed(s, 0, [&] { return launch_gather<double>(s->P, walkers_of<double>(s), static_cast<const double*>(s->d_table), 1, s->stream); });
-  if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "orbital gather launch: %s", hipGetErrorString(e));
-  qmc_status st = run_rebuild(s, nullptr);
-  if (st != QMC_OK) return st;
-  st = check_singular(s);
+  // Rows, inverses and log|D| of the current positions.  Positions drawn here are uniform in
+  // the cell; a walker's draw is redrawn (next attempt of its INIT counter) while one of its
+  // Slater matrices is singular or so badly conditioned that the single-precision rounding of
+  // its inverse leaves a residual above kInitResidual.  The attempt numbers live in nacc and
+  // the residuals in drift until the first sweep.
+  std::vector<uint32_t> attempt(W, 0u);
+  std::vector<double> resid((size_t)W * 2);
+  std::vector<int> status(W);
+  uint32_t* d_attempt = s->nacc;
+  for (int round = 0;; ++round) {
+    if (!pos) {
+      HIP_TRY(s, hipMemcpyAsync(d_attempt, attempt.data(), W * sizeof(uint32_t), hipMemcpyHostToDevice, s->stream));
+      HIP_TRY(s, launch_init_positions(s->P, s->pos, d_attempt, s->stream));
+    }
+    HIP_TRY(s, hipMemsetAsync(s->status, 0, z.status, s->stream));
+    HIP_TRY(s, hipMemsetAsync(s->logdet, 0, z.logdet, s->stream));
+    hipError_t e;
+    if (s->d.precision == QMC_MIXED)
+      e = timed(s, 0, [&] { return launch_gather<float>(s->P, walkers_of<float>(s), static_cast<const float*>(s->d_table), 1, s->stream); });
+    else
+      e = timed(s, 0, [&] { return launch_gather<double>(s->P, walkers_of<double>(s), static_cast<const double*>(s->d_table), 1, s->stream); });
+    if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "orbital gather launch: %s", hipGetErrorString(e));
+    qmc_status st = run_rebuild(s, nullptr);
+    if (st != QMC_OK) return st;
+    if (pos) break;
+    e = s->d.precision == QMC_MIXED ? launch_inverse_residual<float>(s->P, walkers_of<float>(s), s->drift, s->stream)
+                                    : launch_inverse_residual<double>(s->P, walkers_of<double>(s), s->drift, s->stream);
+    if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "residual launch: %s", hipGetErrorString(e));
+    HIP_TRY(s, hipMemcpyAsync(resid.data(), s->drift, resid.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipMemcpyAsync(status.data(), s->status, status.size() * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    if (round + 1 >= kInitAttempts) break;
+    bool redraw = false;
+    for (int w = 0; w < W; ++w) {
+      const double r = std::max(resid[2 * w], resid[2 * w + 1]);
+      if (status[w] || !(r <= kInitResidual)) { ++attempt[w]; redraw = true; }
+    }
+    if (!redraw) break;
+  }
+  qmc_status st = check_singular(s);
   s->sweep_index = 0;
   s->has_walkers = (st == QMC_OK);
   return st;
@@ -662,14 +690,14 @@ qmc_status qmc_sweep(qmc_system s, int32_t n_sweeps, uint64_t* n_accepted_out) {
     const int K = s->d.delay_rank;
     const int mfma = s->use_mfma;
     if (s->d.precision == QMC_MIXED) {
-      e = timed(s, 0, [&] { return launch_gather<float>(s->P, walkers_of<float>(s), static_cast<const float*>(s->d_table), 0, s->stream); });
+      e = timed(s, 0, [&] { return launch_gather<float>(s->P, walkers_of<float>(s), static_cast<const float*>(s->d_table), 0, s->stream, s->gather_lanes_log2); });
       if (e == hipSuccess)
         e = timed(s, 1, [&] {
           return K > 1 ? launch_chain_delayed<float>(s->P, walkers_of<float>(s), K, mfma, s->stream)
                        : launch_chain<float>(s->P, walkers_of<float>(s), s->stream);
         });
     } else {
-      e = timed(s, 0, [&] { return launch_gather<double>(s->P, walkers_of<double>(s), static_cast<const double*>(s->d_table), 0, s->stream); });
+      e = timed(s, 0, [&] { return launch_gather<double>(s->P, walkers_of<double>(s), static_cast<const double*>(s->d_table), 0, s->stream, s->gather_lanes_log2); });
       if (e == hipSuccess)
         e = timed(s, 1, [&] {
           return K > 1 ? launch_chain_delayed<double>(s->P, walkers_of<double>(s), K, mfma, s->stream)
@@ -831,6 +859,42 @@ qmc_status qmc_set_delay_rank(qmc_system s, int32_t delay_rank) {
   return QMC_OK;
 }
 
+qmc_status qmc_autotune_gather(qmc_system s, int32_t trial_sweeps, int32_t* best_lanes_log2, double* best_ms) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (!s->has_walkers) return fail(s, QMC_ERR_STATE, "init_walkers first");
+  if (!s->d_table) return fail(s, QMC_ERR_STATE, "load_spline_table first");
+  if (trial_sweeps < 2) return fail(s, QMC_ERR_ARG, "need >= 2 trial sweeps");
+  const int V = s->d.precision == QMC_MIXED ? 4 : 2;
+  const int base = gather_tpi_log2(s->P.S / V);
+  const bool timing_was = s->timing;
+  const int was = s->gather_lanes_log2;
+  s->timing = true;
+  int best = -1;
+  double best_t = 0.0;
+  for (int tl = base - 1; tl <= base + 2; ++tl) {
+    if (tl < 0 || tl > 6) continue;
+    s->gather_lanes_log2 = tl;
+    qmc_status st = qmc_sweep(s, 1, nullptr);   // untimed: first use of this width
+    double ms = 0.0;
+    int64_t cnt = 0;
+    if (st == QMC_OK) st = qmc_kernel_timing(s, 0, nullptr, nullptr, 1);
+    if (st == QMC_OK) st = qmc_sweep(s, trial_sweeps - 1, nullptr);
+    if (st == QMC_OK) st = qmc_kernel_timing(s, 0, &ms, &cnt, 1);
+    if (st != QMC_OK) {
+      s->timing = timing_was;
+      s->gather_lanes_log2 = was;
+      return st;
+    }
+    const double per = ms / (double)(cnt > 0 ? cnt : 1);
+    if (best < 0 || per < best_t) { best = tl; best_t = per; }
+  }
+  s->gather_lanes_log2 = best;
+  s->timing = timing_was;
+  if (best_lanes_log2) *best_lanes_log2 = best;
+  if (best_ms) *best_ms = best_t;
+  return QMC_OK;
+}
+
 qmc_status qmc_autotune_delay(qmc_system s, const int32_t* ranks, int32_t n_ranks, int32_t trial_sweeps,
                               int32_t* best_rank, double* best_ms) {
   if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
@@ -969,7 +1033,7 @@ qmc_status batch_build(qmc_batch b) {
     d.K = s->d.delay_rank;
     const int nmax = s->P.n_up > s->P.n_dn ? s->P.n_up : s->P.n_dn;
     d.ldl = nmax | 1;
-    d.tpi_log2 = gather_tpi_log2(s->P.S / V);
+    d.tpi_log2 = s->gather_lanes_log2 >= 0 ? s->gather_lanes_log2 : gather_tpi_log2(s->P.S / V);
     const long items = (long)s->P.W * s->P.N;
     const long per_block = kBlock >> d.tpi_log2;
     for (long it = 0; it < items; it += per_block) g.push_back(make_int2(i, (int)it));

@@ -37,7 +37,7 @@ __host__ __device__ inline ChainLayout chain_layout(int N, int nmax, int n_ions,
   L.pos = o; o += sizeof(double) * 3 * N;
   L.prop = o; o += sizeof(double) * 4 * nmax;
   L.ions = o; o += (n_ions <= kLdsIons) ? sizeof(double) * 4 * n_ions : 0;
-  L.red = o; o += sizeof(double) * 5 * kWaves;
+  L.red = o; o += sizeof(double) * 7 * kWaves;
   o = (o + 15) & ~size_t(15);
   L.vbuf = o; o += ts * (size_t)2 * rows_per_chunk * nmax;
   o = (o + 15) & ~size_t(15);
@@ -173,10 +173,15 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, in
 
       // determinant ratio (partial sums over this thread's own row elements)
       T rpart = T(0);
+      double mpart = 0.0;   // mixed: sum |v_j B[j][k]|, the magnitude that bounds R's rounding
 #pragma unroll
       for (int c = 0; c < VPT; ++c) {
         const int j = tid + c * kBlock;
-        if (j < n) rpart += vrow_l[j] * Bm[(size_t)j * ldb + k];
+        if (j < n) {
+          const T vb = vrow_l[j] * Bm[(size_t)j * ldb + k];
+          rpart += vb;
+          if (sizeof(T) == 4) mpart += fabs((double)vb);
+        }
       }
       // Jastrow change (partial sums)
       const double xo = spos[3 * i], yo = spos[3 * i + 1], zo = spos[3 * i + 2];
@@ -204,22 +209,28 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, in
       }
       // block reduction in a fixed order (bitwise repeatable)
       const double ra = wave_sum_dpp((double)rpart), rb = wave_sum_dpp(dj);
-      double* rr = red + parity * 2 * kWaves;
-      if (lane == 0) { rr[wave] = ra; rr[kWaves + wave] = rb; }
+      const double rm = sizeof(T) == 4 ? wave_sum_dpp(mpart) : 0.0;
+      double* rr = red + parity * 3 * kWaves;
+      if (lane == 0) { rr[wave] = ra; rr[kWaves + wave] = rb; rr[2 * kWaves + wave] = rm; }
       block_sync<BLDS>();
-      double Rd = 0.0, dJ = 0.0;
+      double Rd = 0.0, dJ = 0.0, Sm = 0.0;
 #pragma unroll
-      for (int q = 0; q < kWaves; ++q) { Rd += rr[q]; dJ += rr[kWaves + q]; }
+      for (int q = 0; q < kWaves; ++q) { Rd += rr[q]; dJ += rr[kWaves + q]; Sm += rr[2 * kWaves + q]; }
       parity ^= 1;
       const T R = (T)Rd;
       const double ej = exp(2.0 * dJ);
       const double p32 = (double)R * (double)R * ej;
       double Rlog = (double)R;
       bool accept;
-      if (sizeof(T) == 4 && fabs(u - p32) <= P.tie_guard * p32) {
+      // guard band: the relative tie guard widened by a bound on the FP32 rounding of R
+      // (n + 1 unit roundoffs of the magnitude of its terms): heavy cancellation re-decides
+      const double band = sizeof(T) == 4
+          ? P.tie_guard + 2.0 * (n + 1) * 5.9604644775390625e-08 * Sm / fabs((double)R) + 2.4e-7
+          : 0.0;
+      if (sizeof(T) == 4 && fabs(u - p32) <= band * p32) {
         // near tie in FP32: decide again with an FP64 ratio (uniform branch)
         const double* v64 = Wk.val64 + ((size_t)(1 - scur[k]) * P.W * N + item0 + k) * P.S;
-        Rlog = refined_ratio<T>(P, Wk, Bm, ldb, n, item0, scur, v64, k, sgx, sgr, red + 2 * 2 * kWaves, tid);
+        Rlog = refined_ratio<T>(P, Wk, Bm, ldb, n, item0, scur, v64, k, sgx, sgr, red + 2 * 3 * kWaves, tid);
         accept = u < Rlog * Rlog * ej;
         ++nguard;
       } else {

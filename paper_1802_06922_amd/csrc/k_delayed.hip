@@ -39,7 +39,7 @@ constexpr int kMaxWindow = 64;
 constexpr int kLdsIonsD = 256;
 
 struct DLayout {
-  size_t pos, prop, ions, red, gold, gdiff, cur, acc, plist, qlist, vwin, ywin, zwin, gx, gr, grow, b,
+  size_t pos, prop, ions, red, rmag, gold, gdiff, cur, acc, plist, qlist, vwin, ywin, zwin, gx, gr, grow, b,
       total;
 };
 
@@ -55,6 +55,7 @@ __host__ __device__ inline DLayout dlayout(int N, int nmax, int n_ions, int ldl,
   L.prop = o; o += sizeof(double) * 4 * nmax;
   L.ions = o; o += (n_ions <= kLdsIonsD) ? sizeof(double) * 4 * n_ions : 0;
   L.red = o; o += sizeof(double) * kBlock;
+  L.rmag = o; o += (ts == 4) ? sizeof(double) * kBlock : 0;   // mixed: |v| . |B0[:, k]| partials
   L.gold = o; o += sizeof(double) * K * K;
   L.gdiff = o; o += sizeof(double) * K * K;
   L.cur = o; o += nmax;
@@ -249,13 +250,16 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
   double* sion = reinterpret_cast<double*>(smem + lay.ions);
   const double* ions = ions_lds ? sion : P.ions;
   double* red = reinterpret_cast<double*>(smem + lay.red);
+  double* rmag = reinterpret_cast<double*>(smem + lay.rmag);
   double* gold = reinterpret_cast<double*>(smem + lay.gold);
   double* gdiff = reinterpret_cast<double*>(smem + lay.gdiff);
   uint8_t* scur = smem + lay.cur;
   uint8_t* sacc = smem + lay.acc;
   int* plist = reinterpret_cast<int*>(smem + lay.plist);
   int* qlist = reinterpret_cast<int*>(smem + lay.qlist);
-  T* yk = reinterpret_cast<T*>(smem + lay.gold);   // (B): the window block, in the storage of gold
+  // (B): the window block, in FP64 (also in mixed precision: the K x K elimination and the
+  // capacitance inverse are small, and FP32 rounding there compounds over the window)
+  double* yk = reinterpret_cast<double*>(smem + lay.gold);
   T* vwin = reinterpret_cast<T*>(smem + lay.vwin);
   T* ywin = reinterpret_cast<T*>(smem + lay.ywin);
   T* ubuf = ywin;
@@ -341,6 +345,15 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
           }
         }
         red[tid] = part;
+        if (sizeof(T) == 4) {
+          // magnitude of the ratio's terms, sum_l |v_l| |B0[l][k]|, which bounds the FP32
+          // rounding of the ratio (mixed precision guard band)
+          double mag = 0.0;
+          if (q < Kw)
+            for (int l = s; l < n; l += tpq)
+              mag += fabs((double)vwin[(size_t)q * nP + l]) * fabs((double)Bm[(size_t)l * ldb + k0 + q]);
+          rmag[tid] = mag;
+        }
       }
       for (int idx = tid; idx < Kw * Kw; idx += kBlock) {
         const int q = idx / Kw, q2 = idx - q * Kw;
@@ -370,9 +383,11 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
       // window's own columns), so each ratio is read, not recomputed: R_q = yk[q][q].
       if (wave == seq_wave) {
         if (lane == 0) sm_stop = -1;
-        double Fq = 0.0;
+        double Fq = 0.0, Sq = 0.0, Eq = 0.0;
         if (lane < Kw) {
           for (int s = 0; s < tpq; ++s) Fq += red[lane * tpq + s];
+          if (sizeof(T) == 4)
+            for (int s = 0; s < tpq; ++s) Sq += rmag[lane * tpq + s];
           for (int j = 0; j < Kw; ++j) {
             const double gj = gold[lane * K + j];
             Fq += j != lane ? gj : 0.0;
@@ -380,31 +395,42 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
         }
         wave_sync_lds();   // gold is consumed: its storage takes yk
         if (lane < Kw)
-          for (int j = 0; j < Kw; ++j) yk[lane * K + j] = ywin[(size_t)lane * nP + k0 + j];
+          for (int j = 0; j < Kw; ++j) yk[lane * K + j] = (double)ywin[(size_t)lane * nP + k0 + j];
         wave_sync_lds();
         int m = 0;
         for (int q = 0; q < Kw; ++q) {
           const int kq = k0 + q, iq = off + kq;
-          const T R = yk[q * K + q];
+          const double R = yk[q * K + q];
           const double dJ = readlane_d(Fq, q);
           const double u = sprop[4 * kq + 3];
           // mixed precision: an FP32 exponential is well inside the guard band
           const double ex = sizeof(T) == 4 ? (double)__expf((float)(2.0 * dJ)) : exp(2.0 * dJ);
-          const double p32 = (double)R * (double)R * ex;
-          if (sizeof(T) == 4 && fabs(u - p32) <= P.tie_guard * p32) {
+          const double p32 = R * R * ex;
+          // guard band: the relative tie guard, widened by a bound on the FP32 rounding of R:
+          // n + 1 unit roundoffs (the length-n product and the cast of B0) of the magnitude of
+          // the terms that formed R, sum_l |v_l B0[l][k]| plus the eliminated window terms --
+          // ratios that cancel heavily are re-decided in FP64
+          double band = P.tie_guard;
+          if (sizeof(T) == 4) {
+            const double uf = 5.9604644775390625e-08;   // 2^-24
+            const double err = (n + 1) * uf * (readlane_d(Sq, q) + readlane_d(Eq, q));
+            band += 2.0 * err / fabs(R) + 4.0 * uf;
+          }
+          if (sizeof(T) == 4 && fabs(u - p32) <= band * p32) {
             // near tie in FP32: end the window here; the move is re-decided in FP64 below
             if (lane == 0) { sm_stop = q; sm_dj = dJ; }
             break;
           }
           if (u < p32) {
             if (lane > q && lane < Kw) {
-              const T f = yk[lane * K + q] / R;
+              const double f = yk[lane * K + q] / R;
+              if (sizeof(T) == 4) Eq += fabs(f * yk[q * K + lane]);
               // eight columns at a time: all loads before the stores, so they overlap.  The
               // loads are unconditional (a guarded load becomes a branch of its own): columns
               // past Kw read at most 7 entries beyond the row, inside the LDS block that
               // follows yk, and are never stored.
               for (int j0 = q + 1; j0 < Kw; j0 += 8) {
-                T pv[8], rv[8];
+                double pv[8], rv[8];
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                   pv[e] = yk[q * K + j0 + e];
@@ -427,8 +453,8 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
             }
             ++m;
             ++nacc;
-            logd += log(fabs((double)R));
-            if (R < T(0)) sgn = -sgn;
+            logd += log(fabs(R));
+            if (R < 0.0) sgn = -sgn;
           } else if (lane == 0) {
             sacc[kq] = 0;
           }
@@ -445,32 +471,32 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
       const int m = sm_m;
       if (m > 0) {
         const int mP = (m + 3) & ~3;
-        T* ga = reinterpret_cast<T*>(smem + lay.gold);
-        T* gb = reinterpret_cast<T*>(smem + lay.gdiff);
+        double* ga = reinterpret_cast<double*>(smem + lay.gold);
+        double* gb = reinterpret_cast<double*>(smem + lay.gdiff);
         for (int idx = tid; idx < m * m; idx += kBlock) {
           const int a = idx / m, b = idx - a * m;
-          ga[a * K + b] = ywin[(size_t)qlist[a] * nP + plist[b]];
+          ga[a * K + b] = (double)ywin[(size_t)qlist[a] * nP + plist[b]];
         }
         __syncthreads();
         for (int pv = 0; pv < m; ++pv) {
-          const T inv = T(1) / ga[pv * K + pv];
+          const double inv = 1.0 / ga[pv * K + pv];
           for (int idx = tid; idx < m * m; idx += kBlock) {
             const int i = idx / m, j = idx - i * m;
-            const T aip = ga[i * K + pv], apj = ga[pv * K + j];
+            const double aip = ga[i * K + pv], apj = ga[pv * K + j];
             gb[i * K + j] = i == pv ? (j == pv ? inv : apj * inv)
                                     : (j == pv ? -aip * inv : ga[i * K + j] - aip * apj * inv);
           }
           __syncthreads();
-          T* t = ga; ga = gb; gb = t;
+          double* t = ga; ga = gb; gb = t;
         }
-        const T* cinv = ga;
+        const double* cinv = ga;
         for (int idx = tid; idx < mP * n; idx += kBlock) {
           const int r = idx / n, c = idx - r * n;
-          T acc = T(0);
+          double acc = 0.0;
           if (r < m)
             for (int l = 0; l < m; ++l)
-              acc += cinv[r * K + l] * (ywin[(size_t)qlist[l] * nP + c] - (c == plist[l] ? T(1) : T(0)));
-          zwin[(size_t)r * nP + c] = acc;
+              acc += cinv[r * K + l] * ((double)ywin[(size_t)qlist[l] * nP + c] - (c == plist[l] ? 1.0 : 0.0));
+          zwin[(size_t)r * nP + c] = (T)acc;
         }
         __syncthreads();   // Y is dead from here: U takes its storage
         for (int idx = tid; idx < n * mP; idx += kBlock) {

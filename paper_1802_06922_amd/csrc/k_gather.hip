@@ -192,13 +192,16 @@ __global__ __launch_bounds__(kBlock) void k_eval_points(SysParams P, const T* __
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_init_positions(SysParams P, double* __restrict__ pos) {
+// attempt (nullable: all 0) numbers each walker's redraws; it takes the counter's sweep slot.
+__global__ __launch_bounds__(kBlock) void k_init_positions(SysParams P, double* __restrict__ pos,
+                                                           const uint32_t* __restrict__ attempt) {
   const long item = (long)blockIdx.x * kBlock + threadIdx.x;
   if (item >= (long)P.W * P.N) return;
   const int w = (int)(item / P.N), i = (int)(item % P.N);
+  const uint32_t att = attempt ? attempt[w] : 0u;
   double a0, a1, b0, b1;
-  uniform_pair(P, kInit, 0, (uint32_t)w, 0u, (uint32_t)i, a0, a1);
-  uniform_pair(P, kInit, 1, (uint32_t)w, 0u, (uint32_t)i, b0, b1);
+  uniform_pair(P, kInit, 0, (uint32_t)w, att, (uint32_t)i, a0, a1);
+  uniform_pair(P, kInit, 1, (uint32_t)w, att, (uint32_t)i, b0, b1);
   pos[item * 3 + 0] = wrap_cell(P.L * a0, P.L);
   pos[item * 3 + 1] = wrap_cell(P.L * a1, P.L);
   pos[item * 3 + 2] = wrap_cell(P.L * b0, P.L);
@@ -211,9 +214,10 @@ int gather_tpi_log2(int nvec) {
 }
 
 template <typename T>
-hipError_t launch_gather(const SysParams& P, const Walkers<T>& Wk, const T* table, int mode, hipStream_t st) {
+hipError_t launch_gather(const SysParams& P, const Walkers<T>& Wk, const T* table, int mode, hipStream_t st,
+                         int lanes_log2) {
   const int nvec = P.S / VecOf<T>::V;
-  const int tl = gather_tpi_log2(nvec);
+  const int tl = lanes_log2 >= 0 && lanes_log2 <= 6 ? lanes_log2 : gather_tpi_log2(nvec);
   const long items = (long)P.W * P.N;
   const long per_block = kBlock >> tl;
   const unsigned blocks = (unsigned)((items + per_block - 1) / per_block);
@@ -242,17 +246,17 @@ hipError_t launch_eval_points(const SysParams& P, const T* table, const double* 
   return hipGetLastError();
 }
 
-hipError_t launch_init_positions(const SysParams& P, double* pos, hipStream_t st) {
+hipError_t launch_init_positions(const SysParams& P, double* pos, const uint32_t* attempt, hipStream_t st) {
   const long items = (long)P.W * P.N;
   const unsigned blocks = (unsigned)((items + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_init_positions, dim3(blocks), dim3(kBlock), 0, st, P, pos);
+  hipLaunchKernelGGL(k_init_positions, dim3(blocks), dim3(kBlock), 0, st, P, pos, attempt);
   return hipGetLastError();
 }
 
 template hipError_t launch_gather<double>(const SysParams&, const Walkers<double>&, const double*, int,
-                                          hipStream_t);
+                                          hipStream_t, int);
 template hipError_t launch_gather<float>(const SysParams&, const Walkers<float>&, const float*, int,
-                                         hipStream_t);
+                                         hipStream_t, int);
 template hipError_t launch_gather_batched<double>(const SysDev<double>*, const int2*, int, hipStream_t);
 template hipError_t launch_gather_batched<float>(const SysDev<float>*, const int2*, int, hipStream_t);
 template hipError_t launch_eval_points<double>(const SysParams&, const double*, const double*, int,

@@ -281,6 +281,54 @@ hipError_t launch_refine_batched(const SysDev<T>* sd, const int2* fmap, int n_wa
 }
 
 template hipError_t launch_refine<float>(const SysParams&, const Walkers<float>&, double*, hipStream_t);
+
+// max |I - A fl32(B)| of one (walker, spin), for the acceptance test of initial configurations.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_inverse_residual(SysParams P, Walkers<T> Wk, double* out) {
+  __shared__ double sL[kTile * kLs];
+  __shared__ double sR[kChunk * kRs];
+  __shared__ const T* arow[kMaxSpin];
+  __shared__ double wmax[kWaves];
+  const int w = blockIdx.x >> 1, sp = blockIdx.x & 1, tid = threadIdx.x;
+  const int n = sp ? P.n_dn : P.n_up, off = sp ? P.n_up : 0;
+  if (n == 0) {
+    if (tid == 0) out[2 * w + sp] = 0.0;
+    return;
+  }
+  const int N = P.N;
+  const T* B = Wk.binv + (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0);
+  __shared__ const double* arow64[kMaxSpin];
+  for (int i = tid; i < n; i += kBlock) {
+    const size_t item = (size_t)w * N + off + i;
+    const size_t row = (size_t)Wk.cur[item] * P.W * N + item;
+    arow64[i] = Wk.val64 ? Wk.val64 + row * P.S : nullptr;
+    arow[i] = Wk.vgl + row * kComp * P.S;
+  }
+  __syncthreads();
+  double worst = 0.0;
+  gemm64(n, [&](int i, int l) { return arow64[i] ? arow64[i][l] : (double)arow[i][l]; },
+         [&](int l, int k) { return (double)(float)B[(size_t)l * n + k]; },
+         [&](int i, int k, double c) { worst = fmax(worst, fabs((i == k ? 1.0 : 0.0) - c)); }, sL, sR);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) worst = fmax(worst, __shfl_xor(worst, o, 64));
+  if ((tid & 63) == 0) wmax[tid >> 6] = worst;
+  __syncthreads();
+  if (tid == 0) {
+    double m = wmax[0];
+    for (int q = 1; q < kWaves; ++q) m = fmax(m, wmax[q]);
+    out[2 * w + sp] = m;
+  }
+}
+
+template <typename T>
+hipError_t launch_inverse_residual(const SysParams& P, const Walkers<T>& Wk, double* out, hipStream_t st) {
+  if (P.n_up > kMaxSpin || P.n_dn > kMaxSpin) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_inverse_residual<T>, dim3(2 * P.W), dim3(kBlock), 0, st, P, Wk, out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_inverse_residual<double>(const SysParams&, const Walkers<double>&, double*, hipStream_t);
+template hipError_t launch_inverse_residual<float>(const SysParams&, const Walkers<float>&, double*, hipStream_t);
 template hipError_t launch_refine_batched<float>(const SysDev<float>*, const int2*, int, hipStream_t);
 
 template <typename T>

@@ -51,8 +51,10 @@ struct SysDev {
 // the sweep in *Wk.sweep_ctr and evaluate all orbitals there (mode 0, written
 // to the buffer that does not hold the current row), or evaluate at the
 // current position (mode 1, written to buffer 0 and cur reset).
+// lanes_log2: lanes per proposal (log2, 0..6); negative = the default for the orbital count.
 template <typename T>
-hipError_t launch_gather(const SysParams& P, const Walkers<T>& Wk, const T* table, int mode, hipStream_t st);
+hipError_t launch_gather(const SysParams& P, const Walkers<T>& Wk, const T* table, int mode, hipStream_t st,
+                         int lanes_log2 = -1);
 // Several systems' proposals in one launch; bmap[b] = (system, first item of block b).
 template <typename T>
 hipError_t launch_gather_batched(const SysDev<T>* sd, const int2* bmap, int n_blocks, hipStream_t st);
@@ -82,8 +84,16 @@ template <typename T>
 hipError_t launch_chain_delayed_batched(const SysDev<T>* sd, const int2* bmap, int n_blocks, bool b_in_lds,
                                         int use_mfma, size_t lds, hipStream_t st);
 
-// Initial positions from the INIT stream.
-hipError_t launch_init_positions(const SysParams& P, double* pos, hipStream_t st);
+// Initial positions from the INIT stream; attempt[W] (nullable) numbers each walker's redraw.
+hipError_t launch_init_positions(const SysParams& P, double* pos, const uint32_t* attempt, hipStream_t st);
+// Initial configurations: initial draws are redrawn while a Slater matrix is singular or the
+// single-precision rounding of its inverse leaves a residual above kInitResidual.
+constexpr int kInitAttempts = 16;
+constexpr double kInitResidual = 1e-5;
+// out[2w + sp] = max_{i,k} |delta_ik - sum_l A[i][l] fl32(B[l][k])| (FP64 products), A from the
+// current value rows (val64 when present), B the current inverse.
+template <typename T>
+hipError_t launch_inverse_residual(const SysParams& P, const Walkers<T>& Wk, double* out, hipStream_t st);
 
 // Full FP64 inverse of every Slater matrix from the current value rows
 // (Gauss-Jordan with partial pivoting); scratch: W * bstride doubles.

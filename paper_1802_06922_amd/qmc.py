@@ -28,7 +28,7 @@ EXPORTS = [
     "qmc_eval_spo_vgl", "qmc_set_timing", "qmc_kernel_timing", "qmc_destroy_system",
     "qmc_last_error", "qmc_estimate_device_bytes", "qmc_set_delay_rank", "qmc_autotune_delay",
     "qmc_get_last_energies", "qmc_batch_create", "qmc_batch_sweep", "qmc_batch_set_graph",
-    "qmc_batch_timing", "qmc_batch_destroy", "qmc_max_delay_rank",
+    "qmc_batch_timing", "qmc_batch_destroy", "qmc_max_delay_rank", "qmc_autotune_gather",
 ]
 
 
@@ -94,6 +94,7 @@ def load_library():
     L.qmc_batch_set_graph.argtypes = [vp, C.c_int32]
     L.qmc_batch_timing.argtypes = [vp, dp, C.POINTER(C.c_int64), C.c_int32]
     L.qmc_batch_destroy.argtypes = [vp]
+    L.qmc_autotune_gather.argtypes = [vp, C.c_int32, ip, dp]
     L.qmc_max_delay_rank.argtypes = [C.POINTER(Desc)]
     L.qmc_max_delay_rank.restype = C.c_int32
     for name in EXPORTS:
@@ -277,6 +278,13 @@ class System:
                                               C.byref(ms)))
         self.wl.delay_rank = int(best.value)
         return int(best.value), float(ms.value)
+
+    def autotune_gather(self, trial_sweeps: int = 3):
+        """Choose the gather's lanes per proposal by timing; returns (log2 lanes, gather ms)."""
+        tl = C.c_int32(0)
+        ms = C.c_double(0.0)
+        self._check(self.L.qmc_autotune_gather(self.h, int(trial_sweeps), C.byref(tl), C.byref(ms)))
+        return tl.value, ms.value
 
     def last_energies(self) -> np.ndarray:
         e = np.zeros((self.W, 4))

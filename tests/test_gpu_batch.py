@@ -89,3 +89,22 @@ def test_autotune_keeps_the_chain_exact(gpu, orc):
     assert np.array_equal(bits, ref["accept"][:, -1])
     np.testing.assert_allclose(pos, ref["final_pos"], atol=1e-11)
     np.testing.assert_allclose(ld, ref["logdet"], atol=1e-9)
+
+
+def test_gather_autotune_keeps_rows_bitwise(gpu):
+    """Every gather width gives the same orbital rows: a tuned run and an untuned run of the
+    same number of sweeps coincide bit for bit."""
+    wl = qi.solid(40, 14, n_walkers=16, n_sweeps=1, precision="mixed", table_dtype=np.float32,
+                  delay_rank=8, recompute_period=0)
+    s = gpu.System(wl)
+    tl, ms = s.autotune_gather(trial_sweeps=2)
+    assert 0 <= tl <= 6 and ms > 0
+    s.sweep(2)
+    _, n_sweeps = s.counters()
+    tuned = (s.get_walkers()[0], s.measure())
+    s.close()
+    s = gpu.System(wl)
+    s.sweep(int(n_sweeps))
+    ref = (s.get_walkers()[0], s.measure())
+    s.close()
+    assert np.array_equal(tuned[0], ref[0]) and np.array_equal(tuned[1], ref[1])

@@ -127,3 +127,30 @@ def test_heg14_energy_components(orc):
     E = r["energies"]
     assert np.all(E[..., 2] == 0) and np.all(E[..., 3] == 0)    # no ions
     assert np.all(E[..., 1] < 0) and np.all(E[..., 0] > 0)
+
+
+def test_initial_configurations_reject_ill_conditioned_draws(orc):
+    """Initial positions are uniform draws from the INIT stream; a walker's draw is redrawn
+    (next attempt) while the single-precision rounding of an inverse leaves a residual above
+    1e-5.  Walker 114 of the 384-electron system draws an up-spin matrix of condition ~1e8
+    first; walker 0 keeps its first draw."""
+    wl = qi.mixed384()
+    osys = orc.OracleSystem(wl)
+    out = osys.run([114, 0], 0, measure_every=0)
+    n = wl.n_up
+
+    def draw(w, att):
+        return np.array([orc.init_position(wl.seed, w, i, wl.L, att) for i in range(wl.n_elec)])
+
+    def residual(P):
+        A = np.array([osys.spo_vgl(P[i])[0] for i in range(wl.n_elec)])
+        return max(orc.fp32_inverse_residual(A[:n], np.linalg.inv(A[:n])),
+                   orc.fp32_inverse_residual(A[n:], np.linalg.inv(A[n:])))
+
+    assert residual(draw(114, 0)) > orc.INIT_RESIDUAL
+    kept = [a for a in range(orc.INIT_ATTEMPTS) if np.array_equal(out["final_pos"][0], draw(114, a))]
+    assert kept and kept[0] >= 1
+    assert residual(out["final_pos"][0]) <= orc.INIT_RESIDUAL
+    for a in range(kept[0]):   # every earlier draw fails the test
+        assert residual(draw(114, a)) > orc.INIT_RESIDUAL
+    assert np.array_equal(out["final_pos"][1], draw(0, 0))
