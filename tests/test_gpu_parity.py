@@ -333,3 +333,32 @@ def test_mixed384_full_run_sampled_walkers(gpu, orc):
     # log|D| is rebuilt in FP64 at sweep 448 and then accumulates ~5e3 logs of FP32 ratios
     # (relative error ~1e-6 each) per spin block
     np.testing.assert_allclose(ld[sample], ref["logdet"], atol=1e-3)
+
+
+@pytest.mark.parametrize("K", [16, 32])
+def test_mixed384_all_walkers_take_the_fp64_decisions(gpu, K):
+    """Every walker of the 384-electron system (1024 walkers, 12 sweeps): the mixed path takes
+    exactly the FP64 path's decisions (the FP64 path is the oracle's, see above) and its local
+    energies stay within 1e-5 relative."""
+    import dataclasses
+    mixed = qi.mixed384()
+    fp64 = dataclasses.replace(mixed, precision="fp64", coefs=mixed.coefs.astype(np.float64),
+                               recompute_period=0, name="solid384_fp64")
+    out = {}
+    for tag, wl in (("mixed", mixed), ("fp64", fp64)):
+        wl.delay_rank = K
+        print(f"[mixed-vs-fp64] {tag} K={K}", flush=True)
+        s = gpu.System(wl)
+        bits = []
+        for _ in range(12):
+            s.sweep(1)
+            bits.append(s.accept_log())
+        out[tag] = (np.stack(bits), s.measure(), s.get_walkers()[0])
+        s.close()
+    assert np.array_equal(out["mixed"][0], out["fp64"][0]), \
+        f"{int((out['mixed'][0] != out['fp64'][0]).sum())} decisions differ"
+    assert np.array_equal(out["mixed"][2], out["fp64"][2])
+    rel = _rel(out["mixed"][1], out["fp64"][1])
+    print(f"[mixed-vs-fp64] rel energy difference max {rel.max():.2e} p99 {np.percentile(rel, 99):.2e}",
+          flush=True)
+    assert rel.max() < MIXED_TOL
