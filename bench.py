@@ -88,6 +88,8 @@ def main(argv=None) -> int:
     ap.add_argument("--sweep-scale", type=float, default=0.05, help="served: scale of each request's sweeps")
     ap.add_argument("--no-graph", action="store_true", help="batched/served: no HIP graph replay")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--gather-lanes", type=int, default=None,
+                    help="gather lanes per proposal, log2 (default: autotuned before the timed region)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the mixed-vs-FP64 comparison on the 384-electron system")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -112,7 +114,7 @@ def main(argv=None) -> int:
     if args.mode == "copy":
         return copy_reference()
     wl = qi.WORKLOADS[args.workload]()
-    r = run_single(wl, args.steps, args.warmup, args.delay)
+    r = run_single(wl, args.steps, args.warmup, args.delay, args.gather_lanes)
     W, N = r["walkers"], wl.n_elec
     kt = r["kt"]
     b = wl.coefs.dtype.itemsize
@@ -155,7 +157,7 @@ def main(argv=None) -> int:
     return 0
 
 
-def run_single(wl, steps: int, warmup: int, delay, quiet: bool = False):
+def run_single(wl, steps: int, warmup: int, delay, lanes=None):
     """Steps of (sweep + local energy) of one system; the delay rank is autotuned when not given
     (the trial sweeps are ordinary sweeps, before the timed region)."""
     import torch
@@ -165,7 +167,11 @@ def run_single(wl, steps: int, warmup: int, delay, quiet: bool = False):
         wl.delay_rank = delay
     print(f"[bench] building {wl.name}", file=sys.stderr, flush=True)
     s = System(wl)
-    lanes_log2, _ = s.autotune_gather(trial_sweeps=3)
+    if lanes is None:
+        lanes_log2, _ = s.autotune_gather(trial_sweeps=3)
+    else:
+        s.set_gather_lanes(lanes)
+        lanes_log2 = lanes
     if delay is None:
         K, _ = s.autotune_delay(ranks=(1, 8, 16, 32, 64), trial_sweeps=3)
         print(f"[bench] {wl.name}: delay rank {K}, gather lanes 2^{lanes_log2} (autotuned)",
@@ -215,12 +221,16 @@ def compare_precisions(args):
                                recompute_period=0, name="solid384_fp64")
     out = {"workload": "384 electrons, 192 orbitals, 64^3 table, 96 ions, 1024 walkers"}
     runs = {}
-    for tag, wl in (("mixed", mixed), ("fp64", fp64)):
-        r = run_single(wl, steps, 1, None)
+    plain = dataclasses.replace(fp64, name="solid384_fp64_plain")
+    # mixed and FP64 with their autotuned delay ranks, and the plain FP64 sweep
+    # (Sherman-Morrison updates, rank 1)
+    for tag, wl, K in (("mixed", mixed, None), ("fp64", fp64, None), ("fp64_plain", plain, 1)):
+        r = run_single(wl, steps, 1, K)
         runs[tag] = r
         out[tag] = {"moves_per_s": r["value"], "ms_per_step": r["ms_per_step"], "delay_rank": r["delay_rank"],
                     "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in r["kt"].items()}}
     out["mixed_over_fp64"] = out["mixed"]["moves_per_s"] / out["fp64"]["moves_per_s"]
+    out["mixed_over_fp64_plain"] = out["mixed"]["moves_per_s"] / out["fp64_plain"]["moves_per_s"]
     # both ran the same number of sweeps from the same start; the mixed path takes the FP64
     # decisions, so the walkers coincide and the last local energies compare one to one
     same = bool(np.array_equal(runs["mixed"]["positions"], runs["fp64"]["positions"]))

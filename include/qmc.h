@@ -210,6 +210,10 @@ qmc_status qmc_set_delay_rank(qmc_system s, int32_t delay_rank);
  * milliseconds.  Errors: STATE before init_walkers or without a table. */
 qmc_status qmc_autotune_gather(qmc_system s, int32_t trial_sweeps, int32_t* best_lanes_log2, double* best_ms);
 
+/* Set the gather's lanes per proposal directly: lanes_log2 in 0..6, or -1 for
+ * the default of the orbital count.  Errors: ARG outside that range. */
+qmc_status qmc_set_gather_lanes(qmc_system s, int32_t lanes_log2);
+
 /* Autotuner: runs trial_sweeps sweeps (>= 2; the first is not timed) with each
  * candidate delay rank, times the move-chain kernel with HIP events, keeps the
  * fastest and writes it to best_rank (best_ms: its mean chain milliseconds per

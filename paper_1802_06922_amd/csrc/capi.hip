@@ -859,6 +859,13 @@ qmc_status qmc_set_delay_rank(qmc_system s, int32_t delay_rank) {
   return QMC_OK;
 }
 
+qmc_status qmc_set_gather_lanes(qmc_system s, int32_t lanes_log2) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (lanes_log2 < -1 || lanes_log2 > 6) return fail(s, QMC_ERR_ARG, "lanes_log2 must be -1 or 0..6");
+  s->gather_lanes_log2 = lanes_log2;
+  return QMC_OK;
+}
+
 qmc_status qmc_autotune_gather(qmc_system s, int32_t trial_sweeps, int32_t* best_lanes_log2, double* best_ms) {
   if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
   if (!s->has_walkers) return fail(s, QMC_ERR_STATE, "init_walkers first");

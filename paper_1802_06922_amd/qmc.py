@@ -29,6 +29,7 @@ EXPORTS = [
     "qmc_last_error", "qmc_estimate_device_bytes", "qmc_set_delay_rank", "qmc_autotune_delay",
     "qmc_get_last_energies", "qmc_batch_create", "qmc_batch_sweep", "qmc_batch_set_graph",
     "qmc_batch_timing", "qmc_batch_destroy", "qmc_max_delay_rank", "qmc_autotune_gather",
+    "qmc_set_gather_lanes",
 ]
 
 
@@ -95,6 +96,7 @@ def load_library():
     L.qmc_batch_timing.argtypes = [vp, dp, C.POINTER(C.c_int64), C.c_int32]
     L.qmc_batch_destroy.argtypes = [vp]
     L.qmc_autotune_gather.argtypes = [vp, C.c_int32, ip, dp]
+    L.qmc_set_gather_lanes.argtypes = [vp, C.c_int32]
     L.qmc_max_delay_rank.argtypes = [C.POINTER(Desc)]
     L.qmc_max_delay_rank.restype = C.c_int32
     for name in EXPORTS:
@@ -285,6 +287,9 @@ class System:
         ms = C.c_double(0.0)
         self._check(self.L.qmc_autotune_gather(self.h, int(trial_sweeps), C.byref(tl), C.byref(ms)))
         return tl.value, ms.value
+
+    def set_gather_lanes(self, lanes_log2: int):
+        self._check(self.L.qmc_set_gather_lanes(self.h, int(lanes_log2)))
 
     def last_energies(self) -> np.ndarray:
         e = np.zeros((self.W, 4))
