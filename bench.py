@@ -127,7 +127,7 @@ def main(argv=None) -> int:
         "value": r["value"],
         "unit": "electron-moves/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": r["steps"],
         "warmup": args.warmup,
         "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
@@ -145,6 +145,7 @@ def main(argv=None) -> int:
                      "bytes_per_launch": bytes_per_move * W * N,
                      "avg_launch_ms": avg_gather_s * 1e3},
         "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
+        "rebuilds_in_timed_steps": r["rebuilds"],
         "sweep_only_moves_per_s": r["sweep_only_moves_per_s"],
         "mean_local_energy": r["mean_local_energy"],
     }
@@ -162,7 +163,10 @@ def run_single(wl, steps: int, warmup: int, delay, lanes=None):
     (the trial sweeps are ordinary sweeps, before the timed region)."""
     import torch
 
-    from paper_1802_06922_amd import KERNEL_CHAIN, KERNEL_GATHER, KERNEL_MEASURE, System
+    from paper_1802_06922_amd import KERNEL_CHAIN, KERNEL_GATHER, KERNEL_MEASURE, KERNEL_REBUILD, System
+    if wl.recompute_period > 0 and steps % wl.recompute_period:
+        # the timed window holds whole rebuild periods, so it pays for every FP64 rebuild
+        steps = (steps // wl.recompute_period + 1) * wl.recompute_period
     if delay is not None:
         wl.delay_rank = delay
     print(f"[bench] building {wl.name}", file=sys.stderr, flush=True)
@@ -185,7 +189,7 @@ def run_single(wl, steps: int, warmup: int, delay, lanes=None):
         s.measure(out=energies)
     torch.cuda.synchronize()
     s.set_timing(True)
-    for k in (KERNEL_GATHER, KERNEL_CHAIN, KERNEL_MEASURE):
+    for k in (KERNEL_GATHER, KERNEL_CHAIN, KERNEL_MEASURE, KERNEL_REBUILD):
         s.kernel_timing(k, reset=True)
     print(f"[bench] {wl.name}: timing {steps} steps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -197,12 +201,14 @@ def run_single(wl, steps: int, warmup: int, delay, lanes=None):
     dt = time.perf_counter() - t0
     kt = {name: s.kernel_timing(k) for name, k in
           (("gather", KERNEL_GATHER), ("chain", KERNEL_CHAIN), ("measure", KERNEL_MEASURE))}
+    rebuild = s.kernel_timing(KERNEL_REBUILD)
     e_host = energies.cpu().numpy()
     pos_host = s.get_walkers()[0]
     s.close()
     moves = W * N * steps
     sweep_ms = (kt["gather"][0] + kt["chain"][0]) / steps
-    return {"value": moves / dt, "ms_per_step": dt / steps * 1e3, "kt": kt, "walkers": W,
+    return {"value": moves / dt, "ms_per_step": dt / steps * 1e3, "kt": kt, "walkers": W, "steps": steps,
+            "rebuilds": {"launches": rebuild[1], "ms_per_launch": rebuild[0] / max(rebuild[1], 1)},
             "delay_rank": K, "gather_lanes_log2": lanes_log2, "sweep_only_moves_per_s": moves / (sweep_ms * steps / 1e3) if sweep_ms > 0 else None,
             "mean_local_energy": float(e_host.sum(axis=1).mean()), "energies": e_host, "positions": pos_host}
 
@@ -215,8 +221,8 @@ def compare_precisions(args):
     import numpy as np
 
     import qmc_inputs as qi
-    steps = max(3, args.steps // 6)
     mixed = qi.mixed384()
+    steps = mixed.recompute_period   # one rebuild period: the mixed run pays for its FP64 rebuild
     fp64 = dataclasses.replace(mixed, precision="fp64", coefs=mixed.coefs.astype(np.float64),
                                recompute_period=0, name="solid384_fp64")
     out = {"workload": "384 electrons, 192 orbitals, 64^3 table, 96 ions, 1024 walkers"}
@@ -228,6 +234,7 @@ def compare_precisions(args):
         r = run_single(wl, steps, 1, K)
         runs[tag] = r
         out[tag] = {"moves_per_s": r["value"], "ms_per_step": r["ms_per_step"], "delay_rank": r["delay_rank"],
+                    "steps": r["steps"], "rebuilds": r["rebuilds"],
                     "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in r["kt"].items()}}
     out["mixed_over_fp64"] = out["mixed"]["moves_per_s"] / out["fp64"]["moves_per_s"]
     out["mixed_over_fp64_plain"] = out["mixed"]["moves_per_s"] / out["fp64_plain"]["moves_per_s"]

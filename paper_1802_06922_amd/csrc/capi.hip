@@ -192,28 +192,41 @@ double erf_over_sqrt(double x) {
   return std::erf(r) / r;
 }
 
-// Coefficients of H on each interval: Chebyshev interpolation at kHDeg + 1 Chebyshev
-// points of the interval, rewritten in powers of the interval's scaled variable u.
-void h_table(std::vector<double>& tab) {
+// G(x) = erfc(sqrt x) / sqrt x, for images beyond the minimum one (x >= kGX0 > 0).
+double erfc_over_sqrt(double x) {
+  const double r = std::sqrt(x);
+  return std::erfc(r) / r;
+}
+
+// Coefficients of f on n_int intervals of width kHW from x0: Chebyshev interpolation at
+// kHDeg + 1 Chebyshev points of each interval, rewritten in powers of the interval's
+// scaled variable u.
+void fit_intervals(double (*f)(double), double x0, int n_int, double* tab) {
   constexpr int D = kHDeg, M = kHDeg + 1;
   double T[M][M] = {};   // T[j][m]: coefficient of u^m in the Chebyshev polynomial T_j
   T[0][0] = 1.0;
   if (D >= 1) T[1][1] = 1.0;
   for (int j = 2; j <= D; ++j)
     for (int m = 0; m <= D; ++m) T[j][m] = (m > 0 ? 2.0 * T[j - 1][m - 1] : 0.0) - T[j - 2][m];
-  tab.assign(kHTab, 0.0);
-  for (int i = 0; i < kHInt; ++i) {
-    const double xc = (i + 0.5) * kHW;
-    double f[M], a[M];
-    for (int k = 0; k < M; ++k) f[k] = erf_over_sqrt(xc + 0.5 * kHW * std::cos(kPi * (k + 0.5) / M));
+  for (int i = 0; i < n_int; ++i) {
+    const double xc = x0 + (i + 0.5) * kHW;
+    double fv[M], a[M];
+    for (int k = 0; k < M; ++k) fv[k] = f(xc + 0.5 * kHW * std::cos(kPi * (k + 0.5) / M));
     for (int j = 0; j < M; ++j) {
       double acc = 0.0;
-      for (int k = 0; k < M; ++k) acc += f[k] * std::cos(j * kPi * (k + 0.5) / M);
+      for (int k = 0; k < M; ++k) acc += fv[k] * std::cos(j * kPi * (k + 0.5) / M);
       a[j] = (j == 0 ? 1.0 : 2.0) * acc / M;
     }
+    for (int m = 0; m <= D; ++m) tab[(size_t)i * M + m] = 0.0;
     for (int j = 0; j < M; ++j)
       for (int m = 0; m <= D; ++m) tab[(size_t)i * M + m] += a[j] * T[j][m];
   }
+}
+
+void h_table(std::vector<double>& tab) {
+  tab.assign(kHTab, 0.0);
+  fit_intervals(erf_over_sqrt, 0.0, kHInt, tab.data());
+  fit_intervals(erfc_over_sqrt, kGX0, kGInt, tab.data() + (size_t)kHInt * (kHDeg + 1));
 }
 
 void ewald_setup(qmc_system s, std::vector<double>& gvec, std::vector<double>& sion,

@@ -129,6 +129,199 @@ __global__ __launch_bounds__(kBlock) void k_rebuild(SysParams P, Walkers<T> Wk, 
 }
 
 // ---------------------------------------------------------------------------
+// The same elimination with the matrix held in registers (spin blocks up to
+// kRegRebuildMax).  A 32 x 32 grid of threads covers the matrix cyclically:
+// thread (r0, c0), r0 = tid % 32, c0 = tid / 32, holds the entries
+// (r0 + 32 i, c0 + 32 j), i, j < R, so a column's owners are 32 consecutive
+// lanes (the pivot search is one half-wave reduction).  Rows are not swapped:
+// step k takes as pivot the largest |a[i][k]| over the rows not yet used and
+// records it, which is partial pivoting applied to the row-permuted matrix
+// C = P A (C's row k = A's row p_k); the in-place elimination of C leaves
+// C^-1[k][j] in physical row p_k, column j, and A^-1[k][p_j] = C^-1[k][j].
+// Each entry sees the same operations, in the same order, as in k_rebuild, so
+// both kernels give the same bits.  Per step only the pivot column and the
+// pivot row pass through LDS (double-buffered by step parity: two barriers).
+// ---------------------------------------------------------------------------
+constexpr int kRegRebuildMax = 192;
+constexpr int kRegBlock = 1024;
+
+template <typename T, int R>
+__global__ __launch_bounds__(kRegBlock) void k_rebuild_reg(SysParams P, Walkers<T> Wk, double* drift) {
+  __shared__ double scol[2][32 * R];
+  __shared__ double srow[2][32 * R];
+  __shared__ int spiv[32 * R];    // physical row of each step's pivot
+  __shared__ int sstep[32 * R];   // step at which each physical row was the pivot
+  __shared__ double spv[32 * R];   // pivot of each step
+  __shared__ double slog[32 * R];
+  __shared__ double sbest[2];
+  __shared__ double samax[kRegBlock / 64];
+  const int w = blockIdx.x >> 1, sp = blockIdx.x & 1, tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int r0 = tid & 31, c0 = tid >> 5;
+  const int n = sp ? P.n_dn : P.n_up, off = sp ? P.n_up : 0;
+  const int N = P.N;
+  if (n == 0) {
+    if (tid == 0) {
+      if (drift) drift[2 * w + sp] = Wk.logdet[2 * w + sp];
+      Wk.logdet[2 * w + sp] = 0.0;
+      Wk.sign[2 * w + sp] = 1;
+    }
+    return;
+  }
+  for (int q = tid; q < 2 * 32 * R; q += kRegBlock) {
+    (&scol[0][0])[q] = 0.0;
+    (&srow[0][0])[q] = 0.0;
+  }
+  double a[R][R];
+  unsigned used = 0;   // bit i: row r0 + 32 i is padding or has been a pivot
+  double amax = 0.0;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int e = r0 + 32 * i;
+    if (e < n) {
+      const size_t item = (size_t)w * N + off + e;
+      const size_t row = (size_t)Wk.cur[item] * P.W * N + item;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const int l = c0 + 32 * j;
+        a[i][j] = l < n ? (Wk.val64 ? Wk.val64[row * P.S + l] : (double)Wk.vgl[row * kComp * P.S + l]) : 0.0;
+        amax = fmax(amax, fabs(a[i][j]));
+      }
+    } else {
+      used |= 1u << i;
+#pragma unroll
+      for (int j = 0; j < R; ++j) a[i][j] = 0.0;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
+  if (lane == 0) samax[wave] = amax;
+  __syncthreads();
+  amax = samax[0];
+  for (int q = 1; q < kRegBlock / 64; ++q) amax = fmax(amax, samax[q]);
+  // a pivot this small relative to the largest entry means a numerically singular matrix
+  const double tiny = 1e-14 * amax;
+  double logabs = 0.0;
+  int sgn = 1;
+  bool singular = false;
+  for (int k = 0; k < n; ++k) {
+    const int b = k & 1;
+    const int jk = k >> 5;
+    const bool colk = c0 == (k & 31);   // this thread holds entries of column k
+    double* sc = &scol[b][r0];           // scol[b][r0 + 32 i] = sc[32 i]
+    double* sr = &srow[b][c0];           // srow[b][c0 + 32 j] = sr[32 j]
+    if (colk) {
+      // this half-wave owns column k: publish it and find the pivot among the unused rows
+      double best = -1.0;
+      int bi = n;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        if (j != jk) continue;   // uniform: one register column is taken
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const double v = a[i][j];
+          if (r0 + 32 * i < n) sc[32 * i] = v;
+          if (!((used >> i) & 1u) && fabs(v) > best) { best = fabs(v); bi = r0 + 32 * i; }
+        }
+      }
+#pragma unroll
+      for (int o = 16; o >= 1; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (r0 == 0) { spiv[k] = bi; sbest[b] = best; }
+    }
+    __syncthreads();
+    const int p = uniform(spiv[k]);
+    const double best = uniform(sbest[b]);
+    if (!(best > tiny) || !isfinite(best)) { singular = true; break; }
+    const int ip = p >> 5;
+    const bool rowp = r0 == (p & 31);   // this thread holds entries of the pivot row
+    if (rowp) {
+      used |= 1u << ip;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        if (i != ip) continue;   // uniform: one register row is taken
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+          if (c0 + 32 * j < n) sr[32 * j] = a[i][j];
+      }
+    }
+    __syncthreads();
+    const double piv = uniform(srow[b][k]);
+    const double pinv = 1.0 / piv;
+    if (tid == 0) spv[k] = piv;
+    // scaled pivot row; the pivot column's entry becomes 1 / piv
+    double rs[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) rs[j] = (j == jk && colk) ? pinv : sr[32 * j] * pinv;
+    // column k restarts from zero, so the update leaves -a[i][k] / piv there
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      if (j != jk) continue;
+#pragma unroll
+      for (int i = 0; i < R; ++i) a[i][j] = colk ? 0.0 : a[i][j];
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const double f = sc[32 * i];
+#pragma unroll
+      for (int j = 0; j < R; ++j) a[i][j] = a[i][j] - f * rs[j];
+    }
+    // the pivot row itself becomes the scaled row
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      if (i != ip) continue;
+#pragma unroll
+      for (int j = 0; j < R; ++j) a[i][j] = rowp ? rs[j] : a[i][j];
+    }
+  }
+  if (!singular) {
+    for (int k = tid; k < n; k += kRegBlock) sstep[spiv[k]] = k;
+    __syncthreads();
+    T* B = Wk.binv + (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int e = r0 + 32 * i;
+      if (e >= n) continue;
+      const size_t orow = (size_t)sstep[e] * n;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const int l = c0 + 32 * j;
+        if (l < n) B[orow + spiv[l]] = (T)a[i][j];
+      }
+    }
+    for (int k = tid; k < n; k += kRegBlock) slog[k] = log(fabs(spv[k]));
+    __syncthreads();
+    if (tid == 0) {
+      for (int k = 0; k < n; ++k) {
+        logabs += slog[k];
+        if (spv[k] < 0.0) sgn = -sgn;
+      }
+      // sign of the permutation k -> p_k: (-1)^(n - number of cycles)
+      int cycles = 0;
+      for (int s0 = 0; s0 < n; ++s0) {
+        if (sstep[s0] < 0) continue;
+        ++cycles;
+        for (int t = s0; sstep[t] >= 0;) {
+          const int nx = spiv[t];
+          sstep[t] = -1;
+          t = nx;
+        }
+      }
+      if ((n - cycles) & 1) sgn = -sgn;
+    }
+  }
+  if (tid == 0) {
+    if (drift) drift[2 * w + sp] = Wk.logdet[2 * w + sp] - (singular ? NAN : logabs);
+    Wk.logdet[2 * w + sp] = singular ? NAN : logabs;
+    Wk.sign[2 * w + sp] = singular ? 0 : sgn;
+    if (singular) atomicOr(Wk.status + w, 1 << sp);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // FP64 refinement of the FP32 inverses before a measurement (mixed precision).
 //
 // Between full rebuilds the FP32 rank-one and delayed updates let B drift from
@@ -335,6 +528,22 @@ template <typename T>
 hipError_t launch_rebuild(const SysParams& P, const Walkers<T>& Wk, double* scratch, double* drift,
                           hipStream_t st) {
   if (P.n_up > kMaxSpin || P.n_dn > kMaxSpin) return hipErrorInvalidValue;
+  const int nmax = P.n_up > P.n_dn ? P.n_up : P.n_dn;
+  // QMC_REBUILD_GLOBAL=1 takes the global-memory elimination for every size (lets the
+  // tests compare the two kernels)
+  const char* fg = getenv("QMC_REBUILD_GLOBAL");
+  if (!(fg && fg[0] == '1') && nmax <= kRegRebuildMax) {
+    const dim3 grid(2 * P.W), block(kRegBlock);
+    switch ((nmax + 31) / 32) {
+      case 1: hipLaunchKernelGGL((k_rebuild_reg<T, 1>), grid, block, 0, st, P, Wk, drift); break;
+      case 2: hipLaunchKernelGGL((k_rebuild_reg<T, 2>), grid, block, 0, st, P, Wk, drift); break;
+      case 3: hipLaunchKernelGGL((k_rebuild_reg<T, 3>), grid, block, 0, st, P, Wk, drift); break;
+      case 4: hipLaunchKernelGGL((k_rebuild_reg<T, 4>), grid, block, 0, st, P, Wk, drift); break;
+      case 5: hipLaunchKernelGGL((k_rebuild_reg<T, 5>), grid, block, 0, st, P, Wk, drift); break;
+      default: hipLaunchKernelGGL((k_rebuild_reg<T, 6>), grid, block, 0, st, P, Wk, drift); break;
+    }
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_rebuild<T>, dim3(2 * P.W), dim3(kBlock), 0, st, P, Wk, scratch, drift);
   return hipGetLastError();
 }

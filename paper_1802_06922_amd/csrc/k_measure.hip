@@ -29,7 +29,7 @@ __device__ __forceinline__ const Radial& pick(const Jastrow& J, int kind) {
 __device__ __forceinline__ double screened(double r2, double kappa, const double* __restrict__ htab) {
   const double ri = rsqrt(r2);
   const double x = kappa * kappa * r2;
-  const int i = (int)(x * (1.0 / kHW));
+  const int i = min((int)(x * (1.0 / kHW)), kHInt - 1);
   const double u = (x - (i + 0.5) * kHW) * (2.0 / kHW);
   const double* c = htab + i * (kHDeg + 1);
   double h = c[kHDeg];
@@ -38,19 +38,33 @@ __device__ __forceinline__ double screened(double r2, double kappa, const double
   return ri - kappa * h;
 }
 
+// G(x) = erfc(sqrt x) / sqrt x from its table, for kGX0 <= x < 5.5^2.
+__device__ __forceinline__ double screened_tail(double x, const double* __restrict__ htab) {
+  const int i = max(0, min((int)((x - kGX0) * (1.0 / kHW)), kGInt - 1));
+  const double u = (x - (kGX0 + (i + 0.5) * kHW)) * (2.0 / kHW);
+  const double* c = htab + (kHInt + i) * (kHDeg + 1);
+  double g = c[kHDeg];
+#pragma unroll
+  for (int m = kHDeg - 1; m >= 0; --m) g = g * u + c[m];
+  return g;
+}
+
 // sum of erfc(kappa r) / r over the images of d (minimum-imaged) with r < rcut <= L:
-// per axis only the shift toward the nearer neighbouring cell can qualify.
+// per axis only the shift toward the nearer neighbouring cell can qualify.  The
+// minimum image itself is always inside the cutoff (r <= sqrt(3) L / 2); the others lie
+// at r >= L / 2 and take the erfc table.
 __device__ __forceinline__ double screened_images(double dx, double dy, double dz, double L,
                                                   double kappa, double rcut2, const double* htab) {
   const double sx = dx > 0.0 ? -L : L, sy = dy > 0.0 ? -L : L, sz = dz > 0.0 ? -L : L;
-  double s = 0.0;
+  const double k2 = kappa * kappa;
+  double s = screened(dx * dx + dy * dy + dz * dz, kappa, htab);
 #pragma unroll
-  for (int m = 0; m < 8; ++m) {
+  for (int m = 1; m < 8; ++m) {
     const double x = dx + ((m & 1) ? sx : 0.0);
     const double y = dy + ((m & 2) ? sy : 0.0);
     const double z = dz + ((m & 4) ? sz : 0.0);
     const double r2 = x * x + y * y + z * z;
-    if (r2 < rcut2) s += screened(r2, kappa, htab);
+    if (r2 < rcut2) s += kappa * screened_tail(k2 * r2, htab);
   }
   return s;
 }

@@ -225,6 +225,15 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// A value every lane of the wave holds alike, moved to scalar registers.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uniform(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)b);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // 16x16x4 matrix-core products.  Operands: lane l holds A[l % 16][l / 16] and
 // B[l / 16][l % 16]; result register r of lane l holds D[row(l, r)][l % 16],
 // where the row mapping differs between the FP32 and FP64 instructions.

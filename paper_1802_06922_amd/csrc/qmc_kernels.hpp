@@ -13,10 +13,15 @@ constexpr int kEwaldSeg = 10;   // reciprocal vectors per segment of a (Gx, Gy) 
 // Real-space Ewald term erfc(kappa r) / r = 1 / r - kappa H(kappa^2 r^2) with the entire
 // function H(x) = erf(sqrt x) / sqrt x, tabulated on [0, (kappa rcut)^2] = [0, 5.5^2] as
 // degree-kHDeg polynomials in u = (x - x_c) / (kHW / 2) on intervals of width kHW.
+// Images other than the minimum one lie at r >= L / 2, i.e. x >= 5.5^2 / 4; there
+// erfc(kappa r) / r = kappa G(x) with G(x) = erfc(sqrt x) / sqrt x, tabulated the same way
+// on [kGX0, 5.5^2] (no reciprocal square root needed).  G's intervals follow H's.
 constexpr int kHDeg = 7;
 constexpr double kHW = 0.25;
 constexpr int kHInt = 122;                     // covers x < 30.5
-constexpr int kHTab = kHInt * (kHDeg + 1);    // doubles
+constexpr double kGX0 = 7.5;
+constexpr int kGInt = 92;                      // covers 7.5 <= x < 30.5
+constexpr int kHTab = (kHInt + kGInt) * (kHDeg + 1);    // doubles
 
 struct EwaldParams {
   int enabled;
@@ -25,7 +30,8 @@ struct EwaldParams {
   const double* gvec;    // [n_g][4]: Gx, Gy, Gz, (4 pi / V) exp(-G^2 / 4 kappa^2) / G^2
   const double* s_ion;   // [n_g][2]: sum_I Z_I exp(i G.R_I)
   const int* segs;       // [n_seg][5]: mx, my, mz_lo, mz_hi, index of the first vector in gvec
-  const double* htab;    // [kHInt][kHDeg + 1]: polynomial coefficients of H, lowest degree first
+  const double* htab;    // [kHInt + kGInt][kHDeg + 1]: polynomial coefficients of H, then of G,
+                         // lowest degree first
   double c_ee;           // electron self, self-image and background terms
   double c_ei;           // electron-ion background cross term
   double v_ii;           // ion-ion energy (constant)

@@ -138,6 +138,34 @@ def test_recompute_drift_is_tiny(gpu, orc):
         assert _rel(e1[w], ref).max() < E_TOL
 
 
+@pytest.mark.parametrize("n_elec,grid,precision", [(14, 12, "fp64"), (128, 20, "fp64"), (200, 20, "fp64"),
+                                                    (384, 24, "mixed")])
+def test_register_rebuild_matches_global(gpu, monkeypatch, n_elec, grid, precision):
+    """The register-resident elimination (spin blocks up to 192) against the global-memory
+    one: same pivots and operations, so the rebuilt log|D|, signs and the trajectory that
+    follows agree bit for bit."""
+    runs = []
+    for force_global in (True, False):
+        if force_global:
+            monkeypatch.setenv("QMC_REBUILD_GLOBAL", "1")
+        else:
+            monkeypatch.delenv("QMC_REBUILD_GLOBAL", raising=False)
+        wl = qi.solid(n_elec, grid, n_walkers=8, n_sweeps=1, precision=precision)
+        s = gpu.System(wl)
+        s.sweep(2)
+        drift = s.recompute()
+        _, ld, sg = s.get_walkers()
+        s.sweep(2)
+        e = s.measure()
+        _, ld2, _ = s.get_walkers()
+        runs.append((drift, ld, sg, s.accept_log(), e, ld2))
+        s.close()
+    for a, b in zip(runs[0], runs[1]):
+        assert np.array_equal(a, b)
+    if precision == "fp64":   # (FP32 updates accumulate log|R| with FP32 ratios)
+        assert np.abs(runs[0][0]).max() < 1e-8
+
+
 def test_measure_at_given_positions(gpu, orc):
     wl = qi.solid(32, 16, n_walkers=5, n_sweeps=1)
     rng = np.random.default_rng(4)
