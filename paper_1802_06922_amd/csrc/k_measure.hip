@@ -25,16 +25,22 @@ __device__ __forceinline__ const Radial& pick(const Jastrow& J, int kind) {
   return kind == 0 ? J.same : (kind == 1 ? J.opp : J.ei);
 }
 
+// In LDS the tables are stored coefficient-major, c_m of interval i at [m][i]: the lanes of
+// a wave look up unrelated intervals, and with consecutive intervals in consecutive banks
+// their reads spread over all banks (interval-major rows of 8 doubles would put every
+// lane's c_m in one of a few banks).
+constexpr int kTabInt = kHInt + kGInt;
+
 // erfc(kappa r) / r = 1 / r - kappa H(kappa^2 r^2) for r^2 < rcut^2, H from its table.
 __device__ __forceinline__ double screened(double r2, double kappa, const double* __restrict__ htab) {
   const double ri = rsqrt(r2);
   const double x = kappa * kappa * r2;
   const int i = min((int)(x * (1.0 / kHW)), kHInt - 1);
   const double u = (x - (i + 0.5) * kHW) * (2.0 / kHW);
-  const double* c = htab + i * (kHDeg + 1);
-  double h = c[kHDeg];
+  const double* c = htab + i;
+  double h = c[kHDeg * kTabInt];
 #pragma unroll
-  for (int m = kHDeg - 1; m >= 0; --m) h = h * u + c[m];
+  for (int m = kHDeg - 1; m >= 0; --m) h = h * u + c[m * kTabInt];
   return ri - kappa * h;
 }
 
@@ -42,10 +48,10 @@ __device__ __forceinline__ double screened(double r2, double kappa, const double
 __device__ __forceinline__ double screened_tail(double x, const double* __restrict__ htab) {
   const int i = max(0, min((int)((x - kGX0) * (1.0 / kHW)), kGInt - 1));
   const double u = (x - (kGX0 + (i + 0.5) * kHW)) * (2.0 / kHW);
-  const double* c = htab + (kHInt + i) * (kHDeg + 1);
-  double g = c[kHDeg];
+  const double* c = htab + kHInt + i;
+  double g = c[kHDeg * kTabInt];
 #pragma unroll
-  for (int m = kHDeg - 1; m >= 0; --m) g = g * u + c[m];
+  for (int m = kHDeg - 1; m >= 0; --m) g = g * u + c[m * kTabInt];
   return g;
 }
 
@@ -134,7 +140,7 @@ __device__ __forceinline__ void measure_part(const SysParams& P, const Walkers<T
   double* shtab = reinterpret_cast<double*>(smem + lay.htab);
   for (int j = tid; j < 3 * N; j += kBlock) spos[j] = Wk.pos[(size_t)w * 3 * N + j];
   if (E.enabled)
-    for (int j = tid; j < kHTab; j += kBlock) shtab[j] = E.htab[j];
+    for (int j = tid; j < kHTab; j += kBlock) shtab[(j % (kHDeg + 1)) * kTabInt + j / (kHDeg + 1)] = E.htab[j];
   __syncthreads();
   const double g0 = 2.0 * kPi / P.L, invL = 1.0 / P.L;
   if (E.enabled)
