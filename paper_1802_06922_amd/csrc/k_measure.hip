@@ -82,11 +82,13 @@ struct MeasureLayout {
 };
 
 // Every walker's local energy is computed by np workgroups (parts): part p
-// takes the kinetic terms of electrons p nloc .. (p + 1) nloc - 1 and every np-th pair,
-// ion pair and reciprocal segment; it writes five partial sums, and a second
+// takes the kinetic terms of electrons p nloc .. (p + 1) nloc - 1, the p-th
+// contiguous block of the electron pairs and of the electron-ion pairs, and
+// every np-th reciprocal segment; it writes five partial sums, and a second
 // kernel adds the parts of a walker in a fixed order.  Spreading a walker
 // over several workgroups keeps enough waves in flight to hide the latency of
-// the FP64 transcendental sequences (erfc, sincos) that dominate here.
+// the FP64 sequences (rsqrt, sincos, table polynomials) that dominate here.
+
 // Sum over the four lanes of a lane quad (all four active), the same in each lane.
 __device__ __forceinline__ double quad_sum(double v) {
   v = dpp_add<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
@@ -138,7 +140,11 @@ __device__ __forceinline__ void measure_part(const SysParams& P, const Walkers<T
     for (int q = tid; q < (int)(sizeof(Jastrow) / 4); q += kBlock) dst[q] = src[q];
   }
   double* shtab = reinterpret_cast<double*>(smem + lay.htab);
-  for (int j = tid; j < 3 * N; j += kBlock) spos[j] = Wk.pos[(size_t)w * 3 * N + j];
+  // positions structure-of-arrays: x of every electron, then y, then z
+  for (int j = tid; j < 3 * N; j += kBlock) spos[(j % 3) * N + j / 3] = Wk.pos[(size_t)w * 3 * N + j];
+  const double* sx = spos;
+  const double* sy = spos + N;
+  const double* sz = spos + 2 * N;
   if (E.enabled)
     for (int j = tid; j < kHTab; j += kBlock) shtab[(j % (kHDeg + 1)) * kTabInt + j / (kHDeg + 1)] = E.htab[j];
   __syncthreads();
@@ -146,7 +152,7 @@ __device__ __forceinline__ void measure_part(const SysParams& P, const Walkers<T
   if (E.enabled)
     for (int i = tid; i < N; i += kBlock) {
       double s, c;
-      sincos(g0 * spos[3 * i + 2], &s, &c);
+      sincos(g0 * sz[i], &s, &c);
       sez[2 * i] = c;
       sez[2 * i + 1] = s;
     }
@@ -179,16 +185,17 @@ __device__ __forceinline__ void measure_part(const SysParams& P, const Walkers<T
   for (int q = tid; q < nloc * parts; q += kBlock) {
     const int li = q % nloc, part = q / nloc, i = p * nloc + li;
     if (i >= N) continue;
-    const double xi = spos[3 * i], yi = spos[3 * i + 1], zi = spos[3 * i + 2];
+    const double xi = sx[i], yi = sy[i], zi = sz[i];
     const bool up_i = i < P.n_up;
     double g[3] = {0.0, 0.0, 0.0}, lj = 0.0;
     // partners j = part (mod parts) in three ranges, each with its own radial function:
     // same-spin electrons, opposite-spin electrons, ions
-    auto range = [&](const Radial& R, int lo, int hi, const double* c, int stride) {
+    auto range = [&](const Radial& R, int lo, int hi, auto&& at) {
       for (int j = lo + ((part - lo) % parts + parts) % parts; j < hi; j += parts) {
-        const double* cj = c + (size_t)stride * j;
-        const double dx = min_image(xi - cj[0], P.L, invL), dy = min_image(yi - cj[1], P.L, invL);
-        const double dz = min_image(zi - cj[2], P.L, invL);
+        double cx, cy, cz;
+        at(j, cx, cy, cz);
+        const double dx = min_image(xi - cx, P.L, invL), dy = min_image(yi - cy, P.L, invL);
+        const double dz = min_image(zi - cz, P.L, invL);
         const double r2 = dx * dx + dy * dy + dz * dz;
         const double ri = rsqrt(r2), r = r2 * ri;
         double u, du, d2u;
@@ -198,38 +205,46 @@ __device__ __forceinline__ void measure_part(const SysParams& P, const Walkers<T
         lj += j == i ? 0.0 : d2u + 2.0 * f;
       }
     };
-    range(up_i ? sj.same : sj.opp, 0, P.n_up, spos, 3);
-    range(up_i ? sj.opp : sj.same, P.n_up, N, spos, 3);
-    if (P.n_ions > 0) range(sj.ei, N, N + P.n_ions, P.ions - 4 * (size_t)N, 4);
+    auto elec = [&](int j, double& cx, double& cy, double& cz) { cx = sx[j]; cy = sy[j]; cz = sz[j]; };
+    auto ion = [&](int j, double& cx, double& cy, double& cz) {
+      const double* c = P.ions + 4 * (size_t)(j - N);
+      cx = c[0]; cy = c[1]; cz = c[2];
+    };
+    range(up_i ? sj.same : sj.opp, 0, P.n_up, elec);
+    range(up_i ? sj.opp : sj.same, P.n_up, N, elec);
+    if (P.n_ions > 0) range(sj.ei, N, N + P.n_ions, ion);
     double* gp = sgj + 3 * ((size_t)part * nloc + li);
     gp[0] = g[0]; gp[1] = g[1]; gp[2] = g[2];
     slj[(size_t)part * nloc + li] = lj;
   }
 
-  // (3) Coulomb terms: every np-th item of each list, items q = p + np * (tid + kBlock * r)
+  // (3) Coulomb terms: part p takes the p-th of np contiguous blocks of each pair list, its
+  // threads consecutive items (consecutive electrons i, read from consecutive LDS banks)
   double vee = 0.0, vei = 0.0, vee_k = 0.0, vei_k = 0.0;
   if (E.enabled) {
     const double rcut2 = E.rcut * E.rcut;
-    const int stride = np * kBlock;
     // (3a) electron pairs, each once: j = i + d (mod N), d = 1..(N-1)/2, and d = N/2 for i < N/2
     const int D = (N - 1) / 2;
     const int n_pairs = N * D + ((N % 2 == 0) ? N / 2 : 0);
-    for (int q = p + np * tid; q < n_pairs; q += stride) {
+    const int qa0 = (int)((long)n_pairs * p / np), qa1 = (int)((long)n_pairs * (p + 1) / np);
+    for (int q = qa0 + tid; q < qa1; q += kBlock) {
       int i, j;
       if (q < N * D) { i = q % N; j = i + q / N + 1; if (j >= N) j -= N; }
       else { i = q - N * D; j = i + N / 2; }
-      const double dx = min_image(spos[3 * i] - spos[3 * j], P.L, invL);
-      const double dy = min_image(spos[3 * i + 1] - spos[3 * j + 1], P.L, invL);
-      const double dz = min_image(spos[3 * i + 2] - spos[3 * j + 2], P.L, invL);
+      const double dx = min_image(sx[i] - sx[j], P.L, invL);
+      const double dy = min_image(sy[i] - sy[j], P.L, invL);
+      const double dz = min_image(sz[i] - sz[j], P.L, invL);
       vee += screened_images(dx, dy, dz, P.L, E.kappa, rcut2, shtab);
     }
     // (3b) electron-ion pairs
-    for (int q = p + np * tid; q < N * P.n_ions; q += stride) {
+    const int n_ei = N * P.n_ions;
+    const int qb0 = (int)((long)n_ei * p / np), qb1 = (int)((long)n_ei * (p + 1) / np);
+    for (int q = qb0 + tid; q < qb1; q += kBlock) {
       const int i = q % N, I = q / N;
       const double* ion = P.ions + 4 * I;
-      const double dx = min_image(spos[3 * i] - ion[0], P.L, invL);
-      const double dy = min_image(spos[3 * i + 1] - ion[1], P.L, invL);
-      const double dz = min_image(spos[3 * i + 2] - ion[2], P.L, invL);
+      const double dx = min_image(sx[i] - ion[0], P.L, invL);
+      const double dy = min_image(sy[i] - ion[1], P.L, invL);
+      const double dz = min_image(sz[i] - ion[2], P.L, invL);
       vei -= ion[3] * screened_images(dx, dy, dz, P.L, E.kappa, rcut2, shtab);
     }
     // (3c) reciprocal space: items (segment, quarter of the electrons) in lane quads; a
@@ -246,7 +261,7 @@ __device__ __forceinline__ void measure_part(const SysParams& P, const Walkers<T
       for (int m = 0; m < kSeg; ++m) { sr[m] = 0.0; si[m] = 0.0; }
       for (int i = c4; i < N; i += 4) {
         double br, bi;
-        sincos(g0 * (mx * spos[3 * i] + my * spos[3 * i + 1] + lo * spos[3 * i + 2]), &bi, &br);
+        sincos(g0 * (mx * sx[i] + my * sy[i] + lo * sz[i]), &bi, &br);
         const double er = sez[2 * i], ei = sez[2 * i + 1];
 #pragma unroll
         for (int m = 0; m < kSeg; ++m) {
