@@ -56,7 +56,9 @@ __host__ __device__ inline DLayout dlayout(int N, int nmax, int n_ions, int ldl,
   L.ions = o; o += (n_ions <= kLdsIonsD) ? sizeof(double) * 4 * n_ions : 0;
   L.red = o; o += sizeof(double) * kBlock;
   L.rmag = o; o += (ts == 4) ? sizeof(double) * kBlock : 0;   // mixed: |v| . |B0[:, k]| partials
-  L.gold = o; o += sizeof(double) * K * K;
+  // gold's storage later holds the window block yk with rows of K + 1 (bank spread) and
+  // up to 7 entries read past its last row
+  L.gold = o; o += sizeof(double) * ((size_t)K * (K + 1) + 8);
   L.gdiff = o; o += sizeof(double) * K * K;
   L.cur = o; o += nmax;
   L.acc = o; o += nmax;
@@ -270,6 +272,7 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
   T* sB = reinterpret_cast<T*>(smem + lay.b);
   const double L = P.L, invL = 1.0 / P.L;
   const int tpq = kBlock / K;   // threads per window slot in the Jastrow sums
+  const int ldy = K + 1;        // row stride of yk: the lanes' rows start in different banks
   // the wave that runs the moves in sequence rotates with the workgroup index, so that the
   // sequential phases of workgroups sharing a compute unit fall on different SIMDs
   const int seq_wave = (int)(blockIdx.x & (kWaves - 1)), seq_tid = seq_wave * 64;
@@ -364,12 +367,12 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
         const double cx = spos[3 * i2], cy = spos[3 * i2 + 1], cz = spos[3 * i2 + 2];
         const double g_old = ju(sj, 0, dist(px, py, pz, cx, cy, cz, L, invL)) -
                              ju(sj, 0, dist(ox, oy, oz, cx, cy, cz, L, invL));
-        gold[q * K + q2] = g_old;
+        gold[q2 * K + q] = g_old;   // transposed: lane q reads column q
         if (q2 < q) {
           const double nx = sprop[4 * k2], ny = sprop[4 * k2 + 1], nz = sprop[4 * k2 + 2];
           const double g_new = ju(sj, 0, dist(px, py, pz, nx, ny, nz, L, invL)) -
                                ju(sj, 0, dist(ox, oy, oz, nx, ny, nz, L, invL));
-          gdiff[q * K + q2] = g_new - g_old;
+          gdiff[q2 * K + q] = g_new - g_old;
         }
       }
       // (A3) Y = V B0
@@ -389,22 +392,34 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
           if (sizeof(T) == 4)
             for (int s = 0; s < tpq; ++s) Sq += rmag[lane * tpq + s];
           for (int j = 0; j < Kw; ++j) {
-            const double gj = gold[lane * K + j];
+            const double gj = gold[j * K + lane];
             Fq += j != lane ? gj : 0.0;
           }
         }
         wave_sync_lds();   // gold is consumed: its storage takes yk
         if (lane < Kw)
-          for (int j = 0; j < Kw; ++j) yk[lane * K + j] = (double)ywin[(size_t)lane * nP + k0 + j];
+          for (int j = 0; j < Kw; ++j) yk[lane * ldy + j] = (double)ywin[(size_t)lane * nP + k0 + j];
+        // mixed precision: an FP32 exponential is well inside the guard band
+        auto jexp = [](double x) { return sizeof(T) == 4 ? (double)__expf((float)x) : exp(x); };
+        // lane q: its move's acceptance uniform and the exponential of its current Jastrow
+        // change (kept current as earlier moves are accepted)
+        const double uq = lane < Kw ? sprop[4 * (k0 + lane) + 3] : 0.0;
+        double exq = lane < Kw ? jexp(2.0 * Fq) : 0.0;
+        double racc = 1.0;      // lane q: R of move q once accepted
+        uint64_t amask = 0;     // accepted moves of the window
         wave_sync_lds();
         int m = 0;
         for (int q = 0; q < Kw; ++q) {
           const int kq = k0 + q, iq = off + kq;
-          const double R = yk[q * K + q];
+          const double R = yk[q * ldy + q];
           const double dJ = readlane_d(Fq, q);
-          const double u = sprop[4 * kq + 3];
-          // mixed precision: an FP32 exponential is well inside the guard band
-          const double ex = sizeof(T) == 4 ? (double)__expf((float)(2.0 * dJ)) : exp(2.0 * dJ);
+          const double u = readlane_d(uq, q);
+          const double ex = readlane_d(exq, q);
+          // later lanes: their exponential should move q be accepted, formed ahead of the
+          // decision
+          const bool later = lane > q && lane < Kw;
+          const double gq = later ? gdiff[q * K + lane] : 0.0;
+          const double ex_acc = later ? jexp(2.0 * (Fq + gq)) : 0.0;
           const double p32 = R * R * ex;
           // guard band: the relative tie guard, widened by a bound on the FP32 rounding of R:
           // n + 1 unit roundoffs (the length-n product and the cast of B0) of the magnitude of
@@ -423,8 +438,8 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
           }
           if (u < p32) {
             if (lane > q && lane < Kw) {
-              const double f = yk[lane * K + q] / R;
-              if (sizeof(T) == 4) Eq += fabs(f * yk[q * K + lane]);
+              const double f = yk[lane * ldy + q] / R;
+              if (sizeof(T) == 4) Eq += fabs(f * yk[q * ldy + lane]);
               // eight columns at a time: all loads before the stores, so they overlap.  The
               // loads are unconditional (a guarded load becomes a branch of its own): columns
               // past Kw read at most 7 entries beyond the row, inside the LDS block that
@@ -433,14 +448,15 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
                 double pv[8], rv[8];
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                  pv[e] = yk[q * K + j0 + e];
-                  rv[e] = yk[lane * K + j0 + e];
+                  pv[e] = yk[q * ldy + j0 + e];
+                  rv[e] = yk[lane * ldy + j0 + e];
                 }
 #pragma unroll
                 for (int e = 0; e < 8; ++e)
-                  if (j0 + e < Kw) yk[lane * K + j0 + e] = rv[e] - f * pv[e];
+                  if (j0 + e < Kw) yk[lane * ldy + j0 + e] = rv[e] - f * pv[e];
               }
-              Fq += gdiff[lane * K + q];
+              Fq += gq;
+              exq = ex_acc;
             }
             if (lane == 0) {
               plist[m] = kq;
@@ -453,12 +469,19 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
             }
             ++m;
             ++nacc;
-            logd += log(fabs(R));
+            racc = lane == q ? R : racc;
+            amask |= 1ull << q;
             if (R < 0.0) sgn = -sgn;
           } else if (lane == 0) {
             sacc[kq] = 0;
           }
           wave_sync_lds();
+        }
+        {
+          // log|R| of the accepted moves: all lanes at once, added in move order
+          const double lg = log(fabs(racc));
+          for (int q = 0; q < Kw; ++q)
+            if ((amask >> q) & 1ull) logd += readlane_d(lg, q);
         }
         if (lane == 0) sm_m = m;
       }
