@@ -330,22 +330,20 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
           const int kq = k0 + q, iq = off + kq;
           const double px = sprop[4 * kq], py = sprop[4 * kq + 1], pz = sprop[4 * kq + 2];
           const double ox = spos[3 * iq], oy = spos[3 * iq + 1], oz = spos[3 * iq + 2];
-          const int w0 = off + k0, w1 = off + k0 + Kw;
-          for (int j = s; j < N + P.n_ions; j += tpq) {
-            if (j >= w0 && j < w1) continue;
-            double cx, cy, cz;
-            int kind;
-            if (j < N) {
-              cx = spos[3 * j]; cy = spos[3 * j + 1]; cz = spos[3 * j + 2];
-              kind = ((j < P.n_up) == up_block) ? 0 : 1;
-            } else {
-              const double* ion = ions + 4 * (j - N);
-              cx = ion[0]; cy = ion[1]; cz = ion[2];
-              kind = 2;
+          // partner ranges with one radial function each (no divergence between lanes):
+          // same-spin electrons before and after the window, the other spin block, the ions
+          auto range = [&](const Radial& R, int lo, int hi, const double* c, int stride) {
+            for (int j = lo + s; j < hi; j += tpq) {
+              const double* cj = c + (size_t)stride * j;
+              part += radial_value(R, dist(px, py, pz, cj[0], cj[1], cj[2], L, invL)) -
+                      radial_value(R, dist(ox, oy, oz, cj[0], cj[1], cj[2], L, invL));
             }
-            part += ju(sj, kind, dist(px, py, pz, cx, cy, cz, L, invL)) -
-                    ju(sj, kind, dist(ox, oy, oz, cx, cy, cz, L, invL));
-          }
+          };
+          const int ooff = up_block ? P.n_up : 0, no = up_block ? P.n_dn : P.n_up;
+          range(sj.same, off, off + k0, spos, 3);
+          range(sj.same, off + k0 + Kw, off + n, spos, 3);
+          range(sj.opp, ooff, ooff + no, spos, 3);
+          range(sj.ei, 0, P.n_ions, ions, 4);
         }
         red[tid] = part;
         if (sizeof(T) == 4) {
