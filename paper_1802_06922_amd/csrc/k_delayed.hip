@@ -236,6 +236,52 @@ __device__ __forceinline__ void gemm_flush(T* B, int ldb, const T* U, int ldu, c
   }
 }
 
+// The flush for an inverse in global memory.  There the product is bound by the latency
+// of the B loads, not by arithmetic: each thread updates blocks of 4 rows by 16 bytes of
+// columns (4 FP32 or 2 FP64) with 16-byte loads and stores, kFlushBatch blocks at a
+// time, so a wave keeps 4 kFlushBatch wide loads in flight; consecutive threads take
+// consecutive column blocks of the same rows (coalesced).  Needs n a multiple of 4, ldb a
+// multiple of the vector width, and B, Z 16-byte aligned.
+constexpr int kFlushBatch = 2;
+template <typename T>
+__device__ __forceinline__ void flush_global(T* B, int ldb, const T* U, int ldu, const T* Z, int nP, int n,
+                                             int mP, int tid) {
+  constexpr int V = 16 / sizeof(T);
+  typedef T vec __attribute__((ext_vector_type(V)));
+  const int cbn = n / V, nb = (n >> 2) * cbn;
+  for (int b0 = tid; b0 < nb; b0 += kBlock * kFlushBatch) {
+    vec old[kFlushBatch][4], acc[kFlushBatch][4];
+    int lr[kFlushBatch], cv[kFlushBatch];
+#pragma unroll
+    for (int j = 0; j < kFlushBatch; ++j) {
+      const int b = min(b0 + j * kBlock, nb - 1);   // clamped: loads stay in bounds
+      lr[j] = (b / cbn) * 4;
+      cv[j] = (b - (b / cbn) * cbn) * V;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        old[j][i] = *reinterpret_cast<const vec*>(B + (size_t)(lr[j] + i) * ldb + cv[j]);
+        acc[j][i] = vec(T(0));
+      }
+    }
+#pragma unroll 1
+    for (int r = 0; r < mP; ++r) {
+#pragma unroll
+      for (int j = 0; j < kFlushBatch; ++j) {
+        const vec z = *reinterpret_cast<const vec*>(Z + (size_t)r * nP + cv[j]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[j][i] += U[(size_t)(lr[j] + i) * ldu + r] * z;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kFlushBatch; ++j) {
+      if (b0 + j * kBlock >= nb) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        *reinterpret_cast<vec*>(B + (size_t)(lr[j] + i) * ldb + cv[j]) = old[j][i] - acc[j][i];
+    }
+  }
+}
+
 template <typename T, bool BLDS, bool MF>
 __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const Walkers<T>& Wk, int w, int K,
                                                      int ldl) {
@@ -525,7 +571,12 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
           ubuf[(size_t)l * K + r] = (r < m) ? Bm[(size_t)l * ldb + plist[r]] : T(0);
         }
         __syncthreads();
-        gemm_flush<T, MF>(Bm, ldb, ubuf, K, zwin, nP, n, mP, tid);
+        constexpr int kVec = 16 / sizeof(T);
+        if (!BLDS && (n & 3) == 0 && (n % kVec) == 0 && (ldb % kVec) == 0 &&
+            (reinterpret_cast<uintptr_t>(Bm) & 15) == 0)
+          flush_global<T>(Bm, ldb, ubuf, K, zwin, nP, n, mP, tid);
+        else
+          gemm_flush<T, MF>(Bm, ldb, ubuf, K, zwin, nP, n, mP, tid);
         __syncthreads();
       }
       // (D) a move stopped at a near tie (mixed precision): FP64 decision against the
@@ -603,13 +654,13 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
 }
 
 template <typename T, bool BLDS, bool MF>
-__global__ __launch_bounds__(kBlock) void k_chain_delayed(SysParams P, Walkers<T> Wk, int K, int ldl) {
+__global__ __launch_bounds__(kBlock, 2) void k_chain_delayed(SysParams P, Walkers<T> Wk, int K, int ldl) {
   chain_delayed_walker<T, BLDS, MF>(P, Wk, blockIdx.x, K, ldl);
 }
 
 // Several systems in one launch: block b is walker bmap[b].y of system bmap[b].x.
 template <typename T, bool BLDS, bool MF>
-__global__ __launch_bounds__(kBlock) void k_chain_delayed_batched(const SysDev<T>* __restrict__ sd,
+__global__ __launch_bounds__(kBlock, 2) void k_chain_delayed_batched(const SysDev<T>* __restrict__ sd,
                                                                   const int2* __restrict__ bmap) {
   __shared__ SysDev<T> s;
   const int2 m = bmap[blockIdx.x];
