@@ -578,12 +578,14 @@ qmc_status qmc_load_spline_table(qmc_system s, int32_t gx, int32_t gy, int32_t g
   return QMC_OK;
 }
 
-static qmc_status run_rebuild(qmc_system s, double* drift_dev) {
+// sel (nullable): rebuild only the walkers w with sel[w] == sel_value
+static qmc_status run_rebuild(qmc_system s, double* drift_dev, const uint32_t* sel = nullptr,
+                              uint32_t sel_value = 0) {
   hipError_t e;
   if (s->d.precision == QMC_MIXED)
-    e = timed(s, 3, [&] { return launch_rebuild<float>(s->P, walkers_of<float>(s), s->scratch, drift_dev, s->stream); });
+    e = timed(s, 3, [&] { return launch_rebuild<float>(s->P, walkers_of<float>(s), s->scratch, drift_dev, s->stream, sel, sel_value); });
   else
-    e = timed(s, 3, [&] { return launch_rebuild<double>(s->P, walkers_of<double>(s), s->scratch, drift_dev, s->stream); });
+    e = timed(s, 3, [&] { return launch_rebuild<double>(s->P, walkers_of<double>(s), s->scratch, drift_dev, s->stream, sel, sel_value); });
   if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "inverse rebuild launch: %s", hipGetErrorString(e));
   return QMC_OK;
 }
@@ -649,7 +651,9 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
   // the cell; a walker's draw is redrawn (next attempt of its INIT counter) while one of its
   // Slater matrices is singular or so badly conditioned that the single-precision rounding of
   // its inverse leaves a residual above kInitResidual.  The attempt numbers live in nacc and
-  // the residuals in drift until the first sweep.
+  // the residuals in drift until the first sweep.  A walker is redrawn in round r exactly when
+  // its attempt number is r, so later rounds rebuild and check only those walkers (the
+  // others' positions and rows are regenerated unchanged, their inverses are kept).
   std::vector<uint32_t> attempt(W, 0u);
   std::vector<double> resid((size_t)W * 2);
   std::vector<int> status(W);
@@ -660,18 +664,20 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
       HIP_TRY(s, launch_init_positions(s->P, s->pos, d_attempt, s->stream));
     }
     HIP_TRY(s, hipMemsetAsync(s->status, 0, z.status, s->stream));
-    HIP_TRY(s, hipMemsetAsync(s->logdet, 0, z.logdet, s->stream));
+    if (round == 0) HIP_TRY(s, hipMemsetAsync(s->logdet, 0, z.logdet, s->stream));
+    const uint32_t* sel = pos ? nullptr : d_attempt;
     hipError_t e;
     if (s->d.precision == QMC_MIXED)
       e = timed(s, 0, [&] { return launch_gather<float>(s->P, walkers_of<float>(s), static_cast<const float*>(s->d_table), 1, s->stream); });
     else
       e = timed(s, 0, [&] { return launch_gather<double>(s->P, walkers_of<double>(s), static_cast<const double*>(s->d_table), 1, s->stream); });
     if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "orbital gather launch: %s", hipGetErrorString(e));
-    qmc_status st = run_rebuild(s, nullptr);
+    qmc_status st = run_rebuild(s, nullptr, sel, (uint32_t)round);
     if (st != QMC_OK) return st;
     if (pos) break;
-    e = s->d.precision == QMC_MIXED ? launch_inverse_residual<float>(s->P, walkers_of<float>(s), s->drift, s->stream)
-                                    : launch_inverse_residual<double>(s->P, walkers_of<double>(s), s->drift, s->stream);
+    e = s->d.precision == QMC_MIXED
+            ? launch_inverse_residual<float>(s->P, walkers_of<float>(s), s->drift, s->stream, sel, (uint32_t)round)
+            : launch_inverse_residual<double>(s->P, walkers_of<double>(s), s->drift, s->stream, sel, (uint32_t)round);
     if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "residual launch: %s", hipGetErrorString(e));
     HIP_TRY(s, hipMemcpyAsync(resid.data(), s->drift, resid.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(s, hipMemcpyAsync(status.data(), s->status, status.size() * sizeof(int), hipMemcpyDeviceToHost, s->stream));

@@ -18,7 +18,7 @@ constexpr int kMaxSpin = 1024;
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_rebuild(SysParams P, Walkers<T> Wk, double* scratch,
-                                                    double* drift) {
+                                                    double* drift, const uint32_t* sel, uint32_t sel_value) {
   __shared__ double scol[kMaxSpin];
   __shared__ int perm[kMaxSpin];
   __shared__ double rv[kWaves];
@@ -27,6 +27,7 @@ __global__ __launch_bounds__(kBlock) void k_rebuild(SysParams P, Walkers<T> Wk, 
   const int lane = tid & 63, wave = tid >> 6;
   const int n = sp ? P.n_dn : P.n_up, off = sp ? P.n_up : 0;
   const int N = P.N;
+  if (sel && sel[w] != sel_value) return;
   if (n == 0) {
     if (tid == 0) {
       if (drift) drift[2 * w + sp] = Wk.logdet[2 * w + sp];
@@ -146,7 +147,8 @@ constexpr int kRegRebuildMax = 192;
 constexpr int kRegBlock = 1024;
 
 template <typename T, int R>
-__global__ __launch_bounds__(kRegBlock) void k_rebuild_reg(SysParams P, Walkers<T> Wk, double* drift) {
+__global__ __launch_bounds__(kRegBlock) void k_rebuild_reg(SysParams P, Walkers<T> Wk, double* drift,
+                                                           const uint32_t* sel, uint32_t sel_value) {
   __shared__ double scol[2][32 * R];
   __shared__ double srow[2][32 * R];
   __shared__ int spiv[32 * R];    // physical row of each step's pivot
@@ -160,6 +162,7 @@ __global__ __launch_bounds__(kRegBlock) void k_rebuild_reg(SysParams P, Walkers<
   const int r0 = tid & 31, c0 = tid >> 5;
   const int n = sp ? P.n_dn : P.n_up, off = sp ? P.n_up : 0;
   const int N = P.N;
+  if (sel && sel[w] != sel_value) return;
   if (n == 0) {
     if (tid == 0) {
       if (drift) drift[2 * w + sp] = Wk.logdet[2 * w + sp];
@@ -322,6 +325,248 @@ __global__ __launch_bounds__(kRegBlock) void k_rebuild_reg(SysParams P, Walkers<
 }
 
 // ---------------------------------------------------------------------------
+// The same elimination, blocked, for spin blocks beyond kRegRebuildMax.  The
+// matrix stays in the FP64 scratch buffer and its columns are taken in panels
+// of PB.  A panel's PB steps run in LDS on the panel columns (pivot among the
+// unused rows, scaling, elimination, as above); every other column then takes
+// the panel's PB steps in one pass, so the matrix is read and written once per
+// panel instead of once per step.  For a column c outside the panel, with
+// col_s the panel's column s just before step s and p_t the pivot row of step t:
+//   r_t = (a[p_t][c] - sum_{s<t} col_s[p_t] r_s) / piv_t   (scaled pivot row)
+//   a[i][c] <- a[i][c] - sum_s col_s[i] r_s                 (rows not pivots here)
+//   a[p_t][c] <- r_t - sum_{s>t} col_s[p_t] r_s             (the panel's pivot rows)
+// Each entry sees the operations of the sequential elimination in the same
+// order, so the result has the same bits.
+// ---------------------------------------------------------------------------
+struct PanelLayout {
+  size_t pan, cols, pinv, prow, piv, pstep, used, total;
+};
+
+__host__ __device__ inline PanelLayout panel_layout(int n, int pb) {
+  PanelLayout L;
+  size_t o = 0;
+  L.pan = o; o += sizeof(double) * (size_t)n * pb;    // panel columns, row-major [n][pb]
+  L.cols = o; o += sizeof(double) * (size_t)pb * n;   // col_s, [pb][n]
+  L.pinv = o; o += sizeof(double) * pb;
+  L.prow = o; o += sizeof(double) * pb;
+  L.piv = o; o += sizeof(int) * (size_t)n;            // pivot row of each step
+  L.pstep = o; o += sizeof(int) * (size_t)n;          // step within the current panel, or -1
+  L.used = o; o += (size_t)n;
+  L.total = (o + 15) & ~(size_t)15;
+  return L;
+}
+
+template <typename T, int PB>
+__global__ __launch_bounds__(kBlock) void k_rebuild_panel(SysParams P, Walkers<T> Wk, double* scratch,
+                                                          double* drift, const uint32_t* sel, uint32_t sel_value) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double rv[kWaves];
+  __shared__ int ri[kWaves];
+  const int w = blockIdx.x >> 1, sp = blockIdx.x & 1, tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int n = sp ? P.n_dn : P.n_up, off = sp ? P.n_up : 0;
+  const int N = P.N;
+  if (sel && sel[w] != sel_value) return;
+  if (n == 0) {
+    if (tid == 0) {
+      if (drift) drift[2 * w + sp] = Wk.logdet[2 * w + sp];
+      Wk.logdet[2 * w + sp] = 0.0;
+      Wk.sign[2 * w + sp] = 1;
+    }
+    return;
+  }
+  const PanelLayout lay = panel_layout(n, PB);
+  double* pan = reinterpret_cast<double*>(smem + lay.pan);
+  double* cols = reinterpret_cast<double*>(smem + lay.cols);
+  double* spinv = reinterpret_cast<double*>(smem + lay.pinv);
+  double* prow = reinterpret_cast<double*>(smem + lay.prow);
+  int* spiv = reinterpret_cast<int*>(smem + lay.piv);
+  int* pstep = reinterpret_cast<int*>(smem + lay.pstep);
+  uint8_t* used = smem + lay.used;
+  const size_t boff = (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0);
+  double* a = scratch + boff;
+  double amax = 0.0;
+  for (int q = tid; q < n * n; q += kBlock) {
+    const int k = q / n, l = q - k * n;
+    const size_t item = (size_t)w * N + off + k;
+    const int cb = Wk.cur[item];
+    a[q] = Wk.val64 ? Wk.val64[((size_t)cb * P.W * N + item) * P.S + l]
+                    : (double)Wk.vgl[((size_t)cb * P.W * N + item) * kComp * P.S + l];
+    amax = fmax(amax, fabs(a[q]));
+  }
+  for (int i = tid; i < n; i += kBlock) used[i] = 0;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
+  if (lane == 0) rv[wave] = amax;
+  __syncthreads();
+  amax = fmax(fmax(rv[0], rv[1]), fmax(rv[2], rv[3]));
+  // a pivot this small relative to the largest entry means a numerically singular matrix
+  const double tiny = 1e-14 * amax;
+  __syncthreads();
+  double logabs = 0.0;
+  int sgn = 1;
+  bool singular = false;
+  for (int k0 = 0; k0 < n; k0 += PB) {
+    const int bw = min(PB, n - k0);
+    // (1) the panel's columns into LDS
+    for (int q = tid; q < n * bw; q += kBlock) {
+      const int i = q / bw, t = q - i * bw;
+      pan[i * PB + t] = a[(size_t)i * n + k0 + t];
+    }
+    for (int i = tid; i < n; i += kBlock) pstep[i] = -1;
+    __syncthreads();
+    for (int t = 0; t < bw; ++t) {
+      // pivot: largest |pan[i][t]| over the unused rows (smallest index on ties)
+      double best = -1.0;
+      int bi = n;
+      for (int i = tid; i < n; i += kBlock) {
+        const double v = fabs(pan[i * PB + t]);
+        if (!used[i] && v > best) { best = v; bi = i; }
+      }
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (lane == 0) { rv[wave] = best; ri[wave] = bi; }
+      __syncthreads();
+      best = rv[0];
+      bi = ri[0];
+      for (int q = 1; q < kWaves; ++q)
+        if (rv[q] > best || (rv[q] == best && ri[q] < bi)) { best = rv[q]; bi = ri[q]; }
+      if (!(best > tiny) || !isfinite(best)) { singular = true; break; }
+      const int p = bi;
+      const double piv = pan[p * PB + t];
+      const double pinv = 1.0 / piv;
+      if (tid == 0) {
+        logabs += log(fabs(piv));
+        if (piv < 0.0) sgn = -sgn;
+      }
+      for (int i = tid; i < n; i += kBlock) cols[t * n + i] = pan[i * PB + t];
+      if (tid < bw) prow[tid] = (tid == t) ? pinv : pan[p * PB + tid] * pinv;
+      __syncthreads();   // everyone has read the reductions, column t and the pivot row
+      if (tid == 0) {
+        spiv[k0 + t] = p;
+        pstep[p] = t;
+        used[p] = 1;
+        spinv[t] = pinv;
+      }
+      for (int q = tid; q < n * bw; q += kBlock) {
+        const int i = q / bw, tt = q - i * bw;
+        pan[i * PB + tt] = (i == p) ? prow[tt] : ((tt == t) ? 0.0 : pan[i * PB + tt]) - cols[t * n + i] * prow[tt];
+      }
+      __syncthreads();
+    }
+    if (singular) break;
+    // (2) the panel back, and its steps applied to every other column (one column per thread)
+    for (int q = tid; q < n * bw; q += kBlock) {
+      const int i = q / bw, t = q - i * bw;
+      a[(size_t)i * n + k0 + t] = pan[i * PB + t];
+    }
+    for (int c = tid; c < n; c += kBlock) {
+      if (c >= k0 && c < k0 + bw) continue;
+      double r[PB];
+#pragma unroll
+      for (int t = 0; t < PB; ++t) {
+        r[t] = 0.0;
+        if (t < bw) {
+          const int pt = spiv[k0 + t];
+          double v = a[(size_t)pt * n + c];
+#pragma unroll
+          for (int s2 = 0; s2 < t; ++s2) v = v - cols[s2 * n + pt] * r[s2];
+          r[t] = v * spinv[t];
+        }
+      }
+      constexpr int kRows = 8;   // rows in flight
+      for (int i0 = 0; i0 < n; i0 += kRows) {
+        double v[kRows];
+#pragma unroll
+        for (int u = 0; u < kRows; ++u) v[u] = a[(size_t)min(i0 + u, n - 1) * n + c];
+#pragma unroll
+        for (int u = 0; u < kRows; ++u) {
+          const int i = i0 + u;
+          if (i >= n) break;
+          const int ps = pstep[i];   // the same for every thread
+          if (ps < 0) {
+#pragma unroll
+            for (int s2 = 0; s2 < PB; ++s2)
+              if (s2 < bw) v[u] = v[u] - cols[s2 * n + i] * r[s2];
+          } else {
+            double x = 0.0;
+#pragma unroll
+            for (int t = 0; t < PB; ++t) x = (t == ps) ? r[t] : x;
+#pragma unroll
+            for (int s2 = 0; s2 < PB; ++s2)
+              if (s2 > ps && s2 < bw) x = x - cols[s2 * n + i] * r[s2];
+            v[u] = x;
+          }
+          a[(size_t)i * n + c] = v[u];
+        }
+      }
+    }
+    __syncthreads();   // the matrix is current before the next panel is read
+  }
+  int* sstep = pstep;   // reused: step at which each physical row was the pivot
+  if (!singular) {
+    for (int k = tid; k < n; k += kBlock) sstep[spiv[k]] = k;
+    __syncthreads();
+    T* B = Wk.binv + boff;
+    for (int q = tid; q < n * n; q += kBlock) {
+      const int r = q / n, c = q - r * n;
+      B[(size_t)sstep[r] * n + spiv[c]] = (T)a[q];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      // sign of the permutation k -> p_k: (-1)^(n - number of cycles)
+      int cycles = 0;
+      for (int s0 = 0; s0 < n; ++s0) {
+        if (sstep[s0] < 0) continue;
+        ++cycles;
+        for (int t = s0; sstep[t] >= 0;) {
+          const int nx = spiv[t];
+          sstep[t] = -1;
+          t = nx;
+        }
+      }
+      if ((n - cycles) & 1) sgn = -sgn;
+    }
+  }
+  if (tid == 0) {
+    if (drift) drift[2 * w + sp] = Wk.logdet[2 * w + sp] - (singular ? NAN : logabs);
+    Wk.logdet[2 * w + sp] = singular ? NAN : logabs;
+    Wk.sign[2 * w + sp] = singular ? 0 : sgn;
+    if (singular) atomicOr(Wk.status + w, 1 << sp);
+  }
+}
+
+template <typename T, int PB>
+static hipError_t launch_rebuild_panel(const SysParams& P, const Walkers<T>& Wk, double* scratch, double* drift,
+                                       hipStream_t st, const uint32_t* sel, uint32_t sel_value, size_t bytes) {
+  if (bytes > 65536) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rebuild_panel<T, PB>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_rebuild_panel<T, PB>), dim3(2 * P.W), dim3(kBlock), bytes, st, P, Wk, scratch, drift,
+                     sel, sel_value);
+  return hipGetLastError();
+}
+
+static int lds_budget_rebuild() {
+  static int budget = -1;
+  if (budget < 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+      budget = v;
+    else
+      budget = 65536;
+  }
+  return budget;
+}
+
+// ---------------------------------------------------------------------------
 // FP64 refinement of the FP32 inverses before a measurement (mixed precision).
 //
 // Between full rebuilds the FP32 rank-one and delayed updates let B drift from
@@ -477,13 +722,15 @@ template hipError_t launch_refine<float>(const SysParams&, const Walkers<float>&
 
 // max |I - A fl32(B)| of one (walker, spin), for the acceptance test of initial configurations.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_inverse_residual(SysParams P, Walkers<T> Wk, double* out) {
+__global__ __launch_bounds__(kBlock) void k_inverse_residual(SysParams P, Walkers<T> Wk, double* out,
+                                                             const uint32_t* sel, uint32_t sel_value) {
   __shared__ double sL[kTile * kLs];
   __shared__ double sR[kChunk * kRs];
   __shared__ const T* arow[kMaxSpin];
   __shared__ double wmax[kWaves];
   const int w = blockIdx.x >> 1, sp = blockIdx.x & 1, tid = threadIdx.x;
   const int n = sp ? P.n_dn : P.n_up, off = sp ? P.n_up : 0;
+  if (sel && sel[w] != sel_value) return;
   if (n == 0) {
     if (tid == 0) out[2 * w + sp] = 0.0;
     return;
@@ -514,19 +761,22 @@ __global__ __launch_bounds__(kBlock) void k_inverse_residual(SysParams P, Walker
 }
 
 template <typename T>
-hipError_t launch_inverse_residual(const SysParams& P, const Walkers<T>& Wk, double* out, hipStream_t st) {
+hipError_t launch_inverse_residual(const SysParams& P, const Walkers<T>& Wk, double* out, hipStream_t st,
+                                   const uint32_t* sel, uint32_t sel_value) {
   if (P.n_up > kMaxSpin || P.n_dn > kMaxSpin) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_inverse_residual<T>, dim3(2 * P.W), dim3(kBlock), 0, st, P, Wk, out);
+  hipLaunchKernelGGL(k_inverse_residual<T>, dim3(2 * P.W), dim3(kBlock), 0, st, P, Wk, out, sel, sel_value);
   return hipGetLastError();
 }
 
-template hipError_t launch_inverse_residual<double>(const SysParams&, const Walkers<double>&, double*, hipStream_t);
-template hipError_t launch_inverse_residual<float>(const SysParams&, const Walkers<float>&, double*, hipStream_t);
+template hipError_t launch_inverse_residual<double>(const SysParams&, const Walkers<double>&, double*, hipStream_t,
+                                                    const uint32_t*, uint32_t);
+template hipError_t launch_inverse_residual<float>(const SysParams&, const Walkers<float>&, double*, hipStream_t,
+                                                   const uint32_t*, uint32_t);
 template hipError_t launch_refine_batched<float>(const SysDev<float>*, const int2*, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_rebuild(const SysParams& P, const Walkers<T>& Wk, double* scratch, double* drift,
-                          hipStream_t st) {
+                          hipStream_t st, const uint32_t* sel, uint32_t sel_value) {
   if (P.n_up > kMaxSpin || P.n_dn > kMaxSpin) return hipErrorInvalidValue;
   const int nmax = P.n_up > P.n_dn ? P.n_up : P.n_dn;
   // QMC_REBUILD_GLOBAL=1 takes the global-memory elimination for every size (lets the
@@ -535,22 +785,28 @@ hipError_t launch_rebuild(const SysParams& P, const Walkers<T>& Wk, double* scra
   if (!(fg && fg[0] == '1') && nmax <= kRegRebuildMax) {
     const dim3 grid(2 * P.W), block(kRegBlock);
     switch ((nmax + 31) / 32) {
-      case 1: hipLaunchKernelGGL((k_rebuild_reg<T, 1>), grid, block, 0, st, P, Wk, drift); break;
-      case 2: hipLaunchKernelGGL((k_rebuild_reg<T, 2>), grid, block, 0, st, P, Wk, drift); break;
-      case 3: hipLaunchKernelGGL((k_rebuild_reg<T, 3>), grid, block, 0, st, P, Wk, drift); break;
-      case 4: hipLaunchKernelGGL((k_rebuild_reg<T, 4>), grid, block, 0, st, P, Wk, drift); break;
-      case 5: hipLaunchKernelGGL((k_rebuild_reg<T, 5>), grid, block, 0, st, P, Wk, drift); break;
-      default: hipLaunchKernelGGL((k_rebuild_reg<T, 6>), grid, block, 0, st, P, Wk, drift); break;
+      case 1: hipLaunchKernelGGL((k_rebuild_reg<T, 1>), grid, block, 0, st, P, Wk, drift, sel, sel_value); break;
+      case 2: hipLaunchKernelGGL((k_rebuild_reg<T, 2>), grid, block, 0, st, P, Wk, drift, sel, sel_value); break;
+      case 3: hipLaunchKernelGGL((k_rebuild_reg<T, 3>), grid, block, 0, st, P, Wk, drift, sel, sel_value); break;
+      case 4: hipLaunchKernelGGL((k_rebuild_reg<T, 4>), grid, block, 0, st, P, Wk, drift, sel, sel_value); break;
+      case 5: hipLaunchKernelGGL((k_rebuild_reg<T, 5>), grid, block, 0, st, P, Wk, drift, sel, sel_value); break;
+      default: hipLaunchKernelGGL((k_rebuild_reg<T, 6>), grid, block, 0, st, P, Wk, drift, sel, sel_value); break;
     }
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_rebuild<T>, dim3(2 * P.W), dim3(kBlock), 0, st, P, Wk, scratch, drift);
+  if (!(fg && fg[0] == '1')) {
+    const size_t b16 = panel_layout(nmax, 16).total, b8 = panel_layout(nmax, 8).total;
+    const size_t budget = (size_t)lds_budget_rebuild();
+    if (b16 <= budget) return launch_rebuild_panel<T, 16>(P, Wk, scratch, drift, st, sel, sel_value, b16);
+    if (b8 <= budget) return launch_rebuild_panel<T, 8>(P, Wk, scratch, drift, st, sel, sel_value, b8);
+  }
+  hipLaunchKernelGGL(k_rebuild<T>, dim3(2 * P.W), dim3(kBlock), 0, st, P, Wk, scratch, drift, sel, sel_value);
   return hipGetLastError();
 }
 
 template hipError_t launch_rebuild<double>(const SysParams&, const Walkers<double>&, double*, double*,
-                                           hipStream_t);
+                                           hipStream_t, const uint32_t*, uint32_t);
 template hipError_t launch_rebuild<float>(const SysParams&, const Walkers<float>&, double*, double*,
-                                          hipStream_t);
+                                          hipStream_t, const uint32_t*, uint32_t);
 
 }  // namespace qmc

@@ -99,14 +99,17 @@ constexpr double kInitResidual = 1e-5;
 // out[2w + sp] = max_{i,k} |delta_ik - sum_l A[i][l] fl32(B[l][k])| (FP64 products), A from the
 // current value rows (val64 when present), B the current inverse.
 template <typename T>
-hipError_t launch_inverse_residual(const SysParams& P, const Walkers<T>& Wk, double* out, hipStream_t st);
+hipError_t launch_inverse_residual(const SysParams& P, const Walkers<T>& Wk, double* out, hipStream_t st,
+                                   const uint32_t* sel = nullptr, uint32_t sel_value = 0);
 
 // Full FP64 inverse of every Slater matrix from the current value rows
 // (Gauss-Jordan with partial pivoting); scratch: W * bstride doubles.
 // drift (nullable): receives log|D|_old - log|D|_new per [W][2].
+// sel (nullable, both here and in launch_inverse_residual): only walkers w with
+// sel[w] == sel_value are processed, the others keep their results.
 template <typename T>
 hipError_t launch_rebuild(const SysParams& P, const Walkers<T>& Wk, double* scratch, double* drift,
-                          hipStream_t st);
+                          hipStream_t st, const uint32_t* sel = nullptr, uint32_t sel_value = 0);
 
 // Mixed precision: Wk.xinv = B + B (I - A B) with the FP64 Slater matrix A (from val64) and
 // FP64 products, the inverse the measurement reads; scratch: W * bstride doubles.

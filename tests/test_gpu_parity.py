@@ -139,11 +139,12 @@ def test_recompute_drift_is_tiny(gpu, orc):
 
 
 @pytest.mark.parametrize("n_elec,grid,precision", [(14, 12, "fp64"), (128, 20, "fp64"), (200, 20, "fp64"),
-                                                    (384, 24, "mixed")])
+                                                    (384, 24, "mixed"), (400, 24, "fp64"), (518, 24, "mixed")])
 def test_register_rebuild_matches_global(gpu, monkeypatch, n_elec, grid, precision):
-    """The register-resident elimination (spin blocks up to 192) against the global-memory
-    one: same pivots and operations, so the rebuilt log|D|, signs and the trajectory that
-    follows agree bit for bit."""
+    """The register-resident elimination (spin blocks up to 192) and the blocked one (larger
+    blocks, panels of 16 columns with a ragged last panel here) against the sequential
+    global-memory elimination: same pivots and operations, so the rebuilt log|D|, signs and
+    the trajectory that follows agree bit for bit."""
     runs = []
     for force_global in (True, False):
         if force_global:
