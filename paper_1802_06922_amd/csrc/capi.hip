@@ -650,27 +650,24 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
   // Rows, inverses and log|D| of the current positions.  Positions drawn here are uniform in
   // the cell; a walker's draw is redrawn (next attempt of its INIT counter) while one of its
   // Slater matrices is singular or so badly conditioned that the single-precision rounding of
-  // its inverse leaves a residual above kInitResidual.  The attempt numbers live in nacc and
-  // the residuals in drift until the first sweep.  A walker is redrawn in round r exactly when
-  // its attempt number is r, so later rounds rebuild and check only those walkers (the
-  // others' positions and rows are regenerated unchanged, their inverses are kept).
-  std::vector<uint32_t> attempt(W, 0u);
-  std::vector<double> resid((size_t)W * 2);
-  std::vector<int> status(W);
+  // its inverse leaves a residual above kInitResidual, at most kInitAttempts draws.  The
+  // attempt numbers live in nacc and the residuals in drift until the first sweep.  A walker
+  // is drawn in round r exactly when its attempt number is r, so every round draws, evaluates,
+  // rebuilds and checks only those walkers, and the decision is taken on the device: all
+  // rounds are queued without waiting for the host (rounds with nobody left are empty).
   uint32_t* d_attempt = s->nacc;
-  for (int round = 0;; ++round) {
-    if (!pos) {
-      HIP_TRY(s, hipMemcpyAsync(d_attempt, attempt.data(), W * sizeof(uint32_t), hipMemcpyHostToDevice, s->stream));
-      HIP_TRY(s, launch_init_positions(s->P, s->pos, d_attempt, s->stream));
-    }
-    HIP_TRY(s, hipMemsetAsync(s->status, 0, z.status, s->stream));
-    if (round == 0) HIP_TRY(s, hipMemsetAsync(s->logdet, 0, z.logdet, s->stream));
+  HIP_TRY(s, hipMemsetAsync(s->logdet, 0, z.logdet, s->stream));
+  if (!pos) HIP_TRY(s, hipMemsetAsync(d_attempt, 0, W * sizeof(uint32_t), s->stream));
+  const int rounds = pos ? 1 : kInitAttempts;
+  for (int round = 0; round < rounds; ++round) {
     const uint32_t* sel = pos ? nullptr : d_attempt;
+    if (!pos) HIP_TRY(s, launch_init_positions(s->P, s->pos, d_attempt, s->stream, round));
+    HIP_TRY(s, hipMemsetAsync(s->status, 0, z.status, s->stream));
     hipError_t e;
     if (s->d.precision == QMC_MIXED)
-      e = timed(s, 0, [&] { return launch_gather<float>(s->P, walkers_of<float>(s), static_cast<const float*>(s->d_table), 1, s->stream); });
+      e = timed(s, 0, [&] { return launch_gather<float>(s->P, walkers_of<float>(s), static_cast<const float*>(s->d_table), 1, s->stream, -1, sel, (uint32_t)round); });
     else
-      e = timed(s, 0, [&] { return launch_gather<double>(s->P, walkers_of<double>(s), static_cast<const double*>(s->d_table), 1, s->stream); });
+      e = timed(s, 0, [&] { return launch_gather<double>(s->P, walkers_of<double>(s), static_cast<const double*>(s->d_table), 1, s->stream, -1, sel, (uint32_t)round); });
     if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "orbital gather launch: %s", hipGetErrorString(e));
     qmc_status st = run_rebuild(s, nullptr, sel, (uint32_t)round);
     if (st != QMC_OK) return st;
@@ -678,17 +675,8 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
     e = s->d.precision == QMC_MIXED
             ? launch_inverse_residual<float>(s->P, walkers_of<float>(s), s->drift, s->stream, sel, (uint32_t)round)
             : launch_inverse_residual<double>(s->P, walkers_of<double>(s), s->drift, s->stream, sel, (uint32_t)round);
+    if (e == hipSuccess) e = launch_init_decide(W, s->drift, s->status, d_attempt, round, s->stream);
     if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "residual launch: %s", hipGetErrorString(e));
-    HIP_TRY(s, hipMemcpyAsync(resid.data(), s->drift, resid.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(s, hipMemcpyAsync(status.data(), s->status, status.size() * sizeof(int), hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(s, hipStreamSynchronize(s->stream));
-    if (round + 1 >= kInitAttempts) break;
-    bool redraw = false;
-    for (int w = 0; w < W; ++w) {
-      const double r = std::max(resid[2 * w], resid[2 * w + 1]);
-      if (status[w] || !(r <= kInitResidual)) { ++attempt[w]; redraw = true; }
-    }
-    if (!redraw) break;
   }
   qmc_status st = check_singular(s);
   s->sweep_index = 0;

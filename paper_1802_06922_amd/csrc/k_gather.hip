@@ -96,11 +96,12 @@ __device__ __forceinline__ void spline_vgl_vec(const T* __restrict__ table, cons
 template <typename T>
 __device__ __forceinline__ void gather_item(const SysParams& P, const Walkers<T>& Wk,
                                             const T* __restrict__ table, int mode, long item, int lane,
-                                            int tpi) {
+                                            int tpi, const uint32_t* sel = nullptr, uint32_t sel_value = 0) {
   constexpr int V = VecOf<T>::V;
   if (item >= (long)P.W * P.N) return;
   const uint32_t sweep = mode == 0 ? *Wk.sweep_ctr : 0u;
   const int w = (int)(item / P.N), i = (int)(item % P.N);
+  if (sel && sel[w] != sel_value) return;   // (lanes work independently: no wave operations below)
   const double* p0 = Wk.pos + item * 3;
   double r[3];
   int buf;
@@ -148,9 +149,9 @@ __device__ __forceinline__ void gather_item(const SysParams& P, const Walkers<T>
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_gather(SysParams P, Walkers<T> Wk, const T* __restrict__ table,
-                                                   int mode, int tpi_log2) {
+                                                   int mode, int tpi_log2, const uint32_t* sel, uint32_t sel_value) {
   const long item = (long)blockIdx.x * (kBlock >> tpi_log2) + (threadIdx.x >> tpi_log2);
-  gather_item<T>(P, Wk, table, mode, item, threadIdx.x & ((1 << tpi_log2) - 1), 1 << tpi_log2);
+  gather_item<T>(P, Wk, table, mode, item, threadIdx.x & ((1 << tpi_log2) - 1), 1 << tpi_log2, sel, sel_value);
 }
 
 // Several systems in one launch: block b works on items bmap[b].y .. of system bmap[b].x.
@@ -194,11 +195,12 @@ __global__ __launch_bounds__(kBlock) void k_eval_points(SysParams P, const T* __
 
 // attempt (nullable: all 0) numbers each walker's redraws; it takes the counter's sweep slot.
 __global__ __launch_bounds__(kBlock) void k_init_positions(SysParams P, double* __restrict__ pos,
-                                                           const uint32_t* __restrict__ attempt) {
+                                                           const uint32_t* __restrict__ attempt, int sel_round) {
   const long item = (long)blockIdx.x * kBlock + threadIdx.x;
   if (item >= (long)P.W * P.N) return;
   const int w = (int)(item / P.N), i = (int)(item % P.N);
   const uint32_t att = attempt ? attempt[w] : 0u;
+  if (attempt && sel_round >= 0 && att != (uint32_t)sel_round) return;
   double a0, a1, b0, b1;
   uniform_pair(P, kInit, 0, (uint32_t)w, att, (uint32_t)i, a0, a1);
   uniform_pair(P, kInit, 1, (uint32_t)w, att, (uint32_t)i, b0, b1);
@@ -215,13 +217,13 @@ int gather_tpi_log2(int nvec) {
 
 template <typename T>
 hipError_t launch_gather(const SysParams& P, const Walkers<T>& Wk, const T* table, int mode, hipStream_t st,
-                         int lanes_log2) {
+                         int lanes_log2, const uint32_t* sel, uint32_t sel_value) {
   const int nvec = P.S / VecOf<T>::V;
   const int tl = lanes_log2 >= 0 && lanes_log2 <= 6 ? lanes_log2 : gather_tpi_log2(nvec);
   const long items = (long)P.W * P.N;
   const long per_block = kBlock >> tl;
   const unsigned blocks = (unsigned)((items + per_block - 1) / per_block);
-  hipLaunchKernelGGL(k_gather<T>, dim3(blocks), dim3(kBlock), 0, st, P, Wk, table, mode, tl);
+  hipLaunchKernelGGL(k_gather<T>, dim3(blocks), dim3(kBlock), 0, st, P, Wk, table, mode, tl, sel, sel_value);
   return hipGetLastError();
 }
 
@@ -246,17 +248,35 @@ hipError_t launch_eval_points(const SysParams& P, const T* table, const double* 
   return hipGetLastError();
 }
 
-hipError_t launch_init_positions(const SysParams& P, double* pos, const uint32_t* attempt, hipStream_t st) {
+hipError_t launch_init_positions(const SysParams& P, double* pos, const uint32_t* attempt, hipStream_t st,
+                                 int sel_round) {
   const long items = (long)P.W * P.N;
   const unsigned blocks = (unsigned)((items + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_init_positions, dim3(blocks), dim3(kBlock), 0, st, P, pos, attempt);
+  hipLaunchKernelGGL(k_init_positions, dim3(blocks), dim3(kBlock), 0, st, P, pos, attempt, sel_round);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_decide(int W, const double* __restrict__ resid,
+                                                        const int* __restrict__ status, uint32_t* attempt,
+                                                        int round) {
+  const int w = blockIdx.x * kBlock + threadIdx.x;
+  if (w >= W || attempt[w] != (uint32_t)round || round + 1 >= kInitAttempts) return;
+  const double r = fmax(resid[2 * w], resid[2 * w + 1]);
+  if (status[w] || !(r <= kInitResidual)) attempt[w] = (uint32_t)round + 1u;
+}
+
+hipError_t launch_init_decide(int W, const double* resid, const int* status, uint32_t* attempt, int round,
+                              hipStream_t st) {
+  if (W <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init_decide, dim3((W + kBlock - 1) / kBlock), dim3(kBlock), 0, st, W, resid, status,
+                     attempt, round);
   return hipGetLastError();
 }
 
 template hipError_t launch_gather<double>(const SysParams&, const Walkers<double>&, const double*, int,
-                                          hipStream_t, int);
+                                          hipStream_t, int, const uint32_t*, uint32_t);
 template hipError_t launch_gather<float>(const SysParams&, const Walkers<float>&, const float*, int,
-                                         hipStream_t, int);
+                                         hipStream_t, int, const uint32_t*, uint32_t);
 template hipError_t launch_gather_batched<double>(const SysDev<double>*, const int2*, int, hipStream_t);
 template hipError_t launch_gather_batched<float>(const SysDev<float>*, const int2*, int, hipStream_t);
 template hipError_t launch_eval_points<double>(const SysParams&, const double*, const double*, int,

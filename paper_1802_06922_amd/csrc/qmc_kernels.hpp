@@ -58,9 +58,10 @@ struct SysDev {
 // to the buffer that does not hold the current row), or evaluate at the
 // current position (mode 1, written to buffer 0 and cur reset).
 // lanes_log2: lanes per proposal (log2, 0..6); negative = the default for the orbital count.
+// sel (nullable): only the walkers w with sel[w] == sel_value are evaluated.
 template <typename T>
 hipError_t launch_gather(const SysParams& P, const Walkers<T>& Wk, const T* table, int mode, hipStream_t st,
-                         int lanes_log2 = -1);
+                         int lanes_log2 = -1, const uint32_t* sel = nullptr, uint32_t sel_value = 0);
 // Several systems' proposals in one launch; bmap[b] = (system, first item of block b).
 template <typename T>
 hipError_t launch_gather_batched(const SysDev<T>* sd, const int2* bmap, int n_blocks, hipStream_t st);
@@ -91,11 +92,18 @@ hipError_t launch_chain_delayed_batched(const SysDev<T>* sd, const int2* bmap, i
                                         int use_mfma, size_t lds, hipStream_t st);
 
 // Initial positions from the INIT stream; attempt[W] (nullable) numbers each walker's redraw.
-hipError_t launch_init_positions(const SysParams& P, double* pos, const uint32_t* attempt, hipStream_t st);
+// With sel_round >= 0 only the walkers whose attempt number equals it are drawn.
+hipError_t launch_init_positions(const SysParams& P, double* pos, const uint32_t* attempt, hipStream_t st,
+                                 int sel_round = -1);
 // Initial configurations: initial draws are redrawn while a Slater matrix is singular or the
 // single-precision rounding of its inverse leaves a residual above kInitResidual.
 constexpr int kInitAttempts = 16;
 constexpr double kInitResidual = 1e-5;
+// After round `round` of the initial draws: every walker drawn in that round (attempt[w] ==
+// round) whose matrices are singular (status) or whose residual (resid[2w], resid[2w+1])
+// exceeds kInitResidual moves to the next attempt, unless round is the last.
+hipError_t launch_init_decide(int W, const double* resid, const int* status, uint32_t* attempt, int round,
+                              hipStream_t st);
 // out[2w + sp] = max_{i,k} |delta_ik - sum_l A[i][l] fl32(B[l][k])| (FP64 products), A from the
 // current value rows (val64 when present), B the current inverse.
 template <typename T>
