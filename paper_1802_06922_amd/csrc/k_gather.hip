@@ -147,11 +147,21 @@ __device__ __forceinline__ void gather_item(const SysParams& P, const Walkers<T>
   }
 }
 
+// The sweep's proposals (mode 0).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_gather(SysParams P, Walkers<T> Wk, const T* __restrict__ table,
-                                                   int mode, int tpi_log2, const uint32_t* sel, uint32_t sel_value) {
+                                                   int tpi_log2) {
   const long item = (long)blockIdx.x * (kBlock >> tpi_log2) + (threadIdx.x >> tpi_log2);
-  gather_item<T>(P, Wk, table, mode, item, threadIdx.x & ((1 << tpi_log2) - 1), 1 << tpi_log2, sel, sel_value);
+  gather_item<T>(P, Wk, table, 0, item, threadIdx.x & ((1 << tpi_log2) - 1), 1 << tpi_log2);
+}
+
+// Rows at the current positions (mode 1: walker initialisation), optionally for the selected
+// walkers only; a kernel of its own so that profiles keep it apart from the sweeps.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gather_current(SysParams P, Walkers<T> Wk, const T* __restrict__ table,
+                                                           int tpi_log2, const uint32_t* sel, uint32_t sel_value) {
+  const long item = (long)blockIdx.x * (kBlock >> tpi_log2) + (threadIdx.x >> tpi_log2);
+  gather_item<T>(P, Wk, table, 1, item, threadIdx.x & ((1 << tpi_log2) - 1), 1 << tpi_log2, sel, sel_value);
 }
 
 // Several systems in one launch: block b works on items bmap[b].y .. of system bmap[b].x.
@@ -223,7 +233,10 @@ hipError_t launch_gather(const SysParams& P, const Walkers<T>& Wk, const T* tabl
   const long items = (long)P.W * P.N;
   const long per_block = kBlock >> tl;
   const unsigned blocks = (unsigned)((items + per_block - 1) / per_block);
-  hipLaunchKernelGGL(k_gather<T>, dim3(blocks), dim3(kBlock), 0, st, P, Wk, table, mode, tl, sel, sel_value);
+  if (mode == 0)
+    hipLaunchKernelGGL(k_gather<T>, dim3(blocks), dim3(kBlock), 0, st, P, Wk, table, tl);
+  else
+    hipLaunchKernelGGL(k_gather_current<T>, dim3(blocks), dim3(kBlock), 0, st, P, Wk, table, tl, sel, sel_value);
   return hipGetLastError();
 }
 

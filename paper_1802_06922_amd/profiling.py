@@ -71,10 +71,16 @@ def pmc_md(title: str, cmd: str, paths) -> str:
 
 
 def _kernel_mean(path: str, kernel: str, counter: str) -> float:
-    vals = [v[counter] for k, v in _pmc_means(path).items() if kernel in k and counter in v]
-    if not vals:
+    """Mean counter value over the dispatches of the kernel that have the launch shape (grid
+    size) of its last dispatch: the timed sweeps, not the walker initialisation, which launches
+    the same kernel in another shape."""
+    rows = [r for r in csv.DictReader(open(path))
+            if kernel in _short(r["Kernel_Name"]) and r["Counter_Name"] == counter]
+    if not rows:
         raise ValueError(f"no {counter} for a kernel matching {kernel!r} in {path}")
-    return vals[0]
+    last = max(rows, key=lambda r: int(r["Dispatch_Id"]))
+    vals = [float(r["Counter_Value"]) for r in rows if r["Grid_Size"] == last["Grid_Size"]]
+    return sum(vals) / len(vals)
 
 
 def _copy_total(path: str, counter: str) -> float:

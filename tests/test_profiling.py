@@ -5,18 +5,25 @@ from paper_1802_06922_amd import profiling
 
 
 def _pmc(path, rows):
+    """rows: (kernel, counter, value) or (kernel, counter, value, grid size); dispatch ids in order."""
     with open(path, "w", newline="") as f:
-        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Grid_Size", "Kernel_Name", "Counter_Name",
+                                          "Counter_Value"])
         w.writeheader()
-        for k, c, v in rows:
-            w.writerow({"Kernel_Name": k, "Counter_Name": c, "Counter_Value": v})
+        for d, row in enumerate(rows):
+            k, c, v = row[:3]
+            grid = row[3] if len(row) > 3 else 1024
+            w.writerow({"Dispatch_Id": d + 1, "Grid_Size": grid, "Kernel_Name": k, "Counter_Name": c,
+                        "Counter_Value": v})
 
 
 def test_traffic_record_scales_by_the_copy(tmp_path):
     g = "void qmc::k_gather<double>(qmc::SysParams, ...)"
-    _pmc(tmp_path / "f.csv", [(g, "FETCH_SIZE", 1000.0), (g, "FETCH_SIZE", 1200.0),
+    # two initialisation launches of another shape (ignored), then the timed launches
+    _pmc(tmp_path / "f.csv", [(g, "FETCH_SIZE", 9000.0, 2048), (g, "FETCH_SIZE", 7.0, 2048),
+                              (g, "FETCH_SIZE", 1000.0), (g, "FETCH_SIZE", 1200.0),
                               ("qmc::k_chain", "FETCH_SIZE", 5.0)])
-    _pmc(tmp_path / "w.csv", [(g, "WRITE_SIZE", 300.0)])
+    _pmc(tmp_path / "w.csv", [(g, "WRITE_SIZE", 50.0, 2048), (g, "WRITE_SIZE", 300.0)])
     copy = 1 << 30
     # a copy whose FETCH_SIZE reads half the bytes moved and whose WRITE_SIZE reads all of them
     _pmc(tmp_path / "cf.csv", [("elementwise_copy", "FETCH_SIZE", copy / 2048.0)] * 3)
