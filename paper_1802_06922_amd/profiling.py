@@ -4,6 +4,9 @@
         Markdown table of a ``rocprofv3 --kernel-trace --stats`` run.
     python -m paper_1802_06922_amd.profiling pmc <title> <command> <counter_collection.csv>...
         Markdown table of ``rocprofv3 --pmc`` passes (mean counter value per dispatch).
+    python -m paper_1802_06922_amd.profiling mfma <title> <command> <counter_collection.csv> <kernel>
+        Markdown table of a kernel's matrix-core use (SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE,
+        SQ_INSTS_VALU_MFMA_MOPS_F64 / _F32 in one pass).
     python -m paper_1802_06922_amd.profiling traffic <workload> <kernel> <fetch.csv> <write.csv>
             <copy_fetch.csv> <copy_write.csv> <copy_bytes> <command>...
         JSON record of a kernel's HBM traffic per dispatch: FETCH_SIZE and WRITE_SIZE (KiB) of
@@ -70,6 +73,38 @@ def pmc_md(title: str, cmd: str, paths) -> str:
     return "\n".join(out) + "\n"
 
 
+def mfma_md(title: str, cmd: str, path: str, kernel: str, simd_num: int = 1024) -> str:
+    """Matrix-core use of one kernel from a pass with SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE
+    and SQ_INSTS_VALU_MFMA_MOPS_F64 / _F32: utilisation = busy cycles / (active cycles x SIMDs),
+    flops = MOPS x 512, rate = flops / dispatch duration (from the dispatch timestamps)."""
+    per = collections.defaultdict(dict)
+    dur = {}
+    for r in csv.DictReader(open(path)):
+        if kernel not in _short(r["Kernel_Name"]):
+            continue
+        d = int(r["Dispatch_Id"])
+        per[d][r["Counter_Name"]] = float(r["Counter_Value"])
+        dur[d] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    if not per:
+        raise ValueError(f"no dispatch of a kernel matching {kernel!r} in {path}")
+    util, f64, f32, rate = [], [], [], []
+    for d, c in per.items():
+        busy, act = c.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0), c.get("GRBM_GUI_ACTIVE", 0.0)
+        util.append(100.0 * busy / (act * simd_num) if act > 0 else 0.0)
+        a, b = 512.0 * c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0), 512.0 * c.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0)
+        f64.append(a)
+        f32.append(b)
+        rate.append((a + b) / dur[d] / 1e12 if dur[d] > 0 else 0.0)
+    n = len(per)
+    out = [f"# {title}\n", "Command (from the repository root, one MI355X):\n", f"```\n{cmd}\n```\n",
+           "| kernel | dispatches | MFMA busy (% of SIMD cycles) | FP64 MFMA GFLOP / dispatch | "
+           "FP32 MFMA GFLOP / dispatch | MFMA TFLOP/s (dispatch time) |",
+           "|---|---|---|---|---|---|",
+           f"| `{kernel}` | {n} | {sum(util) / n:.2f} | {sum(f64) / n / 1e9:.3f} | {sum(f32) / n / 1e9:.3f} | "
+           f"{sum(rate) / n:.2f} |"]
+    return "\n".join(out) + "\n"
+
+
 def _kernel_mean(path: str, kernel: str, counter: str) -> float:
     """Mean counter value over the dispatches of the kernel that have the launch shape (grid
     size) of its last dispatch: the timed sweeps, not the walker initialisation, which launches
@@ -125,6 +160,8 @@ def main(argv) -> int:
         print(stats_md(rest[0], rest[1], rest[2]), end="")
     elif cmd == "pmc":
         print(pmc_md(rest[0], rest[1], rest[2:]), end="")
+    elif cmd == "mfma":
+        print(mfma_md(rest[0], rest[1], rest[2], rest[3]), end="")
     elif cmd == "traffic":
         d = traffic_json(rest[0], rest[1], rest[2], rest[3], rest[4], rest[5], int(rest[6]), rest[7:])
         print(json.dumps(d, indent=1))
