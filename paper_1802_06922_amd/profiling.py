@@ -73,10 +73,12 @@ def pmc_md(title: str, cmd: str, paths) -> str:
     return "\n".join(out) + "\n"
 
 
-def mfma_md(title: str, cmd: str, path: str, kernel: str, simd_num: int = 1024) -> str:
+def mfma_md(title: str, cmd: str, path: str, kernel: str, simd_num: int = 1024, n_xcd: int = 8) -> str:
     """Matrix-core use of one kernel from a pass with SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE
     and SQ_INSTS_VALU_MFMA_MOPS_F64 / _F32: utilisation = busy cycles / (active cycles x SIMDs),
-    flops = MOPS x 512, rate = flops / dispatch duration (from the dispatch timestamps)."""
+    with the per-dispatch GRBM_GUI_ACTIVE, which the collection sums over the n_xcd dies, taken
+    per die (rocprof's own MFMA utilisation takes its maximum over them); flops = MOPS x 512,
+    rate = flops / dispatch duration (from the dispatch timestamps)."""
     per = collections.defaultdict(dict)
     dur = {}
     for r in csv.DictReader(open(path)):
@@ -90,7 +92,7 @@ def mfma_md(title: str, cmd: str, path: str, kernel: str, simd_num: int = 1024) 
     util, f64, f32, rate = [], [], [], []
     for d, c in per.items():
         busy, act = c.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0), c.get("GRBM_GUI_ACTIVE", 0.0)
-        util.append(100.0 * busy / (act * simd_num) if act > 0 else 0.0)
+        util.append(100.0 * busy / (act / n_xcd * simd_num) if act > 0 else 0.0)
         a, b = 512.0 * c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0), 512.0 * c.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0)
         f64.append(a)
         f32.append(b)
