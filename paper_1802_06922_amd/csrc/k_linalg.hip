@@ -573,11 +573,13 @@ static int lds_budget_rebuild() {
 // A^-1 by a few FP32 units times the conditioning of A; the kinetic energy sums
 // B[l][k] times orbital Laplacians with heavy cancellation, so that drift can
 // reach 1e-4 of the energy.  One correction step X = B + B (I - A B), with the
-// FP64 Slater matrix A and all products in FP64, squares the relative error of
-// the inverse.  Both products run on the FP64 matrix cores in 64 x 64 output
-// tiles staged through LDS; the residual I - A B goes to an FP64 scratch
-// matrix, X to the buffer the measurement reads (binv itself is not changed,
-// so a measurement never alters the chain).
+// FP64 Slater matrix A, squares the relative error of the inverse.  The residual
+// E = I - A B cancels to ~1e-6 and is formed on the FP64 matrix cores; the
+// correction B E is that small relative to B, so it is formed on the FP32
+// matrix cores from E rounded to FP32 (its rounding is far below that of the
+// FP32 X).  Both products run in 64 x 64 output tiles staged through LDS; E
+// goes to the scratch buffer, X to the buffer the measurement reads (binv
+// itself is not changed, so a measurement never alters the chain).
 // ---------------------------------------------------------------------------
 constexpr int kTile = 64, kChunk = 32;
 constexpr int kLs = kChunk + 1;    // padded LDS row strides (fewer bank conflicts)
@@ -588,9 +590,9 @@ constexpr int kPerThread = kTile * kChunk / kBlock;   // panel entries each thre
 // result.  All threads of the block call it; each wave owns a 32 x 32 quadrant of a
 // 64 x 64 output tile.  The panels of the next k-chunk are loaded into registers while
 // the matrix cores work on the current chunk from LDS.
-template <typename LF, typename RF, typename EF>
-__device__ __forceinline__ void gemm64(int n, LF Lf, RF Rf, EF epi, double* sL, double* sR) {
-  typedef Mfma<double> M;
+template <typename V, typename LF, typename RF, typename EF>
+__device__ __forceinline__ void gemm_tiles(int n, LF Lf, RF Rf, EF epi, V* sL, V* sR) {
+  typedef Mfma<V> M;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
@@ -598,12 +600,12 @@ __device__ __forceinline__ void gemm64(int n, LF Lf, RF Rf, EF epi, double* sL, 
   const int nc = (n + kChunk - 1) / kChunk;
   for (int t = 0; t < nt * nt; ++t) {
     const int i0 = (t / nt) * kTile, k0 = (t % nt) * kTile;
-    M::v4 acc[2][2];
+    typename M::v4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = M::v4{0.0, 0.0, 0.0, 0.0};
-    double rl[kPerThread], rr[kPerThread];
+      for (int b = 0; b < 2; ++b) acc[a][b] = typename M::v4{V(0), V(0), V(0), V(0)};
+    V rl[kPerThread], rr[kPerThread];
     auto fetch = [&](int l0) {
 #pragma unroll
       for (int e = 0; e < kPerThread; ++e) {
@@ -611,12 +613,12 @@ __device__ __forceinline__ void gemm64(int n, LF Lf, RF Rf, EF epi, double* sL, 
         const int r = q / kChunk, c = q % kChunk;          // left panel: row r, column c
         // unconditional loads from clamped indices, out-of-range entries zeroed
         const int i = i0 + r, l = l0 + c;
-        const double vl = Lf(i < n ? i : n - 1, l < n ? l : n - 1);
-        rl[e] = (i < n && l < n) ? vl : 0.0;
+        const V vl = Lf(i < n ? i : n - 1, l < n ? l : n - 1);
+        rl[e] = (i < n && l < n) ? vl : V(0);
         const int rr2 = q / kTile, cc = q % kTile;         // right panel: row rr2, column cc
         const int l2 = l0 + rr2, k = k0 + cc;
-        const double vr = Rf(l2 < n ? l2 : n - 1, k < n ? k : n - 1);
-        rr[e] = (l2 < n && k < n) ? vr : 0.0;
+        const V vr = Rf(l2 < n ? l2 : n - 1, k < n ? k : n - 1);
+        rr[e] = (l2 < n && k < n) ? vr : V(0);
       }
     };
     fetch(0);
@@ -633,10 +635,10 @@ __device__ __forceinline__ void gemm64(int n, LF Lf, RF Rf, EF epi, double* sL, 
       for (int kk = 0; kk < kChunk; kk += 4) {
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
-          const double av = sL[(wr + 16 * a + li) * kLs + kk + lk];
+          const V av = sL[(wr + 16 * a + li) * kLs + kk + lk];
 #pragma unroll
           for (int b = 0; b < 2; ++b) {
-            const double bv = sR[(kk + lk) * kRs + wc + 16 * b + li];
+            const V bv = sR[(kk + lk) * kRs + wc + 16 * b + li];
             acc[a][b] = M::mma(av, bv, acc[a][b]);
           }
         }
@@ -655,6 +657,12 @@ __device__ __forceinline__ void gemm64(int n, LF Lf, RF Rf, EF epi, double* sL, 
   }
 }
 
+// The FP64 product.
+template <typename LF, typename RF, typename EF>
+__device__ __forceinline__ void gemm64(int n, LF Lf, RF Rf, EF epi, double* sL, double* sR) {
+  gemm_tiles<double>(n, Lf, Rf, epi, sL, sR);
+}
+
 template <typename T>
 __device__ __forceinline__ void refine_spin(const SysParams& P, const Walkers<T>& Wk, double* scratch, int w,
                                             int sp) {
@@ -667,21 +675,24 @@ __device__ __forceinline__ void refine_spin(const SysParams& P, const Walkers<T>
   const size_t boff = (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0);
   const T* B = Wk.binv + boff;
   T* X = Wk.xinv + boff;
-  double* E = scratch + boff;
+  float* E = reinterpret_cast<float*>(scratch + boff);
   for (int i = threadIdx.x; i < n; i += kBlock) {
     const size_t item = (size_t)w * N + off + i;
     arow[i] = Wk.val64 + ((size_t)Wk.cur[item] * P.W * N + item) * P.S;
   }
   __syncthreads();
-  // E = I - A B
+  // E = I - A B in FP64 (A B is the identity up to ~1e-6: the difference needs FP64 products);
+  // E itself is small and is kept in FP32
   gemm64(n, [&](int i, int l) { return arow[i][l]; },
          [&](int l, int k) { return (double)B[(size_t)l * n + k]; },
-         [&](int i, int k, double c) { E[(size_t)i * n + k] = (i == k ? 1.0 : 0.0) - c; }, sL, sR);
+         [&](int i, int k, double c) { E[(size_t)i * n + k] = (float)((i == k ? 1.0 : 0.0) - c); }, sL, sR);
   __syncthreads();   // E (global) complete before it is read
-  // X = B + B E
-  gemm64(n, [&](int i, int l) { return (double)B[(size_t)i * n + l]; },
-         [&](int l, int k) { return E[(size_t)l * n + k]; },
-         [&](int i, int k, double c) { X[(size_t)i * n + k] = (T)((double)B[(size_t)i * n + k] + c); }, sL, sR);
+  // X = B + B E: the correction B E is ~1e-6 of B, so FP32 products (relative error ~1e-5 of
+  // the correction, ~1e-11 of X) are far inside the FP32 rounding of the stored X
+  gemm_tiles<float>(n, [&](int i, int l) { return (float)B[(size_t)i * n + l]; },
+                    [&](int l, int k) { return E[(size_t)l * n + k]; },
+                    [&](int i, int k, float c) { X[(size_t)i * n + k] = (T)((double)B[(size_t)i * n + k] + (double)c); },
+                    reinterpret_cast<float*>(sL), reinterpret_cast<float*>(sR));
 }
 
 template <typename T>
