@@ -202,7 +202,7 @@ qmc_status qmc_kernel_timing(qmc_system s, int32_t kernel_class, double* total_m
 qmc_status qmc_set_delay_rank(qmc_system s, int32_t delay_rank);
 
 /* Gather autotuner: times the orbital gather (section "B-spline basis sets")
- * with 1/2, 1, 2 and 4 times the default number of lanes per proposal (lanes
+ * with 1/4, 1/2, 1, 2 and 4 times the default number of lanes per proposal (lanes
  * split a proposal's orbitals, never a sum, so every width gives the same
  * rows bit for bit), trial_sweeps (>= 2; the first untimed) ordinary sweeps
  * each, and keeps the fastest for later sweeps and batches.  best_lanes_log2,

@@ -885,7 +885,7 @@ qmc_status qmc_autotune_gather(qmc_system s, int32_t trial_sweeps, int32_t* best
   s->timing = true;
   int best = -1;
   double best_t = 0.0;
-  for (int tl = base - 1; tl <= base + 2; ++tl) {
+  for (int tl = base - 2; tl <= base + 2; ++tl) {
     if (tl < 0 || tl > 6) continue;
     s->gather_lanes_log2 = tl;
     qmc_status st = qmc_sweep(s, 1, nullptr);   // untimed: first use of this width
