@@ -8,7 +8,10 @@
 #include <cstdlib>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
+#include <set>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "qmc_kernels.hpp"
@@ -409,7 +412,39 @@ qmc_status validate(const qmc_system_desc* d) {
 
 }  // namespace
 
+namespace qmc {
+
+hipError_t allow_dynamic_lds(const void* kernel) {
+  static std::mutex mu;
+  static std::set<std::pair<const void*, int>> done;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  if (done.count({kernel, dev})) return hipSuccess;
+  hipFuncAttributes a;
+  e = hipFuncGetAttributes(&a, kernel);
+  if (e != hipSuccess) return e;
+  int max = 0;
+  e = hipDeviceGetAttribute(&max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, max - (int)a.sharedSizeBytes);
+  if (e == hipSuccess) done.insert({kernel, dev});
+  return e;
+}
+
+hipError_t prepare_dynamic_lds() {
+  hipError_t e = chain_lds_limits();
+  if (e == hipSuccess) e = delayed_lds_limits();
+  if (e == hipSuccess) e = linalg_lds_limits();
+  if (e == hipSuccess) e = measure_lds_limits();
+  return e;
+}
+
+}  // namespace qmc
+
 extern "C" {
+
 
 qmc_status qmc_create_system(const qmc_system_desc* desc, void* hip_stream, qmc_system* out) {
   if (!out) return fail(nullptr, QMC_ERR_ARG, "out is NULL");
@@ -428,6 +463,13 @@ qmc_status qmc_create_system(const qmc_system_desc* desc, void* hip_stream, qmc_
   if (hipGetDevice(&s->device) != hipSuccess) {
     delete s;
     return fail(nullptr, QMC_ERR_DEVICE, "no HIP device");
+  }
+  {
+    const hipError_t e = prepare_dynamic_lds();
+    if (e != hipSuccess) {
+      delete s;
+      return fail(nullptr, QMC_ERR_DEVICE, "raising the kernels' dynamic LDS limits failed: %s", hipGetErrorString(e));
+    }
   }
   if (desc->arena) {
     s->mem.arena = static_cast<char*>(desc->arena);

@@ -317,8 +317,7 @@ template <typename T, bool BLDS, int VPT>
 static hipError_t launch_chain_variant(const SysParams& P, const Walkers<T>& Wk, hipStream_t st,
                                        size_t bytes, int ldl) {
   if (bytes > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chain<T, BLDS, VPT>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const hipError_t e = allow_dynamic_lds(reinterpret_cast<const void*>(&k_chain<T, BLDS, VPT>));
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL((k_chain<T, BLDS, VPT>), dim3(P.W), dim3(kBlock), bytes, st, P, Wk, ldl);
@@ -354,5 +353,20 @@ hipError_t launch_chain(const SysParams& P, const Walkers<T>& Wk, hipStream_t st
 
 template hipError_t launch_chain<double>(const SysParams&, const Walkers<double>&, hipStream_t);
 template hipError_t launch_chain<float>(const SysParams&, const Walkers<float>&, hipStream_t);
+
+hipError_t chain_lds_limits() {
+  const void* ks[] = {
+      reinterpret_cast<const void*>(&k_chain<double, true, 1>), reinterpret_cast<const void*>(&k_chain<double, true, 2>),
+      reinterpret_cast<const void*>(&k_chain<double, true, 4>), reinterpret_cast<const void*>(&k_chain<double, false, 1>),
+      reinterpret_cast<const void*>(&k_chain<double, false, 2>), reinterpret_cast<const void*>(&k_chain<double, false, 4>),
+      reinterpret_cast<const void*>(&k_chain<float, true, 1>), reinterpret_cast<const void*>(&k_chain<float, true, 2>),
+      reinterpret_cast<const void*>(&k_chain<float, true, 4>), reinterpret_cast<const void*>(&k_chain<float, false, 1>),
+      reinterpret_cast<const void*>(&k_chain<float, false, 2>), reinterpret_cast<const void*>(&k_chain<float, false, 4>)};
+  for (const void* k : ks) {
+    const hipError_t e = allow_dynamic_lds(k);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 }  // namespace qmc

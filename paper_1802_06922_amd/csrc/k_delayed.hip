@@ -690,8 +690,7 @@ template <typename T, bool BLDS, bool MF>
 static hipError_t launch_delayed_variant(const SysParams& P, const Walkers<T>& Wk, int K, hipStream_t st,
                                          size_t bytes, int ldl) {
   if (bytes > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chain_delayed<T, BLDS, MF>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const hipError_t e = allow_dynamic_lds(reinterpret_cast<const void*>(&k_chain_delayed<T, BLDS, MF>));
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL((k_chain_delayed<T, BLDS, MF>), dim3(P.W), dim3(kBlock), bytes, st, P, Wk, K, ldl);
@@ -735,8 +734,7 @@ template <typename T, bool BLDS, bool MF>
 static hipError_t launch_delayed_batched_variant(const SysDev<T>* sd, const int2* bmap, int n_blocks, size_t lds,
                                                  hipStream_t st) {
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chain_delayed_batched<T, BLDS, MF>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const hipError_t e = allow_dynamic_lds(reinterpret_cast<const void*>(&k_chain_delayed_batched<T, BLDS, MF>));
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL((k_chain_delayed_batched<T, BLDS, MF>), dim3(n_blocks), dim3(kBlock), lds, st, sd, bmap);
@@ -761,5 +759,27 @@ template hipError_t launch_chain_delayed_batched<double>(const SysDev<double>*, 
                                                          hipStream_t);
 template hipError_t launch_chain_delayed_batched<float>(const SysDev<float>*, const int2*, int, bool, int, size_t,
                                                         hipStream_t);
+
+template <typename T>
+static hipError_t delayed_lds_limits_t() {
+  const void* ks[] = {reinterpret_cast<const void*>(&k_chain_delayed<T, true, true>),
+                      reinterpret_cast<const void*>(&k_chain_delayed<T, true, false>),
+                      reinterpret_cast<const void*>(&k_chain_delayed<T, false, true>),
+                      reinterpret_cast<const void*>(&k_chain_delayed<T, false, false>),
+                      reinterpret_cast<const void*>(&k_chain_delayed_batched<T, true, true>),
+                      reinterpret_cast<const void*>(&k_chain_delayed_batched<T, true, false>),
+                      reinterpret_cast<const void*>(&k_chain_delayed_batched<T, false, true>),
+                      reinterpret_cast<const void*>(&k_chain_delayed_batched<T, false, false>)};
+  for (const void* k : ks) {
+    const hipError_t e = allow_dynamic_lds(k);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t delayed_lds_limits() {
+  const hipError_t e = delayed_lds_limits_t<double>();
+  return e != hipSuccess ? e : delayed_lds_limits_t<float>();
+}
 
 }  // namespace qmc

@@ -544,8 +544,7 @@ template <typename T, int PB>
 static hipError_t launch_rebuild_panel(const SysParams& P, const Walkers<T>& Wk, double* scratch, double* drift,
                                        hipStream_t st, const uint32_t* sel, uint32_t sel_value, size_t bytes) {
   if (bytes > 65536) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rebuild_panel<T, PB>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const hipError_t e = allow_dynamic_lds(reinterpret_cast<const void*>(&k_rebuild_panel<T, PB>));
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL((k_rebuild_panel<T, PB>), dim3(2 * P.W), dim3(kBlock), bytes, st, P, Wk, scratch, drift,
@@ -819,5 +818,17 @@ template hipError_t launch_rebuild<double>(const SysParams&, const Walkers<doubl
                                            hipStream_t, const uint32_t*, uint32_t);
 template hipError_t launch_rebuild<float>(const SysParams&, const Walkers<float>&, double*, double*,
                                           hipStream_t, const uint32_t*, uint32_t);
+
+hipError_t linalg_lds_limits() {
+  const void* ks[] = {reinterpret_cast<const void*>(&k_rebuild_panel<double, 16>),
+                      reinterpret_cast<const void*>(&k_rebuild_panel<double, 8>),
+                      reinterpret_cast<const void*>(&k_rebuild_panel<float, 16>),
+                      reinterpret_cast<const void*>(&k_rebuild_panel<float, 8>)};
+  for (const void* k : ks) {
+    const hipError_t e = allow_dynamic_lds(k);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 }  // namespace qmc

@@ -385,8 +385,7 @@ hipError_t launch_measure_batched(const SysDev<T>* sd, const int2* bmap, int n_b
                                   int n_walkers, size_t lds, hipStream_t st) {
   if (n_blocks <= 0) return hipSuccess;
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_measure_batched<T>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const hipError_t e = allow_dynamic_lds(reinterpret_cast<const void*>(&k_measure_batched<T>));
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_measure_batched<T>, dim3(n_blocks), dim3(kBlock), lds, st, sd, bmap);
@@ -408,8 +407,7 @@ hipError_t launch_measure(const SysParams& P, const Walkers<T>& Wk, const EwaldP
   const int np = measure_parts(P.W);
   const size_t bytes = measure_layout(P.N, np).total;
   if (bytes > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_measure<T>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const hipError_t e = allow_dynamic_lds(reinterpret_cast<const void*>(&k_measure<T>));
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_measure<T>, dim3(P.W * np), dim3(kBlock), bytes, st, P, Wk, E, partial, np);
@@ -424,5 +422,16 @@ template hipError_t launch_measure<double>(const SysParams&, const Walkers<doubl
                                            double*, hipStream_t);
 template hipError_t launch_measure<float>(const SysParams&, const Walkers<float>&, const EwaldParams&, double*,
                                           double*, hipStream_t);
+
+hipError_t measure_lds_limits() {
+  const void* ks[] = {reinterpret_cast<const void*>(&k_measure<double>), reinterpret_cast<const void*>(&k_measure<float>),
+                      reinterpret_cast<const void*>(&k_measure_batched<double>),
+                      reinterpret_cast<const void*>(&k_measure_batched<float>)};
+  for (const void* k : ks) {
+    const hipError_t e = allow_dynamic_lds(k);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 }  // namespace qmc

@@ -91,6 +91,18 @@ template <typename T>
 hipError_t launch_chain_delayed_batched(const SysDev<T>* sd, const int2* bmap, int n_blocks, bool b_in_lds,
                                         int use_mfma, size_t lds, hipStream_t st);
 
+// Dynamic LDS above 64 KiB needs a per-kernel limit.  allow_dynamic_lds raises it once per
+// kernel and device, to what the device allows beside the kernel's static LDS; later calls
+// only look it up.  prepare_dynamic_lds raises it for every kernel that can need it, at
+// system creation: an attribute call made while another thread captures a graph can
+// invalidate that capture, so none is made on the launch path once systems exist.
+hipError_t allow_dynamic_lds(const void* kernel);
+hipError_t prepare_dynamic_lds();
+hipError_t chain_lds_limits();
+hipError_t delayed_lds_limits();
+hipError_t linalg_lds_limits();
+hipError_t measure_lds_limits();
+
 // Initial positions from the INIT stream; attempt[W] (nullable) numbers each walker's redraw.
 // With sel_round >= 0 only the walkers whose attempt number equals it are drawn.
 hipError_t launch_init_positions(const SysParams& P, double* pos, const uint32_t* attempt, hipStream_t st,
