@@ -93,6 +93,9 @@ def main(argv=None) -> int:
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the mixed-vs-FP64 comparison on the 384-electron system")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--serial", action="store_true",
+                    help="single: sweep and measurement calls in turn instead of pipelined steps "
+                         "(each kernel then runs alone: the gather's own roofline)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -114,7 +117,7 @@ def main(argv=None) -> int:
     if args.mode == "copy":
         return copy_reference()
     wl = qi.WORKLOADS[args.workload]()
-    r = run_single(wl, args.steps, args.warmup, args.delay, args.gather_lanes)
+    r = run_single(wl, args.steps, args.warmup, args.delay, args.gather_lanes, serial=args.serial)
     W, N = r["walkers"], wl.n_elec
     kt = r["kt"]
     b = wl.coefs.dtype.itemsize
@@ -138,12 +141,17 @@ def main(argv=None) -> int:
         "config": {"workload": describe(wl), "walkers": W, "electrons": N, "orbitals": wl.n_orb,
                    "grid": list(wl.grid), "delay_rank": r["delay_rank"],
                    "gather_lanes_log2": r["gather_lanes_log2"],
-                   "step": "1 sweep (N moves per walker) + local energy"},
+                   "step": "1 sweep (N moves per walker) + local energy",
+                   "steps_run": "sweep and measurement calls in turn" if args.serial else
+                   "pipelined (a step's measurement beside the next step's proposals)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(wl),
                      "kernel": "k_gather (proposal + tricubic B-spline VGL of every orbital)",
                      "bytes_per_launch": bytes_per_move * W * N,
-                     "avg_launch_ms": avg_gather_s * 1e3},
+                     "avg_launch_ms": avg_gather_s * 1e3,
+                     "launches": "alone (--serial)" if args.serial else
+                     "beside the previous step's local-energy kernels (shared compute units and "
+                     "HBM; --serial times the gather alone)"},
         "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
         "rebuilds_in_timed_steps": r["rebuilds"],
         "sweep_only_moves_per_s": r["sweep_only_moves_per_s"],
@@ -158,7 +166,7 @@ def main(argv=None) -> int:
     return 0
 
 
-def run_single(wl, steps: int, warmup: int, delay, lanes=None):
+def run_single(wl, steps: int, warmup: int, delay, lanes=None, serial: bool = False):
     """Steps of (sweep + local energy) of one system; the delay rank is autotuned when not given
     (the trial sweeps are ordinary sweeps, before the timed region)."""
     import torch
@@ -183,10 +191,19 @@ def run_single(wl, steps: int, warmup: int, delay, lanes=None):
     else:
         K = delay
     W, N = s.W, wl.n_elec
-    energies = torch.empty((W, 4), dtype=torch.float64, device="cuda")
-    for _ in range(warmup):
-        s.sweep(1)
-        s.measure(out=energies)
+    # every step's energies stay on the device; steps run pipelined (qmc_run_steps: a step's
+    # measurement beside the next step's proposals)
+    energies = torch.empty((max(steps, warmup, 1), W, 4), dtype=torch.float64, device="cuda")
+    def run(n, out):
+        if serial:
+            for k in range(n):
+                s.sweep(1)
+                s.measure(out=out[k])
+        else:
+            s.run_steps(n, out)
+
+    if warmup:
+        run(warmup, energies[:warmup])
     torch.cuda.synchronize()
     s.set_timing(True)
     for k in (KERNEL_GATHER, KERNEL_CHAIN, KERNEL_MEASURE, KERNEL_REBUILD):
@@ -194,15 +211,13 @@ def run_single(wl, steps: int, warmup: int, delay, lanes=None):
     print(f"[bench] {wl.name}: timing {steps} steps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        s.sweep(1)
-        s.measure(out=energies)
+    run(steps, energies[:steps])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     kt = {name: s.kernel_timing(k) for name, k in
           (("gather", KERNEL_GATHER), ("chain", KERNEL_CHAIN), ("measure", KERNEL_MEASURE))}
     rebuild = s.kernel_timing(KERNEL_REBUILD)
-    e_host = energies.cpu().numpy()
+    e_host = energies[steps - 1].cpu().numpy()
     pos_host = s.get_walkers()[0]
     s.close()
     moves = W * N * steps

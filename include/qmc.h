@@ -166,6 +166,18 @@ qmc_status qmc_sweep(qmc_system s, int32_t n_sweeps, uint64_t* n_accepted_out);
  * Errors: STATE; DEVICE; NUMERIC (host output only) if a value is not finite. */
 qmc_status qmc_measure_local_energy(qmc_system s, double* out, int32_t out_on_device);
 
+/* n_steps VMC steps, each one sweep (as qmc_sweep) followed by the local
+ * energies (as qmc_measure_local_energy) of every walker, the collection
+ * after each step that section "Hamiltonian" prescribes.  energies_dev: device
+ * buffer [n_steps][W][4], step k's energies at offset k*W*4 (caller-owned).
+ * Results are bit for bit those of n_steps (qmc_sweep(s, 1) +
+ * qmc_measure_local_energy) calls.  Step k's measurement runs on a side stream
+ * of the handle while step k+1's proposals are evaluated on the handle's stream
+ * (they touch disjoint buffers), and step k+1's move chain waits for it; all
+ * work completes in the handle's stream order (asynchronous).
+ * Errors: ARG (negative n_steps, NULL buffer), STATE before init_walkers, DEVICE. */
+qmc_status qmc_run_steps(qmc_system s, int32_t n_steps, double* energies_dev);
+
 /* Copy walker state to host buffers (each nullable): pos[W][N][3];
  * logabs_det[W][2] = log|D_up|, log|D_dn| accumulated as the sum of
  * log|R| of the accepted moves since the last full inverse; sign[W][2]. */

@@ -117,6 +117,8 @@ struct qmc_system_s {
   bool timing = false;
   int use_mfma = 1;   // delayed-update products on the matrix cores (QMC_DELAYED_VALU=1: vector ALU)
   TimerClass timers[4];
+  hipStream_t side = nullptr;              // measurements of qmc_run_steps (created on first use)
+  hipEvent_t ev_swept = nullptr, ev_measured = nullptr;
 };
 
 namespace {
@@ -151,7 +153,16 @@ Walkers<T> walkers_of(qmc_system s) {
 
 // Event-bracketed launch: f() issues the kernel on s->stream.
 template <typename F>
+hipError_t timed(qmc_system s, int cls, F&& f, hipStream_t st);
+
+// Event-bracketed launch on the handle's stream.
+template <typename F>
 hipError_t timed(qmc_system s, int cls, F&& f) {
+  return timed(s, cls, static_cast<F&&>(f), s->stream);
+}
+
+template <typename F>
+hipError_t timed(qmc_system s, int cls, F&& f, hipStream_t st) {
   if (!s->timing) return f();
   TimerClass& tc = s->timers[cls];
   std::pair<hipEvent_t, hipEvent_t> ev;
@@ -162,11 +173,11 @@ hipError_t timed(qmc_system s, int cls, F&& f) {
     e = hipEventCreate(&ev.second);
     if (e != hipSuccess) return e;
   }
-  hipError_t e = hipEventRecord(ev.first, s->stream);
+  hipError_t e = hipEventRecord(ev.first, st);
   if (e != hipSuccess) return e;
   e = f();
   if (e != hipSuccess) return e;
-  e = hipEventRecord(ev.second, s->stream);
+  e = hipEventRecord(ev.second, st);
   tc.live.push_back(ev);
   return e;
 }
@@ -726,6 +737,65 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
   return st;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The proposals of one sweep (gather), on stream st.
+qmc_status sweep_gather(qmc_system s, hipStream_t st) {
+  hipError_t e;
+  if (s->d.precision == QMC_MIXED)
+    e = timed(s, 0, [&] { return launch_gather<float>(s->P, walkers_of<float>(s), static_cast<const float*>(s->d_table), 0, st, s->gather_lanes_log2); }, st);
+  else
+    e = timed(s, 0, [&] { return launch_gather<double>(s->P, walkers_of<double>(s), static_cast<const double*>(s->d_table), 0, st, s->gather_lanes_log2); }, st);
+  if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "sweep launch: %s", hipGetErrorString(e));
+  return QMC_OK;
+}
+
+// The move chain of one sweep and the periodic rebuild when due, on the handle's stream.
+qmc_status sweep_chain(qmc_system s) {
+  const int K = s->d.delay_rank;
+  const int mfma = s->use_mfma;
+  hipError_t e;
+  if (s->d.precision == QMC_MIXED)
+    e = timed(s, 1, [&] {
+      return K > 1 ? launch_chain_delayed<float>(s->P, walkers_of<float>(s), K, mfma, s->stream)
+                   : launch_chain<float>(s->P, walkers_of<float>(s), s->stream);
+    });
+  else
+    e = timed(s, 1, [&] {
+      return K > 1 ? launch_chain_delayed<double>(s->P, walkers_of<double>(s), K, mfma, s->stream)
+                   : launch_chain<double>(s->P, walkers_of<double>(s), s->stream);
+    });
+  if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "sweep launch: %s", hipGetErrorString(e));
+  s->sweep_index += 1;
+  if (s->d.recompute_period > 0 && s->sweep_index % (uint32_t)s->d.recompute_period == 0) {
+    qmc_status st = run_rebuild(s, nullptr);
+    if (st != QMC_OK) return st;
+  }
+  return QMC_OK;
+}
+
+// The local energies (with the mixed path's refinement first) into device memory dst, on st.
+qmc_status measure_on(qmc_system s, double* dst, hipStream_t st) {
+  hipError_t e;
+  if (s->d.precision == QMC_MIXED)
+    e = timed(s, 2, [&] {
+      const hipError_t er = launch_refine<float>(s->P, walkers_of<float>(s), s->scratch, st);
+      return er != hipSuccess ? er
+                              : launch_measure<float>(s->P, walkers_of<float>(s), s->E, s->energy + 4 * (size_t)s->P.W,
+                                                      dst, st);
+    }, st);
+  else
+    e = timed(s, 2, [&] { return launch_measure<double>(s->P, walkers_of<double>(s), s->E, s->energy + 4 * (size_t)s->P.W, dst, st); }, st);
+  if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "measure launch: %s", hipGetErrorString(e));
+  return QMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 qmc_status qmc_sweep(qmc_system s, int32_t n_sweeps, uint64_t* n_accepted_out) {
   if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
   if (!s->has_walkers) return fail(s, QMC_ERR_STATE, "init_walkers first");
@@ -734,31 +804,9 @@ qmc_status qmc_sweep(qmc_system s, int32_t n_sweeps, uint64_t* n_accepted_out) {
   uint64_t total = 0;
   std::vector<uint32_t> na;
   for (int it = 0; it < n_sweeps; ++it) {
-    const uint32_t sw = s->sweep_index;
-    hipError_t e;
-    const int K = s->d.delay_rank;
-    const int mfma = s->use_mfma;
-    if (s->d.precision == QMC_MIXED) {
-      e = timed(s, 0, [&] { return launch_gather<float>(s->P, walkers_of<float>(s), static_cast<const float*>(s->d_table), 0, s->stream, s->gather_lanes_log2); });
-      if (e == hipSuccess)
-        e = timed(s, 1, [&] {
-          return K > 1 ? launch_chain_delayed<float>(s->P, walkers_of<float>(s), K, mfma, s->stream)
-                       : launch_chain<float>(s->P, walkers_of<float>(s), s->stream);
-        });
-    } else {
-      e = timed(s, 0, [&] { return launch_gather<double>(s->P, walkers_of<double>(s), static_cast<const double*>(s->d_table), 0, s->stream, s->gather_lanes_log2); });
-      if (e == hipSuccess)
-        e = timed(s, 1, [&] {
-          return K > 1 ? launch_chain_delayed<double>(s->P, walkers_of<double>(s), K, mfma, s->stream)
-                       : launch_chain<double>(s->P, walkers_of<double>(s), s->stream);
-        });
-    }
-    if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "sweep launch: %s", hipGetErrorString(e));
-    s->sweep_index = sw + 1;
-    if (s->d.recompute_period > 0 && s->sweep_index % (uint32_t)s->d.recompute_period == 0) {
-      qmc_status st = run_rebuild(s, nullptr);
-      if (st != QMC_OK) return st;
-    }
+    qmc_status st = sweep_gather(s, s->stream);
+    if (st == QMC_OK) st = sweep_chain(s);
+    if (st != QMC_OK) return st;
     if (n_accepted_out) {
       na.resize(s->P.W);
       HIP_TRY(s, hipMemcpyAsync(na.data(), s->nacc, na.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream));
@@ -776,17 +824,8 @@ qmc_status qmc_measure_local_energy(qmc_system s, double* out, int32_t out_on_de
   if (!out) return fail(s, QMC_ERR_ARG, "out is NULL");
   HIP_TRY(s, hipSetDevice(s->device));
   double* dst = out_on_device ? out : s->energy;
-  hipError_t e;
-  if (s->d.precision == QMC_MIXED)
-    e = timed(s, 2, [&] {
-      const hipError_t er = launch_refine<float>(s->P, walkers_of<float>(s), s->scratch, s->stream);
-      return er != hipSuccess ? er
-                              : launch_measure<float>(s->P, walkers_of<float>(s), s->E, s->energy + 4 * (size_t)s->P.W,
-                                                      dst, s->stream);
-    });
-  else
-    e = timed(s, 2, [&] { return launch_measure<double>(s->P, walkers_of<double>(s), s->E, s->energy + 4 * (size_t)s->P.W, dst, s->stream); });
-  if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "measure launch: %s", hipGetErrorString(e));
+  qmc_status st = measure_on(s, dst, s->stream);
+  if (st != QMC_OK) return st;
   if (out_on_device) return QMC_OK;
   const size_t nb = (size_t)s->P.W * 4 * sizeof(double);
   HIP_TRY(s, hipMemcpyAsync(out, s->energy, nb, hipMemcpyDeviceToHost, s->stream));
@@ -794,6 +833,40 @@ qmc_status qmc_measure_local_energy(qmc_system s, double* out, int32_t out_on_de
   for (size_t q = 0; q < (size_t)s->P.W * 4; ++q)
     if (!std::isfinite(out[q])) return fail(s, QMC_ERR_NUMERIC, "non-finite local energy (walker %zu)", q / 4);
   return QMC_OK;
+}
+
+qmc_status qmc_run_steps(qmc_system s, int32_t n_steps, double* energies_dev) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (!s->has_walkers) return fail(s, QMC_ERR_STATE, "init_walkers first");
+  if (n_steps < 0) return fail(s, QMC_ERR_ARG, "n_steps must be >= 0");
+  if (n_steps > 0 && !energies_dev) return fail(s, QMC_ERR_ARG, "energies_dev is NULL");
+  if (n_steps == 0) return QMC_OK;
+  HIP_TRY(s, hipSetDevice(s->device));
+  if (!s->side) {
+    HIP_TRY(s, hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
+    HIP_TRY(s, hipEventCreateWithFlags(&s->ev_swept, hipEventDisableTiming));
+    HIP_TRY(s, hipEventCreateWithFlags(&s->ev_measured, hipEventDisableTiming));
+  }
+  const size_t stride = (size_t)s->P.W * 4;
+  // Step k's measurement reads the positions, current rows and inverses its sweep left; the
+  // next sweep's gather writes only the proposals and the other row buffers, so it runs on the
+  // handle's stream while the measurement runs on the side stream.  The next chain, which
+  // changes what the measurement reads, waits for it.
+  qmc_status st = sweep_gather(s, s->stream);
+  for (int it = 0; it < n_steps && st == QMC_OK; ++it) {
+    if (it > 0) HIP_TRY(s, hipStreamWaitEvent(s->stream, s->ev_measured, 0));
+    st = sweep_chain(s);
+    if (st != QMC_OK) break;
+    HIP_TRY(s, hipEventRecord(s->ev_swept, s->stream));
+    HIP_TRY(s, hipStreamWaitEvent(s->side, s->ev_swept, 0));
+    st = measure_on(s, energies_dev + (size_t)it * stride, s->side);
+    if (st != QMC_OK) break;
+    HIP_TRY(s, hipEventRecord(s->ev_measured, s->side));
+    if (it + 1 < n_steps) st = sweep_gather(s, s->stream);
+  }
+  // everything, including the last measurement, completes in the handle's stream order
+  HIP_TRY(s, hipStreamWaitEvent(s->stream, s->ev_measured, 0));
+  return st;
 }
 
 qmc_status qmc_get_walkers(qmc_system s, double* pos, double* logabs_det, int32_t* sign) {
@@ -1007,6 +1080,12 @@ qmc_status qmc_destroy_system(qmc_system s) {
   if (!s) return QMC_OK;
   (void)hipSetDevice(s->device);
   (void)hipStreamSynchronize(s->stream);
+  if (s->side) {
+    (void)hipStreamSynchronize(s->side);
+    (void)hipStreamDestroy(s->side);
+    (void)hipEventDestroy(s->ev_swept);
+    (void)hipEventDestroy(s->ev_measured);
+  }
   for (auto& tc : s->timers) {
     for (auto& ev : tc.live) { (void)hipEventDestroy(ev.first); (void)hipEventDestroy(ev.second); }
     for (auto& ev : tc.pool) { (void)hipEventDestroy(ev.first); (void)hipEventDestroy(ev.second); }

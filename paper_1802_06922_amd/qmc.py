@@ -29,7 +29,7 @@ EXPORTS = [
     "qmc_last_error", "qmc_estimate_device_bytes", "qmc_set_delay_rank", "qmc_autotune_delay",
     "qmc_get_last_energies", "qmc_batch_create", "qmc_batch_sweep", "qmc_batch_set_graph",
     "qmc_batch_timing", "qmc_batch_destroy", "qmc_max_delay_rank", "qmc_autotune_gather",
-    "qmc_set_gather_lanes",
+    "qmc_set_gather_lanes", "qmc_run_steps",
 ]
 
 
@@ -97,6 +97,7 @@ def load_library():
     L.qmc_batch_destroy.argtypes = [vp]
     L.qmc_autotune_gather.argtypes = [vp, C.c_int32, ip, dp]
     L.qmc_set_gather_lanes.argtypes = [vp, C.c_int32]
+    L.qmc_run_steps.argtypes = [vp, C.c_int32, vp]
     L.qmc_max_delay_rank.argtypes = [C.POINTER(Desc)]
     L.qmc_max_delay_rank.restype = C.c_int32
     for name in EXPORTS:
@@ -237,6 +238,14 @@ class System:
         e = np.zeros((self.W, 4))
         self._check(self.L.qmc_measure_local_energy(self.h, e.ctypes.data_as(C.c_void_p), 0))
         return e
+
+    def run_steps(self, n: int, out):
+        """n steps of (sweep + local energies), asynchronous; ``out`` a CUDA float64 tensor of
+        shape [n, W, 4] receives every step's energies."""
+        if tuple(out.shape) != (int(n), self.W, 4) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous [n, W, 4] tensor")
+        self._check(self.L.qmc_run_steps(self.h, int(n), C.c_void_p(out.data_ptr())))
+        return out
 
     def get_walkers(self):
         N = self.wl.n_elec

@@ -167,6 +167,38 @@ def test_register_rebuild_matches_global(gpu, monkeypatch, n_elec, grid, precisi
         assert np.abs(runs[0][0]).max() < 1e-8
 
 
+@pytest.mark.parametrize("case", ["fp64_delayed", "mixed_rebuild", "sherman_morrison"])
+def test_run_steps_matches_sweep_then_measure(gpu, case):
+    """The pipelined steps (measurement on a side stream beside the next sweep's proposals)
+    against sweep + measurement calls: the same bits for every step's energies, the final
+    positions, log|D| and the last decisions."""
+    import torch
+    if case == "fp64_delayed":
+        wl, K = qi.solid(64, 20, n_walkers=32, n_sweeps=1), 8
+    elif case == "mixed_rebuild":
+        wl, K = qi.solid(96, 24, n_walkers=32, n_sweeps=1, precision="mixed", recompute_period=3), 8
+    else:
+        wl, K = qi.solid(32, 16, n_walkers=16, n_sweeps=1), 1
+    n = 7
+    res = []
+    for pipelined in (False, True):
+        s = gpu.System(wl)
+        s.set_delay_rank(K)
+        out = torch.empty((n, s.W, 4), dtype=torch.float64, device="cuda")
+        if pipelined:
+            s.run_steps(n, out)
+        else:
+            for k in range(n):
+                s.sweep(1)
+                s.measure(out=out[k])
+        torch.cuda.synchronize()
+        pos, ld, sg = s.get_walkers()
+        res.append((out.cpu().numpy(), pos, ld, sg, s.accept_log()))
+        s.close()
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
+
+
 def test_measure_at_given_positions(gpu, orc):
     wl = qi.solid(32, 16, n_walkers=5, n_sweeps=1)
     rng = np.random.default_rng(4)
