@@ -85,7 +85,7 @@ class _Sys(C.Structure):
         ("j1_kind", C.c_int32), ("j1_M", C.c_int32), ("j1_rc", C.c_double),
         ("j1_p", C.POINTER(C.c_double)), ("j1_cusp", C.c_double),
         ("sigma", C.c_double), ("seed", C.c_uint64),
-        ("coulomb", C.c_int32), ("ewald_kappa", C.c_double),
+        ("coulomb", C.c_int32), ("ewald_kappa", C.c_double), ("all_electron", C.c_int32),
     ]
 
 
@@ -142,6 +142,7 @@ class OracleSystem:
         s.sigma, s.seed = wl.sigma, wl.seed
         s.coulomb = int((wl.hamiltonian == "coulomb") if coulomb is None else coulomb)
         s.ewald_kappa = kappa
+        s.all_electron = int(bool(getattr(wl, "all_electron", False)))
         self.s = s
         self._keep = keep
 

@@ -161,6 +161,7 @@ typedef struct {
     uint64_t seed;
     int32_t coulomb;           /* 0: kinetic only; 1: kinetic + Ewald Coulomb */
     double ewald_kappa;        /* <= 0: 5 / L */
+    int32_t all_electron;      /* 0: particle-by-particle sweeps; 1: all-electron moves */
 } orc_system;
 
 /* ------------------------------------------------------------------ */
@@ -768,6 +769,61 @@ static void orc_sweep(const orc_system* s, orc_walker* w, uint32_t walker_id, ui
 }
 
 /*
+ * All-electron move (section "Trial Moves", all coordinates proposed together):
+ * r'_i = r_i + sigma xi_i for every electron from the PROPOSE counters of the
+ * particle-by-particle sweep, one uniform per walker (electron 0's ACCEPT
+ * counter), accepted with probability min(1, |Psi(R')/Psi(R)|^2), the ratio from
+ * fresh LU determinants of both spin blocks at R' and the change of the full
+ * Jastrow factor.  A singular matrix at R' rejects the move.
+ */
+static void orc_ae_step(const orc_system* s, orc_walker* w, uint32_t walker_id, uint32_t step,
+                        uint8_t* accept_bits)
+{
+    const int N = s->n_up + s->n_dn, no = s->n_orb;
+    double* rp = (double*)malloc(sizeof(double) * 3 * (N > 0 ? N : 1));
+    double* v = (double*)malloc(sizeof(double) * no);
+    double* g = (double*)malloc(sizeof(double) * 3 * no);
+    double* l = (double*)malloc(sizeof(double) * no);
+    for (int i = 0; i < N; ++i) {
+        double xi[3];
+        orc_gauss3(s->seed, walker_id, step, (uint32_t)i, xi);
+        for (int a = 0; a < 3; ++a) rp[3 * i + a] = orc_wrap(w->pos[3 * i + a] + s->sigma * xi[a], s->L);
+    }
+    double* Ap[2];
+    double* Bp[2];
+    double ldp[2] = {0.0, 0.0};
+    int sgp[2] = {1, 1}, bad = 0;
+    for (int sp = 0; sp < 2; ++sp) {
+        const int n = orc_spin_count(s, sp), off = orc_spin_offset(s, sp);
+        Ap[sp] = (double*)calloc((size_t)n * n + 1, sizeof(double));
+        Bp[sp] = (double*)calloc((size_t)n * n + 1, sizeof(double));
+        for (int k = 0; k < n; ++k) {
+            orc_spo_vgl(s, rp + 3 * (off + k), v, g, l);
+            for (int j = 0; j < n; ++j) Ap[sp][k * n + j] = v[j];
+        }
+        bad |= orc_inverse(n, Ap[sp], Bp[sp], &ldp[sp], &sgp[sp]);
+    }
+    const double dlog = (ldp[0] - w->logdet[0]) + (ldp[1] - w->logdet[1]);
+    const double dJ = orc_jastrow_total(s, rp) - orc_jastrow_total(s, w->pos);
+    const double u = orc_accept_uniform(s->seed, walker_id, step, 0u);
+    const int acc = !bad && u < exp(2.0 * (dlog + dJ));
+    if (acc) {
+        for (int sp = 0; sp < 2; ++sp) {
+            double* t = w->A[sp]; w->A[sp] = Ap[sp]; Ap[sp] = t;
+            t = w->B[sp]; w->B[sp] = Bp[sp]; Bp[sp] = t;
+            w->logdet[sp] = ldp[sp];
+            w->logdet_accum[sp] = ldp[sp];
+            w->sign[sp] = sgp[sp];
+        }
+        memcpy(w->pos, rp, sizeof(double) * 3 * N);
+    }
+    if (accept_bits)
+        for (int i = 0; i < N; ++i) accept_bits[i] = (uint8_t)acc;
+    for (int sp = 0; sp < 2; ++sp) { free(Ap[sp]); free(Bp[sp]); }
+    free(rp); free(v); free(g); free(l);
+}
+
+/*
  * Run independent walkers (section "Variational Monte Carlo": walkers are
  * independent Markov chains).  walker_ids[w] selects the random streams of
  * chain w, so any subset of a large run can be reproduced alone.
@@ -841,7 +897,8 @@ int orc_vmc_run(const orc_system* s, int n_walk, const int32_t* walker_ids, cons
         int im = 0;
         for (int st = 0; st < n_sweeps; ++st) {
             uint8_t* bits = accept_bits ? accept_bits + ((size_t)wi * n_sweeps + st) * N : NULL;
-            orc_sweep(s, &w, wid, (uint32_t)(sweep0 + st), bits);
+            if (s->all_electron) orc_ae_step(s, &w, wid, (uint32_t)(sweep0 + st), bits);
+            else orc_sweep(s, &w, wid, (uint32_t)(sweep0 + st), bits);
             if (pos_trace) memcpy(pos_trace + ((size_t)wi * n_sweeps + st) * N * 3, w.pos, sizeof(double) * 3 * N);
             if (measure_every > 0 && (st + 1) % measure_every == 0 && im < n_meas) {
                 orc_measure(s, &w, v_ii, energies + ((size_t)wi * n_meas + im) * 4);

@@ -59,6 +59,7 @@ class Workload:
     recompute_period: int = 0     # sweeps between full FP64 inverse recomputes (0 = never)
     pw_k: Optional[np.ndarray] = None     # [n_orb][3] wave vectors of the analytic plane-wave orbitals
     pw_kind: Optional[np.ndarray] = None  # [n_orb] 0 = cos(k.r), 1 = sin(k.r)
+    all_electron: bool = False    # moves: False = particle-by-particle sweeps, True = all-electron moves
 
     @property
     def n_elec(self) -> int:
