@@ -93,7 +93,18 @@ typedef enum { QMC_H_KINETIC = 0, QMC_H_COULOMB_EWALD = 1 } qmc_hamiltonian;
  *                 PyTorch caching allocator).  If arena != NULL every device
  *                 buffer of the handle is carved from it and nothing is
  *                 allocated; size it with qmc_estimate_device_bytes().
+ *  move_kind      QMC_MOVE_PBYP (0): a sweep moves the electrons one at a
+ *                 time (section "Trial Moves", particle by particle);
+ *                 QMC_MOVE_ALL (1): a sweep is one all-electron move per
+ *                 walker, every electron proposed from the same PROPOSE
+ *                 counters, one uniform per walker (electron 0's ACCEPT
+ *                 counter), accepted with min(1, |Psi(R')/Psi(R)|^2) from FP64
+ *                 Gauss-Jordan determinants of both spin blocks at R' and the
+ *                 full Jastrow change; a singular matrix at R' rejects.
+ *                 delay_rank and recompute_period do not apply.
  */
+enum { QMC_MOVE_PBYP = 0, QMC_MOVE_ALL = 1 };
+
 typedef struct {
     int32_t n_up, n_dn;
     double L;
@@ -120,6 +131,7 @@ typedef struct {
     double tie_guard;
     void* arena;
     size_t arena_bytes;
+    int32_t move_kind;
 } qmc_system_desc;
 
 /* Create a handle.  hip_stream: a hipStream_t (e.g. PyTorch's current
@@ -149,9 +161,11 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos);
 /* Run n_sweeps particle-by-particle sweeps of every walker.  Each sweep
  * proposes every electron once, in index order, and accepts with
  * probability min(1, R^2 exp(2 dJ)), R the determinant ratio and dJ the
- * Jastrow change.  n_accepted_out (nullable; non-NULL synchronises): total
- * accepted moves over all walkers and these sweeps.  Errors: STATE before
- * init_walkers; DEVICE. */
+ * Jastrow change.  With move_kind QMC_MOVE_ALL a sweep is instead one
+ * all-electron move per walker (see qmc_system_desc), an accepted walker
+ * counting as N accepted electrons.  n_accepted_out (nullable; non-NULL
+ * synchronises): total accepted electron moves over all walkers and these
+ * sweeps.  Errors: STATE before init_walkers; DEVICE. */
 qmc_status qmc_sweep(qmc_system s, int32_t n_sweeps, uint64_t* n_accepted_out);
 
 /* Local energy of every walker at its current configuration (section
@@ -239,7 +253,7 @@ qmc_status qmc_get_last_energies(qmc_system s, double* out);
 
 /* ---- Batches: several systems advanced by fused launches -------------------
  * The walkers of all systems of a batch (any sizes, one precision, delay rank
- * >= 4, initialised) are advanced by one orbital-gather launch, one delayed-
+ * >= 4, particle-by-particle moves, initialised) are advanced by one orbital-gather launch, one delayed-
  * chain launch per LDS class and one measurement launch per sweep.  Each
  * system's results are identical to advancing it alone.  All launches go to
  * the batch's stream.  qmc_batch_sweep orders itself after work already

@@ -111,6 +111,12 @@ struct qmc_system_s {
   int gather_lanes_log2 = -1;   // lanes per proposal in the gather (log2); -1 = default
   uint32_t* nguard = nullptr;
   uint32_t* sweep_ctr = nullptr;
+  // all-electron moves: the state at the proposed configurations (null for particle-by-particle)
+  void* ae_binv = nullptr;
+  double* ae_logdet = nullptr;
+  double* ae_dj = nullptr;
+  int* ae_sign = nullptr;
+  int* ae_status = nullptr;
   double* scratch = nullptr;
   double* drift = nullptr;
   double* energy = nullptr;
@@ -148,6 +154,7 @@ Walkers<T> walkers_of(qmc_system s) {
   w.binv = static_cast<T*>(s->binv); w.logdet = s->logdet; w.sign = s->sign; w.acc = s->acc;
   w.nacc = s->nacc; w.status = s->status; w.val64 = s->val64; w.nguard = s->nguard; w.sweep_ctr = s->sweep_ctr;
   w.xinv = static_cast<T*>(s->xinv);
+  w.row_flip = 0;
   return w;
 }
 
@@ -333,20 +340,26 @@ void free_walkers(qmc_system s) {
   s->xinv = nullptr;
   s->nguard = nullptr;
   s->sweep_ctr = nullptr;
+  s->ae_binv = nullptr;
+  s->ae_logdet = s->ae_dj = nullptr;
+  s->ae_sign = s->ae_status = nullptr;
 }
 
 struct WalkerSizes {
   size_t pos, prop, vgl, cur, binv, logdet, sign, acc, nacc, status, scratch, drift, energy, val64, nguard, sweep,
-      xinv;
+      xinv, ae_binv, ae_logdet, ae_dj, ae_sign, ae_status;
   size_t total() const {
     return align_up(pos) + align_up(prop) + align_up(vgl) + align_up(cur) + align_up(binv) +
            align_up(logdet) + align_up(sign) + align_up(acc) + align_up(nacc) + align_up(status) +
            align_up(scratch) + align_up(drift) + align_up(energy) + align_up(val64) + align_up(nguard) +
-           align_up(sweep) + align_up(xinv);
+           align_up(sweep) + align_up(xinv) +
+           (ae_binv ? align_up(ae_binv) + align_up(ae_logdet) + align_up(ae_dj) + align_up(ae_sign) +
+                          align_up(ae_status)
+                    : 0);
   }
 };
 
-WalkerSizes walker_sizes(int n_up, int n_dn, int precision, int W, int n_orb) {
+WalkerSizes walker_sizes(int n_up, int n_dn, int precision, int W, int n_orb, int move_kind) {
   const size_t N = (size_t)n_up + n_dn, S = padded_stride(n_orb, precision), ts = tsize_of(precision);
   const size_t bs = (size_t)n_up * n_up + (size_t)n_dn * n_dn;
   WalkerSizes z;
@@ -367,6 +380,12 @@ WalkerSizes walker_sizes(int n_up, int n_dn, int precision, int W, int n_orb) {
   z.xinv = precision == QMC_MIXED ? W * bs * ts : 0;
   z.nguard = W * sizeof(uint32_t);
   z.sweep = sizeof(uint32_t);
+  const bool ae = move_kind == QMC_MOVE_ALL;
+  z.ae_binv = ae ? W * bs * ts : 0;
+  z.ae_logdet = ae ? W * 2 * sizeof(double) : 0;
+  z.ae_dj = ae ? W * sizeof(double) : 0;
+  z.ae_sign = ae ? W * 2 * sizeof(int) : 0;
+  z.ae_status = ae ? W * sizeof(int) : 0;
   return z;
 }
 
@@ -394,6 +413,8 @@ qmc_status validate(const qmc_system_desc* d) {
     return fail(nullptr, QMC_ERR_ARG, "delay_rank %d: use 1 (Sherman-Morrison) or a power of two in [4, 64]",
                 d->delay_rank);
   if (d->recompute_period < 0) return fail(nullptr, QMC_ERR_ARG, "recompute_period must be >= 0");
+  if (d->move_kind != QMC_MOVE_PBYP && d->move_kind != QMC_MOVE_ALL)
+    return fail(nullptr, QMC_ERR_ARG, "unknown move_kind %d", d->move_kind);
   if (d->hamiltonian != QMC_H_KINETIC && d->hamiltonian != QMC_H_COULOMB_EWALD)
     return fail(nullptr, QMC_ERR_ARG, "unknown hamiltonian %d", d->hamiltonian);
   if (d->n_ions < 0 || (d->n_ions > 0 && (!d->ion_pos || !d->ion_Z)))
@@ -659,7 +680,7 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
   HIP_TRY(s, hipSetDevice(s->device));
   free_walkers(s);
   const int W = n_walkers;
-  const WalkerSizes z = walker_sizes(s->P.n_up, s->P.n_dn, s->d.precision, W, s->P.n_orb);
+  const WalkerSizes z = walker_sizes(s->P.n_up, s->P.n_dn, s->d.precision, W, s->P.n_orb, s->d.move_kind);
   s->pos = static_cast<double*>(s->mem.alloc(z.pos));
   s->prop = static_cast<double*>(s->mem.alloc(z.prop));
   s->vgl = s->mem.alloc(z.vgl);
@@ -679,9 +700,18 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
     s->val64 = static_cast<double*>(s->mem.alloc(z.val64));
     s->xinv = s->mem.alloc(z.xinv);
   }
+  const bool ae = s->d.move_kind == QMC_MOVE_ALL;
+  if (ae) {
+    s->ae_binv = s->mem.alloc(z.ae_binv);
+    s->ae_logdet = static_cast<double*>(s->mem.alloc(z.ae_logdet));
+    s->ae_dj = static_cast<double*>(s->mem.alloc(z.ae_dj));
+    s->ae_sign = static_cast<int*>(s->mem.alloc(z.ae_sign));
+    s->ae_status = static_cast<int*>(s->mem.alloc(z.ae_status));
+  }
   if (!s->pos || !s->prop || !s->vgl || !s->cur || !s->binv || !s->logdet || !s->sign || !s->acc ||
       !s->nacc || !s->status || !s->scratch || !s->drift || !s->energy || !s->nguard || !s->sweep_ctr ||
-      (s->d.precision == QMC_MIXED && (!s->val64 || !s->xinv))) {
+      (s->d.precision == QMC_MIXED && (!s->val64 || !s->xinv)) ||
+      (ae && (!s->ae_binv || !s->ae_logdet || !s->ae_dj || !s->ae_sign || !s->ae_status))) {
     free_walkers(s);
     return fail(s, QMC_ERR_OOM, "device allocation of %zu walker bytes failed", z.total());
   }
@@ -753,7 +783,33 @@ qmc_status sweep_gather(qmc_system s, hipStream_t st) {
 }
 
 // The move chain of one sweep and the periodic rebuild when due, on the handle's stream.
+// One all-electron move per walker (the sweep's gather already holds R' and its rows): the
+// Jastrow change, FP64 determinants of the proposed matrices, then decision and installation.
+template <typename T>
+hipError_t ae_step(qmc_system s) {
+  hipError_t e = launch_ae_jastrow(s->P, s->pos, s->prop, s->ae_dj, s->ae_status, s->stream);
+  if (e != hipSuccess) return e;
+  Walkers<T> prop = walkers_of<T>(s);
+  prop.binv = static_cast<T*>(s->ae_binv);
+  prop.logdet = s->ae_logdet;
+  prop.sign = s->ae_sign;
+  prop.status = s->ae_status;
+  prop.row_flip = 1;
+  e = launch_rebuild<T>(s->P, prop, s->scratch, nullptr, s->stream);
+  if (e != hipSuccess) return e;
+  AeProposal<T> A{static_cast<T*>(s->ae_binv), s->ae_logdet, s->ae_sign, s->ae_status, s->ae_dj};
+  return launch_ae_apply<T>(s->P, walkers_of<T>(s), A, s->stream);
+}
+
 qmc_status sweep_chain(qmc_system s) {
+  if (s->d.move_kind == QMC_MOVE_ALL) {
+    // the inverses are recomputed at every accepted move, so no periodic rebuild is needed
+    const hipError_t e = s->d.precision == QMC_MIXED ? timed(s, 1, [&] { return ae_step<float>(s); })
+                                                     : timed(s, 1, [&] { return ae_step<double>(s); });
+    if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "all-electron move launch: %s", hipGetErrorString(e));
+    s->sweep_index += 1;
+    return QMC_OK;
+  }
   const int K = s->d.delay_rank;
   const int mfma = s->use_mfma;
   hipError_t e;
@@ -1250,6 +1306,10 @@ qmc_status qmc_batch_create(const qmc_system* systems, int32_t n_systems, void* 
       delete b;
       return bfail(nullptr, QMC_ERR_ARG, "systems of a batch share the device and the precision");
     }
+    if (s->d.move_kind != QMC_MOVE_PBYP) {
+      delete b;
+      return bfail(nullptr, QMC_ERR_ARG, "system %d: batches run particle-by-particle moves", i);
+    }
     if (s->d.delay_rank < 4) {
       delete b;
       return bfail(nullptr, QMC_ERR_ARG, "system %d: batches run the delayed chain (delay rank >= 4)", i);
@@ -1420,7 +1480,7 @@ size_t qmc_estimate_device_bytes(const qmc_system_desc* desc, int32_t n_walkers,
   if (desc->precision != QMC_FP64 && desc->precision != QMC_MIXED) return 0;
   const int n_orb = desc->n_up > desc->n_dn ? desc->n_up : desc->n_dn;
   const size_t table = align_up((size_t)gx * gy * gz * padded_stride(n_orb, desc->precision) * tsize_of(desc->precision));
-  return system_bytes(desc) + table + walker_sizes(desc->n_up, desc->n_dn, desc->precision, n_walkers, n_orb).total();
+  return system_bytes(desc) + table + walker_sizes(desc->n_up, desc->n_dn, desc->precision, n_walkers, n_orb, desc->move_kind).total();
 }
 
 }  // extern "C"

@@ -1,0 +1,155 @@
+// k_allelectron.hip -- all-electron moves: every electron of a walker is proposed at once
+// (section "Trial Moves", the move that displaces all coordinates together) and the walker
+// accepts with min(1, |Psi(R')/Psi(R)|^2).
+//
+// The proposals and their value rows come from the sweep gather (the rows land in the
+// buffers that do not hold the current rows).  The determinants at R' are fresh FP64
+// Gauss-Jordan eliminations of those rows (the rebuild kernels, pointed at the other row
+// buffer and at side outputs), so |D(R')/D(R)| = exp(log|D'| - log|D|) per spin.  This file
+// adds the full Jastrow change and the per-walker decision that installs the new state.
+#include "qmc_kernels.hpp"
+
+namespace qmc {
+
+namespace {
+
+__device__ __forceinline__ double ae_u(const Jastrow& J, int kind, double r) {
+  return kind == 0 ? radial_value(J.same, r) : (kind == 1 ? radial_value(J.opp, r) : radial_value(J.ei, r));
+}
+
+__device__ __forceinline__ double ae_dist(const double* a, const double* b, double L, double invL) {
+  const double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+  const double x = dx - L * rint(dx * invL), y = dy - L * rint(dy * invL), z = dz - L * rint(dz * invL);
+  return sqrt(x * x + y * y + z * z);
+}
+
+}  // namespace
+
+// dJ[w] = J(R') - J(R), J = sum_{i<j} u2(r_ij) + sum_{i,I} u1(r_iI) (section "Jastrow
+// factors", minimum image), as the sum of the per-pair changes.  One workgroup per walker.
+// The N(N-1)/2 pairs are enumerated as circulant diagonals, pair (i, i + d mod N) for
+// d = 1 .. (N-1)/2 and, for even N, (i, i + N/2) with i < N/2, so the work is balanced
+// over the threads without a triangular index decode.  Also clears status_prop[w], which the
+// rebuild of the proposed matrices then sets on a singular matrix.
+__global__ __launch_bounds__(kBlock) void k_ae_jastrow(SysParams P, const double* __restrict__ pos,
+                                                       const double* __restrict__ prop, double* dj,
+                                                       int* status_prop) {
+  __shared__ Jastrow sj;
+  __shared__ double red[kWaves];
+  const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int N = P.N;
+  for (int q = tid; q < (int)(sizeof(Jastrow) / sizeof(double)); q += kBlock)
+    reinterpret_cast<double*>(&sj)[q] = reinterpret_cast<const double*>(&P.jas)[q];
+  __syncthreads();
+  const double L = P.L, invL = 1.0 / P.L;
+  const double* x0 = pos + (size_t)w * N * 3;
+  const double* x1 = prop + (size_t)w * N * 4;
+  const int D = (N - 1) / 2;
+  const int n_pairs = N * D + ((N & 1) ? 0 : N / 2);
+  double acc = 0.0;
+  for (int q = tid; q < n_pairs; q += kBlock) {
+    int i, j;
+    if (q < N * D) {
+      const int d = 1 + q / N;
+      i = q - (d - 1) * N;
+      j = i + d;
+      if (j >= N) j -= N;
+    } else {
+      i = q - N * D;
+      j = i + N / 2;
+    }
+    const int kind = ((i < P.n_up) == (j < P.n_up)) ? 0 : 1;
+    const double r1 = ae_dist(x1 + 4 * i, x1 + 4 * j, L, invL);
+    const double r0 = ae_dist(x0 + 3 * i, x0 + 3 * j, L, invL);
+    acc += ae_u(sj, kind, r1) - ae_u(sj, kind, r0);
+  }
+  if (sj.ei.kind != QMC_J_NONE)
+    for (int q = tid; q < N * P.n_ions; q += kBlock) {
+      const int i = q / P.n_ions, I = q - i * P.n_ions;
+      const double* ion = P.ions + 4 * I;
+      acc += ae_u(sj, 2, ae_dist(x1 + 4 * i, ion, L, invL)) - ae_u(sj, 2, ae_dist(x0 + 3 * i, ion, L, invL));
+    }
+  acc = wave_sum_dpp(acc);
+  if (lane == 0) red[wave] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) s += red[q];   // fixed order: bitwise repeatable
+    dj[w] = s;
+    status_prop[w] = 0;
+  }
+}
+
+// Decision and installation, one workgroup per walker.  u is the walker's uniform (the
+// ACCEPT draw of electron 0, kept with electron 0's proposal); a singular matrix at R'
+// rejects.  On acceptance the positions become the proposals, every electron's row buffer
+// flag flips (the proposal rows become current), and the inverses, log|D| and signs become
+// those of R'.  acc[w][i] = the decision for every electron, nacc[w] = N or 0.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ae_apply(SysParams P, Walkers<T> Wk, AeProposal<T> A) {
+  __shared__ int sacc;
+  const int w = blockIdx.x, tid = threadIdx.x;
+  const int N = P.N;
+  if (tid == 0) {
+    const double u = Wk.prop[(size_t)w * N * 4 + 3];
+    const double dlog = (A.logdet[2 * w] - Wk.logdet[2 * w]) + (A.logdet[2 * w + 1] - Wk.logdet[2 * w + 1]);
+    sacc = (A.status[w] == 0) && (u < exp(2.0 * (dlog + A.dj[w])));
+  }
+  __syncthreads();
+  const int acc = sacc;
+  const size_t e0 = (size_t)w * N;
+  for (int i = tid; i < N; i += kBlock) {
+    Wk.acc[e0 + i] = (uint8_t)acc;
+    if (acc) {
+      const double* pr = Wk.prop + (e0 + i) * 4;
+      double* p = Wk.pos + (e0 + i) * 3;
+      p[0] = pr[0]; p[1] = pr[1]; p[2] = pr[2];
+      Wk.cur[e0 + i] ^= (uint8_t)1;
+    }
+  }
+  if (acc) {
+    // the walker's two inverses (bstride elements); as 16-byte vectors when every walker's
+    // block starts on a 16-byte boundary (the buffers themselves are 256-byte aligned)
+    const size_t base = (size_t)w * P.bstride;
+    if (((size_t)P.bstride * sizeof(T)) % 16 == 0) {
+      const size_t nv = (size_t)P.bstride * sizeof(T) / 16;
+      const uint4* src = reinterpret_cast<const uint4*>(A.binv + base);
+      uint4* dst = reinterpret_cast<uint4*>(Wk.binv + base);
+      for (size_t q = tid; q < nv; q += kBlock) dst[q] = src[q];
+    } else {
+      for (size_t q = tid; q < (size_t)P.bstride; q += kBlock) Wk.binv[base + q] = A.binv[base + q];
+    }
+  }
+  if (tid == 0) {
+    if (acc) {
+      Wk.logdet[2 * w] = A.logdet[2 * w];
+      Wk.logdet[2 * w + 1] = A.logdet[2 * w + 1];
+      Wk.sign[2 * w] = A.sign[2 * w];
+      Wk.sign[2 * w + 1] = A.sign[2 * w + 1];
+    }
+    Wk.nacc[w] = acc ? (uint32_t)N : 0u;
+    if (w == 0) *Wk.sweep_ctr += 1u;   // read by the next sweep's gather
+  }
+}
+
+hipError_t launch_ae_jastrow(const SysParams& P, const double* pos, const double* prop, double* dj,
+                             int* status_prop, hipStream_t st) {
+  if (P.W <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ae_jastrow, dim3(P.W), dim3(kBlock), 0, st, P, pos, prop, dj, status_prop);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ae_apply(const SysParams& P, const Walkers<T>& Wk, const AeProposal<T>& A, hipStream_t st) {
+  if (P.W <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ae_apply<T>, dim3(P.W), dim3(kBlock), 0, st, P, Wk, A);
+  return hipGetLastError();
+}
+
+template hipError_t launch_ae_apply<float>(const SysParams&, const Walkers<float>&, const AeProposal<float>&,
+                                           hipStream_t);
+template hipError_t launch_ae_apply<double>(const SysParams&, const Walkers<double>&,
+                                            const AeProposal<double>&, hipStream_t);
+
+}  // namespace qmc

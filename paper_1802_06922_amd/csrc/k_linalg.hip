@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kBlock) void k_rebuild(SysParams P, Walkers<T> Wk, 
   for (int q = tid; q < n * n; q += kBlock) {
     const int k = q / n, l = q - k * n;
     const size_t item = (size_t)w * N + off + k;
-    const int cb = Wk.cur[item];
+    const int cb = Wk.cur[item] ^ Wk.row_flip;
     a[q] = Wk.val64 ? Wk.val64[((size_t)cb * P.W * N + item) * P.S + l]
                     : (double)Wk.vgl[((size_t)cb * P.W * N + item) * kComp * P.S + l];
     amax = fmax(amax, fabs(a[q]));
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(kRegBlock) void k_rebuild_reg(SysParams P, Walkers<
     const int e = r0 + 32 * i;
     if (e < n) {
       const size_t item = (size_t)w * N + off + e;
-      const size_t row = (size_t)Wk.cur[item] * P.W * N + item;
+      const size_t row = (size_t)(Wk.cur[item] ^ Wk.row_flip) * P.W * N + item;
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         const int l = c0 + 32 * j;
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_rebuild_panel(SysParams P, Walkers<T
   for (int q = tid; q < n * n; q += kBlock) {
     const int k = q / n, l = q - k * n;
     const size_t item = (size_t)w * N + off + k;
-    const int cb = Wk.cur[item];
+    const int cb = Wk.cur[item] ^ Wk.row_flip;
     a[q] = Wk.val64 ? Wk.val64[((size_t)cb * P.W * N + item) * P.S + l]
                     : (double)Wk.vgl[((size_t)cb * P.W * N + item) * kComp * P.S + l];
     amax = fmax(amax, fabs(a[q]));

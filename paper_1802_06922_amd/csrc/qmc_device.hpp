@@ -64,6 +64,7 @@ struct Walkers {
   uint32_t* nguard;   // [W]: moves re-decided in FP64 (cumulative; mixed precision)
   uint32_t* sweep_ctr;  // index of the next sweep (device side, so captured sweeps replay correctly)
   T* xinv;            // [W][bstride]: FP64-refined copy of binv the measurement reads (mixed only, else null)
+  int row_flip;       // rebuilds: 1 = invert the rows of the buffer that does not hold the current row
 };
 
 // ---------------------------------------------------------------------------

@@ -153,6 +153,22 @@ hipError_t launch_measure_batched(const SysDev<T>* sd, const int2* bmap, int n_b
                                   int n_walkers, size_t lds, hipStream_t st);
 size_t measure_lds_bytes(const SysParams& P, int np);
 
+// All-electron moves: the state at the proposed configuration R' of every walker.
+template <typename T>
+struct AeProposal {
+  T* binv;          // [W][bstride]: inverses at R' (written by the rebuild with row_flip = 1)
+  double* logdet;   // [W][2]: log|D(R')| per spin (NaN when singular)
+  int* sign;        // [W][2]
+  int* status;      // [W]: nonzero = a singular matrix at R'
+  double* dj;       // [W]: J(R') - J(R)
+};
+// dj[w] = J(R') - J(R) from pos and the proposals; clears status_prop.
+hipError_t launch_ae_jastrow(const SysParams& P, const double* pos, const double* prop, double* dj,
+                             int* status_prop, hipStream_t st);
+// Accept or reject every walker's all-electron move and install R' on acceptance.
+template <typename T>
+hipError_t launch_ae_apply(const SysParams& P, const Walkers<T>& Wk, const AeProposal<T>& A, hipStream_t st);
+
 // Size in bytes of the dynamic LDS the chain kernel needs for P.
 size_t chain_lds_bytes(const SysParams& P, size_t tsize, bool b_in_lds);
 

@@ -49,7 +49,7 @@ class Desc(C.Structure):
         ("j2_rcut", C.c_double), ("j2_cusp_same", C.c_double), ("j2_cusp_opp", C.c_double),
         ("j1_kind", C.c_int32), ("j1_params", C.POINTER(C.c_double)), ("j1_n", C.c_int32),
         ("j1_rcut", C.c_double), ("j1_cusp", C.c_double), ("tie_guard", C.c_double),
-        ("arena", C.c_void_p), ("arena_bytes", C.c_size_t),
+        ("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("move_kind", C.c_int32),
     ]
 
 
@@ -152,6 +152,7 @@ def make_desc(wl, keep: list, arena=None, arena_bytes: int = 0, tie_guard: float
     d.tie_guard = tie_guard
     d.arena = arena
     d.arena_bytes = arena_bytes
+    d.move_kind = 1 if getattr(wl, "all_electron", False) else 0
     return d
 
 

@@ -1,0 +1,152 @@
+"""GPU parity of all-electron moves (section "Trial Moves": every coordinate of a walker
+proposed at once, accepted with min(1, |Psi(R')/Psi(R)|^2)) against the FP64 oracle's
+all-electron mode, through the C ABI.
+
+Bars as for the particle-by-particle path: decisions bit-exact, FP64 local energies within
+1e-10 relative, final positions within 1e-11, log|D| within 1e-9, signs exact; mixed
+precision (FP32 table and inverses, FP64 determinants at R') decisions bit-exact and energies
+within 1e-5 relative.  Proposal widths are chosen so that a fair share of the moves is
+accepted and a fair share rejected (checked)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import qmc_inputs as qi
+
+pytestmark = pytest.mark.gpu
+
+E_TOL = 1e-10
+MIXED_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1802_06922_amd import qmc
+    qmc.load_library()
+    return qmc
+
+
+def _rel(a, b):
+    return np.abs(a - b) / np.maximum(np.abs(b), 1.0)
+
+
+def _ae(wl, sigma):
+    return dataclasses.replace(wl, all_electron=True, sigma=sigma)
+
+
+def _run(gpu, wl, n_sweeps, sample):
+    s = gpu.System(wl)
+    bits, energies, counts = [], [], []
+    for _ in range(n_sweeps):
+        counts.append(s.sweep(1, count_accepted=True))
+        b = s.accept_log()
+        bits.append(b)
+        energies.append(s.measure())
+    pos, ld, sg = s.get_walkers()
+    s.close()
+    b = np.stack(bits, 1)
+    # an accepted walker counts as N accepted electron moves
+    assert counts == [int(x.sum()) for x in bits]
+    return b[sample], np.stack(energies, 1)[sample], pos[sample], ld[sample], sg[sample]
+
+
+def _compare(gpu, orc, wl, n_sweeps, walkers, tol=E_TOL):
+    sample = np.asarray(walkers)
+    print(f"[ae] {wl.name} {wl.precision} sigma={wl.sigma}: walkers {sample[:6].tolist()}.. "
+          f"{n_sweeps} sweeps", flush=True)
+    b, e, pos, ld, sg = _run(gpu, wl, n_sweeps, sample)
+    ref = orc.OracleSystem(wl).run(sample, n_sweeps, measure_every=1)
+    assert np.array_equal(b, ref["accept"]), f"first differing decision: {np.argwhere(b != ref['accept'])[:3]}"
+    # every electron of a walker carries the walker's one decision
+    assert (b == b[:, :, :1]).all()
+    rel = _rel(e, ref["energies"])
+    print(f"[ae] acceptance {b[:, :, 0].mean():.3f}, rel energy error max {rel.max():.2e}", flush=True)
+    assert rel.max() < tol, f"max rel energy error {rel.max():.3e}"
+    np.testing.assert_allclose(pos, ref["final_pos"], atol=1e-11)
+    np.testing.assert_allclose(ld, ref["logdet"], atol=1e-9)
+    assert np.array_equal(sg, ref["sign"])
+    return b
+
+
+def test_ae_heg14_trajectory(gpu, orc):
+    """The 14-electron gas (Pade J2, 8 walkers) over 60 all-electron moves per walker."""
+    b = _compare(gpu, orc, _ae(qi.heg14(), 0.1), 60, range(8))
+    assert 0.2 < b.mean() < 0.9
+
+
+def test_ae_ragged_solid_with_ions(gpu, orc):
+    """9 up and 7 down electrons (ragged rows), ions, B-spline one- and two-body Jastrows."""
+    wl = qi.solid(18, 14, n_walkers=24, n_sweeps=1)
+    wl.n_up, wl.n_dn, wl.n_orb = 9, 7, 9
+    wl.coefs = qi.solid_table(9, 14, seed=3, dtype=np.float64)
+    b = _compare(gpu, orc, _ae(wl, 0.1), 20, range(24))
+    assert 0.2 < b.mean() < 0.9
+
+
+def test_ae_no_down_electrons(gpu, orc):
+    """An empty spin block: its determinant is 1 at R and at R'."""
+    wl = qi.solid(10, 12, n_walkers=6, n_sweeps=1)
+    wl.n_up, wl.n_dn, wl.n_orb = 5, 0, 5
+    wl.coefs = qi.solid_table(5, 12, seed=5, dtype=np.float64)
+    _compare(gpu, orc, _ae(wl, 0.1), 15, range(6))
+
+
+def test_ae_solid128_sampled_walkers(gpu, orc):
+    """The 128-electron solid (48^3 FP64 table, 32 ions, 512 walkers): sampled walkers."""
+    b = _compare(gpu, orc, _ae(qi.solid128(), 0.02), 6, [0, 255, 511])
+    assert 0.05 < b.mean() < 0.95
+
+
+@pytest.mark.parametrize("path", ["panel", "global"])
+def test_ae_large_spin_blocks(gpu, orc, monkeypatch, path):
+    """Spin blocks of 200 (the LDS panel elimination) and, forced, the global-memory one."""
+    if path == "global":
+        monkeypatch.setenv("QMC_REBUILD_GLOBAL", "1")
+        wl = qi.solid(96, 16, n_walkers=6, n_sweeps=1)
+    else:
+        wl = qi.solid(400, 24, n_walkers=4, n_sweeps=1)
+    _compare(gpu, orc, _ae(wl, 0.01), 4, range(wl.n_walkers))
+
+
+def test_ae_mixed_precision(gpu, orc):
+    """FP32 table and inverses: the determinants at R' are FP64 eliminations of the FP64
+    value rows, so the decisions are the oracle's on the same FP32-valued table."""
+    wl = qi.solid(48, 16, n_walkers=16, n_sweeps=1, precision="mixed", table_dtype=np.float32)
+    b = _compare(gpu, orc, _ae(wl, 0.05), 12, range(16), tol=MIXED_TOL)
+    assert 0.1 < b.mean() < 0.95
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_ae_run_steps_matches_sweep_then_measure(gpu, precision):
+    """Pipelined steps with all-electron moves: the same bits as sweep + measurement calls."""
+    import torch
+    kw = dict(table_dtype=np.float32) if precision == "mixed" else {}
+    wl = _ae(qi.solid(64, 20, n_walkers=32, n_sweeps=1, precision=precision, **kw), 0.04)
+    n = 7
+    res = []
+    for pipelined in (False, True):
+        s = gpu.System(wl)
+        out = torch.empty((n, s.W, 4), dtype=torch.float64, device="cuda")
+        if pipelined:
+            s.run_steps(n, out)
+        else:
+            for k in range(n):
+                s.sweep(1)
+                s.measure(out=out[k])
+        torch.cuda.synchronize()
+        pos, ld, sg = s.get_walkers()
+        res.append((out.cpu().numpy(), pos, ld, sg, s.accept_log()))
+        s.close()
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
+
+
+def test_ae_systems_are_not_batched(gpu):
+    s = gpu.System(_ae(qi.solid(16, 12, n_walkers=4, n_sweeps=1), 0.1))
+    with pytest.raises(gpu.QMCError):
+        gpu.Batch([s])
+    s.close()
