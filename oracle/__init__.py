@@ -142,7 +142,8 @@ class OracleSystem:
         s.sigma, s.seed = wl.sigma, wl.seed
         s.coulomb = int((wl.hamiltonian == "coulomb") if coulomb is None else coulomb)
         s.ewald_kappa = kappa
-        s.all_electron = int(bool(getattr(wl, "all_electron", False)))
+        ae = bool(getattr(wl, "all_electron", False))
+        s.all_electron = (2 if getattr(wl, "drift", False) else 1) if ae else 0
         self.s = s
         self._keep = keep
 

@@ -161,7 +161,8 @@ typedef struct {
     uint64_t seed;
     int32_t coulomb;           /* 0: kinetic only; 1: kinetic + Ewald Coulomb */
     double ewald_kappa;        /* <= 0: 5 / L */
-    int32_t all_electron;      /* 0: particle-by-particle sweeps; 1: all-electron moves */
+    int32_t all_electron;      /* 0: particle-by-particle sweeps; 1: all-electron moves;
+                                  2: all-electron drift-diffusion moves */
 } orc_system;
 
 /* ------------------------------------------------------------------ */
@@ -769,12 +770,48 @@ static void orc_sweep(const orc_system* s, orc_walker* w, uint32_t walker_id, ui
 }
 
 /*
+ * Drift velocity v_i = grad_i ln|Psi| of every electron at configuration pos with
+ * inverses B[sp] (B[l][k]): the log-determinant gradient sum_l grad phi_l(r_i) B[l][k]
+ * of the electron's spin block plus the Jastrow gradient.  v: [N][3].
+ */
+static void orc_drift_velocity(const orc_system* s, const double* pos, double* const B[2], double* vel)
+{
+    const int no = s->n_orb;
+    double* v = (double*)malloc(sizeof(double) * no);
+    double* g = (double*)malloc(sizeof(double) * 3 * no);
+    double* l = (double*)malloc(sizeof(double) * no);
+    for (int sp = 0; sp < 2; ++sp) {
+        const int n = orc_spin_count(s, sp), off = orc_spin_offset(s, sp);
+        for (int k = 0; k < n; ++k) {
+            const int i = off + k;
+            orc_spo_vgl(s, pos + 3 * i, v, g, l);
+            double gD[3] = {0.0, 0.0, 0.0}, gJ[3], lJ;
+            for (int j = 0; j < n; ++j) {
+                const double b = B[sp][j * n + k];
+                gD[0] += b * g[j]; gD[1] += b * g[no + j]; gD[2] += b * g[2 * no + j];
+            }
+            orc_jastrow_grad_lap(s, pos, i, gJ, &lJ);
+            for (int a = 0; a < 3; ++a) vel[3 * i + a] = gD[a] + gJ[a];
+        }
+    }
+    free(v); free(g); free(l);
+}
+
+/*
  * All-electron move (section "Trial Moves", all coordinates proposed together):
  * r'_i = r_i + sigma xi_i for every electron from the PROPOSE counters of the
  * particle-by-particle sweep, one uniform per walker (electron 0's ACCEPT
  * counter), accepted with probability min(1, |Psi(R')/Psi(R)|^2), the ratio from
  * fresh LU determinants of both spin blocks at R' and the change of the full
  * Jastrow factor.  A singular matrix at R' rejects the move.
+ *
+ * With drift (all_electron == 2) the proposal is drawn from the drift-diffusion
+ * transition probability T(R -> R') (eq. trans_prob_alle with the wavefunction force
+ * F = 2 grad ln Psi and lambda = 1/2): the time step is tau = sigma^2, the Gaussian
+ * has variance 2 lambda tau = tau per coordinate and mean R + lambda tau F = R + tau v(R),
+ * v = grad ln|Psi|.  The acceptance (eq. accept_reject) gains T(R' -> R) / T(R -> R'),
+ * which with R' - R = tau v(R) + sigma xi is
+ *   exp( sum_i [ |sigma xi_i|^2 - |sigma xi_i + tau (v_i(R) + v_i(R'))|^2 ] / (2 tau) ).
  */
 static void orc_ae_step(const orc_system* s, orc_walker* w, uint32_t walker_id, uint32_t step,
                         uint8_t* accept_bits)
@@ -784,10 +821,20 @@ static void orc_ae_step(const orc_system* s, orc_walker* w, uint32_t walker_id, 
     double* v = (double*)malloc(sizeof(double) * no);
     double* g = (double*)malloc(sizeof(double) * 3 * no);
     double* l = (double*)malloc(sizeof(double) * no);
+    const int drift = s->all_electron == 2;
+    const double tau = s->sigma * s->sigma;
+    double* sx = (double*)malloc(sizeof(double) * 3 * (N > 0 ? N : 1));   /* sigma xi */
+    double* vR = (double*)malloc(sizeof(double) * 3 * (N > 0 ? N : 1));
+    double* vP = (double*)malloc(sizeof(double) * 3 * (N > 0 ? N : 1));
+    if (drift) orc_drift_velocity(s, w->pos, w->B, vR);
     for (int i = 0; i < N; ++i) {
         double xi[3];
         orc_gauss3(s->seed, walker_id, step, (uint32_t)i, xi);
-        for (int a = 0; a < 3; ++a) rp[3 * i + a] = orc_wrap(w->pos[3 * i + a] + s->sigma * xi[a], s->L);
+        for (int a = 0; a < 3; ++a) {
+            sx[3 * i + a] = s->sigma * xi[a];
+            rp[3 * i + a] = drift ? orc_wrap(w->pos[3 * i + a] + tau * vR[3 * i + a] + sx[3 * i + a], s->L)
+                                  : orc_wrap(w->pos[3 * i + a] + sx[3 * i + a], s->L);
+        }
     }
     double* Ap[2];
     double* Bp[2];
@@ -805,8 +852,16 @@ static void orc_ae_step(const orc_system* s, orc_walker* w, uint32_t walker_id, 
     }
     const double dlog = (ldp[0] - w->logdet[0]) + (ldp[1] - w->logdet[1]);
     const double dJ = orc_jastrow_total(s, rp) - orc_jastrow_total(s, w->pos);
+    double logT = 0.0;
+    if (drift && !bad) {
+        orc_drift_velocity(s, rp, Bp, vP);
+        for (int q = 0; q < 3 * N; ++q) {
+            const double back = sx[q] + tau * (vR[q] + vP[q]);
+            logT += (sx[q] * sx[q] - back * back) / (2.0 * tau);
+        }
+    }
     const double u = orc_accept_uniform(s->seed, walker_id, step, 0u);
-    const int acc = !bad && u < exp(2.0 * (dlog + dJ));
+    const int acc = !bad && u < exp(2.0 * (dlog + dJ) + logT);
     if (acc) {
         for (int sp = 0; sp < 2; ++sp) {
             double* t = w->A[sp]; w->A[sp] = Ap[sp]; Ap[sp] = t;
@@ -820,7 +875,7 @@ static void orc_ae_step(const orc_system* s, orc_walker* w, uint32_t walker_id, 
     if (accept_bits)
         for (int i = 0; i < N; ++i) accept_bits[i] = (uint8_t)acc;
     for (int sp = 0; sp < 2; ++sp) { free(Ap[sp]); free(Bp[sp]); }
-    free(rp); free(v); free(g); free(l);
+    free(rp); free(v); free(g); free(l); free(sx); free(vR); free(vP);
 }
 
 /*

@@ -60,6 +60,7 @@ class Workload:
     pw_k: Optional[np.ndarray] = None     # [n_orb][3] wave vectors of the analytic plane-wave orbitals
     pw_kind: Optional[np.ndarray] = None  # [n_orb] 0 = cos(k.r), 1 = sin(k.r)
     all_electron: bool = False    # moves: False = particle-by-particle sweeps, True = all-electron moves
+    drift: bool = False           # all-electron moves drawn from the drift-diffusion distribution
 
     @property
     def n_elec(self) -> int:
