@@ -102,8 +102,15 @@ typedef enum { QMC_H_KINETIC = 0, QMC_H_COULOMB_EWALD = 1 } qmc_hamiltonian;
  *                 Gauss-Jordan determinants of both spin blocks at R' and the
  *                 full Jastrow change; a singular matrix at R' rejects.
  *                 delay_rank and recompute_period do not apply.
+ *                 QMC_MOVE_ALL_DRIFT (2): all-electron moves drawn from the
+ *                 drift-diffusion distribution (section "Trial Moves", eq.
+ *                 trans_prob_alle with the wavefunction force F = 2 grad ln
+ *                 Psi and lambda = 1/2): time step tau = sigma^2, every
+ *                 electron proposed at r + tau grad ln|Psi| + sigma xi, the
+ *                 acceptance (eq. accept_reject) including the ratio of the
+ *                 transition probabilities T(R'->R)/T(R->R').  N <= 1024.
  */
-enum { QMC_MOVE_PBYP = 0, QMC_MOVE_ALL = 1 };
+enum { QMC_MOVE_PBYP = 0, QMC_MOVE_ALL = 1, QMC_MOVE_ALL_DRIFT = 2 };
 
 typedef struct {
     int32_t n_up, n_dn;

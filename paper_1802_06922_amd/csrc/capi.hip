@@ -117,6 +117,9 @@ struct qmc_system_s {
   double* ae_dj = nullptr;
   int* ae_sign = nullptr;
   int* ae_status = nullptr;
+  double* ae_vcur = nullptr;   // drift moves: velocities at R, at R', and the transition-ratio logs
+  double* ae_vprop = nullptr;
+  double* ae_logT = nullptr;
   double* scratch = nullptr;
   double* drift = nullptr;
   double* energy = nullptr;
@@ -155,6 +158,7 @@ Walkers<T> walkers_of(qmc_system s) {
   w.nacc = s->nacc; w.status = s->status; w.val64 = s->val64; w.nguard = s->nguard; w.sweep_ctr = s->sweep_ctr;
   w.xinv = static_cast<T*>(s->xinv);
   w.row_flip = 0;
+  w.drift_v = s->d.move_kind == QMC_MOVE_ALL_DRIFT ? s->ae_vcur : nullptr;
   return w;
 }
 
@@ -343,11 +347,12 @@ void free_walkers(qmc_system s) {
   s->ae_binv = nullptr;
   s->ae_logdet = s->ae_dj = nullptr;
   s->ae_sign = s->ae_status = nullptr;
+  s->ae_vcur = s->ae_vprop = s->ae_logT = nullptr;
 }
 
 struct WalkerSizes {
   size_t pos, prop, vgl, cur, binv, logdet, sign, acc, nacc, status, scratch, drift, energy, val64, nguard, sweep,
-      xinv, ae_binv, ae_logdet, ae_dj, ae_sign, ae_status;
+      xinv, ae_binv, ae_logdet, ae_dj, ae_sign, ae_status, ae_vel, ae_logT;
   size_t total() const {
     return align_up(pos) + align_up(prop) + align_up(vgl) + align_up(cur) + align_up(binv) +
            align_up(logdet) + align_up(sign) + align_up(acc) + align_up(nacc) + align_up(status) +
@@ -355,7 +360,8 @@ struct WalkerSizes {
            align_up(sweep) + align_up(xinv) +
            (ae_binv ? align_up(ae_binv) + align_up(ae_logdet) + align_up(ae_dj) + align_up(ae_sign) +
                           align_up(ae_status)
-                    : 0);
+                    : 0) +
+           (ae_vel ? 2 * align_up(ae_vel) + align_up(ae_logT) : 0);
   }
 };
 
@@ -380,12 +386,15 @@ WalkerSizes walker_sizes(int n_up, int n_dn, int precision, int W, int n_orb, in
   z.xinv = precision == QMC_MIXED ? W * bs * ts : 0;
   z.nguard = W * sizeof(uint32_t);
   z.sweep = sizeof(uint32_t);
-  const bool ae = move_kind == QMC_MOVE_ALL;
+  const bool ae = move_kind == QMC_MOVE_ALL || move_kind == QMC_MOVE_ALL_DRIFT;
   z.ae_binv = ae ? W * bs * ts : 0;
   z.ae_logdet = ae ? W * 2 * sizeof(double) : 0;
   z.ae_dj = ae ? W * sizeof(double) : 0;
   z.ae_sign = ae ? W * 2 * sizeof(int) : 0;
   z.ae_status = ae ? W * sizeof(int) : 0;
+  const bool drift = move_kind == QMC_MOVE_ALL_DRIFT;
+  z.ae_vel = drift ? W * N * 3 * sizeof(double) : 0;
+  z.ae_logT = drift ? W * sizeof(double) : 0;
   return z;
 }
 
@@ -413,7 +422,7 @@ qmc_status validate(const qmc_system_desc* d) {
     return fail(nullptr, QMC_ERR_ARG, "delay_rank %d: use 1 (Sherman-Morrison) or a power of two in [4, 64]",
                 d->delay_rank);
   if (d->recompute_period < 0) return fail(nullptr, QMC_ERR_ARG, "recompute_period must be >= 0");
-  if (d->move_kind != QMC_MOVE_PBYP && d->move_kind != QMC_MOVE_ALL)
+  if (d->move_kind != QMC_MOVE_PBYP && d->move_kind != QMC_MOVE_ALL && d->move_kind != QMC_MOVE_ALL_DRIFT)
     return fail(nullptr, QMC_ERR_ARG, "unknown move_kind %d", d->move_kind);
   if (d->hamiltonian != QMC_H_KINETIC && d->hamiltonian != QMC_H_COULOMB_EWALD)
     return fail(nullptr, QMC_ERR_ARG, "unknown hamiltonian %d", d->hamiltonian);
@@ -700,7 +709,13 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
     s->val64 = static_cast<double*>(s->mem.alloc(z.val64));
     s->xinv = s->mem.alloc(z.xinv);
   }
-  const bool ae = s->d.move_kind == QMC_MOVE_ALL;
+  const bool ae = s->d.move_kind != QMC_MOVE_PBYP;
+  const bool drift = s->d.move_kind == QMC_MOVE_ALL_DRIFT;
+  if (drift) {
+    s->ae_vcur = static_cast<double*>(s->mem.alloc(z.ae_vel));
+    s->ae_vprop = static_cast<double*>(s->mem.alloc(z.ae_vel));
+    s->ae_logT = static_cast<double*>(s->mem.alloc(z.ae_logT));
+  }
   if (ae) {
     s->ae_binv = s->mem.alloc(z.ae_binv);
     s->ae_logdet = static_cast<double*>(s->mem.alloc(z.ae_logdet));
@@ -711,7 +726,8 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
   if (!s->pos || !s->prop || !s->vgl || !s->cur || !s->binv || !s->logdet || !s->sign || !s->acc ||
       !s->nacc || !s->status || !s->scratch || !s->drift || !s->energy || !s->nguard || !s->sweep_ctr ||
       (s->d.precision == QMC_MIXED && (!s->val64 || !s->xinv)) ||
-      (ae && (!s->ae_binv || !s->ae_logdet || !s->ae_dj || !s->ae_sign || !s->ae_status))) {
+      (ae && (!s->ae_binv || !s->ae_logdet || !s->ae_dj || !s->ae_sign || !s->ae_status)) ||
+      (drift && (!s->ae_vcur || !s->ae_vprop || !s->ae_logT))) {
     free_walkers(s);
     return fail(s, QMC_ERR_OOM, "device allocation of %zu walker bytes failed", z.total());
   }
@@ -774,6 +790,13 @@ namespace {
 // The proposals of one sweep (gather), on stream st.
 qmc_status sweep_gather(qmc_system s, hipStream_t st) {
   hipError_t e;
+  if (s->d.move_kind == QMC_MOVE_ALL_DRIFT) {
+    // drift velocities at the current configuration, which the proposals are centred on
+    e = s->d.precision == QMC_MIXED
+            ? timed(s, 0, [&] { return launch_ae_velocity<float>(s->P, walkers_of<float>(s), AeProposal<float>{}, 0, s->ae_vcur, nullptr, st); }, st)
+            : timed(s, 0, [&] { return launch_ae_velocity<double>(s->P, walkers_of<double>(s), AeProposal<double>{}, 0, s->ae_vcur, nullptr, st); }, st);
+    if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "drift velocity launch: %s", hipGetErrorString(e));
+  }
   if (s->d.precision == QMC_MIXED)
     e = timed(s, 0, [&] { return launch_gather<float>(s->P, walkers_of<float>(s), static_cast<const float*>(s->d_table), 0, st, s->gather_lanes_log2); }, st);
   else
@@ -797,12 +820,16 @@ hipError_t ae_step(qmc_system s) {
   prop.row_flip = 1;
   e = launch_rebuild<T>(s->P, prop, s->scratch, nullptr, s->stream);
   if (e != hipSuccess) return e;
-  AeProposal<T> A{static_cast<T*>(s->ae_binv), s->ae_logdet, s->ae_sign, s->ae_status, s->ae_dj};
+  AeProposal<T> A{static_cast<T*>(s->ae_binv), s->ae_logdet, s->ae_sign, s->ae_status, s->ae_dj, s->ae_logT};
+  if (s->d.move_kind == QMC_MOVE_ALL_DRIFT) {
+    e = launch_ae_velocity<T>(s->P, walkers_of<T>(s), A, 1, s->ae_vprop, s->ae_vcur, s->stream);
+    if (e != hipSuccess) return e;
+  }
   return launch_ae_apply<T>(s->P, walkers_of<T>(s), A, s->stream);
 }
 
 qmc_status sweep_chain(qmc_system s) {
-  if (s->d.move_kind == QMC_MOVE_ALL) {
+  if (s->d.move_kind != QMC_MOVE_PBYP) {
     // the inverses are recomputed at every accepted move, so no periodic rebuild is needed
     const hipError_t e = s->d.precision == QMC_MIXED ? timed(s, 1, [&] { return ae_step<float>(s); })
                                                      : timed(s, 1, [&] { return ae_step<double>(s); });

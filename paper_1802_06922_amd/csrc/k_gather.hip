@@ -115,9 +115,18 @@ __device__ __forceinline__ void gather_item(const SysParams& P, const Walkers<T>
     double sa, ca;
     sincos(2.0 * kPi * a1, &sa, &ca);
     const double cb = cos(2.0 * kPi * b1);
-    r[0] = wrap_cell(p0[0] + P.sigma * (ra * ca), P.L);
-    r[1] = wrap_cell(p0[1] + P.sigma * (ra * sa), P.L);
-    r[2] = wrap_cell(p0[2] + P.sigma * (rb * cb), P.L);
+    if (Wk.drift_v) {
+      // drift-diffusion proposal: mean r + tau v with tau = sigma^2 (variance tau per coordinate)
+      const double* v = Wk.drift_v + item * 3;
+      const double tau = P.sigma * P.sigma;
+      r[0] = wrap_cell(p0[0] + tau * v[0] + P.sigma * (ra * ca), P.L);
+      r[1] = wrap_cell(p0[1] + tau * v[1] + P.sigma * (ra * sa), P.L);
+      r[2] = wrap_cell(p0[2] + tau * v[2] + P.sigma * (rb * cb), P.L);
+    } else {
+      r[0] = wrap_cell(p0[0] + P.sigma * (ra * ca), P.L);
+      r[1] = wrap_cell(p0[1] + P.sigma * (ra * sa), P.L);
+      r[2] = wrap_cell(p0[2] + P.sigma * (rb * cb), P.L);
+    }
     if (lane == 0) {
       double* pr = Wk.prop + item * 4;
       pr[0] = r[0]; pr[1] = r[1]; pr[2] = r[2]; pr[3] = u0;

@@ -65,6 +65,8 @@ struct Walkers {
   uint32_t* sweep_ctr;  // index of the next sweep (device side, so captured sweeps replay correctly)
   T* xinv;            // [W][bstride]: FP64-refined copy of binv the measurement reads (mixed only, else null)
   int row_flip;       // rebuilds: 1 = invert the rows of the buffer that does not hold the current row
+  const double* drift_v;  // [W][N][3] or null: drift velocities grad ln|Psi| at the current positions;
+                          // the sweep's proposals then take the mean r + sigma^2 v
 };
 
 // ---------------------------------------------------------------------------

@@ -161,10 +161,16 @@ struct AeProposal {
   int* sign;        // [W][2]
   int* status;      // [W]: nonzero = a singular matrix at R'
   double* dj;       // [W]: J(R') - J(R)
+  double* logT;     // [W] or null: log T(R' -> R) / T(R -> R') of drift-diffusion proposals
 };
 // dj[w] = J(R') - J(R) from pos and the proposals; clears status_prop.
 hipError_t launch_ae_jastrow(const SysParams& P, const double* pos, const double* prop, double* dj,
                              int* status_prop, hipStream_t st);
+// Drift velocities grad ln|Psi| of every electron at R (prop = 0) or R' (prop = 1, also
+// A.logT from vcur = v(R)); vel, vcur: [W][N][3].  N at most 1024.
+template <typename T>
+hipError_t launch_ae_velocity(const SysParams& P, const Walkers<T>& Wk, const AeProposal<T>& A, int prop,
+                              double* vel, const double* vcur, hipStream_t st);
 // Accept or reject every walker's all-electron move and install R' on acceptance.
 template <typename T>
 hipError_t launch_ae_apply(const SysParams& P, const Walkers<T>& Wk, const AeProposal<T>& A, hipStream_t st);

@@ -152,7 +152,8 @@ def make_desc(wl, keep: list, arena=None, arena_bytes: int = 0, tie_guard: float
     d.tie_guard = tie_guard
     d.arena = arena
     d.arena_bytes = arena_bytes
-    d.move_kind = 1 if getattr(wl, "all_electron", False) else 0
+    ae = bool(getattr(wl, "all_electron", False))
+    d.move_kind = (2 if getattr(wl, "drift", False) else 1) if ae else 0
     return d
 
 

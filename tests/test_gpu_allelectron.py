@@ -34,8 +34,8 @@ def _rel(a, b):
     return np.abs(a - b) / np.maximum(np.abs(b), 1.0)
 
 
-def _ae(wl, sigma):
-    return dataclasses.replace(wl, all_electron=True, sigma=sigma)
+def _ae(wl, sigma, drift=False):
+    return dataclasses.replace(wl, all_electron=True, sigma=sigma, drift=drift)
 
 
 def _run(gpu, wl, n_sweeps, sample):
@@ -54,9 +54,9 @@ def _run(gpu, wl, n_sweeps, sample):
     return b[sample], np.stack(energies, 1)[sample], pos[sample], ld[sample], sg[sample]
 
 
-def _compare(gpu, orc, wl, n_sweeps, walkers, tol=E_TOL):
+def _compare(gpu, orc, wl, n_sweeps, walkers, tol=E_TOL, pos_tol=1e-11):
     sample = np.asarray(walkers)
-    print(f"[ae] {wl.name} {wl.precision} sigma={wl.sigma}: walkers {sample[:6].tolist()}.. "
+    print(f"[ae] {wl.name} {wl.precision} drift={wl.drift} sigma={wl.sigma}: walkers {sample[:6].tolist()}.. "
           f"{n_sweeps} sweeps", flush=True)
     b, e, pos, ld, sg = _run(gpu, wl, n_sweeps, sample)
     ref = orc.OracleSystem(wl).run(sample, n_sweeps, measure_every=1)
@@ -66,8 +66,8 @@ def _compare(gpu, orc, wl, n_sweeps, walkers, tol=E_TOL):
     rel = _rel(e, ref["energies"])
     print(f"[ae] acceptance {b[:, :, 0].mean():.3f}, rel energy error max {rel.max():.2e}", flush=True)
     assert rel.max() < tol, f"max rel energy error {rel.max():.3e}"
-    np.testing.assert_allclose(pos, ref["final_pos"], atol=1e-11)
-    np.testing.assert_allclose(ld, ref["logdet"], atol=1e-9)
+    np.testing.assert_allclose(pos, ref["final_pos"], atol=pos_tol)
+    np.testing.assert_allclose(ld, ref["logdet"], atol=1e-9 if pos_tol <= 1e-11 else 1e-6)
     assert np.array_equal(sg, ref["sign"])
     return b
 
@@ -80,10 +80,7 @@ def test_ae_heg14_trajectory(gpu, orc):
 
 def test_ae_ragged_solid_with_ions(gpu, orc):
     """9 up and 7 down electrons (ragged rows), ions, B-spline one- and two-body Jastrows."""
-    wl = qi.solid(18, 14, n_walkers=24, n_sweeps=1)
-    wl.n_up, wl.n_dn, wl.n_orb = 9, 7, 9
-    wl.coefs = qi.solid_table(9, 14, seed=3, dtype=np.float64)
-    b = _compare(gpu, orc, _ae(wl, 0.1), 20, range(24))
+    b = _compare(gpu, orc, _ae(_ragged(), 0.1), 20, range(24))
     assert 0.2 < b.mean() < 0.9
 
 
@@ -120,12 +117,51 @@ def test_ae_mixed_precision(gpu, orc):
     assert 0.1 < b.mean() < 0.95
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_ae_run_steps_matches_sweep_then_measure(gpu, precision):
+def _ragged():
+    wl = qi.solid(18, 14, n_walkers=24, n_sweeps=1)
+    wl.n_up, wl.n_dn, wl.n_orb = 9, 7, 9
+    wl.coefs = qi.solid_table(9, 14, seed=3, dtype=np.float64)
+    return wl
+
+
+# Drift-diffusion all-electron moves (eq. trans_prob_alle with F = 2 grad ln Psi, tau =
+# sigma^2; acceptance eq. accept_reject with the transition ratio).  The drift velocities are
+# sums in another order than the oracle's, so proposals agree to rounding (1e-11 bohr here).
+
+def test_drift_heg14_trajectory(gpu, orc):
+    b = _compare(gpu, orc, _ae(qi.heg14(), 0.1, drift=True), 40, range(8))
+    assert 0.2 < b.mean() < 0.95
+
+
+def test_drift_ragged_solid_with_ions(gpu, orc):
+    b = _compare(gpu, orc, _ae(_ragged(), 0.1, drift=True), 15, range(24))
+    assert 0.2 < b.mean() < 0.95
+
+
+def test_drift_solid128_sampled_walkers(gpu, orc):
+    _compare(gpu, orc, _ae(qi.solid128(), 0.03, drift=True), 5, [0, 255, 511])
+
+
+def test_drift_large_spin_blocks(gpu, orc):
+    _compare(gpu, orc, _ae(qi.solid(400, 24, n_walkers=4, n_sweeps=1), 0.01, drift=True), 3, range(4))
+
+
+def test_drift_mixed_precision(gpu, orc):
+    """FP32 inverses and gradient rows: the drift velocities carry FP32 rounding, so the
+    proposals agree with the oracle's to about 1e-9 bohr and the decisions are still the
+    oracle's (none falls that close to its threshold)."""
+    wl = qi.solid(48, 16, n_walkers=16, n_sweeps=1, precision="mixed", table_dtype=np.float32)
+    b = _compare(gpu, orc, _ae(wl, 0.08, drift=True), 12, range(16), tol=MIXED_TOL, pos_tol=1e-7)
+    assert 0.1 < b.mean() < 0.97
+
+
+@pytest.mark.parametrize("precision,drift", [("fp64", False), ("mixed", False), ("fp64", True),
+                                             ("mixed", True)])
+def test_ae_run_steps_matches_sweep_then_measure(gpu, precision, drift):
     """Pipelined steps with all-electron moves: the same bits as sweep + measurement calls."""
     import torch
     kw = dict(table_dtype=np.float32) if precision == "mixed" else {}
-    wl = _ae(qi.solid(64, 20, n_walkers=32, n_sweeps=1, precision=precision, **kw), 0.04)
+    wl = _ae(qi.solid(64, 20, n_walkers=32, n_sweeps=1, precision=precision, **kw), 0.04, drift=drift)
     n = 7
     res = []
     for pipelined in (False, True):
