@@ -47,6 +47,11 @@ def lib():
         L.orc_gauss3.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, dp]
         L.orc_accept_uniform.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32]
         L.orc_accept_uniform.restype = C.c_double
+        L.orc_branch_uniform.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32]
+        L.orc_branch_uniform.restype = C.c_double
+        L.orc_dmc_run.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int,
+                                  dp, dp, ip, ip, dp, dp, ip, C.c_int]
+        L.orc_dmc_run.restype = C.c_int
         L.orc_init_position.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_double, dp]
         L.orc_fp32_inverse_residual.argtypes = [C.c_int, dp, dp]
         L.orc_fp32_inverse_residual.restype = C.c_double
@@ -206,6 +211,33 @@ class OracleSystem:
                 "logdet": ld, "sign": sg, "logdet_lu": ldlu}
 
 
+    def dmc(self, n_slots: int, n_target: int, n_steps: int, e_trial: float = float("nan"),
+            feedback: float = 1.0, sweep0: int = 0, threads: int = 0):
+        """Diffusion Monte Carlo on ``n_slots`` walker slots (the first ``n_target`` alive at
+        the start, drawn from the INIT stream with walker id = slot): per-step statistics
+        (E, sum of weights, population, E_T used, dropped copies, node-crossing moves rejected),
+        per-slot weights,
+        multiplicities, copy plans and local energies, final positions and signs."""
+        N = self.wl.n_elec
+        st = np.zeros((n_steps, 6))
+        w = np.zeros((n_steps, n_slots))
+        m = np.zeros((n_steps, n_slots), dtype=np.int32)
+        pl = np.zeros((n_steps, n_slots), dtype=np.int32)
+        en = np.zeros((n_steps, n_slots))
+        fp = np.zeros((n_slots, N, 3))
+        fs = np.zeros(n_slots, dtype=np.int32)
+        rc = lib().orc_dmc_run(self.ptr, n_slots, n_target, e_trial, feedback, sweep0, n_steps, _dp(st),
+                               _dp(w), _ip(m), _ip(pl), _dp(en), _dp(fp), _ip(fs), threads)
+        if rc == -2:
+            raise ValueError("DMC needs drift-diffusion all-electron moves (all_electron and drift)")
+        if rc == -1:
+            raise ValueError("the population died out")
+        if rc:
+            raise ValueError(f"singular Slater matrix at initialisation of slot {rc - 1}")
+        return {"stats": st, "weights": w, "mult": m, "plan": pl, "energies": en,
+                "final_pos": fp, "final_sign": fs}
+
+
 # -- free functions ------------------------------------------------------------------
 
 def philox4x32_10(ctr, key):
@@ -231,6 +263,10 @@ def gauss3(seed, walker, sweep, electron):
 
 def accept_uniform(seed, walker, sweep, electron):
     return lib().orc_accept_uniform(seed, walker, sweep, electron)
+
+
+def branch_uniform(seed, slot, step):
+    return lib().orc_branch_uniform(seed, slot, step)
 
 
 def init_position(seed, walker, electron, L, attempt=0):

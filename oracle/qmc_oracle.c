@@ -71,7 +71,7 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-enum { ORC_INIT = 1, ORC_PROPOSE = 2, ORC_ACCEPT = 3 };
+enum { ORC_INIT = 1, ORC_PROPOSE = 2, ORC_ACCEPT = 3, ORC_BRANCH = 4 };
 /* Initial configurations: at most ORC_INIT_ATTEMPTS draws per walker; a draw is kept
  * when the single-precision rounding of its inverses leaves residual <= ORC_INIT_RESIDUAL. */
 #define ORC_INIT_ATTEMPTS 16
@@ -110,6 +110,14 @@ double orc_accept_uniform(uint64_t seed, uint32_t walker, uint32_t sweep, uint32
 {
     double u[2];
     orc_uniform2(seed, ORC_ACCEPT, 0, walker, sweep, electron, u);
+    return u[0];
+}
+
+/* The uniform xi of the branching multiplicity of walker slot `slot` at DMC step `step`. */
+double orc_branch_uniform(uint64_t seed, uint32_t slot, uint32_t step)
+{
+    double u[2];
+    orc_uniform2(seed, ORC_BRANCH, 0, slot, step, 0u, u);
     return u[0];
 }
 
@@ -803,7 +811,8 @@ static void orc_drift_velocity(const orc_system* s, const double* pos, double* c
  * particle-by-particle sweep, one uniform per walker (electron 0's ACCEPT
  * counter), accepted with probability min(1, |Psi(R')/Psi(R)|^2), the ratio from
  * fresh LU determinants of both spin blocks at R' and the change of the full
- * Jastrow factor.  A singular matrix at R' rejects the move.
+ * Jastrow factor.  A singular matrix at R' rejects the move.  With fixed_node a move to a
+ * configuration where Psi has the other sign is rejected too; returns 1 for such a move.
  *
  * With drift (all_electron == 2) the proposal is drawn from the drift-diffusion
  * transition probability T(R -> R') (eq. trans_prob_alle with the wavefunction force
@@ -813,8 +822,8 @@ static void orc_drift_velocity(const orc_system* s, const double* pos, double* c
  * which with R' - R = tau v(R) + sigma xi is
  *   exp( sum_i [ |sigma xi_i|^2 - |sigma xi_i + tau (v_i(R) + v_i(R'))|^2 ] / (2 tau) ).
  */
-static void orc_ae_step(const orc_system* s, orc_walker* w, uint32_t walker_id, uint32_t step,
-                        uint8_t* accept_bits)
+static int orc_ae_step(const orc_system* s, orc_walker* w, uint32_t walker_id, uint32_t step,
+                       uint8_t* accept_bits, int fixed_node)
 {
     const int N = s->n_up + s->n_dn, no = s->n_orb;
     double* rp = (double*)malloc(sizeof(double) * 3 * (N > 0 ? N : 1));
@@ -861,7 +870,10 @@ static void orc_ae_step(const orc_system* s, orc_walker* w, uint32_t walker_id, 
         }
     }
     const double u = orc_accept_uniform(s->seed, walker_id, step, 0u);
-    const int acc = !bad && u < exp(2.0 * (dlog + dJ) + logT);
+    /* fixed node (section "Diffusion Monte Carlo"): a move that changes the sign of the
+     * wavefunction (the Jastrow factor is positive, so the sign of D_up D_dn) is rejected */
+    const int crossed = fixed_node && !bad && sgp[0] * sgp[1] != w->sign[0] * w->sign[1];
+    const int acc = !bad && !crossed && u < exp(2.0 * (dlog + dJ) + logT);
     if (acc) {
         for (int sp = 0; sp < 2; ++sp) {
             double* t = w->A[sp]; w->A[sp] = Ap[sp]; Ap[sp] = t;
@@ -876,6 +888,7 @@ static void orc_ae_step(const orc_system* s, orc_walker* w, uint32_t walker_id, 
         for (int i = 0; i < N; ++i) accept_bits[i] = (uint8_t)acc;
     for (int sp = 0; sp < 2; ++sp) { free(Ap[sp]); free(Bp[sp]); }
     free(rp); free(v); free(g); free(l); free(sx); free(vR); free(vP);
+    return crossed;
 }
 
 /*
@@ -896,6 +909,33 @@ static void orc_ae_step(const orc_system* s, orc_walker* w, uint32_t walker_id, 
  * Returns 0, or 1 + walker index of the first walker whose Slater matrix
  * was singular at initialisation.
  */
+/* Initial configuration of walker wid: the given positions (wrapped), or uniform draws
+ * from the INIT stream, redrawn while a Slater matrix is singular or too badly conditioned
+ * for its inverse to survive rounding to single precision.  Returns nonzero if singular. */
+static int orc_walker_init(const orc_system* s, orc_walker* w, uint32_t wid, const double* pos)
+{
+    const int N = s->n_up + s->n_dn;
+    if (pos) {
+        for (int i = 0; i < 3 * N; ++i) w->pos[i] = orc_wrap(pos[i], s->L);
+        return orc_walker_rebuild(s, w);
+    }
+    int bad = 0;
+    for (uint32_t att = 0;; ++att) {
+        for (int i = 0; i < N; ++i) orc_init_position(s->seed, wid, (uint32_t)i, att, s->L, w->pos + 3 * i);
+        bad = orc_walker_rebuild(s, w);
+        double res = 0.0;
+        for (int sp = 0; sp < 2 && !bad; ++sp) {
+            const int n = orc_spin_count(s, sp);
+            if (n > 0) {
+                const double r = orc_fp32_inverse_residual(n, w->A[sp], w->B[sp]);
+                if (r > res) res = r;
+            }
+        }
+        if ((!bad && res <= ORC_INIT_RESIDUAL) || att + 1 >= ORC_INIT_ATTEMPTS) break;
+    }
+    return bad;
+}
+
 int orc_vmc_run(const orc_system* s, int n_walk, const int32_t* walker_ids, const double* init_pos,
                 int sweep0, int n_sweeps, int measure_every, double* energies, uint8_t* accept_bits,
                 double* pos_trace, double* final_pos, double* logdet, int32_t* sign, double* logdet_lu,
@@ -919,28 +959,7 @@ int orc_vmc_run(const orc_system* s, int n_walk, const int32_t* walker_ids, cons
         orc_walker w;
         orc_walker_alloc(s, &w);
         uint32_t wid = (uint32_t)walker_ids[wi];
-        int bad_init;
-        if (init_pos) {
-            for (int i = 0; i < N; ++i)
-                for (int a = 0; a < 3; ++a) w.pos[3 * i + a] = orc_wrap(init_pos[((size_t)wi * N + i) * 3 + a], s->L);
-            bad_init = orc_walker_rebuild(s, &w);
-        } else {
-            /* uniform configurations, redrawn while a Slater matrix is singular or too badly
-             * conditioned for its inverse to survive rounding to single precision */
-            for (uint32_t att = 0;; ++att) {
-                for (int i = 0; i < N; ++i) orc_init_position(s->seed, wid, (uint32_t)i, att, s->L, w.pos + 3 * i);
-                bad_init = orc_walker_rebuild(s, &w);
-                double res = 0.0;
-                for (int sp = 0; sp < 2 && !bad_init; ++sp) {
-                    const int n = orc_spin_count(s, sp);
-                    if (n > 0) {
-                        const double r = orc_fp32_inverse_residual(n, w.A[sp], w.B[sp]);
-                        if (r > res) res = r;
-                    }
-                }
-                if ((!bad_init && res <= ORC_INIT_RESIDUAL) || att + 1 >= ORC_INIT_ATTEMPTS) break;
-            }
-        }
+        int bad_init = orc_walker_init(s, &w, wid, init_pos ? init_pos + (size_t)wi * N * 3 : NULL);
         if (bad_init) {
 #ifdef _OPENMP
 #pragma omp critical
@@ -952,7 +971,7 @@ int orc_vmc_run(const orc_system* s, int n_walk, const int32_t* walker_ids, cons
         int im = 0;
         for (int st = 0; st < n_sweeps; ++st) {
             uint8_t* bits = accept_bits ? accept_bits + ((size_t)wi * n_sweeps + st) * N : NULL;
-            if (s->all_electron) orc_ae_step(s, &w, wid, (uint32_t)(sweep0 + st), bits);
+            if (s->all_electron) orc_ae_step(s, &w, wid, (uint32_t)(sweep0 + st), bits, 0);
             else orc_sweep(s, &w, wid, (uint32_t)(sweep0 + st), bits);
             if (pos_trace) memcpy(pos_trace + ((size_t)wi * n_sweeps + st) * N * 3, w.pos, sizeof(double) * 3 * N);
             if (measure_every > 0 && (st + 1) % measure_every == 0 && im < n_meas) {
@@ -971,6 +990,168 @@ int orc_vmc_run(const orc_system* s, int n_walk, const int32_t* walker_ids, cons
         orc_walker_free(&w);
     }
     return first_bad;
+}
+
+/* Deep copy of a walker's state: positions, Slater matrices, inverses, log|D| and signs. */
+static void orc_walker_copy(const orc_system* s, orc_walker* dst, const orc_walker* src)
+{
+    const int N = s->n_up + s->n_dn;
+    memcpy(dst->pos, src->pos, sizeof(double) * 3 * N);
+    for (int sp = 0; sp < 2; ++sp) {
+        const int n = orc_spin_count(s, sp);
+        memcpy(dst->A[sp], src->A[sp], sizeof(double) * ((size_t)n * n + 1));
+        memcpy(dst->B[sp], src->B[sp], sizeof(double) * ((size_t)n * n + 1));
+        dst->logdet[sp] = src->logdet[sp];
+        dst->sign[sp] = src->sign[sp];
+        dst->logdet_accum[sp] = src->logdet_accum[sp];
+    }
+}
+
+/*
+ * Diffusion Monte Carlo (section "Diffusion Monte Carlo") on a population held in n_slots
+ * walker slots, of which the first n_target start alive with weight 1 from the INIT stream
+ * (walker id = slot).  Step k (moves use sweep index sweep0 + k):
+ *   1. every alive walker makes one drift-diffusion all-electron move (eq.
+ *      pmc:driftdiffusion_step with the Metropolis acceptance of eq. accept_reject), a move
+ *      that crosses a node (changes the sign of Psi) being rejected (fixed node);
+ *   2. w <- w G_B with G_B = exp(-tau (E_L(R) + E_L(R_new) - 2 E_T) / 2) (eqs.
+ *      pmc:g_growth, pmc:walker_weight), tau = sigma^2, R_new the configuration after the
+ *      move (R itself when rejected);
+ *   3. the mixed estimate E = sum w E_L / sum w over alive walkers (eq.
+ *      pmc:weighted_average);
+ *   4. branching: M = INT(w + xi) copies of every alive walker (xi from the BRANCH stream of
+ *      (slot, k)); walkers with M = 0 die; a walker with M >= 1 keeps its slot and its
+ *      M - 1 extra copies take the free slots (slots of dead walkers) in ascending order,
+ *      the copies of lower slots first; copies beyond the free slots are dropped; every
+ *      walker alive after branching has weight 1;
+ *   5. E_T <- E - feedback ln(population / n_target).
+ * Outputs (each nullable): stats[k] = (E, sum w, population after branching, E_T used in
+ * step k, dropped copies, moves rejected for crossing a node); weights[k][slot] = w after step 2 (0 for dead slots);
+ * mult[k][slot] = M (0 for dead); plan[k][slot] = source slot of a copy placed there, or -1;
+ * energies[k][slot] = E_L after the move (alive slots); final_pos[slot][N][3] and
+ * final_sign[slot] (sign of D_up D_dn) after the last step (alive slots).
+ * Returns 0, 1 + slot of a singular initial walker, -1 if the population dies out, -2 if
+ * the system does not make drift-diffusion all-electron moves.
+ */
+int orc_dmc_run(const orc_system* s, int n_slots, int n_target, double e_trial, double feedback, int sweep0,
+                int n_steps, double* stats, double* weights, int32_t* mult, int32_t* plan, double* energies,
+                double* final_pos, int32_t* final_sign, int n_threads)
+{
+    if (s->all_electron != 2) return -2;
+    const int N = s->n_up + s->n_dn;
+    const double tau = s->sigma * s->sigma;
+    double v_ii = NAN;
+    if (s->coulomb && s->n_ions > 0) {
+        double* q = (double*)malloc(sizeof(double) * s->n_ions);
+        for (int I = 0; I < s->n_ions; ++I) q[I] = s->ion_Z[I];
+        v_ii = orc_ewald(s->n_ions, s->ion_pos, q, s->L, s->ewald_kappa);
+        free(q);
+    }
+    orc_walker* W = (orc_walker*)calloc((size_t)n_slots, sizeof(orc_walker));
+    double* w = (double*)calloc((size_t)n_slots, sizeof(double));
+    double* E = (double*)calloc((size_t)n_slots, sizeof(double));
+    int* alive = (int*)calloc((size_t)n_slots, sizeof(int));
+    int* M = (int*)calloc((size_t)n_slots, sizeof(int));
+    int* pl = (int*)calloc((size_t)n_slots, sizeof(int));
+    int* crossed = (int*)calloc((size_t)n_slots, sizeof(int));
+    for (int j = 0; j < n_slots; ++j) orc_walker_alloc(s, &W[j]);
+    int ret = 0;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+    int first_bad = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int j = 0; j < n_target; ++j) {
+        const int bad = orc_walker_init(s, &W[j], (uint32_t)j, NULL);
+        double o[4] = {0.0, 0.0, 0.0, 0.0};
+        if (!bad) orc_measure(s, &W[j], v_ii, o);
+        E[j] = o[0] + o[1] + o[2] + o[3];
+#ifdef _OPENMP
+#pragma omp critical
+#endif
+        { if (bad && (!first_bad || j + 1 < first_bad)) first_bad = j + 1; }
+    }
+    if (first_bad) { ret = first_bad; goto done; }
+    for (int j = 0; j < n_target; ++j) { alive[j] = 1; w[j] = 1.0; }
+    if (!isfinite(e_trial)) {
+        double se = 0.0;
+        for (int j = 0; j < n_target; ++j) se += E[j];
+        e_trial = se / n_target;
+    }
+    for (int k = 0; k < n_steps; ++k) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+        for (int j = 0; j < n_slots; ++j) {
+            if (!alive[j]) continue;
+            crossed[j] = orc_ae_step(s, &W[j], (uint32_t)j, (uint32_t)(sweep0 + k), NULL, 1);
+            double o[4];
+            orc_measure(s, &W[j], v_ii, o);
+            const double en = o[0] + o[1] + o[2] + o[3];
+            w[j] *= exp(-tau * (E[j] + en - 2.0 * e_trial) / 2.0);
+            E[j] = en;
+        }
+        double sw = 0.0, swe = 0.0;
+        int n_crossed = 0;
+        for (int j = 0; j < n_slots; ++j)
+            if (alive[j]) { sw += w[j]; swe += w[j] * E[j]; n_crossed += crossed[j]; }
+        const double emix = swe / sw;
+        if (weights) for (int j = 0; j < n_slots; ++j) weights[(size_t)k * n_slots + j] = alive[j] ? w[j] : 0.0;
+        if (energies) for (int j = 0; j < n_slots; ++j) energies[(size_t)k * n_slots + j] = alive[j] ? E[j] : NAN;
+        for (int j = 0; j < n_slots; ++j)
+            M[j] = alive[j] ? (int)floor(w[j] + orc_branch_uniform(s->seed, (uint32_t)j, (uint32_t)k)) : 0;
+        /* extra copies (source slot ascending) into free slots (ascending) */
+        int src = 0, left = 0;   /* the source of the next extra copy and its copies still to place */
+        while (src < n_slots && M[src] < 2) ++src;
+        if (src < n_slots) left = M[src] - 1;
+        long dropped = 0;
+        for (int f = 0; f < n_slots; ++f) {
+            pl[f] = -1;
+            if (M[f] != 0) continue;
+            if (src < n_slots) {
+                pl[f] = src;
+                if (--left == 0) {
+                    ++src;
+                    while (src < n_slots && M[src] < 2) ++src;
+                    if (src < n_slots) left = M[src] - 1;
+                }
+            }
+        }
+        if (src < n_slots) {
+            dropped = left;
+            for (int j = src + 1; j < n_slots; ++j) if (M[j] >= 2) dropped += M[j] - 1;
+        }
+        for (int f = 0; f < n_slots; ++f)
+            if (pl[f] >= 0) { orc_walker_copy(s, &W[f], &W[pl[f]]); E[f] = E[pl[f]]; }
+        int pop = 0;
+        for (int j = 0; j < n_slots; ++j) {
+            alive[j] = M[j] >= 1 || pl[j] >= 0;
+            w[j] = alive[j] ? 1.0 : 0.0;
+            pop += alive[j];
+        }
+        if (mult) for (int j = 0; j < n_slots; ++j) mult[(size_t)k * n_slots + j] = M[j];
+        if (plan) for (int j = 0; j < n_slots; ++j) plan[(size_t)k * n_slots + j] = pl[j];
+        if (stats) {
+            double* st = stats + (size_t)k * 6;
+            st[0] = emix; st[1] = sw; st[2] = pop; st[3] = e_trial; st[4] = (double)dropped;
+            st[5] = n_crossed;
+        }
+        if (pop == 0) { ret = -1; goto done; }
+        e_trial = emix - feedback * log((double)pop / n_target);
+    }
+    for (int j = 0; j < n_slots; ++j) {
+        if (final_pos) {
+            if (alive[j]) memcpy(final_pos + (size_t)j * N * 3, W[j].pos, sizeof(double) * 3 * N);
+            else for (int q = 0; q < 3 * N; ++q) final_pos[(size_t)j * N * 3 + q] = NAN;
+        }
+        if (final_sign) final_sign[j] = alive[j] ? W[j].sign[0] * W[j].sign[1] : 0;
+    }
+done:
+    for (int j = 0; j < n_slots; ++j) orc_walker_free(&W[j]);
+    free(W); free(w); free(E); free(alive); free(M); free(pl); free(crossed);
+    return ret;
 }
 
 /* Number of threads the OpenMP runtime would use. */
