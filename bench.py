@@ -2,8 +2,10 @@
 
 One step = one sweep (every electron of every walker proposes once, the
 orbital gather plus the sequential move chain) followed by the local-energy
-measurement of every walker.  Inputs are seeded synthetic workloads from
-``qmc_inputs`` and are resident in HBM before the timed region starts.
+measurement of every walker.  With ``--moves all`` a step is one all-electron
+move per walker instead of the sweep (throughput still counted in electrons
+proposed).  Inputs are seeded synthetic workloads from ``qmc_inputs`` and are
+resident in HBM before the timed region starts.
 
 Prints one JSON line (see the keys below).  ``--gpus N`` with N > 1 exits:
 this build measures one GPU.
@@ -35,7 +37,9 @@ def describe(wl) -> str:
             f"{wl.grid[0]}x{wl.grid[1]}x{wl.grid[2]} {tb} B-spline table, {wl.n_ions} ions, "
             f"{'+'.join(j) or 'no Jastrow'}, {wl.n_walkers} walkers, sigma {wl.sigma}, "
             f"{'Ewald Coulomb' if wl.hamiltonian == 'coulomb' else 'kinetic only'}, "
-            f"{wl.precision}, delay rank {wl.delay_rank}")
+            f"{wl.precision}, " + (("all-electron drift-diffusion moves" if wl.drift else "all-electron moves")
+                                   if getattr(wl, "all_electron", False)
+                                   else f"delay rank {wl.delay_rank}"))
 
 
 def measured_traffic(wl):
@@ -80,7 +84,7 @@ def main(argv=None) -> int:
     ap.add_argument("--delay", type=int, default=None,
                     help="delay rank K (1 = Sherman-Morrison; 4..64 = delayed updates); "
                          "default: autotuned before the timed region")
-    ap.add_argument("--mode", default="single", choices=["single", "batched", "served", "copy"],
+    ap.add_argument("--mode", default="single", choices=["single", "batched", "served", "copy", "dmc"],
                     help="single: one system (default); batched: the four uneven systems in fused "
                          "launches; served: a Poisson request stream with continuous batching; copy: "
                          "a plain 1 GiB device copy (x3), the reference for HBM counter readings")
@@ -93,6 +97,11 @@ def main(argv=None) -> int:
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the mixed-vs-FP64 comparison on the 384-electron system")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--moves", default="pbyp", choices=["pbyp", "all", "drift"],
+                    help="single: particle-by-particle sweeps (default), or one all-electron move per "
+                         "walker per step, plain or drift-diffusion")
+    ap.add_argument("--ae-sigma", type=float, default=None,
+                    help="all-electron proposal width (default: the workload's sigma / sqrt(N))")
     ap.add_argument("--serial", action="store_true",
                     help="single: sweep and measurement calls in turn instead of pipelined steps "
                          "(each kernel then runs alone: the gather's own roofline)")
@@ -116,7 +125,18 @@ def main(argv=None) -> int:
         return bench_served(args)
     if args.mode == "copy":
         return copy_reference()
+    if args.mode == "dmc":
+        return bench_dmc(args)
     wl = qi.WORKLOADS[args.workload]()
+    ae = args.moves in ("all", "drift")
+    if ae:
+        # one move displaces all N electrons: a width sigma / sqrt(N) keeps the mean squared
+        # displacement of the walker that of one particle-by-particle move
+        import dataclasses
+        import math
+        wl = dataclasses.replace(wl, all_electron=True, drift=args.moves == "drift",
+                                 sigma=args.ae_sigma or wl.sigma / math.sqrt(wl.n_elec))
+        args.no_compare = True
     r = run_single(wl, args.steps, args.warmup, args.delay, args.gather_lanes, serial=args.serial)
     W, N = r["walkers"], wl.n_elec
     kt = r["kt"]
@@ -141,7 +161,10 @@ def main(argv=None) -> int:
         "config": {"workload": describe(wl), "walkers": W, "electrons": N, "orbitals": wl.n_orb,
                    "grid": list(wl.grid), "delay_rank": r["delay_rank"],
                    "gather_lanes_log2": r["gather_lanes_log2"],
-                   "step": "1 sweep (N moves per walker) + local energy",
+                   "step": (f"1 all-electron {'drift-diffusion ' if wl.drift else ''}move per walker "
+                            "(N electrons proposed at once, FP64 determinants at R') + local energy")
+                           if ae else
+                           "1 sweep (N moves per walker) + local energy",
                    "steps_run": "sweep and measurement calls in turn" if args.serial else
                    "pipelined (a step's measurement beside the next step's proposals)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -154,6 +177,7 @@ def main(argv=None) -> int:
                      "HBM; --serial times the gather alone)"},
         "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
         "rebuilds_in_timed_steps": r["rebuilds"],
+        "acceptance_last_step": r["acceptance"],
         "sweep_only_moves_per_s": r["sweep_only_moves_per_s"],
         "mean_local_energy": r["mean_local_energy"],
     }
@@ -172,7 +196,7 @@ def run_single(wl, steps: int, warmup: int, delay, lanes=None, serial: bool = Fa
     import torch
 
     from paper_1802_06922_amd import KERNEL_CHAIN, KERNEL_GATHER, KERNEL_MEASURE, KERNEL_REBUILD, System
-    if wl.recompute_period > 0 and steps % wl.recompute_period:
+    if wl.recompute_period > 0 and steps % wl.recompute_period and not wl.all_electron:
         # the timed window holds whole rebuild periods, so it pays for every FP64 rebuild
         steps = (steps // wl.recompute_period + 1) * wl.recompute_period
     if delay is not None:
@@ -184,7 +208,9 @@ def run_single(wl, steps: int, warmup: int, delay, lanes=None, serial: bool = Fa
     else:
         s.set_gather_lanes(lanes)
         lanes_log2 = lanes
-    if delay is None:
+    if wl.all_electron:
+        K = None   # no update chain: every accepted move installs fresh inverses
+    elif delay is None:
         K, _ = s.autotune_delay(ranks=(1, 8, 16, 32, 64), trial_sweeps=3)
         print(f"[bench] {wl.name}: delay rank {K}, gather lanes 2^{lanes_log2} (autotuned)",
               file=sys.stderr, flush=True)
@@ -218,13 +244,14 @@ def run_single(wl, steps: int, warmup: int, delay, lanes=None, serial: bool = Fa
           (("gather", KERNEL_GATHER), ("chain", KERNEL_CHAIN), ("measure", KERNEL_MEASURE))}
     rebuild = s.kernel_timing(KERNEL_REBUILD)
     e_host = energies[steps - 1].cpu().numpy()
+    acceptance = float(s.accept_log().mean())
     pos_host = s.get_walkers()[0]
     s.close()
     moves = W * N * steps
     sweep_ms = (kt["gather"][0] + kt["chain"][0]) / steps
     return {"value": moves / dt, "ms_per_step": dt / steps * 1e3, "kt": kt, "walkers": W, "steps": steps,
             "rebuilds": {"launches": rebuild[1], "ms_per_launch": rebuild[0] / max(rebuild[1], 1)},
-            "delay_rank": K, "gather_lanes_log2": lanes_log2, "sweep_only_moves_per_s": moves / (sweep_ms * steps / 1e3) if sweep_ms > 0 else None,
+            "delay_rank": K, "gather_lanes_log2": lanes_log2, "acceptance": acceptance, "sweep_only_moves_per_s": moves / (sweep_ms * steps / 1e3) if sweep_ms > 0 else None,
             "mean_local_energy": float(e_host.sum(axis=1).mean()), "energies": e_host, "positions": pos_host}
 
 
@@ -262,6 +289,81 @@ def compare_precisions(args):
         "same_walker_positions": same, "components": "kinetic, e-e, e-I, I-I per walker",
         "max": float(rel.max()), "p99": float(np.percentile(rel, 99)), "median": float(np.median(rel))}
     return out
+
+
+def bench_dmc(args) -> int:
+    """Diffusion Monte Carlo steps (drift-diffusion all-electron move of every slot, local
+    energies, branching on the device) on the workload's walker slots; value = electrons of
+    the walkers alive at each step, per second."""
+    import dataclasses
+    import math
+
+    import torch
+
+    import qmc_inputs as qi
+    from paper_1802_06922_amd import KERNEL_CHAIN, KERNEL_GATHER, KERNEL_MEASURE, KERNEL_REBUILD, System
+    wl = qi.WORKLOADS[args.workload]()
+    wl = dataclasses.replace(wl, all_electron=True, drift=True,
+                             sigma=args.ae_sigma or wl.sigma / math.sqrt(wl.n_elec))
+    print(f"[bench] building {wl.name} (DMC)", file=sys.stderr, flush=True)
+    s = System(wl)
+    if args.gather_lanes is None:
+        lanes_log2, _ = s.autotune_gather(trial_sweeps=3)
+    else:
+        s.set_gather_lanes(args.gather_lanes)
+        lanes_log2 = args.gather_lanes
+    W, N = s.W, wl.n_elec
+    target = W * 7 // 8
+    s.dmc_init(target, feedback=1.0)
+    stats = torch.zeros((max(args.steps, args.warmup, 1), 6), dtype=torch.float64, device="cuda")
+    if args.warmup:
+        s.dmc_steps(args.warmup, stats[:args.warmup])
+    torch.cuda.synchronize()
+    _, _, _, pop0 = s.dmc_state()
+    s.set_timing(True)
+    for k in (KERNEL_GATHER, KERNEL_CHAIN, KERNEL_MEASURE, KERNEL_REBUILD):
+        s.kernel_timing(k, reset=True)
+    print(f"[bench] {wl.name}: timing {args.steps} DMC steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.dmc_steps(args.steps, stats[:args.steps])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = {name: s.kernel_timing(k) for name, k in
+          (("gather", KERNEL_GATHER), ("move", KERNEL_CHAIN), ("measure", KERNEL_MEASURE),
+           ("branch", KERNEL_REBUILD))}
+    st = stats[:args.steps].cpu().numpy()
+    s.close()
+    moved = pop0 + st[:-1, 2].sum()   # walkers alive at the start of each timed step
+    b = wl.coefs.dtype.itemsize
+    g_ms, g_n = kt["gather"]
+    avg_gather_s = g_ms / max(g_n, 1) / 1e3
+    achieved = 64 * wl.n_orb * b * W * N / avg_gather_s / 1e9
+    line = {
+        "metric": METRIC + "; DMC mode",
+        "value": moved * N / dt,
+        "unit": "electron-moves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if wl.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": describe(wl), "slots": W, "target_population": target, "electrons": N,
+                   "tau": wl.sigma ** 2, "feedback_hartree": 1.0, "gather_lanes_log2": lanes_log2,
+                   "step": "1 DMC step: drift-diffusion all-electron move of every slot (fixed node), "
+                           "local energies, weights, branching and copies on the device"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(wl),
+                     "kernel": "k_gather (proposal + tricubic B-spline VGL of every orbital)",
+                     "bytes_per_launch": 64 * wl.n_orb * b * W * N, "avg_launch_ms": avg_gather_s * 1e3},
+        "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
+        "population": {"start": pop0, "min": float(st[:, 2].min()), "max": float(st[:, 2].max())},
+        "mixed_estimate_last": float(st[-1, 0]),
+        "dropped_copies": float(st[:, 4].sum()),
+        "node_crossings_rejected": float(st[:, 5].sum()),
+    }
+    print(json.dumps(line), flush=True)
+    return 0
 
 
 def copy_reference() -> int:

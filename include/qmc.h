@@ -199,6 +199,39 @@ qmc_status qmc_measure_local_energy(qmc_system s, double* out, int32_t out_on_de
  * Errors: ARG (negative n_steps, NULL buffer), STATE before init_walkers, DEVICE. */
 qmc_status qmc_run_steps(qmc_system s, int32_t n_steps, double* energies_dev);
 
+/* ---- Diffusion Monte Carlo (section "Diffusion Monte Carlo") ----------------
+ * The handle's W walker slots hold the population (fixed capacity); a slot is
+ * alive while its weight is positive.  Needs move_kind QMC_MOVE_ALL_DRIFT.
+ * A step: every slot makes one drift-diffusion all-electron move (section
+ * "Trial Moves"), a move across a node of Psi being rejected (fixed node);
+ * alive slots take w <- w exp(-tau (E_L(R) + E_L(R_new) - 2 E_T) / 2), tau =
+ * sigma^2 (eqs. pmc:g_growth, pmc:walker_weight); the estimate is E = sum w
+ * E_L / sum w (eq. pmc:weighted_average); branching gives each alive slot
+ * M = INT(w + xi) copies (xi from the BRANCH counter of (slot, step)): M = 0
+ * dies, M >= 1 keeps its slot and its M - 1 extra copies fill the free slots in
+ * ascending order, lower slots' copies first (copies beyond the free slots are
+ * dropped and counted); every walker alive afterwards has weight 1; then
+ * E_T <- E - feedback ln(population / n_target).  Dead slots move too (their
+ * results are never read), so a step runs entirely on the device. */
+
+/* Start a population: slots [0, n_target) alive with weight 1 at their current
+ * configurations, local energies measured; E_T = e_trial, or (NaN) the mean
+ * local energy of the alive slots; feedback >= 0 in hartree.  Synchronises.
+ * Errors: STATE (no walkers, or not QMC_MOVE_ALL_DRIFT), ARG, OOM, NUMERIC. */
+qmc_status qmc_dmc_init(qmc_system s, int32_t n_target, double e_trial, double feedback);
+
+/* n_steps DMC steps on the handle's stream, asynchronous.  stats_dev: device
+ * buffer [n_steps][6] (caller-owned) receiving per step (E, sum of weights
+ * before branching, population after branching, E_T used by the step, dropped
+ * copies, moves rejected for crossing a node).  Errors: STATE, ARG, DEVICE. */
+qmc_status qmc_dmc_steps(qmc_system s, int32_t n_steps, double* stats_dev);
+
+/* Population state (host buffers, each nullable): weights[W] (0 = dead slot),
+ * energies[W] (local energy of each slot's configuration), the current E_T and
+ * the population.  Synchronises.  Errors: STATE; NUMERIC if the population died
+ * out (the state is still returned). */
+qmc_status qmc_dmc_get(qmc_system s, double* weights, double* energies, double* e_trial, int32_t* population);
+
 /* Copy walker state to host buffers (each nullable): pos[W][N][3];
  * logabs_det[W][2] = log|D_up|, log|D_dn| accumulated as the sum of
  * log|R| of the accepted moves since the last full inverse; sign[W][2]. */

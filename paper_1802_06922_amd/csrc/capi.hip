@@ -120,6 +120,13 @@ struct qmc_system_s {
   double* ae_vcur = nullptr;   // drift moves: velocities at R, at R', and the transition-ratio logs
   double* ae_vprop = nullptr;
   double* ae_logT = nullptr;
+  // diffusion Monte Carlo population (allocated by qmc_dmc_init)
+  bool dmc_ready = false, fixed_node = false;
+  double* dmc_w = nullptr;
+  double* dmc_E = nullptr;
+  double* dmc_e4 = nullptr;
+  double* dmc_ctl = nullptr;
+  int* dmc_i = nullptr;   // crossed, mult, plan, xscan, fscan ([W] each), then the 3 control ints
   double* scratch = nullptr;
   double* drift = nullptr;
   double* energy = nullptr;
@@ -348,6 +355,9 @@ void free_walkers(qmc_system s) {
   s->ae_logdet = s->ae_dj = nullptr;
   s->ae_sign = s->ae_status = nullptr;
   s->ae_vcur = s->ae_vprop = s->ae_logT = nullptr;
+  s->dmc_ready = s->fixed_node = false;
+  s->dmc_w = s->dmc_E = s->dmc_e4 = s->dmc_ctl = nullptr;
+  s->dmc_i = nullptr;
 }
 
 struct WalkerSizes {
@@ -792,9 +802,10 @@ qmc_status sweep_gather(qmc_system s, hipStream_t st) {
   hipError_t e;
   if (s->d.move_kind == QMC_MOVE_ALL_DRIFT) {
     // drift velocities at the current configuration, which the proposals are centred on
+    // (timed with the move kernels, so the gather's own time stays separate)
     e = s->d.precision == QMC_MIXED
-            ? timed(s, 0, [&] { return launch_ae_velocity<float>(s->P, walkers_of<float>(s), AeProposal<float>{}, 0, s->ae_vcur, nullptr, st); }, st)
-            : timed(s, 0, [&] { return launch_ae_velocity<double>(s->P, walkers_of<double>(s), AeProposal<double>{}, 0, s->ae_vcur, nullptr, st); }, st);
+            ? timed(s, 1, [&] { return launch_ae_velocity<float>(s->P, walkers_of<float>(s), AeProposal<float>{}, 0, s->ae_vcur, nullptr, st); }, st)
+            : timed(s, 1, [&] { return launch_ae_velocity<double>(s->P, walkers_of<double>(s), AeProposal<double>{}, 0, s->ae_vcur, nullptr, st); }, st);
     if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "drift velocity launch: %s", hipGetErrorString(e));
   }
   if (s->d.precision == QMC_MIXED)
@@ -820,7 +831,8 @@ hipError_t ae_step(qmc_system s) {
   prop.row_flip = 1;
   e = launch_rebuild<T>(s->P, prop, s->scratch, nullptr, s->stream);
   if (e != hipSuccess) return e;
-  AeProposal<T> A{static_cast<T*>(s->ae_binv), s->ae_logdet, s->ae_sign, s->ae_status, s->ae_dj, s->ae_logT};
+  AeProposal<T> A{static_cast<T*>(s->ae_binv), s->ae_logdet, s->ae_sign, s->ae_status, s->ae_dj, s->ae_logT,
+                  s->fixed_node ? 1 : 0, s->fixed_node ? s->dmc_i : nullptr};
   if (s->d.move_kind == QMC_MOVE_ALL_DRIFT) {
     e = launch_ae_velocity<T>(s->P, walkers_of<T>(s), A, 1, s->ae_vprop, s->ae_vcur, s->stream);
     if (e != hipSuccess) return e;
@@ -950,6 +962,122 @@ qmc_status qmc_run_steps(qmc_system s, int32_t n_steps, double* energies_dev) {
   // everything, including the last measurement, completes in the handle's stream order
   HIP_TRY(s, hipStreamWaitEvent(s->stream, s->ev_measured, 0));
   return st;
+}
+
+}  // extern "C"
+
+namespace {
+
+DmcState dmc_state_of(qmc_system s, double* stats) {
+  const size_t W = s->P.W;
+  DmcState D;
+  D.w = s->dmc_w;
+  D.E = s->dmc_E;
+  D.e4 = s->dmc_e4;
+  D.crossed = s->dmc_i;
+  D.mult = s->dmc_i + W;
+  D.plan = s->dmc_i + 2 * W;
+  D.xscan = s->dmc_i + 3 * W;
+  D.fscan = s->dmc_i + 4 * W;
+  D.ictl = s->dmc_i + 5 * W;
+  D.ctl = s->dmc_ctl;
+  D.stats = stats;
+  return D;
+}
+
+}  // namespace
+
+extern "C" {
+
+qmc_status qmc_dmc_init(qmc_system s, int32_t n_target, double e_trial, double feedback) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (!s->has_walkers) return fail(s, QMC_ERR_STATE, "init_walkers first");
+  if (s->d.move_kind != QMC_MOVE_ALL_DRIFT)
+    return fail(s, QMC_ERR_STATE, "diffusion Monte Carlo needs move_kind QMC_MOVE_ALL_DRIFT");
+  const int W = s->P.W;
+  if (n_target < 1 || n_target > W) return fail(s, QMC_ERR_ARG, "n_target must be in [1, %d]", W);
+  if (!(feedback >= 0.0) || !std::isfinite(feedback)) return fail(s, QMC_ERR_ARG, "feedback must be >= 0");
+  if (!std::isnan(e_trial) && !std::isfinite(e_trial)) return fail(s, QMC_ERR_ARG, "e_trial must be finite or NaN");
+  HIP_TRY(s, hipSetDevice(s->device));
+  if (!s->dmc_w) {
+    s->dmc_w = static_cast<double*>(s->mem.alloc(W * sizeof(double)));
+    s->dmc_E = static_cast<double*>(s->mem.alloc(W * sizeof(double)));
+    s->dmc_e4 = static_cast<double*>(s->mem.alloc(W * 4 * sizeof(double)));
+    s->dmc_ctl = static_cast<double*>(s->mem.alloc(2 * sizeof(double)));
+    s->dmc_i = static_cast<int*>(s->mem.alloc((5 * (size_t)W + 3) * sizeof(int)));
+    if (!s->dmc_w || !s->dmc_E || !s->dmc_e4 || !s->dmc_ctl || !s->dmc_i)
+      return fail(s, QMC_ERR_OOM, "device allocation of the DMC population failed");
+  }
+  // local energies of every slot's configuration; the first n_target slots are alive
+  qmc_status st = measure_on(s, s->dmc_e4, s->stream);
+  if (st != QMC_OK) return st;
+  std::vector<double> e4((size_t)W * 4), E(W), w(W);
+  HIP_TRY(s, hipMemcpyAsync(e4.data(), s->dmc_e4, e4.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(s, hipStreamSynchronize(s->stream));
+  double se = 0.0;
+  for (int j = 0; j < W; ++j) {
+    E[j] = e4[4 * j] + e4[4 * j + 1] + e4[4 * j + 2] + e4[4 * j + 3];
+    w[j] = j < n_target ? 1.0 : 0.0;
+    if (j < n_target) {
+      if (!std::isfinite(E[j])) return fail(s, QMC_ERR_NUMERIC, "non-finite local energy (walker %d)", j);
+      se += E[j];
+    }
+  }
+  const double ctl[2] = {std::isnan(e_trial) ? se / n_target : e_trial, feedback};
+  const int ictl[3] = {0, 0, n_target};
+  HIP_TRY(s, hipMemcpy(s->dmc_E, E.data(), W * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(s, hipMemcpy(s->dmc_w, w.data(), W * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(s, hipMemcpy(s->dmc_ctl, ctl, sizeof ctl, hipMemcpyHostToDevice));
+  HIP_TRY(s, hipMemcpy(s->dmc_i + 5 * (size_t)W, ictl, sizeof ictl, hipMemcpyHostToDevice));
+  s->dmc_ready = true;
+  return QMC_OK;
+}
+
+qmc_status qmc_dmc_steps(qmc_system s, int32_t n_steps, double* stats_dev) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (!s->has_walkers || !s->dmc_ready) return fail(s, QMC_ERR_STATE, "qmc_dmc_init first");
+  if (n_steps < 0) return fail(s, QMC_ERR_ARG, "n_steps must be >= 0");
+  if (n_steps > 0 && !stats_dev) return fail(s, QMC_ERR_ARG, "stats_dev is NULL");
+  HIP_TRY(s, hipSetDevice(s->device));
+  qmc_status st = QMC_OK;
+  s->fixed_node = true;
+  for (int k = 0; k < n_steps && st == QMC_OK; ++k) {
+    st = sweep_gather(s, s->stream);
+    if (st == QMC_OK) st = sweep_chain(s);
+    if (st == QMC_OK) st = measure_on(s, s->dmc_e4, s->stream);
+    if (st != QMC_OK) break;
+    const DmcState D = dmc_state_of(s, stats_dev + 6 * (size_t)k);
+    hipError_t e = timed(s, 3, [&] { return launch_dmc_branch(s->P, D, s->stream); });
+    if (e == hipSuccess)
+      e = timed(s, 3, [&] {
+        return s->d.precision == QMC_MIXED ? launch_dmc_copy<float>(s->P, walkers_of<float>(s), D, s->stream)
+                                           : launch_dmc_copy<double>(s->P, walkers_of<double>(s), D, s->stream);
+      });
+    if (e != hipSuccess) st = fail(s, QMC_ERR_DEVICE, "branching launch: %s", hipGetErrorString(e));
+  }
+  s->fixed_node = false;
+  return st;
+}
+
+qmc_status qmc_dmc_get(qmc_system s, double* weights, double* energies, double* e_trial, int32_t* population) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (!s->has_walkers || !s->dmc_ready) return fail(s, QMC_ERR_STATE, "qmc_dmc_init first");
+  HIP_TRY(s, hipSetDevice(s->device));
+  const int W = s->P.W;
+  std::vector<double> w(W), ctl(2);
+  int ictl[3];
+  HIP_TRY(s, hipMemcpyAsync(w.data(), s->dmc_w, W * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  if (energies) HIP_TRY(s, hipMemcpyAsync(energies, s->dmc_E, W * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(s, hipMemcpyAsync(ctl.data(), s->dmc_ctl, 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(s, hipMemcpyAsync(ictl, s->dmc_i + 5 * (size_t)W, sizeof ictl, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(s, hipStreamSynchronize(s->stream));
+  int pop = 0;
+  for (double v : w) pop += v > 0.0;
+  if (weights) std::memcpy(weights, w.data(), W * sizeof(double));
+  if (e_trial) *e_trial = ctl[0];
+  if (population) *population = pop;
+  if (ictl[1]) return fail(s, QMC_ERR_NUMERIC, "the population died out");
+  return QMC_OK;
 }
 
 qmc_status qmc_get_walkers(qmc_system s, double* pos, double* logabs_det, int32_t* sign) {

@@ -220,7 +220,12 @@ __global__ __launch_bounds__(kBlock) void k_ae_apply(SysParams P, Walkers<T> Wk,
     const double u = Wk.prop[(size_t)w * N * 4 + 3];
     const double dlog = (A.logdet[2 * w] - Wk.logdet[2 * w]) + (A.logdet[2 * w + 1] - Wk.logdet[2 * w + 1]);
     const double lt = A.logT ? A.logT[w] : 0.0;
-    sacc = (A.status[w] == 0) && (u < exp(2.0 * (dlog + A.dj[w]) + lt));
+    // fixed node: a move to where Psi has the other sign is rejected (the Jastrow factor is
+    // positive, so the sign is that of D_up D_dn)
+    const int crossed = A.fixed_node && A.status[w] == 0 &&
+                        A.sign[2 * w] * A.sign[2 * w + 1] != Wk.sign[2 * w] * Wk.sign[2 * w + 1];
+    if (A.crossed) A.crossed[w] = crossed;
+    sacc = (A.status[w] == 0) && !crossed && (u < exp(2.0 * (dlog + A.dj[w]) + lt));
   }
   __syncthreads();
   const int acc = sacc;

@@ -73,7 +73,7 @@ struct Walkers {
 // Counter-based random numbers: Philox4x32-10 (Salmon, Moraes, Dror and Shaw,
 // SC'11).  Counter (electron, sweep, walker, purpose << 16 | sub), key = seed.
 // ---------------------------------------------------------------------------
-enum Purpose : uint32_t { kInit = 1, kPropose = 2, kAccept = 3 };
+enum Purpose : uint32_t { kInit = 1, kPropose = 2, kAccept = 3, kBranch = 4 };
 
 __device__ __forceinline__ void philox10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
                                          uint32_t k0, uint32_t k1) {

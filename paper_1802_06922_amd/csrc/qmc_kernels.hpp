@@ -162,6 +162,8 @@ struct AeProposal {
   int* status;      // [W]: nonzero = a singular matrix at R'
   double* dj;       // [W]: J(R') - J(R)
   double* logT;     // [W] or null: log T(R' -> R) / T(R -> R') of drift-diffusion proposals
+  int fixed_node;   // 1: reject moves that change the sign of Psi (diffusion Monte Carlo)
+  int* crossed;     // [W] or null: 1 where the move was rejected for crossing a node
 };
 // dj[w] = J(R') - J(R) from pos and the proposals; clears status_prop.
 hipError_t launch_ae_jastrow(const SysParams& P, const double* pos, const double* prop, double* dj,
@@ -174,6 +176,26 @@ hipError_t launch_ae_velocity(const SysParams& P, const Walkers<T>& Wk, const Ae
 // Accept or reject every walker's all-electron move and install R' on acceptance.
 template <typename T>
 hipError_t launch_ae_apply(const SysParams& P, const Walkers<T>& Wk, const AeProposal<T>& A, hipStream_t st);
+
+// Diffusion Monte Carlo population of W slots (a slot is alive while its weight is > 0).
+struct DmcState {
+  double* w;        // [W] weights
+  double* E;        // [W] local energy of each slot's current configuration
+  const double* e4; // [W][4] the step's local energies (kinetic, e-e, e-I, I-I)
+  const int* crossed;  // [W] node-crossing rejections of the step
+  int* mult;        // [W] branching multiplicities
+  int* plan;        // [W] source slot of the copy placed in each slot, or -1
+  int* xscan;       // [W] exclusive prefix sums of the extra copies
+  int* fscan;       // [W] exclusive prefix sums of the free slots
+  double* ctl;      // [2]: E_T, feedback
+  int* ictl;        // [3]: step, extinct flag, target population
+  double* stats;    // [6] of this step: E, sum w, population, E_T used, dropped copies, crossings
+};
+// Weights, estimator, multiplicities, copy plan, new weights and E_T of one DMC step (one
+// workgroup), then the walker states of the copies.
+hipError_t launch_dmc_branch(const SysParams& P, const DmcState& D, hipStream_t st);
+template <typename T>
+hipError_t launch_dmc_copy(const SysParams& P, const Walkers<T>& Wk, const DmcState& D, hipStream_t st);
 
 // Size in bytes of the dynamic LDS the chain kernel needs for P.
 size_t chain_lds_bytes(const SysParams& P, size_t tsize, bool b_in_lds);

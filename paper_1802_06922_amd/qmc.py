@@ -29,7 +29,7 @@ EXPORTS = [
     "qmc_last_error", "qmc_estimate_device_bytes", "qmc_set_delay_rank", "qmc_autotune_delay",
     "qmc_get_last_energies", "qmc_batch_create", "qmc_batch_sweep", "qmc_batch_set_graph",
     "qmc_batch_timing", "qmc_batch_destroy", "qmc_max_delay_rank", "qmc_autotune_gather",
-    "qmc_set_gather_lanes", "qmc_run_steps",
+    "qmc_set_gather_lanes", "qmc_run_steps", "qmc_dmc_init", "qmc_dmc_steps", "qmc_dmc_get",
 ]
 
 
@@ -98,6 +98,9 @@ def load_library():
     L.qmc_autotune_gather.argtypes = [vp, C.c_int32, ip, dp]
     L.qmc_set_gather_lanes.argtypes = [vp, C.c_int32]
     L.qmc_run_steps.argtypes = [vp, C.c_int32, vp]
+    L.qmc_dmc_init.argtypes = [vp, C.c_int32, C.c_double, C.c_double]
+    L.qmc_dmc_steps.argtypes = [vp, C.c_int32, vp]
+    L.qmc_dmc_get.argtypes = [vp, dp, dp, dp, C.POINTER(C.c_int32)]
     L.qmc_max_delay_rank.argtypes = [C.POINTER(Desc)]
     L.qmc_max_delay_rank.restype = C.c_int32
     for name in EXPORTS:
@@ -248,6 +251,28 @@ class System:
             raise ValueError("out must be a contiguous [n, W, 4] tensor")
         self._check(self.L.qmc_run_steps(self.h, int(n), C.c_void_p(out.data_ptr())))
         return out
+
+    def dmc_init(self, n_target: int, e_trial: float = float("nan"), feedback: float = 1.0):
+        """Start a diffusion Monte Carlo population in the first ``n_target`` slots."""
+        self._check(self.L.qmc_dmc_init(self.h, int(n_target), float(e_trial), float(feedback)))
+
+    def dmc_steps(self, n: int, out):
+        """n DMC steps, asynchronous; ``out`` a CUDA float64 tensor [n, 6] receives per step
+        (E, sum of weights, population, E_T used, dropped copies, node-crossing rejections)."""
+        if tuple(out.shape) != (int(n), 6) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous [n, 6] tensor")
+        self._check(self.L.qmc_dmc_steps(self.h, int(n), C.c_void_p(out.data_ptr())))
+        return out
+
+    def dmc_state(self):
+        """(weights[W], energies[W], E_T, population)."""
+        w = np.zeros(self.W)
+        e = np.zeros(self.W)
+        et = C.c_double(0.0)
+        pop = C.c_int32(0)
+        self._check(self.L.qmc_dmc_get(self.h, w.ctypes.data_as(C.POINTER(C.c_double)),
+                                       e.ctypes.data_as(C.POINTER(C.c_double)), C.byref(et), C.byref(pop)))
+        return w, e, et.value, pop.value
 
     def get_walkers(self):
         N = self.wl.n_elec

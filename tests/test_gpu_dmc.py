@@ -1,0 +1,100 @@
+"""GPU parity of diffusion Monte Carlo (section "Diffusion Monte Carlo") against the oracle's
+DMC, through the C ABI: per step the mixed estimate, the sum of weights and E_T within 1e-10
+relative (FP64; 1e-5 mixed), the population, dropped copies and node-crossing rejections
+exactly; at the end the set of alive slots exactly, their positions within 1e-10 bohr and
+their signs exactly.  Branching decisions M = INT(w + xi) are integers decided in FP64 on
+both sides from weights that agree to rounding."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import qmc_inputs as qi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1802_06922_amd import qmc
+    qmc.load_library()
+    return qmc
+
+
+def _drift(wl, sigma):
+    return dataclasses.replace(wl, all_electron=True, drift=True, sigma=sigma)
+
+
+def _compare(gpu, orc, wl, n_slots, n_target, steps, feedback, rel=1e-10, pos_tol=1e-10, e_trial=float("nan")):
+    import torch
+    print(f"[dmc] {wl.name} {wl.precision} sigma={wl.sigma}: {n_target} of {n_slots} slots, {steps} steps",
+          flush=True)
+    s = gpu.System(wl, n_walkers=n_slots)
+    s.dmc_init(n_target, e_trial=e_trial, feedback=feedback)
+    out = torch.zeros((steps, 6), dtype=torch.float64, device="cuda")
+    s.dmc_steps(steps, out)
+    st = out.cpu().numpy()
+    w, _, et, pop = s.dmc_state()
+    pos, _, sg = s.get_walkers()
+    s.close()
+    ref = orc.OracleSystem(wl).dmc(n_slots, n_target, steps, e_trial=e_trial, feedback=feedback)
+    rs = ref["stats"]
+    print(f"[dmc] population {st[:, 2].min():.0f}..{st[:, 2].max():.0f}, copies dropped {st[:, 4].sum():.0f}, "
+          f"node crossings {st[:, 5].sum():.0f}, E {st[-1, 0]:.6f}", flush=True)
+    for c in (2, 4, 5):
+        assert np.array_equal(st[:, c], rs[:, c]), (c, np.flatnonzero(st[:, c] != rs[:, c])[:3])
+    for c in (0, 1, 3):
+        err = np.abs(st[:, c] - rs[:, c]) / np.maximum(np.abs(rs[:, c]), 1.0)
+        assert err.max() < rel, (c, err.max())
+    alive = ref["final_sign"] != 0
+    assert np.array_equal(w > 0, alive)
+    assert pop == alive.sum()
+    np.testing.assert_allclose(pos[alive], ref["final_pos"][alive], atol=pos_tol)
+    assert np.array_equal(sg[alive].prod(axis=1), ref["final_sign"][alive])
+    return st
+
+
+def test_dmc_heg14(gpu, orc):
+    st = _compare(gpu, orc, _drift(qi.heg14(), 0.2), 40, 24, 40, 0.5)
+    assert st[:, 2].min() != st[:, 2].max()   # the population moved
+
+
+def test_dmc_ragged_solid_with_ions(gpu, orc):
+    wl = qi.solid(18, 14, n_walkers=1, n_sweeps=1)
+    wl.n_up, wl.n_dn, wl.n_orb = 9, 7, 9
+    wl.coefs = qi.solid_table(9, 14, seed=3, dtype=np.float64)
+    _compare(gpu, orc, _drift(wl, 0.15), 48, 32, 25, 0.5)
+
+
+def test_dmc_node_crossings_and_full_population(gpu, orc):
+    """Large steps (many proposals cross a node) and a first trial energy far above the
+    estimate: the weights grow, the population reaches the capacity and copies are dropped."""
+    st = _compare(gpu, orc, _drift(qi.heg14(), 0.35), 32, 24, 20, 0.0, e_trial=30.0)
+    assert st[:, 5].sum() > 0 and st[:, 4].sum() > 0
+
+
+def test_dmc_solid128(gpu, orc):
+    """The 128-electron solid: 512 slots, 256 walkers, 2 steps."""
+    _compare(gpu, orc, _drift(qi.solid128(), 0.03), 512, 256, 2, 1.0)
+
+
+def test_dmc_mixed_precision(gpu, orc):
+    wl = qi.solid(48, 16, n_walkers=1, n_sweeps=1, precision="mixed", table_dtype=np.float32)
+    _compare(gpu, orc, _drift(wl, 0.08), 48, 32, 12, 0.5, rel=1e-5, pos_tol=1e-7)
+
+
+def test_dmc_needs_drift_moves_and_init(gpu):
+    s = gpu.System(dataclasses.replace(qi.heg14(), all_electron=True, sigma=0.1))
+    with pytest.raises(gpu.QMCError):
+        s.dmc_init(4)
+    s.close()
+    import torch
+    s = gpu.System(_drift(qi.heg14(), 0.1))
+    with pytest.raises(gpu.QMCError):
+        s.dmc_steps(1, torch.zeros((1, 6), dtype=torch.float64, device="cuda"))
+    with pytest.raises(gpu.QMCError):
+        s.dmc_init(s.W + 1)
+    s.close()
