@@ -404,7 +404,7 @@ WalkerSizes walker_sizes(int n_up, int n_dn, int precision, int W, int n_orb, in
   z.ae_status = ae ? W * sizeof(int) : 0;
   const bool drift = move_kind == QMC_MOVE_ALL_DRIFT;
   z.ae_vel = drift ? W * N * 3 * sizeof(double) : 0;
-  z.ae_logT = drift ? W * sizeof(double) : 0;
+  z.ae_logT = drift ? W * (size_t)velocity_parts((int)N) * sizeof(double) : 0;
   return z;
 }
 
@@ -832,7 +832,7 @@ hipError_t ae_step(qmc_system s) {
   e = launch_rebuild<T>(s->P, prop, s->scratch, nullptr, s->stream);
   if (e != hipSuccess) return e;
   AeProposal<T> A{static_cast<T*>(s->ae_binv), s->ae_logdet, s->ae_sign, s->ae_status, s->ae_dj, s->ae_logT,
-                  s->fixed_node ? 1 : 0, s->fixed_node ? s->dmc_i : nullptr};
+                  velocity_parts(s->P.N), s->fixed_node ? 1 : 0, s->fixed_node ? s->dmc_i : nullptr};
   if (s->d.move_kind == QMC_MOVE_ALL_DRIFT) {
     e = launch_ae_velocity<T>(s->P, walkers_of<T>(s), A, 1, s->ae_vprop, s->ae_vcur, s->stream);
     if (e != hipSuccess) return e;

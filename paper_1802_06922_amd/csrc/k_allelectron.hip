@@ -82,126 +82,120 @@ __global__ __launch_bounds__(kBlock) void k_ae_jastrow(SysParams P, const double
 }
 
 // Drift velocities v_i = grad_i ln|Psi| = sum_l grad phi_l(r_i) B[l][k] + grad_i J of every
-// electron of a walker (one workgroup per walker).  prop = 0: the current configuration R
-// (current rows, Wk.binv, Wk.pos) into vel; prop = 1: the proposed R' (the other row buffer,
-// the inverses A.binv at R', the proposals) into vel, and then the log of the transition
-// ratio T(R' -> R) / T(R -> R') of the drift-diffusion proposal (tau = sigma^2, unwrapped
-// displacement R' - R = tau v(R) + sigma xi, xi redrawn from the sweep's PROPOSE counters):
-//   logT[w] = sum_i [ |sigma xi_i|^2 - |sigma xi_i + tau (v_i(R) + v_i(R'))|^2 ] / (2 tau),
-// v(R) read from vcur.  The determinant part is one thread per electron (column k of the
-// inverse read across consecutive electrons); the Jastrow part is split over (electron,
-// slice) items whose partial sums are added in a fixed order.
+// electron.  prop = 0: the current configuration R (current rows, Wk.binv, Wk.pos) into vel;
+// prop = 1: the proposed R' (the other row buffer, the inverses A.binv at R', the proposals)
+// into vel, and then the log of the transition ratio T(R' -> R) / T(R -> R') of the
+// drift-diffusion proposal (tau = sigma^2, unwrapped displacement R' - R = tau v(R) + sigma xi,
+// xi redrawn from the sweep's PROPOSE counters):
+//   logT = sum_i [ |sigma xi_i|^2 - |sigma xi_i + tau (v_i(R) + v_i(R'))|^2 ] / (2 tau),
+// v(R) read from vcur, one partial sum per workgroup in A.logT[w * parts + p].
+// Grid: (walker, part) with kVelE electrons per part; four lanes per electron split the
+// orbital sum and the partner sum (every fourth term) and add them by lane shuffles.
 constexpr int kVelMaxN = 1024;
-constexpr int kVelItems = 1024;   // (electron, slice) items per pass: slices = max(1, kVelItems / N)
+constexpr int kVelE = kBlock / 4;   // electrons per workgroup
+
+int velocity_parts(int N) { return (N + kVelE - 1) / kVelE; }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_ae_velocity(SysParams P, Walkers<T> Wk, AeProposal<T> A, int prop,
                                                         double* vel, const double* vcur) {
   __shared__ Jastrow sj;
-  __shared__ double sp3[3 * kVelMaxN];
-  __shared__ double sg[3 * kVelItems];
+  __shared__ double sx[kVelMaxN], sy[kVelMaxN], sz[kVelMaxN];
   __shared__ double red[kWaves];
-  const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int parts = gridDim.x / P.W;
+  const int w = blockIdx.x / parts, p = blockIdx.x - w * parts;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int s = tid & 3, i = p * kVelE + (tid >> 2);
   const int N = P.N;
+  const bool valid = i < N;
   for (int q = tid; q < (int)(sizeof(Jastrow) / sizeof(double)); q += kBlock)
     reinterpret_cast<double*>(&sj)[q] = reinterpret_cast<const double*>(&P.jas)[q];
   const double* x = prop ? Wk.prop + (size_t)w * N * 4 : Wk.pos + (size_t)w * N * 3;
   const int xs = prop ? 4 : 3;
-  for (int q = tid; q < 3 * N; q += kBlock) sp3[q] = x[(q / 3) * xs + q % 3];
-  const T* binv = prop ? A.binv : Wk.binv;
-  double* vw = vel + (size_t)w * N * 3;
-  // (1) determinant part, written to vel (read back by the same thread in (3))
-  for (int i = tid; i < N; i += kBlock) {
+  for (int q = tid; q < N; q += kBlock) {
+    sx[q] = x[(size_t)q * xs]; sy[q] = x[(size_t)q * xs + 1]; sz[q] = x[(size_t)q * xs + 2];
+  }
+  __syncthreads();
+  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  if (valid) {
+    // determinant part: orbitals l = s, s + 4, ...
     const int sp = i < P.n_up ? 0 : 1;
     const int n = sp ? P.n_dn : P.n_up, k = i - (sp ? P.n_up : 0);
     const size_t item = (size_t)w * N + i;
     const int buf = Wk.cur[item] ^ prop;
     const T* row = Wk.vgl + ((size_t)buf * P.W * N + item) * kComp * P.S;
-    const T* B = binv + (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0) + k;
-    double gx = 0.0, gy = 0.0, gz = 0.0;
-    for (int l = 0; l < n; ++l) {
+    const T* B = (prop ? A.binv : Wk.binv) + (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0) + k;
+    for (int l = s; l < n; l += 4) {
       const double b = (double)B[(size_t)l * n];
-      gx += b * (double)row[P.S + l];
-      gy += b * (double)row[2 * P.S + l];
-      gz += b * (double)row[3 * P.S + l];
+      g0 += b * (double)row[P.S + l];
+      g1 += b * (double)row[2 * P.S + l];
+      g2 += b * (double)row[3 * P.S + l];
     }
-    vw[3 * i] = gx; vw[3 * i + 1] = gy; vw[3 * i + 2] = gz;
-  }
-  __syncthreads();
-  // (2)+(3) Jastrow part over electron chunks of at most kVelItems / slices electrons
-  const int slices = N >= kVelItems ? 1 : kVelItems / N;
-  const int chunk = kVelItems / slices;
-  const double L = P.L, invL = 1.0 / P.L, tau = P.sigma * P.sigma;
-  const uint32_t sweep = *Wk.sweep_ctr;
-  double tsum = 0.0;
-  for (int c0 = 0; c0 < N; c0 += chunk) {
-    const int nc = min(chunk, N - c0);
-    for (int q = tid; q < nc * slices; q += kBlock) {
-      const int li = q % nc, sl = q / nc, i = c0 + li;
-      const double xi0 = sp3[3 * i], xi1 = sp3[3 * i + 1], xi2 = sp3[3 * i + 2];
-      const bool up_i = i < P.n_up;
-      double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-      for (int j = sl; j < N + P.n_ions; j += slices) {
-        if (j == i) continue;
-        double c[3];
-        const Radial* R;
-        if (j < N) {
-          c[0] = sp3[3 * j]; c[1] = sp3[3 * j + 1]; c[2] = sp3[3 * j + 2];
-          R = ((j < P.n_up) == up_i) ? &sj.same : &sj.opp;
+    // Jastrow part: partners in three ranges (same spin, opposite spin, ions), every fourth
+    const double xi0 = sx[i], xi1 = sy[i], xi2 = sz[i];
+    const double L = P.L, invL = 1.0 / P.L;
+    const bool up = i < P.n_up;
+    auto range = [&](const Radial& R, int lo, int hi, bool ions) {
+      for (int j = lo + s; j < hi; j += 4) {
+        if (!ions && j == i) continue;
+        double cx, cy, cz;
+        if (ions) {
+          const double* c = P.ions + 4 * (size_t)(j - lo);
+          cx = c[0]; cy = c[1]; cz = c[2];
         } else {
-          const double* ion = P.ions + 4 * (size_t)(j - N);
-          c[0] = ion[0]; c[1] = ion[1]; c[2] = ion[2];
-          R = &sj.ei;
+          cx = sx[j]; cy = sy[j]; cz = sz[j];
         }
-        const double dx = xi0 - c[0], dy = xi1 - c[1], dz = xi2 - c[2];
-        const double mx = dx - L * rint(dx * invL), my = dy - L * rint(dy * invL), mz = dz - L * rint(dz * invL);
-        const double r = sqrt(mx * mx + my * my + mz * mz);
+        const double dx = min_image(xi0 - cx, L, invL), dy = min_image(xi1 - cy, L, invL);
+        const double dz = min_image(xi2 - cz, L, invL);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double ri = rsqrt(r2), r = r2 * ri;
         double u, du, d2u;
-        radial_eval(*R, r, u, du, d2u);
-        const double f = du / r;
-        g0 += f * mx; g1 += f * my; g2 += f * mz;
+        radial_eval(R, r, u, du, d2u);
+        const double f = du * ri;
+        g0 += f * dx; g1 += f * dy; g2 += f * dz;
       }
-      sg[3 * q] = g0; sg[3 * q + 1] = g1; sg[3 * q + 2] = g2;
+    };
+    range(up ? sj.same : sj.opp, 0, P.n_up, false);
+    range(up ? sj.opp : sj.same, P.n_up, N, false);
+    if (P.n_ions > 0 && sj.ei.kind != QMC_J_NONE) range(sj.ei, 0, P.n_ions, true);
+  }
+  // the four slices of an electron are adjacent lanes
+#pragma unroll
+  for (int o = 1; o <= 2; o <<= 1) {
+    g0 += __shfl_xor(g0, o, 64); g1 += __shfl_xor(g1, o, 64); g2 += __shfl_xor(g2, o, 64);
+  }
+  double tsum = 0.0;
+  if (valid && s == 0) {
+    double* vw = vel + ((size_t)w * N + i) * 3;
+    vw[0] = g0; vw[1] = g1; vw[2] = g2;
+    if (prop) {
+      const uint32_t sweep = *Wk.sweep_ctr;
+      const double tau = P.sigma * P.sigma;
+      double a0, a1, b0, b1;
+      uniform_pair(P, kPropose, 0, (uint32_t)w, sweep, (uint32_t)i, a0, a1);
+      uniform_pair(P, kPropose, 1, (uint32_t)w, sweep, (uint32_t)i, b0, b1);
+      const double ra = sqrt(-2.0 * log(1.0 - a0)), rb = sqrt(-2.0 * log(1.0 - b0));
+      double sa, ca;
+      sincos(2.0 * kPi * a1, &sa, &ca);
+      const double cb = cos(2.0 * kPi * b1);
+      const double sg[3] = {P.sigma * (ra * ca), P.sigma * (ra * sa), P.sigma * (rb * cb)};
+      const double vn[3] = {g0, g1, g2};
+      const double* vo = vcur + ((size_t)w * N + i) * 3;
+      for (int a = 0; a < 3; ++a) {
+        const double back = sg[a] + tau * (vo[a] + vn[a]);
+        tsum += (sg[a] * sg[a] - back * back) / (2.0 * tau);
+      }
     }
-    __syncthreads();
-    for (int li = tid; li < nc; li += kBlock) {
-      const int i = c0 + li;
-      double g0 = vw[3 * i], g1 = vw[3 * i + 1], g2 = vw[3 * i + 2];
-      double j0 = 0.0, j1 = 0.0, j2 = 0.0;
-      for (int sl = 0; sl < slices; ++sl) {
-        const int q = sl * nc + li;
-        j0 += sg[3 * q]; j1 += sg[3 * q + 1]; j2 += sg[3 * q + 2];
-      }
-      g0 += j0; g1 += j1; g2 += j2;
-      vw[3 * i] = g0; vw[3 * i + 1] = g1; vw[3 * i + 2] = g2;
-      if (prop) {
-        double a0, a1, b0, b1;
-        uniform_pair(P, kPropose, 0, (uint32_t)w, sweep, (uint32_t)i, a0, a1);
-        uniform_pair(P, kPropose, 1, (uint32_t)w, sweep, (uint32_t)i, b0, b1);
-        const double ra = sqrt(-2.0 * log(1.0 - a0)), rb = sqrt(-2.0 * log(1.0 - b0));
-        double sa, ca;
-        sincos(2.0 * kPi * a1, &sa, &ca);
-        const double cb = cos(2.0 * kPi * b1);
-        const double sx[3] = {P.sigma * (ra * ca), P.sigma * (ra * sa), P.sigma * (rb * cb)};
-        const double vn[3] = {g0, g1, g2};
-        const double* vo = vcur + ((size_t)w * N + i) * 3;
-        for (int a = 0; a < 3; ++a) {
-          const double back = sx[a] + tau * (vo[a] + vn[a]);
-          tsum += (sx[a] * sx[a] - back * back) / (2.0 * tau);
-        }
-      }
-    }
-    __syncthreads();
   }
   if (prop) {
     tsum = wave_sum_dpp(tsum);
     if (lane == 0) red[wave] = tsum;
     __syncthreads();
     if (tid == 0) {
-      double s = 0.0;
+      double t = 0.0;
 #pragma unroll
-      for (int q = 0; q < kWaves; ++q) s += red[q];
-      A.logT[w] = s;
+      for (int q = 0; q < kWaves; ++q) t += red[q];
+      A.logT[(size_t)w * parts + p] = t;
     }
   }
 }
@@ -219,7 +213,9 @@ __global__ __launch_bounds__(kBlock) void k_ae_apply(SysParams P, Walkers<T> Wk,
   if (tid == 0) {
     const double u = Wk.prop[(size_t)w * N * 4 + 3];
     const double dlog = (A.logdet[2 * w] - Wk.logdet[2 * w]) + (A.logdet[2 * w + 1] - Wk.logdet[2 * w + 1]);
-    const double lt = A.logT ? A.logT[w] : 0.0;
+    double lt = 0.0;
+    if (A.logT)
+      for (int q = 0; q < A.logT_parts; ++q) lt += A.logT[(size_t)w * A.logT_parts + q];
     // fixed node: a move to where Psi has the other sign is rejected (the Jastrow factor is
     // positive, so the sign is that of D_up D_dn)
     const int crossed = A.fixed_node && A.status[w] == 0 &&
@@ -276,7 +272,9 @@ hipError_t launch_ae_velocity(const SysParams& P, const Walkers<T>& Wk, const Ae
                               double* vel, const double* vcur, hipStream_t st) {
   if (P.W <= 0) return hipSuccess;
   if (P.N > kVelMaxN) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_ae_velocity<T>, dim3(P.W), dim3(kBlock), 0, st, P, Wk, A, prop, vel, vcur);
+  if (prop && A.logT_parts != velocity_parts(P.N)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ae_velocity<T>, dim3((unsigned)P.W * velocity_parts(P.N)), dim3(kBlock), 0, st, P, Wk, A,
+                     prop, vel, vcur);
   return hipGetLastError();
 }
 

@@ -161,7 +161,9 @@ struct AeProposal {
   int* sign;        // [W][2]
   int* status;      // [W]: nonzero = a singular matrix at R'
   double* dj;       // [W]: J(R') - J(R)
-  double* logT;     // [W] or null: log T(R' -> R) / T(R -> R') of drift-diffusion proposals
+  double* logT;     // [W][logT_parts] or null: partial sums of log T(R' -> R) / T(R -> R') of
+                    // drift-diffusion proposals, added in order by the decision
+  int logT_parts;
   int fixed_node;   // 1: reject moves that change the sign of Psi (diffusion Monte Carlo)
   int* crossed;     // [W] or null: 1 where the move was rejected for crossing a node
 };
@@ -169,7 +171,9 @@ struct AeProposal {
 hipError_t launch_ae_jastrow(const SysParams& P, const double* pos, const double* prop, double* dj,
                              int* status_prop, hipStream_t st);
 // Drift velocities grad ln|Psi| of every electron at R (prop = 0) or R' (prop = 1, also
-// A.logT from vcur = v(R)); vel, vcur: [W][N][3].  N at most 1024.
+// A.logT from vcur = v(R), A.logT_parts == velocity_parts(N)); vel, vcur: [W][N][3].  N at
+// most 1024.
+int velocity_parts(int N);
 template <typename T>
 hipError_t launch_ae_velocity(const SysParams& P, const Walkers<T>& Wk, const AeProposal<T>& A, int prop,
                               double* vel, const double* vcur, hipStream_t st);
