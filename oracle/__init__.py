@@ -91,6 +91,8 @@ class _Sys(C.Structure):
         ("j1_p", C.POINTER(C.c_double)), ("j1_cusp", C.c_double),
         ("sigma", C.c_double), ("seed", C.c_uint64),
         ("coulomb", C.c_int32), ("ewald_kappa", C.c_double), ("all_electron", C.c_int32),
+        ("j3_mei", C.c_int32), ("j3_mee", C.c_int32), ("j3_rc", C.c_double),
+        ("j3_gamma", C.POINTER(C.c_double)),
     ]
 
 
@@ -149,6 +151,10 @@ class OracleSystem:
         s.ewald_kappa = kappa
         ae = bool(getattr(wl, "all_electron", False))
         s.all_electron = (2 if getattr(wl, "drift", False) else 1) if ae else 0
+        j3 = getattr(wl, "j3", None)
+        if j3 is not None and wl.n_ions > 0:
+            s.j3_mei, s.j3_mee, s.j3_rc = j3["m_ei"], j3["m_ee"], j3["rc"]
+            s.j3_gamma = _dp(arr(j3["gamma"]))
         self.s = s
         self._keep = keep
 

@@ -171,6 +171,10 @@ typedef struct {
     double ewald_kappa;        /* <= 0: 5 / L */
     int32_t all_electron;      /* 0: particle-by-particle sweeps; 1: all-electron moves;
                                   2: all-electron drift-diffusion moves */
+    int32_t j3_mei, j3_mee;    /* three-body e-e-I term: polynomial orders (0 = term off when
+                                  j3_gamma is NULL) */
+    double j3_rc;              /* its cutoff r_c: the electron-ion distances stay below r_c/2 */
+    const double* j3_gamma;    /* [2][mei+1][mei+1][mee+1] (same spin, opposite spin) or NULL */
 } orc_system;
 
 /* ------------------------------------------------------------------ */
@@ -317,6 +321,48 @@ static void orc_u1(const orc_system* s, double r, double* u, double* du, double*
     else { *u = *du = *d2u = 0.0; }
 }
 
+/*
+ * Three-body electron-electron-ion term (section "Jastrow factors", the form of Drummond et
+ * al.): for electrons i, j near ion I with a = r_iI, b = r_jI, c = r_ij,
+ *   u = sum_{l,m,n} g_lmn a^l b^m c^n (a - h)^3 (b - h)^3,   h = r_c / 2,
+ * zero once a >= h or b >= h.  Out: d = (u, du/da, du/dc, d2u/da2, d2u/dc2, d2u/dadc) at
+ * fixed b (the partial derivatives the gradient and Laplacian with respect to electron i need).
+ */
+static void orc_u3(const orc_system* s, int same, double a, double b, double c, double d[6])
+{
+    const double h = 0.5 * s->j3_rc;
+    for (int q = 0; q < 6; ++q) d[q] = 0.0;
+    if (!s->j3_gamma || a >= h || b >= h) return;
+    const int L = s->j3_mei, M = s->j3_mee;
+    const double* g = s->j3_gamma + (same ? 0 : (size_t)(L + 1) * (L + 1) * (M + 1));
+    double P = 0.0, Pa = 0.0, Pc = 0.0, Paa = 0.0, Pcc = 0.0, Pac = 0.0;
+    for (int l = 0; l <= L; ++l)
+        for (int m = 0; m <= L; ++m)
+            for (int n = 0; n <= M; ++n) {
+                const double gv = g[((size_t)l * (L + 1) + m) * (M + 1) + n];
+                const double bm = pow(b, m);
+                const double al = pow(a, l), cn = pow(c, n);
+                const double al1 = l >= 1 ? l * pow(a, l - 1) : 0.0;
+                const double al2 = l >= 2 ? l * (l - 1) * pow(a, l - 2) : 0.0;
+                const double cn1 = n >= 1 ? n * pow(c, n - 1) : 0.0;
+                const double cn2 = n >= 2 ? n * (n - 1) * pow(c, n - 2) : 0.0;
+                P += gv * al * bm * cn;
+                Pa += gv * al1 * bm * cn;
+                Paa += gv * al2 * bm * cn;
+                Pc += gv * al * bm * cn1;
+                Pcc += gv * al * bm * cn2;
+                Pac += gv * al1 * bm * cn1;
+            }
+    const double fa = (a - h) * (a - h) * (a - h), fa1 = 3.0 * (a - h) * (a - h), fa2 = 6.0 * (a - h);
+    const double fb = (b - h) * (b - h) * (b - h);
+    d[0] = P * fa * fb;
+    d[1] = (Pa * fa + P * fa1) * fb;
+    d[2] = Pc * fa * fb;
+    d[3] = (Paa * fa + 2.0 * Pa * fa1 + P * fa2) * fb;
+    d[4] = Pcc * fa * fb;
+    d[5] = (Pac * fa + Pc * fa1) * fb;
+}
+
 /* Exported for the functor pins. kind: 1 = two-body same spin, 2 = two-body
  * opposite spin, 3 = one-body. */
 void orc_radial(const orc_system* s, int kind, double r, double out[3])
@@ -355,6 +401,17 @@ static double orc_jastrow_total(const orc_system* s, const double* pos)
             J += u;
         }
     }
+    if (s->j3_gamma)
+        for (int I = 0; I < s->n_ions; ++I)
+            for (int i = 0; i < N; ++i)
+                for (int j = i + 1; j < N; ++j) {
+                    double da[3], db[3], dc[3], t[6];
+                    orc_min_image(pos + 3 * i, s->ion_pos + 3 * I, s->L, da);
+                    orc_min_image(pos + 3 * j, s->ion_pos + 3 * I, s->L, db);
+                    orc_min_image(pos + 3 * i, pos + 3 * j, s->L, dc);
+                    orc_u3(s, orc_spin(s, i) == orc_spin(s, j), orc_norm3(da), orc_norm3(db), orc_norm3(dc), t);
+                    J += t[0];
+                }
     return J;
 }
 
@@ -374,6 +431,17 @@ static double orc_jastrow_of(const orc_system* s, const double* pos, int i, cons
         orc_u1(s, orc_norm3(d), &u, &du, &d2u);
         J += u;
     }
+    if (s->j3_gamma)
+        for (int I = 0; I < s->n_ions; ++I)
+            for (int j = 0; j < N; ++j) {
+                if (j == i) continue;
+                double da[3], db[3], dc[3], t[6];
+                orc_min_image(r, s->ion_pos + 3 * I, s->L, da);
+                orc_min_image(pos + 3 * j, s->ion_pos + 3 * I, s->L, db);
+                orc_min_image(r, pos + 3 * j, s->L, dc);
+                orc_u3(s, orc_spin(s, i) == orc_spin(s, j), orc_norm3(da), orc_norm3(db), orc_norm3(dc), t);
+                J += t[0];
+            }
     return J;
 }
 
@@ -399,6 +467,25 @@ static void orc_jastrow_grad_lap(const orc_system* s, const double* pos, int i, 
         for (int k = 0; k < 3; ++k) gJ[k] += du * d[k] / r;
         *lJ += d2u + 2.0 * du / r;
     }
+    /* three-body terms: grad_i u = u_a a^ + u_c c^, lap_i u = u_aa + 2 u_a / a + u_cc + 2 u_c / c
+     * + 2 u_ac a^.c^ (a = r_iI, c = r_ij, b = r_jI fixed) */
+    if (s->j3_gamma)
+        for (int I = 0; I < s->n_ions; ++I)
+            for (int j = 0; j < N; ++j) {
+                if (j == i) continue;
+                double da[3], db[3], dc[3], t[6];
+                orc_min_image(pos + 3 * i, s->ion_pos + 3 * I, s->L, da);
+                orc_min_image(pos + 3 * j, s->ion_pos + 3 * I, s->L, db);
+                orc_min_image(pos + 3 * i, pos + 3 * j, s->L, dc);
+                const double a = orc_norm3(da), c = orc_norm3(dc);
+                orc_u3(s, orc_spin(s, i) == orc_spin(s, j), a, orc_norm3(db), c, t);
+                double ac = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    gJ[k] += t[1] * da[k] / a + t[2] * dc[k] / c;
+                    ac += (da[k] / a) * (dc[k] / c);
+                }
+                *lJ += t[3] + 2.0 * t[1] / a + t[4] + 2.0 * t[2] / c + 2.0 * t[5] * ac;
+            }
 }
 
 /* ------------------------------------------------------------------ */

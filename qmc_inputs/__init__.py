@@ -61,6 +61,7 @@ class Workload:
     pw_kind: Optional[np.ndarray] = None  # [n_orb] 0 = cos(k.r), 1 = sin(k.r)
     all_electron: bool = False    # moves: False = particle-by-particle sweeps, True = all-electron moves
     drift: bool = False           # all-electron moves drawn from the drift-diffusion distribution
+    j3: Optional[dict] = None     # three-body e-e-I term: {"m_ei", "m_ee", "rc", "gamma" [2][m_ei+1][m_ei+1][m_ee+1]}
 
     @property
     def n_elec(self) -> int:
@@ -184,11 +185,30 @@ def bspline_jastrow_params(M: int, A: float) -> np.ndarray:
     return -A * (1.0 - (m - 1.0) / (M - 1.0)) ** 3
 
 
+def j3_params(m_ei: int, m_ee: int, rc: float, seed: int, A: float = 0.05) -> dict:
+    """Seeded coefficients of the three-body term: gamma_lmn = A z_lmn / (h^(6+l+m) (2h)^n),
+    h = rc/2, z uniform in (-1, 1) and symmetric in (l, m), one set per spin relation (same,
+    opposite), so that no single term exceeds A in size inside the cutoff."""
+    rng = np.random.default_rng([seed, 0x3B0D])
+    h = rc / 2.0
+    g = np.zeros((2, m_ei + 1, m_ei + 1, m_ee + 1))
+    for sp in range(2):
+        z = rng.uniform(-1.0, 1.0, size=(m_ei + 1, m_ei + 1, m_ee + 1))
+        z = 0.5 * (z + z.transpose(1, 0, 2))
+        for l in range(m_ei + 1):
+            for m in range(m_ei + 1):
+                for n in range(m_ee + 1):
+                    g[sp, l, m, n] = A * z[l, m, n] / (h ** (6 + l + m) * (2 * h) ** n)
+    return {"m_ei": m_ei, "m_ee": m_ee, "rc": rc, "gamma": g}
+
+
 def solid(n_elec: int, grid: int, n_walkers: int, n_sweeps: int, precision: str = "fp64",
           table_dtype=None, delay_rank: int = 1, recompute_period: int = 0, seed: int = 0,
           sigma: float = 0.3, M: int = 8, A_ee: float = 0.4, A_eI: float = 0.3,
-          ions_per_elec: float = 0.25, Z: float = 4.0, name: Optional[str] = None) -> Workload:
-    """Spin-balanced solid-like system at rs = 1 with one- and two-body B-spline Jastrows."""
+          ions_per_elec: float = 0.25, Z: float = 4.0, name: Optional[str] = None,
+          j3: bool = False) -> Workload:
+    """Spin-balanced solid-like system at rs = 1 with one- and two-body B-spline Jastrows
+    (and, with j3, a three-body e-e-I term of orders 2, 2 and cutoff L/2)."""
     if n_elec % 2:
         raise ValueError("solid-like systems are spin balanced: n_elec must be even")
     ns = n_elec // 2
@@ -208,7 +228,8 @@ def solid(n_elec: int, grid: int, n_walkers: int, n_sweeps: int, precision: str 
         name=name or f"solid{n_elec}_g{grid}_{precision}", n_up=ns, n_dn=ns, L=L, n_orb=ns,
         grid=(grid, grid, grid), coefs=coefs, ion_pos=ion_pos, ion_Z=ion_Z, j2=j2, j1=j1,
         hamiltonian="coulomb", sigma=sigma, seed=seed, n_walkers=n_walkers, n_sweeps=n_sweeps,
-        precision=precision, delay_rank=delay_rank, recompute_period=recompute_period)
+        precision=precision, delay_rank=delay_rank, recompute_period=recompute_period,
+        j3=j3_params(2, 2, rc, seed) if j3 else None)
 
 
 # --------------------------------------------------------------------------
