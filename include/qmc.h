@@ -93,6 +93,14 @@ typedef enum { QMC_H_KINETIC = 0, QMC_H_COULOMB_EWALD = 1 } qmc_hamiltonian;
  *                 PyTorch caching allocator).  If arena != NULL every device
  *                 buffer of the handle is carved from it and nothing is
  *                 allocated; size it with qmc_estimate_device_bytes().
+ *  j3_gamma       three-body electron-electron-ion term (section "Jastrow
+ *                 factors", the form of Drummond et al.), or NULL for none: for
+ *                 electrons i, j and ion I with a = r_iI, b = r_jI, c = r_ij,
+ *                 u = sum_{l,m<=j3_m_ei, n<=j3_m_ee} g_lmn a^l b^m c^n
+ *                 (a - h)^3 (b - h)^3 while a, b < h = j3_rcut / 2 (else 0),
+ *                 J3 = sum_I sum_{i<j} u.  Layout [2][m_ei+1][m_ei+1][m_ee+1],
+ *                 equal-spin pairs first; g_lmn must equal g_mln; orders
+ *                 0..3; 0 < j3_rcut <= L/2; needs ions.  Copied.
  *  move_kind      QMC_MOVE_PBYP (0): a sweep moves the electrons one at a
  *                 time (section "Trial Moves", particle by particle);
  *                 QMC_MOVE_ALL (1): a sweep is one all-electron move per
@@ -139,6 +147,9 @@ typedef struct {
     void* arena;
     size_t arena_bytes;
     int32_t move_kind;
+    int32_t j3_m_ei, j3_m_ee;
+    double j3_rcut;
+    const double* j3_gamma;
 } qmc_system_desc;
 
 /* Create a handle.  hip_stream: a hipStream_t (e.g. PyTorch's current

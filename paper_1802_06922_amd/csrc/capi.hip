@@ -88,6 +88,7 @@ struct qmc_system_s {
   SysParams P{};
   EwaldParams E{};
   double* d_ions = nullptr;
+  double* d_j3 = nullptr;
   double* d_gvec = nullptr;
   double* d_sion = nullptr;
   int* d_segs = nullptr;
@@ -458,7 +459,24 @@ qmc_status validate(const qmc_system_desc* d) {
   if (st != QMC_OK) return st;
   if (d->j1_kind == QMC_J_PADE) return fail(nullptr, QMC_ERR_ARG, "j1 supports NONE or BSPLINE");
   st = check_j(d->j1_kind, d->j1_params, d->j1_n, d->j1_rcut, "j1");
-  return st;
+  if (st != QMC_OK) return st;
+  if (d->j3_gamma) {
+    const int L3 = d->j3_m_ei, M3 = d->j3_m_ee;
+    if (d->n_ions < 1) return fail(nullptr, QMC_ERR_ARG, "the three-body term needs ions");
+    if (L3 < 0 || L3 > 3 || M3 < 0 || M3 > 3) return fail(nullptr, QMC_ERR_ARG, "three-body orders must be in [0, 3]");
+    if (!(d->j3_rcut > 0.0) || d->j3_rcut > 0.5 * d->L * (1.0 + 1e-12))
+      return fail(nullptr, QMC_ERR_ARG, "three-body cutoff must be in (0, L/2]");
+    for (int sp = 0; sp < 2; ++sp)
+      for (int l = 0; l <= L3; ++l)
+        for (int m = 0; m <= L3; ++m)
+          for (int n = 0; n <= M3; ++n) {
+            const double* g = d->j3_gamma + (size_t)sp * (L3 + 1) * (L3 + 1) * (M3 + 1);
+            const double x = g[((size_t)l * (L3 + 1) + m) * (M3 + 1) + n];
+            if (!std::isfinite(x) || x != g[((size_t)m * (L3 + 1) + l) * (M3 + 1) + n])
+              return fail(nullptr, QMC_ERR_ARG, "three-body coefficients must be finite with g_lmn = g_mln");
+          }
+  }
+  return QMC_OK;
 }
 
 }  // namespace
@@ -505,6 +523,7 @@ qmc_status qmc_create_system(const qmc_system_desc* desc, void* hip_stream, qmc_
   qmc_system s = new (std::nothrow) qmc_system_s;
   if (!s) return fail(nullptr, QMC_ERR_OOM, "host allocation failed");
   s->d = *desc;
+  s->d.j3_gamma = nullptr;   // copied to the device below; the caller's array is not kept
   if (s->d.delay_rank == 0) s->d.delay_rank = 1;
   {
     const char* v = getenv("QMC_DELAYED_VALU");
@@ -567,6 +586,18 @@ qmc_status qmc_create_system(const qmc_system_desc* desc, void* hip_stream, qmc_
   s->d.ion_pos = s->d.ion_Z = s->d.j2_params = s->d.j1_params = nullptr;
   s->d.arena = nullptr;
 
+  if (desc->j3_gamma) {
+    const size_t ng = 2 * (size_t)(desc->j3_m_ei + 1) * (desc->j3_m_ei + 1) * (desc->j3_m_ee + 1);
+    s->d_j3 = static_cast<double*>(s->mem.alloc(ng * sizeof(double)));
+    if (!s->d_j3 || hipMemcpy(s->d_j3, desc->j3_gamma, ng * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+      qmc_destroy_system(s);
+      return fail(nullptr, QMC_ERR_OOM, "device allocation (three-body coefficients)");
+    }
+    P.j3_g = s->d_j3;
+    P.j3_mei = desc->j3_m_ei;
+    P.j3_mee = desc->j3_m_ee;
+    P.j3_h = 0.5 * desc->j3_rcut;
+  }
   s->d_ions = static_cast<double*>(s->mem.alloc(s->ions4.size() * sizeof(double)));
   if (!s->d_ions) { qmc_destroy_system(s); return fail(nullptr, QMC_ERR_OOM, "device allocation (ions)"); }
   if (hipMemcpyAsync(s->d_ions, s->ions4.data(), s->ions4.size() * sizeof(double), hipMemcpyHostToDevice,

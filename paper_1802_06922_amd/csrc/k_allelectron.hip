@@ -69,6 +69,23 @@ __global__ __launch_bounds__(kBlock) void k_ae_jastrow(SysParams P, const double
       const double* ion = P.ions + 4 * I;
       acc += ae_u(sj, 2, ae_dist(x1 + 4 * i, ion, L, invL)) - ae_u(sj, 2, ae_dist(x0 + 3 * i, ion, L, invL));
     }
+  if (P.j3_g) {
+    // three-body terms: (ion, electron i) items, partners j > i near the same ion
+    const double h = P.j3_h;
+    for (int q = tid; q < N * P.n_ions; q += kBlock) {
+      const int I = q / N, i = q - I * N;
+      const double* ion = P.ions + 4 * I;
+      const double a1 = ae_dist(x1 + 4 * i, ion, L, invL), a0 = ae_dist(x0 + 3 * i, ion, L, invL);
+      if (a1 >= h && a0 >= h) continue;
+      const bool up_i = i < P.n_up;
+      for (int j = i + 1; j < N; ++j) {
+        const double b1 = ae_dist(x1 + 4 * j, ion, L, invL), b0 = ae_dist(x0 + 3 * j, ion, L, invL);
+        const bool same = up_i == (j < P.n_up);
+        if (a1 < h && b1 < h) acc += u3_value(P, same, a1, b1, ae_dist(x1 + 4 * i, x1 + 4 * j, L, invL));
+        if (a0 < h && b0 < h) acc -= u3_value(P, same, a0, b0, ae_dist(x0 + 3 * i, x0 + 3 * j, L, invL));
+      }
+    }
+  }
   acc = wave_sum_dpp(acc);
   if (lane == 0) red[wave] = acc;
   __syncthreads();
@@ -158,6 +175,31 @@ __global__ __launch_bounds__(kBlock) void k_ae_velocity(SysParams P, Walkers<T> 
     range(up ? sj.same : sj.opp, 0, P.n_up, false);
     range(up ? sj.opp : sj.same, P.n_up, N, false);
     if (P.n_ions > 0 && sj.ei.kind != QMC_J_NONE) range(sj.ei, 0, P.n_ions, true);
+    if (P.j3_g) {
+      // three-body terms: grad_i u = u_a a^ + u_c c^ over ions near i and partners j near them
+      const double h = P.j3_h;
+      for (int I = 0; I < P.n_ions; ++I) {
+        const double* ion = P.ions + 4 * (size_t)I;
+        const double ax = min_image(xi0 - ion[0], L, invL), ay = min_image(xi1 - ion[1], L, invL);
+        const double az = min_image(xi2 - ion[2], L, invL);
+        const double a = sqrt(ax * ax + ay * ay + az * az);
+        if (a >= h) continue;
+        for (int j = s; j < N; j += 4) {
+          if (j == i) continue;
+          const double bx = min_image(sx[j] - ion[0], L, invL), by = min_image(sy[j] - ion[1], L, invL);
+          const double bz = min_image(sz[j] - ion[2], L, invL);
+          const double b = sqrt(bx * bx + by * by + bz * bz);
+          if (b >= h) continue;
+          const double cx = min_image(xi0 - sx[j], L, invL), cy = min_image(xi1 - sy[j], L, invL);
+          const double cz = min_image(xi2 - sz[j], L, invL);
+          const double c = sqrt(cx * cx + cy * cy + cz * cz);
+          double d[6];
+          u3_derivs(P, up == (j < P.n_up), a, b, c, d);
+          const double fa = d[1] / a, fc = d[2] / c;
+          g0 += fa * ax + fc * cx; g1 += fa * ay + fc * cy; g2 += fa * az + fc * cz;
+        }
+      }
+    }
   }
   // the four slices of an electron are adjacent lanes
 #pragma unroll

@@ -207,6 +207,28 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, in
         const double r0 = sqrt(dx * dx + dy * dy + dz * dz);
         dj += pair_u(sj, kind, r1) - pair_u(sj, kind, r0);
       }
+      if (P.j3_g) {
+        // three-body terms of electron i with partner j near ion I, at r' and at r
+        const double h = P.j3_h;
+        for (int q = tid; q < P.n_ions * N; q += kBlock) {
+          const int I = q / N, j = q - I * N;
+          if (j == i) continue;
+          const double* ion = ions + 4 * I;
+          auto d3 = [&](double x, double y, double z, double cx, double cy, double cz) {
+            const double dx = min_image_inv(x - cx, L, invL), dy = min_image_inv(y - cy, L, invL);
+            const double dz = min_image_inv(z - cz, L, invL);
+            return sqrt(dx * dx + dy * dy + dz * dz);
+          };
+          const double a1 = d3(rx, ry, rz, ion[0], ion[1], ion[2]), a0 = d3(xo, yo, zo, ion[0], ion[1], ion[2]);
+          if (a1 >= h && a0 >= h) continue;
+          const double px = spos[3 * j], py = spos[3 * j + 1], pz = spos[3 * j + 2];
+          const double b = d3(px, py, pz, ion[0], ion[1], ion[2]);
+          if (b >= h) continue;
+          const bool same = (j < P.n_up) == up_i;
+          if (a1 < h) dj += u3_value(P, same, a1, b, d3(rx, ry, rz, px, py, pz));
+          if (a0 < h) dj -= u3_value(P, same, a0, b, d3(xo, yo, zo, px, py, pz));
+        }
+      }
       // block reduction in a fixed order (bitwise repeatable)
       const double ra = wave_sum_dpp((double)rpart), rb = wave_sum_dpp(dj);
       const double rm = sizeof(T) == 4 ? wave_sum_dpp(mpart) : 0.0;

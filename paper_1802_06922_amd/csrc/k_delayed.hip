@@ -390,6 +390,27 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
           range(sj.same, off + k0 + Kw, off + n, spos, 3);
           range(sj.opp, ooff, ooff + no, spos, 3);
           range(sj.ei, 0, P.n_ions, ions, 4);
+          if (P.j3_g) {
+            // three-body terms with partners outside the window (in-window partners are pair
+            // terms below), over the ions within the cutoff of r or r'
+            const double h = P.j3_h;
+            const int w0 = off + k0, w1 = off + k0 + Kw;
+            for (int I = 0; I < P.n_ions; ++I) {
+              const double* ion = ions + 4 * I;
+              const double a1 = dist(px, py, pz, ion[0], ion[1], ion[2], L, invL);
+              const double a0 = dist(ox, oy, oz, ion[0], ion[1], ion[2], L, invL);
+              if (a1 >= h && a0 >= h) continue;
+              for (int j = s; j < N; j += tpq) {
+                if (j >= w0 && j < w1) continue;
+                const double* cj = spos + 3 * j;
+                const double b = dist(cj[0], cj[1], cj[2], ion[0], ion[1], ion[2], L, invL);
+                if (b >= h) continue;
+                const bool same = (j < P.n_up) == up_block;
+                if (a1 < h) part += u3_value(P, same, a1, b, dist(px, py, pz, cj[0], cj[1], cj[2], L, invL));
+                if (a0 < h) part -= u3_value(P, same, a0, b, dist(ox, oy, oz, cj[0], cj[1], cj[2], L, invL));
+              }
+            }
+          }
         }
         red[tid] = part;
         if (sizeof(T) == 4) {
@@ -409,15 +430,37 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
         const double px = sprop[4 * kq], py = sprop[4 * kq + 1], pz = sprop[4 * kq + 2];
         const double ox = spos[3 * iq], oy = spos[3 * iq + 1], oz = spos[3 * iq + 2];
         const double cx = spos[3 * i2], cy = spos[3 * i2 + 1], cz = spos[3 * i2 + 2];
-        const double g_old = ju(sj, 0, dist(px, py, pz, cx, cy, cz, L, invL)) -
-                             ju(sj, 0, dist(ox, oy, oz, cx, cy, cz, L, invL));
-        gold[q2 * K + q] = g_old;   // transposed: lane q reads column q
-        if (q2 < q) {
-          const double nx = sprop[4 * k2], ny = sprop[4 * k2 + 1], nz = sprop[4 * k2 + 2];
-          const double g_new = ju(sj, 0, dist(px, py, pz, nx, ny, nz, L, invL)) -
-                               ju(sj, 0, dist(ox, oy, oz, nx, ny, nz, L, invL));
-          gdiff[q2 * K + q] = g_new - g_old;
+        double g_old = ju(sj, 0, dist(px, py, pz, cx, cy, cz, L, invL)) -
+                       ju(sj, 0, dist(ox, oy, oz, cx, cy, cz, L, invL));
+        const double nx = sprop[4 * k2], ny = sprop[4 * k2 + 1], nz = sprop[4 * k2 + 2];
+        double g_new = 0.0;
+        if (q2 < q)
+          g_new = ju(sj, 0, dist(px, py, pz, nx, ny, nz, L, invL)) -
+                  ju(sj, 0, dist(ox, oy, oz, nx, ny, nz, L, invL));
+        if (P.j3_g) {
+          // three-body terms of the pair (same spin) over the ions near either electron
+          const double h = P.j3_h;
+          for (int I = 0; I < P.n_ions; ++I) {
+            const double* ion = ions + 4 * I;
+            const double a1 = dist(px, py, pz, ion[0], ion[1], ion[2], L, invL);
+            const double a0 = dist(ox, oy, oz, ion[0], ion[1], ion[2], L, invL);
+            if (a1 >= h && a0 >= h) continue;
+            const double bo = dist(cx, cy, cz, ion[0], ion[1], ion[2], L, invL);
+            if (bo < h) {
+              if (a1 < h) g_old += u3_value(P, true, a1, bo, dist(px, py, pz, cx, cy, cz, L, invL));
+              if (a0 < h) g_old -= u3_value(P, true, a0, bo, dist(ox, oy, oz, cx, cy, cz, L, invL));
+            }
+            if (q2 < q) {
+              const double bn = dist(nx, ny, nz, ion[0], ion[1], ion[2], L, invL);
+              if (bn < h) {
+                if (a1 < h) g_new += u3_value(P, true, a1, bn, dist(px, py, pz, nx, ny, nz, L, invL));
+                if (a0 < h) g_new -= u3_value(P, true, a0, bn, dist(ox, oy, oz, nx, ny, nz, L, invL));
+              }
+            }
+          }
         }
+        gold[q2 * K + q] = g_old;   // transposed: lane q reads column q
+        if (q2 < q) gdiff[q2 * K + q] = g_new - g_old;
       }
       // (A3) Y = V B0
       gemm_window<T, MF>(vwin, Bm, ldb, ywin, Kw, n, nP, tid);

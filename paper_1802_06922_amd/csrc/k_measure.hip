@@ -213,6 +213,34 @@ __device__ __forceinline__ void measure_part(const SysParams& P, const Walkers<T
     range(up_i ? sj.same : sj.opp, 0, P.n_up, elec);
     range(up_i ? sj.opp : sj.same, P.n_up, N, elec);
     if (P.n_ions > 0) range(sj.ei, N, N + P.n_ions, ion);
+    if (P.j3_g) {
+      // three-body terms (a = r_iI, c = r_ij at fixed b = r_jI): grad_i u = u_a a^ + u_c c^,
+      // lap_i u = u_aa + 2 u_a / a + u_cc + 2 u_c / c + 2 u_ac a^.c^; partners j = part (mod parts)
+      const double h = P.j3_h;
+      for (int I = 0; I < P.n_ions; ++I) {
+        const double* ion = P.ions + 4 * (size_t)I;
+        const double ax = min_image(xi - ion[0], P.L, invL), ay = min_image(yi - ion[1], P.L, invL);
+        const double az = min_image(zi - ion[2], P.L, invL);
+        const double a = sqrt(ax * ax + ay * ay + az * az);
+        if (a >= h) continue;
+        for (int j = part; j < N; j += parts) {
+          if (j == i) continue;
+          const double bx = min_image(sx[j] - ion[0], P.L, invL), by = min_image(sy[j] - ion[1], P.L, invL);
+          const double bz = min_image(sz[j] - ion[2], P.L, invL);
+          const double b = sqrt(bx * bx + by * by + bz * bz);
+          if (b >= h) continue;
+          const double cx = min_image(xi - sx[j], P.L, invL), cy = min_image(yi - sy[j], P.L, invL);
+          const double cz = min_image(zi - sz[j], P.L, invL);
+          const double c = sqrt(cx * cx + cy * cy + cz * cz);
+          double d[6];
+          u3_derivs(P, up_i == (j < P.n_up), a, b, c, d);
+          const double fa = d[1] / a, fc = d[2] / c;
+          g[0] += fa * ax + fc * cx; g[1] += fa * ay + fc * cy; g[2] += fa * az + fc * cz;
+          const double ac = (ax * cx + ay * cy + az * cz) / (a * c);
+          lj += d[3] + 2.0 * fa + d[4] + 2.0 * fc + 2.0 * d[5] * ac;
+        }
+      }
+    }
     double* gp = sgj + 3 * ((size_t)part * nloc + li);
     gp[0] = g[0]; gp[1] = g[1]; gp[2] = g[2];
     slj[(size_t)part * nloc + li] = lj;

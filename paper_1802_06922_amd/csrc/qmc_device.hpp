@@ -45,6 +45,10 @@ struct SysParams {
   uint32_t key0, key1;    // Philox key (seed)
   const double* ions;     // [n_ions][4] = x, y, z, Z
   Jastrow jas;
+  // three-body e-e-I term: coefficients [2][mei+1][mei+1][mee+1] (null = no term), cutoff h
+  const double* j3_g;
+  int j3_mei, j3_mee;
+  double j3_h;
 };
 
 // Device buffers of the walkers.  T is the orbital/inverse precision.
@@ -192,6 +196,76 @@ __device__ __forceinline__ double radial_value(const Radial& R, double r) {
     return in ? c0 + f * (c1 + f * (c2 + f * c3)) : 0.0;
   }
   return 0.0;
+}
+
+// Three-body electron-electron-ion term for electrons i, j near one ion (section "Jastrow
+// factors", the form of Drummond et al.): a = r_iI, b = r_jI, c = r_ij,
+//   u = sum_{l,m,n} g_lmn a^l b^m c^n (a - h)^3 (b - h)^3, zero unless a < h and b < h.
+__device__ __forceinline__ const double* u3_coefs(const SysParams& P, bool same) {
+  return P.j3_g + (same ? 0 : (P.j3_mei + 1) * (P.j3_mei + 1) * (P.j3_mee + 1));
+}
+
+__device__ __forceinline__ double u3_value(const SysParams& P, bool same, double a, double b, double c) {
+  const double h = P.j3_h;
+  if (a >= h || b >= h) return 0.0;
+  const double* g = u3_coefs(P, same);
+  const int M1 = P.j3_mei + 1, N1 = P.j3_mee + 1;
+  double pa = 0.0;
+  for (int l = M1 - 1; l >= 0; --l) {
+    double pb = 0.0;
+    for (int m = M1 - 1; m >= 0; --m) {
+      const double* gl = g + (l * M1 + m) * N1;
+      double pc = 0.0;
+      for (int n = N1 - 1; n >= 0; --n) pc = pc * c + gl[n];
+      pb = pb * b + pc;
+    }
+    pa = pa * a + pb;
+  }
+  const double fa = (a - h) * (a - h) * (a - h), fb = (b - h) * (b - h) * (b - h);
+  return pa * fa * fb;
+}
+
+// The same with its partial derivatives at fixed b: d = (u, u_a, u_c, u_aa, u_cc, u_ac).
+__device__ __forceinline__ void u3_derivs(const SysParams& P, bool same, double a, double b, double c, double d[6]) {
+  const double h = P.j3_h;
+  d[0] = d[1] = d[2] = d[3] = d[4] = d[5] = 0.0;
+  if (a >= h || b >= h) return;
+  const double* g = u3_coefs(P, same);
+  const int M1 = P.j3_mei + 1, N1 = P.j3_mee + 1;
+  double Pv = 0.0, Pa = 0.0, Pc = 0.0, Paa = 0.0, Pcc = 0.0, Pac = 0.0;
+  double al = 1.0, al1 = 0.0, al2 = 0.0;   // a^l, l a^(l-1), l (l-1) a^(l-2) (likewise for c)
+  for (int l = 0; l < M1; ++l) {
+    double bm = 1.0;
+    for (int m = 0; m < M1; ++m) {
+      const double* gl = g + (l * M1 + m) * N1;
+      double cn = 1.0, cn1 = 0.0, cn2 = 0.0;
+      for (int n = 0; n < N1; ++n) {
+        const double gb = gl[n] * bm;
+        Pv += gb * al * cn;
+        Pa += gb * al1 * cn;
+        Paa += gb * al2 * cn;
+        Pc += gb * al * cn1;
+        Pcc += gb * al * cn2;
+        Pac += gb * al1 * cn1;
+        // next n: (n+1) n c^(n-1) = (n+1) cn1, (n+1) c^n = (n+1) cn, c^(n+1)
+        cn2 = (n + 1) * cn1;
+        cn1 = (n + 1) * cn;
+        cn *= c;
+      }
+      bm *= b;
+    }
+    al2 = (l + 1) * al1;
+    al1 = (l + 1) * al;
+    al *= a;
+  }
+  const double t = a - h, fa = t * t * t, fa1 = 3.0 * t * t, fa2 = 6.0 * t;
+  const double fb = (b - h) * (b - h) * (b - h);
+  d[0] = Pv * fa * fb;
+  d[1] = (Pa * fa + Pv * fa1) * fb;
+  d[2] = Pc * fa * fb;
+  d[3] = (Paa * fa + 2.0 * Pa * fa1 + Pv * fa2) * fb;
+  d[4] = Pcc * fa * fb;
+  d[5] = (Pac * fa + Pc * fa1) * fb;
 }
 
 // Wave64 sum of a double (xor butterfly: every lane gets the total).

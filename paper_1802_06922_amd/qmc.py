@@ -50,6 +50,8 @@ class Desc(C.Structure):
         ("j1_kind", C.c_int32), ("j1_params", C.POINTER(C.c_double)), ("j1_n", C.c_int32),
         ("j1_rcut", C.c_double), ("j1_cusp", C.c_double), ("tie_guard", C.c_double),
         ("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("move_kind", C.c_int32),
+        ("j3_m_ei", C.c_int32), ("j3_m_ee", C.c_int32), ("j3_rcut", C.c_double),
+        ("j3_gamma", C.POINTER(C.c_double)),
     ]
 
 
@@ -157,6 +159,10 @@ def make_desc(wl, keep: list, arena=None, arena_bytes: int = 0, tie_guard: float
     d.arena_bytes = arena_bytes
     ae = bool(getattr(wl, "all_electron", False))
     d.move_kind = (2 if getattr(wl, "drift", False) else 1) if ae else 0
+    j3 = getattr(wl, "j3", None)
+    if j3 is not None and wl.n_ions > 0:
+        d.j3_m_ei, d.j3_m_ee, d.j3_rcut = j3["m_ei"], j3["m_ee"], j3["rc"]
+        d.j3_gamma = _dp(arr(j3["gamma"]))
     return d
 
 

@@ -206,7 +206,7 @@ def solid(n_elec: int, grid: int, n_walkers: int, n_sweeps: int, precision: str 
           table_dtype=None, delay_rank: int = 1, recompute_period: int = 0, seed: int = 0,
           sigma: float = 0.3, M: int = 8, A_ee: float = 0.4, A_eI: float = 0.3,
           ions_per_elec: float = 0.25, Z: float = 4.0, name: Optional[str] = None,
-          j3: bool = False) -> Workload:
+          j3: bool = False, j3_strength: float = 0.05) -> Workload:
     """Spin-balanced solid-like system at rs = 1 with one- and two-body B-spline Jastrows
     (and, with j3, a three-body e-e-I term of orders 2, 2 and cutoff L/2)."""
     if n_elec % 2:
@@ -229,7 +229,7 @@ def solid(n_elec: int, grid: int, n_walkers: int, n_sweeps: int, precision: str 
         grid=(grid, grid, grid), coefs=coefs, ion_pos=ion_pos, ion_Z=ion_Z, j2=j2, j1=j1,
         hamiltonian="coulomb", sigma=sigma, seed=seed, n_walkers=n_walkers, n_sweeps=n_sweeps,
         precision=precision, delay_rank=delay_rank, recompute_period=recompute_period,
-        j3=j3_params(2, 2, rc, seed) if j3 else None)
+        j3=j3_params(2, 2, rc, seed, A=j3_strength) if j3 else None)
 
 
 # --------------------------------------------------------------------------

@@ -1,0 +1,98 @@
+"""GPU parity with the three-body electron-electron-ion Jastrow term (section "Jastrow
+factors") against the oracle, through the C ABI: particle-by-particle sweeps with
+Sherman-Morrison and with delayed updates (the term enters the windows' pair corrections),
+mixed precision, all-electron and drift moves; the bars of the paths without it."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import qmc_inputs as qi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1802_06922_amd import qmc
+    qmc.load_library()
+    return qmc
+
+
+def _rel(a, b):
+    return np.abs(a - b) / np.maximum(np.abs(b), 1.0)
+
+
+def _compare(gpu, orc, wl, n_sweeps, walkers, tol=1e-10, pos_tol=1e-11):
+    sample = np.asarray(walkers)
+    print(f"[j3] {wl.name} K={wl.delay_rank} {wl.precision} all_electron={wl.all_electron} drift={wl.drift}: "
+          f"walkers {sample[:6].tolist()}, {n_sweeps} sweeps", flush=True)
+    s = gpu.System(wl)
+    bits, energies = [], []
+    for _ in range(n_sweeps):
+        s.sweep(1)
+        bits.append(s.accept_log()[sample])
+        energies.append(s.measure()[sample])
+    pos, ld, sg = s.get_walkers()
+    s.close()
+    b, e = np.stack(bits, 1), np.stack(energies, 1)
+    ref = orc.OracleSystem(wl).run(sample, n_sweeps, measure_every=1)
+    assert np.array_equal(b, ref["accept"]), f"first differing decision {np.argwhere(b != ref['accept'])[:3]}"
+    rel = _rel(e, ref["energies"])
+    print(f"[j3] acceptance {b.mean():.3f}, rel energy error max {rel.max():.2e}", flush=True)
+    assert rel.max() < tol
+    np.testing.assert_allclose(pos[sample], ref["final_pos"], atol=pos_tol)
+    assert np.array_equal(sg[sample], ref["sign"])
+    return b
+
+
+# a strong three-body term (coefficient scale 50): its change decides moves in the first sweep
+J3_STRENGTH = 50.0
+
+
+def _j3_solid(n, grid, W, **kw):
+    return qi.solid(n, grid, n_walkers=W, n_sweeps=1, j3=True, j3_strength=J3_STRENGTH, **kw)
+
+
+@pytest.mark.parametrize("K", [1, 8])
+def test_j3_particle_by_particle(gpu, orc, K):
+    wl = _j3_solid(32, 14, 16, delay_rank=K)
+    b = _compare(gpu, orc, wl, 8, range(16))
+    assert 0.2 < b.mean() < 0.95
+
+
+def test_j3_ragged_spins_delayed(gpu, orc):
+    wl = _j3_solid(18, 14, 12, delay_rank=4)
+    wl.n_up, wl.n_dn, wl.n_orb = 9, 7, 9
+    wl.coefs = qi.solid_table(9, 14, seed=3, dtype=np.float64)
+    _compare(gpu, orc, wl, 6, range(12))
+
+
+def test_j3_solid128_sampled_walkers(gpu, orc):
+    base = qi.solid128()
+    wl = dataclasses.replace(base, j3=qi.j3_params(2, 2, base.L / 2, 0, A=J3_STRENGTH), delay_rank=16)
+    _compare(gpu, orc, wl, 2, [0, 511])
+
+
+def test_j3_mixed_precision(gpu, orc):
+    wl = _j3_solid(48, 16, 16, precision="mixed", table_dtype=np.float32, delay_rank=8)
+    _compare(gpu, orc, wl, 6, range(16), tol=1e-5, pos_tol=1e-11)
+
+
+@pytest.mark.parametrize("drift", [False, True])
+def test_j3_all_electron(gpu, orc, drift):
+    wl = dataclasses.replace(_j3_solid(32, 14, 16), all_electron=True, drift=drift, sigma=0.06)
+    _compare(gpu, orc, wl, 10, range(16), pos_tol=1e-10)
+
+
+def test_j3_validation(gpu):
+    wl = _j3_solid(16, 12, 2)
+    g = wl.j3["gamma"].copy()
+    g[0, 0, 1, 0] += 1e-3   # no longer symmetric in (l, m)
+    with pytest.raises(gpu.QMCError):
+        gpu.System(dataclasses.replace(wl, j3=dict(wl.j3, gamma=g)))
+    with pytest.raises(gpu.QMCError):
+        gpu.System(dataclasses.replace(wl, j3=dict(wl.j3, rc=wl.L)))
