@@ -33,6 +33,8 @@ def describe(wl) -> str:
         j.append("J1")
     if wl.j2:
         j.append("J2 " + wl.j2["kind"])
+    if getattr(wl, "j3", None):
+        j.append("J3 e-e-I")
     return (f"{wl.name}: {wl.n_elec} electrons ({wl.n_up}+{wl.n_dn}), {wl.n_orb} orbitals on "
             f"{wl.grid[0]}x{wl.grid[1]}x{wl.grid[2]} {tb} B-spline table, {wl.n_ions} ions, "
             f"{'+'.join(j) or 'no Jastrow'}, {wl.n_walkers} walkers, sigma {wl.sigma}, "
@@ -100,6 +102,9 @@ def main(argv=None) -> int:
     ap.add_argument("--moves", default="pbyp", choices=["pbyp", "all", "drift"],
                     help="single: particle-by-particle sweeps (default), or one all-electron move per "
                          "walker per step, plain or drift-diffusion")
+    ap.add_argument("--j3", type=float, default=None,
+                    help="single: add a three-body e-e-I Jastrow term of this coefficient scale "
+                         "(orders 2 and 2, cutoff L/2) to the workload")
     ap.add_argument("--ae-sigma", type=float, default=None,
                     help="all-electron proposal width (default: the workload's sigma / sqrt(N))")
     ap.add_argument("--serial", action="store_true",
@@ -128,6 +133,10 @@ def main(argv=None) -> int:
     if args.mode == "dmc":
         return bench_dmc(args)
     wl = qi.WORKLOADS[args.workload]()
+    if args.j3 is not None:
+        import dataclasses
+        wl = dataclasses.replace(wl, j3=qi.j3_params(2, 2, wl.L / 2, wl.seed, A=args.j3))
+        args.no_compare = True
     ae = args.moves in ("all", "drift")
     if ae:
         # one move displaces all N electrons: a width sigma / sqrt(N) keeps the mean squared
