@@ -88,7 +88,6 @@ struct qmc_system_s {
   SysParams P{};
   EwaldParams E{};
   double* d_ions = nullptr;
-  double* d_j3 = nullptr;
   double* d_gvec = nullptr;
   double* d_sion = nullptr;
   int* d_segs = nullptr;
@@ -588,12 +587,8 @@ qmc_status qmc_create_system(const qmc_system_desc* desc, void* hip_stream, qmc_
 
   if (desc->j3_gamma) {
     const size_t ng = 2 * (size_t)(desc->j3_m_ei + 1) * (desc->j3_m_ei + 1) * (desc->j3_m_ee + 1);
-    s->d_j3 = static_cast<double*>(s->mem.alloc(ng * sizeof(double)));
-    if (!s->d_j3 || hipMemcpy(s->d_j3, desc->j3_gamma, ng * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
-      qmc_destroy_system(s);
-      return fail(nullptr, QMC_ERR_OOM, "device allocation (three-body coefficients)");
-    }
-    P.j3_g = s->d_j3;
+    std::memcpy(P.j3_g, desc->j3_gamma, ng * sizeof(double));
+    P.j3_on = 1;
     P.j3_mei = desc->j3_m_ei;
     P.j3_mee = desc->j3_m_ee;
     P.j3_h = 0.5 * desc->j3_rcut;

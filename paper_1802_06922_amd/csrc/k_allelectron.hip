@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kBlock) void k_ae_jastrow(SysParams P, const double
       const double* ion = P.ions + 4 * I;
       acc += ae_u(sj, 2, ae_dist(x1 + 4 * i, ion, L, invL)) - ae_u(sj, 2, ae_dist(x0 + 3 * i, ion, L, invL));
     }
-  if (P.j3_g) {
+  if (P.j3_on) {
     // three-body terms: (ion, electron i) items, partners j > i near the same ion
     const double h = P.j3_h;
     for (int q = tid; q < N * P.n_ions; q += kBlock) {
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void k_ae_velocity(SysParams P, Walkers<T> 
     range(up ? sj.same : sj.opp, 0, P.n_up, false);
     range(up ? sj.opp : sj.same, P.n_up, N, false);
     if (P.n_ions > 0 && sj.ei.kind != QMC_J_NONE) range(sj.ei, 0, P.n_ions, true);
-    if (P.j3_g) {
+    if (P.j3_on) {
       // three-body terms: grad_i u = u_a a^ + u_c c^ over ions near i and partners j near them
       const double h = P.j3_h;
       for (int I = 0; I < P.n_ions; ++I) {

@@ -207,7 +207,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, in
         const double r0 = sqrt(dx * dx + dy * dy + dz * dz);
         dj += pair_u(sj, kind, r1) - pair_u(sj, kind, r0);
       }
-      if (P.j3_g) {
+      if (P.j3_on) {
         // three-body terms of electron i with partner j near ion I, at r' and at r
         const double h = P.j3_h;
         for (int q = tid; q < P.n_ions * N; q += kBlock) {

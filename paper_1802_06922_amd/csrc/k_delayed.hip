@@ -390,7 +390,7 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
           range(sj.same, off + k0 + Kw, off + n, spos, 3);
           range(sj.opp, ooff, ooff + no, spos, 3);
           range(sj.ei, 0, P.n_ions, ions, 4);
-          if (P.j3_g) {
+          if (P.j3_on) {
             // three-body terms with partners outside the window (in-window partners are pair
             // terms below), over the ions within the cutoff of r or r'
             const double h = P.j3_h;
@@ -437,7 +437,7 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
         if (q2 < q)
           g_new = ju(sj, 0, dist(px, py, pz, nx, ny, nz, L, invL)) -
                   ju(sj, 0, dist(ox, oy, oz, nx, ny, nz, L, invL));
-        if (P.j3_g) {
+        if (P.j3_on) {
           // three-body terms of the pair (same spin) over the ions near either electron
           const double h = P.j3_h;
           for (int I = 0; I < P.n_ions; ++I) {

@@ -213,7 +213,7 @@ __device__ __forceinline__ void measure_part(const SysParams& P, const Walkers<T
     range(up_i ? sj.same : sj.opp, 0, P.n_up, elec);
     range(up_i ? sj.opp : sj.same, P.n_up, N, elec);
     if (P.n_ions > 0) range(sj.ei, N, N + P.n_ions, ion);
-    if (P.j3_g) {
+    if (P.j3_on) {
       // three-body terms (a = r_iI, c = r_ij at fixed b = r_jI): grad_i u = u_a a^ + u_c c^,
       // lap_i u = u_aa + 2 u_a / a + u_cc + 2 u_c / c + 2 u_ac a^.c^; partners j = part (mod parts)
       const double h = P.j3_h;

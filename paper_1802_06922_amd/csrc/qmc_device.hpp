@@ -45,10 +45,11 @@ struct SysParams {
   uint32_t key0, key1;    // Philox key (seed)
   const double* ions;     // [n_ions][4] = x, y, z, Z
   Jastrow jas;
-  // three-body e-e-I term: coefficients [2][mei+1][mei+1][mee+1] (null = no term), cutoff h
-  const double* j3_g;
-  int j3_mei, j3_mee;
+  // three-body e-e-I term (j3_on): coefficients [2][mei+1][mei+1][mee+1] in the parameter
+  // block itself, so that the loops' uniform indices read them as scalar loads; cutoff h
+  int j3_on, j3_mei, j3_mee;
   double j3_h;
+  double j3_g[2 * 4 * 4 * 4];
 };
 
 // Device buffers of the walkers.  T is the orbital/inverse precision.
@@ -201,22 +202,18 @@ __device__ __forceinline__ double radial_value(const Radial& R, double r) {
 // Three-body electron-electron-ion term for electrons i, j near one ion (section "Jastrow
 // factors", the form of Drummond et al.): a = r_iI, b = r_jI, c = r_ij,
 //   u = sum_{l,m,n} g_lmn a^l b^m c^n (a - h)^3 (b - h)^3, zero unless a < h and b < h.
-__device__ __forceinline__ const double* u3_coefs(const SysParams& P, bool same) {
-  return P.j3_g + (same ? 0 : (P.j3_mei + 1) * (P.j3_mei + 1) * (P.j3_mee + 1));
-}
-
 __device__ __forceinline__ double u3_value(const SysParams& P, bool same, double a, double b, double c) {
   const double h = P.j3_h;
   if (a >= h || b >= h) return 0.0;
-  const double* g = u3_coefs(P, same);
   const int M1 = P.j3_mei + 1, N1 = P.j3_mee + 1;
+  const int g0 = same ? 0 : M1 * M1 * N1;
   double pa = 0.0;
   for (int l = M1 - 1; l >= 0; --l) {
     double pb = 0.0;
     for (int m = M1 - 1; m >= 0; --m) {
-      const double* gl = g + (l * M1 + m) * N1;
+      const int gl = g0 + (l * M1 + m) * N1;
       double pc = 0.0;
-      for (int n = N1 - 1; n >= 0; --n) pc = pc * c + gl[n];
+      for (int n = N1 - 1; n >= 0; --n) pc = pc * c + P.j3_g[gl + n];
       pb = pb * b + pc;
     }
     pa = pa * a + pb;
@@ -230,17 +227,17 @@ __device__ __forceinline__ void u3_derivs(const SysParams& P, bool same, double 
   const double h = P.j3_h;
   d[0] = d[1] = d[2] = d[3] = d[4] = d[5] = 0.0;
   if (a >= h || b >= h) return;
-  const double* g = u3_coefs(P, same);
   const int M1 = P.j3_mei + 1, N1 = P.j3_mee + 1;
+  const int g0 = same ? 0 : M1 * M1 * N1;
   double Pv = 0.0, Pa = 0.0, Pc = 0.0, Paa = 0.0, Pcc = 0.0, Pac = 0.0;
   double al = 1.0, al1 = 0.0, al2 = 0.0;   // a^l, l a^(l-1), l (l-1) a^(l-2) (likewise for c)
   for (int l = 0; l < M1; ++l) {
     double bm = 1.0;
     for (int m = 0; m < M1; ++m) {
-      const double* gl = g + (l * M1 + m) * N1;
+      const int gl = g0 + (l * M1 + m) * N1;
       double cn = 1.0, cn1 = 0.0, cn2 = 0.0;
       for (int n = 0; n < N1; ++n) {
-        const double gb = gl[n] * bm;
+        const double gb = P.j3_g[gl + n] * bm;
         Pv += gb * al * cn;
         Pa += gb * al1 * cn;
         Paa += gb * al2 * cn;
