@@ -202,11 +202,14 @@ __device__ __forceinline__ double radial_value(const Radial& R, double r) {
 // Three-body electron-electron-ion term for electrons i, j near one ion (section "Jastrow
 // factors", the form of Drummond et al.): a = r_iI, b = r_jI, c = r_ij,
 //   u = sum_{l,m,n} g_lmn a^l b^m c^n (a - h)^3 (b - h)^3, zero unless a < h and b < h.
-__device__ __forceinline__ double u3_value(const SysParams& P, bool same, double a, double b, double c) {
+// SAME selects the coefficient set (equal or opposite spins) at compile time, so that every
+// coefficient index is uniform across the wave; u3_value / u3_derivs branch to it.
+template <bool SAME>
+__device__ __forceinline__ double u3_value_t(const SysParams& P, double a, double b, double c) {
   const double h = P.j3_h;
   if (a >= h || b >= h) return 0.0;
   const int M1 = P.j3_mei + 1, N1 = P.j3_mee + 1;
-  const int g0 = same ? 0 : M1 * M1 * N1;
+  const int g0 = SAME ? 0 : M1 * M1 * N1;
   double pa = 0.0;
   for (int l = M1 - 1; l >= 0; --l) {
     double pb = 0.0;
@@ -222,13 +225,18 @@ __device__ __forceinline__ double u3_value(const SysParams& P, bool same, double
   return pa * fa * fb;
 }
 
+__device__ __forceinline__ double u3_value(const SysParams& P, bool same, double a, double b, double c) {
+  return same ? u3_value_t<true>(P, a, b, c) : u3_value_t<false>(P, a, b, c);
+}
+
 // The same with its partial derivatives at fixed b: d = (u, u_a, u_c, u_aa, u_cc, u_ac).
-__device__ __forceinline__ void u3_derivs(const SysParams& P, bool same, double a, double b, double c, double d[6]) {
+template <bool SAME>
+__device__ __forceinline__ void u3_derivs_t(const SysParams& P, double a, double b, double c, double d[6]) {
   const double h = P.j3_h;
   d[0] = d[1] = d[2] = d[3] = d[4] = d[5] = 0.0;
   if (a >= h || b >= h) return;
   const int M1 = P.j3_mei + 1, N1 = P.j3_mee + 1;
-  const int g0 = same ? 0 : M1 * M1 * N1;
+  const int g0 = SAME ? 0 : M1 * M1 * N1;
   double Pv = 0.0, Pa = 0.0, Pc = 0.0, Paa = 0.0, Pcc = 0.0, Pac = 0.0;
   double al = 1.0, al1 = 0.0, al2 = 0.0;   // a^l, l a^(l-1), l (l-1) a^(l-2) (likewise for c)
   for (int l = 0; l < M1; ++l) {
@@ -263,6 +271,11 @@ __device__ __forceinline__ void u3_derivs(const SysParams& P, bool same, double 
   d[3] = (Paa * fa + 2.0 * Pa * fa1 + Pv * fa2) * fb;
   d[4] = Pcc * fa * fb;
   d[5] = (Pac * fa + Pc * fa1) * fb;
+}
+
+__device__ __forceinline__ void u3_derivs(const SysParams& P, bool same, double a, double b, double c, double d[6]) {
+  if (same) u3_derivs_t<true>(P, a, b, c, d);
+  else u3_derivs_t<false>(P, a, b, c, d);
 }
 
 // Wave64 sum of a double (xor butterfly: every lane gets the total).
