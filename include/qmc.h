@@ -228,6 +228,8 @@ qmc_status qmc_run_steps(qmc_system s, int32_t n_steps, double* energies_dev);
 /* Start a population: slots [0, n_target) alive with weight 1 at their current
  * configurations, local energies measured; E_T = e_trial, or (NaN) the mean
  * local energy of the alive slots; feedback >= 0 in hartree.  Synchronises.
+ * The first call after qmc_init_walkers allocates the population buffers
+ * (about 60 bytes per slot; qmc_estimate_device_bytes counts them).
  * Errors: STATE (no walkers, or not QMC_MOVE_ALL_DRIFT), ARG, OOM, NUMERIC. */
 qmc_status qmc_dmc_init(qmc_system s, int32_t n_target, double e_trial, double feedback);
 

@@ -362,7 +362,7 @@ void free_walkers(qmc_system s) {
 
 struct WalkerSizes {
   size_t pos, prop, vgl, cur, binv, logdet, sign, acc, nacc, status, scratch, drift, energy, val64, nguard, sweep,
-      xinv, ae_binv, ae_logdet, ae_dj, ae_sign, ae_status, ae_vel, ae_logT;
+      xinv, ae_binv, ae_logdet, ae_dj, ae_sign, ae_status, ae_vel, ae_logT, dmc;
   size_t total() const {
     return align_up(pos) + align_up(prop) + align_up(vgl) + align_up(cur) + align_up(binv) +
            align_up(logdet) + align_up(sign) + align_up(acc) + align_up(nacc) + align_up(status) +
@@ -371,7 +371,7 @@ struct WalkerSizes {
            (ae_binv ? align_up(ae_binv) + align_up(ae_logdet) + align_up(ae_dj) + align_up(ae_sign) +
                           align_up(ae_status)
                     : 0) +
-           (ae_vel ? 2 * align_up(ae_vel) + align_up(ae_logT) : 0);
+           (ae_vel ? 2 * align_up(ae_vel) + align_up(ae_logT) : 0) + dmc;
   }
 };
 
@@ -405,6 +405,11 @@ WalkerSizes walker_sizes(int n_up, int n_dn, int precision, int W, int n_orb, in
   const bool drift = move_kind == QMC_MOVE_ALL_DRIFT;
   z.ae_vel = drift ? W * N * 3 * sizeof(double) : 0;
   z.ae_logT = drift ? W * (size_t)velocity_parts((int)N) * sizeof(double) : 0;
+  // the DMC population qmc_dmc_init carves out (weights, energies, [W][4] energies, control
+  // doubles, five [W] int arrays and the control ints)
+  z.dmc = drift ? align_up(W * sizeof(double)) * 2 + align_up(W * 4 * sizeof(double)) + align_up(2 * sizeof(double)) +
+                      align_up((5 * (size_t)W + 3) * sizeof(int))
+                : 0;
   return z;
 }
 

@@ -97,3 +97,20 @@ def test_max_delay_rank_is_host_only_and_monotone(libqmc):
     d = qmc.make_desc(qi.heg14(), keep)
     d.n_up = 0
     assert libqmc.qmc_max_delay_rank(ctypes.byref(d)) == 0
+
+
+def test_estimate_counts_move_kind_buffers(libqmc):
+    """All-electron moves add the proposal's inverses and log-determinants; drift moves add the
+    velocities, the transition-ratio partials and the DMC population on top."""
+    import dataclasses
+
+    import qmc_inputs as qi
+    from paper_1802_06922_amd import qmc
+    qmc.load_library()
+    wl = qi.solid(32, 12, n_walkers=64, n_sweeps=1)
+    W, N, n = 64, 32, 16
+    pbyp = qmc.estimate_device_bytes(wl, W)
+    ae = qmc.estimate_device_bytes(dataclasses.replace(wl, all_electron=True), W)
+    drift = qmc.estimate_device_bytes(dataclasses.replace(wl, all_electron=True, drift=True), W)
+    assert ae - pbyp >= W * 2 * n * n * 8            # inverses at R'
+    assert drift - ae >= 2 * W * N * 3 * 8 + W * 6 * 8   # velocities at R and R', DMC weights and energies

@@ -86,6 +86,23 @@ def test_dmc_mixed_precision(gpu, orc):
     _compare(gpu, orc, _drift(wl, 0.08), 48, 32, 12, 0.5, rel=1e-5, pos_tol=1e-7)
 
 
+def test_dmc_in_a_caller_arena(gpu):
+    """The population buffers fit an arena sized by qmc_estimate_device_bytes, and the run is
+    bit for bit the one with the library's own allocations."""
+    import torch
+    wl = _drift(qi.heg14(), 0.2)
+    out = []
+    for arena in (False, True):
+        s = gpu.System(wl, n_walkers=32, use_torch_arena=arena)
+        s.dmc_init(24, feedback=0.5)
+        st = torch.zeros((10, 6), dtype=torch.float64, device="cuda")
+        s.dmc_steps(10, st)
+        out.append((st.cpu().numpy(), s.get_walkers()[0], s.dmc_state()[0]))
+        s.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
 def test_dmc_needs_drift_moves_and_init(gpu):
     s = gpu.System(dataclasses.replace(qi.heg14(), all_electron=True, sigma=0.1))
     with pytest.raises(gpu.QMCError):
