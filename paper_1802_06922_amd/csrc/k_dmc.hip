@@ -152,20 +152,21 @@ __global__ __launch_bounds__(kBlock) void k_dmc_copy(SysParams P, Walkers<T> Wk,
   const int N = P.N;
   const size_t s0 = (size_t)src * N, f0 = (size_t)f * N;
   for (int q = tid; q < 3 * N; q += kBlock) Wk.pos[f0 * 3 + q] = Wk.pos[s0 * 3 + q];
-  const size_t rl = (size_t)kComp * P.S;
-  for (size_t q = tid; q < (size_t)N * rl; q += kBlock) {
-    const int i = (int)(q / rl);
-    const size_t c = q - (size_t)i * rl;
+  // rows: one wave per electron, 16-byte vectors (a row of 5 S values and an FP64 value row
+  // are multiples of 16 bytes: S is padded to 16 bytes and the buffers are 256-byte aligned)
+  const int lane = tid & 63, wave = tid >> 6;
+  const int rv = kComp * P.S * (int)sizeof(T) / 16, r64 = P.S * 8 / 16;
+  for (int i = wave; i < N; i += kWaves) {
     const size_t b = Wk.cur[s0 + i];
-    Wk.vgl[((b * P.W * N) + f0 + i) * rl + c] = Wk.vgl[((b * P.W * N) + s0 + i) * rl + c];
-  }
-  if (Wk.val64)
-    for (size_t q = tid; q < (size_t)N * P.S; q += kBlock) {
-      const int i = (int)(q / P.S);
-      const size_t c = q - (size_t)i * P.S;
-      const size_t b = Wk.cur[s0 + i];
-      Wk.val64[((b * P.W * N) + f0 + i) * P.S + c] = Wk.val64[((b * P.W * N) + s0 + i) * P.S + c];
+    const uint4* src_row = reinterpret_cast<const uint4*>(Wk.vgl + ((b * P.W * N) + s0 + i) * kComp * P.S);
+    uint4* dst_row = reinterpret_cast<uint4*>(Wk.vgl + ((b * P.W * N) + f0 + i) * kComp * P.S);
+    for (int c = lane; c < rv; c += 64) dst_row[c] = src_row[c];
+    if (Wk.val64) {
+      const uint4* s64 = reinterpret_cast<const uint4*>(Wk.val64 + ((b * P.W * N) + s0 + i) * P.S);
+      uint4* d64 = reinterpret_cast<uint4*>(Wk.val64 + ((b * P.W * N) + f0 + i) * P.S);
+      for (int c = lane; c < r64; c += 64) d64[c] = s64[c];
     }
+  }
   for (size_t q = tid; q < (size_t)P.bstride; q += kBlock)
     Wk.binv[(size_t)f * P.bstride + q] = Wk.binv[(size_t)src * P.bstride + q];
   __syncthreads();   // every thread has read the source's row flags
