@@ -131,10 +131,11 @@ __global__ __launch_bounds__(kBlock) void k_rebuild(SysParams P, Walkers<T> Wk, 
 
 // ---------------------------------------------------------------------------
 // The same elimination with the matrix held in registers (spin blocks up to
-// kRegRebuildMax).  A 32 x 32 grid of threads covers the matrix cyclically:
-// thread (r0, c0), r0 = tid % 32, c0 = tid / 32, holds the entries
-// (r0 + 32 i, c0 + 32 j), i, j < R, so a column's owners are 32 consecutive
-// lanes (the pivot search is one half-wave reduction).  Rows are not swapped:
+// kRegRebuildMax).  A G x G grid of threads (G = 16 for blocks up to 64, else
+// 32) covers the matrix cyclically: thread (r0, c0), r0 = tid % G, c0 = tid / G,
+// holds the entries (r0 + G i, c0 + G j), i, j < R, so a column's owners are G
+// consecutive lanes (the pivot search is one reduction within them).  The small
+// grid keeps a step's barriers to four waves for the common small blocks.  Rows are not swapped:
 // step k takes as pivot the largest |a[i][k]| over the rows not yet used and
 // records it, which is partial pivoting applied to the row-permuted matrix
 // C = P A (C's row k = A's row p_k); the in-place elimination of C leaves
@@ -146,20 +147,20 @@ __global__ __launch_bounds__(kBlock) void k_rebuild(SysParams P, Walkers<T> Wk, 
 constexpr int kRegRebuildMax = 192;
 constexpr int kRegBlock = 1024;
 
-template <typename T, int R>
-__global__ __launch_bounds__(kRegBlock) void k_rebuild_reg(SysParams P, Walkers<T> Wk, double* drift,
+template <typename T, int R, int G>
+__global__ __launch_bounds__(G * G) void k_rebuild_reg(SysParams P, Walkers<T> Wk, double* drift,
                                                            const uint32_t* sel, uint32_t sel_value) {
-  __shared__ double scol[2][32 * R];
-  __shared__ double srow[2][32 * R];
-  __shared__ int spiv[32 * R];    // physical row of each step's pivot
-  __shared__ int sstep[32 * R];   // step at which each physical row was the pivot
-  __shared__ double spv[32 * R];   // pivot of each step
-  __shared__ double slog[32 * R];
+  __shared__ double scol[2][G * R];
+  __shared__ double srow[2][G * R];
+  __shared__ int spiv[G * R];    // physical row of each step's pivot
+  __shared__ int sstep[G * R];   // step at which each physical row was the pivot
+  __shared__ double spv[G * R];   // pivot of each step
+  __shared__ double slog[G * R];
   __shared__ double sbest[2];
-  __shared__ double samax[kRegBlock / 64];
+  __shared__ double samax[G * G / 64];
   const int w = blockIdx.x >> 1, sp = blockIdx.x & 1, tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int r0 = tid & 31, c0 = tid >> 5;
+  const int r0 = tid & (G - 1), c0 = tid / G;
   const int n = sp ? P.n_dn : P.n_up, off = sp ? P.n_up : 0;
   const int N = P.N;
   if (sel && sel[w] != sel_value) return;
@@ -171,22 +172,22 @@ __global__ __launch_bounds__(kRegBlock) void k_rebuild_reg(SysParams P, Walkers<
     }
     return;
   }
-  for (int q = tid; q < 2 * 32 * R; q += kRegBlock) {
+  for (int q = tid; q < 2 * G * R; q += (G * G)) {
     (&scol[0][0])[q] = 0.0;
     (&srow[0][0])[q] = 0.0;
   }
   double a[R][R];
-  unsigned used = 0;   // bit i: row r0 + 32 i is padding or has been a pivot
+  unsigned used = 0;   // bit i: row r0 + G i is padding or has been a pivot
   double amax = 0.0;
 #pragma unroll
   for (int i = 0; i < R; ++i) {
-    const int e = r0 + 32 * i;
+    const int e = r0 + G * i;
     if (e < n) {
       const size_t item = (size_t)w * N + off + e;
       const size_t row = (size_t)(Wk.cur[item] ^ Wk.row_flip) * P.W * N + item;
 #pragma unroll
       for (int j = 0; j < R; ++j) {
-        const int l = c0 + 32 * j;
+        const int l = c0 + G * j;
         a[i][j] = l < n ? (Wk.val64 ? Wk.val64[row * P.S + l] : (double)Wk.vgl[row * kComp * P.S + l]) : 0.0;
         amax = fmax(amax, fabs(a[i][j]));
       }
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(kRegBlock) void k_rebuild_reg(SysParams P, Walkers<
   if (lane == 0) samax[wave] = amax;
   __syncthreads();
   amax = samax[0];
-  for (int q = 1; q < kRegBlock / 64; ++q) amax = fmax(amax, samax[q]);
+  for (int q = 1; q < G * G / 64; ++q) amax = fmax(amax, samax[q]);
   // a pivot this small relative to the largest entry means a numerically singular matrix
   const double tiny = 1e-14 * amax;
   double logabs = 0.0;
@@ -209,12 +210,12 @@ __global__ __launch_bounds__(kRegBlock) void k_rebuild_reg(SysParams P, Walkers<
   bool singular = false;
   for (int k = 0; k < n; ++k) {
     const int b = k & 1;
-    const int jk = k >> 5;
-    const bool colk = c0 == (k & 31);   // this thread holds entries of column k
-    double* sc = &scol[b][r0];           // scol[b][r0 + 32 i] = sc[32 i]
-    double* sr = &srow[b][c0];           // srow[b][c0 + 32 j] = sr[32 j]
+    const int jk = k / G;
+    const bool colk = c0 == (k & (G - 1));   // this thread holds entries of column k
+    double* sc = &scol[b][r0];           // scol[b][r0 + G i] = sc[G i]
+    double* sr = &srow[b][c0];           // srow[b][c0 + G j] = sr[G j]
     if (colk) {
-      // this half-wave owns column k: publish it and find the pivot among the unused rows
+      // these G lanes own column k: publish it and find the pivot among the unused rows
       double best = -1.0;
       int bi = n;
 #pragma unroll
@@ -223,12 +224,12 @@ __global__ __launch_bounds__(kRegBlock) void k_rebuild_reg(SysParams P, Walkers<
 #pragma unroll
         for (int i = 0; i < R; ++i) {
           const double v = a[i][j];
-          if (r0 + 32 * i < n) sc[32 * i] = v;
-          if (!((used >> i) & 1u) && fabs(v) > best) { best = fabs(v); bi = r0 + 32 * i; }
+          if (r0 + G * i < n) sc[G * i] = v;
+          if (!((used >> i) & 1u) && fabs(v) > best) { best = fabs(v); bi = r0 + G * i; }
         }
       }
 #pragma unroll
-      for (int o = 16; o >= 1; o >>= 1) {
+      for (int o = G / 2; o >= 1; o >>= 1) {
         const double ob = __shfl_xor(best, o, 64);
         const int oi = __shfl_xor(bi, o, 64);
         if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
@@ -239,8 +240,8 @@ __global__ __launch_bounds__(kRegBlock) void k_rebuild_reg(SysParams P, Walkers<
     const int p = uniform(spiv[k]);
     const double best = uniform(sbest[b]);
     if (!(best > tiny) || !isfinite(best)) { singular = true; break; }
-    const int ip = p >> 5;
-    const bool rowp = r0 == (p & 31);   // this thread holds entries of the pivot row
+    const int ip = p / G;
+    const bool rowp = r0 == (p & (G - 1));   // this thread holds entries of the pivot row
     if (rowp) {
       used |= 1u << ip;
 #pragma unroll
@@ -248,7 +249,7 @@ __global__ __launch_bounds__(kRegBlock) void k_rebuild_reg(SysParams P, Walkers<
         if (i != ip) continue;   // uniform: one register row is taken
 #pragma unroll
         for (int j = 0; j < R; ++j)
-          if (c0 + 32 * j < n) sr[32 * j] = a[i][j];
+          if (c0 + G * j < n) sr[G * j] = a[i][j];
       }
     }
     __syncthreads();
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(kRegBlock) void k_rebuild_reg(SysParams P, Walkers<
     // scaled pivot row; the pivot column's entry becomes 1 / piv
     double rs[R];
 #pragma unroll
-    for (int j = 0; j < R; ++j) rs[j] = (j == jk && colk) ? pinv : sr[32 * j] * pinv;
+    for (int j = 0; j < R; ++j) rs[j] = (j == jk && colk) ? pinv : sr[G * j] * pinv;
     // column k restarts from zero, so the update leaves -a[i][k] / piv there
 #pragma unroll
     for (int j = 0; j < R; ++j) {
@@ -268,7 +269,7 @@ __global__ __launch_bounds__(kRegBlock) void k_rebuild_reg(SysParams P, Walkers<
     }
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-      const double f = sc[32 * i];
+      const double f = sc[G * i];
 #pragma unroll
       for (int j = 0; j < R; ++j) a[i][j] = a[i][j] - f * rs[j];
     }
@@ -281,21 +282,21 @@ __global__ __launch_bounds__(kRegBlock) void k_rebuild_reg(SysParams P, Walkers<
     }
   }
   if (!singular) {
-    for (int k = tid; k < n; k += kRegBlock) sstep[spiv[k]] = k;
+    for (int k = tid; k < n; k += (G * G)) sstep[spiv[k]] = k;
     __syncthreads();
     T* B = Wk.binv + (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0);
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-      const int e = r0 + 32 * i;
+      const int e = r0 + G * i;
       if (e >= n) continue;
       const size_t orow = (size_t)sstep[e] * n;
 #pragma unroll
       for (int j = 0; j < R; ++j) {
-        const int l = c0 + 32 * j;
+        const int l = c0 + G * j;
         if (l < n) B[orow + spiv[l]] = (T)a[i][j];
       }
     }
-    for (int k = tid; k < n; k += kRegBlock) slog[k] = log(fabs(spv[k]));
+    for (int k = tid; k < n; k += (G * G)) slog[k] = log(fabs(spv[k]));
     __syncthreads();
     if (tid == 0) {
       for (int k = 0; k < n; ++k) {
@@ -793,14 +794,23 @@ hipError_t launch_rebuild(const SysParams& P, const Walkers<T>& Wk, double* scra
   // tests compare the two kernels)
   const char* fg = getenv("QMC_REBUILD_GLOBAL");
   if (!(fg && fg[0] == '1') && nmax <= kRegRebuildMax) {
-    const dim3 grid(2 * P.W), block(kRegBlock);
+    const dim3 grid(2 * P.W);
+    if (nmax <= 64) {
+      const dim3 block(16 * 16);
+      switch ((nmax + 15) / 16) {
+        case 1: hipLaunchKernelGGL((k_rebuild_reg<T, 1, 16>), grid, block, 0, st, P, Wk, drift, sel, sel_value); break;
+        case 2: hipLaunchKernelGGL((k_rebuild_reg<T, 2, 16>), grid, block, 0, st, P, Wk, drift, sel, sel_value); break;
+        case 3: hipLaunchKernelGGL((k_rebuild_reg<T, 3, 16>), grid, block, 0, st, P, Wk, drift, sel, sel_value); break;
+        default: hipLaunchKernelGGL((k_rebuild_reg<T, 4, 16>), grid, block, 0, st, P, Wk, drift, sel, sel_value); break;
+      }
+      return hipGetLastError();
+    }
+    const dim3 block(kRegBlock);
     switch ((nmax + 31) / 32) {
-      case 1: hipLaunchKernelGGL((k_rebuild_reg<T, 1>), grid, block, 0, st, P, Wk, drift, sel, sel_value); break;
-      case 2: hipLaunchKernelGGL((k_rebuild_reg<T, 2>), grid, block, 0, st, P, Wk, drift, sel, sel_value); break;
-      case 3: hipLaunchKernelGGL((k_rebuild_reg<T, 3>), grid, block, 0, st, P, Wk, drift, sel, sel_value); break;
-      case 4: hipLaunchKernelGGL((k_rebuild_reg<T, 4>), grid, block, 0, st, P, Wk, drift, sel, sel_value); break;
-      case 5: hipLaunchKernelGGL((k_rebuild_reg<T, 5>), grid, block, 0, st, P, Wk, drift, sel, sel_value); break;
-      default: hipLaunchKernelGGL((k_rebuild_reg<T, 6>), grid, block, 0, st, P, Wk, drift, sel, sel_value); break;
+      case 3: hipLaunchKernelGGL((k_rebuild_reg<T, 3, 32>), grid, block, 0, st, P, Wk, drift, sel, sel_value); break;
+      case 4: hipLaunchKernelGGL((k_rebuild_reg<T, 4, 32>), grid, block, 0, st, P, Wk, drift, sel, sel_value); break;
+      case 5: hipLaunchKernelGGL((k_rebuild_reg<T, 5, 32>), grid, block, 0, st, P, Wk, drift, sel, sel_value); break;
+      default: hipLaunchKernelGGL((k_rebuild_reg<T, 6, 32>), grid, block, 0, st, P, Wk, drift, sel, sel_value); break;
     }
     return hipGetLastError();
   }
