@@ -108,3 +108,24 @@ def test_gather_autotune_keeps_rows_bitwise(gpu):
     ref = (s.get_walkers()[0], s.measure())
     s.close()
     assert np.array_equal(tuned[0], ref[0]) and np.array_equal(tuned[1], ref[1])
+
+
+def test_batch_with_a_three_body_member_equals_alone(gpu):
+    """The three-body term travels in each member's parameter block, so a batch with a
+    member that has it and one that has not advances each as alone, bit for bit."""
+    sweeps = 4
+    j3 = qi.solid(32, 12, n_walkers=24, n_sweeps=1, precision="mixed", delay_rank=8, recompute_period=3,
+                  seed=5, j3=True, j3_strength=50.0)
+    plain = _systems()[0]
+    wls = [j3, plain]
+    ref = [_alone(gpu, wl, sweeps) for wl in wls]
+    systems = [gpu.System(wl) for wl in wls]
+    batch = gpu.Batch(systems)
+    for it in range(sweeps):
+        batch.sweep(1, measure=True)
+        for k, s in enumerate(systems):
+            assert np.array_equal(s.accept_log(), ref[k][0][it])
+            assert np.array_equal(s.last_energies(), ref[k][1][it])
+    batch.close()
+    for s in systems:
+        s.close()
