@@ -92,6 +92,8 @@ def main(argv=None) -> int:
                          "a plain 1 GiB device copy (x3), the reference for HBM counter readings")
     ap.add_argument("--requests", type=int, default=40, help="served: requests of each trace")
     ap.add_argument("--sweep-scale", type=float, default=0.05, help="served: scale of each request's sweeps")
+    ap.add_argument("--dmc-every", type=int, default=4,
+                    help="served: every k-th request is a DMC run (0: VMC only)")
     ap.add_argument("--no-graph", action="store_true", help="batched/served: no HIP graph replay")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--gather-lanes", type=int, default=None,
@@ -438,7 +440,8 @@ def bench_batched(args) -> int:
 
 def bench_served(args) -> int:
     """Served request streams: Poisson arrivals of requests with electron counts log-uniform in
-    [32, 1024], grids 32..64^3, 64..1024 walkers, 100..1000 sweeps scaled by --sweep-scale.
+    [32, 1024], grids 32..64^3, 64..1024 walkers, 100..1000 sweeps scaled by --sweep-scale; every
+    --dmc-every-th request is a DMC run (as many steps), the others VMC runs.
     First at 20 requests/s (far above one GPU's capacity), then at 0.8 x the capacity measured
     in that run; p50/p99 per-sweep latency for both, throughput of the first."""
     import dataclasses
@@ -448,7 +451,8 @@ def bench_served(args) -> int:
 
     log = lambda m: print(m, file=sys.stderr, flush=True)
     trace = qi.served_trace(n_requests=args.requests, rate_per_s=20.0, seed=0)
-    reqs = serve.build_requests(trace, sweep_scale=args.sweep_scale, table_pool=True, log=log)
+    reqs = serve.build_requests(trace, sweep_scale=args.sweep_scale, table_pool=True, log=log,
+                                dmc_every=args.dmc_every)
     srv = serve.Server(graph=not args.no_graph)
     st = srv.run(reqs, log=log)
     capacity = st["requests"] / st["wall_s"]
@@ -456,7 +460,7 @@ def bench_served(args) -> int:
     rate = 0.8 * capacity
     slow = qi.served_trace(n_requests=args.requests, rate_per_s=rate, seed=0)
     reqs2 = [dataclasses.replace(r, arrival_s=e["arrival_s"], system=None, done_sweeps=0, latencies_ms=[],
-                                 gpu_ms=[], energy=None, final_pos=None)
+                                 gpu_ms=[], energy=None, final_pos=None, stats=None, stream=None)
              for r, e in zip(sorted(reqs, key=lambda r: r.rid), slow)]
     st2 = srv.run(reqs2, log=log)
     line = {
@@ -466,8 +470,9 @@ def bench_served(args) -> int:
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"served stream: {args.requests} Poisson arrivals, N log-uniform [32, 1024], "
-                               f"grids 32..64^3, 64..1024 walkers, 100..1000 sweeps x{args.sweep_scale}",
-                   "hbm_budget_bytes": srv.budget},
+                               f"grids 32..64^3, 64..1024 walkers, 100..1000 sweeps x{args.sweep_scale}"
+                               + (f", every {args.dmc_every}th request a DMC run" if args.dmc_every else ""),
+                   "hbm_budget_bytes": srv.budget, "dmc_requests": st["dmc_requests"]},
         "overload_20_per_s": {"p50_sweep_latency_ms": st["p50_sweep_ms"], "p99_sweep_latency_ms": st["p99_sweep_ms"],
                               "requests": st["requests"], "wall_s": st["wall_s"], "mean_queue_s": st["mean_queue_s"],
                               "capacity_requests_per_s": capacity},

@@ -1,14 +1,17 @@
-"""Serving loop: continuous batching of VMC requests on one GPU.
+"""Serving loop: continuous batching of VMC and DMC requests on one GPU.
 
-Requests (each a VMC run with its own system, table, walker count and sweep
-count) arrive on a trace.  A request is admitted as soon as its device memory
+Requests (each a VMC run, or a DMC run, with its own system, table, walker
+count and sweep or step count) arrive on a trace.  A request is admitted as soon as its device memory
 (``qmc_estimate_device_bytes``) fits the HBM budget next to the requests
 already resident; its walkers, inverses and table then stay on the GPU until
 it finishes.  Every iteration advances all resident requests by one sweep
 with one fused batch launch (``qmc_batch_*``), so requests that arrive while
 others run join at the next sweep boundary and their work overlaps on the
-device.  A request's results do not depend on which other requests share the
-GPU: every walker runs the same per-walker arithmetic in any batch.
+device.  A DMC request (drift-diffusion all-electron moves, branching on the
+device) advances one step per iteration on its own stream, issued before the
+fused VMC sweep so that the two overlap.  A request's results do not depend on
+which other requests share the GPU: every walker runs the same per-walker
+arithmetic in any batch, and a DMC population is private to its request.
 
 Per-sweep latency of a request = wall time between its consecutive sweep
 completions (the first one counted from its admission), so host work between
@@ -49,8 +52,13 @@ class Request:
     latencies_ms: list = dataclasses.field(default_factory=list)
     gpu_ms: list = dataclasses.field(default_factory=list)
     last_done_s: float = 0.0
-    energy: Optional[np.ndarray] = None
+    energy: Optional[np.ndarray] = None   # VMC: last energies [W][4]; DMC: per-step statistics [steps][6]
     final_pos: Optional[np.ndarray] = None
+    kind: str = "vmc"                     # "vmc" or "dmc" (the workload makes drift-diffusion moves)
+    dmc_target: int = 0                   # DMC: target population (slots alive at the start)
+    dmc_feedback: float = 1.0             # DMC: E_T feedback constant (hartree)
+    stats: Optional[object] = None        # DMC: device tensor [steps][6] of per-step statistics
+    stream: Optional[object] = None       # DMC: the request's own stream
 
 
 class Server:
@@ -87,6 +95,14 @@ class Server:
         t0 = time.perf_counter()
 
         def prepare(r, k):
+            if r.kind == "dmc":
+                # a DMC request keeps its own stream: its steps overlap the fused VMC sweeps
+                r.stream = torch.cuda.Stream()
+                with torch.cuda.stream(r.stream):
+                    s = qmc.System(r.wl, stream=r.stream)
+                    s.dmc_init(r.dmc_target, feedback=r.dmc_feedback)
+                    r.stats = torch.zeros((r.n_sweeps, 6), dtype=torch.float64, device="cuda")
+                    return s
             with torch.cuda.stream(prep_streams[k]):
                 return qmc.System(r.wl, stream=prep_streams[k])
 
@@ -118,7 +134,7 @@ class Server:
                         r.admitted_s = time.perf_counter() - t0
                         r.last_done_s = r.admitted_s
                         active.append(r)
-                        dirty = True
+                        dirty = dirty or r.kind == "vmc"
                         if log:
                             log(f"[serve] t={r.admitted_s:.3f}s admit {r.rid} N={r.wl.n_elec} "
                                 f"W={r.wl.n_walkers} sweeps={r.n_sweeps} ({len(active)} resident)")
@@ -129,13 +145,23 @@ class Server:
                     if pending and not queue and not preparing:
                         time.sleep(max(0.0, pending[0].arrival_s * time_scale - (time.perf_counter() - t0)))
                     continue
+                vmc = [r for r in active if r.kind == "vmc"]
                 if dirty:
                     if batch is not None:
                         batch.close()
-                    batch = qmc.Batch([r.system for r in active], stream=self.stream, graph=self.graph)
+                    batch = (qmc.Batch([r.system for r in vmc], stream=self.stream, graph=self.graph)
+                             if vmc else None)
                     dirty = False
-                batch.sweep(1, measure=True)
-                ms, _ = batch.timing(reset=True)     # synchronises: this sweep's GPU time
+                for r in active:   # DMC steps first, on their own streams
+                    if r.kind == "dmc":
+                        r.system.dmc_steps(1, r.stats[r.done_sweeps:r.done_sweeps + 1])
+                ms = 0.0
+                if batch is not None:
+                    batch.sweep(1, measure=True)
+                    ms, _ = batch.timing(reset=True)     # synchronises: this sweep's GPU time
+                for r in active:
+                    if r.kind == "dmc":
+                        r.stream.synchronize()
                 done = time.perf_counter() - t0
                 n_sweep_iters += 1
                 still = []
@@ -145,14 +171,18 @@ class Server:
                     r.last_done_s = done
                     r.done_sweeps += 1
                     if r.done_sweeps >= r.n_sweeps:
-                        r.energy = r.system.last_energies()
+                        if r.kind == "dmc":
+                            r.energy = r.stats.cpu().numpy()
+                            r.stats = None
+                        else:
+                            r.energy = r.system.last_energies()
                         r.final_pos = r.system.get_walkers()[0]
                         r.finished_s = time.perf_counter() - t0
                         r.system.close()
                         r.system = None
                         used -= r.est_bytes
                         finished.append(r)
-                        dirty = True
+                        dirty = dirty or r.kind == "vmc"
                     else:
                         still.append(r)
                 active = still
@@ -160,7 +190,13 @@ class Server:
             batch.close()
         wall = time.perf_counter() - t0
         lat = np.array([x for r in finished for x in r.latencies_ms])
-        moves = sum(r.wl.n_walkers * r.wl.n_elec * r.n_sweeps for r in finished)
+        def moves_of(r):
+            if r.kind == "dmc":   # electrons of the walkers alive at each step
+                alive = r.dmc_target + float(np.sum(r.energy[:-1, 2]))
+                return alive * r.wl.n_elec
+            return r.wl.n_walkers * r.wl.n_elec * r.n_sweeps
+
+        moves = sum(moves_of(r) for r in finished)
         return {
             "requests": len(finished),
             "wall_s": wall,
@@ -172,17 +208,20 @@ class Server:
             "p50_sweep_ms": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_sweep_ms": float(np.percentile(lat, 99)) if lat.size else None,
             "mean_queue_s": float(np.mean([r.admitted_s - r.arrival_s * time_scale for r in finished])),
+            "dmc_requests": sum(r.kind == "dmc" for r in finished),
             "finished": finished,
         }
 
 
 def build_requests(trace, sweep_scale: float = 1.0, max_workers: int = 8, table_pool: bool = False,
-                   log=None):
+                   log=None, dmc_every: int = 0):
     """Requests for a trace of ``qmc_inputs.served_trace`` entries, each a solid-like mixed-precision
     system.  Tables are generated on the host before serving starts: per request with seed = its
     id, or, with ``table_pool``, as the first n_orb orbitals of one 512-orbital table per grid size
     (seed = grid), which keeps generation of a long trace to a few tables; the served arithmetic
-    does not depend on the coefficient values."""
+    does not depend on the coefficient values.  With ``dmc_every`` = k > 0 every k-th request is a
+    DMC run instead (drift-diffusion moves with sigma 0.3 / sqrt(N), 7/8 of its walkers as the
+    target population, feedback 1 hartree, as many steps as the request's sweeps)."""
     import qmc_inputs as qi
 
     pool: dict = {}
@@ -205,7 +244,11 @@ def build_requests(trace, sweep_scale: float = 1.0, max_workers: int = 8, table_
             wl.coefs = np.ascontiguousarray(pool[g][..., :wl.n_orb])
         wl.delay_rank = delay_rank_for(wl)
         n = max(1, int(round(e["n_sweeps"] * sweep_scale)))
-        r = Request(rid=e["id"], arrival_s=e["arrival_s"], wl=wl, n_sweeps=n)
+        dmc = dmc_every > 0 and e["id"] % dmc_every == dmc_every - 1
+        if dmc:
+            wl = dataclasses.replace(wl, all_electron=True, drift=True, sigma=0.3 / np.sqrt(wl.n_elec))
+        r = Request(rid=e["id"], arrival_s=e["arrival_s"], wl=wl, n_sweeps=n, kind="dmc" if dmc else "vmc",
+                    dmc_target=max(1, wl.n_walkers * 7 // 8) if dmc else 0)
         r.est_bytes = qmc.estimate_device_bytes(wl, wl.n_walkers)
         if log:
             log(f"[serve] request {r.rid}: N={wl.n_elec} grid={e['grid']} W={wl.n_walkers} "

@@ -46,3 +46,43 @@ def test_served_requests_match_alone(gpu):
         assert np.array_equal(e, r.energy)
         assert np.array_equal(pos, r.final_pos)
         assert len(r.latencies_ms) == r.n_sweeps and min(r.latencies_ms) > 0
+
+
+def test_served_dmc_requests_match_alone(gpu):
+    """DMC requests served beside VMC requests (their steps on their own streams, overlapping the
+    fused VMC sweeps): each request's results are the ones it gets alone, bit for bit."""
+    import dataclasses
+
+    import torch
+    from paper_1802_06922_amd import serve
+    spec = [(24, 12, 6, 4, "vmc"), (16, 12, 16, 6, "dmc"), (48, 14, 10, 5, "vmc"), (32, 12, 24, 5, "dmc")]
+    reqs = []
+    for i, (n, g, w, sw, kind) in enumerate(spec):
+        wl = qi.solid(n, g, n_walkers=w, n_sweeps=1, precision="mixed", table_dtype=np.float32,
+                      recompute_period=2, seed=20 + i, name=f"req{i}")
+        wl.delay_rank = serve.delay_rank_for(wl, cap=16)
+        if kind == "dmc":
+            wl = dataclasses.replace(wl, all_electron=True, drift=True, sigma=0.3 / np.sqrt(n))
+        r = serve.Request(rid=i, arrival_s=0.0, wl=wl, n_sweeps=sw, kind=kind,
+                          dmc_target=w * 3 // 4 if kind == "dmc" else 0, dmc_feedback=0.5)
+        r.est_bytes = gpu.estimate_device_bytes(wl, w)
+        reqs.append(r)
+    srv = serve.Server(reserve_bytes=0)
+    st = srv.run(reqs, time_scale=0.0, log=lambda m: print(m, flush=True))
+    assert st["requests"] == len(spec) and st["dmc_requests"] == 2
+    for r in st["finished"]:
+        print(f"[serve] compare request {r.rid} ({r.kind})", flush=True)
+        s = gpu.System(r.wl)
+        if r.kind == "dmc":
+            s.dmc_init(r.dmc_target, feedback=r.dmc_feedback)
+            out = torch.zeros((r.n_sweeps, 6), dtype=torch.float64, device="cuda")
+            s.dmc_steps(r.n_sweeps, out)
+            e = out.cpu().numpy()
+        else:
+            for _ in range(r.n_sweeps):
+                s.sweep(1)
+                e = s.measure()
+        pos = s.get_walkers()[0]
+        s.close()
+        assert np.array_equal(e, r.energy)
+        assert np.array_equal(pos, r.final_pos)
