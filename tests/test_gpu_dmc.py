@@ -86,6 +86,13 @@ def test_dmc_mixed_precision(gpu, orc):
     _compare(gpu, orc, _drift(wl, 0.08), 48, 32, 12, 0.5, rel=1e-5, pos_tol=1e-7)
 
 
+def test_dmc_with_three_body_jastrow(gpu, orc):
+    """The three-body term enters the drift velocities, the Jastrow change and the local
+    energies that weight the walkers."""
+    wl = qi.solid(24, 12, n_walkers=1, n_sweeps=1, j3=True, j3_strength=50.0)
+    _compare(gpu, orc, _drift(wl, 0.12), 32, 24, 12, 0.5)
+
+
 def test_dmc_in_a_caller_arena(gpu):
     """The population buffers fit an arena sized by qmc_estimate_device_bytes, and the run is
     bit for bit the one with the library's own allocations."""
