@@ -122,6 +122,7 @@ struct qmc_system_s {
   double* ae_logT = nullptr;
   // diffusion Monte Carlo population (allocated by qmc_dmc_init)
   bool dmc_ready = false, fixed_node = false;
+  bool vcur_valid = false;   // drift moves: ae_vcur holds the velocities at the current configuration
   double* dmc_w = nullptr;
   double* dmc_E = nullptr;
   double* dmc_e4 = nullptr;
@@ -356,6 +357,7 @@ void free_walkers(qmc_system s) {
   s->ae_sign = s->ae_status = nullptr;
   s->ae_vcur = s->ae_vprop = s->ae_logT = nullptr;
   s->dmc_ready = s->fixed_node = false;
+  s->vcur_valid = false;
   s->dmc_w = s->dmc_E = s->dmc_e4 = s->dmc_ctl = nullptr;
   s->dmc_i = nullptr;
 }
@@ -831,13 +833,17 @@ namespace {
 // The proposals of one sweep (gather), on stream st.
 qmc_status sweep_gather(qmc_system s, hipStream_t st) {
   hipError_t e;
-  if (s->d.move_kind == QMC_MOVE_ALL_DRIFT) {
+  if (s->d.move_kind == QMC_MOVE_ALL_DRIFT && !s->vcur_valid) {
     // drift velocities at the current configuration, which the proposals are centred on
-    // (timed with the move kernels, so the gather's own time stays separate)
+    // (timed with the move kernels, so the gather's own time stays separate).  Afterwards a
+    // move keeps them current: an accepted walker takes the velocities computed at R' (the
+    // same kernel on the same positions, rows and inverses, so the same bits), a rejected one
+    // keeps its own; DMC copies carry them along.
     e = s->d.precision == QMC_MIXED
             ? timed(s, 1, [&] { return launch_ae_velocity<float>(s->P, walkers_of<float>(s), AeProposal<float>{}, 0, s->ae_vcur, nullptr, st); }, st)
             : timed(s, 1, [&] { return launch_ae_velocity<double>(s->P, walkers_of<double>(s), AeProposal<double>{}, 0, s->ae_vcur, nullptr, st); }, st);
     if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "drift velocity launch: %s", hipGetErrorString(e));
+    s->vcur_valid = true;
   }
   if (s->d.precision == QMC_MIXED)
     e = timed(s, 0, [&] { return launch_gather<float>(s->P, walkers_of<float>(s), static_cast<const float*>(s->d_table), 0, st, s->gather_lanes_log2); }, st);
@@ -862,8 +868,10 @@ hipError_t ae_step(qmc_system s) {
   prop.row_flip = 1;
   e = launch_rebuild<T>(s->P, prop, s->scratch, nullptr, s->stream);
   if (e != hipSuccess) return e;
+  const bool drift = s->d.move_kind == QMC_MOVE_ALL_DRIFT;
   AeProposal<T> A{static_cast<T*>(s->ae_binv), s->ae_logdet, s->ae_sign, s->ae_status, s->ae_dj, s->ae_logT,
-                  velocity_parts(s->P.N), s->fixed_node ? 1 : 0, s->fixed_node ? s->dmc_i : nullptr};
+                  velocity_parts(s->P.N), s->fixed_node ? 1 : 0, s->fixed_node ? s->dmc_i : nullptr,
+                  drift ? s->ae_vprop : nullptr, drift ? s->ae_vcur : nullptr};
   if (s->d.move_kind == QMC_MOVE_ALL_DRIFT) {
     e = launch_ae_velocity<T>(s->P, walkers_of<T>(s), A, 1, s->ae_vprop, s->ae_vcur, s->stream);
     if (e != hipSuccess) return e;
@@ -1013,6 +1021,7 @@ DmcState dmc_state_of(qmc_system s, double* stats) {
   D.ictl = s->dmc_i + 5 * W;
   D.ctl = s->dmc_ctl;
   D.stats = stats;
+  D.vel = s->d.move_kind == QMC_MOVE_ALL_DRIFT ? s->ae_vcur : nullptr;
   return D;
 }
 
@@ -1156,6 +1165,7 @@ qmc_status qmc_recompute(qmc_system s, double* drift_out) {
   HIP_TRY(s, hipMemsetAsync(s->status, 0, (size_t)s->P.W * sizeof(int), s->stream));
   qmc_status st = run_rebuild(s, s->drift);
   if (st != QMC_OK) return st;
+  s->vcur_valid = false;   // (the same bits would come back; recomputed for simplicity)
   if (drift_out)
     HIP_TRY(s, hipMemcpyAsync(drift_out, s->drift, (size_t)s->P.W * 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
   return check_singular(s);

@@ -277,6 +277,8 @@ __global__ __launch_bounds__(kBlock) void k_ae_apply(SysParams P, Walkers<T> Wk,
       Wk.cur[e0 + i] ^= (uint8_t)1;
     }
   }
+  if (acc && A.vcur)   // the velocities at R' are those at the new current configuration
+    for (int q = tid; q < 3 * N; q += kBlock) A.vcur[e0 * 3 + q] = A.vprop[e0 * 3 + q];
   if (acc) {
     // the walker's two inverses (bstride elements); as 16-byte vectors when every walker's
     // block starts on a 16-byte boundary (the buffers themselves are 256-byte aligned)

@@ -169,6 +169,8 @@ __global__ __launch_bounds__(kBlock) void k_dmc_copy(SysParams P, Walkers<T> Wk,
   }
   for (size_t q = tid; q < (size_t)P.bstride; q += kBlock)
     Wk.binv[(size_t)f * P.bstride + q] = Wk.binv[(size_t)src * P.bstride + q];
+  if (D.vel)
+    for (int q = tid; q < 3 * N; q += kBlock) D.vel[f0 * 3 + q] = D.vel[s0 * 3 + q];
   __syncthreads();   // every thread has read the source's row flags
   for (int i = tid; i < N; i += kBlock) Wk.cur[f0 + i] = Wk.cur[s0 + i];
   if (tid < 2) {

@@ -166,6 +166,8 @@ struct AeProposal {
   int logT_parts;
   int fixed_node;   // 1: reject moves that change the sign of Psi (diffusion Monte Carlo)
   int* crossed;     // [W] or null: 1 where the move was rejected for crossing a node
+  const double* vprop;  // [W][N][3] or null: drift velocities at R', which become those at R
+  double* vcur;         //   (vcur) of an accepted walker
 };
 // dj[w] = J(R') - J(R) from pos and the proposals; clears status_prop.
 hipError_t launch_ae_jastrow(const SysParams& P, const double* pos, const double* prop, double* dj,
@@ -194,6 +196,7 @@ struct DmcState {
   double* ctl;      // [2]: E_T, feedback
   int* ictl;        // [3]: step, extinct flag, target population
   double* stats;    // [6] of this step: E, sum w, population, E_T used, dropped copies, crossings
+  double* vel;      // [W][N][3] or null: drift velocities at each slot's configuration (copied along)
 };
 // Weights, estimator, multiplicities, copy plan, new weights and E_T of one DMC step (one
 // workgroup), then the walker states of the copies.
