@@ -401,7 +401,7 @@ WalkerSizes walker_sizes(int n_up, int n_dn, int precision, int W, int n_orb, in
   const bool ae = move_kind == QMC_MOVE_ALL || move_kind == QMC_MOVE_ALL_DRIFT;
   z.ae_binv = ae ? W * bs * ts : 0;
   z.ae_logdet = ae ? W * 2 * sizeof(double) : 0;
-  z.ae_dj = ae ? W * sizeof(double) : 0;
+  z.ae_dj = ae ? W * (size_t)jastrow_parts((int)N) * sizeof(double) : 0;
   z.ae_sign = ae ? W * 2 * sizeof(int) : 0;
   z.ae_status = ae ? W * sizeof(int) : 0;
   const bool drift = move_kind == QMC_MOVE_ALL_DRIFT;
@@ -870,7 +870,8 @@ hipError_t ae_step(qmc_system s) {
   if (e != hipSuccess) return e;
   const bool drift = s->d.move_kind == QMC_MOVE_ALL_DRIFT;
   AeProposal<T> A{static_cast<T*>(s->ae_binv), s->ae_logdet, s->ae_sign, s->ae_status, s->ae_dj, s->ae_logT,
-                  velocity_parts(s->P.N), s->fixed_node ? 1 : 0, s->fixed_node ? s->dmc_i : nullptr,
+                  velocity_parts(s->P.N), jastrow_parts(s->P.N), s->fixed_node ? 1 : 0,
+                  s->fixed_node ? s->dmc_i : nullptr,
                   drift ? s->ae_vprop : nullptr, drift ? s->ae_vcur : nullptr};
   if (s->d.move_kind == QMC_MOVE_ALL_DRIFT) {
     e = launch_ae_velocity<T>(s->P, walkers_of<T>(s), A, 1, s->ae_vprop, s->ae_vcur, s->stream);

@@ -25,8 +25,10 @@ __device__ __forceinline__ double ae_dist(const double* a, const double* b, doub
 
 }  // namespace
 
-// dJ[w] = J(R') - J(R), J = sum_{i<j} u2(r_ij) + sum_{i,I} u1(r_iI) (section "Jastrow
-// factors", minimum image), as the sum of the per-pair changes.  One workgroup per walker.
+// dJ[w] = J(R') - J(R), J = sum_{i<j} u2(r_ij) + sum_{i,I} u1(r_iI) (+ the three-body terms)
+// (section "Jastrow factors", minimum image), as the sum of the per-pair changes.  Workgroup
+// (w, p) of jastrow_parts(N) per walker takes the p-th contiguous share of each item list and
+// writes dj[w * parts + p]; the decision adds the parts in order.
 // The N(N-1)/2 pairs are enumerated as circulant diagonals, pair (i, i + d mod N) for
 // d = 1 .. (N-1)/2 and, for even N, (i, i + N/2) with i < N/2, so the work is balanced
 // over the threads without a triangular index decode.  Also clears status_prop[w], which the
@@ -36,7 +38,9 @@ __global__ __launch_bounds__(kBlock) void k_ae_jastrow(SysParams P, const double
                                                        int* status_prop) {
   __shared__ Jastrow sj;
   __shared__ double red[kWaves];
-  const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int parts = gridDim.x / P.W;
+  const int w = blockIdx.x / parts, p = blockIdx.x - w * parts;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = P.N;
   for (int q = tid; q < (int)(sizeof(Jastrow) / sizeof(double)); q += kBlock)
     reinterpret_cast<double*>(&sj)[q] = reinterpret_cast<const double*>(&P.jas)[q];
@@ -47,7 +51,8 @@ __global__ __launch_bounds__(kBlock) void k_ae_jastrow(SysParams P, const double
   const int D = (N - 1) / 2;
   const int n_pairs = N * D + ((N & 1) ? 0 : N / 2);
   double acc = 0.0;
-  for (int q = tid; q < n_pairs; q += kBlock) {
+  const int q0 = (int)((long)n_pairs * p / parts), q1 = (int)((long)n_pairs * (p + 1) / parts);
+  for (int q = q0 + tid; q < q1; q += kBlock) {
     int i, j;
     if (q < N * D) {
       const int d = 1 + q / N;
@@ -63,8 +68,10 @@ __global__ __launch_bounds__(kBlock) void k_ae_jastrow(SysParams P, const double
     const double r0 = ae_dist(x0 + 3 * i, x0 + 3 * j, L, invL);
     acc += ae_u(sj, kind, r1) - ae_u(sj, kind, r0);
   }
+  const int ne = N * P.n_ions;
+  const int e0 = (int)((long)ne * p / parts), e1 = (int)((long)ne * (p + 1) / parts);
   if (sj.ei.kind != QMC_J_NONE)
-    for (int q = tid; q < N * P.n_ions; q += kBlock) {
+    for (int q = e0 + tid; q < e1; q += kBlock) {
       const int i = q / P.n_ions, I = q - i * P.n_ions;
       const double* ion = P.ions + 4 * I;
       acc += ae_u(sj, 2, ae_dist(x1 + 4 * i, ion, L, invL)) - ae_u(sj, 2, ae_dist(x0 + 3 * i, ion, L, invL));
@@ -72,7 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_ae_jastrow(SysParams P, const double
   if (P.j3_on) {
     // three-body terms: (ion, electron i) items, partners j > i near the same ion
     const double h = P.j3_h;
-    for (int q = tid; q < N * P.n_ions; q += kBlock) {
+    for (int q = e0 + tid; q < e1; q += kBlock) {
       const int I = q / N, i = q - I * N;
       const double* ion = P.ions + 4 * I;
       const double a1 = ae_dist(x1 + 4 * i, ion, L, invL), a0 = ae_dist(x0 + 3 * i, ion, L, invL);
@@ -93,8 +100,8 @@ __global__ __launch_bounds__(kBlock) void k_ae_jastrow(SysParams P, const double
     double s = 0.0;
 #pragma unroll
     for (int q = 0; q < kWaves; ++q) s += red[q];   // fixed order: bitwise repeatable
-    dj[w] = s;
-    status_prop[w] = 0;
+    dj[(size_t)w * parts + p] = s;
+    if (p == 0) status_prop[w] = 0;
   }
 }
 
@@ -263,7 +270,9 @@ __global__ __launch_bounds__(kBlock) void k_ae_apply(SysParams P, Walkers<T> Wk,
     const int crossed = A.fixed_node && A.status[w] == 0 &&
                         A.sign[2 * w] * A.sign[2 * w + 1] != Wk.sign[2 * w] * Wk.sign[2 * w + 1];
     if (A.crossed) A.crossed[w] = crossed;
-    sacc = (A.status[w] == 0) && !crossed && (u < exp(2.0 * (dlog + A.dj[w]) + lt));
+    double dJ = 0.0;
+    for (int q = 0; q < A.dj_parts; ++q) dJ += A.dj[(size_t)w * A.dj_parts + q];
+    sacc = (A.status[w] == 0) && !crossed && (u < exp(2.0 * (dlog + dJ) + lt));
   }
   __syncthreads();
   const int acc = sacc;
@@ -304,10 +313,17 @@ __global__ __launch_bounds__(kBlock) void k_ae_apply(SysParams P, Walkers<T> Wk,
   }
 }
 
+int jastrow_parts(int N) {
+  const long pairs = (long)N * (N - 1) / 2;
+  const long p = (pairs + 2047) / 2048;
+  return (int)(p < 1 ? 1 : (p > 8 ? 8 : p));
+}
+
 hipError_t launch_ae_jastrow(const SysParams& P, const double* pos, const double* prop, double* dj,
                              int* status_prop, hipStream_t st) {
   if (P.W <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ae_jastrow, dim3(P.W), dim3(kBlock), 0, st, P, pos, prop, dj, status_prop);
+  hipLaunchKernelGGL(k_ae_jastrow, dim3((unsigned)P.W * jastrow_parts(P.N)), dim3(kBlock), 0, st, P, pos, prop,
+                     dj, status_prop);
   return hipGetLastError();
 }
 

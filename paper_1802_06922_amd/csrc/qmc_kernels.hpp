@@ -160,16 +160,19 @@ struct AeProposal {
   double* logdet;   // [W][2]: log|D(R')| per spin (NaN when singular)
   int* sign;        // [W][2]
   int* status;      // [W]: nonzero = a singular matrix at R'
-  double* dj;       // [W]: J(R') - J(R)
+  double* dj;       // [W][dj_parts]: partial sums of J(R') - J(R)
   double* logT;     // [W][logT_parts] or null: partial sums of log T(R' -> R) / T(R -> R') of
                     // drift-diffusion proposals, added in order by the decision
   int logT_parts;
+  int dj_parts;
   int fixed_node;   // 1: reject moves that change the sign of Psi (diffusion Monte Carlo)
   int* crossed;     // [W] or null: 1 where the move was rejected for crossing a node
   const double* vprop;  // [W][N][3] or null: drift velocities at R', which become those at R
   double* vcur;         //   (vcur) of an accepted walker
 };
-// dj[w] = J(R') - J(R) from pos and the proposals; clears status_prop.
+// dj[w][jastrow_parts(N)] = partial sums of J(R') - J(R) from pos and the proposals; clears
+// status_prop.
+int jastrow_parts(int N);
 hipError_t launch_ae_jastrow(const SysParams& P, const double* pos, const double* prop, double* dj,
                              int* status_prop, hipStream_t st);
 // Drift velocities grad ln|Psi| of every electron at R (prop = 0) or R' (prop = 1, also
