@@ -395,7 +395,18 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
             // terms below), over the ions within the cutoff of r or r'
             const double h = P.j3_h;
             const int w0 = off + k0, w1 = off + k0 + Kw;
-            for (int I = 0; I < P.n_ions; ++I) {
+            // ions near r' or r, ascending; with at most 64 ions a lane visits only its own
+            uint64_t near = 0;
+            const bool masked = P.n_ions <= 64;
+            if (masked)
+              for (int I = 0; I < P.n_ions; ++I) {
+                const double* ion = ions + 4 * I;
+                if (dist(px, py, pz, ion[0], ion[1], ion[2], L, invL) < h ||
+                    dist(ox, oy, oz, ion[0], ion[1], ion[2], L, invL) < h)
+                  near |= 1ull << I;
+              }
+            for (int I = masked ? (near ? __builtin_ctzll(near) : P.n_ions) : 0; I < P.n_ions;
+                 I = masked ? ((near &= near - 1) ? __builtin_ctzll(near) : P.n_ions) : I + 1) {
               const double* ion = ions + 4 * I;
               const double a1 = dist(px, py, pz, ion[0], ion[1], ion[2], L, invL);
               const double a0 = dist(ox, oy, oz, ion[0], ion[1], ion[2], L, invL);

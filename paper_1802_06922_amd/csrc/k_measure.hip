@@ -217,7 +217,19 @@ __device__ __forceinline__ void measure_part(const SysParams& P, const Walkers<T
       // three-body terms (a = r_iI, c = r_ij at fixed b = r_jI): grad_i u = u_a a^ + u_c c^,
       // lap_i u = u_aa + 2 u_a / a + u_cc + 2 u_c / c + 2 u_ac a^.c^; partners j = part (mod parts)
       const double h = P.j3_h;
-      for (int I = 0; I < P.n_ions; ++I) {
+      // ions near electron i (a < h), ascending; with at most 64 ions a lane visits only its own
+      // near ions instead of every ion some lane of the wave is near
+      uint64_t near = 0;
+      const bool masked = P.n_ions <= 64;
+      if (masked)
+        for (int I = 0; I < P.n_ions; ++I) {
+          const double* ion = P.ions + 4 * (size_t)I;
+          const double ax = min_image(xi - ion[0], P.L, invL), ay = min_image(yi - ion[1], P.L, invL);
+          const double az = min_image(zi - ion[2], P.L, invL);
+          if (sqrt(ax * ax + ay * ay + az * az) < h) near |= 1ull << I;
+        }
+      for (int I = masked ? (near ? __builtin_ctzll(near) : P.n_ions) : 0; I < P.n_ions;
+           I = masked ? ((near &= near - 1) ? __builtin_ctzll(near) : P.n_ions) : I + 1) {
         const double* ion = P.ions + 4 * (size_t)I;
         const double ax = min_image(xi - ion[0], P.L, invL), ay = min_image(yi - ion[1], P.L, invL);
         const double az = min_image(zi - ion[2], P.L, invL);
