@@ -179,9 +179,9 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos);
 /* Run n_sweeps particle-by-particle sweeps of every walker.  Each sweep
  * proposes every electron once, in index order, and accepts with
  * probability min(1, R^2 exp(2 dJ)), R the determinant ratio and dJ the
- * Jastrow change.  With move_kind QMC_MOVE_ALL a sweep is instead one
- * all-electron move per walker (see qmc_system_desc), an accepted walker
- * counting as N accepted electrons.  n_accepted_out (nullable; non-NULL
+ * Jastrow change.  With move_kind QMC_MOVE_ALL or QMC_MOVE_ALL_DRIFT a sweep
+ * is instead one all-electron move per walker (see qmc_system_desc), an
+ * accepted walker counting as N accepted electrons.  n_accepted_out (nullable; non-NULL
  * synchronises): total accepted electron moves over all walkers and these
  * sweeps.  Errors: STATE before init_walkers; DEVICE. */
 qmc_status qmc_sweep(qmc_system s, int32_t n_sweeps, uint64_t* n_accepted_out);
