@@ -1,5 +1,6 @@
 """Host-side checks of the C ABI library (no GPU needed)."""
 import ctypes
+import dataclasses
 import os
 import re
 
@@ -114,3 +115,25 @@ def test_estimate_counts_move_kind_buffers(libqmc):
     drift = qmc.estimate_device_bytes(dataclasses.replace(wl, all_electron=True, drift=True), W)
     assert ae - pbyp >= W * 2 * n * n * 8            # inverses at R'
     assert drift - ae >= 2 * W * N * 3 * 8 + W * 6 * 8   # velocities at R and R', DMC weights and energies
+
+
+def test_served_request_mix_without_gpu(libqmc):
+    """Every k-th served request becomes a DMC run of drift-diffusion all-electron moves whose
+    device-memory estimate includes its population buffers; the others stay VMC runs."""
+    import qmc_inputs as qi
+    from paper_1802_06922_amd import qmc, serve
+    qmc.load_library()
+    trace = qi.served_trace(n_requests=6, rate_per_s=20.0, seed=0)
+    for e in trace:   # keep the host-side table generation small
+        e["n_elec"], e["grid"], e["n_walkers"] = 16, 8, 8
+    reqs = serve.build_requests(trace, sweep_scale=0.01, dmc_every=3)
+    kinds = [r.kind for r in sorted(reqs, key=lambda r: r.rid)]
+    assert kinds == ["vmc", "vmc", "dmc", "vmc", "vmc", "dmc"]
+    for r in reqs:
+        if r.kind == "dmc":
+            assert r.wl.all_electron and r.wl.drift and 1 <= r.dmc_target <= r.wl.n_walkers
+            vmc_like = qmc.estimate_device_bytes(dataclasses.replace(r.wl, all_electron=False, drift=False),
+                                                 r.wl.n_walkers)
+            assert r.est_bytes > vmc_like
+        else:
+            assert not r.wl.all_electron
