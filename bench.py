@@ -13,6 +13,7 @@ this build measures one GPU.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -44,10 +45,19 @@ def describe(wl) -> str:
                                    else f"delay rank {wl.delay_rank}"))
 
 
+def source_hash(files) -> str:
+    """First 16 hex digits of the SHA-256 of the given repository files, in order: the key that
+    ties a committed counter record to the kernel sources it was measured on."""
+    m = hashlib.sha256()
+    for p in files:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            m.update(f.read())
+    return m.hexdigest()[:16]
+
+
 def measured_traffic(wl):
     """HBM bytes per gather launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE runs,
     scaled by a plain copy's counter readings; None once the kernel source has changed."""
-    from paper_1802_06922_amd.profiling import source_hash
     path = os.path.join(ROOT, "profiles", f"gather_traffic_{wl.name}.json")
     if not os.path.exists(path):
         return None
