@@ -52,9 +52,7 @@ def lib():
         L.orc_dmc_run.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int,
                                   dp, dp, ip, ip, dp, dp, ip, C.c_int]
         L.orc_dmc_run.restype = C.c_int
-        L.orc_init_position.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_double, dp]
-        L.orc_fp32_inverse_residual.argtypes = [C.c_int, dp, dp]
-        L.orc_fp32_inverse_residual.restype = C.c_double
+        L.orc_init_position.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_double, dp]
         L.orc_spo_vgl.argtypes = [C.c_void_p, dp, dp, dp, dp]
         L.orc_radial.argtypes = [C.c_void_p, C.c_int, C.c_double, dp]
         L.orc_inverse.argtypes = [C.c_int, dp, dp, dp, ip]
@@ -275,9 +273,9 @@ def branch_uniform(seed, slot, step):
     return lib().orc_branch_uniform(seed, slot, step)
 
 
-def init_position(seed, walker, electron, L, attempt=0):
+def init_position(seed, walker, electron, L):
     r = np.zeros(3)
-    lib().orc_init_position(seed, walker, electron, attempt, L, _dp(r))
+    lib().orc_init_position(seed, walker, electron, L, _dp(r))
     return r
 
 
@@ -319,14 +317,3 @@ def ewald(pos, q, L, kappa=0.0):
 
 def max_threads():
     return lib().orc_max_threads()
-
-
-def fp32_inverse_residual(A, B):
-    """max |I - A fl32(B)| in double (the oracle's acceptance test for initial configurations)."""
-    A = np.ascontiguousarray(A, dtype=np.float64)
-    B = np.ascontiguousarray(B, dtype=np.float64)
-    return lib().orc_fp32_inverse_residual(A.shape[0], _dp(A), _dp(B))
-
-
-INIT_ATTEMPTS = 16
-INIT_RESIDUAL = 1e-5

@@ -72,10 +72,6 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 }
 
 enum { ORC_INIT = 1, ORC_PROPOSE = 2, ORC_ACCEPT = 3, ORC_BRANCH = 4 };
-/* Initial configurations: at most ORC_INIT_ATTEMPTS draws per walker; a draw is kept
- * when the single-precision rounding of its inverses leaves residual <= ORC_INIT_RESIDUAL. */
-#define ORC_INIT_ATTEMPTS 16
-#define ORC_INIT_RESIDUAL 1e-5
 
 /* Two uniforms in [0,1) with 53 random bits each, from one Philox block.
  * counter = (electron, sweep, walker, purpose << 16 | sub), key = seed. */
@@ -121,15 +117,13 @@ double orc_branch_uniform(uint64_t seed, uint32_t slot, uint32_t step)
     return u[0];
 }
 
-/* Uniform position in the cell from the INIT stream; attempt (in the counter's sweep slot)
- * numbers the redraws of a walker whose first configuration is rejected (see
- * orc_vmc_run). */
-void orc_init_position(uint64_t seed, uint32_t walker, uint32_t electron, uint32_t attempt, double L,
-                       double r[3])
+/* Uniform position of an electron in the cell (the starting distribution of a walker) from
+ * the INIT stream of (walker, electron); the counter's sweep slot is 0. */
+void orc_init_position(uint64_t seed, uint32_t walker, uint32_t electron, double L, double r[3])
 {
     double a[2], b[2];
-    orc_uniform2(seed, ORC_INIT, 0, walker, attempt, electron, a);
-    orc_uniform2(seed, ORC_INIT, 1, walker, attempt, electron, b);
+    orc_uniform2(seed, ORC_INIT, 0, walker, 0u, electron, a);
+    orc_uniform2(seed, ORC_INIT, 1, walker, 0u, electron, b);
     r[0] = L * a[0];
     r[1] = L * a[1];
     r[2] = L * b[0];
@@ -752,21 +746,6 @@ static int orc_walker_rebuild(const orc_system* s, orc_walker* w)
     return bad;
 }
 
-/* max_{i,k} |delta_ik - sum_l A[i][l] fl32(B[l][k])|: how far the inverse rounded to
- * single precision is from inverting A (computed in double). */
-double orc_fp32_inverse_residual(int n, const double* A, const double* B)
-{
-    double worst = 0.0;
-    for (int i = 0; i < n; ++i)
-        for (int k = 0; k < n; ++k) {
-            double acc = 0.0;
-            for (int l = 0; l < n; ++l) acc += A[i * n + l] * (double)(float)B[l * n + k];
-            const double e = fabs((i == k ? 1.0 : 0.0) - acc);
-            if (e > worst) worst = e;
-        }
-    return worst;
-}
-
 /* log|Psi| with everything recomputed from scratch (for finite differences). */
 double orc_log_psi(const orc_system* s, const double* pos, int* sign)
 {
@@ -996,31 +975,17 @@ static int orc_ae_step(const orc_system* s, orc_walker* w, uint32_t walker_id, u
  * Returns 0, or 1 + walker index of the first walker whose Slater matrix
  * was singular at initialisation.
  */
-/* Initial configuration of walker wid: the given positions (wrapped), or uniform draws
- * from the INIT stream, redrawn while a Slater matrix is singular or too badly conditioned
- * for its inverse to survive rounding to single precision.  Returns nonzero if singular. */
+/* Initial configuration of walker wid: the given positions (wrapped), or uniform draws in
+ * the cell from the INIT stream.  Returns nonzero if a Slater matrix is singular. */
 static int orc_walker_init(const orc_system* s, orc_walker* w, uint32_t wid, const double* pos)
 {
     const int N = s->n_up + s->n_dn;
     if (pos) {
         for (int i = 0; i < 3 * N; ++i) w->pos[i] = orc_wrap(pos[i], s->L);
-        return orc_walker_rebuild(s, w);
+    } else {
+        for (int i = 0; i < N; ++i) orc_init_position(s->seed, wid, (uint32_t)i, s->L, w->pos + 3 * i);
     }
-    int bad = 0;
-    for (uint32_t att = 0;; ++att) {
-        for (int i = 0; i < N; ++i) orc_init_position(s->seed, wid, (uint32_t)i, att, s->L, w->pos + 3 * i);
-        bad = orc_walker_rebuild(s, w);
-        double res = 0.0;
-        for (int sp = 0; sp < 2 && !bad; ++sp) {
-            const int n = orc_spin_count(s, sp);
-            if (n > 0) {
-                const double r = orc_fp32_inverse_residual(n, w->A[sp], w->B[sp]);
-                if (r > res) res = r;
-            }
-        }
-        if ((!bad && res <= ORC_INIT_RESIDUAL) || att + 1 >= ORC_INIT_ATTEMPTS) break;
-    }
-    return bad;
+    return orc_walker_rebuild(s, w);
 }
 
 int orc_vmc_run(const orc_system* s, int n_walk, const int32_t* walker_ids, const double* init_pos,
