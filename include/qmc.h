@@ -258,6 +258,19 @@ qmc_status qmc_get_accept_log(qmc_system s, uint8_t* bits);
  * from an FP64 ratio; sweeps = sweeps run.  Synchronises. */
 qmc_status qmc_get_counters(qmc_system s, uint64_t* redecided, uint64_t* sweeps);
 
+/* Mixed precision, particle-by-particle moves: how the FP32 path keeps the FP64 decisions.
+ * Every walker's inverse error ||I - A B||_F is measured after each full rebuild and by
+ * the refinement before each measurement (A the FP64 Slater matrix); it widens that
+ * walker's re-decision band (see tie_guard).  A walker whose measured error passes 2e-4 is
+ * rebuilt in FP64 on its own; one whose freshly rounded FP32 inverse still errs by more
+ * than 2e-4 (an ill-conditioned Slater matrix) runs its moves and its kinetic energy in
+ * FP64 (fallback) until the error of its FP32 rounding drops below 5e-5.  Counters since
+ * qmc_init_walkers (each nullable): early_rebuilds = single-walker FP64 rebuilds;
+ * fallback_sweeps = walker sweeps run in FP64; fallback_now = walkers in fallback now;
+ * fallback_mask = host [W], 1 for those walkers.  Zero for other systems.  Synchronises. */
+qmc_status qmc_get_precision_stats(qmc_system s, uint64_t* early_rebuilds, uint64_t* fallback_sweeps,
+                                   int32_t* fallback_now, int32_t* fallback_mask);
+
 /* Rebuild every inverse from scratch in FP64 and reset log|D|.  drift_out
  * (nullable, host [W][2]): accumulated log|D| minus the rebuilt one. */
 qmc_status qmc_recompute(qmc_system s, double* drift_out);

@@ -108,6 +108,13 @@ struct qmc_system_s {
   int* status = nullptr;
   double* val64 = nullptr;
   void* xinv = nullptr;      // FP64-refined inverse read by the measurement (mixed precision)
+  // mixed precision, particle-by-particle moves: FP64 fallback of ill-conditioned walkers
+  double* binv64 = nullptr;
+  int* fb = nullptr;
+  double* eta = nullptr;
+  uint32_t* eta_age = nullptr;
+  uint32_t* pstat = nullptr;
+  uint32_t* fbmark = nullptr;
   int gather_lanes_log2 = -1;   // lanes per proposal in the gather (log2); -1 = default
   uint32_t* nguard = nullptr;
   uint32_t* sweep_ctr = nullptr;
@@ -167,8 +174,35 @@ Walkers<T> walkers_of(qmc_system s) {
   w.xinv = static_cast<T*>(s->xinv);
   w.row_flip = 0;
   w.drift_v = s->d.move_kind == QMC_MOVE_ALL_DRIFT ? s->ae_vcur : nullptr;
+  w.vstride = kComp * s->P.S;
+  w.binv64 = s->binv64;
+  w.fb = s->fb;
+  w.fb_sel = 0;
+  w.eta = s->eta;
+  w.eta_age = s->eta_age;
+  w.pstat = s->pstat;
+  w.table = static_cast<const T*>(s->d_table);
   return w;
 }
+
+// The FP64 view of a mixed system's fallback walkers: the chain runs on the FP64 value rows
+// and the FP64 inverses of the walkers with fb[w] = 1.
+Walkers<double> fallback_of(qmc_system s) {
+  Walkers<double> w = walkers_of<double>(s);
+  w.vgl = s->val64;
+  w.vstride = s->P.S;
+  w.binv = s->binv64;
+  w.val64 = nullptr;
+  w.xinv = nullptr;
+  w.binv64 = nullptr;
+  w.fb_sel = 1;
+  w.eta = nullptr;
+  w.eta_age = nullptr;
+  w.table = nullptr;
+  return w;
+}
+
+bool uses_fallback(qmc_system s) { return s->d.precision == QMC_MIXED && s->d.move_kind == QMC_MOVE_PBYP; }
 
 // Event-bracketed launch: f() issues the kernel on s->stream.
 template <typename F>
@@ -350,6 +384,9 @@ void free_walkers(qmc_system s) {
   s->nacc = nullptr;
   s->val64 = nullptr;
   s->xinv = nullptr;
+  s->binv64 = s->eta = nullptr;
+  s->fb = nullptr;
+  s->eta_age = s->pstat = s->fbmark = nullptr;
   s->nguard = nullptr;
   s->sweep_ctr = nullptr;
   s->ae_binv = nullptr;
@@ -364,12 +401,16 @@ void free_walkers(qmc_system s) {
 
 struct WalkerSizes {
   size_t pos, prop, vgl, cur, binv, logdet, sign, acc, nacc, status, scratch, drift, energy, val64, nguard, sweep,
-      xinv, ae_binv, ae_logdet, ae_dj, ae_sign, ae_status, ae_vel, ae_logT, dmc;
+      xinv, binv64, fb, eta, eta_age, pstat, fbmark, ae_binv, ae_logdet, ae_dj, ae_sign, ae_status, ae_vel, ae_logT,
+      dmc;
   size_t total() const {
     return align_up(pos) + align_up(prop) + align_up(vgl) + align_up(cur) + align_up(binv) +
            align_up(logdet) + align_up(sign) + align_up(acc) + align_up(nacc) + align_up(status) +
            align_up(scratch) + align_up(drift) + align_up(energy) + align_up(val64) + align_up(nguard) +
            align_up(sweep) + align_up(xinv) +
+           (binv64 ? align_up(binv64) + align_up(fb) + align_up(eta) + align_up(eta_age) + align_up(pstat) +
+                         align_up(fbmark)
+                   : 0) +
            (ae_binv ? align_up(ae_binv) + align_up(ae_logdet) + align_up(ae_dj) + align_up(ae_sign) +
                           align_up(ae_status)
                     : 0) +
@@ -396,6 +437,13 @@ WalkerSizes walker_sizes(int n_up, int n_dn, int precision, int W, int n_orb, in
   z.energy = W * (4 + kMaxMeasureParts * 5) * sizeof(double);   // energies, then measurement partials
   z.val64 = precision == QMC_MIXED ? 2 * W * N * S * sizeof(double) : 0;
   z.xinv = precision == QMC_MIXED ? W * bs * ts : 0;
+  const bool fbk = precision == QMC_MIXED && move_kind == QMC_MOVE_PBYP;   // FP64 fallback state
+  z.binv64 = fbk ? W * bs * sizeof(double) : 0;
+  z.fb = fbk ? W * sizeof(int) : 0;
+  z.eta = fbk ? W * 4 * sizeof(double) : 0;
+  z.eta_age = fbk ? W * sizeof(uint32_t) : 0;
+  z.pstat = fbk ? W * 2 * sizeof(uint32_t) : 0;
+  z.fbmark = fbk ? W * sizeof(uint32_t) : 0;
   z.nguard = W * sizeof(uint32_t);
   z.sweep = sizeof(uint32_t);
   const bool ae = move_kind == QMC_MOVE_ALL || move_kind == QMC_MOVE_ALL_DRIFT;
@@ -716,6 +764,31 @@ static qmc_status run_rebuild(qmc_system s, double* drift_dev, const uint32_t* s
   return QMC_OK;
 }
 
+// Mixed precision: the check of the walkers' inverses (FP64 fallback or early FP64 rebuild),
+// on stream st.  after_rebuild: every walker was just rebuilt in FP64 (check all of them);
+// otherwise a refinement has just measured every FP32 walker's inverse error: walkers past
+// kEtaRebuild are rebuilt, fallback walkers are checked, and walkers back in FP32 are refined.
+static hipError_t fallback_check(qmc_system s, hipStream_t st, bool after_rebuild) {
+  if (!uses_fallback(s)) return hipSuccess;
+  const Walkers<float> wk = walkers_of<float>(s);
+  hipError_t e = launch_fb_mark(s->P.W, s->eta, s->fb, s->fbmark, after_rebuild ? 1 : 0, st);
+  if (e == hipSuccess && !after_rebuild) e = launch_rebuild<float>(s->P, wk, s->scratch, nullptr, st, s->fbmark, 1u);
+  if (e == hipSuccess) e = launch_fb_residual(s->P, wk, s->fbmark, st);
+  if (e == hipSuccess) e = launch_fb_decide(s->P, wk, s->fbmark, after_rebuild ? 0 : 1, st);
+  if (e == hipSuccess && !after_rebuild) e = launch_refine<float>(s->P, wk, s->scratch, st, s->fbmark, 3u);
+  return e;
+}
+
+// Mixed precision: the sweep of the FP64 fallback walkers (the FP32 chain skipped them), in
+// FP64 on their FP64 value rows and inverses; any delay rank gives the same decisions.
+static hipError_t fallback_chain(qmc_system s, hipStream_t st) {
+  if (!uses_fallback(s)) return hipSuccess;
+  const Walkers<double> fw = fallback_of(s);
+  int K = s->d.delay_rank >= 4 ? std::min(s->d.delay_rank, 16) : 1;
+  while (K >= 4 && !delayed_feasible(s->P, sizeof(double), K)) K >>= 1;
+  return K >= 4 ? launch_chain_delayed<double>(s->P, fw, K, s->use_mfma, st) : launch_chain<double>(s->P, fw, st);
+}
+
 static qmc_status check_singular(qmc_system s) {
   std::vector<int> st(s->P.W);
   HIP_TRY(s, hipMemcpyAsync(st.data(), s->status, st.size() * sizeof(int), hipMemcpyDeviceToHost, s->stream));
@@ -752,6 +825,14 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
     s->val64 = static_cast<double*>(s->mem.alloc(z.val64));
     s->xinv = s->mem.alloc(z.xinv);
   }
+  if (z.binv64) {
+    s->binv64 = static_cast<double*>(s->mem.alloc(z.binv64));
+    s->fb = static_cast<int*>(s->mem.alloc(z.fb));
+    s->eta = static_cast<double*>(s->mem.alloc(z.eta));
+    s->eta_age = static_cast<uint32_t*>(s->mem.alloc(z.eta_age));
+    s->pstat = static_cast<uint32_t*>(s->mem.alloc(z.pstat));
+    s->fbmark = static_cast<uint32_t*>(s->mem.alloc(z.fbmark));
+  }
   const bool ae = s->d.move_kind != QMC_MOVE_PBYP;
   const bool drift = s->d.move_kind == QMC_MOVE_ALL_DRIFT;
   if (drift) {
@@ -769,6 +850,7 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
   if (!s->pos || !s->prop || !s->vgl || !s->cur || !s->binv || !s->logdet || !s->sign || !s->acc ||
       !s->nacc || !s->status || !s->scratch || !s->drift || !s->energy || !s->nguard || !s->sweep_ctr ||
       (s->d.precision == QMC_MIXED && (!s->val64 || !s->xinv)) ||
+      (z.binv64 && (!s->binv64 || !s->fb || !s->eta || !s->eta_age || !s->pstat || !s->fbmark)) ||
       (ae && (!s->ae_binv || !s->ae_logdet || !s->ae_dj || !s->ae_sign || !s->ae_status)) ||
       (drift && (!s->ae_vcur || !s->ae_vprop || !s->ae_logT))) {
     free_walkers(s);
@@ -789,37 +871,25 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
   HIP_TRY(s, hipMemsetAsync(s->nguard, 0, z.nguard, s->stream));
   HIP_TRY(s, hipMemsetAsync(s->sweep_ctr, 0, z.sweep, s->stream));
   HIP_TRY(s, hipMemsetAsync(s->acc, 0, z.acc, s->stream));
-  // Rows, inverses and log|D| of the current positions.  Positions drawn here are uniform in
-  // the cell; a walker's draw is redrawn (next attempt of its INIT counter) while one of its
-  // Slater matrices is singular or so badly conditioned that the single-precision rounding of
-  // its inverse leaves a residual above kInitResidual, at most kInitAttempts draws.  The
-  // attempt numbers live in nacc and the residuals in drift until the first sweep.  A walker
-  // is drawn in round r exactly when its attempt number is r, so every round draws, evaluates,
-  // rebuilds and checks only those walkers, and the decision is taken on the device: all
-  // rounds are queued without waiting for the host (rounds with nobody left are empty).
-  uint32_t* d_attempt = s->nacc;
   HIP_TRY(s, hipMemsetAsync(s->logdet, 0, z.logdet, s->stream));
-  if (!pos) HIP_TRY(s, hipMemsetAsync(d_attempt, 0, W * sizeof(uint32_t), s->stream));
-  const int rounds = pos ? 1 : kInitAttempts;
-  for (int round = 0; round < rounds; ++round) {
-    const uint32_t* sel = pos ? nullptr : d_attempt;
-    if (!pos) HIP_TRY(s, launch_init_positions(s->P, s->pos, d_attempt, s->stream, round));
-    HIP_TRY(s, hipMemsetAsync(s->status, 0, z.status, s->stream));
-    hipError_t e;
-    if (s->d.precision == QMC_MIXED)
-      e = timed(s, 0, [&] { return launch_gather<float>(s->P, walkers_of<float>(s), static_cast<const float*>(s->d_table), 1, s->stream, -1, sel, (uint32_t)round); });
-    else
-      e = timed(s, 0, [&] { return launch_gather<double>(s->P, walkers_of<double>(s), static_cast<const double*>(s->d_table), 1, s->stream, -1, sel, (uint32_t)round); });
-    if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "orbital gather launch: %s", hipGetErrorString(e));
-    qmc_status st = run_rebuild(s, nullptr, sel, (uint32_t)round);
-    if (st != QMC_OK) return st;
-    if (pos) break;
-    e = s->d.precision == QMC_MIXED
-            ? launch_inverse_residual<float>(s->P, walkers_of<float>(s), s->drift, s->stream, sel, (uint32_t)round)
-            : launch_inverse_residual<double>(s->P, walkers_of<double>(s), s->drift, s->stream, sel, (uint32_t)round);
-    if (e == hipSuccess) e = launch_init_decide(W, s->drift, s->status, d_attempt, round, s->stream);
-    if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "residual launch: %s", hipGetErrorString(e));
+  HIP_TRY(s, hipMemsetAsync(s->status, 0, z.status, s->stream));
+  if (z.binv64) {
+    HIP_TRY(s, hipMemsetAsync(s->fb, 0, z.fb, s->stream));
+    HIP_TRY(s, hipMemsetAsync(s->pstat, 0, z.pstat, s->stream));
   }
+  // Without given positions every electron starts uniform in the cell (INIT stream).  Then the
+  // rows, inverses and log|D| of the current positions.
+  if (!pos) HIP_TRY(s, launch_init_positions(s->P, s->pos, s->stream));
+  hipError_t e;
+  if (s->d.precision == QMC_MIXED)
+    e = timed(s, 0, [&] { return launch_gather<float>(s->P, walkers_of<float>(s), static_cast<const float*>(s->d_table), 1, s->stream); });
+  else
+    e = timed(s, 0, [&] { return launch_gather<double>(s->P, walkers_of<double>(s), static_cast<const double*>(s->d_table), 1, s->stream); });
+  if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "orbital gather launch: %s", hipGetErrorString(e));
+  qmc_status rst = run_rebuild(s, nullptr);
+  if (rst != QMC_OK) return rst;
+  e = fallback_check(s, s->stream, true);
+  if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "inverse check launch: %s", hipGetErrorString(e));
   qmc_status st = check_singular(s);
   s->sweep_index = 0;
   s->has_walkers = (st == QMC_OK);
@@ -894,8 +964,9 @@ qmc_status sweep_chain(qmc_system s) {
   hipError_t e;
   if (s->d.precision == QMC_MIXED)
     e = timed(s, 1, [&] {
-      return K > 1 ? launch_chain_delayed<float>(s->P, walkers_of<float>(s), K, mfma, s->stream)
-                   : launch_chain<float>(s->P, walkers_of<float>(s), s->stream);
+      const hipError_t e1 = K > 1 ? launch_chain_delayed<float>(s->P, walkers_of<float>(s), K, mfma, s->stream)
+                                  : launch_chain<float>(s->P, walkers_of<float>(s), s->stream);
+      return e1 != hipSuccess ? e1 : fallback_chain(s, s->stream);
     });
   else
     e = timed(s, 1, [&] {
@@ -907,6 +978,8 @@ qmc_status sweep_chain(qmc_system s) {
   if (s->d.recompute_period > 0 && s->sweep_index % (uint32_t)s->d.recompute_period == 0) {
     qmc_status st = run_rebuild(s, nullptr);
     if (st != QMC_OK) return st;
+    e = fallback_check(s, s->stream, true);
+    if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "inverse check launch: %s", hipGetErrorString(e));
   }
   return QMC_OK;
 }
@@ -916,7 +989,8 @@ qmc_status measure_on(qmc_system s, double* dst, hipStream_t st) {
   hipError_t e;
   if (s->d.precision == QMC_MIXED)
     e = timed(s, 2, [&] {
-      const hipError_t er = launch_refine<float>(s->P, walkers_of<float>(s), s->scratch, st);
+      hipError_t er = launch_refine<float>(s->P, walkers_of<float>(s), s->scratch, st);
+      if (er == hipSuccess) er = fallback_check(s, st, false);
       return er != hipSuccess ? er
                               : launch_measure<float>(s->P, walkers_of<float>(s), s->E, s->energy + 4 * (size_t)s->P.W,
                                                       dst, st);
@@ -1159,6 +1233,33 @@ qmc_status qmc_get_counters(qmc_system s, uint64_t* redecided, uint64_t* sweeps)
   return QMC_OK;
 }
 
+qmc_status qmc_get_precision_stats(qmc_system s, uint64_t* early_rebuilds, uint64_t* fallback_sweeps,
+                                   int32_t* fallback_now, int32_t* fallback_mask) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (!s->has_walkers) return fail(s, QMC_ERR_STATE, "init_walkers first");
+  HIP_TRY(s, hipSetDevice(s->device));
+  const int W = s->P.W;
+  std::vector<uint32_t> ps(2 * (size_t)W, 0u);
+  std::vector<int> fb(W, 0);
+  if (uses_fallback(s)) {
+    HIP_TRY(s, hipMemcpyAsync(ps.data(), s->pstat, ps.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipMemcpyAsync(fb.data(), s->fb, fb.size() * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+  }
+  uint64_t rb = 0, fs = 0;
+  int32_t now = 0;
+  for (int w = 0; w < W; ++w) {
+    rb += ps[2 * (size_t)w];
+    fs += ps[2 * (size_t)w + 1];
+    now += fb[w] ? 1 : 0;
+    if (fallback_mask) fallback_mask[w] = fb[w] ? 1 : 0;
+  }
+  if (early_rebuilds) *early_rebuilds = rb;
+  if (fallback_sweeps) *fallback_sweeps = fs;
+  if (fallback_now) *fallback_now = now;
+  return QMC_OK;
+}
+
 qmc_status qmc_recompute(qmc_system s, double* drift_out) {
   if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
   if (!s->has_walkers) return fail(s, QMC_ERR_STATE, "init_walkers first");
@@ -1166,6 +1267,8 @@ qmc_status qmc_recompute(qmc_system s, double* drift_out) {
   HIP_TRY(s, hipMemsetAsync(s->status, 0, (size_t)s->P.W * sizeof(int), s->stream));
   qmc_status st = run_rebuild(s, s->drift);
   if (st != QMC_OK) return st;
+  const hipError_t e = fallback_check(s, s->stream, true);
+  if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "inverse check launch: %s", hipGetErrorString(e));
   s->vcur_valid = false;   // (the same bits would come back; recomputed for simplicity)
   if (drift_out)
     HIP_TRY(s, hipMemcpyAsync(drift_out, s->drift, (size_t)s->P.W * 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
@@ -1473,9 +1576,13 @@ hipError_t batch_launch(qmc_batch b, int sweep, int measure) {
       e = launch_chain_delayed_batched<T>(sd, b->clmap, b->n_cl, true, b->use_mfma, b->lds_cl, b->stream);
     if (e == hipSuccess)
       e = launch_chain_delayed_batched<T>(sd, b->cgmap, b->n_cg, false, b->use_mfma, b->lds_cg, b->stream);
+    // mixed precision: each member's FP64 fallback walkers (the fused chains skipped them)
+    for (size_t i = 0; e == hipSuccess && i < b->sys.size(); ++i) e = fallback_chain(b->sys[i], b->stream);
   }
-  if (e == hipSuccess && measure && b->precision == QMC_MIXED)
+  if (e == hipSuccess && measure && b->precision == QMC_MIXED) {
     e = launch_refine_batched<float>(reinterpret_cast<const SysDev<float>*>(sd), b->fmap, b->n_f, b->stream);
+    for (size_t i = 0; e == hipSuccess && i < b->sys.size(); ++i) e = fallback_check(b->sys[i], b->stream, false);
+  }
   if (e == hipSuccess && measure) e = launch_measure_batched<T>(sd, b->mmap, b->n_m, b->fmap, b->n_f, b->lds_m, b->stream);
   return e;
 }
@@ -1599,9 +1706,10 @@ qmc_status qmc_batch_sweep(qmc_batch b, int32_t n_sweeps, int32_t measure) {
     for (qmc_system s : b->sys) {
       s->sweep_index += 1;
       if (s->d.recompute_period > 0 && s->sweep_index % (uint32_t)s->d.recompute_period == 0) {
-        const hipError_t e = s->d.precision == QMC_MIXED
+        hipError_t e = s->d.precision == QMC_MIXED
             ? launch_rebuild<float>(s->P, walkers_of<float>(s), s->scratch, nullptr, b->stream)
             : launch_rebuild<double>(s->P, walkers_of<double>(s), s->scratch, nullptr, b->stream);
+        if (e == hipSuccess) e = fallback_check(s, b->stream, true);
         if (e != hipSuccess) return bfail(b, QMC_ERR_DEVICE, "rebuild launch: %s", hipGetErrorString(e));
       }
     }

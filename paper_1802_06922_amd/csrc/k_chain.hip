@@ -37,7 +37,7 @@ __host__ __device__ inline ChainLayout chain_layout(int N, int nmax, int n_ions,
   L.pos = o; o += sizeof(double) * 3 * N;
   L.prop = o; o += sizeof(double) * 4 * nmax;
   L.ions = o; o += (n_ions <= kLdsIons) ? sizeof(double) * 4 * n_ions : 0;
-  L.red = o; o += sizeof(double) * 7 * kWaves;
+  L.red = o; o += sizeof(double) * 9 * kWaves;
   o = (o + 15) & ~size_t(15);
   L.vbuf = o; o += ts * (size_t)2 * rows_per_chunk * nmax;
   o = (o + 15) & ~size_t(15);
@@ -79,6 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, in
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ Jastrow sj;
   const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (chain_skips(Wk, w)) return;
   const int N = P.N, nmax = P.n_up > P.n_dn ? P.n_up : P.n_dn;
   const ChainLayout lay = chain_layout(N, nmax, P.n_ions, ldl, sizeof(T), BLDS, C);
   double* spos = reinterpret_cast<double*>(smem + lay.pos);
@@ -143,7 +144,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, in
       for (int r = 0; r < C; ++r) {
         const int kk = c0 + r;
         if (kk < n) {
-          const T* vrow = Wk.vgl + ((size_t)(1 - scur[kk]) * P.W * N + item0 + kk) * kComp * P.S;
+          const T* vrow = Wk.vgl + ((size_t)(1 - scur[kk]) * P.W * N + item0 + kk) * Wk.vstride;
 #pragma unroll
           for (int c = 0; c < VPT; ++c) {
             const int j = tid + c * kBlock;
@@ -174,13 +175,17 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, in
       // determinant ratio (partial sums over this thread's own row elements)
       T rpart = T(0);
       double mpart = 0.0;   // mixed: sum |v_j B[j][k]|, the magnitude that bounds R's rounding
+      double vpart = 0.0;   // mixed: |v|^2 (with ||B||_F it bounds ||v^T B||)
 #pragma unroll
       for (int c = 0; c < VPT; ++c) {
         const int j = tid + c * kBlock;
         if (j < n) {
           const T vb = vrow_l[j] * Bm[(size_t)j * ldb + k];
           rpart += vb;
-          if (sizeof(T) == 4) mpart += fabs((double)vb);
+          if (sizeof(T) == 4) {
+            mpart += fabs((double)vb);
+            vpart += (double)vrow_l[j] * (double)vrow_l[j];
+          }
         }
       }
       // Jastrow change (partial sums)
@@ -232,12 +237,17 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, in
       // block reduction in a fixed order (bitwise repeatable)
       const double ra = wave_sum_dpp((double)rpart), rb = wave_sum_dpp(dj);
       const double rm = sizeof(T) == 4 ? wave_sum_dpp(mpart) : 0.0;
-      double* rr = red + parity * 3 * kWaves;
-      if (lane == 0) { rr[wave] = ra; rr[kWaves + wave] = rb; rr[2 * kWaves + wave] = rm; }
+      const double rv = sizeof(T) == 4 ? wave_sum_dpp(vpart) : 0.0;
+      double* rr = red + parity * 4 * kWaves;
+      if (lane == 0) {
+        rr[wave] = ra; rr[kWaves + wave] = rb; rr[2 * kWaves + wave] = rm; rr[3 * kWaves + wave] = rv;
+      }
       block_sync<BLDS>();
-      double Rd = 0.0, dJ = 0.0, Sm = 0.0;
+      double Rd = 0.0, dJ = 0.0, Sm = 0.0, V2 = 0.0;
 #pragma unroll
-      for (int q = 0; q < kWaves; ++q) { Rd += rr[q]; dJ += rr[kWaves + q]; Sm += rr[2 * kWaves + q]; }
+      for (int q = 0; q < kWaves; ++q) {
+        Rd += rr[q]; dJ += rr[kWaves + q]; Sm += rr[2 * kWaves + q]; V2 += rr[3 * kWaves + q];
+      }
       parity ^= 1;
       const T R = (T)Rd;
       const double ej = exp(2.0 * dJ);
@@ -245,14 +255,16 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, in
       double Rlog = (double)R;
       bool accept;
       // guard band: the relative tie guard widened by a bound on the FP32 rounding of R
-      // (n + 1 unit roundoffs of the magnitude of its terms): heavy cancellation re-decides
+      // (n + 1 unit roundoffs of the magnitude of its terms: heavy cancellation re-decides) and
+      // by the error of the inverse itself, ||v^T B|| <= |v| ||B||_F times its measured residual
       const double band = sizeof(T) == 4
-          ? P.tie_guard + 2.0 * (n + 1) * 5.9604644775390625e-08 * Sm / fabs((double)R) + 2.4e-7
+          ? P.tie_guard + 2.0 * (n + 1) * 5.9604644775390625e-08 * Sm / fabs((double)R) + 2.4e-7 +
+                inverse_error_term(Wk, w, sp, n, sqrt(V2) * (Wk.eta ? Wk.eta[4 * w + 2 + sp] : 0.0), (double)R)
           : 0.0;
       if (sizeof(T) == 4 && fabs(u - p32) <= band * p32) {
         // near tie in FP32: decide again with an FP64 ratio (uniform branch)
         const double* v64 = Wk.val64 + ((size_t)(1 - scur[k]) * P.W * N + item0 + k) * P.S;
-        Rlog = refined_ratio<T>(P, Wk, Bm, ldb, n, item0, scur, v64, k, sgx, sgr, red + 2 * 3 * kWaves, tid);
+        Rlog = refined_ratio<T>(P, Wk, Bm, ldb, n, item0, scur, v64, k, sgx, sgr, red + 8 * kWaves, tid);
         accept = u < Rlog * Rlog * ej;
         ++nguard;
       } else {
@@ -311,6 +323,8 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, in
   if (tid == 0) {
     Wk.nacc[w] = nacc;
     Wk.nguard[w] += nguard;
+    if (Wk.eta_age) Wk.eta_age[w] += 1u;
+    if (Wk.fb && Wk.fb_sel == 1) Wk.pstat[2 * w + 1] += 1u;
     if (w == 0) *Wk.sweep_ctr += 1u;   // read by the next sweep's gather
   }
 }

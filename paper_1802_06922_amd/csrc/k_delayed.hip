@@ -39,7 +39,7 @@ constexpr int kMaxWindow = 64;
 constexpr int kLdsIonsD = 256;
 
 struct DLayout {
-  size_t pos, prop, ions, red, rmag, gold, gdiff, cur, acc, plist, qlist, vwin, ywin, zwin, gx, gr, grow, b,
+  size_t pos, prop, ions, red, rmag, tn, gold, gdiff, cur, acc, plist, qlist, vwin, ywin, zwin, gx, gr, grow, b,
       total;
 };
 
@@ -56,6 +56,7 @@ __host__ __device__ inline DLayout dlayout(int N, int nmax, int n_ions, int ldl,
   L.ions = o; o += (n_ions <= kLdsIonsD) ? sizeof(double) * 4 * n_ions : 0;
   L.red = o; o += sizeof(double) * kBlock;
   L.rmag = o; o += (ts == 4) ? sizeof(double) * kBlock : 0;   // mixed: |v| . |B0[:, k]| partials
+  L.tn = o; o += (ts == 4) ? sizeof(double) * kBlock : 0;     // mixed: |v^T B0|^2 partials
   // gold's storage later holds the window block yk with rows of K + 1 (bank spread) and
   // up to 7 entries read past its last row
   L.gold = o; o += sizeof(double) * ((size_t)K * (K + 1) + 8);
@@ -290,6 +291,7 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
   __shared__ int sm_m, sm_stop;
   __shared__ double sm_dj;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (chain_skips(Wk, w)) return;
   const int N = P.N, nmax = P.n_up > P.n_dn ? P.n_up : P.n_dn, nP = round16(nmax);
   const DLayout lay = dlayout(N, nmax, P.n_ions, ldl, sizeof(T), BLDS, K);
   double* spos = reinterpret_cast<double*>(smem + lay.pos);
@@ -299,6 +301,7 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
   const double* ions = ions_lds ? sion : P.ions;
   double* red = reinterpret_cast<double*>(smem + lay.red);
   double* rmag = reinterpret_cast<double*>(smem + lay.rmag);
+  double* tnp = reinterpret_cast<double*>(smem + lay.tn);
   double* gold = reinterpret_cast<double*>(smem + lay.gold);
   double* gdiff = reinterpret_cast<double*>(smem + lay.gdiff);
   uint8_t* scur = smem + lay.cur;
@@ -365,7 +368,7 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
       for (int idx = tid; idx < Kw * n; idx += kBlock) {
         const int q = idx / n, l = idx - q * n;
         const size_t it = item0 + k0 + q;
-        vwin[(size_t)q * nP + l] = Wk.vgl[((size_t)(1 - scur[k0 + q]) * P.W * N + it) * kComp * P.S + l];
+        vwin[(size_t)q * nP + l] = Wk.vgl[((size_t)(1 - scur[k0 + q]) * P.W * N + it) * Wk.vstride + l];
       }
       __syncthreads();
       // (A2) Jastrow: fixed partners (outside the window) per slot, and in-window pair terms
@@ -476,6 +479,18 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
       // (A3) Y = V B0
       gemm_window<T, MF>(vwin, Bm, ldb, ywin, Kw, n, nP, tid);
       __syncthreads();
+      if (sizeof(T) == 4) {
+        // mixed: |v_q^T B0|^2 partials (row q of Y), for the inverse-error part of the guard band
+        const int q = tid / tpq, s = tid - q * tpq;
+        double t2 = 0.0;
+        if (q < Kw)
+          for (int c = s; c < n; c += tpq) {
+            const double y = (double)ywin[(size_t)q * nP + c];
+            t2 += y * y;
+          }
+        tnp[tid] = t2;
+        __syncthreads();
+      }
 
       // (B) the moves of the window, in order, by one wave.  Lane q keeps move q's Jastrow
       // change (partners at their positions before the window, in-window partners too) and
@@ -484,11 +499,14 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
       // window's own columns), so each ratio is read, not recomputed: R_q = yk[q][q].
       if (wave == seq_wave) {
         if (lane == 0) sm_stop = -1;
-        double Fq = 0.0, Sq = 0.0, Eq = 0.0;
+        double Fq = 0.0, Sq = 0.0, Eq = 0.0, Tq = 0.0;
         if (lane < Kw) {
           for (int s = 0; s < tpq; ++s) Fq += red[lane * tpq + s];
-          if (sizeof(T) == 4)
+          if (sizeof(T) == 4) {
             for (int s = 0; s < tpq; ++s) Sq += rmag[lane * tpq + s];
+            for (int s = 0; s < tpq; ++s) Tq += tnp[lane * tpq + s];
+            Tq = sqrt(Tq);
+          }
           for (int j = 0; j < Kw; ++j) {
             const double gj = gold[j * K + lane];
             Fq += j != lane ? gj : 0.0;
@@ -527,7 +545,7 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
           if (sizeof(T) == 4) {
             const double uf = 5.9604644775390625e-08;   // 2^-24
             const double err = (n + 1) * uf * (readlane_d(Sq, q) + readlane_d(Eq, q));
-            band += 2.0 * err / fabs(R) + 4.0 * uf;
+            band += 2.0 * err / fabs(R) + 4.0 * uf + inverse_error_term(Wk, w, sp, n, readlane_d(Tq, q), R);
           }
           if (sizeof(T) == 4 && fabs(u - p32) <= band * p32) {
             // near tie in FP32: end the window here; the move is re-decided in FP64 below
@@ -535,9 +553,13 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
             break;
           }
           if (u < p32) {
+            const double Tacc = sizeof(T) == 4 ? readlane_d(Tq, q) : 0.0;
             if (lane > q && lane < Kw) {
               const double f = yk[lane * ldy + q] / R;
-              if (sizeof(T) == 4) Eq += fabs(f * yk[q * ldy + lane]);
+              if (sizeof(T) == 4) {
+                Eq += fabs(f * yk[q * ldy + lane]);
+                Tq += fabs(f) * Tacc;   // row q's new v^T B is its old one minus f times move q's
+              }
               // eight columns at a time: all loads before the stores, so they overlap.  The
               // loads are unconditional (a guarded load becomes a branch of its own): columns
               // past Kw read at most 7 entries beyond the row, inside the LDS block that
@@ -639,7 +661,7 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
       if (stop >= 0) {
         const int kq = k0 + stop, iq = off + kq;
         const size_t it = item0 + kq;
-        const T* vg = Wk.vgl + ((size_t)(1 - scur[kq]) * P.W * N + it) * kComp * P.S;
+        const T* vg = Wk.vgl + ((size_t)(1 - scur[kq]) * P.W * N + it) * Wk.vstride;
         for (int l = tid; l < n; l += kBlock) sgrow[l] = vg[l];
         const double* v64 = Wk.val64 + ((size_t)(1 - scur[kq]) * P.W * N + it) * P.S;
         const double R64 = refined_ratio<T>(P, Wk, Bm, ldb, n, item0, scur, v64, kq, sgx, sgr, red, tid);
@@ -703,6 +725,8 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
   if (tid == seq_tid) {
     Wk.nacc[w] = nacc;
     Wk.nguard[w] += nguard;
+    if (Wk.eta_age) Wk.eta_age[w] += 1u;
+    if (Wk.fb && Wk.fb_sel == 1) Wk.pstat[2 * w + 1] += 1u;
     if (w == 0) *Wk.sweep_ctr += 1u;   // read by the next sweep's gather
   }
 }

@@ -212,17 +212,14 @@ __global__ __launch_bounds__(kBlock) void k_eval_points(SysParams P, const T* __
     }
 }
 
-// attempt (nullable: all 0) numbers each walker's redraws; it takes the counter's sweep slot.
-__global__ __launch_bounds__(kBlock) void k_init_positions(SysParams P, double* __restrict__ pos,
-                                                           const uint32_t* __restrict__ attempt, int sel_round) {
+// Uniform starting positions: electron i of walker w from the INIT counters (i, 0, w).
+__global__ __launch_bounds__(kBlock) void k_init_positions(SysParams P, double* __restrict__ pos) {
   const long item = (long)blockIdx.x * kBlock + threadIdx.x;
   if (item >= (long)P.W * P.N) return;
   const int w = (int)(item / P.N), i = (int)(item % P.N);
-  const uint32_t att = attempt ? attempt[w] : 0u;
-  if (attempt && sel_round >= 0 && att != (uint32_t)sel_round) return;
   double a0, a1, b0, b1;
-  uniform_pair(P, kInit, 0, (uint32_t)w, att, (uint32_t)i, a0, a1);
-  uniform_pair(P, kInit, 1, (uint32_t)w, att, (uint32_t)i, b0, b1);
+  uniform_pair(P, kInit, 0, (uint32_t)w, 0u, (uint32_t)i, a0, a1);
+  uniform_pair(P, kInit, 1, (uint32_t)w, 0u, (uint32_t)i, b0, b1);
   pos[item * 3 + 0] = wrap_cell(P.L * a0, P.L);
   pos[item * 3 + 1] = wrap_cell(P.L * a1, P.L);
   pos[item * 3 + 2] = wrap_cell(P.L * b0, P.L);
@@ -274,28 +271,10 @@ hipError_t launch_eval_points(const SysParams& P, const T* table, const double* 
   return hipGetLastError();
 }
 
-hipError_t launch_init_positions(const SysParams& P, double* pos, const uint32_t* attempt, hipStream_t st,
-                                 int sel_round) {
+hipError_t launch_init_positions(const SysParams& P, double* pos, hipStream_t st) {
   const long items = (long)P.W * P.N;
   const unsigned blocks = (unsigned)((items + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_init_positions, dim3(blocks), dim3(kBlock), 0, st, P, pos, attempt, sel_round);
-  return hipGetLastError();
-}
-
-__global__ __launch_bounds__(kBlock) void k_init_decide(int W, const double* __restrict__ resid,
-                                                        const int* __restrict__ status, uint32_t* attempt,
-                                                        int round) {
-  const int w = blockIdx.x * kBlock + threadIdx.x;
-  if (w >= W || attempt[w] != (uint32_t)round || round + 1 >= kInitAttempts) return;
-  const double r = fmax(resid[2 * w], resid[2 * w + 1]);
-  if (status[w] || !(r <= kInitResidual)) attempt[w] = (uint32_t)round + 1u;
-}
-
-hipError_t launch_init_decide(int W, const double* resid, const int* status, uint32_t* attempt, int round,
-                              hipStream_t st) {
-  if (W <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_init_decide, dim3((W + kBlock - 1) / kBlock), dim3(kBlock), 0, st, W, resid, status,
-                     attempt, round);
+  hipLaunchKernelGGL(k_init_positions, dim3(blocks), dim3(kBlock), 0, st, P, pos);
   return hipGetLastError();
 }
 

@@ -120,6 +120,8 @@ __global__ __launch_bounds__(kBlock) void k_rebuild(SysParams P, Walkers<T> Wk, 
     }
     T* B = Wk.binv + boff;
     for (int q = tid; q < n * n; q += kBlock) B[q] = (T)a[q];
+    if (Wk.binv64)   // mixed precision: the FP64 inverse too (fallback walkers run on it)
+      for (int q = tid; q < n * n; q += kBlock) Wk.binv64[boff + q] = a[q];
   }
   if (tid == 0) {
     if (drift) drift[2 * w + sp] = Wk.logdet[2 * w + sp] - (singular ? NAN : logabs);
@@ -284,7 +286,9 @@ __global__ __launch_bounds__(G * G) void k_rebuild_reg(SysParams P, Walkers<T> W
   if (!singular) {
     for (int k = tid; k < n; k += (G * G)) sstep[spiv[k]] = k;
     __syncthreads();
-    T* B = Wk.binv + (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0);
+    const size_t boff = (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0);
+    T* B = Wk.binv + boff;
+    double* B64 = Wk.binv64 ? Wk.binv64 + boff : nullptr;   // mixed precision: the FP64 inverse too
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const int e = r0 + G * i;
@@ -293,7 +297,10 @@ __global__ __launch_bounds__(G * G) void k_rebuild_reg(SysParams P, Walkers<T> W
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         const int l = c0 + G * j;
-        if (l < n) B[orow + spiv[l]] = (T)a[i][j];
+        if (l < n) {
+          B[orow + spiv[l]] = (T)a[i][j];
+          if (B64) B64[orow + spiv[l]] = a[i][j];
+        }
       }
     }
     for (int k = tid; k < n; k += (G * G)) slog[k] = log(fabs(spv[k]));
@@ -513,9 +520,11 @@ __global__ __launch_bounds__(kBlock) void k_rebuild_panel(SysParams P, Walkers<T
     for (int k = tid; k < n; k += kBlock) sstep[spiv[k]] = k;
     __syncthreads();
     T* B = Wk.binv + boff;
+    double* B64 = Wk.binv64 ? Wk.binv64 + boff : nullptr;   // mixed precision: the FP64 inverse too
     for (int q = tid; q < n * n; q += kBlock) {
       const int r = q / n, c = q - r * n;
       B[(size_t)sstep[r] * n + spiv[c]] = (T)a[q];
+      if (B64) B64[(size_t)sstep[r] * n + spiv[c]] = a[q];
     }
     __syncthreads();
     if (tid == 0) {
@@ -663,14 +672,32 @@ __device__ __forceinline__ void gemm64(int n, LF Lf, RF Rf, EF epi, double* sL, 
   gemm_tiles<double>(n, Lf, Rf, epi, sL, sR);
 }
 
+// Sum over the workgroup (every thread gets it; fixed order).
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum_dpp(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int q = 0; q < kWaves; ++q) t += red[q];
+  return t;
+}
+
 template <typename T>
 __device__ __forceinline__ void refine_spin(const SysParams& P, const Walkers<T>& Wk, double* scratch, int w,
                                             int sp) {
   __shared__ double sL[kTile * kLs];
   __shared__ double sR[kChunk * kRs];
   __shared__ const double* arow[kMaxSpin];
+  __shared__ double red[kWaves];
   const int n = sp ? P.n_dn : P.n_up, off = sp ? P.n_up : 0;
-  if (n == 0) return;
+  if (Wk.fb && Wk.fb[w]) return;   // an FP64 fallback walker is measured on its FP64 inverse
+  if (sp == 0 && threadIdx.x == 0 && Wk.eta_age) Wk.eta_age[w] = 0u;
+  if (n == 0) {
+    if (threadIdx.x == 0 && Wk.eta) Wk.eta[4 * w + sp] = Wk.eta[4 * w + 2 + sp] = 0.0;
+    return;
+  }
   const int N = P.N;
   const size_t boff = (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0);
   const T* B = Wk.binv + boff;
@@ -683,20 +710,38 @@ __device__ __forceinline__ void refine_spin(const SysParams& P, const Walkers<T>
   __syncthreads();
   // E = I - A B in FP64 (A B is the identity up to ~1e-6: the difference needs FP64 products);
   // E itself is small and is kept in FP32
+  double e2 = 0.0, x2 = 0.0;   // ||E||_F^2 and ||X||_F^2 partials (the guard band's inverse error)
   gemm64(n, [&](int i, int l) { return arow[i][l]; },
          [&](int l, int k) { return (double)B[(size_t)l * n + k]; },
-         [&](int i, int k, double c) { E[(size_t)i * n + k] = (float)((i == k ? 1.0 : 0.0) - c); }, sL, sR);
+         [&](int i, int k, double c) {
+           const double e = (i == k ? 1.0 : 0.0) - c;
+           e2 += e * e;
+           E[(size_t)i * n + k] = (float)e;
+         }, sL, sR);
   __syncthreads();   // E (global) complete before it is read
   // X = B + B E: the correction B E is ~1e-6 of B, so FP32 products (relative error ~1e-5 of
   // the correction, ~1e-11 of X) are far inside the FP32 rounding of the stored X
   gemm_tiles<float>(n, [&](int i, int l) { return (float)B[(size_t)i * n + l]; },
                     [&](int l, int k) { return E[(size_t)l * n + k]; },
-                    [&](int i, int k, float c) { X[(size_t)i * n + k] = (T)((double)B[(size_t)i * n + k] + (double)c); },
+                    [&](int i, int k, float c) {
+                      const T x = (T)((double)B[(size_t)i * n + k] + (double)c);
+                      x2 += (double)x * (double)x;
+                      X[(size_t)i * n + k] = x;
+                    },
                     reinterpret_cast<float*>(sL), reinterpret_cast<float*>(sR));
+  e2 = block_sum(e2, red);
+  x2 = block_sum(x2, red);
+  if (threadIdx.x == 0 && Wk.eta) {
+    Wk.eta[4 * w + sp] = sqrt(e2);
+    Wk.eta[4 * w + 2 + sp] = sqrt(x2);
+  }
 }
 
+// sel (nullable): only the walkers with sel[w] == sel_value are refined.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_refine(SysParams P, Walkers<T> Wk, double* scratch) {
+__global__ __launch_bounds__(kBlock) void k_refine(SysParams P, Walkers<T> Wk, double* scratch,
+                                                   const uint32_t* sel, uint32_t sel_value) {
+  if (sel && sel[blockIdx.x >> 1] != sel_value) return;
   refine_spin<T>(P, Wk, scratch, blockIdx.x >> 1, blockIdx.x & 1);
 }
 
@@ -716,9 +761,10 @@ __global__ __launch_bounds__(kBlock) void k_refine_batched(const SysDev<T>* __re
 }
 
 template <typename T>
-hipError_t launch_refine(const SysParams& P, const Walkers<T>& Wk, double* scratch, hipStream_t st) {
+hipError_t launch_refine(const SysParams& P, const Walkers<T>& Wk, double* scratch, hipStream_t st,
+                         const uint32_t* sel, uint32_t sel_value) {
   if (P.n_up > kMaxSpin || P.n_dn > kMaxSpin || !Wk.val64 || !Wk.xinv) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_refine<T>, dim3(2 * P.W), dim3(kBlock), 0, st, P, Wk, scratch);
+  hipLaunchKernelGGL(k_refine<T>, dim3(2 * P.W), dim3(kBlock), 0, st, P, Wk, scratch, sel, sel_value);
   return hipGetLastError();
 }
 
@@ -729,60 +775,113 @@ hipError_t launch_refine_batched(const SysDev<T>* sd, const int2* fmap, int n_wa
   return hipGetLastError();
 }
 
-template hipError_t launch_refine<float>(const SysParams&, const Walkers<float>&, double*, hipStream_t);
+template hipError_t launch_refine<float>(const SysParams&, const Walkers<float>&, double*, hipStream_t,
+                                         const uint32_t*, uint32_t);
 
-// max |I - A fl32(B)| of one (walker, spin), for the acceptance test of initial configurations.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_inverse_residual(SysParams P, Walkers<T> Wk, double* out,
-                                                             const uint32_t* sel, uint32_t sel_value) {
-  __shared__ double sL[kTile * kLs];
-  __shared__ double sR[kChunk * kRs];
-  __shared__ const T* arow[kMaxSpin];
-  __shared__ double wmax[kWaves];
-  const int w = blockIdx.x >> 1, sp = blockIdx.x & 1, tid = threadIdx.x;
-  const int n = sp ? P.n_dn : P.n_up, off = sp ? P.n_up : 0;
-  if (sel && sel[w] != sel_value) return;
-  if (n == 0) {
-    if (tid == 0) out[2 * w + sp] = 0.0;
-    return;
-  }
-  const int N = P.N;
-  const T* B = Wk.binv + (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0);
-  __shared__ const double* arow64[kMaxSpin];
-  for (int i = tid; i < n; i += kBlock) {
-    const size_t item = (size_t)w * N + off + i;
-    const size_t row = (size_t)Wk.cur[item] * P.W * N + item;
-    arow64[i] = Wk.val64 ? Wk.val64 + row * P.S : nullptr;
-    arow[i] = Wk.vgl + row * kComp * P.S;
-  }
-  __syncthreads();
-  double worst = 0.0;
-  gemm64(n, [&](int i, int l) { return arow64[i] ? arow64[i][l] : (double)arow[i][l]; },
-         [&](int l, int k) { return (double)(float)B[(size_t)l * n + k]; },
-         [&](int i, int k, double c) { worst = fmax(worst, fabs((i == k ? 1.0 : 0.0) - c)); }, sL, sR);
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) worst = fmax(worst, __shfl_xor(worst, o, 64));
-  if ((tid & 63) == 0) wmax[tid >> 6] = worst;
-  __syncthreads();
-  if (tid == 0) {
-    double m = wmax[0];
-    for (int q = 1; q < kWaves; ++q) m = fmax(m, wmax[q]);
-    out[2 * w + sp] = m;
-  }
+// ---------------------------------------------------------------------------
+// FP64 fallback of ill-conditioned walkers (mixed precision).
+//
+// A walker's FP32 inverse B can carry the FP64 chain's decisions only while its
+// error is small: with A B = I - E the ratio of a proposal v errs by at most
+// ||v^T B|| ||E||_F.  An inverse rounded to FP32 has ||E|| of the order of the
+// condition number of A times 2^-24, so an ill-conditioned walker (two electrons
+// of one spin close together at a uniform start, for instance) cannot be run in
+// FP32 at all.  After every full rebuild and every measurement the walkers are
+// checked: a measured ||E||_F above kEtaRebuild (drift of the FP32 updates) has
+// the walker's inverse rebuilt in FP64; a fresh FP32 rounding of the FP64 inverse
+// whose residual still exceeds kEtaEnter sends the walker to the FP64 fallback
+// (its chain runs in FP64 on binv64, its kinetic energy reads binv64), and a
+// fallback walker whose FP32 rounding falls below kEtaLeave returns to FP32.
+//
+// mark[w]: 1 = rebuild and check, 2 = check a fallback walker, 3 = refine (back in
+// FP32 after a check), 0 = nothing.
+// ---------------------------------------------------------------------------
+
+// mark[w] after a measurement's refinement (all = 1: after a full rebuild of every walker).
+__global__ __launch_bounds__(kBlock) void k_fb_mark(int W, const double* __restrict__ eta, const int* __restrict__ fb,
+                                                    uint32_t* __restrict__ mark, int all) {
+  const int w = blockIdx.x * kBlock + threadIdx.x;
+  if (w >= W) return;
+  mark[w] = all ? 1u : (fb[w] ? 2u : (fmax(eta[4 * w], eta[4 * w + 1]) > kEtaRebuild ? 1u : 0u));
 }
 
-template <typename T>
-hipError_t launch_inverse_residual(const SysParams& P, const Walkers<T>& Wk, double* out, hipStream_t st,
-                                   const uint32_t* sel, uint32_t sel_value) {
-  if (P.n_up > kMaxSpin || P.n_dn > kMaxSpin) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_inverse_residual<T>, dim3(2 * P.W), dim3(kBlock), 0, st, P, Wk, out, sel, sel_value);
+hipError_t launch_fb_mark(int W, const double* eta, const int* fb, uint32_t* mark, int all, hipStream_t st) {
+  hipLaunchKernelGGL(k_fb_mark, dim3((W + kBlock - 1) / kBlock), dim3(kBlock), 0, st, W, eta, fb, mark, all);
   return hipGetLastError();
 }
 
-template hipError_t launch_inverse_residual<double>(const SysParams&, const Walkers<double>&, double*, hipStream_t,
-                                                    const uint32_t*, uint32_t);
-template hipError_t launch_inverse_residual<float>(const SysParams&, const Walkers<float>&, double*, hipStream_t,
-                                                   const uint32_t*, uint32_t);
+// eta[w] = ||I - A fl32(B64)||_F and ||B64||_F per spin for the walkers with mark 1 or 2: the
+// error an FP32 copy of the FP64 inverse would start from (FP64 products, A = the FP64 rows).
+__global__ __launch_bounds__(kBlock) void k_fb_residual(SysParams P, Walkers<float> Wk, const uint32_t* mark) {
+  __shared__ double sL[kTile * kLs];
+  __shared__ double sR[kChunk * kRs];
+  __shared__ const double* arow[kMaxSpin];
+  __shared__ double red[kWaves];
+  const int w = blockIdx.x >> 1, sp = blockIdx.x & 1, tid = threadIdx.x;
+  if (mark[w] != 1u && mark[w] != 2u) return;
+  if (sp == 0 && tid == 0) Wk.eta_age[w] = 0u;
+  const int n = sp ? P.n_dn : P.n_up, off = sp ? P.n_up : 0;
+  if (n == 0) {
+    if (tid == 0) Wk.eta[4 * w + sp] = Wk.eta[4 * w + 2 + sp] = 0.0;
+    return;
+  }
+  const int N = P.N;
+  const double* B = Wk.binv64 + (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0);
+  for (int i = tid; i < n; i += kBlock) {
+    const size_t item = (size_t)w * N + off + i;
+    arow[i] = Wk.val64 + ((size_t)Wk.cur[item] * P.W * N + item) * P.S;
+  }
+  __syncthreads();
+  double e2 = 0.0, b2 = 0.0;
+  gemm64(n, [&](int i, int l) { return arow[i][l]; },
+         [&](int l, int k) { return (double)(float)B[(size_t)l * n + k]; },
+         [&](int i, int k, double c) {
+           const double e = (i == k ? 1.0 : 0.0) - c;
+           e2 += e * e;
+         }, sL, sR);
+  for (int q = tid; q < n * n; q += kBlock) b2 += B[q] * B[q];
+  e2 = block_sum(e2, red);
+  b2 = block_sum(b2, red);
+  if (tid == 0) {
+    Wk.eta[4 * w + sp] = sqrt(e2);
+    Wk.eta[4 * w + 2 + sp] = sqrt(b2);
+  }
+}
+
+hipError_t launch_fb_residual(const SysParams& P, const Walkers<float>& Wk, const uint32_t* mark, hipStream_t st) {
+  if (P.n_up > kMaxSpin || P.n_dn > kMaxSpin || !Wk.binv64 || !Wk.eta) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_fb_residual, dim3(2 * P.W), dim3(kBlock), 0, st, P, Wk, mark);
+  return hipGetLastError();
+}
+
+// The decision for the checked walkers: FP64 fallback while the FP32 rounding's residual
+// exceeds kEtaEnter (kEtaLeave for a walker already in fallback).  A walker returning to
+// FP32 takes binv = fl32(binv64) and mark 3 (its refinement is due); mark 1 counts an early
+// rebuild when early != 0.
+__global__ __launch_bounds__(kBlock) void k_fb_decide(SysParams P, Walkers<float> Wk, uint32_t* mark, int early) {
+  const int w = blockIdx.x, tid = threadIdx.x;
+  const uint32_t m = mark[w];
+  if (m != 1u && m != 2u) return;
+  const int was = Wk.fb[w];
+  const double eta = fmax(Wk.eta[4 * w], Wk.eta[4 * w + 1]);
+  const int now = eta > (was ? kEtaLeave : kEtaEnter) ? 1 : 0;
+  if (!now && m == 2u) {
+    const size_t off = (size_t)w * P.bstride;
+    for (int q = tid; q < P.bstride; q += kBlock) Wk.binv[off + q] = (float)Wk.binv64[off + q];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    Wk.fb[w] = now;
+    mark[w] = now ? 0u : 3u;
+    if (early && m == 1u) Wk.pstat[2 * w] += 1u;
+  }
+}
+
+hipError_t launch_fb_decide(const SysParams& P, const Walkers<float>& Wk, uint32_t* mark, int early, hipStream_t st) {
+  hipLaunchKernelGGL(k_fb_decide, dim3(P.W), dim3(kBlock), 0, st, P, Wk, mark, early);
+  return hipGetLastError();
+}
+
 template hipError_t launch_refine_batched<float>(const SysDev<float>*, const int2*, int, hipStream_t);
 
 template <typename T>

@@ -118,6 +118,32 @@ __host__ __device__ inline MeasureLayout measure_layout(int N, int np) {
   return L;
 }
 
+// sum_l B[l][k] (grad phi_l, lap phi_l)(r) for one electron of an FP64 fallback walker: the
+// orbitals are evaluated in FP64 from the table, summed against the column as
+// sum_stencil weights * (sum_l B[l][k] c_stencil,l), so no FP32-rounded row enters.
+// bcol: column k of the FP64 inverse (stride n).
+template <typename T>
+__device__ void det_terms_fp64(const SysParams& P, const T* __restrict__ table, double x, double y, double z,
+                               const double* __restrict__ bcol, int n, double& gx, double& gy, double& gz,
+                               double& l2) {
+  Axis ax, ay, az;
+  axis_weights(x, P.L, P.gx, ax);
+  axis_weights(y, P.L, P.gy, ay);
+  axis_weights(z, P.L, P.gz, az);
+  gx = gy = gz = l2 = 0.0;
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b)
+      for (int c = 0; c < 4; ++c) {
+        const T* cf = table + (((size_t)ax.idx[a] * P.gy + ay.idx[b]) * P.gz + az.idx[c]) * P.S;
+        double d = 0.0;
+        for (int l = 0; l < n; ++l) d += bcol[(size_t)l * n] * (double)cf[l];
+        gx += ax.dw[a] * ay.w[b] * az.w[c] * d;
+        gy += ax.w[a] * ay.dw[b] * az.w[c] * d;
+        gz += ax.w[a] * ay.w[b] * az.dw[c] * d;
+        l2 += (ax.d2w[a] * ay.w[b] * az.w[c] + ax.w[a] * ay.d2w[b] * az.w[c] + ax.w[a] * ay.w[b] * az.d2w[c]) * d;
+      }
+}
+
 template <typename T>
 __device__ __forceinline__ void measure_part(const SysParams& P, const Walkers<T>& Wk, const EwaldParams& E,
                                              double* __restrict__ partial, int w, int p, int np) {
@@ -159,12 +185,21 @@ __device__ __forceinline__ void measure_part(const SysParams& P, const Walkers<T
 
   // (1) determinant part of this part's electrons i = p nloc + li, one thread per electron:
   // column k of the inverse is read across the threads of consecutive electrons (coalesced),
-  // each thread walking its own value/gradient/Laplacian row
+  // each thread walking its own value/gradient/Laplacian row.  An FP64 fallback walker of the
+  // mixed path takes its FP64 inverse and orbitals evaluated in FP64 instead.
+  const bool fb64 = Wk.fb && Wk.fb[w];
   for (int li = tid; li < nloc; li += kBlock) {
     const int i = p * nloc + li;
     if (i >= N) break;
     const int sp = i < P.n_up ? 0 : 1;
     const int n = sp ? P.n_dn : P.n_up, k = i - (sp ? P.n_up : 0);
+    if (fb64) {
+      const double* bcol = Wk.binv64 + (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0) + k;
+      double gx, gy, gz, l2;
+      det_terms_fp64<T>(P, Wk.table, sx[i], sy[i], sz[i], bcol, n, gx, gy, gz, l2);
+      sgd[3 * li] = gx; sgd[3 * li + 1] = gy; sgd[3 * li + 2] = gz; sld[li] = l2;
+      continue;
+    }
     const size_t item = (size_t)w * N + i;
     const T* row = Wk.vgl + ((size_t)Wk.cur[item] * P.W * N + item) * kComp * P.S;
     const T* B = (Wk.xinv ? Wk.xinv : Wk.binv) + (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0) + k;

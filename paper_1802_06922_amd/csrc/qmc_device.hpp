@@ -72,7 +72,42 @@ struct Walkers {
   int row_flip;       // rebuilds: 1 = invert the rows of the buffer that does not hold the current row
   const double* drift_v;  // [W][N][3] or null: drift velocities grad ln|Psi| at the current positions;
                           // the sweep's proposals then take the mean r + sigma^2 v
+  int vstride;        // elements from one value row of vgl to the next (kComp * S; S for FP64 value rows)
+  // Mixed precision, particle-by-particle moves (all null otherwise).  A walker whose FP32
+  // inverse cannot carry FP64 decisions (an ill-conditioned Slater matrix) runs its chain in
+  // FP64 on binv64 until its conditioning allows FP32 again.
+  double* binv64;     // [W][bstride]: FP64 inverses; current for the walkers with fb[w] = 1
+  int* fb;            // [W]: 1 = FP64 fallback walker
+  int fb_sel;         // chain launches advance only the walkers with fb[w] == fb_sel
+  double* eta;        // [W][4]: ||I - A B||_F of each spin's inverse at the last check, then ||B||_F
+  uint32_t* eta_age;  // [W]: sweeps since eta was measured
+  uint32_t* pstat;    // [W][2]: early FP64 rebuilds, sweeps run in FP64 fallback (cumulative)
+  const T* table;     // the orbital table (the measurement of fallback walkers evaluates it in FP64)
 };
+
+// Walkers a chain launch skips: those of the other precision class.
+template <typename T>
+__device__ __forceinline__ bool chain_skips(const Walkers<T>& Wk, int w) {
+  return Wk.fb && Wk.fb[w] != Wk.fb_sel;
+}
+
+// Mixed-precision guard: a safety factor on the measured inverse error (it grows with the
+// updates of a sweep), and the thresholds of the FP64 fallback.
+constexpr double kEtaSafety = 4.0;
+constexpr double kEtaRebuild = 2e-4;   // measured ||I - A B||_F above this: rebuild the inverse in FP64
+constexpr double kEtaEnter = 2e-4;     // a fresh FP32 inverse this far off: FP64 fallback
+constexpr double kEtaLeave = 5e-5;     // a fallback walker returns to FP32 below this
+
+// Relative error bound on an FP32 ratio R = v . B[:, k] that the inverse's own error causes:
+// with A B = I - E, |dR| <= ||v^T B|| ||E||_F (1 + O(||E||)); tnorm bounds ||v^T B||.
+template <typename T>
+__device__ __forceinline__ double inverse_error_term(const Walkers<T>& Wk, int w, int sp, int n, double tnorm,
+                                                     double R) {
+  if (!Wk.eta) return 0.0;
+  const double eta = fmax(Wk.eta[4 * w + sp], (double)n * 5.9604644775390625e-08);
+  const double age = Wk.eta_age ? (double)Wk.eta_age[w] : 0.0;
+  return 2.0 * kEtaSafety * eta * (1.0 + age) * tnorm / fabs(R);
+}
 
 // ---------------------------------------------------------------------------
 // Counter-based random numbers: Philox4x32-10 (Salmon, Moraes, Dror and Shaw,

@@ -4,7 +4,7 @@
 // the uniform u falls within a relative band around that value the decision
 // could differ from the one FP64 arithmetic makes, so it is taken again from
 // an FP64 ratio: the inverse column x = A^-1 e_k is refined from the FP32
-// column by two steps of x <- x + B (e_k - A x), with the FP64 Slater matrix A
+// column by three steps of x <- x + B (e_k - A x), with the FP64 Slater matrix A
 // assembled from the FP64 orbital values the gather kept, and R = v . x.
 #pragma once
 
@@ -23,7 +23,7 @@ __device__ double refined_ratio(const SysParams& P, const Walkers<T>& Wk, const 
   const int lane = tid & 63, wave = tid >> 6;
   for (int l = tid; l < n; l += kBlock) sx[l] = (double)Bm[(size_t)l * ldb + k];
   __syncthreads();
-  for (int it = 0; it < 2; ++it) {
+  for (int it = 0; it < 3; ++it) {
     for (int j = tid; j < n; j += kBlock) {
       const double* arow = Wk.val64 + ((size_t)scur[j] * P.W * P.N + item0 + j) * P.S;
       double a = 0.0;

@@ -103,38 +103,33 @@ hipError_t delayed_lds_limits();
 hipError_t linalg_lds_limits();
 hipError_t measure_lds_limits();
 
-// Initial positions from the INIT stream; attempt[W] (nullable) numbers each walker's redraw.
-// With sel_round >= 0 only the walkers whose attempt number equals it are drawn.
-hipError_t launch_init_positions(const SysParams& P, double* pos, const uint32_t* attempt, hipStream_t st,
-                                 int sel_round = -1);
-// Initial configurations: initial draws are redrawn while a Slater matrix is singular or the
-// single-precision rounding of its inverse leaves a residual above kInitResidual.
-constexpr int kInitAttempts = 16;
-constexpr double kInitResidual = 1e-5;
-// After round `round` of the initial draws: every walker drawn in that round (attempt[w] ==
-// round) whose matrices are singular (status) or whose residual (resid[2w], resid[2w+1])
-// exceeds kInitResidual moves to the next attempt, unless round is the last.
-hipError_t launch_init_decide(int W, const double* resid, const int* status, uint32_t* attempt, int round,
-                              hipStream_t st);
-// out[2w + sp] = max_{i,k} |delta_ik - sum_l A[i][l] fl32(B[l][k])| (FP64 products), A from the
-// current value rows (val64 when present), B the current inverse.
-template <typename T>
-hipError_t launch_inverse_residual(const SysParams& P, const Walkers<T>& Wk, double* out, hipStream_t st,
-                                   const uint32_t* sel = nullptr, uint32_t sel_value = 0);
+// Uniform initial positions from the INIT stream of every (walker, electron).
+hipError_t launch_init_positions(const SysParams& P, double* pos, hipStream_t st);
+
+// Mixed precision, FP64 fallback of ill-conditioned walkers (k_linalg.hip): mark[w] from the
+// measured inverse errors (all != 0: every walker, after a full rebuild); the FP32 rounding
+// residual of binv64 for the walkers with mark 1 or 2; the decision, which copies binv =
+// fl32(binv64) for walkers returning to FP32 and leaves them mark 3 (refinement due).
+hipError_t launch_fb_mark(int W, const double* eta, const int* fb, uint32_t* mark, int all, hipStream_t st);
+hipError_t launch_fb_residual(const SysParams& P, const Walkers<float>& Wk, const uint32_t* mark, hipStream_t st);
+hipError_t launch_fb_decide(const SysParams& P, const Walkers<float>& Wk, uint32_t* mark, int early, hipStream_t st);
 
 // Full FP64 inverse of every Slater matrix from the current value rows
 // (Gauss-Jordan with partial pivoting); scratch: W * bstride doubles.
 // drift (nullable): receives log|D|_old - log|D|_new per [W][2].
-// sel (nullable, both here and in launch_inverse_residual): only walkers w with
-// sel[w] == sel_value are processed, the others keep their results.
+// sel (nullable): only walkers w with sel[w] == sel_value are processed, the others keep
+// their results.  Mixed precision: the FP64 inverse goes to binv64 as well.
 template <typename T>
 hipError_t launch_rebuild(const SysParams& P, const Walkers<T>& Wk, double* scratch, double* drift,
                           hipStream_t st, const uint32_t* sel = nullptr, uint32_t sel_value = 0);
 
 // Mixed precision: Wk.xinv = B + B (I - A B) with the FP64 Slater matrix A (from val64) and
-// FP64 products, the inverse the measurement reads; scratch: W * bstride doubles.
+// FP64 products, the inverse the measurement reads; eta = ||I - A B||_F and ||X||_F per spin;
+// scratch: W * bstride doubles.  FP64 fallback walkers are skipped; sel (nullable): only the
+// walkers with sel[w] == sel_value.
 template <typename T>
-hipError_t launch_refine(const SysParams& P, const Walkers<T>& Wk, double* scratch, hipStream_t st);
+hipError_t launch_refine(const SysParams& P, const Walkers<T>& Wk, double* scratch, hipStream_t st,
+                         const uint32_t* sel = nullptr, uint32_t sel_value = 0);
 // Batched refinement of every (system, walker) of fmap, both spins.
 template <typename T>
 hipError_t launch_refine_batched(const SysDev<T>* sd, const int2* fmap, int n_walkers, hipStream_t st);

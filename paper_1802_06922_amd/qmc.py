@@ -30,6 +30,7 @@ EXPORTS = [
     "qmc_get_last_energies", "qmc_batch_create", "qmc_batch_sweep", "qmc_batch_set_graph",
     "qmc_batch_timing", "qmc_batch_destroy", "qmc_max_delay_rank", "qmc_autotune_gather",
     "qmc_set_gather_lanes", "qmc_run_steps", "qmc_dmc_init", "qmc_dmc_steps", "qmc_dmc_get",
+    "qmc_get_precision_stats",
 ]
 
 
@@ -104,6 +105,8 @@ def load_library():
     L.qmc_dmc_steps.argtypes = [vp, C.c_int32, vp]
     L.qmc_dmc_get.argtypes = [vp, dp, dp, dp, C.POINTER(C.c_int32)]
     L.qmc_max_delay_rank.argtypes = [C.POINTER(Desc)]
+    L.qmc_get_precision_stats.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                          C.POINTER(C.c_int32), ip]
     L.qmc_max_delay_rank.restype = C.c_int32
     for name in EXPORTS:
         if name not in ("qmc_last_error", "qmc_estimate_device_bytes", "qmc_max_delay_rank"):
@@ -298,6 +301,15 @@ class System:
         a, b = C.c_uint64(0), C.c_uint64(0)
         self._check(self.L.qmc_get_counters(self.h, C.byref(a), C.byref(b)))
         return int(a.value), int(b.value)
+
+    def precision_stats(self):
+        """Mixed precision: (early FP64 rebuilds, walker sweeps run in FP64 fallback, walkers in
+        fallback now, fallback mask [W]) since init_walkers."""
+        a, b, c = C.c_uint64(0), C.c_uint64(0), C.c_int32(0)
+        mask = np.zeros(self.W, dtype=np.int32)
+        self._check(self.L.qmc_get_precision_stats(self.h, C.byref(a), C.byref(b), C.byref(c),
+                                                   mask.ctypes.data_as(C.POINTER(C.c_int32))))
+        return int(a.value), int(b.value), int(c.value), mask
 
     def recompute(self) -> np.ndarray:
         drift = np.zeros((self.W, 2))
