@@ -24,7 +24,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "electron-moves/sec (1 GPU) mixed vs FP64; p50/p99 sweep latency served"
-HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, GB/s
+MFMA_FP32_TFLOPS = 157.3    # MI355X dense FP32 matrix peak
+MFMA_FP64_TFLOPS = 78.6     # MI355X dense FP64 matrix peak
+BOX_CPU_SHARE = 16          # host threads a one-GPU machine grants a process
 
 
 def describe(wl) -> str:
@@ -67,10 +70,30 @@ def measured_traffic(wl):
     return d["traffic_bytes_per_dispatch"]
 
 
+def host_description():
+    """Host cores and CPU model, for the CPU baseline."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": os.cpu_count() or 1, "affinity_cpus": affinity}
+
+
 def cpu_baseline(wl, target_s: float = 12.0):
-    """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload: one walker per
+    thread, as many threads as the process may use on a one-GPU machine (its share of the host)."""
     import oracle
-    threads = min(os.cpu_count() or 1, 16)
+    host = host_description()
+    threads = max(1, min(host["affinity_cpus"], BOX_CPU_SHARE))
     osys = oracle.OracleSystem(wl)
     # calibrate with one sweep of one walker per thread
     ids = list(range(threads))
@@ -84,7 +107,9 @@ def cpu_baseline(wl, target_s: float = 12.0):
     moves = len(ids) * wl.n_elec * sweeps
     return {"value": moves / dt, "unit": "electron-moves/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(ids)} walkers x {sweeps} sweeps (+ measurement every sweep) of "
-                      f"{wl.name}, {moves} moves in {dt:.2f} s, one walker per thread"}
+                      f"{wl.name}, {moves} moves in {dt:.2f} s, one walker per thread",
+            "host": host, "threads_rule": f"min(cpus this process may use, {BOX_CPU_SHARE}): the "
+                                          "share of the host a one-GPU box grants"}
 
 
 def main(argv=None) -> int:
@@ -92,7 +117,8 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="solid128", help="solid128 | heg14 | mixed384")
+    ap.add_argument("--workload", default="mixed384",
+                    help="mixed384 (default: the mixed-precision headline, with FP64 beside it) | solid128 | heg14")
     ap.add_argument("--delay", type=int, default=None,
                     help="delay rank K (1 = Sherman-Morrison; 4..64 = delayed updates); "
                          "default: autotuned before the timed region")
@@ -100,8 +126,10 @@ def main(argv=None) -> int:
                     help="single: one system (default); batched: the four uneven systems in fused "
                          "launches; served: a Poisson request stream with continuous batching; copy: "
                          "a plain 1 GiB device copy (x3), the reference for HBM counter readings")
-    ap.add_argument("--requests", type=int, default=40, help="served: requests of each trace")
-    ap.add_argument("--sweep-scale", type=float, default=0.05, help="served: scale of each request's sweeps")
+    ap.add_argument("--requests", type=int, default=200, help="served: requests of each trace")
+    ap.add_argument("--sweep-scale", type=float, default=0.02, help="served: scale of each request's sweeps")
+    ap.add_argument("--no-served", action="store_true",
+                    help="single: skip the served block (the 200-arrival trace) of the headline line")
     ap.add_argument("--dmc-every", type=int, default=4,
                     help="served: every k-th request is a DMC run (0: VMC only)")
     ap.add_argument("--no-graph", action="store_true", help="batched/served: no HIP graph replay")
@@ -109,7 +137,7 @@ def main(argv=None) -> int:
     ap.add_argument("--gather-lanes", type=int, default=None,
                     help="gather lanes per proposal, log2 (default: autotuned before the timed region)")
     ap.add_argument("--no-compare", action="store_true",
-                    help="skip the mixed-vs-FP64 comparison on the 384-electron system")
+                    help="mixed384: skip the FP64 runs of the same system beside the mixed one")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--moves", default="pbyp", choices=["pbyp", "all", "drift"],
                     help="single: particle-by-particle sweeps (default), or one all-electron move per "
@@ -159,6 +187,8 @@ def main(argv=None) -> int:
                                  sigma=args.ae_sigma or wl.sigma / math.sqrt(wl.n_elec))
         args.no_compare = True
     r = run_single(wl, args.steps, args.warmup, args.delay, args.gather_lanes, serial=args.serial)
+    if r["delay_rank"] is not None:
+        wl.delay_rank = r["delay_rank"]
     W, N = r["walkers"], wl.n_elec
     kt = r["kt"]
     b = wl.coefs.dtype.itemsize
@@ -202,13 +232,73 @@ def main(argv=None) -> int:
         "sweep_only_moves_per_s": r["sweep_only_moves_per_s"],
         "mean_local_energy": r["mean_local_energy"],
     }
-    if not args.no_compare:
-        line["mixed_vs_fp64"] = compare_precisions(args)
+    if not ae:
+        line["roofline_chain"] = chain_roofline(wl, r)
+    headline = args.workload == "mixed384" and wl.precision == "mixed" and not ae and args.j3 is None
+    if headline and not args.no_compare:
+        line.update(fp64_beside(wl, r))
     if not args.no_cpu_baseline:
         print("[bench] CPU baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    if headline and not args.no_served:
+        line["served"] = served_block(args)
     print(json.dumps(line), flush=True)
     return 0
+
+
+def chain_roofline(wl, r):
+    """The move chain against the matrix-core peak of its precision.  Its matrix-core work per
+    launch: per walker and spin block of n electrons, the window products Y = V B0 (2 n^3 over
+    a sweep) and the rank-m flushes (2 n^2 per accepted move), i.e. 2 W sum_spin n^3 (1 + a) at
+    acceptance a; the inverse itself moves 2 n^2 b bytes per spin and walker when the chain
+    keeps it on chip for the sweep (read once, written once)."""
+    kt = r["kt"]
+    c_ms, c_n = kt["chain"]
+    avg_s = c_ms / max(c_n, 1) / 1e3
+    W, a = r["walkers"], r["acceptance"]
+    b = wl.coefs.dtype.itemsize
+    n3 = wl.n_up ** 3 + wl.n_dn ** 3
+    flops = 2.0 * W * n3 * (1.0 + a) if r["delay_rank"] and r["delay_rank"] > 1 else 0.0
+    peak = MFMA_FP32_TFLOPS if b == 4 else MFMA_FP64_TFLOPS
+    achieved = flops / avg_s / 1e12 if avg_s > 0 else 0.0
+    return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": None,
+            "kernel": "move chain (ratios, Jastrow, decisions, delayed-update products)",
+            "flops_per_launch": flops, "avg_launch_ms": avg_s * 1e3, "delay_rank": r["delay_rank"],
+            "inverse_bytes_per_launch": 2 * W * (wl.n_up ** 2 + wl.n_dn ** 2) * b,
+            "note": "sequential per walker (each move depends on the previous decision): the matrix "
+                    "cores are busy only in the window products and flushes"}
+
+
+def fp64_beside(mixed_wl, rm):
+    """The same 384-electron system in FP64 (the FP32-valued table stored in FP64, FP64 updates,
+    no guard) with its autotuned delay rank, and the plain FP64 sweep (Sherman-Morrison, rank 1),
+    for as many steps as the mixed run; the mixed energies against the FP64 ones at the same
+    walker positions (the mixed path takes the FP64 decisions, so the walkers coincide)."""
+    import dataclasses
+
+    import numpy as np
+    steps = rm["steps"]
+    fp64 = dataclasses.replace(mixed_wl, precision="fp64", coefs=mixed_wl.coefs.astype(np.float64),
+                               recompute_period=0, name="solid384_fp64")
+    plain = dataclasses.replace(fp64, name="solid384_fp64_plain")
+    out = {}
+    runs = {}
+    for tag, wl, K in (("fp64", fp64, None), ("fp64_plain", plain, 1)):
+        r = run_single(wl, steps, 1, K)
+        runs[tag] = r
+        out[tag] = {"moves_per_s": r["value"], "ms_per_step": r["ms_per_step"], "delay_rank": r["delay_rank"],
+                    "steps": r["steps"],
+                    "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in r["kt"].items()}}
+    out["mixed_over_fp64"] = rm["value"] / out["fp64"]["moves_per_s"]
+    out["mixed_over_fp64_plain"] = rm["value"] / out["fp64_plain"]["moves_per_s"]
+    same = bool(np.array_equal(rm["positions"], runs["fp64"]["positions"]))
+    em, ef = rm["energies"], runs["fp64"]["energies"]
+    rel = np.abs(em - ef) / np.maximum(np.abs(ef), 1.0)
+    out["mixed_energy_error_vs_fp64"] = {
+        "same_walker_positions": same, "components": "kinetic, e-e, e-I, I-I per walker, last step",
+        "max": float(rel.max()), "p99": float(np.percentile(rel, 99)), "median": float(np.median(rel))}
+    return out
 
 
 def run_single(wl, steps: int, warmup: int, delay, lanes=None, serial: bool = False):
@@ -274,42 +364,6 @@ def run_single(wl, steps: int, warmup: int, delay, lanes=None, serial: bool = Fa
             "rebuilds": {"launches": rebuild[1], "ms_per_launch": rebuild[0] / max(rebuild[1], 1)},
             "delay_rank": K, "gather_lanes_log2": lanes_log2, "acceptance": acceptance, "sweep_only_moves_per_s": moves / (sweep_ms * steps / 1e3) if sweep_ms > 0 else None,
             "mean_local_energy": float(e_host.sum(axis=1).mean()), "energies": e_host, "positions": pos_host}
-
-
-def compare_precisions(args):
-    """The 384-electron system in mixed precision and in FP64 (the same FP32-valued table stored
-    in FP64, FP64 inverse updates, no guard), each with its autotuned delay rank."""
-    import dataclasses
-
-    import numpy as np
-
-    import qmc_inputs as qi
-    mixed = qi.mixed384()
-    steps = mixed.recompute_period   # one rebuild period: the mixed run pays for its FP64 rebuild
-    fp64 = dataclasses.replace(mixed, precision="fp64", coefs=mixed.coefs.astype(np.float64),
-                               recompute_period=0, name="solid384_fp64")
-    out = {"workload": "384 electrons, 192 orbitals, 64^3 table, 96 ions, 1024 walkers"}
-    runs = {}
-    plain = dataclasses.replace(fp64, name="solid384_fp64_plain")
-    # mixed and FP64 with their autotuned delay ranks, and the plain FP64 sweep
-    # (Sherman-Morrison updates, rank 1)
-    for tag, wl, K in (("mixed", mixed, None), ("fp64", fp64, None), ("fp64_plain", plain, 1)):
-        r = run_single(wl, steps, 1, K)
-        runs[tag] = r
-        out[tag] = {"moves_per_s": r["value"], "ms_per_step": r["ms_per_step"], "delay_rank": r["delay_rank"],
-                    "steps": r["steps"], "rebuilds": r["rebuilds"],
-                    "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in r["kt"].items()}}
-    out["mixed_over_fp64"] = out["mixed"]["moves_per_s"] / out["fp64"]["moves_per_s"]
-    out["mixed_over_fp64_plain"] = out["mixed"]["moves_per_s"] / out["fp64_plain"]["moves_per_s"]
-    # both ran the same number of sweeps from the same start; the mixed path takes the FP64
-    # decisions, so the walkers coincide and the last local energies compare one to one
-    same = bool(np.array_equal(runs["mixed"]["positions"], runs["fp64"]["positions"]))
-    em, ef = runs["mixed"]["energies"], runs["fp64"]["energies"]
-    rel = np.abs(em - ef) / np.maximum(np.abs(ef), 1.0)
-    out["mixed_energy_error_vs_fp64"] = {
-        "same_walker_positions": same, "components": "kinetic, e-e, e-I, I-I per walker",
-        "max": float(rel.max()), "p99": float(np.percentile(rel, 99)), "median": float(np.median(rel))}
-    return out
 
 
 def bench_dmc(args) -> int:
@@ -448,47 +502,61 @@ def bench_batched(args) -> int:
     return 0
 
 
-def bench_served(args) -> int:
+def served_block(args):
     """Served request streams: Poisson arrivals of requests with electron counts log-uniform in
-    [32, 1024], grids 32..64^3, 64..1024 walkers, 100..1000 sweeps scaled by --sweep-scale; every
-    --dmc-every-th request is a DMC run (as many steps), the others VMC runs.
-    First at 20 requests/s (far above one GPU's capacity), then at 0.8 x the capacity measured
-    in that run; p50/p99 per-sweep latency for both, throughput of the first."""
+    [32, 1024], grids 32..64^3, 64..1024 walkers, 100..1000 sweeps scaled by --sweep-scale, each
+    with its own table; every --dmc-every-th request is a DMC run (as many steps), the others VMC
+    runs.  First at 20 requests/s (far above one GPU's capacity), then at 0.8 x the capacity
+    measured in that run; p50/p99 per-sweep latency for both, throughput of each."""
     import dataclasses
 
     import qmc_inputs as qi
     from paper_1802_06922_amd import serve
 
     log = lambda m: print(m, file=sys.stderr, flush=True)
+    print(f"[bench] served: {args.requests} requests, sweeps x{args.sweep_scale}", file=sys.stderr, flush=True)
     trace = qi.served_trace(n_requests=args.requests, rate_per_s=20.0, seed=0)
-    reqs = serve.build_requests(trace, sweep_scale=args.sweep_scale, table_pool=True, log=log,
+    reqs = serve.build_requests(trace, sweep_scale=args.sweep_scale, table_pool=True, log=None,
                                 dmc_every=args.dmc_every)
     srv = serve.Server(graph=not args.no_graph)
-    st = srv.run(reqs, log=log)
+    st = srv.run(reqs, log=None)
+    print(f"[bench] served at 20/s: {st['requests']} requests in {st['wall_s']:.1f} s", file=sys.stderr, flush=True)
     capacity = st["requests"] / st["wall_s"]
     # the same requests again, arriving at 0.8 x the measured capacity
     rate = 0.8 * capacity
     slow = qi.served_trace(n_requests=args.requests, rate_per_s=rate, seed=0)
     reqs2 = [dataclasses.replace(r, arrival_s=e["arrival_s"], system=None, done_sweeps=0, latencies_ms=[],
-                                 gpu_ms=[], energy=None, final_pos=None, stats=None, stream=None)
+                                 gpu_ms=[], energy=None, final_pos=None, stats=None, stream=None, status="queued",
+                                 error="")
              for r, e in zip(sorted(reqs, key=lambda r: r.rid), slow)]
-    st2 = srv.run(reqs2, log=log)
-    line = {
-        "metric": METRIC, "value": st["moves_per_s"], "unit": "electron-moves/s", "n_gpus": 1,
-        "steps": st["sweep_iterations"], "warmup": 0,
-        "ms_per_step": st["wall_s"] / max(st["sweep_iterations"], 1) * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": f"served stream: {args.requests} Poisson arrivals, N log-uniform [32, 1024], "
-                               f"grids 32..64^3, 64..1024 walkers, 100..1000 sweeps x{args.sweep_scale}"
-                               + (f", every {args.dmc_every}th request a DMC run" if args.dmc_every else ""),
-                   "hbm_budget_bytes": srv.budget, "dmc_requests": st["dmc_requests"]},
+    st2 = srv.run(reqs2, log=None)
+    print(f"[bench] served at {rate:.2f}/s: {st2['requests']} requests in {st2['wall_s']:.1f} s", file=sys.stderr,
+          flush=True)
+    return {
+        "workload": f"served stream: {args.requests} Poisson arrivals, N log-uniform [32, 1024], grids "
+                    f"32..64^3, 64..1024 walkers, 100..1000 sweeps x{args.sweep_scale}, each request its own "
+                    "FP32 table" + (f", every {args.dmc_every}th request a DMC run" if args.dmc_every else ""),
+        "hbm_budget_bytes": srv.budget, "dmc_requests": st["dmc_requests"],
         "overload_20_per_s": {"p50_sweep_latency_ms": st["p50_sweep_ms"], "p99_sweep_latency_ms": st["p99_sweep_ms"],
-                              "requests": st["requests"], "wall_s": st["wall_s"], "mean_queue_s": st["mean_queue_s"],
-                              "capacity_requests_per_s": capacity},
+                              "moves_per_s": st["moves_per_s"], "requests": st["requests"],
+                              "rejected": st["rejected"], "failed": st["failed"], "wall_s": st["wall_s"],
+                              "mean_queue_s": st["mean_queue_s"], "capacity_requests_per_s": capacity},
         "at_0.8_capacity": {"rate_per_s": rate, "p50_sweep_latency_ms": st2["p50_sweep_ms"],
                             "p99_sweep_latency_ms": st2["p99_sweep_ms"], "moves_per_s": st2["moves_per_s"],
-                            "wall_s": st2["wall_s"], "mean_queue_s": st2["mean_queue_s"]},
+                            "requests": st2["requests"], "wall_s": st2["wall_s"],
+                            "mean_queue_s": st2["mean_queue_s"]},
+    }
+
+
+def bench_served(args) -> int:
+    """The served streams alone (--mode served): value = aggregate electron-moves/s at 20/s."""
+    sv = served_block(args)
+    st = sv["overload_20_per_s"]
+    line = {
+        "metric": METRIC, "value": st["moves_per_s"], "unit": "electron-moves/s", "n_gpus": 1,
+        "steps": st["requests"], "warmup": 0, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic", "config": {"workload": sv["workload"]}, "served": sv,
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -59,6 +59,9 @@ class Request:
     dmc_feedback: float = 1.0             # DMC: E_T feedback constant (hartree)
     stats: Optional[object] = None        # DMC: device tensor [steps][6] of per-step statistics
     stream: Optional[object] = None       # DMC: the request's own stream
+    table_fn: Optional[object] = None     # makes the request's table when it is prepared (wl.coefs None)
+    status: str = "queued"                # "done"; "rejected" (can never fit the budget); "failed"
+    error: str = ""                       # why a request was rejected or failed
 
 
 class Server:
@@ -70,13 +73,13 @@ class Server:
                  graph: bool = False, prep_threads: int = 2):
         import torch
         self.torch = torch
-        free, total = torch.cuda.mem_get_info()
-        budget = free - reserve_bytes
+        gpu = torch.cuda.is_available()
+        budget = torch.cuda.mem_get_info()[0] - reserve_bytes if gpu else 0
         if hbm_budget_bytes is not None:
-            budget = min(budget, hbm_budget_bytes)
+            budget = min(budget, hbm_budget_bytes) if gpu else hbm_budget_bytes
         self.budget = max(0, int(budget))
         self.graph = graph
-        self.stream = torch.cuda.Stream()
+        self.stream = torch.cuda.Stream() if gpu else None
         self.prep_threads = prep_threads
 
     def run(self, requests, time_scale: float = 1.0, log=None):
@@ -91,20 +94,25 @@ class Server:
         batch = None
         dirty = True
         n_sweep_iters = 0
-        prep_streams = [torch.cuda.Stream() for _ in range(self.prep_threads)]
+        prep_streams: dict = {}   # created on first use (a trace whose requests are all rejected needs none)
         t0 = time.perf_counter()
 
         def prepare(r, k):
+            wl = r.wl
+            if wl.coefs is None:   # the request's own table, made while others sweep
+                wl = dataclasses.replace(wl, coefs=r.table_fn())
             if r.kind == "dmc":
                 # a DMC request keeps its own stream: its steps overlap the fused VMC sweeps
                 r.stream = torch.cuda.Stream()
                 with torch.cuda.stream(r.stream):
-                    s = qmc.System(r.wl, stream=r.stream)
+                    s = qmc.System(wl, stream=r.stream)
                     s.dmc_init(r.dmc_target, feedback=r.dmc_feedback)
                     r.stats = torch.zeros((r.n_sweeps, 6), dtype=torch.float64, device="cuda")
                     return s
+            if k not in prep_streams:
+                prep_streams[k] = torch.cuda.Stream() if torch.cuda.is_available() else None
             with torch.cuda.stream(prep_streams[k]):
-                return qmc.System(r.wl, stream=prep_streams[k])
+                return qmc.System(wl, stream=prep_streams[k])
 
         with cf.ThreadPoolExecutor(max_workers=self.prep_threads) as pool, torch.cuda.stream(self.stream):
             n_sub = 0
@@ -114,9 +122,17 @@ class Server:
                     queue.append(pending.popleft())
                 while queue:   # admission by device memory (first come, first served)
                     r = queue[0]
-                    if r.est_bytes > self.budget:
-                        raise qmc.QMCError(qmc.QMC_ERR_OOM, f"request {r.rid} needs {r.est_bytes} bytes, "
-                                           f"more than the whole budget {self.budget}")
+                    if r.est_bytes > self.budget or r.est_bytes <= 0:
+                        # can never fit (or has no valid size): refused, the others go on
+                        queue.popleft()
+                        r.status = "rejected"
+                        r.error = (f"needs {r.est_bytes} bytes of device memory, the whole budget is "
+                                   f"{self.budget}")
+                        r.finished_s = time.perf_counter() - t0
+                        finished.append(r)
+                        if log:
+                            log(f"[serve] reject {r.rid}: {r.error}")
+                        continue
                     if used + r.est_bytes > self.budget:
                         break
                     queue.popleft()
@@ -130,7 +146,17 @@ class Server:
                 still_prep = []
                 for r, f in preparing:
                     if f.done():
-                        r.system = f.result()
+                        try:
+                            r.system = f.result()
+                        except Exception as ex:   # this request fails alone; its memory is released
+                            used -= r.est_bytes
+                            r.status = "failed"
+                            r.error = str(ex)
+                            r.finished_s = time.perf_counter() - t0
+                            finished.append(r)
+                            if log:
+                                log(f"[serve] request {r.rid} failed in preparation: {ex}")
+                            continue
                         r.admitted_s = time.perf_counter() - t0
                         r.last_done_s = r.admitted_s
                         active.append(r)
@@ -177,6 +203,7 @@ class Server:
                         else:
                             r.energy = r.system.last_energies()
                         r.final_pos = r.system.get_walkers()[0]
+                        r.status = "done"
                         r.finished_s = time.perf_counter() - t0
                         r.system.close()
                         r.system = None
@@ -189,6 +216,8 @@ class Server:
         if batch is not None:
             batch.close()
         wall = time.perf_counter() - t0
+        refused = [r for r in finished if r.status != "done"]
+        finished = [r for r in finished if r.status == "done"]
         lat = np.array([x for r in finished for x in r.latencies_ms])
         def moves_of(r):
             if r.kind == "dmc":   # electrons of the walkers alive at each step
@@ -207,21 +236,28 @@ class Server:
             "sweep_iterations": n_sweep_iters,
             "p50_sweep_ms": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_sweep_ms": float(np.percentile(lat, 99)) if lat.size else None,
-            "mean_queue_s": float(np.mean([r.admitted_s - r.arrival_s * time_scale for r in finished])),
+            "mean_queue_s": float(np.mean([r.admitted_s - r.arrival_s * time_scale for r in finished]))
+            if finished else None,
             "dmc_requests": sum(r.kind == "dmc" for r in finished),
+            "rejected": sum(r.status == "rejected" for r in refused),
+            "failed": sum(r.status == "failed" for r in refused),
             "finished": finished,
+            "refused": refused,
         }
 
 
 def build_requests(trace, sweep_scale: float = 1.0, max_workers: int = 8, table_pool: bool = False,
                    log=None, dmc_every: int = 0):
     """Requests for a trace of ``qmc_inputs.served_trace`` entries, each a solid-like mixed-precision
-    system.  Tables are generated on the host before serving starts: per request with seed = its
-    id, or, with ``table_pool``, as the first n_orb orbitals of one 512-orbital table per grid size
-    (seed = grid), which keeps generation of a long trace to a few tables; the served arithmetic
-    does not depend on the coefficient values.  With ``dmc_every`` = k > 0 every k-th request is a
-    DMC run instead (drift-diffusion moves with sigma 0.3 / sqrt(N), 7/8 of its walkers as the
-    target population, feedback 1 hartree, as many steps as the request's sweeps)."""
+    system with its own table.  Tables are generated on the host before serving starts: per
+    request with seed = its id, or, with ``table_pool``, from one orbital bank per grid size
+    (seed = grid, as many orbitals as the largest request of that grid): a request takes a cyclic
+    window of the bank's orbitals, translated periodically on the grid and with signs, all drawn
+    from its own seed (``qmc_inputs.request_table``).  A translated window of a stationary random
+    field is again a draw of that field, so every request still has random smooth orbitals of its
+    own, and a long trace needs only a few filtered tables.  With ``dmc_every`` = k > 0 every k-th
+    request is a DMC run instead (drift-diffusion moves with sigma 0.3 / sqrt(N), 7/8 of its walkers
+    as the target population, feedback 1 hartree, as many steps as the request's sweeps)."""
     import qmc_inputs as qi
 
     pool: dict = {}
@@ -232,23 +268,25 @@ def build_requests(trace, sweep_scale: float = 1.0, max_workers: int = 8, table_
             tabs = list(ex.map(lambda g: qi.solid_table(need[g], g, seed=g, dtype=np.float32), grids))
         pool = dict(zip(grids, tabs))
         if log:
-            log(f"[serve] table pool: grids {grids}")
+            log(f"[serve] orbital banks: grids {grids}")
 
     def make(e):
         wl = qi.solid(e["n_elec"], 4 if table_pool else e["grid"], n_walkers=e["n_walkers"], n_sweeps=1,
                       precision="mixed", table_dtype=np.float32, delay_rank=16, recompute_period=64,
                       seed=e["seed"], name=f"req{e['id']}")
+        table_fn = None
         if table_pool:
             g = e["grid"]
             wl.grid = (g, g, g)
-            wl.coefs = np.ascontiguousarray(pool[g][..., :wl.n_orb])
+            wl.coefs = None
+            table_fn = (lambda bank=pool[g], n=wl.n_orb, sd=e["seed"]: qi.request_table(bank, n, sd))
         wl.delay_rank = delay_rank_for(wl)
         n = max(1, int(round(e["n_sweeps"] * sweep_scale)))
         dmc = dmc_every > 0 and e["id"] % dmc_every == dmc_every - 1
         if dmc:
             wl = dataclasses.replace(wl, all_electron=True, drift=True, sigma=0.3 / np.sqrt(wl.n_elec))
         r = Request(rid=e["id"], arrival_s=e["arrival_s"], wl=wl, n_sweeps=n, kind="dmc" if dmc else "vmc",
-                    dmc_target=max(1, wl.n_walkers * 7 // 8) if dmc else 0)
+                    dmc_target=max(1, wl.n_walkers * 7 // 8) if dmc else 0, table_fn=table_fn)
         r.est_bytes = qmc.estimate_device_bytes(wl, wl.n_walkers)
         if log:
             log(f"[serve] request {r.rid}: N={wl.n_elec} grid={e['grid']} W={wl.n_walkers} "

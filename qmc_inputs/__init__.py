@@ -29,7 +29,7 @@ import numpy as np
 
 __all__ = [
     "Workload", "cell_side", "heg_shell", "heg_coefficients", "heg",
-    "solid_table", "bspline_jastrow_params", "solid", "heg14", "solid128",
+    "solid_table", "request_table", "bspline_jastrow_params", "solid", "heg14", "solid128",
     "mixed384", "batched_systems", "served_trace", "WORKLOADS",
 ]
 
@@ -176,6 +176,26 @@ def solid_table(n_orb: int, grid: int, seed: int, width_cells: float = 4.0,
         sm = np.fft.ifftn(np.fft.fftn(noise) * H).real
         sm /= math.sqrt(float(np.mean(sm * sm)))
         out[..., j] = sm.astype(np.float32)
+    return out
+
+
+def request_table(bank: np.ndarray, n_orb: int, seed: int) -> np.ndarray:
+    """A request's own table from an orbital bank [G][G][G][M] of ``solid_table``: the cyclic
+    window of n_orb orbitals starting at a seeded offset, translated on the periodic grid by a
+    seeded shift per axis, each orbital with a seeded sign.  Translation, selection and sign
+    keep the orbitals draws of the same stationary filtered field."""
+    rng = np.random.default_rng([seed, 0x7AB1E])
+    G, M = bank.shape[0], bank.shape[3]
+    if n_orb > M:
+        raise ValueError("the bank holds fewer orbitals than requested")
+    start = int(rng.integers(0, M))
+    idx = (start + np.arange(n_orb)) % M
+    shift = rng.integers(0, G, size=3)
+    sign = np.where(rng.random(n_orb) < 0.5, -1.0, 1.0).astype(bank.dtype)
+    # out[x, y, z, j] = sign_j bank[x - sx, y - sy, z - sz, idx_j] (periodic), one gather
+    ax = [(np.arange(G) - int(sh)) % G for sh in shift]
+    out = bank[np.ix_(ax[0], ax[1], ax[2], idx)]
+    out *= sign
     return out
 
 

@@ -137,3 +137,59 @@ def test_served_request_mix_without_gpu(libqmc):
             assert r.est_bytes > vmc_like
         else:
             assert not r.wl.all_electron
+
+
+def test_server_refuses_a_request_that_can_never_fit(libqmc):
+    """A request larger than the whole device-memory budget is refused and recorded; the loop
+    goes on with the rest (here: nothing else, so no GPU work at all)."""
+    import qmc_inputs as qi
+    from paper_1802_06922_amd import qmc, serve
+    qmc.load_library()
+    trace = qi.served_trace(n_requests=3, rate_per_s=1000.0, seed=0)
+    for e in trace:
+        e["n_elec"], e["grid"], e["n_walkers"] = 16, 8, 8
+    reqs = serve.build_requests(trace, sweep_scale=0.01, table_pool=True)
+    srv = serve.Server(hbm_budget_bytes=min(r.est_bytes for r in reqs) - 1)
+    st = srv.run(reqs)
+    assert st["requests"] == 0 and st["rejected"] == 3 and st["failed"] == 0
+    assert all(r.status == "rejected" and "budget" in r.error for r in st["refused"])
+
+
+def test_server_records_a_failed_preparation(libqmc, monkeypatch):
+    """A request whose preparation raises finishes as failed and gives its memory back."""
+    import qmc_inputs as qi
+    from paper_1802_06922_amd import qmc, serve
+    qmc.load_library()
+    trace = qi.served_trace(n_requests=2, rate_per_s=1000.0, seed=0)
+    for e in trace:
+        e["n_elec"], e["grid"], e["n_walkers"] = 16, 8, 8
+    reqs = serve.build_requests(trace, sweep_scale=0.01)
+
+    def boom(*a, **k):
+        raise qmc.QMCError(qmc.QMC_ERR_SINGULAR, "singular start")
+
+    monkeypatch.setattr(qmc, "System", boom)
+    srv = serve.Server(hbm_budget_bytes=sum(r.est_bytes for r in reqs))
+    st = srv.run(reqs)
+    assert st["requests"] == 0 and st["failed"] == 2 and st["rejected"] == 0
+    assert all("singular" in r.error for r in st["refused"])
+
+
+def test_request_tables_are_translated_windows_of_the_bank():
+    """A served request's own table: a seeded cyclic window of the bank's orbitals, translated on
+    the periodic grid, with seeded signs (checked entry by entry against np.roll)."""
+    import numpy as np
+
+    import qmc_inputs as qi
+    bank = qi.solid_table(12, 8, seed=8)
+    t = qi.request_table(bank, 5, seed=3)
+    assert t.shape == (8, 8, 8, 5) and t.dtype == np.float32
+    # recover the common shift and the window start from the seeded draw, then compare exactly
+    rng = np.random.default_rng([3, 0x7AB1E])
+    start = int(rng.integers(0, 12))
+    shift = rng.integers(0, 8, size=3)
+    sign = np.where(rng.random(5) < 0.5, -1.0, 1.0)
+    idx = (start + np.arange(5)) % 12
+    want = np.roll(bank[..., idx], shift=tuple(int(x) for x in shift), axis=(0, 1, 2)) * sign.astype(np.float32)
+    assert np.array_equal(t, want)
+    assert not np.array_equal(t, qi.request_table(bank, 5, seed=4))
