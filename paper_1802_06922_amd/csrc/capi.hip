@@ -724,7 +724,8 @@ qmc_status qmc_load_spline_table(qmc_system s, int32_t gx, int32_t gy, int32_t g
     const unsigned char* hs = static_cast<const unsigned char*>(coefs);
     if (coefs_on_device) {
       src.resize(pts * n_orb * dtype);
-      HIP_TRY(s, hipMemcpy(src.data(), coefs, src.size(), hipMemcpyDeviceToHost));
+      HIP_TRY(s, hipMemcpyAsync(src.data(), coefs, src.size(), hipMemcpyDeviceToHost, s->stream));
+      HIP_TRY(s, hipStreamSynchronize(s->stream));
       hs = src.data();
     }
     const size_t chunk = 1 << 16;   // points per staging chunk
@@ -740,8 +741,11 @@ qmc_status qmc_load_spline_table(qmc_system s, int32_t gx, int32_t gy, int32_t g
           if (ts == 8) reinterpret_cast<double*>(stage.data())[p * S + j] = v;
           else reinterpret_cast<float*>(stage.data())[p * S + j] = (float)v;
         }
-      HIP_TRY(s, hipMemcpy(static_cast<char*>(s->d_table) + p0 * S * ts, stage.data(), np * S * ts,
-                           hipMemcpyHostToDevice));
+      // stream-ordered (a synchronous copy would touch the null stream, which another thread's
+      // graph capture must not see); the staging buffer is reused, so each chunk completes first
+      HIP_TRY(s, hipMemcpyAsync(static_cast<char*>(s->d_table) + p0 * S * ts, stage.data(), np * S * ts,
+                                hipMemcpyHostToDevice, s->stream));
+      HIP_TRY(s, hipStreamSynchronize(s->stream));
     }
   }
   s->P.gx = gx;
@@ -866,7 +870,8 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
       double y = x - s->d.L * std::floor(x / s->d.L);
       wp[q] = (y >= s->d.L) ? 0.0 : y;
     }
-    HIP_TRY(s, hipMemcpy(s->pos, wp.data(), wp.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(s, hipMemcpyAsync(s->pos, wp.data(), wp.size() * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
   }
   HIP_TRY(s, hipMemsetAsync(s->nguard, 0, z.nguard, s->stream));
   HIP_TRY(s, hipMemsetAsync(s->sweep_ctr, 0, z.sweep, s->stream));
@@ -1140,10 +1145,11 @@ qmc_status qmc_dmc_init(qmc_system s, int32_t n_target, double e_trial, double f
   }
   const double ctl[2] = {std::isnan(e_trial) ? se / n_target : e_trial, feedback};
   const int ictl[3] = {0, 0, n_target};
-  HIP_TRY(s, hipMemcpy(s->dmc_E, E.data(), W * sizeof(double), hipMemcpyHostToDevice));
-  HIP_TRY(s, hipMemcpy(s->dmc_w, w.data(), W * sizeof(double), hipMemcpyHostToDevice));
-  HIP_TRY(s, hipMemcpy(s->dmc_ctl, ctl, sizeof ctl, hipMemcpyHostToDevice));
-  HIP_TRY(s, hipMemcpy(s->dmc_i + 5 * (size_t)W, ictl, sizeof ictl, hipMemcpyHostToDevice));
+  HIP_TRY(s, hipMemcpyAsync(s->dmc_E, E.data(), W * sizeof(double), hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(s, hipMemcpyAsync(s->dmc_w, w.data(), W * sizeof(double), hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(s, hipMemcpyAsync(s->dmc_ctl, ctl, sizeof ctl, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(s, hipMemcpyAsync(s->dmc_i + 5 * (size_t)W, ictl, sizeof ictl, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(s, hipStreamSynchronize(s->stream));
   s->dmc_ready = true;
   return QMC_OK;
 }
@@ -1285,7 +1291,7 @@ qmc_status qmc_eval_spo_vgl(qmc_system s, int32_t n, const double* pos, double* 
   const size_t ob = (size_t)n * kComp * s->P.n_orb * sizeof(double);
   HIP_TRY(s, hipMalloc(&dp, (size_t)n * 3 * sizeof(double)));
   hipError_t e = hipMalloc(&dout, ob);
-  if (e == hipSuccess) e = hipMemcpy(dp, pos, (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpyAsync(dp, pos, (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice, s->stream);
   if (e == hipSuccess) {
     if (s->d.precision == QMC_MIXED)
       e = launch_eval_points<float>(s->P, static_cast<const float*>(s->d_table), dp, n, dout, s->stream);
@@ -1293,7 +1299,8 @@ qmc_status qmc_eval_spo_vgl(qmc_system s, int32_t n, const double* pos, double* 
       e = launch_eval_points<double>(s->P, static_cast<const double*>(s->d_table), dp, n, dout, s->stream);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-  if (e == hipSuccess) e = hipMemcpy(out, dout, ob, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, dout, ob, hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   (void)hipFree(dp);
   if (dout) (void)hipFree(dout);
   if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "eval_spo_vgl: %s", hipGetErrorString(e));
@@ -1465,6 +1472,7 @@ struct qmc_batch_s {
   size_t lds_cl = 0, lds_cg = 0, lds_m = 0;
   int use_mfma = 1;
   bool use_graph = false;
+  int graph_fallbacks = 0;   // captures invalidated from outside (the batch then launches eagerly)
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   // ordering against the members' own streams: one event per distinct member stream
   // (work queued there before a batch sweep) and one on the batch stream (after it)
@@ -1560,8 +1568,9 @@ qmc_status batch_build(qmc_batch b) {
   all.insert(all.end(), cg.begin(), cg.end());
   all.insert(all.end(), m.begin(), m.end());
   all.insert(all.end(), f.begin(), f.end());
-  BHIP_TRY(b, hipMemcpy(b->d_sysdev, sd.data(), sizeof(SysDev<T>) * n, hipMemcpyHostToDevice));
-  BHIP_TRY(b, hipMemcpy(b->d_maps, all.data(), sizeof(int2) * nm, hipMemcpyHostToDevice));
+  BHIP_TRY(b, hipMemcpyAsync(b->d_sysdev, sd.data(), sizeof(SysDev<T>) * n, hipMemcpyHostToDevice, b->stream));
+  BHIP_TRY(b, hipMemcpyAsync(b->d_maps, all.data(), sizeof(int2) * nm, hipMemcpyHostToDevice, b->stream));
+  BHIP_TRY(b, hipStreamSynchronize(b->stream));
   return QMC_OK;
 }
 
@@ -1663,6 +1672,15 @@ qmc_status qmc_batch_sweep(qmc_batch b, int32_t n_sweeps, int32_t measure) {
     BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
     const hipError_t e = batch_launch_any(b, 1, v);
     const hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
+    if (e2 == hipErrorStreamCaptureInvalidated && e == hipSuccess) {
+      // the capture was invalidated from outside the batch's launches (another thread's work on
+      // the device): nothing captured ran, so this batch goes on with ordinary launches
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      b->use_graph = false;
+      b->graph_fallbacks += 1;
+      return QMC_OK;
+    }
     if (e != hipSuccess || e2 != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
       return bfail(b, QMC_ERR_DEVICE, "sweep capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));

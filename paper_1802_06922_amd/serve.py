@@ -94,7 +94,10 @@ class Server:
         batch = None
         dirty = True
         n_sweep_iters = 0
-        prep_streams: dict = {}   # created on first use (a trace whose requests are all rejected needs none)
+        # every stream is made here, by the serving thread, never by a preparation thread while
+        # the serving thread may be capturing a sweep graph
+        gpu = torch.cuda.is_available()
+        prep_streams = [torch.cuda.Stream() if gpu else None for _ in range(self.prep_threads)]
         t0 = time.perf_counter()
 
         def prepare(r, k):
@@ -102,15 +105,13 @@ class Server:
             if wl.coefs is None:   # the request's own table, made while others sweep
                 wl = dataclasses.replace(wl, coefs=r.table_fn())
             if r.kind == "dmc":
-                # a DMC request keeps its own stream: its steps overlap the fused VMC sweeps
-                r.stream = torch.cuda.Stream()
+                # a DMC request keeps its own stream (made at admission): its steps overlap the
+                # fused VMC sweeps
                 with torch.cuda.stream(r.stream):
                     s = qmc.System(wl, stream=r.stream)
                     s.dmc_init(r.dmc_target, feedback=r.dmc_feedback)
                     r.stats = torch.zeros((r.n_sweeps, 6), dtype=torch.float64, device="cuda")
                     return s
-            if k not in prep_streams:
-                prep_streams[k] = torch.cuda.Stream() if torch.cuda.is_available() else None
             with torch.cuda.stream(prep_streams[k]):
                 return qmc.System(wl, stream=prep_streams[k])
 
@@ -137,6 +138,8 @@ class Server:
                         break
                     queue.popleft()
                     used += r.est_bytes
+                    if r.kind == "dmc" and gpu:
+                        r.stream = torch.cuda.Stream()
                     preparing.append((r, pool.submit(prepare, r, n_sub % self.prep_threads)))
                     n_sub += 1
                 # prepared requests join at this sweep boundary (and the loop waits for one
