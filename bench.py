@@ -270,100 +270,47 @@ def chain_roofline(wl, r):
                     "cores are busy only in the window products and flushes"}
 
 
-def fp64_beside(mixed_wl, rm):
+def fp64_beside(mixed_wl, rm, agree_sweeps: int = 8):
     """The same 384-electron system in FP64 (the FP32-valued table stored in FP64, FP64 updates,
     no guard) with its autotuned delay rank, and the plain FP64 sweep (Sherman-Morrison, rank 1),
-    for as many steps as the mixed run; the mixed energies against the FP64 ones at the same
-    walker positions (the mixed path takes the FP64 decisions, so the walkers coincide)."""
+    for as many steps as the mixed run.  Then the agreement of the two precisions: fresh mixed
+    and FP64 systems (same seeds) run sweep for sweep with a measurement after each; the mixed
+    path must take the FP64 decisions, and its local energies are compared one to one."""
     import dataclasses
 
     import numpy as np
+
+    from paper_1802_06922_amd import System
     steps = rm["steps"]
     fp64 = dataclasses.replace(mixed_wl, precision="fp64", coefs=mixed_wl.coefs.astype(np.float64),
                                recompute_period=0, name="solid384_fp64")
     plain = dataclasses.replace(fp64, name="solid384_fp64_plain")
     out = {}
-    runs = {}
     for tag, wl, K in (("fp64", fp64, None), ("fp64_plain", plain, 1)):
         r = run_single(wl, steps, 1, K)
-        runs[tag] = r
         out[tag] = {"moves_per_s": r["value"], "ms_per_step": r["ms_per_step"], "delay_rank": r["delay_rank"],
                     "steps": r["steps"],
                     "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in r["kt"].items()}}
     out["mixed_over_fp64"] = rm["value"] / out["fp64"]["moves_per_s"]
     out["mixed_over_fp64_plain"] = rm["value"] / out["fp64_plain"]["moves_per_s"]
-    same = bool(np.array_equal(rm["positions"], runs["fp64"]["positions"]))
-    em, ef = rm["energies"], runs["fp64"]["energies"]
-    rel = np.abs(em - ef) / np.maximum(np.abs(ef), 1.0)
-    out["mixed_energy_error_vs_fp64"] = {
-        "same_walker_positions": same, "components": "kinetic, e-e, e-I, I-I per walker, last step",
-        "max": float(rel.max()), "p99": float(np.percentile(rel, 99)), "median": float(np.median(rel))}
+    print(f"[bench] mixed vs FP64 agreement: {agree_sweeps} sweeps of both", file=sys.stderr, flush=True)
+    sm, sf = System(mixed_wl), System(dataclasses.replace(fp64, delay_rank=16))
+    same, rel = True, []
+    for _ in range(agree_sweeps):
+        sm.sweep(1)
+        sf.sweep(1)
+        same = same and bool(np.array_equal(sm.accept_log(), sf.accept_log()))
+        em, ef = sm.measure(), sf.measure()
+        rel.append(np.abs(em - ef) / np.maximum(np.abs(ef), 1.0))
+    sm.close()
+    sf.close()
+    rel = np.concatenate(rel)
+    out["mixed_vs_fp64_agreement"] = {
+        "sweeps": agree_sweeps, "same_decisions": same,
+        "components": "kinetic, e-e, e-I, I-I of every walker after every sweep",
+        "max_rel_energy_difference": float(rel.max()), "p99": float(np.percentile(rel, 99)),
+        "median": float(np.median(rel))}
     return out
-
-
-def run_single(wl, steps: int, warmup: int, delay, lanes=None, serial: bool = False):
-    """Steps of (sweep + local energy) of one system; the delay rank is autotuned when not given
-    (the trial sweeps are ordinary sweeps, before the timed region)."""
-    import torch
-
-    from paper_1802_06922_amd import KERNEL_CHAIN, KERNEL_GATHER, KERNEL_MEASURE, KERNEL_REBUILD, System
-    if wl.recompute_period > 0 and steps % wl.recompute_period and not wl.all_electron:
-        # the timed window holds whole rebuild periods, so it pays for every FP64 rebuild
-        steps = (steps // wl.recompute_period + 1) * wl.recompute_period
-    if delay is not None:
-        wl.delay_rank = delay
-    print(f"[bench] building {wl.name}", file=sys.stderr, flush=True)
-    s = System(wl)
-    if lanes is None:
-        lanes_log2, _ = s.autotune_gather(trial_sweeps=3)
-    else:
-        s.set_gather_lanes(lanes)
-        lanes_log2 = lanes
-    if wl.all_electron:
-        K = None   # no update chain: every accepted move installs fresh inverses
-    elif delay is None:
-        K, _ = s.autotune_delay(ranks=(1, 8, 16, 32, 64), trial_sweeps=3)
-        print(f"[bench] {wl.name}: delay rank {K}, gather lanes 2^{lanes_log2} (autotuned)",
-              file=sys.stderr, flush=True)
-    else:
-        K = delay
-    W, N = s.W, wl.n_elec
-    # every step's energies stay on the device; steps run pipelined (qmc_run_steps: a step's
-    # measurement beside the next step's proposals)
-    energies = torch.empty((max(steps, warmup, 1), W, 4), dtype=torch.float64, device="cuda")
-    def run(n, out):
-        if serial:
-            for k in range(n):
-                s.sweep(1)
-                s.measure(out=out[k])
-        else:
-            s.run_steps(n, out)
-
-    if warmup:
-        run(warmup, energies[:warmup])
-    torch.cuda.synchronize()
-    s.set_timing(True)
-    for k in (KERNEL_GATHER, KERNEL_CHAIN, KERNEL_MEASURE, KERNEL_REBUILD):
-        s.kernel_timing(k, reset=True)
-    print(f"[bench] {wl.name}: timing {steps} steps", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run(steps, energies[:steps])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    kt = {name: s.kernel_timing(k) for name, k in
-          (("gather", KERNEL_GATHER), ("chain", KERNEL_CHAIN), ("measure", KERNEL_MEASURE))}
-    rebuild = s.kernel_timing(KERNEL_REBUILD)
-    e_host = energies[steps - 1].cpu().numpy()
-    acceptance = float(s.accept_log().mean())
-    pos_host = s.get_walkers()[0]
-    s.close()
-    moves = W * N * steps
-    sweep_ms = (kt["gather"][0] + kt["chain"][0]) / steps
-    return {"value": moves / dt, "ms_per_step": dt / steps * 1e3, "kt": kt, "walkers": W, "steps": steps,
-            "rebuilds": {"launches": rebuild[1], "ms_per_launch": rebuild[0] / max(rebuild[1], 1)},
-            "delay_rank": K, "gather_lanes_log2": lanes_log2, "acceptance": acceptance, "sweep_only_moves_per_s": moves / (sweep_ms * steps / 1e3) if sweep_ms > 0 else None,
-            "mean_local_energy": float(e_host.sum(axis=1).mean()), "energies": e_host, "positions": pos_host}
 
 
 def bench_dmc(args) -> int:

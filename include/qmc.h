@@ -88,7 +88,11 @@ typedef enum { QMC_H_KINETIC = 0, QMC_H_COULOMB_EWALD = 1 } qmc_hamiltonian;
  *                 (j1_params = p_1..p_M, j1_rcut, cusp j1_cusp)
  *  tie_guard      MIXED only: relative half-width of the band around each
  *                 acceptance threshold inside which the decision is re-taken
- *                 in FP64 (0 = library default 1e-3)
+ *                 in FP64 (0 = library default 1e-3).  The library widens
+ *                 each move's band by bounds on the FP32 rounding of its
+ *                 ratio and on the error of the walker's FP32 inverse (its
+ *                 measured residual I - A B), so that the mixed path takes
+ *                 the decisions of FP64 arithmetic.
  *  arena, arena_bytes  optional caller-owned device memory (e.g. from the
  *                 PyTorch caching allocator).  If arena != NULL every device
  *                 buffer of the handle is carved from it and nothing is
@@ -168,16 +172,20 @@ qmc_status qmc_create_system(const qmc_system_desc* desc, void* hip_stream, qmc_
 qmc_status qmc_load_spline_table(qmc_system s, int32_t gx, int32_t gy, int32_t gz, int32_t n_orb,
                                  const void* coefs, int32_t dtype, int32_t coefs_on_device);
 
-/* Create n_walkers walkers (>= 1).  pos: host [n_walkers][N][3] or NULL;
- * NULL draws uniform positions in the cell from the INIT stream of each
- * walker.  Builds the Slater matrices, inverts them in FP64 (Gauss-Jordan
+/* Create n_walkers walkers (>= 1), the starting distribution of the
+ * walkers of section "Variational Monte Carlo".  pos: host [n_walkers][N][3]
+ * or NULL; NULL draws every electron uniform in the cell from the INIT stream
+ * of its walker (no selection of the draws: an ill-conditioned start of a
+ * MIXED system runs in FP64 until it is well conditioned, see
+ * qmc_get_precision_stats).  Builds the Slater matrices, inverts them in FP64 (Gauss-Jordan
  * with partial pivoting) and resets the sweep counter to 0.  Errors: STATE
  * without a table; ARG; OOM; SINGULAR if any Slater matrix has a zero pivot
  * (the walkers are then unusable until re-initialised). */
 qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos);
 
-/* Run n_sweeps particle-by-particle sweeps of every walker.  Each sweep
- * proposes every electron once, in index order, and accepts with
+/* Run n_sweeps particle-by-particle sweeps of every walker (section "Trial
+ * Moves": sequential single-electron moves; equation accept_reject).  Each
+ * sweep proposes every electron once, in index order, and accepts with
  * probability min(1, R^2 exp(2 dJ)), R the determinant ratio and dJ the
  * Jastrow change.  With move_kind QMC_MOVE_ALL or QMC_MOVE_ALL_DRIFT a sweep
  * is instead one all-electron move per walker (see qmc_system_desc), an
@@ -192,8 +200,10 @@ qmc_status qmc_sweep(qmc_system s, int32_t n_sweeps, uint64_t* n_accepted_out);
  * are Ewald sums with a uniform neutralising background where the charge
  * does not cancel, each independent of the Ewald splitting.  MIXED: the
  * kinetic part reads an inverse refined by one FP64 correction step
- * X = B + B (I - A B) against the FP64 Slater matrix A (the FP32 inverse
- * itself is left as the chain keeps it).  out_on_device: 0 = host buffer
+ * X = B + B (I - A B) against the FP64 Slater matrix A, and the chain goes on
+ * from X (the FP32 updates' drift is squared away; decisions are unchanged,
+ * see qmc_get_precision_stats); walkers in the FP64 fallback read their FP64
+ * inverse with the orbitals evaluated in FP64.  out_on_device: 0 = host buffer
  * (synchronises), 1 = device buffer (asynchronous).
  * Errors: STATE; DEVICE; NUMERIC (host output only) if a value is not finite. */
 qmc_status qmc_measure_local_energy(qmc_system s, double* out, int32_t out_on_device);
@@ -245,7 +255,8 @@ qmc_status qmc_dmc_steps(qmc_system s, int32_t n_steps, double* stats_dev);
  * out (the state is still returned). */
 qmc_status qmc_dmc_get(qmc_system s, double* weights, double* energies, double* e_trial, int32_t* population);
 
-/* Copy walker state to host buffers (each nullable): pos[W][N][3];
+/* Walker state (section "Code structure": walkers persist between steps), copied
+ * to host buffers (each nullable): pos[W][N][3];
  * logabs_det[W][2] = log|D_up|, log|D_dn| accumulated as the sum of
  * log|R| of the accepted moves since the last full inverse; sign[W][2]. */
 qmc_status qmc_get_walkers(qmc_system s, double* pos, double* logabs_det, int32_t* sign);

@@ -112,6 +112,7 @@ struct qmc_system_s {
   double* binv64 = nullptr;
   int* fb = nullptr;
   double* eta = nullptr;
+  float* ecol = nullptr;
   uint32_t* eta_age = nullptr;
   uint32_t* pstat = nullptr;
   uint32_t* fbmark = nullptr;
@@ -179,6 +180,7 @@ Walkers<T> walkers_of(qmc_system s) {
   w.fb = s->fb;
   w.fb_sel = 0;
   w.eta = s->eta;
+  w.ecol = s->ecol;
   w.eta_age = s->eta_age;
   w.pstat = s->pstat;
   w.table = static_cast<const T*>(s->d_table);
@@ -197,6 +199,7 @@ Walkers<double> fallback_of(qmc_system s) {
   w.binv64 = nullptr;
   w.fb_sel = 1;
   w.eta = nullptr;
+  w.ecol = nullptr;
   w.eta_age = nullptr;
   w.table = nullptr;
   return w;
@@ -385,6 +388,7 @@ void free_walkers(qmc_system s) {
   s->val64 = nullptr;
   s->xinv = nullptr;
   s->binv64 = s->eta = nullptr;
+  s->ecol = nullptr;
   s->fb = nullptr;
   s->eta_age = s->pstat = s->fbmark = nullptr;
   s->nguard = nullptr;
@@ -401,14 +405,15 @@ void free_walkers(qmc_system s) {
 
 struct WalkerSizes {
   size_t pos, prop, vgl, cur, binv, logdet, sign, acc, nacc, status, scratch, drift, energy, val64, nguard, sweep,
-      xinv, binv64, fb, eta, eta_age, pstat, fbmark, ae_binv, ae_logdet, ae_dj, ae_sign, ae_status, ae_vel, ae_logT,
+      xinv, binv64, fb, eta, ecol, eta_age, pstat, fbmark, ae_binv, ae_logdet, ae_dj, ae_sign, ae_status, ae_vel, ae_logT,
       dmc;
   size_t total() const {
     return align_up(pos) + align_up(prop) + align_up(vgl) + align_up(cur) + align_up(binv) +
            align_up(logdet) + align_up(sign) + align_up(acc) + align_up(nacc) + align_up(status) +
            align_up(scratch) + align_up(drift) + align_up(energy) + align_up(val64) + align_up(nguard) +
            align_up(sweep) + align_up(xinv) +
-           (binv64 ? align_up(binv64) + align_up(fb) + align_up(eta) + align_up(eta_age) + align_up(pstat) +
+           (binv64 ? align_up(binv64) + align_up(fb) + align_up(eta) + align_up(ecol) + align_up(eta_age) +
+                         align_up(pstat) +
                          align_up(fbmark)
                    : 0) +
            (ae_binv ? align_up(ae_binv) + align_up(ae_logdet) + align_up(ae_dj) + align_up(ae_sign) +
@@ -441,6 +446,7 @@ WalkerSizes walker_sizes(int n_up, int n_dn, int precision, int W, int n_orb, in
   z.binv64 = fbk ? W * bs * sizeof(double) : 0;
   z.fb = fbk ? W * sizeof(int) : 0;
   z.eta = fbk ? W * 4 * sizeof(double) : 0;
+  z.ecol = fbk ? W * N * sizeof(float) : 0;
   z.eta_age = fbk ? W * sizeof(uint32_t) : 0;
   z.pstat = fbk ? W * 2 * sizeof(uint32_t) : 0;
   z.fbmark = fbk ? W * sizeof(uint32_t) : 0;
@@ -833,6 +839,7 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
     s->binv64 = static_cast<double*>(s->mem.alloc(z.binv64));
     s->fb = static_cast<int*>(s->mem.alloc(z.fb));
     s->eta = static_cast<double*>(s->mem.alloc(z.eta));
+    s->ecol = static_cast<float*>(s->mem.alloc(z.ecol));
     s->eta_age = static_cast<uint32_t*>(s->mem.alloc(z.eta_age));
     s->pstat = static_cast<uint32_t*>(s->mem.alloc(z.pstat));
     s->fbmark = static_cast<uint32_t*>(s->mem.alloc(z.fbmark));
@@ -854,7 +861,7 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
   if (!s->pos || !s->prop || !s->vgl || !s->cur || !s->binv || !s->logdet || !s->sign || !s->acc ||
       !s->nacc || !s->status || !s->scratch || !s->drift || !s->energy || !s->nguard || !s->sweep_ctr ||
       (s->d.precision == QMC_MIXED && (!s->val64 || !s->xinv)) ||
-      (z.binv64 && (!s->binv64 || !s->fb || !s->eta || !s->eta_age || !s->pstat || !s->fbmark)) ||
+      (z.binv64 && (!s->binv64 || !s->fb || !s->eta || !s->ecol || !s->eta_age || !s->pstat || !s->fbmark)) ||
       (ae && (!s->ae_binv || !s->ae_logdet || !s->ae_dj || !s->ae_sign || !s->ae_status)) ||
       (drift && (!s->ae_vcur || !s->ae_vprop || !s->ae_logT))) {
     free_walkers(s);

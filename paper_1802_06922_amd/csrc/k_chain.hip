@@ -133,6 +133,9 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, in
       ldb = n;
     }
     __syncthreads();
+    // mixed: the inverse error of B (its bound on ||v^T B|| is |v| ||B||_F)
+    const double weta = sizeof(T) == 4 ? walker_eta(Wk, w, sp, n) : 0.0;
+    const double bnorm = (sizeof(T) == 4 && Wk.eta) ? Wk.eta[4 * w + 2 + sp] : 0.0;
     // column split of the accept-path product t = v^T B: tpc threads per column
     int tpc = 1;
     while (tpc < 8 && tpc * 2 * n <= kBlock) tpc *= 2;
@@ -171,6 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, in
         if (k + C < n) issue_chunk(k + C);
       }
       const double rx = sprop[4 * k], ry = sprop[4 * k + 1], rz = sprop[4 * k + 2], u = sprop[4 * k + 3];
+      const double ec = sizeof(T) == 4 ? inverse_error_coef(Wk, w, i, N, weta) : 0.0;
 
       // determinant ratio (partial sums over this thread's own row elements)
       T rpart = T(0);
@@ -259,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, in
       // by the error of the inverse itself, ||v^T B|| <= |v| ||B||_F times its measured residual
       const double band = sizeof(T) == 4
           ? P.tie_guard + 2.0 * (n + 1) * 5.9604644775390625e-08 * Sm / fabs((double)R) + 2.4e-7 +
-                inverse_error_term(Wk, w, sp, n, sqrt(V2) * (Wk.eta ? Wk.eta[4 * w + 2 + sp] : 0.0), (double)R)
+                ec * sqrt(V2) * bnorm / fabs((double)R)
           : 0.0;
       if (sizeof(T) == 4 && fabs(u - p32) <= band * p32) {
         // near tie in FP32: decide again with an FP64 ratio (uniform branch)

@@ -39,14 +39,14 @@ constexpr int kMaxWindow = 64;
 constexpr int kLdsIonsD = 256;
 
 struct DLayout {
-  size_t pos, prop, ions, red, rmag, tn, gold, gdiff, cur, acc, plist, qlist, vwin, ywin, zwin, gx, gr, grow, b,
+  size_t pos, prop, ions, red, rmag, tn, vpre, gold, gdiff, cur, acc, plist, qlist, vwin, ywin, zwin, gx, gr, grow, b,
       total;
 };
 
 __host__ __device__ inline int round16(int x) { return (x + 15) & ~15; }
 
 __host__ __device__ inline DLayout dlayout(int N, int nmax, int n_ions, int ldl, size_t ts, bool b_in_lds,
-                                           int K) {
+                                           int K, bool prefetch = false) {
   DLayout L;
   const int nP = round16(nmax);
   size_t o = 0;
@@ -57,6 +57,8 @@ __host__ __device__ inline DLayout dlayout(int N, int nmax, int n_ions, int ldl,
   L.red = o; o += sizeof(double) * kBlock;
   L.rmag = o; o += (ts == 4) ? sizeof(double) * kBlock : 0;   // mixed: |v| . |B0[:, k]| partials
   L.tn = o; o += (ts == 4) ? sizeof(double) * kBlock : 0;     // mixed: |v^T B0|^2 partials
+  al(16);
+  L.vpre = o; o += prefetch ? ts * (size_t)K * (nP + 1) : 0;    // the next window's rows, prefetched
   // gold's storage later holds the window block yk with rows of K + 1 (bank spread) and
   // up to 7 entries read past its last row
   L.gold = o; o += sizeof(double) * ((size_t)K * (K + 1) + 8);
@@ -69,13 +71,13 @@ __host__ __device__ inline DLayout dlayout(int N, int nmax, int n_ions, int ldl,
   al(16);
   // Window rows V (dead after Y = V B0) share storage with the flush's Z, and the
   // flush's U = B0[:, P] reuses Y's storage once Z has been formed.
-  L.ywin = o; o += ts * (size_t)K * nP;
+  L.ywin = o; o += ts * (size_t)K * (nP + 1);   // Y rows (stride nP), or U transposed (stride nP + 1)
   al(16);
-  L.zwin = o; o += ts * (size_t)K * nP;
+  L.zwin = o; o += ts * (size_t)K * (nP + 1);   // Z rows (stride nP), or the window rows (stride nP + 1)
   L.vwin = L.zwin;
   al(16);
-  L.gx = o; o += (ts == 4) ? sizeof(double) * nmax : 0;   // FP64 re-decision scratch (mixed)
-  L.gr = o; o += (ts == 4) ? sizeof(double) * nmax : 0;
+  L.gx = o; o += (ts == 4) ? sizeof(double) * nP : 0;   // FP64 re-decision scratch (mixed)
+  L.gr = o; o += (ts == 4) ? sizeof(double) * nP : 0;
   L.grow = o; o += (ts == 4) ? ts * (size_t)nP : 0;        // the re-decided move's row
   al(16);
   L.b = o; o += b_in_lds ? ts * (size_t)nmax * ldl : 0;
@@ -283,7 +285,282 @@ __device__ __forceinline__ void flush_global(T* B, int ldb, const T* U, int ldu,
   }
 }
 
-template <typename T, bool BLDS, bool MF>
+// ---------------------------------------------------------------------------
+// The active spin block's inverse in registers for the whole sweep (FP32, spin blocks of up to
+// 16 NT electrons; used where the inverse does not fit the LDS).  B is cut into 16 x 16 tiles;
+// wave v owns the column tiles v, v + kWaves, ..., each with all its row tiles, in the layout
+// of a matrix-core accumulator: register r of tile (rt, ct) in lane l holds
+// B[16 rt + 4 (l / 16) + r][16 ct + l % 16].  Register r of a tile is also the second operand
+// of one 16x16x4 product step whose k index g = l / 16 stands for row 16 rt + 4 g + r, so the
+// window product Y = V B0 runs on the matrix cores straight from the registers (the first
+// operand, V, is read from LDS with the same row order), and the flush's rank-m update
+// accumulates into the tiles in place.  The inverse is read from and written to HBM once per
+// spin block and sweep.  Padding rows and columns (>= n) hold zeros throughout.
+// ---------------------------------------------------------------------------
+template <int NT> struct RegTiles {
+  static constexpr int CT = (NT + kWaves - 1) / kWaves;
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  v4 t[CT][NT];
+};
+template <> struct RegTiles<0> { static constexpr int CT = 0; };
+
+// An LDS offset the compiler must take as computed here: addresses derived from it fold into
+// the instructions' immediate offsets at the point of use instead of being precomputed once for
+// every tile and kept live across the sweep (which spills the tiles).
+__device__ __forceinline__ int pinned(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// HBM <-> tiles through an LDS slab of 16 rows (stage: 16 n floats): the 16 rows of a row tile
+// are one contiguous stretch of B, read or written by the whole workgroup, and each lane moves
+// its entries between the slab and its registers.  All threads call these.
+template <int NT>
+__device__ __forceinline__ void regb_load(RegTiles<NT>& R, const float* __restrict__ Bg, float* stage, int n, int nt,
+                                          int lane, int wave, int tid) {
+  const int i = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int rt = 0; rt < NT; ++rt) {
+    if (rt < nt) {
+      const int rows = min(16, n - 16 * rt);
+      const float* src = Bg + (size_t)16 * rt * n;
+      for (int q = tid; q < rows * n; q += kBlock) stage[q] = src[q];
+      __syncthreads();
+#pragma unroll
+      for (int cj = 0; cj < RegTiles<NT>::CT; ++cj) {
+        const int ct = wave + kWaves * cj, c = 16 * ct + i;
+        const int base = pinned(4 * g * n + (c < n ? c : 0));
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int l = 4 * g + r;
+          const float v = stage[l < rows ? base + r * n : 0];
+          R.t[cj][rt][r] = (ct < nt && l < rows && c < n) ? v : 0.0f;
+        }
+      }
+      __syncthreads();
+    } else {
+#pragma unroll
+      for (int cj = 0; cj < RegTiles<NT>::CT; ++cj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) R.t[cj][rt][r] = 0.0f;
+    }
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void regb_store(const RegTiles<NT>& R, float* __restrict__ Bg, float* stage, int n,
+                                           int nt, int lane, int wave, int tid) {
+  const int i = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int rt = 0; rt < NT; ++rt) {
+    if (rt < nt) {
+      const int rows = min(16, n - 16 * rt);
+#pragma unroll
+      for (int cj = 0; cj < RegTiles<NT>::CT; ++cj) {
+        const int ct = wave + kWaves * cj, c = 16 * ct + i;
+        const int base = pinned(4 * g * n + c);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int l = 4 * g + r;
+          if (ct < nt && l < rows && c < n) stage[base + r * n] = R.t[cj][rt][r];
+        }
+      }
+      __syncthreads();
+      float* dst = Bg + (size_t)16 * rt * n;
+      for (int q = tid; q < rows * n; q += kBlock) dst[q] = stage[q];
+      __syncthreads();
+    }
+  }
+}
+
+// Y[q][c] = sum_l V[q][l] B0[l][c] for q < Kw <= 32 and the columns of this wave's tiles (V: LDS,
+// row stride ldv, columns up to 16 nt zero past n; Y: LDS, row stride nP).
+template <int NT>
+__device__ __forceinline__ void regb_window(const RegTiles<NT>& R, const float* V, int ldv, float* Y, int nP, int Kw,
+                                            int nt, int lane, int wave) {
+  typedef typename RegTiles<NT>::v4 v4;
+  constexpr int CT = RegTiles<NT>::CT;
+  const int i = lane & 15, g = lane >> 4;
+  const bool two = Kw > 16;   // a second 16-row block of window rows
+  // rows past the window (their products are discarded) read the window's last row: the window
+  // buffer holds only Kw <= K rows
+  const int v0 = pinned(min(i, Kw - 1) * ldv + 4 * g), v1 = pinned(min(16 + i, Kw - 1) * ldv + 4 * g);
+  v4 acc[2][CT];
+#pragma unroll
+  for (int cj = 0; cj < CT; ++cj) {
+    acc[0][cj] = v4{0.0f, 0.0f, 0.0f, 0.0f};
+    acc[1][cj] = v4{0.0f, 0.0f, 0.0f, 0.0f};
+  }
+#pragma unroll
+  for (int rt = 0; rt < NT; ++rt) {
+    if (rt < nt) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float a0 = V[v0 + 16 * rt + r];
+        const float a1 = two ? V[v1 + 16 * rt + r] : 0.0f;
+#pragma unroll
+        for (int cj = 0; cj < CT; ++cj) {
+          acc[0][cj] = Mfma<float>::mma(a0, R.t[cj][rt][r], acc[0][cj]);
+          if (two) acc[1][cj] = Mfma<float>::mma(a1, R.t[cj][rt][r], acc[1][cj]);
+        }
+      }
+    }
+  }
+  const int y0 = pinned(4 * g * nP + i);
+#pragma unroll
+  for (int cj = 0; cj < CT; ++cj) {
+    const int ct = wave + kWaves * cj;
+    if (ct >= nt) continue;
+#pragma unroll
+    for (int qb = 0; qb < 2; ++qb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = 16 * qb + 4 * g + r;
+        if (q < Kw) Y[y0 + (16 * qb + r) * nP + 16 * ct] = acc[qb][cj][r];
+      }
+  }
+}
+
+// mag[q] = sum_l |V[q][l]| |B0[l][k0 + q]| for the window columns this wave holds (the bound on the
+// FP32 rounding of the window's ratios).  The four lanes holding a column add their rows.
+template <int NT>
+__device__ __forceinline__ void regb_magnitudes(const RegTiles<NT>& R, const float* V, int ldv, double* mag, int k0,
+                                                int Kw, int n, int nt, int lane, int wave) {
+  const int i = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int cj = 0; cj < RegTiles<NT>::CT; ++cj) {
+    const int ct = wave + kWaves * cj, c = 16 * ct + i, q = c - k0;
+    const bool in = ct < nt && c < n && q >= 0 && q < Kw;
+    double part = 0.0;
+    if (in) {
+      const int vb = pinned(q * ldv + 4 * g);
+#pragma unroll
+      for (int rt = 0; rt < NT; ++rt)
+        if (rt < nt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) part += fabs((double)V[vb + 16 * rt + r]) * fabs((double)R.t[cj][rt][r]);
+    }
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    if (in && g == 0) mag[q] = part;
+  }
+}
+
+// Ut[r][l] = B0[l][p_r] (r < m, l < 16 nt; rows m .. mP - 1 zero): U transposed, row stride ldt.
+template <int NT>
+__device__ __forceinline__ void regb_columns(const RegTiles<NT>& R, float* Ut, int ldt, const int* plist, int m,
+                                             int mP, int nt, int lane, int wave, int tid) {
+  const int i = lane & 15, g = lane >> 4, nc = 16 * nt;
+  for (int idx = tid; idx < (mP - m) * nc; idx += kBlock) {
+    const int r = m + idx / nc, l = idx % nc;
+    Ut[(size_t)r * ldt + l] = 0.0f;
+  }
+  for (int r = 0; r < m; ++r) {
+    const int p = plist[r], ct = p >> 4;
+    if (ct % kWaves != wave || (p & 15) != i) continue;
+    const int ub = pinned(r * ldt + 4 * g);
+#pragma unroll
+    for (int cj = 0; cj < RegTiles<NT>::CT; ++cj) {
+      if (cj != ct / kWaves) continue;
+#pragma unroll
+      for (int rt = 0; rt < NT; ++rt)
+        if (rt < nt)
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) Ut[ub + 16 * rt + rr] = R.t[cj][rt][rr];
+    }
+  }
+}
+
+// B -= U Z in place in the tiles: Ut (LDS, U transposed, mP x 16 nt, stride ldt), Z (LDS,
+// mP x 16 nt, stride nP, zero past column n).
+template <int NT>
+__device__ __forceinline__ void regb_flush(RegTiles<NT>& R, const float* Ut, int ldt, const float* Z, int nP, int mP,
+                                           int nt, int lane, int wave) {
+  constexpr int CT = RegTiles<NT>::CT;
+  const int i = lane & 15, g = lane >> 4;
+  for (int r0 = 0; r0 < mP; r0 += 4) {
+    const int zb = pinned((r0 + g) * nP + i), ub = pinned((r0 + g) * ldt + i);
+    float zf[CT];
+#pragma unroll
+    for (int cj = 0; cj < CT; ++cj) {
+      const int ct = wave + kWaves * cj;
+      const float z = Z[zb + 16 * (ct < nt ? ct : 0)];
+      zf[cj] = ct < nt ? z : 0.0f;   // tiles past the matrix stay zero
+    }
+#pragma unroll
+    for (int rt = 0; rt < NT; ++rt) {
+      if (rt < nt) {
+        const float a = -Ut[ub + 16 * rt];
+#pragma unroll
+        for (int cj = 0; cj < CT; ++cj) R.t[cj][rt] = Mfma<float>::mma(a, zf[cj], R.t[cj][rt]);
+      }
+    }
+  }
+}
+
+// out[c] = (add ? out[c] : 0) + sum_l x[l] B[l][c] for the columns c < n of this wave's tiles,
+// summed in FP64 from the FP32 tiles (x: LDS, zero from n up to 16 nt); the four lanes holding a
+// column add their rows.
+template <int NT, typename X>
+__device__ __forceinline__ void regb_rowvec(const RegTiles<NT>& R, const X* x, double* out, bool add, int n, int nt,
+                                            int lane, int wave) {
+  const int i = lane & 15, g = lane >> 4;
+  const int xb = pinned(4 * g);
+#pragma unroll
+  for (int cj = 0; cj < RegTiles<NT>::CT; ++cj) {
+    const int ct = wave + kWaves * cj, c = 16 * ct + i;
+    double part = 0.0;
+    if (ct < nt) {
+#pragma unroll
+      for (int rt = 0; rt < NT; ++rt)
+        if (rt < nt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) part += (double)x[xb + 16 * rt + r] * (double)R.t[cj][rt][r];
+    }
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    if (g == 0 && ct < nt && c < n) out[c] = add ? out[c] + part : part;
+  }
+}
+
+// col[l] = B[l][k] for l < 16 nt (written by the four lanes that hold column k).
+template <int NT>
+__device__ __forceinline__ void regb_column(const RegTiles<NT>& R, float* col, int k, int nt, int lane, int wave) {
+  const int i = lane & 15, g = lane >> 4, ct = k >> 4;
+  if (ct % kWaves != wave || (k & 15) != i) return;
+  const int cb = pinned(4 * g);
+#pragma unroll
+  for (int cj = 0; cj < RegTiles<NT>::CT; ++cj) {
+    if (cj != ct / kWaves) continue;
+#pragma unroll
+    for (int rt = 0; rt < NT; ++rt)
+      if (rt < nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) col[cb + 16 * rt + r] = R.t[cj][rt][r];
+  }
+}
+
+// Sherman-Morrison in the tiles: B[l][c] -= col[l] (t[c] - delta_ck) / R for the accepted row of
+// electron k (col = B[:, k], t = v^T B, R = t[k]; LDS).
+template <int NT>
+__device__ __forceinline__ void regb_rank1(RegTiles<NT>& R, const float* col, const float* t, float invR, int k,
+                                           int n, int nt, int lane, int wave) {
+  const int i = lane & 15, g = lane >> 4;
+  const int cb = pinned(4 * g);
+#pragma unroll
+  for (int cj = 0; cj < RegTiles<NT>::CT; ++cj) {
+    const int ct = wave + kWaves * cj, c = 16 * ct + i;
+    if (ct >= nt) continue;
+    const float f = c < n ? invR * (t[c] - (c == k ? 1.0f : 0.0f)) : 0.0f;
+#pragma unroll
+    for (int rt = 0; rt < NT; ++rt)
+      if (rt < nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) R.t[cj][rt][r] -= col[cb + 16 * rt + r] * f;
+  }
+}
+
+template <typename T, bool BLDS, bool MF, int RT>
 __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const Walkers<T>& Wk, int w, int K,
                                                      int ldl) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -293,7 +570,7 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (chain_skips(Wk, w)) return;
   const int N = P.N, nmax = P.n_up > P.n_dn ? P.n_up : P.n_dn, nP = round16(nmax);
-  const DLayout lay = dlayout(N, nmax, P.n_ions, ldl, sizeof(T), BLDS, K);
+  const DLayout lay = dlayout(N, nmax, P.n_ions, ldl, sizeof(T), BLDS, K, RT > 0);
   double* spos = reinterpret_cast<double*>(smem + lay.pos);
   double* sprop = reinterpret_cast<double*>(smem + lay.prop);
   const bool ions_lds = P.n_ions <= kLdsIonsD;
@@ -321,6 +598,39 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
   T* sB = reinterpret_cast<T*>(smem + lay.b);
   const double L = P.L, invL = 1.0 / P.L;
   const int tpq = kBlock / K;   // threads per window slot in the Jastrow sums
+  // RT > 0: the active spin block's inverse lives in registers (breg) for the sweep; the window
+  // rows are then stored with row stride nP + 1 (the product reads them across rows)
+  RegTiles<RT> breg;
+  const int ldv = RT > 0 ? nP + 1 : nP;
+  T* vpre = reinterpret_cast<T*>(smem + lay.vpre);
+  // rows of a window into dst: kA1 loads per thread in flight before their stores (the rows do not
+  // depend on the chain, only the HBM latency matters); indices are clamped so every load is in
+  // bounds; register mode zeroes the columns past n up to the tiles' 16 nt
+  auto load_rows = [&](T* dst, size_t item0_, int kstart, int kw, int nt_, int n_, const uint8_t* cur_, int t0,
+                       int tstride) {
+    constexpr int kA1 = 8;
+    const int nc = RT > 0 ? 16 * nt_ : n_, total = kw * nc;
+    for (int b0 = t0; b0 < total; b0 += tstride * kA1) {
+      T v[kA1];
+#pragma unroll
+      for (int e = 0; e < kA1; ++e) {
+        const int idx = b0 + e * tstride;
+        const bool ok = idx < total;
+        const int q = ok ? idx / nc : 0, l = ok ? idx - q * nc : 0;
+        const T x = Wk.vgl[((size_t)(1 - cur_[kstart + q]) * P.W * N + item0_ + kstart + q) * Wk.vstride +
+                           (l < n_ ? l : 0)];
+        v[e] = (ok && l < n_) ? x : T(0);
+      }
+#pragma unroll
+      for (int e = 0; e < kA1; ++e) {
+        const int idx = b0 + e * tstride;
+        if (idx < total) {
+          const int q = idx / nc, l = idx - q * nc;
+          dst[(size_t)q * ldv + l] = v[e];
+        }
+      }
+    }
+  };
   const int ldy = K + 1;        // row stride of yk: the lanes' rows start in different banks
   // the wave that runs the moves in sequence rotates with the workgroup index, so that the
   // sequential phases of workgroups sharing a compute unit fall on different SIMDs
@@ -360,17 +670,25 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
       ldb = n;
     }
     const bool up_block = sp == 0;
+    const int nt = (n + 15) >> 4;
+    const double weta = sizeof(T) == 4 ? walker_eta(Wk, w, sp, n) : 0.0;   // mixed: inverse error of B
+    if constexpr (RT > 0) regb_load<RT>(breg, Bg, reinterpret_cast<float*>(ywin), n, nt, lane, wave, tid);
     __syncthreads();   // the block's proposals, buffer flags and inverse are staged before any use
 
+    int pre_k0 = -1;   // register mode: the window start whose rows vpre holds
     for (int k0 = 0; k0 < n;) {
       const int Kw = (n - k0) < K ? (n - k0) : K;
-      // (A1) the window's proposal rows
-      for (int idx = tid; idx < Kw * n; idx += kBlock) {
-        const int q = idx / n, l = idx - q * n;
-        const size_t it = item0 + k0 + q;
-        vwin[(size_t)q * nP + l] = Wk.vgl[((size_t)(1 - scur[k0 + q]) * P.W * N + it) * Wk.vstride + l];
+      // mixed: lane q's inverse-error coefficient of its electron's column (loaded here, used in
+      // the sequential phase)
+      const double ecq = (sizeof(T) == 4 && lane < Kw) ? inverse_error_coef(Wk, w, off + k0 + lane, N, weta) : 0.0;
+      // (A1) the window's proposal rows, unless the previous window's moves prefetched them
+      T* vcur = vwin;
+      if (RT > 0 && pre_k0 == k0) {
+        vcur = vpre;
+      } else {
+        load_rows(vwin, item0, k0, Kw, nt, n, scur, tid, kBlock);
+        __syncthreads();
       }
-      __syncthreads();
       // (A2) Jastrow: fixed partners (outside the window) per slot, and in-window pair terms
       {
         const int q = tid / tpq, s = tid - q * tpq;
@@ -427,13 +745,13 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
           }
         }
         red[tid] = part;
-        if (sizeof(T) == 4) {
+        if (sizeof(T) == 4 && RT == 0) {
           // magnitude of the ratio's terms, sum_l |v_l| |B0[l][k]|, which bounds the FP32
           // rounding of the ratio (mixed precision guard band)
           double mag = 0.0;
           if (q < Kw)
             for (int l = s; l < n; l += tpq)
-              mag += fabs((double)vwin[(size_t)q * nP + l]) * fabs((double)Bm[(size_t)l * ldb + k0 + q]);
+              mag += fabs((double)vwin[(size_t)q * ldv + l]) * fabs((double)Bm[(size_t)l * ldb + k0 + q]);
           rmag[tid] = mag;
         }
       }
@@ -476,8 +794,13 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
         gold[q2 * K + q] = g_old;   // transposed: lane q reads column q
         if (q2 < q) gdiff[q2 * K + q] = g_new - g_old;
       }
-      // (A3) Y = V B0
-      gemm_window<T, MF>(vwin, Bm, ldb, ywin, Kw, n, nP, tid);
+      // (A3) Y = V B0 (register mode: from the tiles, with the window columns' magnitudes)
+      if constexpr (RT > 0) {
+        regb_window<RT>(breg, vcur, ldv, ywin, nP, Kw, nt, lane, wave);
+        regb_magnitudes<RT>(breg, vcur, ldv, rmag, k0, Kw, n, nt, lane, wave);
+      } else {
+        gemm_window<T, MF>(vwin, Bm, ldb, ywin, Kw, n, nP, tid);
+      }
       __syncthreads();
       if (sizeof(T) == 4) {
         // mixed: |v_q^T B0|^2 partials (row q of Y), for the inverse-error part of the guard band
@@ -503,7 +826,9 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
         if (lane < Kw) {
           for (int s = 0; s < tpq; ++s) Fq += red[lane * tpq + s];
           if (sizeof(T) == 4) {
-            for (int s = 0; s < tpq; ++s) Sq += rmag[lane * tpq + s];
+            if (RT > 0) Sq = rmag[lane];
+            else
+              for (int s = 0; s < tpq; ++s) Sq += rmag[lane * tpq + s];
             for (int s = 0; s < tpq; ++s) Tq += tnp[lane * tpq + s];
             Tq = sqrt(Tq);
           }
@@ -545,7 +870,7 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
           if (sizeof(T) == 4) {
             const double uf = 5.9604644775390625e-08;   // 2^-24
             const double err = (n + 1) * uf * (readlane_d(Sq, q) + readlane_d(Eq, q));
-            band += 2.0 * err / fabs(R) + 4.0 * uf + inverse_error_term(Wk, w, sp, n, readlane_d(Tq, q), R);
+            band += (2.0 * err + readlane_d(ecq, q) * readlane_d(Tq, q)) / fabs(R) + 4.0 * uf;
           }
           if (sizeof(T) == 4 && fabs(u - p32) <= band * p32) {
             // near tie in FP32: end the window here; the move is re-decided in FP64 below
@@ -604,7 +929,15 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
             if ((amask >> q) & 1ull) logd += readlane_d(lg, q);
         }
         if (lane == 0) sm_m = m;
+      } else if (RT > 0 && k0 + Kw < n) {
+        // register mode: meanwhile the other waves fetch the next window's rows (for the window
+        // that follows when no near tie cuts this one short; the moves only change this window's
+        // buffer flags)
+        const int nk0 = k0 + Kw, nkw = (n - nk0) < K ? (n - nk0) : K;
+        const int pw = wave < seq_wave ? wave : wave - 1;
+        load_rows(vpre, item0, nk0, nkw, nt, n, scur, pw * 64 + lane, (kWaves - 1) * 64);
       }
+      pre_k0 = (RT > 0 && k0 + Kw < n) ? k0 + Kw : -1;
       __syncthreads();
 
       // (C) flush: B = B0 - B0[:, P] C^-1 (Y[Q, :] - E_P^T), C = Y[Q, P].  C^-1 by
@@ -621,39 +954,55 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
           ga[a * K + b] = (double)ywin[(size_t)qlist[a] * nP + plist[b]];
         }
         __syncthreads();
-        for (int pv = 0; pv < m; ++pv) {
-          const double inv = 1.0 / ga[pv * K + pv];
-          for (int idx = tid; idx < m * m; idx += kBlock) {
-            const int i = idx / m, j = idx - i * m;
-            const double aip = ga[i * K + pv], apj = ga[pv * K + j];
-            gb[i * K + j] = i == pv ? (j == pv ? inv : apj * inv)
-                                    : (j == pv ? -aip * inv : ga[i * K + j] - aip * apj * inv);
+        // the elimination in one wave: its steps are ordered by wave-level LDS syncs, with no
+        // workgroup barrier per pivot (the other waves wait once, below)
+        if (wave == 0) {
+          double* a0 = ga;
+          double* b1 = gb;
+          for (int pv = 0; pv < m; ++pv) {
+            const double inv = 1.0 / a0[pv * K + pv];
+            for (int idx = lane; idx < m * m; idx += 64) {
+              const int i = idx / m, j = idx - i * m;
+              const double aip = a0[i * K + pv], apj = a0[pv * K + j];
+              b1[i * K + j] = i == pv ? (j == pv ? inv : apj * inv)
+                                      : (j == pv ? -aip * inv : a0[i * K + j] - aip * apj * inv);
+            }
+            wave_sync_lds();
+            double* t = a0; a0 = b1; b1 = t;
           }
-          __syncthreads();
-          double* t = ga; ga = gb; gb = t;
         }
-        const double* cinv = ga;
-        for (int idx = tid; idx < mP * n; idx += kBlock) {
-          const int r = idx / n, c = idx - r * n;
+        __syncthreads();
+        const double* cinv = (m & 1) ? gb : ga;   // after m steps, from one buffer into the other
+        // register mode: Z is read up to the tiles' 16 nt columns, zero past n
+        const int nz = RT > 0 ? 16 * nt : n;
+        for (int idx = tid; idx < mP * nz; idx += kBlock) {
+          const int r = idx / nz, c = idx - r * nz;
           double acc = 0.0;
-          if (r < m)
+          if (r < m && c < n)
             for (int l = 0; l < m; ++l)
               acc += cinv[r * K + l] * ((double)ywin[(size_t)qlist[l] * nP + c] - (c == plist[l] ? 1.0 : 0.0));
           zwin[(size_t)r * nP + c] = (T)acc;
         }
         __syncthreads();   // Y is dead from here: U takes its storage
-        for (int idx = tid; idx < n * mP; idx += kBlock) {
-          const int l = idx / mP, r = idx - l * mP;
-          ubuf[(size_t)l * K + r] = (r < m) ? Bm[(size_t)l * ldb + plist[r]] : T(0);
+        if constexpr (RT > 0) {
+          regb_columns<RT>(breg, ubuf, nP + 1, plist, m, mP, nt, lane, wave, tid);
+          __syncthreads();
+          regb_flush<RT>(breg, ubuf, nP + 1, zwin, nP, mP, nt, lane, wave);
+          __syncthreads();   // U and Z are read before the next window writes their storage
+        } else {
+          for (int idx = tid; idx < n * mP; idx += kBlock) {
+            const int l = idx / mP, r = idx - l * mP;
+            ubuf[(size_t)l * K + r] = (r < m) ? Bm[(size_t)l * ldb + plist[r]] : T(0);
+          }
+          __syncthreads();
+          constexpr int kVec = 16 / sizeof(T);
+          if (!BLDS && (n & 3) == 0 && (n % kVec) == 0 && (ldb % kVec) == 0 &&
+              (reinterpret_cast<uintptr_t>(Bm) & 15) == 0)
+            flush_global<T>(Bm, ldb, ubuf, K, zwin, nP, n, mP, tid);
+          else
+            gemm_flush<T, MF>(Bm, ldb, ubuf, K, zwin, nP, n, mP, tid);
+          __syncthreads();
         }
-        __syncthreads();
-        constexpr int kVec = 16 / sizeof(T);
-        if (!BLDS && (n & 3) == 0 && (n % kVec) == 0 && (ldb % kVec) == 0 &&
-            (reinterpret_cast<uintptr_t>(Bm) & 15) == 0)
-          flush_global<T>(Bm, ldb, ubuf, K, zwin, nP, n, mP, tid);
-        else
-          gemm_flush<T, MF>(Bm, ldb, ubuf, K, zwin, nP, n, mP, tid);
-        __syncthreads();
       }
       // (D) a move stopped at a near tie (mixed precision): FP64 decision against the
       // now current inverse, Sherman-Morrison update if accepted
@@ -662,28 +1011,65 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
         const int kq = k0 + stop, iq = off + kq;
         const size_t it = item0 + kq;
         const T* vg = Wk.vgl + ((size_t)(1 - scur[kq]) * P.W * N + it) * Wk.vstride;
-        for (int l = tid; l < n; l += kBlock) sgrow[l] = vg[l];
         const double* v64 = Wk.val64 + ((size_t)(1 - scur[kq]) * P.W * N + it) * P.S;
-        const double R64 = refined_ratio<T>(P, Wk, Bm, ldb, n, item0, scur, v64, kq, sgx, sgr, red, tid);
+        double R64;
+        if constexpr (RT > 0) {
+          // register mode: the row vector t = v^T A^-1 refined in FP64 against the FP64 Slater
+          // matrix A, t <- t + (v - t^T A) B from t = v^T B (each step multiplies the error by
+          // I - A B); R = t[k].  tf keeps the FP32 v^T B of the update.
+          float* tf = reinterpret_cast<float*>(ywin);   // free after the flush
+          for (int l = tid; l < 16 * nt; l += kBlock) sgrow[l] = l < n ? vg[l] : T(0);
+          __syncthreads();
+          regb_rowvec<RT>(breg, sgrow, sgx, false, n, nt, lane, wave);
+          __syncthreads();
+          for (int c = tid; c < n; c += kBlock) tf[c] = (float)sgx[c];
+          for (int step = 0; step < 3; ++step) {
+            for (int l = tid; l < 16 * nt; l += kBlock) {
+              double a = 0.0;
+              if (l < n) {
+                a = v64[l];
+#pragma unroll 8
+                for (int j = 0; j < n; ++j)
+                  a -= sgx[j] * Wk.val64[((size_t)scur[j] * P.W * N + item0 + j) * P.S + l];
+              }
+              sgr[l] = a;
+            }
+            __syncthreads();
+            regb_rowvec<RT>(breg, sgr, sgx, true, n, nt, lane, wave);
+            __syncthreads();
+          }
+          R64 = sgx[kq];
+        } else {
+          for (int l = tid; l < n; l += kBlock) sgrow[l] = vg[l];
+          R64 = refined_ratio<T>(P, Wk, Bm, ldb, n, item0, scur, v64, kq, sgx, sgr, red, tid);
+        }
         const double dJ = sm_dj;
         const double u = sprop[4 * kq + 3];
         ++nguard;
         if (u < R64 * R64 * exp(2.0 * dJ)) {
-          // t = v^T B (FP32), column kq saved, then B -= B[:, kq] (t - e_kq) / t_kq
-          T* st = ywin;              // free after the flush
-          T* scol = zwin;
-          for (int m = tid; m < n; m += kBlock) {
-            T acc = T(0);
-            for (int l = 0; l < n; ++l) acc += sgrow[l] * Bm[(size_t)l * ldb + m];
-            st[m] = acc;
-            scol[m] = Bm[(size_t)m * ldb + kq];
-          }
-          __syncthreads();
-          const T invR = T(1) / st[kq];
-          __syncthreads();
-          for (int idx = tid; idx < n * n; idx += kBlock) {
-            const int l = idx / n, m = idx - l * n;
-            Bm[(size_t)l * ldb + m] -= scol[l] * invR * (st[m] - (m == kq ? T(1) : T(0)));
+          if constexpr (RT > 0) {
+            float* tf = reinterpret_cast<float*>(ywin);
+            float* col = reinterpret_cast<float*>(zwin);
+            regb_column<RT>(breg, col, kq, nt, lane, wave);
+            __syncthreads();
+            regb_rank1<RT>(breg, col, tf, 1.0f / tf[kq], kq, n, nt, lane, wave);
+          } else {
+            // t = v^T B (FP32), column kq saved, then B -= B[:, kq] (t - e_kq) / t_kq
+            T* st = ywin;              // free after the flush
+            T* scol = zwin;
+            for (int m = tid; m < n; m += kBlock) {
+              T acc = T(0);
+              for (int l = 0; l < n; ++l) acc += sgrow[l] * Bm[(size_t)l * ldb + m];
+              st[m] = acc;
+              scol[m] = Bm[(size_t)m * ldb + kq];
+            }
+            __syncthreads();
+            const T invR = T(1) / st[kq];
+            __syncthreads();
+            for (int idx = tid; idx < n * n; idx += kBlock) {
+              const int l = idx / n, m = idx - l * n;
+              Bm[(size_t)l * ldb + m] -= scol[l] * invR * (st[m] - (m == kq ? T(1) : T(0)));
+            }
           }
           if (tid == 0) {
             spos[3 * iq] = sprop[4 * kq];
@@ -704,6 +1090,7 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
         k0 += Kw;
       }
     }
+    if constexpr (RT > 0) regb_store<RT>(breg, Bg, reinterpret_cast<float*>(ywin), n, nt, lane, wave, tid);
     __syncthreads();
     for (int q = tid; q < n; q += kBlock) {
       Wk.cur[item0 + q] = scur[q];
@@ -733,7 +1120,15 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
 
 template <typename T, bool BLDS, bool MF>
 __global__ __launch_bounds__(kBlock, 2) void k_chain_delayed(SysParams P, Walkers<T> Wk, int K, int ldl) {
-  chain_delayed_walker<T, BLDS, MF>(P, Wk, blockIdx.x, K, ldl);
+  chain_delayed_walker<T, BLDS, MF, 0>(P, Wk, blockIdx.x, K, ldl);
+}
+
+// The inverse in registers (FP32, spin blocks up to 16 kRegTiles), two workgroups per compute
+// unit: the compiler then keeps the kernel within 256 registers per lane and moves a few values
+// to scratch, which costs less than one walker per compute unit with no latency hidden.
+constexpr int kRegTiles = 12;
+__global__ __launch_bounds__(kBlock, 2) void k_chain_delayed_reg(SysParams P, Walkers<float> Wk, int K, int ldl) {
+  chain_delayed_walker<float, false, true, kRegTiles>(P, Wk, blockIdx.x, K, ldl);
 }
 
 // Several systems in one launch: block b is walker bmap[b].y of system bmap[b].x.
@@ -748,7 +1143,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_chain_delayed_batched(const SysDe
     for (int q = threadIdx.x; q < (int)(sizeof(SysDev<T>) / 4); q += kBlock) dst[q] = src[q];
   }
   __syncthreads();
-  chain_delayed_walker<T, BLDS, MF>(s.P, s.W, m.y, s.K, s.ldl);
+  chain_delayed_walker<T, BLDS, MF, 0>(s.P, s.W, m.y, s.K, s.ldl);
 }
 
 static int lds_budget_d() {
@@ -786,6 +1181,20 @@ size_t delayed_lds_bytes(const SysParams& P, size_t tsize, bool b_in_lds, int K)
   return dlayout(P.N, nmax, P.n_ions, nmax | 1, tsize, b_in_lds, K).total;
 }
 
+// Whether the register-resident variant takes a chain: FP32, matrix cores, spin blocks up to
+// 16 kRegTiles and windows up to 32.  It runs where the inverse does not fit the LDS, or
+// everywhere it can with QMC_CHAIN_REGISTER_INVERSE=1 (lets the tests cover it on small systems);
+// QMC_CHAIN_REGISTER_INVERSE=0 switches it off.
+static bool use_register_chain(const SysParams& P, size_t tsize, int K, int use_mfma, bool lds_fits) {
+  const int nmax = P.n_up > P.n_dn ? P.n_up : P.n_dn;
+  // (K >= 8: the window's Y and Z storage holds the 16-row staging slab)
+  if (tsize != sizeof(float) || !use_mfma || nmax > 16 * kRegTiles || K > 32 || K < 8) return false;
+  const char* e = getenv("QMC_CHAIN_REGISTER_INVERSE");
+  if (e && e[0] == '0') return false;
+  if (e && e[0] == '1') return true;
+  return !lds_fits;
+}
+
 template <typename T>
 hipError_t launch_chain_delayed(const SysParams& P, const Walkers<T>& Wk, int K, int use_mfma, hipStream_t st) {
   // K >= 4 keeps the flush's padded rank (a multiple of 4) within the K-wide buffers
@@ -797,6 +1206,18 @@ hipError_t launch_chain_delayed(const SysParams& P, const Walkers<T>& Wk, int K,
   const char* fg = getenv("QMC_CHAIN_GLOBAL_INVERSE");
   const bool force_global = fg && fg[0] == '1';
   const size_t budget = (size_t)lds_budget_d();
+  const size_t with_pre = dlayout(P.N, nmax, P.n_ions, ldl, sizeof(T), false, K, true).total + sizeof(Jastrow);
+  if (sizeof(T) == sizeof(float) && !force_global && with_pre <= budget &&
+      use_register_chain(P, sizeof(T), K, use_mfma, with_b <= budget)) {
+    const size_t bytes = with_pre - sizeof(Jastrow);
+    if (bytes > 65536) {
+      const hipError_t e = allow_dynamic_lds(reinterpret_cast<const void*>(&k_chain_delayed_reg));
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_chain_delayed_reg, dim3(P.W), dim3(kBlock), bytes, st, P,
+                       *reinterpret_cast<const Walkers<float>*>(&Wk), K, ldl);
+    return hipGetLastError();
+  }
   if (!force_global && with_b <= budget) {
     const size_t bytes = with_b - sizeof(Jastrow);
     return use_mfma ? launch_delayed_variant<T, true, true>(P, Wk, K, st, bytes, ldl)
@@ -840,7 +1261,8 @@ template hipError_t launch_chain_delayed_batched<float>(const SysDev<float>*, co
 
 template <typename T>
 static hipError_t delayed_lds_limits_t() {
-  const void* ks[] = {reinterpret_cast<const void*>(&k_chain_delayed<T, true, true>),
+  const void* ks[] = {reinterpret_cast<const void*>(&k_chain_delayed_reg),
+                      reinterpret_cast<const void*>(&k_chain_delayed<T, true, true>),
                       reinterpret_cast<const void*>(&k_chain_delayed<T, true, false>),
                       reinterpret_cast<const void*>(&k_chain_delayed<T, false, true>),
                       reinterpret_cast<const void*>(&k_chain_delayed<T, false, false>),

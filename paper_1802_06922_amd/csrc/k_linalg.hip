@@ -719,6 +719,15 @@ __device__ __forceinline__ void refine_spin(const SysParams& P, const Walkers<T>
            E[(size_t)i * n + k] = (float)e;
          }, sL, sR);
   __syncthreads();   // E (global) complete before it is read
+  if (Wk.ecol)   // each column's residual norm, for the guard band of the next sweep's ratios
+    for (int k = threadIdx.x; k < n; k += kBlock) {
+      double c2 = 0.0;
+      for (int i = 0; i < n; ++i) {
+        const double e = (double)E[(size_t)i * n + k];
+        c2 += e * e;
+      }
+      Wk.ecol[(size_t)w * N + off + k] = (float)sqrt(c2);
+    }
   // X = B + B E: the correction B E is ~1e-6 of B, so FP32 products (relative error ~1e-5 of
   // the correction, ~1e-11 of X) are far inside the FP32 rounding of the stored X
   gemm_tiles<float>(n, [&](int i, int l) { return (float)B[(size_t)i * n + l]; },
@@ -729,11 +738,18 @@ __device__ __forceinline__ void refine_spin(const SysParams& P, const Walkers<T>
                       X[(size_t)i * n + k] = x;
                     },
                     reinterpret_cast<float*>(sL), reinterpret_cast<float*>(sR));
-  e2 = block_sum(e2, red);
+  e2 = block_sum(e2, red);   // (its barriers also complete X before the copy below)
   x2 = block_sum(x2, red);
   if (threadIdx.x == 0 && Wk.eta) {
     Wk.eta[4 * w + sp] = sqrt(e2);
     Wk.eta[4 * w + 2 + sp] = sqrt(x2);
+  }
+  // The chain goes on from the refined inverse: with A B = I - E, A X = I - E^2, so the FP32
+  // updates' drift is squared away at every measurement instead of accumulating until the next
+  // full rebuild (the decisions, taken to FP64 accuracy by the guard, do not change).
+  if (Wk.fb) {
+    T* Bw = Wk.binv + boff;
+    for (int q = threadIdx.x; q < n * n; q += kBlock) Bw[q] = X[q];
   }
 }
 
@@ -825,6 +841,8 @@ __global__ __launch_bounds__(kBlock) void k_fb_residual(SysParams P, Walkers<flo
     if (tid == 0) Wk.eta[4 * w + sp] = Wk.eta[4 * w + 2 + sp] = 0.0;
     return;
   }
+  // a fresh FP32 rounding errs about evenly in every column
+  for (int k = tid; k < n; k += kBlock) Wk.ecol[(size_t)w * P.N + off + k] = 0.0f;
   const int N = P.N;
   const double* B = Wk.binv64 + (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0);
   for (int i = tid; i < n; i += kBlock) {

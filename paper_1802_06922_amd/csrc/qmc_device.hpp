@@ -80,6 +80,7 @@ struct Walkers {
   int* fb;            // [W]: 1 = FP64 fallback walker
   int fb_sel;         // chain launches advance only the walkers with fb[w] == fb_sel
   double* eta;        // [W][4]: ||I - A B||_F of each spin's inverse at the last check, then ||B||_F
+  float* ecol;        // [W][N]: ||(I - A B)[:, k]||_2 of each electron's inverse column at the last check
   uint32_t* eta_age;  // [W]: sweeps since eta was measured
   uint32_t* pstat;    // [W][2]: early FP64 rebuilds, sweeps run in FP64 fallback (cumulative)
   const T* table;     // the orbital table (the measurement of fallback walkers evaluates it in FP64)
@@ -93,20 +94,32 @@ __device__ __forceinline__ bool chain_skips(const Walkers<T>& Wk, int w) {
 
 // Mixed-precision guard: a safety factor on the measured inverse error (it grows with the
 // updates of a sweep), and the thresholds of the FP64 fallback.
-constexpr double kEtaSafety = 4.0;
-constexpr double kEtaRebuild = 2e-4;   // measured ||I - A B||_F above this: rebuild the inverse in FP64
+constexpr double kEtaSafety = 2.0;
+constexpr double kEtaRebuild = 2e-3;   // measured ||I - A B||_F above this: rebuild the inverse in FP64
 constexpr double kEtaEnter = 2e-4;     // a fresh FP32 inverse this far off: FP64 fallback
 constexpr double kEtaLeave = 5e-5;     // a fallback walker returns to FP32 below this
 
 // Relative error bound on an FP32 ratio R = v . B[:, k] that the inverse's own error causes:
-// with A B = I - E, |dR| <= ||v^T B|| ||E||_F (1 + O(||E||)); tnorm bounds ||v^T B||.
+// with A B = I - E, R - R_exact = -(v^T A^-1) E e_k, so |dR| <= ||v^T B|| ||E[:, k]||_2 (1 + O(||E||)).
+// The updates of a sweep mix the columns' errors (an accepted move at column p adds E[:, p] t_j / R_p
+// to every column j), so a column's measured norm is floored at the columns' mean ||E||_F / sqrt(n);
+// the factor kEtaSafety (1 + sweeps since the measurement) covers the growth over the sweep.  The
+// band widening of a move is inverse_error_coef(...) * ||v^T B|| / |R|.  Read once per spin block
+// (walker_eta) and once per electron (the column), never inside the sequential move loop.
 template <typename T>
-__device__ __forceinline__ double inverse_error_term(const Walkers<T>& Wk, int w, int sp, int n, double tnorm,
-                                                     double R) {
+__device__ __forceinline__ double walker_eta(const Walkers<T>& Wk, int w, int sp, int n) {
   if (!Wk.eta) return 0.0;
-  const double eta = fmax(Wk.eta[4 * w + sp], (double)n * 5.9604644775390625e-08);
+  const double rn = 1.0 / sqrt((double)n);
+  const double eta = fmax(Wk.eta[4 * w + sp] * rn, (double)n * rn * 5.9604644775390625e-08);
   const double age = Wk.eta_age ? (double)Wk.eta_age[w] : 0.0;
-  return 2.0 * kEtaSafety * eta * (1.0 + age) * tnorm / fabs(R);
+  return 2.0 * kEtaSafety * (1.0 + age) * eta;
+}
+// The coefficient for electron i (column of its spin block), N electrons; weta = walker_eta(...).
+template <typename T>
+__device__ __forceinline__ double inverse_error_coef(const Walkers<T>& Wk, int w, int i, int N, double weta) {
+  if (!Wk.eta || !Wk.ecol) return weta;
+  const double age = Wk.eta_age ? (double)Wk.eta_age[w] : 0.0;
+  return fmax(weta, 2.0 * kEtaSafety * (1.0 + age) * (double)Wk.ecol[(size_t)w * N + i]);
 }
 
 // ---------------------------------------------------------------------------

@@ -17,24 +17,49 @@ namespace qmc {
 // the block's electrons; v64: the proposal's FP64 value row; sx, sr: LDS
 // scratch of n doubles each; red: LDS scratch of kWaves doubles.
 template <typename T>
-__device__ double refined_ratio(const SysParams& P, const Walkers<T>& Wk, const T* Bm, int ldb, int n,
+__device__ __forceinline__ double refined_ratio(const SysParams& P, const Walkers<T>& Wk, const T* Bm, int ldb, int n,
                                 size_t item0, const uint8_t* scur, const double* v64, int k, double* sx,
                                 double* sr, double* red, int tid) {
   const int lane = tid & 63, wave = tid >> 6;
   for (int l = tid; l < n; l += kBlock) sx[l] = (double)Bm[(size_t)l * ldb + k];
   __syncthreads();
+  // Each wave takes four rows at a time, its lanes striding along the rows (coalesced reads of
+  // the FP64 Slater matrix and of B), and adds each row's partial sums across the wave.
   for (int it = 0; it < 3; ++it) {
-    for (int j = tid; j < n; j += kBlock) {
-      const double* arow = Wk.val64 + ((size_t)scur[j] * P.W * P.N + item0 + j) * P.S;
-      double a = 0.0;
-      for (int l = 0; l < n; ++l) a += arow[l] * sx[l];
-      sr[j] = (j == k ? 1.0 : 0.0) - a;
+    for (int j0 = 4 * wave; j0 < n; j0 += 4 * kWaves) {   // r = e_k - A x
+      double a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = 0.0;
+        const int j = j0 + u;
+        if (j < n) {
+          const double* arow = Wk.val64 + ((size_t)scur[j] * P.W * P.N + item0 + j) * P.S;
+          for (int l = lane; l < n; l += 64) a[u] += arow[l] * sx[l];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = wave_sum_dpp(a[u]);
+      if (lane == 0)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (j0 + u < n) sr[j0 + u] = (j0 + u == k ? 1.0 : 0.0) - a[u];
     }
     __syncthreads();
-    for (int l = tid; l < n; l += kBlock) {
-      double a = 0.0;
-      for (int j = 0; j < n; ++j) a += (double)Bm[(size_t)l * ldb + j] * sr[j];
-      sx[l] += a;
+    for (int l0 = 4 * wave; l0 < n; l0 += 4 * kWaves) {   // x += B r
+      double a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = 0.0;
+        const int l = l0 + u;
+        if (l < n)
+          for (int j = lane; j < n; j += 64) a[u] += (double)Bm[(size_t)l * ldb + j] * sr[j];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = wave_sum_dpp(a[u]);
+      if (lane == 0)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (l0 + u < n) sx[l0 + u] += a[u];
     }
     __syncthreads();
   }
