@@ -246,6 +246,71 @@ def main(argv=None) -> int:
     return 0
 
 
+def run_single(wl, steps: int, warmup: int, delay, lanes=None, serial: bool = False):
+    """Steps of (sweep + local energy) of one system; the delay rank is autotuned when not given
+    (the trial sweeps are ordinary sweeps, before the timed region)."""
+    import torch
+
+    from paper_1802_06922_amd import KERNEL_CHAIN, KERNEL_GATHER, KERNEL_MEASURE, KERNEL_REBUILD, System
+    if wl.recompute_period > 0 and steps % wl.recompute_period and not wl.all_electron:
+        # the timed window holds whole rebuild periods, so it pays for every FP64 rebuild
+        steps = (steps // wl.recompute_period + 1) * wl.recompute_period
+    if delay is not None:
+        wl.delay_rank = delay
+    print(f"[bench] building {wl.name}", file=sys.stderr, flush=True)
+    s = System(wl)
+    if lanes is None:
+        lanes_log2, _ = s.autotune_gather(trial_sweeps=3)
+    else:
+        s.set_gather_lanes(lanes)
+        lanes_log2 = lanes
+    if wl.all_electron:
+        K = None   # no update chain: every accepted move installs fresh inverses
+    elif delay is None:
+        K, _ = s.autotune_delay(ranks=(1, 8, 16, 32, 64), trial_sweeps=3)
+        print(f"[bench] {wl.name}: delay rank {K}, gather lanes 2^{lanes_log2} (autotuned)",
+              file=sys.stderr, flush=True)
+    else:
+        K = delay
+    W, N = s.W, wl.n_elec
+    # every step's energies stay on the device; steps run pipelined (qmc_run_steps: a step's
+    # measurement beside the next step's proposals)
+    energies = torch.empty((max(steps, warmup, 1), W, 4), dtype=torch.float64, device="cuda")
+    def run(n, out):
+        if serial:
+            for k in range(n):
+                s.sweep(1)
+                s.measure(out=out[k])
+        else:
+            s.run_steps(n, out)
+
+    if warmup:
+        run(warmup, energies[:warmup])
+    torch.cuda.synchronize()
+    s.set_timing(True)
+    for k in (KERNEL_GATHER, KERNEL_CHAIN, KERNEL_MEASURE, KERNEL_REBUILD):
+        s.kernel_timing(k, reset=True)
+    print(f"[bench] {wl.name}: timing {steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(steps, energies[:steps])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = {name: s.kernel_timing(k) for name, k in
+          (("gather", KERNEL_GATHER), ("chain", KERNEL_CHAIN), ("measure", KERNEL_MEASURE))}
+    rebuild = s.kernel_timing(KERNEL_REBUILD)
+    e_host = energies[steps - 1].cpu().numpy()
+    acceptance = float(s.accept_log().mean())
+    pos_host = s.get_walkers()[0]
+    s.close()
+    moves = W * N * steps
+    sweep_ms = (kt["gather"][0] + kt["chain"][0]) / steps
+    return {"value": moves / dt, "ms_per_step": dt / steps * 1e3, "kt": kt, "walkers": W, "steps": steps,
+            "rebuilds": {"launches": rebuild[1], "ms_per_launch": rebuild[0] / max(rebuild[1], 1)},
+            "delay_rank": K, "gather_lanes_log2": lanes_log2, "acceptance": acceptance, "sweep_only_moves_per_s": moves / (sweep_ms * steps / 1e3) if sweep_ms > 0 else None,
+            "mean_local_energy": float(e_host.sum(axis=1).mean()), "energies": e_host, "positions": pos_host}
+
+
 def chain_roofline(wl, r):
     """The move chain against the matrix-core peak of its precision.  Its matrix-core work per
     launch: per walker and spin block of n electrons, the window products Y = V B0 (2 n^3 over
