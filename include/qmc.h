@@ -290,6 +290,17 @@ qmc_status qmc_recompute(qmc_system s, double* drift_out);
  * host positions pos[n][3], written to host out[n][5][n_orb] in FP64. */
 qmc_status qmc_eval_spo_vgl(qmc_system s, int32_t n, const double* pos, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): qmc_eval_spo_vgl with
+ * its device staging (the positions and the results) in one fixed array of
+ * QMC_NOALLOC_DOUBLES doubles (4 MiB) per GPU, which the library holds until the
+ * process ends, instead of two allocations per call; same arguments, same
+ * results.  Needs n (3 + 5 n_orb) <= QMC_NOALLOC_DOUBLES (else QMC_ERR_ARG, with
+ * nothing done).  Calls that overlap on one GPU race: they share the array.
+ * Synchronises the handle's stream.  Errors: as qmc_eval_spo_vgl. */
+#define QMC_NOALLOC_DOUBLES (1 << 19)
+qmc_status qmc_eval_spo_vgl_noalloc(qmc_system s, int32_t n, const double* pos, double* out);
+
 /* Kernel timing: when enabled, every launch of each kernel class is
  * bracketed by HIP events on the handle's stream.  Classes: 0 = orbital
  * gather (proposal + spline VGL), 1 = move chain (ratio, Jastrow, accept,

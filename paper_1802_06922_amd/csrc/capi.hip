@@ -1288,6 +1288,73 @@ qmc_status qmc_recompute(qmc_system s, double* drift_out) {
   return check_singular(s);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Staging of qmc_eval_spo_vgl_noalloc: a fixed array in every GPU's memory, held until the
+// process ends.  In host code the name stands for nothing usable: the device address of each
+// GPU's copy is taken once per device (hipGetSymbolAddress, with that device current) and only
+// that address is handed to copies and kernels.
+static __device__ __align__(256) double scratch[QMC_NOALLOC_DOUBLES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// This device's copy of scratch (looked up on the first call per device), or null with *e set.
+double* scratch_on(int device, hipError_t* e) {
+  *e = hipSuccess;
+  if (device < 0 || device >= kMaxDevices) {
+    *e = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    *e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (*e != hipSuccess || !ptr) {
+      if (*e == hipSuccess) *e = hipErrorInvalidSymbol;
+      return nullptr;
+    }
+    g_scratch_ptr[device] = static_cast<double*>(ptr);
+  }
+  return g_scratch_ptr[device];
+}
+
+}  // namespace
+
+extern "C" {
+
+qmc_status qmc_eval_spo_vgl_noalloc(qmc_system s, int32_t n, const double* pos, double* out) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (!s->has_table) return fail(s, QMC_ERR_STATE, "load the spline table first");
+  if (n < 0 || (n > 0 && (!pos || !out))) return fail(s, QMC_ERR_ARG, "bad arguments");
+  if (n == 0) return QMC_OK;
+  const size_t need = (size_t)n * (3 + (size_t)kComp * s->P.n_orb);
+  if (need > (size_t)QMC_NOALLOC_DOUBLES)
+    return fail(s, QMC_ERR_ARG, "%d points of %d orbitals need %zu doubles of staging, more than the %d the "
+                "fixed array holds", n, s->P.n_orb, need, (int)QMC_NOALLOC_DOUBLES);
+  HIP_TRY(s, hipSetDevice(s->device));
+  hipError_t e;
+  double* base = scratch_on(s->device, &e);
+  if (!base) return fail(s, QMC_ERR_DEVICE, "device address of the staging array: %s", hipGetErrorString(e));
+  double* dp = base;                       // [n][3] positions
+  double* dout = base + (size_t)n * 3;     // [n][5][n_orb] results (every entry written by the kernel)
+  const size_t ob = (size_t)n * kComp * s->P.n_orb * sizeof(double);
+  e = hipMemcpyAsync(dp, pos, (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) {
+    if (s->d.precision == QMC_MIXED)
+      e = launch_eval_points<float>(s->P, static_cast<const float*>(s->d_table), dp, n, dout, s->stream);
+    else
+      e = launch_eval_points<double>(s->P, static_cast<const double*>(s->d_table), dp, n, dout, s->stream);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(out, dout, ob, hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "eval_spo_vgl_noalloc: %s", hipGetErrorString(e));
+  return QMC_OK;
+}
+
 qmc_status qmc_eval_spo_vgl(qmc_system s, int32_t n, const double* pos, double* out) {
   if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
   if (!s->has_table) return fail(s, QMC_ERR_STATE, "load the spline table first");

@@ -30,8 +30,9 @@ EXPORTS = [
     "qmc_get_last_energies", "qmc_batch_create", "qmc_batch_sweep", "qmc_batch_set_graph",
     "qmc_batch_timing", "qmc_batch_destroy", "qmc_max_delay_rank", "qmc_autotune_gather",
     "qmc_set_gather_lanes", "qmc_run_steps", "qmc_dmc_init", "qmc_dmc_steps", "qmc_dmc_get",
-    "qmc_get_precision_stats",
+    "qmc_get_precision_stats", "qmc_eval_spo_vgl_noalloc",
 ]
+NOALLOC_DOUBLES = 1 << 19   # QMC_NOALLOC_DOUBLES
 
 
 class QMCError(RuntimeError):
@@ -82,6 +83,7 @@ def load_library():
     L.qmc_get_counters.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
     L.qmc_recompute.argtypes = [vp, dp]
     L.qmc_eval_spo_vgl.argtypes = [vp, C.c_int32, dp, dp]
+    L.qmc_eval_spo_vgl_noalloc.argtypes = [vp, C.c_int32, dp, dp]
     L.qmc_set_timing.argtypes = [vp, C.c_int32]
     L.qmc_kernel_timing.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64), C.c_int32]
     L.qmc_destroy_system.argtypes = [vp]
@@ -320,6 +322,13 @@ class System:
         pos = np.ascontiguousarray(np.asarray(pos, dtype=np.float64).reshape(-1, 3))
         out = np.zeros((pos.shape[0], 5, self.wl.n_orb))
         self._check(self.L.qmc_eval_spo_vgl(self.h, pos.shape[0], _dp(pos), _dp(out)))
+        return out
+
+    def eval_spo_vgl_noalloc(self, pos) -> np.ndarray:
+        """As eval_spo_vgl, staged in the library's fixed device array (no device allocation)."""
+        pos = np.ascontiguousarray(np.asarray(pos, dtype=np.float64).reshape(-1, 3))
+        out = np.zeros((pos.shape[0], 5, self.wl.n_orb))
+        self._check(self.L.qmc_eval_spo_vgl_noalloc(self.h, pos.shape[0], _dp(pos), _dp(out)))
         return out
 
     def set_delay_rank(self, K: int):
