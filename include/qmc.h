@@ -255,6 +255,16 @@ qmc_status qmc_dmc_steps(qmc_system s, int32_t n_steps, double* stats_dev);
  * out (the state is still returned). */
 qmc_status qmc_dmc_get(qmc_system s, double* weights, double* energies, double* e_trial, int32_t* population);
 
+/* Branching of the last DMC step (section "Diffusion Monte Carlo", eqs. pmc:g_growth and
+ * pmc:walker_weight, then M = INT(w + xi)), host buffers [W] each, nullable:
+ * weights = w G_B of every slot alive when the step began (0 for the others);
+ * energies = the local energy of its new configuration (NaN for the others);
+ * mult = its multiplicity M (0 for the others); plan = the slot whose walker was
+ * copied into this slot (-1: none).  Free slots (M = 0) take the extra copies
+ * (M - 1 of every slot, lower source slots first) in ascending order.  Synchronises.
+ * Errors: STATE before qmc_dmc_init or before the first step. */
+qmc_status qmc_dmc_get_branching(qmc_system s, double* weights, double* energies, int32_t* mult, int32_t* plan);
+
 /* Walker state (section "Code structure": walkers persist between steps), copied
  * to host buffers (each nullable): pos[W][N][3];
  * logabs_det[W][2] = log|D_up|, log|D_dn| accumulated as the sum of

@@ -134,6 +134,7 @@ struct qmc_system_s {
   double* dmc_w = nullptr;
   double* dmc_E = nullptr;
   double* dmc_e4 = nullptr;
+  double* dmc_wb = nullptr;   // [W][2] weight and energy before the last branching
   double* dmc_ctl = nullptr;
   int* dmc_i = nullptr;   // crossed, mult, plan, xscan, fscan ([W] each), then the 3 control ints
   double* scratch = nullptr;
@@ -399,7 +400,7 @@ void free_walkers(qmc_system s) {
   s->ae_vcur = s->ae_vprop = s->ae_logT = nullptr;
   s->dmc_ready = s->fixed_node = false;
   s->vcur_valid = false;
-  s->dmc_w = s->dmc_E = s->dmc_e4 = s->dmc_ctl = nullptr;
+  s->dmc_w = s->dmc_E = s->dmc_e4 = s->dmc_wb = s->dmc_ctl = nullptr;
   s->dmc_i = nullptr;
 }
 
@@ -461,9 +462,11 @@ WalkerSizes walker_sizes(int n_up, int n_dn, int precision, int W, int n_orb, in
   const bool drift = move_kind == QMC_MOVE_ALL_DRIFT;
   z.ae_vel = drift ? W * N * 3 * sizeof(double) : 0;
   z.ae_logT = drift ? W * (size_t)velocity_parts((int)N) * sizeof(double) : 0;
-  // the DMC population qmc_dmc_init carves out (weights, energies, [W][4] energies, control
-  // doubles, five [W] int arrays and the control ints)
-  z.dmc = drift ? align_up(W * sizeof(double)) * 2 + align_up(W * 4 * sizeof(double)) + align_up(2 * sizeof(double)) +
+  // the DMC population qmc_dmc_init carves out (weights, energies, [W][4] energies, [W][2]
+  // weights and energies before branching, control doubles, five [W] int arrays and the
+  // control ints)
+  z.dmc = drift ? align_up(W * sizeof(double)) * 2 + align_up(W * 4 * sizeof(double)) +
+                      align_up(W * 2 * sizeof(double)) + align_up(2 * sizeof(double)) +
                       align_up((5 * (size_t)W + 3) * sizeof(int))
                 : 0;
   return z;
@@ -1100,6 +1103,7 @@ DmcState dmc_state_of(qmc_system s, double* stats) {
   D.w = s->dmc_w;
   D.E = s->dmc_E;
   D.e4 = s->dmc_e4;
+  D.wb = s->dmc_wb;
   D.crossed = s->dmc_i;
   D.mult = s->dmc_i + W;
   D.plan = s->dmc_i + 2 * W;
@@ -1130,9 +1134,10 @@ qmc_status qmc_dmc_init(qmc_system s, int32_t n_target, double e_trial, double f
     s->dmc_w = static_cast<double*>(s->mem.alloc(W * sizeof(double)));
     s->dmc_E = static_cast<double*>(s->mem.alloc(W * sizeof(double)));
     s->dmc_e4 = static_cast<double*>(s->mem.alloc(W * 4 * sizeof(double)));
+    s->dmc_wb = static_cast<double*>(s->mem.alloc(W * 2 * sizeof(double)));
     s->dmc_ctl = static_cast<double*>(s->mem.alloc(2 * sizeof(double)));
     s->dmc_i = static_cast<int*>(s->mem.alloc((5 * (size_t)W + 3) * sizeof(int)));
-    if (!s->dmc_w || !s->dmc_E || !s->dmc_e4 || !s->dmc_ctl || !s->dmc_i)
+    if (!s->dmc_w || !s->dmc_E || !s->dmc_e4 || !s->dmc_wb || !s->dmc_ctl || !s->dmc_i)
       return fail(s, QMC_ERR_OOM, "device allocation of the DMC population failed");
   }
   // local energies of every slot's configuration; the first n_target slots are alive
@@ -1205,6 +1210,27 @@ qmc_status qmc_dmc_get(qmc_system s, double* weights, double* energies, double* 
   if (e_trial) *e_trial = ctl[0];
   if (population) *population = pop;
   if (ictl[1]) return fail(s, QMC_ERR_NUMERIC, "the population died out");
+  return QMC_OK;
+}
+
+qmc_status qmc_dmc_get_branching(qmc_system s, double* weights, double* energies, int32_t* mult, int32_t* plan) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (!s->has_walkers || !s->dmc_ready) return fail(s, QMC_ERR_STATE, "qmc_dmc_init first");
+  HIP_TRY(s, hipSetDevice(s->device));
+  const size_t W = s->P.W;
+  int ictl[3];
+  HIP_TRY(s, hipMemcpyAsync(ictl, s->dmc_i + 5 * W, sizeof ictl, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(s, hipStreamSynchronize(s->stream));
+  if (ictl[0] == 0) return fail(s, QMC_ERR_STATE, "no DMC step has run since qmc_dmc_init");
+  std::vector<double> wb(2 * W);
+  HIP_TRY(s, hipMemcpyAsync(wb.data(), s->dmc_wb, wb.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  if (mult) HIP_TRY(s, hipMemcpyAsync(mult, s->dmc_i + W, W * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  if (plan) HIP_TRY(s, hipMemcpyAsync(plan, s->dmc_i + 2 * W, W * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(s, hipStreamSynchronize(s->stream));
+  for (size_t j = 0; j < W; ++j) {
+    if (weights) weights[j] = wb[2 * j];
+    if (energies) energies[j] = wb[2 * j + 1];
+  }
   return QMC_OK;
 }
 

@@ -54,6 +54,7 @@ __global__ __launch_bounds__(kBranchBlock) void k_dmc_branch(SysParams P, DmcSta
   int ncr = 0;
   for (int j = tid; j < W; j += kBranchBlock) {
     int m = 0;
+    double wbj = 0.0, ebj = __builtin_nan("");
     if (D.w[j] > 0.0) {
       const double* e = D.e4 + 4 * (size_t)j;
       const double en = e[0] + e[1] + e[2] + e[3];
@@ -66,8 +67,12 @@ __global__ __launch_bounds__(kBranchBlock) void k_dmc_branch(SysParams P, DmcSta
       double xi, unused;
       uniform_pair(P, kBranch, 0, (uint32_t)j, step, 0u, xi, unused);
       m = (int)floor(wj + xi);
+      wbj = wj;
+      ebj = en;
     }
     D.mult[j] = m;
+    D.wb[2 * (size_t)j] = wbj;
+    D.wb[2 * (size_t)j + 1] = ebj;
   }
   sw = wave_sum_dpp(sw);
   swe = wave_sum_dpp(swe);

@@ -185,6 +185,8 @@ hipError_t launch_ae_apply(const SysParams& P, const Walkers<T>& Wk, const AePro
 struct DmcState {
   double* w;        // [W] weights
   double* E;        // [W] local energy of each slot's current configuration
+  double* wb;       // [W][2] the step's weight and local energy before branching (0 and NaN
+                    // for slots that were dead when the step began)
   const double* e4; // [W][4] the step's local energies (kinetic, e-e, e-I, I-I)
   const int* crossed;  // [W] node-crossing rejections of the step
   int* mult;        // [W] branching multiplicities

@@ -29,7 +29,7 @@ EXPORTS = [
     "qmc_last_error", "qmc_estimate_device_bytes", "qmc_set_delay_rank", "qmc_autotune_delay",
     "qmc_get_last_energies", "qmc_batch_create", "qmc_batch_sweep", "qmc_batch_set_graph",
     "qmc_batch_timing", "qmc_batch_destroy", "qmc_max_delay_rank", "qmc_autotune_gather",
-    "qmc_set_gather_lanes", "qmc_run_steps", "qmc_dmc_init", "qmc_dmc_steps", "qmc_dmc_get",
+    "qmc_set_gather_lanes", "qmc_run_steps", "qmc_dmc_init", "qmc_dmc_steps", "qmc_dmc_get", "qmc_dmc_get_branching",
     "qmc_get_precision_stats", "qmc_eval_spo_vgl_noalloc",
 ]
 NOALLOC_DOUBLES = 1 << 19   # QMC_NOALLOC_DOUBLES
@@ -106,6 +106,7 @@ def load_library():
     L.qmc_dmc_init.argtypes = [vp, C.c_int32, C.c_double, C.c_double]
     L.qmc_dmc_steps.argtypes = [vp, C.c_int32, vp]
     L.qmc_dmc_get.argtypes = [vp, dp, dp, dp, C.POINTER(C.c_int32)]
+    L.qmc_dmc_get_branching.argtypes = [vp, dp, dp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.qmc_max_delay_rank.argtypes = [C.POINTER(Desc)]
     L.qmc_get_precision_stats.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                                           C.POINTER(C.c_int32), ip]
@@ -284,6 +285,18 @@ class System:
         self._check(self.L.qmc_dmc_get(self.h, w.ctypes.data_as(C.POINTER(C.c_double)),
                                        e.ctypes.data_as(C.POINTER(C.c_double)), C.byref(et), C.byref(pop)))
         return w, e, et.value, pop.value
+
+    def dmc_branching(self):
+        """The last step's (weights before branching [W], energies [W], multiplicities [W],
+        copy plan [W])."""
+        w = np.zeros(self.W)
+        e = np.zeros(self.W)
+        m = np.zeros(self.W, dtype=np.int32)
+        pl = np.zeros(self.W, dtype=np.int32)
+        i32 = C.POINTER(C.c_int32)
+        self._check(self.L.qmc_dmc_get_branching(self.h, _dp(w), _dp(e), m.ctypes.data_as(i32),
+                                                 pl.ctypes.data_as(i32)))
+        return w, e, m, pl
 
     def get_walkers(self):
         N = self.wl.n_elec

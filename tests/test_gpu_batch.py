@@ -129,3 +129,32 @@ def test_batch_with_a_three_body_member_equals_alone(gpu):
     batch.close()
     for s in systems:
         s.close()
+
+
+def test_batched_members_match_the_oracle(gpu, orc):
+    """The four uneven FP32 systems of the batched workload (32, 96, 192 and 512 electrons on
+    24^3 to 64^3 tables, rank-16 delay, 256 walkers each) advanced together by replayed graphs
+    for 20 sweeps: two sampled walkers of every member take every decision of the FP64 oracle,
+    their energies of every sweep within 1e-5 relative."""
+    sweeps = 20
+    wls = qi.batched_systems(256)
+    samples = [np.array([3 * k, 255 - 5 * k]) for k in range(len(wls))]
+    systems = [gpu.System(wl) for wl in wls]
+    batch = gpu.Batch(systems, graph=True)
+    bits = [[] for _ in wls]
+    energies = [[] for _ in wls]
+    for it in range(sweeps):
+        batch.sweep(1, measure=True)
+        for k, s in enumerate(systems):
+            bits[k].append(s.accept_log()[samples[k]])
+            energies[k].append(s.last_energies()[samples[k]])
+    batch.close()
+    for s in systems:
+        s.close()
+    for k, wl in enumerate(wls):
+        print(f"[batch-oracle] {wl.name}: walkers {list(samples[k])}, {sweeps} sweeps", flush=True)
+        b, e = np.stack(bits[k], 1), np.stack(energies[k], 1)
+        ref = orc.OracleSystem(wl).run(samples[k], sweeps, measure_every=1)
+        assert np.array_equal(b, ref["accept"]), f"decisions differ at {np.argwhere(b != ref['accept'])[:3]}"
+        rel = np.abs(e.sum(-1) - ref["energies"].sum(-1)) / np.maximum(np.abs(ref["energies"].sum(-1)), 1.0)
+        assert rel.max() < 1e-5, rel.max()

@@ -57,6 +57,61 @@ def _compare(gpu, orc, wl, n_slots, n_target, steps, feedback, rel=1e-10, pos_to
     return st
 
 
+def _per_slot(gpu, orc, wl, n_slots, n_target, steps, feedback, rel=1e-10, e_trial=float("nan")):
+    """Steps one at a time; after each, every slot's weight and energy before branching, its
+    multiplicity and copy source (qmc_dmc_get_branching), and its weight and energy after
+    branching (qmc_dmc_get) against the oracle's step."""
+    import torch
+    print(f"[dmc-slots] {wl.name} {wl.precision}: {n_target} of {n_slots} slots, {steps} steps", flush=True)
+    s = gpu.System(wl, n_walkers=n_slots)
+    s.dmc_init(n_target, e_trial=e_trial, feedback=feedback)
+    with pytest.raises(gpu.QMCError):
+        s.dmc_branching()   # no step yet
+    out = torch.zeros((1, 6), dtype=torch.float64, device="cuda")
+    got = []
+    for _ in range(steps):
+        s.dmc_steps(1, out)
+        got.append((out.cpu().numpy()[0].copy(), *s.dmc_branching(), *s.dmc_state()))
+    s.close()
+    ref = orc.OracleSystem(wl).dmc(n_slots, n_target, steps, e_trial=e_trial, feedback=feedback)
+    copies = 0
+    for k, (st, wb, eb, m, pl, w, E, et, pop) in enumerate(got):
+        rw, re, rm, rp = ref["weights"][k], ref["energies"][k], ref["mult"][k], ref["plan"][k]
+        assert np.array_equal(m, rm), (k, np.flatnonzero(m != rm)[:4])
+        assert np.array_equal(pl, rp), (k, np.flatnonzero(pl != rp)[:4])
+        was_alive = ~np.isnan(re)
+        assert np.array_equal(~np.isnan(eb), was_alive), k
+        assert np.all(wb[~was_alive] == 0.0) and np.all(m[~was_alive] == 0)
+        assert (np.abs(wb - rw) / np.maximum(np.abs(rw), 1.0)).max() < rel, k
+        assert (np.abs(eb[was_alive] - re[was_alive]) / np.maximum(np.abs(re[was_alive]), 1.0)).max() < rel, k
+        # after branching: weight 1 where a walker stayed or arrived, and copies carry the
+        # energy of their source
+        alive = (m >= 1) | (pl >= 0)
+        assert np.array_equal(w, alive.astype(np.float64)) and pop == alive.sum() == ref["stats"][k, 2]
+        src = np.where(pl >= 0, pl, np.arange(n_slots))
+        assert np.all(was_alive[src[alive]])
+        np.testing.assert_allclose(E[alive], re[src[alive]], rtol=rel, atol=rel)
+        assert (np.abs(st[:2] - ref["stats"][k, :2]) / np.maximum(np.abs(ref["stats"][k, :2]), 1.0)).max() < rel
+        copies += int((pl >= 0).sum())
+    print(f"[dmc-slots] {copies} copies over {steps} steps, final population {got[-1][-1]}", flush=True)
+    return copies
+
+
+def test_dmc_per_slot_branching_heg14(gpu, orc):
+    """Large steps and a high first E_T: copies, deaths, node crossings and dropped copies."""
+    assert _per_slot(gpu, orc, _drift(qi.heg14(), 0.3), 32, 20, 16, 0.3, e_trial=5.0) > 0
+
+
+def test_dmc_per_slot_branching_solid128(gpu, orc):
+    """The 128-electron solid, 64 slots with 48 alive at the start, 12 steps."""
+    assert _per_slot(gpu, orc, _drift(qi.solid128(), 0.03), 64, 48, 12, 1.0) > 0
+
+
+def test_dmc_per_slot_branching_mixed_precision(gpu, orc):
+    wl = qi.solid(48, 16, n_walkers=1, n_sweeps=1, precision="mixed", table_dtype=np.float32)
+    _per_slot(gpu, orc, _drift(wl, 0.08), 48, 32, 10, 0.5, rel=1e-5)
+
+
 def test_dmc_heg14(gpu, orc):
     st = _compare(gpu, orc, _drift(qi.heg14(), 0.2), 40, 24, 40, 0.5)
     assert st[:, 2].min() != st[:, 2].max()   # the population moved

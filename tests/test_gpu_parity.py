@@ -118,9 +118,11 @@ def test_small_solid_trajectory_ragged(gpu, orc):
 
 
 def test_solid128_sampled_walkers(gpu, orc):
-    """The 128-electron solid (48^3 FP64 table, 32 ions, 512 walkers): sampled walkers."""
+    """The 128-electron solid (48^3 FP64 table, 32 ions, 512 walkers) over its whole 200-sweep
+    run: walkers 0, 255 and 511 take every decision the oracle takes, with the energies of
+    every sweep, the final positions, log|D| and signs."""
     wl = qi.solid128()
-    _compare_run(gpu, orc, wl, 4, [0, 255, 511])
+    _compare_run(gpu, orc, wl, wl.n_sweeps, [0, 255, 511])
 
 
 def test_recompute_drift_is_tiny(gpu, orc):

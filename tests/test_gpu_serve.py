@@ -86,3 +86,44 @@ def test_served_dmc_requests_match_alone(gpu):
         s.close()
         assert np.array_equal(e, r.energy)
         assert np.array_equal(pos, r.final_pos)
+
+
+def test_served_requests_match_the_oracle(gpu, orc):
+    """One VMC and one DMC request (mixed precision) served together: the VMC request's last
+    energies within 1e-5 of the FP64 oracle and its positions to rounding (every decision
+    taken as the oracle takes it); the DMC request's per-step population, dropped copies and
+    node-crossing rejections exactly, its estimates within 1e-5, and its alive walkers where
+    the oracle's are."""
+    import dataclasses
+    from paper_1802_06922_amd import serve
+    spec = [(24, 12, 6, 4, "vmc"), (16, 12, 16, 6, "dmc")]
+    reqs = []
+    for i, (n, g, w, sw, kind) in enumerate(spec):
+        wl = qi.solid(n, g, n_walkers=w, n_sweeps=1, precision="mixed", table_dtype=np.float32,
+                      recompute_period=2, seed=30 + i, name=f"req{i}")
+        wl.delay_rank = serve.delay_rank_for(wl, cap=16)
+        if kind == "dmc":
+            wl = dataclasses.replace(wl, all_electron=True, drift=True, sigma=0.3 / np.sqrt(n))
+        r = serve.Request(rid=i, arrival_s=0.0, wl=wl, n_sweeps=sw, kind=kind,
+                          dmc_target=w * 3 // 4 if kind == "dmc" else 0, dmc_feedback=0.5)
+        r.est_bytes = gpu.estimate_device_bytes(wl, w)
+        reqs.append(r)
+    st = serve.Server(reserve_bytes=0).run(reqs, time_scale=0.0, log=lambda m: print(m, flush=True))
+    assert st["requests"] == 2 and st["dmc_requests"] == 1
+    for r in st["finished"]:
+        print(f"[serve-oracle] request {r.rid} ({r.kind})", flush=True)
+        o = orc.OracleSystem(r.wl)
+        if r.kind == "vmc":
+            ref = o.run(range(r.wl.n_walkers), r.n_sweeps, measure_every=1)
+            e, re = r.energy.sum(-1), ref["energies"][:, -1].sum(-1)
+            assert (np.abs(e - re) / np.maximum(np.abs(re), 1.0)).max() < 1e-5
+            np.testing.assert_allclose(r.final_pos, ref["final_pos"], atol=1e-10)
+        else:
+            ref = o.dmc(r.wl.n_walkers, r.dmc_target, r.n_sweeps, feedback=r.dmc_feedback)
+            for c in (2, 4, 5):
+                assert np.array_equal(r.energy[:, c], ref["stats"][:, c]), c
+            for c in (0, 1, 3):
+                err = np.abs(r.energy[:, c] - ref["stats"][:, c]) / np.maximum(np.abs(ref["stats"][:, c]), 1.0)
+                assert err.max() < 1e-5, (c, err.max())
+            alive = ref["final_sign"] != 0
+            np.testing.assert_allclose(r.final_pos[alive], ref["final_pos"][alive], atol=1e-7)
