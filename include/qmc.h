@@ -121,6 +121,11 @@ typedef enum { QMC_H_KINETIC = 0, QMC_H_COULOMB_EWALD = 1 } qmc_hamiltonian;
  *                 electron proposed at r + tau grad ln|Psi| + sigma xi, the
  *                 acceptance (eq. accept_reject) including the ratio of the
  *                 transition probabilities T(R'->R)/T(R->R').  N <= 1024.
+ *                 In mixed precision the velocities are built from FP64
+ *                 gradient rows and the FP64 inverses of the Gauss-Jordan
+ *                 eliminations (both kept beside the FP32 state), so every
+ *                 quantity that decides a move is FP64; only the local
+ *                 energies read the FP32 rows.
  */
 enum { QMC_MOVE_PBYP = 0, QMC_MOVE_ALL = 1, QMC_MOVE_ALL_DRIFT = 2 };
 

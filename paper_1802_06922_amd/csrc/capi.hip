@@ -108,8 +108,12 @@ struct qmc_system_s {
   int* status = nullptr;
   double* val64 = nullptr;
   void* xinv = nullptr;      // FP64-refined inverse read by the measurement (mixed precision)
-  // mixed precision, particle-by-particle moves: FP64 fallback of ill-conditioned walkers
+  // mixed precision: FP64 inverses (particle-by-particle moves: of the FP64 fallback walkers;
+  // drift moves: of every walker, with the FP64 gradient rows, for the velocities)
   double* binv64 = nullptr;
+  double* grad64 = nullptr;
+  double* ae_binv64 = nullptr;   // drift moves: FP64 inverses at R'
+  // mixed precision, particle-by-particle moves: FP64 fallback of ill-conditioned walkers
   int* fb = nullptr;
   double* eta = nullptr;
   float* ecol = nullptr;
@@ -185,6 +189,7 @@ Walkers<T> walkers_of(qmc_system s) {
   w.eta_age = s->eta_age;
   w.pstat = s->pstat;
   w.table = static_cast<const T*>(s->d_table);
+  w.grad64 = s->grad64;
   return w;
 }
 
@@ -388,7 +393,7 @@ void free_walkers(qmc_system s) {
   s->nacc = nullptr;
   s->val64 = nullptr;
   s->xinv = nullptr;
-  s->binv64 = s->eta = nullptr;
+  s->binv64 = s->eta = s->grad64 = s->ae_binv64 = nullptr;
   s->ecol = nullptr;
   s->fb = nullptr;
   s->eta_age = s->pstat = s->fbmark = nullptr;
@@ -407,16 +412,16 @@ void free_walkers(qmc_system s) {
 struct WalkerSizes {
   size_t pos, prop, vgl, cur, binv, logdet, sign, acc, nacc, status, scratch, drift, energy, val64, nguard, sweep,
       xinv, binv64, fb, eta, ecol, eta_age, pstat, fbmark, ae_binv, ae_logdet, ae_dj, ae_sign, ae_status, ae_vel, ae_logT,
-      dmc;
+      grad64, ae_binv64, dmc;
   size_t total() const {
     return align_up(pos) + align_up(prop) + align_up(vgl) + align_up(cur) + align_up(binv) +
            align_up(logdet) + align_up(sign) + align_up(acc) + align_up(nacc) + align_up(status) +
            align_up(scratch) + align_up(drift) + align_up(energy) + align_up(val64) + align_up(nguard) +
            align_up(sweep) + align_up(xinv) +
-           (binv64 ? align_up(binv64) + align_up(fb) + align_up(eta) + align_up(ecol) + align_up(eta_age) +
-                         align_up(pstat) +
-                         align_up(fbmark)
-                   : 0) +
+           align_up(binv64) + align_up(grad64) + align_up(ae_binv64) +
+           (fb ? align_up(fb) + align_up(eta) + align_up(ecol) + align_up(eta_age) + align_up(pstat) +
+                     align_up(fbmark)
+               : 0) +
            (ae_binv ? align_up(ae_binv) + align_up(ae_logdet) + align_up(ae_dj) + align_up(ae_sign) +
                           align_up(ae_status)
                     : 0) +
@@ -444,7 +449,12 @@ WalkerSizes walker_sizes(int n_up, int n_dn, int precision, int W, int n_orb, in
   z.val64 = precision == QMC_MIXED ? 2 * W * N * S * sizeof(double) : 0;
   z.xinv = precision == QMC_MIXED ? W * bs * ts : 0;
   const bool fbk = precision == QMC_MIXED && move_kind == QMC_MOVE_PBYP;   // FP64 fallback state
-  z.binv64 = fbk ? W * bs * sizeof(double) : 0;
+  // mixed precision with drift moves: FP64 gradient rows and FP64 inverses at R and R', so the
+  // drift velocities (the proposals' centres and the transition ratios) are FP64 quantities
+  const bool mdrift = precision == QMC_MIXED && move_kind == QMC_MOVE_ALL_DRIFT;
+  z.binv64 = fbk || mdrift ? W * bs * sizeof(double) : 0;
+  z.grad64 = mdrift ? 2 * W * N * 3 * S * sizeof(double) : 0;
+  z.ae_binv64 = mdrift ? W * bs * sizeof(double) : 0;
   z.fb = fbk ? W * sizeof(int) : 0;
   z.eta = fbk ? W * 4 * sizeof(double) : 0;
   z.ecol = fbk ? W * N * sizeof(float) : 0;
@@ -838,8 +848,12 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
     s->val64 = static_cast<double*>(s->mem.alloc(z.val64));
     s->xinv = s->mem.alloc(z.xinv);
   }
-  if (z.binv64) {
-    s->binv64 = static_cast<double*>(s->mem.alloc(z.binv64));
+  if (z.binv64) s->binv64 = static_cast<double*>(s->mem.alloc(z.binv64));
+  if (z.grad64) {
+    s->grad64 = static_cast<double*>(s->mem.alloc(z.grad64));
+    s->ae_binv64 = static_cast<double*>(s->mem.alloc(z.ae_binv64));
+  }
+  if (z.fb) {
     s->fb = static_cast<int*>(s->mem.alloc(z.fb));
     s->eta = static_cast<double*>(s->mem.alloc(z.eta));
     s->ecol = static_cast<float*>(s->mem.alloc(z.ecol));
@@ -864,7 +878,8 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
   if (!s->pos || !s->prop || !s->vgl || !s->cur || !s->binv || !s->logdet || !s->sign || !s->acc ||
       !s->nacc || !s->status || !s->scratch || !s->drift || !s->energy || !s->nguard || !s->sweep_ctr ||
       (s->d.precision == QMC_MIXED && (!s->val64 || !s->xinv)) ||
-      (z.binv64 && (!s->binv64 || !s->fb || !s->eta || !s->ecol || !s->eta_age || !s->pstat || !s->fbmark)) ||
+      (z.binv64 && !s->binv64) || (z.grad64 && (!s->grad64 || !s->ae_binv64)) ||
+      (z.fb && (!s->fb || !s->eta || !s->ecol || !s->eta_age || !s->pstat || !s->fbmark)) ||
       (ae && (!s->ae_binv || !s->ae_logdet || !s->ae_dj || !s->ae_sign || !s->ae_status)) ||
       (drift && (!s->ae_vcur || !s->ae_vprop || !s->ae_logT))) {
     free_walkers(s);
@@ -888,7 +903,7 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
   HIP_TRY(s, hipMemsetAsync(s->acc, 0, z.acc, s->stream));
   HIP_TRY(s, hipMemsetAsync(s->logdet, 0, z.logdet, s->stream));
   HIP_TRY(s, hipMemsetAsync(s->status, 0, z.status, s->stream));
-  if (z.binv64) {
+  if (z.fb) {
     HIP_TRY(s, hipMemsetAsync(s->fb, 0, z.fb, s->stream));
     HIP_TRY(s, hipMemsetAsync(s->pstat, 0, z.pstat, s->stream));
   }
@@ -951,13 +966,14 @@ hipError_t ae_step(qmc_system s) {
   prop.sign = s->ae_sign;
   prop.status = s->ae_status;
   prop.row_flip = 1;
+  prop.binv64 = s->ae_binv64;   // mixed precision, drift moves: the FP64 inverses at R'
   e = launch_rebuild<T>(s->P, prop, s->scratch, nullptr, s->stream);
   if (e != hipSuccess) return e;
   const bool drift = s->d.move_kind == QMC_MOVE_ALL_DRIFT;
   AeProposal<T> A{static_cast<T*>(s->ae_binv), s->ae_logdet, s->ae_sign, s->ae_status, s->ae_dj, s->ae_logT,
                   velocity_parts(s->P.N), jastrow_parts(s->P.N), s->fixed_node ? 1 : 0,
                   s->fixed_node ? s->dmc_i : nullptr,
-                  drift ? s->ae_vprop : nullptr, drift ? s->ae_vcur : nullptr};
+                  drift ? s->ae_vprop : nullptr, drift ? s->ae_vcur : nullptr, s->ae_binv64};
   if (s->d.move_kind == QMC_MOVE_ALL_DRIFT) {
     e = launch_ae_velocity<T>(s->P, walkers_of<T>(s), A, 1, s->ae_vprop, s->ae_vcur, s->stream);
     if (e != hipSuccess) return e;

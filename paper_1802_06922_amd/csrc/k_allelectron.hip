@@ -147,13 +147,27 @@ __global__ __launch_bounds__(kBlock) void k_ae_velocity(SysParams P, Walkers<T> 
     const int n = sp ? P.n_dn : P.n_up, k = i - (sp ? P.n_up : 0);
     const size_t item = (size_t)w * N + i;
     const int buf = Wk.cur[item] ^ prop;
-    const T* row = Wk.vgl + ((size_t)buf * P.W * N + item) * kComp * P.S;
-    const T* B = (prop ? A.binv : Wk.binv) + (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0) + k;
-    for (int l = s; l < n; l += 4) {
-      const double b = (double)B[(size_t)l * n];
-      g0 += b * (double)row[P.S + l];
-      g1 += b * (double)row[2 * P.S + l];
-      g2 += b * (double)row[3 * P.S + l];
+    const size_t boff = (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0) + k;
+    if (Wk.grad64) {
+      // mixed precision: FP64 gradient rows and the FP64 inverse, so the proposal centre and
+      // the transition ratio, which decide the move, carry no FP32 rounding
+      const double* g = Wk.grad64 + ((size_t)buf * P.W * N + item) * 3 * P.S;
+      const double* B = (prop ? A.binv64 : Wk.binv64) + boff;
+      for (int l = s; l < n; l += 4) {
+        const double b = B[(size_t)l * n];
+        g0 += b * g[l];
+        g1 += b * g[P.S + l];
+        g2 += b * g[2 * P.S + l];
+      }
+    } else {
+      const T* row = Wk.vgl + ((size_t)buf * P.W * N + item) * kComp * P.S;
+      const T* B = (prop ? A.binv : Wk.binv) + boff;
+      for (int l = s; l < n; l += 4) {
+        const double b = (double)B[(size_t)l * n];
+        g0 += b * (double)row[P.S + l];
+        g1 += b * (double)row[2 * P.S + l];
+        g2 += b * (double)row[3 * P.S + l];
+      }
     }
     // Jastrow part: partners in three ranges (same spin, opposite spin, ions), every fourth
     const double xi0 = sx[i], xi1 = sy[i], xi2 = sz[i];
@@ -300,6 +314,8 @@ __global__ __launch_bounds__(kBlock) void k_ae_apply(SysParams P, Walkers<T> Wk,
     } else {
       for (size_t q = tid; q < (size_t)P.bstride; q += kBlock) Wk.binv[base + q] = A.binv[base + q];
     }
+    if (A.binv64 && Wk.binv64)
+      for (size_t q = tid; q < (size_t)P.bstride; q += kBlock) Wk.binv64[base + q] = A.binv64[base + q];
   }
   if (tid == 0) {
     if (acc) {

@@ -147,7 +147,8 @@ __global__ __launch_bounds__(kBranchBlock) void k_dmc_branch(SysParams P, DmcSta
 }
 
 // The state of slot plan[f] copied into every slot f that received a copy: positions, row
-// flags, the current rows (value, gradient, Laplacian; FP64 values in mixed precision),
+// flags, the current rows (value, gradient, Laplacian; FP64 values, and with drift moves FP64
+// gradients, in mixed precision),
 // inverses, log|D| and signs.  One workgroup per slot.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dmc_copy(SysParams P, Walkers<T> Wk, DmcState D) {
@@ -171,9 +172,17 @@ __global__ __launch_bounds__(kBlock) void k_dmc_copy(SysParams P, Walkers<T> Wk,
       uint4* d64 = reinterpret_cast<uint4*>(Wk.val64 + ((b * P.W * N) + f0 + i) * P.S);
       for (int c = lane; c < r64; c += 64) d64[c] = s64[c];
     }
+    if (Wk.grad64) {
+      const uint4* s64 = reinterpret_cast<const uint4*>(Wk.grad64 + ((b * P.W * N) + s0 + i) * 3 * P.S);
+      uint4* d64 = reinterpret_cast<uint4*>(Wk.grad64 + ((b * P.W * N) + f0 + i) * 3 * P.S);
+      for (int c = lane; c < 3 * r64; c += 64) d64[c] = s64[c];
+    }
   }
   for (size_t q = tid; q < (size_t)P.bstride; q += kBlock)
     Wk.binv[(size_t)f * P.bstride + q] = Wk.binv[(size_t)src * P.bstride + q];
+  if (Wk.binv64)
+    for (size_t q = tid; q < (size_t)P.bstride; q += kBlock)
+      Wk.binv64[(size_t)f * P.bstride + q] = Wk.binv64[(size_t)src * P.bstride + q];
   if (D.vel)
     for (int q = tid; q < 3 * N; q += kBlock) D.vel[f0 * 3 + q] = D.vel[s0 * 3 + q];
   __syncthreads();   // every thread has read the source's row flags

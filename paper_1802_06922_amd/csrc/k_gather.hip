@@ -143,6 +143,7 @@ __device__ __forceinline__ void gather_item(const SysParams& P, const Walkers<T>
   axis_weights(r[2], P.L, P.gz, az);
   T* out = Wk.vgl + ((size_t)buf * P.W * P.N + (size_t)item) * kComp * P.S;
   double* out64 = Wk.val64 ? Wk.val64 + ((size_t)buf * P.W * P.N + (size_t)item) * P.S : nullptr;
+  double* g64 = Wk.grad64 ? Wk.grad64 + ((size_t)buf * P.W * P.N + (size_t)item) * 3 * P.S : nullptr;
   const int nvec = P.S / V;
   for (int q = lane; q < nvec; q += tpi) {
     double acc[kComp][V];
@@ -153,6 +154,11 @@ __device__ __forceinline__ void gather_item(const SysParams& P, const Walkers<T>
 #pragma unroll
       for (int e = 0; e < V; ++e) out64[(size_t)q * V + e] = acc[0][e];
     }
+    if (g64)       // and, with drift moves, the FP64 gradients the velocities are built from
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int e = 0; e < V; ++e) g64[(size_t)c * P.S + (size_t)q * V + e] = acc[1 + c][e];
   }
 }
 

@@ -77,6 +77,7 @@ struct Walkers {
   // inverse cannot carry FP64 decisions (an ill-conditioned Slater matrix) runs its chain in
   // FP64 on binv64 until its conditioning allows FP32 again.
   double* binv64;     // [W][bstride]: FP64 inverses; current for the walkers with fb[w] = 1
+                      // (and, with drift moves, for every walker: the velocities read them)
   int* fb;            // [W]: 1 = FP64 fallback walker
   int fb_sel;         // chain launches advance only the walkers with fb[w] == fb_sel
   double* eta;        // [W][4]: ||I - A B||_F of each spin's inverse at the last check, then ||B||_F
@@ -84,6 +85,9 @@ struct Walkers {
   uint32_t* eta_age;  // [W]: sweeps since eta was measured
   uint32_t* pstat;    // [W][2]: early FP64 rebuilds, sweeps run in FP64 fallback (cumulative)
   const T* table;     // the orbital table (the measurement of fallback walkers evaluates it in FP64)
+  // Mixed precision with drift moves (else null): the FP64 gradient rows the gather computed,
+  // [2][W][N][3][S] beside vgl's buffers, so that drift velocities are FP64 quantities.
+  double* grad64;
 };
 
 // Walkers a chain launch skips: those of the other precision class.

@@ -164,6 +164,8 @@ struct AeProposal {
   int* crossed;     // [W] or null: 1 where the move was rejected for crossing a node
   const double* vprop;  // [W][N][3] or null: drift velocities at R', which become those at R
   double* vcur;         //   (vcur) of an accepted walker
+  double* binv64;       // [W][bstride] or null: FP64 inverses at R' (mixed precision, drift
+                        //   moves), which become the current ones of an accepted walker
 };
 // dj[w][jastrow_parts(N)] = partial sums of J(R') - J(R) from pos and the proposals; clears
 // status_prop.

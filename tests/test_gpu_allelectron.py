@@ -147,11 +147,19 @@ def test_drift_large_spin_blocks(gpu, orc):
 
 
 def test_drift_mixed_precision(gpu, orc):
-    """FP32 inverses and gradient rows: the drift velocities carry FP32 rounding, so the
-    proposals agree with the oracle's to about 1e-9 bohr and the decisions are still the
-    oracle's (none falls that close to its threshold)."""
+    """Mixed precision builds the drift velocities from the FP64 gradient rows and the FP64
+    inverses (the quantities that place the proposals and weigh the transition ratio), so
+    positions and log|D| agree with the oracle's to the FP64 bars and every decision is the
+    oracle's; only the local energies carry FP32 rounding."""
     wl = qi.solid(48, 16, n_walkers=16, n_sweeps=1, precision="mixed", table_dtype=np.float32)
-    b = _compare(gpu, orc, _ae(wl, 0.08, drift=True), 12, range(16), tol=MIXED_TOL, pos_tol=1e-7)
+    b = _compare(gpu, orc, _ae(wl, 0.08, drift=True), 12, range(16), tol=MIXED_TOL)
+    assert 0.1 < b.mean() < 0.97
+
+
+def test_drift_mixed_precision_long_run(gpu, orc):
+    """64 walkers over 60 sweeps (3840 decisions), eight of them against the oracle."""
+    wl = qi.solid(48, 16, n_walkers=64, n_sweeps=1, precision="mixed", table_dtype=np.float32, seed=4)
+    b = _compare(gpu, orc, _ae(wl, 0.08, drift=True), 60, [0, 9, 17, 26, 35, 44, 53, 63], tol=MIXED_TOL)
     assert 0.1 < b.mean() < 0.97
 
 

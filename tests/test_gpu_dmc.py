@@ -137,8 +137,17 @@ def test_dmc_solid128(gpu, orc):
 
 
 def test_dmc_mixed_precision(gpu, orc):
+    """FP32 table and rows; the drift velocities are FP64 (FP64 gradient rows and inverses), so
+    the positions follow the oracle's to the FP64 bar and only the energies carry FP32
+    rounding."""
     wl = qi.solid(48, 16, n_walkers=1, n_sweeps=1, precision="mixed", table_dtype=np.float32)
-    _compare(gpu, orc, _drift(wl, 0.08), 48, 32, 12, 0.5, rel=1e-5, pos_tol=1e-7)
+    _compare(gpu, orc, _drift(wl, 0.08), 48, 32, 12, 0.5, rel=1e-5)
+
+
+def test_dmc_mixed_precision_long_run(gpu, orc):
+    """96 slots, 64 walkers at the start, 40 steps."""
+    wl = qi.solid(48, 16, n_walkers=1, n_sweeps=1, precision="mixed", table_dtype=np.float32, seed=6)
+    _compare(gpu, orc, _drift(wl, 0.08), 96, 64, 40, 0.5, rel=1e-5)
 
 
 def test_dmc_with_three_body_jastrow(gpu, orc):
