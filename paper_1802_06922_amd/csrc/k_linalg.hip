@@ -910,7 +910,12 @@ hipError_t launch_rebuild(const SysParams& P, const Walkers<T>& Wk, double* scra
   // QMC_REBUILD_GLOBAL=1 takes the global-memory elimination for every size (lets the
   // tests compare the two kernels)
   const char* fg = getenv("QMC_REBUILD_GLOBAL");
-  if (!(fg && fg[0] == '1') && nmax <= kRegRebuildMax) {
+  // A selective rebuild (a few walkers, launched beside other kernels) of blocks beyond 64 takes
+  // the panel kernel when it fits: its 256-thread workgroups are placed beside the other
+  // kernels' workgroups, where a 1024-thread one waits for a whole compute unit to drain.
+  const bool beside = sel && nmax > 64;
+  if (!(fg && fg[0] == '1') && nmax <= kRegRebuildMax &&
+      !(beside && panel_layout(nmax, 16).total <= (size_t)lds_budget_rebuild())) {
     const dim3 grid(2 * P.W);
     if (nmax <= 64) {
       const dim3 block(16 * 16);
