@@ -148,7 +148,8 @@ class OracleSystem:
         s.coulomb = int((wl.hamiltonian == "coulomb") if coulomb is None else coulomb)
         s.ewald_kappa = kappa
         ae = bool(getattr(wl, "all_electron", False))
-        s.all_electron = (2 if getattr(wl, "drift", False) else 1) if ae else 0
+        drift = bool(getattr(wl, "drift", False))
+        s.all_electron = (2 if drift else 1) if ae else (3 if drift else 0)
         j3 = getattr(wl, "j3", None)
         if j3 is not None and wl.n_ions > 0:
             s.j3_mei, s.j3_mee, s.j3_rc = j3["m_ei"], j3["m_ee"], j3["rc"]
@@ -233,7 +234,7 @@ class OracleSystem:
         rc = lib().orc_dmc_run(self.ptr, n_slots, n_target, e_trial, feedback, sweep0, n_steps, _dp(st),
                                _dp(w), _ip(m), _ip(pl), _dp(en), _dp(fp), _ip(fs), threads)
         if rc == -2:
-            raise ValueError("DMC needs drift-diffusion all-electron moves (all_electron and drift)")
+            raise ValueError("DMC needs drift-diffusion moves (drift)")
         if rc == -1:
             raise ValueError("the population died out")
         if rc:

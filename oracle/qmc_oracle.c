@@ -164,7 +164,8 @@ typedef struct {
     int32_t coulomb;           /* 0: kinetic only; 1: kinetic + Ewald Coulomb */
     double ewald_kappa;        /* <= 0: 5 / L */
     int32_t all_electron;      /* 0: particle-by-particle sweeps; 1: all-electron moves;
-                                  2: all-electron drift-diffusion moves */
+                                  2: all-electron drift-diffusion moves; 3: particle-by-particle
+                                  drift-diffusion sweeps */
     int32_t j3_mei, j3_mee;    /* three-body e-e-I term: polynomial orders (0 = term off when
                                   j3_gamma is NULL) */
     double j3_rc;              /* its cutoff r_c: the electron-ion distances stay below r_c/2 */
@@ -844,6 +845,81 @@ static void orc_sweep(const orc_system* s, orc_walker* w, uint32_t walker_id, ui
 }
 
 /*
+ * Particle-by-particle drift-diffusion sweep (section "Trial Moves": the transition
+ * probability of one electron's move with the wavefunction force F = 2 grad ln Psi and
+ * lambda = 1/2, time step tau = sigma^2).  Electron i, in index order, at the current
+ * configuration R (the earlier moves of this sweep already applied):
+ *   v   = grad_i ln|Psi(R)| = sum_l grad phi_l(r_i) B[l][k] + grad_i J(R)
+ *   r'  = r_i + tau v + sigma xi        (xi from the PROPOSE counters of (walker, sweep, i))
+ *   R   = sum_l phi_l(r') B[l][k],  dJ = J(R') - J(R)
+ *   v'  = grad_i ln|Psi(R')| = sum_l grad phi_l(r') B[l][k] / R + grad_i J(R')
+ *         (the k-th column of the updated inverse is B[:,k] / R)
+ *   ln T(R'->R) / T(R->R') = [ |sigma xi|^2 - |sigma xi + tau (v + v')|^2 ] / (2 tau)
+ * and the move is accepted iff u < R^2 exp(2 dJ + ln T ratio) (eq. accept_reject), u the
+ * ACCEPT draw of (walker, sweep, i).  R = 0 rejects; with fixed_node a move with R < 0
+ * (a change of the sign of Psi) is rejected too.  Returns the number of such rejections.
+ */
+static int orc_drift_sweep(const orc_system* s, orc_walker* w, uint32_t walker_id, uint32_t sweep,
+                           uint8_t* accept_bits, int fixed_node)
+{
+    const int N = s->n_up + s->n_dn, no = s->n_orb;
+    const double tau = s->sigma * s->sigma;
+    double* v = (double*)malloc(sizeof(double) * no);
+    double* g = (double*)malloc(sizeof(double) * 3 * no);
+    double* l = (double*)malloc(sizeof(double) * no);
+    double* trial = (double*)malloc(sizeof(double) * 3 * (N > 0 ? N : 1));
+    int crossings = 0;
+    for (int i = 0; i < N; ++i) {
+        const int sp = orc_spin(s, i), n = orc_spin_count(s, sp), k = i - orc_spin_offset(s, sp);
+        const double* B = w->B[sp];
+        double vel[3], gJ[3], lJ, xi[3], sx[3], rp[3];
+        orc_spo_vgl(s, w->pos + 3 * i, v, g, l);
+        orc_jastrow_grad_lap(s, w->pos, i, gJ, &lJ);
+        for (int a = 0; a < 3; ++a) {
+            double gd = 0.0;
+            for (int j = 0; j < n; ++j) gd += g[a * no + j] * B[j * n + k];
+            vel[a] = gd + gJ[a];
+        }
+        orc_gauss3(s->seed, walker_id, sweep, (uint32_t)i, xi);
+        for (int a = 0; a < 3; ++a) {
+            sx[a] = s->sigma * xi[a];
+            rp[a] = orc_wrap(w->pos[3 * i + a] + tau * vel[a] + sx[a], s->L);
+        }
+        orc_spo_vgl(s, rp, v, g, l);
+        double R = 0.0;
+        for (int j = 0; j < n; ++j) R += v[j] * B[j * n + k];
+        const double dJ = orc_jastrow_of(s, w->pos, i, rp) - orc_jastrow_of(s, w->pos, i, w->pos + 3 * i);
+        const double u = orc_accept_uniform(s->seed, walker_id, sweep, (uint32_t)i);
+        const int crossed = fixed_node && R < 0.0;
+        int acc = 0;
+        if (R != 0.0 && !crossed) {
+            memcpy(trial, w->pos, sizeof(double) * 3 * N);
+            for (int a = 0; a < 3; ++a) trial[3 * i + a] = rp[a];
+            orc_jastrow_grad_lap(s, trial, i, gJ, &lJ);
+            double logT = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                double gd = 0.0;
+                for (int j = 0; j < n; ++j) gd += g[a * no + j] * B[j * n + k];
+                const double back = sx[a] + tau * (vel[a] + gd / R + gJ[a]);
+                logT += (sx[a] * sx[a] - back * back) / (2.0 * tau);
+            }
+            acc = u < R * R * exp(2.0 * dJ + logT);
+        }
+        crossings += crossed;
+        if (acc) {
+            orc_sherman_morrison(n, w->B[sp], k, v, R);
+            for (int j = 0; j < n; ++j) w->A[sp][k * n + j] = v[j];
+            w->logdet_accum[sp] += log(fabs(R));
+            if (R < 0.0) w->sign[sp] = -w->sign[sp];
+            for (int a = 0; a < 3; ++a) w->pos[3 * i + a] = rp[a];
+        }
+        if (accept_bits) accept_bits[i] = (uint8_t)acc;
+    }
+    free(v); free(g); free(l); free(trial);
+    return crossings;
+}
+
+/*
  * Drift velocity v_i = grad_i ln|Psi| of every electron at configuration pos with
  * inverses B[sp] (B[l][k]): the log-determinant gradient sum_l grad phi_l(r_i) B[l][k]
  * of the electron's spin block plus the Jastrow gradient.  v: [N][3].
@@ -1023,7 +1099,8 @@ int orc_vmc_run(const orc_system* s, int n_walk, const int32_t* walker_ids, cons
         int im = 0;
         for (int st = 0; st < n_sweeps; ++st) {
             uint8_t* bits = accept_bits ? accept_bits + ((size_t)wi * n_sweeps + st) * N : NULL;
-            if (s->all_electron) orc_ae_step(s, &w, wid, (uint32_t)(sweep0 + st), bits, 0);
+            if (s->all_electron == 3) orc_drift_sweep(s, &w, wid, (uint32_t)(sweep0 + st), bits, 0);
+            else if (s->all_electron) orc_ae_step(s, &w, wid, (uint32_t)(sweep0 + st), bits, 0);
             else orc_sweep(s, &w, wid, (uint32_t)(sweep0 + st), bits);
             if (pos_trace) memcpy(pos_trace + ((size_t)wi * n_sweeps + st) * N * 3, w.pos, sizeof(double) * 3 * N);
             if (measure_every > 0 && (st + 1) % measure_every == 0 && im < n_meas) {
@@ -1064,8 +1141,9 @@ static void orc_walker_copy(const orc_system* s, orc_walker* dst, const orc_walk
  * walker slots, of which the first n_target start alive with weight 1 from the INIT stream
  * (walker id = slot).  Step k (moves use sweep index sweep0 + k):
  *   1. every alive walker makes one drift-diffusion all-electron move (eq.
- *      pmc:driftdiffusion_step with the Metropolis acceptance of eq. accept_reject), a move
- *      that crosses a node (changes the sign of Psi) being rejected (fixed node);
+ *      pmc:driftdiffusion_step with the Metropolis acceptance of eq. accept_reject), or one
+ *      particle-by-particle drift-diffusion sweep, a move that crosses a node (changes the
+ *      sign of Psi) being rejected (fixed node);
  *   2. w <- w G_B with G_B = exp(-tau (E_L(R) + E_L(R_new) - 2 E_T) / 2) (eqs.
  *      pmc:g_growth, pmc:walker_weight), tau = sigma^2, R_new the configuration after the
  *      move (R itself when rejected);
@@ -1083,13 +1161,13 @@ static void orc_walker_copy(const orc_system* s, orc_walker* dst, const orc_walk
  * energies[k][slot] = E_L after the move (alive slots); final_pos[slot][N][3] and
  * final_sign[slot] (sign of D_up D_dn) after the last step (alive slots).
  * Returns 0, 1 + slot of a singular initial walker, -1 if the population dies out, -2 if
- * the system does not make drift-diffusion all-electron moves.
+ * the system makes no drift-diffusion moves.
  */
 int orc_dmc_run(const orc_system* s, int n_slots, int n_target, double e_trial, double feedback, int sweep0,
                 int n_steps, double* stats, double* weights, int32_t* mult, int32_t* plan, double* energies,
                 double* final_pos, int32_t* final_sign, int n_threads)
 {
-    if (s->all_electron != 2) return -2;
+    if (s->all_electron != 2 && s->all_electron != 3) return -2;
     const int N = s->n_up + s->n_dn;
     const double tau = s->sigma * s->sigma;
     double v_ii = NAN;
@@ -1138,7 +1216,8 @@ int orc_dmc_run(const orc_system* s, int n_slots, int n_target, double e_trial, 
 #endif
         for (int j = 0; j < n_slots; ++j) {
             if (!alive[j]) continue;
-            crossed[j] = orc_ae_step(s, &W[j], (uint32_t)j, (uint32_t)(sweep0 + k), NULL, 1);
+            crossed[j] = s->all_electron == 3 ? orc_drift_sweep(s, &W[j], (uint32_t)j, (uint32_t)(sweep0 + k), NULL, 1)
+                                              : orc_ae_step(s, &W[j], (uint32_t)j, (uint32_t)(sweep0 + k), NULL, 1);
             double o[4];
             orc_measure(s, &W[j], v_ii, o);
             const double en = o[0] + o[1] + o[2] + o[3];

@@ -60,7 +60,8 @@ class Workload:
     pw_k: Optional[np.ndarray] = None     # [n_orb][3] wave vectors of the analytic plane-wave orbitals
     pw_kind: Optional[np.ndarray] = None  # [n_orb] 0 = cos(k.r), 1 = sin(k.r)
     all_electron: bool = False    # moves: False = particle-by-particle sweeps, True = all-electron moves
-    drift: bool = False           # all-electron moves drawn from the drift-diffusion distribution
+    drift: bool = False           # moves drawn from the drift-diffusion distribution (all-electron
+                                  # or particle-by-particle)
     j3: Optional[dict] = None     # three-body e-e-I term: {"m_ei", "m_ee", "rc", "gamma" [2][m_ei+1][m_ei+1][m_ee+1]}
 
     @property
