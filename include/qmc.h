@@ -126,8 +126,20 @@ typedef enum { QMC_H_KINETIC = 0, QMC_H_COULOMB_EWALD = 1 } qmc_hamiltonian;
  *                 eliminations (both kept beside the FP32 state), so every
  *                 quantity that decides a move is FP64; only the local
  *                 energies read the FP32 rows.
+ *                 QMC_MOVE_PBYP_DRIFT (3): particle-by-particle sweeps whose
+ *                 moves are drawn from the drift-diffusion distribution of one
+ *                 electron (section "Trial Moves"): electron i, in index
+ *                 order, proposes r_i + tau v + sigma xi with v = grad_i
+ *                 ln|Psi| at the configuration the earlier moves of the sweep
+ *                 left, and accepts with min(1, R^2 exp(2 dJ) T(r'->r) /
+ *                 T(r->r')), the velocity at r' from the updated inverse
+ *                 column B[:,k] / R; R = 0 rejects.  The orbital row at each
+ *                 proposal is evaluated inside the sequential chain
+ *                 (Sherman-Morrison updates; delay_rank does not apply,
+ *                 recompute_period does).  FP64 only (ARG otherwise); the
+ *                 spin block's chain must fit one workgroup's LDS (ARG).
  */
-enum { QMC_MOVE_PBYP = 0, QMC_MOVE_ALL = 1, QMC_MOVE_ALL_DRIFT = 2 };
+enum { QMC_MOVE_PBYP = 0, QMC_MOVE_ALL = 1, QMC_MOVE_ALL_DRIFT = 2, QMC_MOVE_PBYP_DRIFT = 3 };
 
 typedef struct {
     int32_t n_up, n_dn;
@@ -227,7 +239,9 @@ qmc_status qmc_run_steps(qmc_system s, int32_t n_steps, double* energies_dev);
 
 /* ---- Diffusion Monte Carlo (section "Diffusion Monte Carlo") ----------------
  * The handle's W walker slots hold the population (fixed capacity); a slot is
- * alive while its weight is positive.  Needs move_kind QMC_MOVE_ALL_DRIFT.
+ * alive while its weight is positive.  Needs move_kind QMC_MOVE_ALL_DRIFT or
+ * QMC_MOVE_PBYP_DRIFT (then a step moves every electron of a slot once, a move
+ * with R < 0 being rejected; the node-crossing count is per electron move).
  * A step: every slot makes one drift-diffusion all-electron move (section
  * "Trial Moves"), a move across a node of Psi being rejected (fixed node);
  * alive slots take w <- w exp(-tau (E_L(R) + E_L(R_new) - 2 E_T) / 2), tau =
@@ -245,7 +259,7 @@ qmc_status qmc_run_steps(qmc_system s, int32_t n_steps, double* energies_dev);
  * local energy of the alive slots; feedback >= 0 in hartree.  Synchronises.
  * The first call after qmc_init_walkers allocates the population buffers
  * (about 60 bytes per slot; qmc_estimate_device_bytes counts them).
- * Errors: STATE (no walkers, or not QMC_MOVE_ALL_DRIFT), ARG, OOM, NUMERIC. */
+ * Errors: STATE (no walkers, or no drift moves), ARG, OOM, NUMERIC. */
 qmc_status qmc_dmc_init(qmc_system s, int32_t n_target, double e_trial, double feedback);
 
 /* n_steps DMC steps on the handle's stream, asynchronous.  stats_dev: device

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libqmc.so")
-SOURCES = ["capi.hip", "k_gather.hip", "k_chain.hip", "k_delayed.hip", "k_linalg.hip", "k_measure.hip", "k_allelectron.hip", "k_dmc.hip"]
+SOURCES = ["capi.hip", "k_gather.hip", "k_chain.hip", "k_delayed.hip", "k_linalg.hip", "k_measure.hip", "k_allelectron.hip", "k_dmc.hip", "k_drift.hip"]
 ARCH = os.environ.get("QMC_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are switched off for every GPU source.

@@ -470,12 +470,13 @@ WalkerSizes walker_sizes(int n_up, int n_dn, int precision, int W, int n_orb, in
   z.ae_sign = ae ? W * 2 * sizeof(int) : 0;
   z.ae_status = ae ? W * sizeof(int) : 0;
   const bool drift = move_kind == QMC_MOVE_ALL_DRIFT;
+  const bool dmc_ok = drift || move_kind == QMC_MOVE_PBYP_DRIFT;   // moves DMC can run on
   z.ae_vel = drift ? W * N * 3 * sizeof(double) : 0;
   z.ae_logT = drift ? W * (size_t)velocity_parts((int)N) * sizeof(double) : 0;
   // the DMC population qmc_dmc_init carves out (weights, energies, [W][4] energies, [W][2]
   // weights and energies before branching, control doubles, five [W] int arrays and the
   // control ints)
-  z.dmc = drift ? align_up(W * sizeof(double)) * 2 + align_up(W * 4 * sizeof(double)) +
+  z.dmc = dmc_ok ? align_up(W * sizeof(double)) * 2 + align_up(W * 4 * sizeof(double)) +
                       align_up(W * 2 * sizeof(double)) + align_up(2 * sizeof(double)) +
                       align_up((5 * (size_t)W + 3) * sizeof(int))
                 : 0;
@@ -506,8 +507,11 @@ qmc_status validate(const qmc_system_desc* d) {
     return fail(nullptr, QMC_ERR_ARG, "delay_rank %d: use 1 (Sherman-Morrison) or a power of two in [4, 64]",
                 d->delay_rank);
   if (d->recompute_period < 0) return fail(nullptr, QMC_ERR_ARG, "recompute_period must be >= 0");
-  if (d->move_kind != QMC_MOVE_PBYP && d->move_kind != QMC_MOVE_ALL && d->move_kind != QMC_MOVE_ALL_DRIFT)
+  if (d->move_kind != QMC_MOVE_PBYP && d->move_kind != QMC_MOVE_ALL && d->move_kind != QMC_MOVE_ALL_DRIFT &&
+      d->move_kind != QMC_MOVE_PBYP_DRIFT)
     return fail(nullptr, QMC_ERR_ARG, "unknown move_kind %d", d->move_kind);
+  if (d->move_kind == QMC_MOVE_PBYP_DRIFT && d->precision != QMC_FP64)
+    return fail(nullptr, QMC_ERR_ARG, "particle-by-particle drift moves run in FP64 (precision QMC_FP64)");
   if (d->hamiltonian != QMC_H_KINETIC && d->hamiltonian != QMC_H_COULOMB_EWALD)
     return fail(nullptr, QMC_ERR_ARG, "unknown hamiltonian %d", d->hamiltonian);
   if (d->n_ions < 0 || (d->n_ions > 0 && (!d->ion_pos || !d->ion_Z)))
@@ -580,6 +584,7 @@ hipError_t prepare_dynamic_lds() {
   if (e == hipSuccess) e = delayed_lds_limits();
   if (e == hipSuccess) e = linalg_lds_limits();
   if (e == hipSuccess) e = measure_lds_limits();
+  if (e == hipSuccess) e = drift_lds_limits();
   return e;
 }
 
@@ -651,6 +656,11 @@ qmc_status qmc_create_system(const qmc_system_desc* desc, void* hip_stream, qmc_
                j2p ? j2p[0] : 0.0, (j2p && desc->j2_n > 1) ? j2p[1] : 0.0);
   build_radial(P.jas.ei, M > 0 ? desc->j1_kind : QMC_J_NONE, desc->j1_params, desc->j1_n,
                desc->j1_rcut, desc->j1_cusp, 0.0, 0.0);
+  if (desc->move_kind == QMC_MOVE_PBYP_DRIFT && !drift_chain_fits(P)) {
+    delete s;
+    return fail(nullptr, QMC_ERR_ARG, "the particle-by-particle drift chain of this system does not fit one "
+                "workgroup's LDS");
+  }
   if (s->d.delay_rank > 1 && !delayed_feasible(P, tsize_of(desc->precision), s->d.delay_rank)) {
     delete s;
     return fail(nullptr, QMC_ERR_ARG, "delay_rank %d does not fit one workgroup's LDS for this system",
@@ -933,6 +943,8 @@ namespace {
 // The proposals of one sweep (gather), on stream st.
 qmc_status sweep_gather(qmc_system s, hipStream_t st) {
   hipError_t e;
+  // particle-by-particle drift moves evaluate each proposal's row inside the chain
+  if (s->d.move_kind == QMC_MOVE_PBYP_DRIFT) return QMC_OK;
   if (s->d.move_kind == QMC_MOVE_ALL_DRIFT && !s->vcur_valid) {
     // drift velocities at the current configuration, which the proposals are centred on
     // (timed with the move kernels, so the gather's own time stays separate).  Afterwards a
@@ -982,6 +994,17 @@ hipError_t ae_step(qmc_system s) {
 }
 
 qmc_status sweep_chain(qmc_system s) {
+  if (s->d.move_kind == QMC_MOVE_PBYP_DRIFT) {
+    const hipError_t e = timed(s, 1, [&] {
+      return launch_chain_drift(s->P, walkers_of<double>(s), static_cast<const double*>(s->d_table), s->sweep_index,
+                                s->fixed_node ? 1 : 0, s->fixed_node ? s->dmc_i : nullptr, s->stream);
+    });
+    if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "drift sweep launch: %s", hipGetErrorString(e));
+    s->sweep_index += 1;
+    if (s->d.recompute_period > 0 && s->sweep_index % (uint32_t)s->d.recompute_period == 0)
+      return run_rebuild(s, nullptr);
+    return QMC_OK;
+  }
   if (s->d.move_kind != QMC_MOVE_PBYP) {
     // the inverses are recomputed at every accepted move, so no periodic rebuild is needed
     const hipError_t e = s->d.precision == QMC_MIXED ? timed(s, 1, [&] { return ae_step<float>(s); })
@@ -1139,8 +1162,9 @@ extern "C" {
 qmc_status qmc_dmc_init(qmc_system s, int32_t n_target, double e_trial, double feedback) {
   if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
   if (!s->has_walkers) return fail(s, QMC_ERR_STATE, "init_walkers first");
-  if (s->d.move_kind != QMC_MOVE_ALL_DRIFT)
-    return fail(s, QMC_ERR_STATE, "diffusion Monte Carlo needs move_kind QMC_MOVE_ALL_DRIFT");
+  if (s->d.move_kind != QMC_MOVE_ALL_DRIFT && s->d.move_kind != QMC_MOVE_PBYP_DRIFT)
+    return fail(s, QMC_ERR_STATE, "diffusion Monte Carlo needs drift moves (QMC_MOVE_ALL_DRIFT or "
+                "QMC_MOVE_PBYP_DRIFT)");
   const int W = s->P.W;
   if (n_target < 1 || n_target > W) return fail(s, QMC_ERR_ARG, "n_target must be in [1, %d]", W);
   if (!(feedback >= 0.0) || !std::isfinite(feedback)) return fail(s, QMC_ERR_ARG, "feedback must be >= 0");

@@ -102,6 +102,15 @@ hipError_t chain_lds_limits();
 hipError_t delayed_lds_limits();
 hipError_t linalg_lds_limits();
 hipError_t measure_lds_limits();
+hipError_t drift_lds_limits();
+
+// Particle-by-particle drift-diffusion sweep of every walker (FP64; k_drift.hip): each move's
+// orbital row at its proposal is evaluated inside the chain.  sweep: the sweep's index in the
+// random streams; crossed (nullable): [W] node-crossing rejections of the sweep (fixed_node).
+hipError_t launch_chain_drift(const SysParams& P, const Walkers<double>& Wk, const double* table, uint32_t sweep,
+                              int fixed_node, int* crossed, hipStream_t st);
+// Whether that chain's LDS (inverse in global memory) fits one workgroup.
+bool drift_chain_fits(const SysParams& P);
 
 // Uniform initial positions from the INIT stream of every (walker, electron).
 hipError_t launch_init_positions(const SysParams& P, double* pos, hipStream_t st);

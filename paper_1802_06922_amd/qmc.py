@@ -164,7 +164,8 @@ def make_desc(wl, keep: list, arena=None, arena_bytes: int = 0, tie_guard: float
     d.arena = arena
     d.arena_bytes = arena_bytes
     ae = bool(getattr(wl, "all_electron", False))
-    d.move_kind = (2 if getattr(wl, "drift", False) else 1) if ae else 0
+    drift = bool(getattr(wl, "drift", False))
+    d.move_kind = (2 if drift else 1) if ae else (3 if drift else 0)
     j3 = getattr(wl, "j3", None)
     if j3 is not None and wl.n_ions > 0:
         d.j3_m_ei, d.j3_m_ee, d.j3_rcut = j3["m_ei"], j3["m_ee"], j3["rc"]

@@ -66,8 +66,8 @@ def _compare(gpu, orc, wl, n_sweeps, walkers, tol=E_TOL, pos_tol=1e-11):
     rel = _rel(e, ref["energies"])
     print(f"[ae] acceptance {b[:, :, 0].mean():.3f}, rel energy error max {rel.max():.2e}", flush=True)
     assert rel.max() < tol, f"max rel energy error {rel.max():.3e}"
-    np.testing.assert_allclose(pos, ref["final_pos"], atol=pos_tol)
-    np.testing.assert_allclose(ld, ref["logdet"], atol=1e-9 if pos_tol <= 1e-11 else 1e-6)
+    np.testing.assert_allclose(pos, ref["final_pos"], rtol=0, atol=pos_tol)
+    np.testing.assert_allclose(ld, ref["logdet"], rtol=0, atol=1e-9 if pos_tol <= 1e-11 else 1e-6)
     assert np.array_equal(sg, ref["sign"])
     return b
 

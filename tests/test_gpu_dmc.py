@@ -52,7 +52,7 @@ def _compare(gpu, orc, wl, n_slots, n_target, steps, feedback, rel=1e-10, pos_to
     alive = ref["final_sign"] != 0
     assert np.array_equal(w > 0, alive)
     assert pop == alive.sum()
-    np.testing.assert_allclose(pos[alive], ref["final_pos"][alive], atol=pos_tol)
+    np.testing.assert_allclose(pos[alive], ref["final_pos"][alive], rtol=0, atol=pos_tol)
     assert np.array_equal(sg[alive].prod(axis=1), ref["final_sign"][alive])
     return st
 
@@ -155,6 +155,29 @@ def test_dmc_with_three_body_jastrow(gpu, orc):
     energies that weight the walkers."""
     wl = qi.solid(24, 12, n_walkers=1, n_sweeps=1, j3=True, j3_strength=50.0)
     _compare(gpu, orc, _drift(wl, 0.12), 32, 24, 12, 0.5)
+
+
+def _pdrift(wl, sigma):
+    return dataclasses.replace(wl, all_electron=False, drift=True, sigma=sigma)
+
+
+def test_dmc_pbyp_drift_heg14(gpu, orc):
+    """DMC on particle-by-particle drift-diffusion sweeps (one sweep per step, a move with
+    R < 0 rejected), with copies, deaths and node-crossing rejections."""
+    st = _compare(gpu, orc, _pdrift(qi.heg14(), 0.4), 40, 24, 30, 0.5)
+    assert st[:, 5].sum() > 0 and st[:, 2].min() != st[:, 2].max()
+
+
+def test_dmc_pbyp_drift_per_slot_ragged_solid(gpu, orc):
+    wl = qi.solid(18, 14, n_walkers=1, n_sweeps=1)
+    wl.n_up, wl.n_dn, wl.n_orb = 9, 7, 9
+    wl.coefs = qi.solid_table(9, 14, seed=3, dtype=np.float64)
+    assert _per_slot(gpu, orc, _pdrift(wl, 0.05), 32, 24, 12, 0.5) > 0
+
+
+def test_dmc_pbyp_drift_solid128(gpu, orc):
+    """The 128-electron solid: 64 slots, 48 walkers, 6 steps."""
+    _compare(gpu, orc, _pdrift(qi.solid128(), 0.03), 64, 48, 6, 1.0)
 
 
 def test_dmc_in_a_caller_arena(gpu):

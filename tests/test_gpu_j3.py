@@ -44,7 +44,7 @@ def _compare(gpu, orc, wl, n_sweeps, walkers, tol=1e-10, pos_tol=1e-11):
     rel = _rel(e, ref["energies"])
     print(f"[j3] acceptance {b.mean():.3f}, rel energy error max {rel.max():.2e}", flush=True)
     assert rel.max() < tol
-    np.testing.assert_allclose(pos[sample], ref["final_pos"], atol=pos_tol)
+    np.testing.assert_allclose(pos[sample], ref["final_pos"], rtol=0, atol=pos_tol)
     assert np.array_equal(sg[sample], ref["sign"])
     return b
 

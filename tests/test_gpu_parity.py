@@ -60,8 +60,8 @@ def _compare_run(gpu, orc, wl, n_sweeps, walkers, n_walkers=None):
         f"first differing move: {np.argwhere(b != ref['accept'])[:3]}")
     rel = _rel(e, ref["energies"])
     assert rel.max() < E_TOL, f"max rel energy error {rel.max():.3e}"
-    np.testing.assert_allclose(pos, ref["final_pos"], atol=1e-11)
-    np.testing.assert_allclose(ld, ref["logdet"], atol=1e-9)
+    np.testing.assert_allclose(pos, ref["final_pos"], rtol=0, atol=1e-11)
+    np.testing.assert_allclose(ld, ref["logdet"], rtol=0, atol=1e-9)
     assert np.array_equal(sg, ref["sign"])
     return b, e
 
@@ -92,8 +92,8 @@ def test_init_matches_oracle(gpu, orc):
     pos, ld, sg = s.get_walkers()
     s.close()
     ref = orc.OracleSystem(wl).run(range(6), 0, measure_every=0)
-    np.testing.assert_allclose(pos, ref["final_pos"], atol=1e-13)
-    np.testing.assert_allclose(ld, ref["logdet_lu"], atol=1e-10)
+    np.testing.assert_allclose(pos, ref["final_pos"], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(ld, ref["logdet_lu"], rtol=0, atol=1e-10)
     assert np.array_equal(sg, ref["sign"])
 
 
@@ -401,13 +401,13 @@ def test_mixed384_full_run_sampled_walkers(gpu, orc):
           f"{n_fb0} walkers start in FP64 fallback, {fb_sweeps} fallback walker-sweeps, "
           f"{early} early rebuilds, {n_fb} in fallback at the end", flush=True)
     assert rel.max() < MIXED_TOL
-    np.testing.assert_allclose(pos[sample], ref["final_pos"], atol=1e-10)
+    np.testing.assert_allclose(pos[sample], ref["final_pos"], rtol=0, atol=1e-10)
     assert np.array_equal(sg[sample], ref["sign"])
     # log|D| is rebuilt in FP64 at sweep 448 and then sums ~5e3 logs of FP32 ratios per spin
     # block; with 50 sweeps between measurements the inverse drifts to ||I - A B|| ~ 1e-3, so each
     # ratio errs by up to ~1e-4 relative and the sum by ~sqrt(5e3) 1e-4 (the decisions, taken to
     # FP64 accuracy by the guard, are exact)
-    np.testing.assert_allclose(ld[sample], ref["logdet"], atol=1e-2)
+    np.testing.assert_allclose(ld[sample], ref["logdet"], rtol=0, atol=1e-2)
 
 
 @pytest.mark.parametrize("K", [16, 32])

@@ -117,7 +117,7 @@ def test_served_requests_match_the_oracle(gpu, orc):
             ref = o.run(range(r.wl.n_walkers), r.n_sweeps, measure_every=1)
             e, re = r.energy.sum(-1), ref["energies"][:, -1].sum(-1)
             assert (np.abs(e - re) / np.maximum(np.abs(re), 1.0)).max() < 1e-5
-            np.testing.assert_allclose(r.final_pos, ref["final_pos"], atol=1e-10)
+            np.testing.assert_allclose(r.final_pos, ref["final_pos"], rtol=0, atol=1e-10)
         else:
             ref = o.dmc(r.wl.n_walkers, r.dmc_target, r.n_sweeps, feedback=r.dmc_feedback)
             for c in (2, 4, 5):
@@ -126,4 +126,4 @@ def test_served_requests_match_the_oracle(gpu, orc):
                 err = np.abs(r.energy[:, c] - ref["stats"][:, c]) / np.maximum(np.abs(ref["stats"][:, c]), 1.0)
                 assert err.max() < 1e-5, (c, err.max())
             alive = ref["final_sign"] != 0
-            np.testing.assert_allclose(r.final_pos[alive], ref["final_pos"][alive], atol=1e-7)
+            np.testing.assert_allclose(r.final_pos[alive], ref["final_pos"][alive], rtol=0, atol=1e-7)
