@@ -293,15 +293,30 @@ qmc_status qmc_get_walkers(qmc_system s, double* pos, double* logabs_det, int32_
 /* Accept flags of the last sweep, host [W][N], 1 = accepted. */
 qmc_status qmc_get_accept_log(qmc_system s, uint8_t* bits);
 
-/* Counters since qmc_init_walkers (each nullable): redecided = moves whose
+/* Counters (each nullable): redecided = moves since qmc_init_walkers whose
  * acceptance fell inside the mixed-precision guard band and was decided again
- * from an FP64 ratio; sweeps = sweeps run.  Synchronises. */
+ * from an FP64 ratio; sweeps = the index of the next sweep in the random
+ * streams (the sweeps run since qmc_init_walkers, plus the index a resume set).
+ * Synchronises. */
 qmc_status qmc_get_counters(qmc_system s, uint64_t* redecided, uint64_t* sweeps);
+
+/* Resume a saved run (section "Variational Monte Carlo": each walker is an
+ * independent Markov chain; here its random numbers are counter-based draws
+ * indexed by walker, sweep and electron).  After qmc_init_walkers with the saved
+ * positions (qmc_get_walkers) this sets the index of the next sweep to the saved
+ * one (qmc_get_counters), so the run continues on the same streams: the moves
+ * propose what the uninterrupted run proposes and take its decisions (the
+ * inverses are fresh eliminations of the same positions, so the ratios differ
+ * only in rounding), and the periodic rebuild keeps its schedule (sweeps whose
+ * index is a multiple of recompute_period).  A DMC population is not resumed.
+ * Synchronises.  Errors: STATE before qmc_init_walkers; ARG for an index of
+ * 2^32 or more. */
+qmc_status qmc_set_sweep_index(qmc_system s, uint64_t sweep_index);
 
 /* Mixed precision, particle-by-particle moves: how the FP32 path keeps the FP64 decisions.
  * Every walker's inverse error ||I - A B||_F is measured after each full rebuild and by
  * the refinement before each measurement (A the FP64 Slater matrix); it widens that
- * walker's re-decision band (see tie_guard).  A walker whose measured error passes 2e-4 is
+ * walker's re-decision band (see tie_guard).  A walker whose measured error passes 2e-3 is
  * rebuilt in FP64 on its own; one whose freshly rounded FP32 inverse still errs by more
  * than 2e-4 (an ill-conditioned Slater matrix) runs its moves and its kinetic energy in
  * FP64 (fallback) until the error of its FP32 rounding drops below 5e-5.  Counters since

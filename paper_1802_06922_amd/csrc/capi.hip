@@ -1312,6 +1312,19 @@ qmc_status qmc_get_counters(qmc_system s, uint64_t* redecided, uint64_t* sweeps)
   return QMC_OK;
 }
 
+qmc_status qmc_set_sweep_index(qmc_system s, uint64_t sweep_index) {
+  if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");
+  if (!s->has_walkers) return fail(s, QMC_ERR_STATE, "init_walkers first");
+  if (sweep_index > 0xFFFFFFFFull) return fail(s, QMC_ERR_ARG, "sweep_index must be below 2^32");
+  HIP_TRY(s, hipSetDevice(s->device));
+  const uint32_t v = (uint32_t)sweep_index;
+  // the device counter is what the gathers read (and graph replays advance)
+  HIP_TRY(s, hipMemcpyAsync(s->sweep_ctr, &v, sizeof v, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(s, hipStreamSynchronize(s->stream));
+  s->sweep_index = v;
+  return QMC_OK;
+}
+
 qmc_status qmc_get_precision_stats(qmc_system s, uint64_t* early_rebuilds, uint64_t* fallback_sweeps,
                                    int32_t* fallback_now, int32_t* fallback_mask) {
   if (!s) return fail(nullptr, QMC_ERR_ARG, "handle is NULL");

@@ -30,7 +30,7 @@ EXPORTS = [
     "qmc_get_last_energies", "qmc_batch_create", "qmc_batch_sweep", "qmc_batch_set_graph",
     "qmc_batch_timing", "qmc_batch_destroy", "qmc_max_delay_rank", "qmc_autotune_gather",
     "qmc_set_gather_lanes", "qmc_run_steps", "qmc_dmc_init", "qmc_dmc_steps", "qmc_dmc_get", "qmc_dmc_get_branching",
-    "qmc_get_precision_stats", "qmc_eval_spo_vgl_noalloc",
+    "qmc_get_precision_stats", "qmc_eval_spo_vgl_noalloc", "qmc_set_sweep_index",
 ]
 NOALLOC_DOUBLES = 1 << 19   # QMC_NOALLOC_DOUBLES
 
@@ -84,6 +84,7 @@ def load_library():
     L.qmc_recompute.argtypes = [vp, dp]
     L.qmc_eval_spo_vgl.argtypes = [vp, C.c_int32, dp, dp]
     L.qmc_eval_spo_vgl_noalloc.argtypes = [vp, C.c_int32, dp, dp]
+    L.qmc_set_sweep_index.argtypes = [vp, C.c_uint64]
     L.qmc_set_timing.argtypes = [vp, C.c_int32]
     L.qmc_kernel_timing.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64), C.c_int32]
     L.qmc_destroy_system.argtypes = [vp]
@@ -286,6 +287,10 @@ class System:
         self._check(self.L.qmc_dmc_get(self.h, w.ctypes.data_as(C.POINTER(C.c_double)),
                                        e.ctypes.data_as(C.POINTER(C.c_double)), C.byref(et), C.byref(pop)))
         return w, e, et.value, pop.value
+
+    def set_sweep_index(self, index: int):
+        """The index of the next sweep in the random streams (resume after init_pos)."""
+        self._check(self.L.qmc_set_sweep_index(self.h, int(index)))
 
     def dmc_branching(self):
         """The last step's (weights before branching [W], energies [W], multiplicities [W],

@@ -461,3 +461,56 @@ def test_register_inverse_chain_matches_oracle(gpu, orc, monkeypatch, n_elec, gr
     n = _compare_mixed(gpu, orc, wl, 8, range(6), tie_guard=guard, require_fp32=True)
     if guard > 0:
         assert n > 50
+
+
+@pytest.mark.parametrize("case", ["fp64", "mixed_rebuild", "pbyp_drift", "ae_drift"])
+def test_resume_continues_the_same_streams(gpu, orc, case):
+    """A run saved after 5 sweeps (positions and the sweep index) and resumed in a new handle
+    (qmc_init_walkers with the positions, qmc_set_sweep_index) takes the uninterrupted run's
+    decisions in sweeps 6 to 10, reaches its positions (bit for bit where the proposals do not
+    depend on the inverses' rounding) and its energies, keeps the rebuild schedule, and takes
+    the oracle's decisions from the saved state."""
+    import dataclasses
+    base = qi.solid(32, 12, n_walkers=16, n_sweeps=1, seed=2)
+    if case == "mixed_rebuild":
+        wl = qi.solid(48, 16, n_walkers=16, n_sweeps=1, precision="mixed", table_dtype=np.float32, delay_rank=8,
+                      recompute_period=4, seed=2)
+    elif case == "pbyp_drift":
+        wl = dataclasses.replace(base, drift=True, sigma=0.3)
+    elif case == "ae_drift":
+        wl = dataclasses.replace(base, all_electron=True, drift=True, sigma=0.3 / np.sqrt(32))
+    else:
+        wl = base
+    print(f"[resume] {case}", flush=True)
+    s = gpu.System(wl)
+    bits, en = [], []
+    for _ in range(10):
+        s.sweep(1)
+        bits.append(s.accept_log())
+        en.append(s.measure())
+    pos_end = s.get_walkers()[0]
+    s.close()
+    s = gpu.System(wl)
+    s.sweep(5)
+    pos5 = s.get_walkers()[0]
+    _, idx = s.counters()
+    s.close()
+    assert idx == 5
+    r = gpu.System(wl, init_pos=pos5)
+    r.set_sweep_index(idx)
+    bits2, en2 = [], []
+    for _ in range(5):
+        r.sweep(1)
+        bits2.append(r.accept_log())
+        en2.append(r.measure())
+    _, idx2 = r.counters()
+    pos2 = r.get_walkers()[0]
+    r.close()
+    assert idx2 == 10
+    assert np.array_equal(np.stack(bits2), np.stack(bits[5:]))
+    dpos = np.abs(pos2 - pos_end).max()
+    assert dpos <= (1e-9 if case == "pbyp_drift" else 0.0), dpos
+    tol = {"fp64": 1e-10, "mixed_rebuild": 1e-5, "pbyp_drift": 1e-8, "ae_drift": 1e-10}[case]
+    assert _rel(np.stack(en2), np.stack(en[5:])).max() < tol
+    ref = orc.OracleSystem(wl).run(range(16), 5, sweep0=5, init_pos=pos5, measure_every=0)
+    assert np.array_equal(np.stack(bits2, 1), ref["accept"])
