@@ -173,8 +173,9 @@ typedef struct {
     const double* j3_gamma;
 } qmc_system_desc;
 
-/* Create a handle.  hip_stream: a hipStream_t (e.g. PyTorch's current
- * stream) or NULL.  Uses the device current at the call.  Errors: ARG for
+/* Create a handle (section "Code structure": a system description -- cell,
+ * particles, trial wavefunction, Hamiltonian, precision -- that every method
+ * works on).  hip_stream: a hipStream_t (e.g. PyTorch's current stream) or NULL.  Uses the device current at the call.  Errors: ARG for
  * invalid sizes or parameters, DEVICE, OOM. */
 qmc_status qmc_create_system(const qmc_system_desc* desc, void* hip_stream, qmc_system* out);
 
@@ -254,7 +255,9 @@ qmc_status qmc_run_steps(qmc_system s, int32_t n_steps, double* energies_dev);
  * E_T <- E - feedback ln(population / n_target).  Dead slots move too (their
  * results are never read), so a step runs entirely on the device. */
 
-/* Start a population: slots [0, n_target) alive with weight 1 at their current
+/* Start a population (section "Diffusion Monte Carlo": walkers of unit
+ * weight drawn from the trial wavefunction's distribution, E_T near the
+ * estimate): slots [0, n_target) alive with weight 1 at their current
  * configurations, local energies measured; E_T = e_trial, or (NaN) the mean
  * local energy of the alive slots; feedback >= 0 in hartree.  Synchronises.
  * The first call after qmc_init_walkers allocates the population buffers
@@ -262,13 +265,16 @@ qmc_status qmc_run_steps(qmc_system s, int32_t n_steps, double* energies_dev);
  * Errors: STATE (no walkers, or no drift moves), ARG, OOM, NUMERIC. */
 qmc_status qmc_dmc_init(qmc_system s, int32_t n_target, double e_trial, double feedback);
 
-/* n_steps DMC steps on the handle's stream, asynchronous.  stats_dev: device
+/* n_steps DMC steps on the handle's stream, asynchronous (section "Diffusion
+ * Monte Carlo"; one step as described above, eqs. pmc:g_growth,
+ * pmc:walker_weight, pmc:weighted_average).  stats_dev: device
  * buffer [n_steps][6] (caller-owned) receiving per step (E, sum of weights
  * before branching, population after branching, E_T used by the step, dropped
  * copies, moves rejected for crossing a node).  Errors: STATE, ARG, DEVICE. */
 qmc_status qmc_dmc_steps(qmc_system s, int32_t n_steps, double* stats_dev);
 
-/* Population state (host buffers, each nullable): weights[W] (0 = dead slot),
+/* Population state (section "Diffusion Monte Carlo", the walker weights of eq.
+ * pmc:walker_weight after branching), host buffers, each nullable: weights[W] (0 = dead slot),
  * energies[W] (local energy of each slot's configuration), the current E_T and
  * the population.  Synchronises.  Errors: STATE; NUMERIC if the population died
  * out (the state is still returned). */
@@ -290,10 +296,12 @@ qmc_status qmc_dmc_get_branching(qmc_system s, double* weights, double* energies
  * log|R| of the accepted moves since the last full inverse; sign[W][2]. */
 qmc_status qmc_get_walkers(qmc_system s, double* pos, double* logabs_det, int32_t* sign);
 
-/* Accept flags of the last sweep, host [W][N], 1 = accepted. */
+/* Accept flags of the last sweep (eq. accept_reject per move), host [W][N],
+ * 1 = accepted. */
 qmc_status qmc_get_accept_log(qmc_system s, uint8_t* bits);
 
-/* Counters (each nullable): redecided = moves since qmc_init_walkers whose
+/* Counters (each nullable; section "Code structure", precision as a parameter
+ * of the same algorithm): redecided = moves since qmc_init_walkers whose
  * acceptance fell inside the mixed-precision guard band and was decided again
  * from an FP64 ratio; sweeps = the index of the next sweep in the random
  * streams (the sweeps run since qmc_init_walkers, plus the index a resume set).
@@ -313,7 +321,8 @@ qmc_status qmc_get_counters(qmc_system s, uint64_t* redecided, uint64_t* sweeps)
  * 2^32 or more. */
 qmc_status qmc_set_sweep_index(qmc_system s, uint64_t sweep_index);
 
-/* Mixed precision, particle-by-particle moves: how the FP32 path keeps the FP64 decisions.
+/* Mixed precision, particle-by-particle moves (section "Code structure": single, double and
+ * mixed precision from one source): how the FP32 path keeps the FP64 decisions.
  * Every walker's inverse error ||I - A B||_F is measured after each full rebuild and by
  * the refinement before each measurement (A the FP64 Slater matrix); it widens that
  * walker's re-decision band (see tie_guard).  A walker whose measured error passes 2e-3 is
@@ -326,12 +335,15 @@ qmc_status qmc_set_sweep_index(qmc_system s, uint64_t sweep_index);
 qmc_status qmc_get_precision_stats(qmc_system s, uint64_t* early_rebuilds, uint64_t* fallback_sweeps,
                                    int32_t* fallback_now, int32_t* fallback_mask);
 
-/* Rebuild every inverse from scratch in FP64 and reset log|D|.  drift_out
- * (nullable, host [W][2]): accumulated log|D| minus the rebuilt one. */
+/* Rebuild every inverse from scratch in FP64 and reset log|D| (section
+ * "Multi-Determinant Slater-Jastrow Form": the updated inverse is periodically
+ * recomputed to bound the accumulated rounding).  drift_out (nullable, host
+ * [W][2]): accumulated log|D| minus the rebuilt one. */
 qmc_status qmc_recompute(qmc_system s, double* drift_out);
 
 /* Diagnostic: value, gradient (x, y, z) and Laplacian of every orbital at n
- * host positions pos[n][3], written to host out[n][5][n_orb] in FP64. */
+ * host positions pos[n][3] (section "B-spline basis sets": 64 coefficients per
+ * orbital and point), written to host out[n][5][n_orb] in FP64. */
 qmc_status qmc_eval_spo_vgl(qmc_system s, int32_t n, const double* pos, double* out);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture,
@@ -345,7 +357,8 @@ qmc_status qmc_eval_spo_vgl(qmc_system s, int32_t n, const double* pos, double* 
 #define QMC_NOALLOC_DOUBLES (1 << 19)
 qmc_status qmc_eval_spo_vgl_noalloc(qmc_system s, int32_t n, const double* pos, double* out);
 
-/* Kernel timing: when enabled, every launch of each kernel class is
+/* Kernel timing (section "Performance and Parallel Scaling": the time of each
+ * part of a step): when enabled, every launch of each kernel class is
  * bracketed by HIP events on the handle's stream.  Classes: 0 = orbital
  * gather (proposal + spline VGL), 1 = move chain (ratio, Jastrow, accept,
  * inverse update), 2 = measurement (kinetic + Ewald), 3 = inverse rebuild.
@@ -355,8 +368,9 @@ qmc_status qmc_set_timing(qmc_system s, int32_t enable);
 qmc_status qmc_kernel_timing(qmc_system s, int32_t kernel_class, double* total_ms, int64_t* launches,
                              int32_t reset);
 
-/* Change the delay rank between sweeps (1, or 4..64 a power of two).  Windows
- * never span sweeps, so any rank is valid at a sweep boundary. */
+/* Change the delay rank between sweeps (1, or 4..64 a power of two; section
+ * "Performance and Parallel Scaling", the delayed update).  Windows never span
+ * sweeps, so any rank is valid at a sweep boundary. */
 qmc_status qmc_set_delay_rank(qmc_system s, int32_t delay_rank);
 
 /* Gather autotuner: times the orbital gather (section "B-spline basis sets")
@@ -368,22 +382,27 @@ qmc_status qmc_set_delay_rank(qmc_system s, int32_t delay_rank);
  * milliseconds.  Errors: STATE before init_walkers or without a table. */
 qmc_status qmc_autotune_gather(qmc_system s, int32_t trial_sweeps, int32_t* best_lanes_log2, double* best_ms);
 
-/* Set the gather's lanes per proposal directly: lanes_log2 in 0..6, or -1 for
- * the default of the orbital count.  Errors: ARG outside that range. */
+/* Set the gather's lanes per proposal directly (section "B-spline basis sets":
+ * the orbital evaluation's work split): lanes_log2 in 0..6, or -1 for the
+ * default of the orbital count.  Errors: ARG outside that range. */
 qmc_status qmc_set_gather_lanes(qmc_system s, int32_t lanes_log2);
 
-/* Autotuner: runs trial_sweeps sweeps (>= 2; the first is not timed) with each
- * candidate delay rank, times the move-chain kernel with HIP events, keeps the
+/* Autotuner (section "Performance and Parallel Scaling": the delay rank is a
+ * tunable of the delayed update): runs trial_sweeps sweeps (>= 2; the first is
+ * not timed) with each candidate delay rank, times the move-chain kernel with HIP events, keeps the
  * fastest and writes it to best_rank (best_ms: its mean chain milliseconds per
  * sweep; both nullable).  The trial sweeps are ordinary sweeps of the chain. */
 qmc_status qmc_autotune_delay(qmc_system s, const int32_t* ranks, int32_t n_ranks, int32_t trial_sweeps,
                               int32_t* best_rank, double* best_ms);
 
-/* Local energies of the last measurement (qmc_measure_local_energy or a batch
- * sweep with measurement), host out[W][4].  Synchronises. */
+/* Local energies of the last measurement (section "Hamiltonian";
+ * qmc_measure_local_energy or a batch sweep with measurement), host out[W][4].
+ * Synchronises. */
 qmc_status qmc_get_last_energies(qmc_system s, double* out);
 
 /* ---- Batches: several systems advanced by fused launches -------------------
+ * (Section "Adapting to trends in High Performance Computing": enough
+ * independent work per launch to fill an accelerator.)
  * The walkers of all systems of a batch (any sizes, one precision, delay rank
  * >= 4, particle-by-particle moves, initialised) are advanced by one orbital-gather launch, one delayed-
  * chain launch per LDS class and one measurement launch per sweep.  Each
@@ -397,26 +416,30 @@ typedef struct qmc_batch_s* qmc_batch;
 
 qmc_status qmc_batch_create(const qmc_system* systems, int32_t n_systems, void* hip_stream, qmc_batch* out);
 
-/* n_sweeps sweeps of every member; measure != 0 also measures every member's
+/* n_sweeps sweeps (section "Trial Moves") of every member; measure != 0 also measures every member's
  * local energies after each sweep (read them with qmc_get_last_energies).
  * Member systems' periodic FP64 rebuilds run between sweeps as configured. */
 qmc_status qmc_batch_sweep(qmc_batch b, int32_t n_sweeps, int32_t measure);
 
 /* use_graph != 0: capture one sweep (all its launches) as a HIP graph on first
- * use and replay it for every later sweep. */
+ * use and replay it for every later sweep (section "Adapting to trends in High
+ * Performance Computing": launch overheads of small kernels). */
 qmc_status qmc_batch_set_graph(qmc_batch b, int32_t use_graph);
 
 /* Summed milliseconds and count of batch sweeps (HIP events around each
- * sweep, including its measurement) since the last reset; synchronises. */
+ * sweep, including its measurement; section "Performance and Parallel
+ * Scaling") since the last reset; synchronises. */
 qmc_status qmc_batch_timing(qmc_batch b, double* total_ms, int64_t* sweeps, int32_t reset);
 
+/* Free the batch (section "Code structure": the members stay the caller's). */
 qmc_status qmc_batch_destroy(qmc_batch b);
 
-/* Free every device buffer of the handle and the handle itself. */
+/* Free every device buffer of the handle and the handle itself (section "Code
+ * structure": the handle owns the walkers' device state). */
 qmc_status qmc_destroy_system(qmc_system s);
 
 /* Message of the last error of s (NULL: of the last failed call on this
- * thread).  Valid until the next call on the same handle/thread. */
+ * thread; section "Code structure", the library's error reporting).  Valid until the next call on the same handle/thread. */
 const char* qmc_last_error(qmc_system s);
 
 /* Largest delay rank (64, 32, 16, 8 or 4) whose delayed-update chain fits
@@ -428,7 +451,9 @@ const char* qmc_last_error(qmc_system s);
 int32_t qmc_max_delay_rank(const qmc_system_desc* desc);
 
 /* Device bytes a handle needs for desc, n_walkers walkers and a gx*gy*gz
- * table (n_orb = max(n_up, n_dn)), including alignment; 0 for invalid input. */
+ * table (n_orb = max(n_up, n_dn)), including alignment; 0 for invalid input
+ * (section "Adapting to trends in High Performance Computing": managing the
+ * accelerator's memory explicitly). */
 size_t qmc_estimate_device_bytes(const qmc_system_desc* desc, int32_t n_walkers, int32_t gx,
                                  int32_t gy, int32_t gz);
 
