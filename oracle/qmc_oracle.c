@@ -1150,9 +1150,10 @@ static void orc_walker_copy(const orc_system* s, orc_walker* dst, const orc_walk
  *   3. the mixed estimate E = sum w E_L / sum w over alive walkers (eq.
  *      pmc:weighted_average);
  *   4. branching: M = INT(w + xi) copies of every alive walker (xi from the BRANCH stream of
- *      (slot, k)); walkers with M = 0 die; a walker with M >= 1 keeps its slot and its
- *      M - 1 extra copies take the free slots (slots of dead walkers) in ascending order,
- *      the copies of lower slots first; copies beyond the free slots are dropped; every
+ *      (slot, k)), at most n_slots; walkers with M = 0 die; a walker with M >= 1 keeps its
+ *      slot and its M - 1 extra copies take the free slots (slots of dead walkers) in
+ *      ascending order, the copies of lower slots first; copies beyond the free slots, and
+ *      those a multiplicity above n_slots asked for, are dropped (and counted); every
  *      walker alive after branching has weight 1;
  *   5. E_T <- E - feedback ln(population / n_target).
  * Outputs (each nullable): stats[k] = (E, sum w, population after branching, E_T used in
@@ -1231,18 +1232,28 @@ int orc_dmc_run(const orc_system* s, int n_slots, int n_target, double e_trial, 
         const double emix = swe / sw;
         if (weights) for (int j = 0; j < n_slots; ++j) weights[(size_t)k * n_slots + j] = alive[j] ? w[j] : 0.0;
         if (energies) for (int j = 0; j < n_slots; ++j) energies[(size_t)k * n_slots + j] = alive[j] ? E[j] : NAN;
-        for (int j = 0; j < n_slots; ++j)
-            M[j] = alive[j] ? (int)floor(w[j] + orc_branch_uniform(s->seed, (uint32_t)j, (uint32_t)k)) : 0;
+        /* M = INT(w + xi), at most n_slots: a slot's copies beyond the capacity could never be
+         * placed; every copy that is not placed (over the capacity or over the free slots)
+         * counts as dropped */
+        double raw_extra = 0.0;
+        for (int j = 0; j < n_slots; ++j) {
+            M[j] = 0;
+            if (!alive[j]) continue;
+            const double mr = floor(w[j] + orc_branch_uniform(s->seed, (uint32_t)j, (uint32_t)k));
+            M[j] = mr < (double)n_slots ? (int)mr : n_slots;
+            if (mr >= 1.0) raw_extra += mr - 1.0;
+        }
         /* extra copies (source slot ascending) into free slots (ascending) */
         int src = 0, left = 0;   /* the source of the next extra copy and its copies still to place */
         while (src < n_slots && M[src] < 2) ++src;
         if (src < n_slots) left = M[src] - 1;
-        long dropped = 0;
+        long placed = 0;
         for (int f = 0; f < n_slots; ++f) {
             pl[f] = -1;
             if (M[f] != 0) continue;
             if (src < n_slots) {
                 pl[f] = src;
+                ++placed;
                 if (--left == 0) {
                     ++src;
                     while (src < n_slots && M[src] < 2) ++src;
@@ -1250,10 +1261,7 @@ int orc_dmc_run(const orc_system* s, int n_slots, int n_target, double e_trial, 
                 }
             }
         }
-        if (src < n_slots) {
-            dropped = left;
-            for (int j = src + 1; j < n_slots; ++j) if (M[j] >= 2) dropped += M[j] - 1;
-        }
+        const double dropped = raw_extra - (double)placed;
         for (int f = 0; f < n_slots; ++f)
             if (pl[f] >= 0) { orc_walker_copy(s, &W[f], &W[pl[f]]); E[f] = E[pl[f]]; }
         int pop = 0;

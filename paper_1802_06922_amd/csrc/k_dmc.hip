@@ -35,14 +35,16 @@ __device__ int block_exclusive_scan(int v, int* lds, int tid, int& excl) {
 // One workgroup.  Step k, tau = sigma^2:
 //   alive slots: w <- w exp(-tau (E + E_new - 2 E_T) / 2), E <- E_new (eqs. pmc:g_growth,
 //   pmc:walker_weight); E_mix = sum w E / sum w (eq. pmc:weighted_average);
-//   M = floor(w + xi), xi the BRANCH draw of (slot, k); dead slots M = 0;
+//   M = floor(w + xi) capped at W (copies beyond the capacity could never be placed), xi the
+//   BRANCH draw of (slot, k); dead slots M = 0;
 //   free slots (M = 0) in ascending order take the extra copies (M - 1 of every slot, lower
 //   slots first); a slot is alive afterwards with weight 1 if M >= 1 or it received a copy;
+//   every extra copy not placed (over the free slots or over the cap) counts as dropped;
 //   E_T <- E_mix - feedback ln(population / target).
 // Sums are taken per thread over a strided range, then in a fixed tree: bitwise repeatable.
 __global__ __launch_bounds__(kBranchBlock) void k_dmc_branch(SysParams P, DmcState D) {
   __shared__ int sscan[kBranchBlock];
-  __shared__ double sred[2][kBranchBlock / 64];
+  __shared__ double sred[3][kBranchBlock / 64];
   __shared__ int ired[2][kBranchBlock / 64];
   __shared__ int stot[2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -50,7 +52,7 @@ __global__ __launch_bounds__(kBranchBlock) void k_dmc_branch(SysParams P, DmcSta
   const double tau = P.sigma * P.sigma, et = D.ctl[0];
   const uint32_t step = (uint32_t)D.ictl[0];
   // (1) weights, energies, multiplicities, partial sums
-  double sw = 0.0, swe = 0.0;
+  double sw = 0.0, swe = 0.0, sx = 0.0;   // sx: the extra copies asked for, before the cap
   int ncr = 0;
   for (int j = tid; j < W; j += kBranchBlock) {
     int m = 0;
@@ -66,7 +68,9 @@ __global__ __launch_bounds__(kBranchBlock) void k_dmc_branch(SysParams P, DmcSta
       ncr += D.crossed[j];
       double xi, unused;
       uniform_pair(P, kBranch, 0, (uint32_t)j, step, 0u, xi, unused);
-      m = (int)floor(wj + xi);
+      const double mr = floor(wj + xi);
+      m = mr < (double)W ? (int)mr : W;
+      if (mr >= 1.0) sx += mr - 1.0;
       wbj = wj;
       ebj = en;
     }
@@ -76,11 +80,14 @@ __global__ __launch_bounds__(kBranchBlock) void k_dmc_branch(SysParams P, DmcSta
   }
   sw = wave_sum_dpp(sw);
   swe = wave_sum_dpp(swe);
+  sx = wave_sum_dpp(sx);
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) ncr += __shfl_xor(ncr, o, 64);
-  if (lane == 0) { sred[0][wave] = sw; sred[1][wave] = swe; ired[0][wave] = ncr; }
+  if (lane == 0) { sred[0][wave] = sw; sred[1][wave] = swe; sred[2][wave] = sx; ired[0][wave] = ncr; }
   __syncthreads();
-  // (2) exclusive scans of the extra copies and of the free slots, chunk by chunk
+  // (2) exclusive scans of the extra copies and of the free slots, chunk by chunk.  The copy
+  // sums saturate at W: no free-slot rank reaches W, so the placement is unchanged, and a
+  // chunk's sum (at most kBranchBlock (W - 1)) stays within an int.
   int carry_x = 0, carry_f = 0;
   for (int c0 = 0; c0 < W; c0 += kBranchBlock) {
     const int j = c0 + tid;
@@ -89,8 +96,8 @@ __global__ __launch_bounds__(kBranchBlock) void k_dmc_branch(SysParams P, DmcSta
     int ex, ef;
     const int tx = block_exclusive_scan(extra, sscan, tid, ex);
     const int tf = block_exclusive_scan(fr, sscan, tid, ef);
-    if (j < W) { D.xscan[j] = carry_x + ex; D.fscan[j] = carry_f + ef; }
-    carry_x += tx;
+    if (j < W) { D.xscan[j] = min(carry_x + ex, W); D.fscan[j] = carry_f + ef; }
+    carry_x = min(carry_x + tx, W);
     carry_f += tf;
   }
   if (tid == 0) { stot[0] = carry_x; stot[1] = carry_f; }
@@ -128,17 +135,17 @@ __global__ __launch_bounds__(kBranchBlock) void k_dmc_branch(SysParams P, DmcSta
   if (lane == 0) ired[1][wave] = pop;
   __syncthreads();
   if (tid == 0) {
-    double tw = 0.0, twe = 0.0;
+    double tw = 0.0, twe = 0.0, tx = 0.0;
     int tcr = 0, tpop = 0;
     for (int q = 0; q < kBranchBlock / 64; ++q) {
-      tw += sred[0][q]; twe += sred[1][q]; tcr += ired[0][q]; tpop += ired[1][q];
+      tw += sred[0][q]; twe += sred[1][q]; tx += sred[2][q]; tcr += ired[0][q]; tpop += ired[1][q];
     }
     const double emix = twe / tw;
     D.stats[0] = emix;
     D.stats[1] = tw;
     D.stats[2] = (double)tpop;
     D.stats[3] = et;
-    D.stats[4] = (double)(total_extra > total_free ? total_extra - total_free : 0);
+    D.stats[4] = tx - (double)(total_extra < total_free ? total_extra : total_free);
     D.stats[5] = (double)tcr;
     if (tpop == 0) D.ictl[1] = 1;   // extinct: E_T is kept
     else D.ctl[0] = emix - D.ctl[1] * log((double)tpop / (double)D.ictl[2]);

@@ -92,6 +92,7 @@ def _per_slot(gpu, orc, wl, n_slots, n_target, steps, feedback, rel=1e-10, e_tri
         assert np.all(was_alive[src[alive]])
         np.testing.assert_allclose(E[alive], re[src[alive]], rtol=rel, atol=rel)
         assert (np.abs(st[:2] - ref["stats"][k, :2]) / np.maximum(np.abs(ref["stats"][k, :2]), 1.0)).max() < rel
+        assert np.array_equal(st[[2, 4, 5]], ref["stats"][k, [2, 4, 5]])
         copies += int((pl >= 0).sum())
     print(f"[dmc-slots] {copies} copies over {steps} steps, final population {got[-1][-1]}", flush=True)
     return copies
@@ -100,6 +101,15 @@ def _per_slot(gpu, orc, wl, n_slots, n_target, steps, feedback, rel=1e-10, e_tri
 def test_dmc_per_slot_branching_heg14(gpu, orc):
     """Large steps and a high first E_T: copies, deaths, node crossings and dropped copies."""
     assert _per_slot(gpu, orc, _drift(qi.heg14(), 0.3), 32, 20, 16, 0.3, e_trial=5.0) > 0
+
+
+def test_dmc_multiplicities_capped_at_the_capacity(gpu, orc):
+    """A first E_T far above the local energies (weights about 1e12 after the first step):
+    multiplicities capped at the slot count, the copy plan, and the dropped copies counted
+    from the uncapped multiplicities, as the oracle has them."""
+    wl = _drift(qi.heg14(), 0.2)
+    e_mean = orc.OracleSystem(wl).dmc(16, 8, 1)["stats"][0, 3]
+    _per_slot(gpu, orc, wl, 16, 8, 3, 0.0, e_trial=e_mean + 28.0 / wl.sigma ** 2)
 
 
 def test_dmc_per_slot_branching_solid128(gpu, orc):

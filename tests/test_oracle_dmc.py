@@ -120,3 +120,27 @@ def test_fixed_node_keeps_the_sign_of_every_lineage(all_electron):
     assert len(alive) == r["stats"][-1, 2]
     for j in alive:
         assert _sign_psi(osys, wl, r["final_pos"][j]) == s0[ancestor[j]] == r["final_sign"][j]
+
+
+def test_multiplicities_are_capped_at_the_capacity():
+    """A first trial energy far above the local energies makes every weight huge (about 1e12
+    after one step): every multiplicity is capped at the number of slots, the free slots take
+    the copies of the lowest alive slots, and every extra copy asked for and not placed counts
+    as dropped, sum(INT(w + xi) - 1) - placed, computed here from the weights and draws."""
+    wl = _dmc_wl(0.2)
+    tau = wl.sigma ** 2
+    n_slots, n_target = 16, 8
+    osys = oracle.OracleSystem(wl)
+    e_mean = osys.dmc(n_slots, n_target, 1)["stats"][0, 3]   # the first E_T: the mean local energy
+    r = osys.dmc(n_slots, n_target, 1, e_trial=e_mean + 28.0 / tau, feedback=0.0)
+    w, m, pl, st = r["weights"][0], r["mult"][0], r["plan"][0], r["stats"][0]
+    alive = np.arange(n_slots) < n_target
+    xi = np.array([oracle.branch_uniform(wl.seed, j, 0) for j in range(n_slots)])
+    raw = np.where(alive, np.floor(w + xi), 0.0)
+    assert raw[alive].min() > 1e10
+    assert np.array_equal(m, np.where(alive, np.minimum(raw, n_slots), 0).astype(np.int64))
+    plan, _ = _plan(m)
+    assert np.array_equal(pl, plan)
+    assert np.array_equal(plan[n_target:], np.zeros(n_slots - n_target, dtype=np.int64))   # all from slot 0
+    assert st[4] == np.sum(raw[alive] - 1.0) - (plan >= 0).sum()
+    assert st[2] == n_slots
