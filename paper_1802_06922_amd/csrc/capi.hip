@@ -805,7 +805,10 @@ static hipError_t fallback_check(qmc_system s, hipStream_t st, bool after_rebuil
   if (!uses_fallback(s)) return hipSuccess;
   const Walkers<float> wk = walkers_of<float>(s);
   hipError_t e = launch_fb_mark(s->P.W, s->eta, s->fb, s->fbmark, after_rebuild ? 1 : 0, st);
-  if (e == hipSuccess && !after_rebuild) e = launch_rebuild<float>(s->P, wk, s->scratch, nullptr, st, s->fbmark, 1u);
+  // on the side stream of pipelined steps the check runs beside the next sweep's gather
+  const bool beside = s->side && st == s->side;
+  if (e == hipSuccess && !after_rebuild)
+    e = launch_rebuild<float>(s->P, wk, s->scratch, nullptr, st, s->fbmark, 1u, beside);
   if (e == hipSuccess) e = launch_fb_residual(s->P, wk, s->fbmark, st);
   if (e == hipSuccess) e = launch_fb_decide(s->P, wk, s->fbmark, after_rebuild ? 0 : 1, st);
   if (e == hipSuccess && !after_rebuild) e = launch_refine<float>(s->P, wk, s->scratch, st, s->fbmark, 3u);

@@ -183,6 +183,34 @@ __device__ __forceinline__ void gemm_window(const T* V, const T* B, int ldb, T* 
   }
 }
 
+// Z[r][c] = sum_l Cinv[r][l] (Y[q_l][c] - [c == p_l]) for r < mP, c < nz (rows from m and
+// columns from n zero) on the FP64 matrix cores; wave w takes the 16 x 16 tiles w, w + kWaves,
+// ...  Loads use clamped indices (always in bounds) and zero what lies outside.
+template <typename T>
+__device__ __forceinline__ void capacitance_z(const double* cinv, int K, const T* Y, int nP, const int* qlist,
+                                              const int* plist, int m, int mP, int n, int nz, T* Z, int lane,
+                                              int wave) {
+  typedef Mfma<double> M;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tr = (mP + 15) >> 4, tc = (nz + 15) >> 4;
+  for (int t = wave; t < tr * tc; t += kWaves) {
+    const int r0 = (t / tc) * 16, r = r0 + li, c = (t % tc) * 16 + li;
+    const int rc = r < m ? r : m - 1, cc = c < n ? c : n - 1;
+    typename M::v4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int l0 = 0; l0 < m; l0 += 4) {
+      const int l = l0 + lk, lc = l < m ? l : m - 1;
+      const double av = cinv[rc * K + lc];
+      const double yv = (double)Y[(size_t)qlist[lc] * nP + cc] - (cc == plist[lc] ? 1.0 : 0.0);
+      acc = M::mma((r < m && l < m) ? av : 0.0, (l < m && c < n) ? yv : 0.0, acc);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int rr = r0 + M::row(lane, q);
+      if (rr < mP && c < nz) Z[(size_t)rr * nP + c] = (T)acc[q];
+    }
+  }
+}
+
 // B[l][c] -= sum_r U[l][r] Z[r][c] for l, c < n, r < mP (U, Z zero-padded to mP).
 template <typename T, bool MF>
 __device__ __forceinline__ void gemm_flush(T* B, int ldb, const T* U, int ldu, const T* Z, int nP, int n,
@@ -957,15 +985,18 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
         // the elimination in one wave: its steps are ordered by wave-level LDS syncs, with no
         // workgroup barrier per pivot (the other waves wait once, below)
         if (wave == 0) {
+          // lane (j0, i0) = (lane % 16, lane / 16) takes the entries (i0 + 4 a, j0 + 16 b)
           double* a0 = ga;
           double* b1 = gb;
           for (int pv = 0; pv < m; ++pv) {
             const double inv = 1.0 / a0[pv * K + pv];
-            for (int idx = lane; idx < m * m; idx += 64) {
-              const int i = idx / m, j = idx - i * m;
-              const double aip = a0[i * K + pv], apj = a0[pv * K + j];
-              b1[i * K + j] = i == pv ? (j == pv ? inv : apj * inv)
-                                      : (j == pv ? -aip * inv : a0[i * K + j] - aip * apj * inv);
+            for (int j = lane & 15; j < m; j += 16) {
+              const double apj = a0[pv * K + j];
+              for (int i = lane >> 4; i < m; i += 4) {
+                const double aip = a0[i * K + pv];
+                b1[i * K + j] = i == pv ? (j == pv ? inv : apj * inv)
+                                        : (j == pv ? -aip * inv : a0[i * K + j] - aip * apj * inv);
+              }
             }
             wave_sync_lds();
             double* t = a0; a0 = b1; b1 = t;
@@ -975,13 +1006,17 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
         const double* cinv = (m & 1) ? gb : ga;   // after m steps, from one buffer into the other
         // register mode: Z is read up to the tiles' 16 nt columns, zero past n
         const int nz = RT > 0 ? 16 * nt : n;
-        for (int idx = tid; idx < mP * nz; idx += kBlock) {
-          const int r = idx / nz, c = idx - r * nz;
-          double acc = 0.0;
-          if (r < m && c < n)
-            for (int l = 0; l < m; ++l)
-              acc += cinv[r * K + l] * ((double)ywin[(size_t)qlist[l] * nP + c] - (c == plist[l] ? 1.0 : 0.0));
-          zwin[(size_t)r * nP + c] = (T)acc;
+        if constexpr (MF) {
+          capacitance_z<T>(cinv, K, ywin, nP, qlist, plist, m, mP, n, nz, zwin, lane, wave);
+        } else {
+          for (int idx = tid; idx < mP * nz; idx += kBlock) {
+            const int r = idx / nz, c = idx - r * nz;
+            double acc = 0.0;
+            if (r < m && c < n)
+              for (int l = 0; l < m; ++l)
+                acc += cinv[r * K + l] * ((double)ywin[(size_t)qlist[l] * nP + c] - (c == plist[l] ? 1.0 : 0.0));
+            zwin[(size_t)r * nP + c] = (T)acc;
+          }
         }
         __syncthreads();   // Y is dead from here: U takes its storage
         if constexpr (RT > 0) {

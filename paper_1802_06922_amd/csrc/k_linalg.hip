@@ -904,16 +904,18 @@ template hipError_t launch_refine_batched<float>(const SysDev<float>*, const int
 
 template <typename T>
 hipError_t launch_rebuild(const SysParams& P, const Walkers<T>& Wk, double* scratch, double* drift,
-                          hipStream_t st, const uint32_t* sel, uint32_t sel_value) {
+                          hipStream_t st, const uint32_t* sel, uint32_t sel_value, bool beside_other) {
   if (P.n_up > kMaxSpin || P.n_dn > kMaxSpin) return hipErrorInvalidValue;
   const int nmax = P.n_up > P.n_dn ? P.n_up : P.n_dn;
   // QMC_REBUILD_GLOBAL=1 takes the global-memory elimination for every size (lets the
   // tests compare the two kernels)
   const char* fg = getenv("QMC_REBUILD_GLOBAL");
-  // A selective rebuild (a few walkers, launched beside other kernels) of blocks beyond 64 takes
-  // the panel kernel when it fits: its 256-thread workgroups are placed beside the other
-  // kernels' workgroups, where a 1024-thread one waits for a whole compute unit to drain.
-  const bool beside = sel && nmax > 64;
+  // A selective rebuild (a few walkers) beside a kernel that fills the device takes the panel
+  // kernel for blocks beyond 64 when it fits: its 256-thread workgroups are placed beside the
+  // other kernel's workgroups, where a 1024-thread one waits for a whole compute unit to drain
+  // (measured at 384 electrons: 2.0 against 3.5 ms per launch beside the gather; alone the
+  // register elimination of one walker takes 0.4 ms and the panel one 2.6 ms).
+  const bool beside = beside_other && sel && nmax > 64;
   if (!(fg && fg[0] == '1') && nmax <= kRegRebuildMax &&
       !(beside && panel_layout(nmax, 16).total <= (size_t)lds_budget_rebuild())) {
     const dim3 grid(2 * P.W);
@@ -947,9 +949,9 @@ hipError_t launch_rebuild(const SysParams& P, const Walkers<T>& Wk, double* scra
 }
 
 template hipError_t launch_rebuild<double>(const SysParams&, const Walkers<double>&, double*, double*,
-                                           hipStream_t, const uint32_t*, uint32_t);
+                                           hipStream_t, const uint32_t*, uint32_t, bool);
 template hipError_t launch_rebuild<float>(const SysParams&, const Walkers<float>&, double*, double*,
-                                          hipStream_t, const uint32_t*, uint32_t);
+                                          hipStream_t, const uint32_t*, uint32_t, bool);
 
 hipError_t linalg_lds_limits() {
   const void* ks[] = {reinterpret_cast<const void*>(&k_rebuild_panel<double, 16>),

@@ -131,17 +131,28 @@ __device__ void det_terms_fp64(const SysParams& P, const T* __restrict__ table, 
   axis_weights(y, P.L, P.gy, ay);
   axis_weights(z, P.L, P.gz, az);
   gx = gy = gz = l2 = 0.0;
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b)
+  // the weights picked by selects, not by indexing (an indexed private array lives in scratch)
+  auto pick = [](const auto (&v)[4], int q) { return q == 0 ? v[0] : (q == 1 ? v[1] : (q == 2 ? v[2] : v[3])); };
+#pragma unroll 1
+  for (int a = 0; a < 4; ++a) {
+    const int ia = pick(ax.idx, a);
+    const double wa = pick(ax.w, a), da = pick(ax.dw, a), d2a = pick(ax.d2w, a);
+#pragma unroll 1
+    for (int b = 0; b < 4; ++b) {
+      const int ib = pick(ay.idx, b);
+      const double wb = pick(ay.w, b), db = pick(ay.dw, b), d2b = pick(ay.d2w, b);
+#pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const T* cf = table + (((size_t)ax.idx[a] * P.gy + ay.idx[b]) * P.gz + az.idx[c]) * P.S;
+        const T* cf = table + (((size_t)ia * P.gy + ib) * P.gz + az.idx[c]) * P.S;
         double d = 0.0;
         for (int l = 0; l < n; ++l) d += bcol[(size_t)l * n] * (double)cf[l];
-        gx += ax.dw[a] * ay.w[b] * az.w[c] * d;
-        gy += ax.w[a] * ay.dw[b] * az.w[c] * d;
-        gz += ax.w[a] * ay.w[b] * az.dw[c] * d;
-        l2 += (ax.d2w[a] * ay.w[b] * az.w[c] + ax.w[a] * ay.d2w[b] * az.w[c] + ax.w[a] * ay.w[b] * az.d2w[c]) * d;
+        gx += da * wb * az.w[c] * d;
+        gy += wa * db * az.w[c] * d;
+        gz += wa * wb * az.dw[c] * d;
+        l2 += (d2a * wb * az.w[c] + wa * d2b * az.w[c] + wa * wb * az.d2w[c]) * d;
       }
+    }
+  }
 }
 
 template <typename T>

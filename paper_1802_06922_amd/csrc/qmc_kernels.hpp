@@ -127,10 +127,14 @@ hipError_t launch_fb_decide(const SysParams& P, const Walkers<float>& Wk, uint32
 // (Gauss-Jordan with partial pivoting); scratch: W * bstride doubles.
 // drift (nullable): receives log|D|_old - log|D|_new per [W][2].
 // sel (nullable): only walkers w with sel[w] == sel_value are processed, the others keep
-// their results.  Mixed precision: the FP64 inverse goes to binv64 as well.
+// their results.  beside: the launch runs beside another kernel that fills the device (a
+// selective rebuild then takes the 256-thread panel elimination, which is placed beside the
+// other kernel's workgroups; alone, the register elimination is faster).  Mixed precision:
+// the FP64 inverse goes to binv64 as well.
 template <typename T>
 hipError_t launch_rebuild(const SysParams& P, const Walkers<T>& Wk, double* scratch, double* drift,
-                          hipStream_t st, const uint32_t* sel = nullptr, uint32_t sel_value = 0);
+                          hipStream_t st, const uint32_t* sel = nullptr, uint32_t sel_value = 0,
+                          bool beside = false);
 
 // Mixed precision: Wk.xinv = B + B (I - A B) with the FP64 Slater matrix A (from val64) and
 // FP64 products, the inverse the measurement reads; eta = ||I - A B||_F and ||X||_F per spin;
