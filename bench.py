@@ -139,9 +139,10 @@ def main(argv=None) -> int:
     ap.add_argument("--no-compare", action="store_true",
                     help="mixed384: skip the FP64 runs of the same system beside the mixed one")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--moves", default="pbyp", choices=["pbyp", "all", "drift"],
-                    help="single: particle-by-particle sweeps (default), or one all-electron move per "
-                         "walker per step, plain or drift-diffusion")
+    ap.add_argument("--moves", default="pbyp", choices=["pbyp", "all", "drift", "pdrift"],
+                    help="single: particle-by-particle sweeps (default), one all-electron move per "
+                         "walker per step (plain or drift-diffusion), or particle-by-particle "
+                         "drift-diffusion sweeps (pdrift; FP64, the table's values stored in FP64)")
     ap.add_argument("--j3", type=float, default=None,
                     help="single: add a three-body e-e-I Jastrow term of this coefficient scale "
                          "(orders 2 and 2, cutoff L/2) to the workload")
@@ -186,6 +187,16 @@ def main(argv=None) -> int:
         wl = dataclasses.replace(wl, all_electron=True, drift=args.moves == "drift",
                                  sigma=args.ae_sigma or wl.sigma / math.sqrt(wl.n_elec))
         args.no_compare = True
+    pdrift = args.moves == "pdrift"
+    if pdrift:
+        import dataclasses
+
+        import numpy as np
+        wl = dataclasses.replace(wl, drift=True, precision="fp64", coefs=np.asarray(wl.coefs, dtype=np.float64),
+                                 delay_rank=1, recompute_period=0, name=wl.name.replace("_mixed", "") + "_pdrift")
+        args.no_compare = True
+        args.delay = 1
+        args.gather_lanes = -1
     r = run_single(wl, args.steps, args.warmup, args.delay, args.gather_lanes, serial=args.serial)
     if r["delay_rank"] is not None:
         wl.delay_rank = r["delay_rank"]
@@ -193,7 +204,7 @@ def main(argv=None) -> int:
     kt = r["kt"]
     b = wl.coefs.dtype.itemsize
     bytes_per_move = 64 * wl.n_orb * b
-    g_ms, g_n = kt["gather"]
+    g_ms, g_n = kt["chain"] if pdrift else kt["gather"]   # drift sweeps read the table inside the chain
     avg_gather_s = g_ms / max(g_n, 1) / 1e3
     achieved = bytes_per_move * W * N / avg_gather_s / 1e9
     line = {
@@ -215,12 +226,15 @@ def main(argv=None) -> int:
                    "step": (f"1 all-electron {'drift-diffusion ' if wl.drift else ''}move per walker "
                             "(N electrons proposed at once, FP64 determinants at R') + local energy")
                            if ae else
-                           "1 sweep (N moves per walker) + local energy",
+                           ("1 drift-diffusion sweep (N moves per walker, each row evaluated in the chain) "
+                            "+ local energy" if pdrift else "1 sweep (N moves per walker) + local energy"),
                    "steps_run": "sweep and measurement calls in turn" if args.serial else
                    "pipelined (a step's measurement beside the next step's proposals)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(wl),
-                     "kernel": "k_gather (proposal + tricubic B-spline VGL of every orbital)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None if pdrift else measured_traffic(wl),
+                     "kernel": ("k_chain_drift (the whole sweep: the table reads of every move's row "
+                                "happen inside the chain, which is latency-bound)") if pdrift else
+                     "k_gather (proposal + tricubic B-spline VGL of every orbital)",
                      "bytes_per_launch": bytes_per_move * W * N,
                      "avg_launch_ms": avg_gather_s * 1e3,
                      "launches": "alone (--serial)" if args.serial else
@@ -232,7 +246,7 @@ def main(argv=None) -> int:
         "sweep_only_moves_per_s": r["sweep_only_moves_per_s"],
         "mean_local_energy": r["mean_local_energy"],
     }
-    if not ae:
+    if not ae and not pdrift:
         line["roofline_chain"] = chain_roofline(wl, r)
     headline = args.workload == "mixed384" and wl.precision == "mixed" and not ae and args.j3 is None
     if headline and not args.no_compare:
