@@ -40,7 +40,7 @@ __global__ __launch_bounds__(kBlock) void k_ae_jastrow(SysParams P, const double
   __shared__ double red[kWaves];
   const int parts = gridDim.x / P.W;
   const int w = blockIdx.x / parts, p = blockIdx.x - w * parts;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_of(tid);
   const int N = P.N;
   for (int q = tid; q < (int)(sizeof(Jastrow) / sizeof(double)); q += kBlock)
     reinterpret_cast<double*>(&sj)[q] = reinterpret_cast<const double*>(&P.jas)[q];
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_ae_velocity(SysParams P, Walkers<T> 
   __shared__ double red[kWaves];
   const int parts = gridDim.x / P.W;
   const int w = blockIdx.x / parts, p = blockIdx.x - w * parts;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_of(tid);
   const int s = tid & 3, i = p * kVelE + (tid >> 2);
   const int N = P.N;
   const bool valid = i < N;

@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(SysParams P, Walkers<T> Wk, in
   constexpr int C = 16 / VPT;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ Jastrow sj;
-  const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = wave_of(tid);
   if (chain_skips(Wk, w)) return;
   const int N = P.N, nmax = P.n_up > P.n_dn ? P.n_up : P.n_dn;
   const ChainLayout lay = chain_layout(N, nmax, P.n_ions, ldl, sizeof(T), BLDS, C);

@@ -132,7 +132,7 @@ __device__ __forceinline__ void gemm_window(const T* V, const T* B, int ldb, T* 
   if (MF) {
     typedef Mfma<T> M;
     constexpr int kGroup = Group<T>::n;
-    const int lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int lane = tid & 63, wave = wave_of(tid), li = lane & 15, lk = lane >> 4;
     const int tq = (Kw + 15) >> 4, tc = (n + 15) >> 4, nt = tq * tc;
     // wave w takes tiles w, w + kWaves, ... in groups of kGroup
     for (int g0 = wave; g0 < nt; g0 += kWaves * kGroup) {
@@ -218,7 +218,7 @@ __device__ __forceinline__ void gemm_flush(T* B, int ldb, const T* U, int ldu, c
   if (MF) {
     typedef Mfma<T> M;
     constexpr int kGroup = Group<T>::n;
-    const int lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int lane = tid & 63, wave = wave_of(tid), li = lane & 15, lk = lane >> 4;
     const int tt = (n + 15) >> 4, nt = tt * tt;
     for (int g0 = wave; g0 < nt; g0 += kWaves * kGroup) {
       // the old values of the group's tiles are loaded first; they arrive while the products run
@@ -338,6 +338,14 @@ template <> struct RegTiles<0> { static constexpr int CT = 0; };
 __device__ __forceinline__ int pinned(int x) {
   asm volatile("" : "+v"(x));
   return x;
+}
+
+// This lane's index, computed afresh at each call: an address derived from it is then formed
+// where it is used instead of being kept live (and spilled) across the sweep.
+__device__ __forceinline__ int lane_now() {
+  int l;
+  asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+  return l;
 }
 
 // HBM <-> tiles through an LDS slab of 16 rows (stage: 16 n floats): the 16 rows of a row tile
@@ -595,7 +603,7 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
   __shared__ Jastrow sj;
   __shared__ int sm_m, sm_stop;
   __shared__ double sm_dj;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_of(tid);
   if (chain_skips(Wk, w)) return;
   const int N = P.N, nmax = P.n_up > P.n_dn ? P.n_up : P.n_dn, nP = round16(nmax);
   const DLayout lay = dlayout(N, nmax, P.n_ions, ldl, sizeof(T), BLDS, K, RT > 0);
@@ -908,9 +916,10 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
           if (u < p32) {
             const double Tacc = sizeof(T) == 4 ? readlane_d(Tq, q) : 0.0;
             if (lane > q && lane < Kw) {
-              const double f = yk[lane * ldy + q] / R;
+              double* ykl = yk + lane_now() * ldy;   // this lane's row
+              const double f = ykl[q] / R;
               if (sizeof(T) == 4) {
-                Eq += fabs(f * yk[q * ldy + lane]);
+                Eq += fabs(f * yk[q * ldy + lane_now()]);
                 Tq += fabs(f) * Tacc;   // row q's new v^T B is its old one minus f times move q's
               }
               // eight columns at a time: all loads before the stores, so they overlap.  The
@@ -922,11 +931,11 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                   pv[e] = yk[q * ldy + j0 + e];
-                  rv[e] = yk[lane * ldy + j0 + e];
+                  rv[e] = ykl[j0 + e];
                 }
 #pragma unroll
                 for (int e = 0; e < 8; ++e)
-                  if (j0 + e < Kw) yk[lane * ldy + j0 + e] = rv[e] - f * pv[e];
+                  if (j0 + e < Kw) ykl[j0 + e] = rv[e] - f * pv[e];
               }
               Fq += gq;
               exq = ex_acc;

@@ -47,7 +47,7 @@ __global__ __launch_bounds__(kBranchBlock) void k_dmc_branch(SysParams P, DmcSta
   __shared__ double sred[3][kBranchBlock / 64];
   __shared__ int ired[2][kBranchBlock / 64];
   __shared__ int stot[2];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_of(tid);
   const int W = P.W;
   const double tau = P.sigma * P.sigma, et = D.ctl[0];
   const uint32_t step = (uint32_t)D.ictl[0];
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void k_dmc_copy(SysParams P, Walkers<T> Wk,
   for (int q = tid; q < 3 * N; q += kBlock) Wk.pos[f0 * 3 + q] = Wk.pos[s0 * 3 + q];
   // rows: one wave per electron, 16-byte vectors (a row of 5 S values and an FP64 value row
   // are multiples of 16 bytes: S is padded to 16 bytes and the buffers are 256-byte aligned)
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = wave_of(tid);
   const int rv = kComp * P.S * (int)sizeof(T) / 16, r64 = P.S * 8 / 16;
   for (int i = wave; i < N; i += kWaves) {
     const size_t b = Wk.cur[s0 + i];

@@ -24,7 +24,7 @@ __global__ __launch_bounds__(kBlock) void k_rebuild(SysParams P, Walkers<T> Wk, 
   __shared__ double rv[kWaves];
   __shared__ int ri[kWaves];
   const int w = blockIdx.x >> 1, sp = blockIdx.x & 1, tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = wave_of(tid);
   const int n = sp ? P.n_dn : P.n_up, off = sp ? P.n_up : 0;
   const int N = P.N;
   if (sel && sel[w] != sel_value) return;
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(G * G) void k_rebuild_reg(SysParams P, Walkers<T> W
   __shared__ double sbest[2];
   __shared__ double samax[G * G / 64];
   const int w = blockIdx.x >> 1, sp = blockIdx.x & 1, tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = wave_of(tid);
   const int r0 = tid & (G - 1), c0 = tid / G;
   const int n = sp ? P.n_dn : P.n_up, off = sp ? P.n_up : 0;
   const int N = P.N;
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(kBlock) void k_rebuild_panel(SysParams P, Walkers<T
   __shared__ double rv[kWaves];
   __shared__ int ri[kWaves];
   const int w = blockIdx.x >> 1, sp = blockIdx.x & 1, tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = wave_of(tid);
   const int n = sp ? P.n_dn : P.n_up, off = sp ? P.n_up : 0;
   const int N = P.N;
   if (sel && sel[w] != sel_value) return;
@@ -602,7 +602,7 @@ constexpr int kPerThread = kTile * kChunk / kBlock;   // panel entries each thre
 template <typename V, typename LF, typename RF, typename EF>
 __device__ __forceinline__ void gemm_tiles(int n, LF Lf, RF Rf, EF epi, V* sL, V* sR) {
   typedef Mfma<V> M;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_of(tid);
   const int li = lane & 15, lk = lane >> 4;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int nt = (n + kTile - 1) / kTile;

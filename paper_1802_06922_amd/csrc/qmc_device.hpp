@@ -14,6 +14,11 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kComp = 5;              // value, d/dx, d/dy, d/dz, Laplacian
 constexpr double kPi = 3.14159265358979323846;
 
+// The wave index of thread tid (64 lanes per wave).  Read from the first lane it is a scalar
+// the compiler knows to be the same over the wave: branches on it stay scalar and values set
+// under them live in scalar registers, which leaves vector registers to the arrays.
+__device__ __forceinline__ int wave_of(int tid) { return __builtin_amdgcn_readfirstlane(tid >> 6); }
+
 // Radial function of a Jastrow term (section "Jastrow factors").
 struct Radial {
   int kind;          // QMC_J_NONE / PADE / BSPLINE

@@ -20,7 +20,7 @@ template <typename T>
 __device__ __forceinline__ double refined_ratio(const SysParams& P, const Walkers<T>& Wk, const T* Bm, int ldb, int n,
                                 size_t item0, const uint8_t* scur, const double* v64, int k, double* sx,
                                 double* sr, double* red, int tid) {
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = wave_of(tid);
   for (int l = tid; l < n; l += kBlock) sx[l] = (double)Bm[(size_t)l * ldb + k];
   __syncthreads();
   // Each wave takes four rows at a time, its lanes striding along the rows (coalesced reads of
