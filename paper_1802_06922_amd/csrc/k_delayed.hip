@@ -884,12 +884,18 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
         double exq = lane < Kw ? jexp(2.0 * Fq) : 0.0;
         double racc = 1.0;      // lane q: R of move q once accepted
         uint64_t amask = 0;     // accepted moves of the window
+        uint64_t dmask = 0;     // decided moves of the window (accepted or rejected)
+        // guard band terms that do not change over the window (mixed precision)
+        const double uf = 5.9604644775390625e-08;   // 2^-24
+        const double band0 = sizeof(T) == 4 ? P.tie_guard + 4.0 * uf : P.tie_guard;
+        const double nuf2 = 2.0 * (n + 1) * uf;
         wave_sync_lds();
         int m = 0;
         for (int q = 0; q < Kw; ++q) {
-          const int kq = k0 + q, iq = off + kq;
           const double R = yk[q * ldy + q];
-          const double dJ = readlane_d(Fq, q);
+          // one reciprocal serves the guard band and the elimination below; it is formed
+          // while the lane reads complete
+          const double invR = 1.0 / R;
           const double u = readlane_d(uq, q);
           const double ex = readlane_d(exq, q);
           // later lanes: their exponential should move q be accepted, formed ahead of the
@@ -902,14 +908,13 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
           // n + 1 unit roundoffs (the length-n product and the cast of B0) of the magnitude of
           // the terms that formed R, sum_l |v_l B0[l][k]| plus the eliminated window terms --
           // ratios that cancel heavily are re-decided in FP64
-          double band = P.tie_guard;
-          if (sizeof(T) == 4) {
-            const double uf = 5.9604644775390625e-08;   // 2^-24
-            const double err = (n + 1) * uf * (readlane_d(Sq, q) + readlane_d(Eq, q));
-            band += (2.0 * err + readlane_d(ecq, q) * readlane_d(Tq, q)) / fabs(R) + 4.0 * uf;
-          }
+          double band = band0;
+          if (sizeof(T) == 4)
+            band += (nuf2 * (readlane_d(Sq, q) + readlane_d(Eq, q)) + readlane_d(ecq, q) * readlane_d(Tq, q)) *
+                    fabs(invR);
           if (sizeof(T) == 4 && fabs(u - p32) <= band * p32) {
             // near tie in FP32: end the window here; the move is re-decided in FP64 below
+            const double dJ = readlane_d(Fq, q);
             if (lane == 0) { sm_stop = q; sm_dj = dJ; }
             break;
           }
@@ -917,7 +922,7 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
             const double Tacc = sizeof(T) == 4 ? readlane_d(Tq, q) : 0.0;
             if (lane > q && lane < Kw) {
               double* ykl = yk + lane_now() * ldy;   // this lane's row
-              const double f = ykl[q] / R;
+              const double f = ykl[q] * invR;
               if (sizeof(T) == 4) {
                 Eq += fabs(f * yk[q * ldy + lane_now()]);
                 Tq += fabs(f) * Tacc;   // row q's new v^T B is its old one minus f times move q's
@@ -940,24 +945,32 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
               Fq += gq;
               exq = ex_acc;
             }
-            if (lane == 0) {
-              plist[m] = kq;
-              qlist[m] = q;
-              spos[3 * iq] = sprop[4 * kq];
-              spos[3 * iq + 1] = sprop[4 * kq + 1];
-              spos[3 * iq + 2] = sprop[4 * kq + 2];
-              scur[kq] = (uint8_t)(1 - scur[kq]);
-              sacc[kq] = 1;
-            }
             ++m;
             ++nacc;
             racc = lane == q ? R : racc;
             amask |= 1ull << q;
             if (R < 0.0) sgn = -sgn;
-          } else if (lane == 0) {
+          }
+          dmask |= 1ull << q;
+          wave_sync_lds();
+        }
+        if ((dmask >> lane) & 1ull) {
+          // the decided moves' bookkeeping, lane q for move q, once the window's decisions are
+          // made: accepted moves take their place in the flush lists (in move order) and the
+          // electron its new position
+          const int kq = k0 + lane, iq = off + kq;
+          if ((amask >> lane) & 1ull) {
+            const int slot = __popcll(amask & ((1ull << lane) - 1ull));
+            plist[slot] = kq;
+            qlist[slot] = lane;
+            spos[3 * iq] = sprop[4 * kq];
+            spos[3 * iq + 1] = sprop[4 * kq + 1];
+            spos[3 * iq + 2] = sprop[4 * kq + 2];
+            scur[kq] = (uint8_t)(1 - scur[kq]);
+            sacc[kq] = 1;
+          } else {
             sacc[kq] = 0;
           }
-          wave_sync_lds();
         }
         {
           // log|R| of the accepted moves: all lanes at once, added in move order
