@@ -121,6 +121,9 @@ struct qmc_system_s {
   uint32_t* pstat = nullptr;
   uint32_t* fbmark = nullptr;
   int gather_lanes_log2 = -1;   // lanes per proposal in the gather (log2); -1 = default
+  // the sweep's proposals evaluated in table order (null: in (walker, electron) order)
+  GatherOrder gorder{};
+  bool gather_ordered = false;
   uint32_t* nguard = nullptr;
   uint32_t* sweep_ctr = nullptr;
   // all-electron moves: the state at the proposed configurations (null for particle-by-particle)
@@ -386,6 +389,8 @@ void free_walkers(qmc_system s) {
   s->mem.release_to(s->mark_table);
   s->has_walkers = false;
   s->pos = s->prop = nullptr;
+  s->gorder = GatherOrder{};
+  s->gather_ordered = false;
   s->vgl = s->binv = nullptr;
   s->cur = s->acc = nullptr;
   s->logdet = s->scratch = s->drift = s->energy = nullptr;
@@ -412,9 +417,10 @@ void free_walkers(qmc_system s) {
 struct WalkerSizes {
   size_t pos, prop, vgl, cur, binv, logdet, sign, acc, nacc, status, scratch, drift, energy, val64, nguard, sweep,
       xinv, binv64, fb, eta, ecol, eta_age, pstat, fbmark, ae_binv, ae_logdet, ae_dj, ae_sign, ae_status, ae_vel, ae_logT,
-      grad64, ae_binv64, dmc;
+      grad64, ae_binv64, dmc, gitem, gbucket;
   size_t total() const {
-    return align_up(pos) + align_up(prop) + align_up(vgl) + align_up(cur) + align_up(binv) +
+    return 2 * align_up(gitem) + 2 * align_up(gbucket) +
+           align_up(pos) + align_up(prop) + align_up(vgl) + align_up(cur) + align_up(binv) +
            align_up(logdet) + align_up(sign) + align_up(acc) + align_up(nacc) + align_up(status) +
            align_up(scratch) + align_up(drift) + align_up(energy) + align_up(val64) + align_up(nguard) +
            align_up(sweep) + align_up(xinv) +
@@ -435,6 +441,10 @@ WalkerSizes walker_sizes(int n_up, int n_dn, int precision, int W, int n_orb, in
   WalkerSizes z;
   z.pos = W * N * 3 * sizeof(double);
   z.prop = W * N * 4 * sizeof(double);
+  // the gather's table order (every move kind whose proposals a gather evaluates)
+  const bool gathers = move_kind != QMC_MOVE_PBYP_DRIFT && W * N < ((size_t)1 << 31);
+  z.gitem = gathers ? W * N * sizeof(int) : 0;
+  z.gbucket = gathers ? kGatherBuckets * sizeof(int) : 0;
   z.vgl = 2 * W * N * kComp * S * ts;
   z.cur = W * N;
   z.binv = W * bs * ts;
@@ -862,6 +872,16 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
     s->xinv = s->mem.alloc(z.xinv);
   }
   if (z.binv64) s->binv64 = static_cast<double*>(s->mem.alloc(z.binv64));
+  if (z.gitem) {
+    s->gorder.key = static_cast<int*>(s->mem.alloc(z.gitem));
+    s->gorder.order = static_cast<int*>(s->mem.alloc(z.gitem));
+    s->gorder.hist = static_cast<int*>(s->mem.alloc(z.gbucket));
+    s->gorder.offs = static_cast<int*>(s->mem.alloc(z.gbucket));
+    const int g[3] = {s->P.gx, s->P.gy, s->P.gz};
+    for (int a = 0; a < 3; ++a) s->gorder.tile[a] = (g[a] + 15) / 16;   // at most 16 tiles per axis
+    const char* e = getenv("QMC_GATHER_ORDER");
+    s->gather_ordered = !(e && e[0] == '0');
+  }
   if (z.grad64) {
     s->grad64 = static_cast<double*>(s->mem.alloc(z.grad64));
     s->ae_binv64 = static_cast<double*>(s->mem.alloc(z.ae_binv64));
@@ -889,6 +909,7 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
     s->ae_status = static_cast<int*>(s->mem.alloc(z.ae_status));
   }
   if (!s->pos || !s->prop || !s->vgl || !s->cur || !s->binv || !s->logdet || !s->sign || !s->acc ||
+      (z.gitem && (!s->gorder.key || !s->gorder.order || !s->gorder.hist || !s->gorder.offs)) ||
       !s->nacc || !s->status || !s->scratch || !s->drift || !s->energy || !s->nguard || !s->sweep_ctr ||
       (s->d.precision == QMC_MIXED && (!s->val64 || !s->xinv)) ||
       (z.binv64 && !s->binv64) || (z.grad64 && (!s->grad64 || !s->ae_binv64)) ||
@@ -916,6 +937,7 @@ qmc_status qmc_init_walkers(qmc_system s, int32_t n_walkers, const double* pos) 
   HIP_TRY(s, hipMemsetAsync(s->acc, 0, z.acc, s->stream));
   HIP_TRY(s, hipMemsetAsync(s->logdet, 0, z.logdet, s->stream));
   HIP_TRY(s, hipMemsetAsync(s->status, 0, z.status, s->stream));
+  if (z.gbucket) HIP_TRY(s, hipMemsetAsync(s->gorder.hist, 0, z.gbucket, s->stream));
   if (z.fb) {
     HIP_TRY(s, hipMemsetAsync(s->fb, 0, z.fb, s->stream));
     HIP_TRY(s, hipMemsetAsync(s->pstat, 0, z.pstat, s->stream));
@@ -960,10 +982,11 @@ qmc_status sweep_gather(qmc_system s, hipStream_t st) {
     if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "drift velocity launch: %s", hipGetErrorString(e));
     s->vcur_valid = true;
   }
+  const GatherOrder* go = s->gather_ordered ? &s->gorder : nullptr;
   if (s->d.precision == QMC_MIXED)
-    e = timed(s, 0, [&] { return launch_gather<float>(s->P, walkers_of<float>(s), static_cast<const float*>(s->d_table), 0, st, s->gather_lanes_log2); }, st);
+    e = timed(s, 0, [&] { return launch_gather<float>(s->P, walkers_of<float>(s), static_cast<const float*>(s->d_table), 0, st, s->gather_lanes_log2, nullptr, 0, go); }, st);
   else
-    e = timed(s, 0, [&] { return launch_gather<double>(s->P, walkers_of<double>(s), static_cast<const double*>(s->d_table), 0, st, s->gather_lanes_log2); }, st);
+    e = timed(s, 0, [&] { return launch_gather<double>(s->P, walkers_of<double>(s), static_cast<const double*>(s->d_table), 0, st, s->gather_lanes_log2, nullptr, 0, go); }, st);
   if (e != hipSuccess) return fail(s, QMC_ERR_DEVICE, "sweep launch: %s", hipGetErrorString(e));
   return QMC_OK;
 }

@@ -162,7 +162,10 @@ __device__ __forceinline__ void uniform_pair(const SysParams& P, uint32_t purpos
   u1 = (double)(x1 >> 11) * 0x1.0p-53;
 }
 
+// wrap_cell and axis_weights round every product and sum on its own (no fused multiply-adds):
+// the kernels that inline them then agree bitwise whatever the surrounding code.
 __device__ __forceinline__ double wrap_cell(double x, double L) {
+#pragma clang fp contract(off)
   double y = x - L * floor(x / L);
   return (y >= L) ? 0.0 : y;
 }
@@ -180,6 +183,7 @@ struct Axis {
 };
 
 __device__ __forceinline__ void axis_weights(double x, double L, int G, Axis& a) {
+#pragma clang fp contract(off)
   const double h = (double)G / L;
   const double t = wrap_cell(x, L) * h;
   const double fl = floor(t);

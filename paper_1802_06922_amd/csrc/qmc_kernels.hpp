@@ -53,15 +53,29 @@ struct SysDev {
   double* scratch;   // [W][bstride] FP64 scratch (rebuild, refinement)
 };
 
+// A sweep's proposals in table order (the buffers of one system): the bucket of each item, the
+// items sorted by bucket, and the bucket counts and starts.  Buckets are tiles of tile[a] grid
+// cells per axis (at most 16 tiles per axis) in Morton order.  hist is zero between sweeps.
+constexpr int kGatherBuckets = 4096;
+struct GatherOrder {
+  int* key;     // [W N]
+  int* order;   // [W N]
+  int* hist;    // [kGatherBuckets]
+  int* offs;    // [kGatherBuckets]
+  int tile[3];
+};
+
 // Orbital gather: for every (walker, electron), either draw the proposal of
 // the sweep in *Wk.sweep_ctr and evaluate all orbitals there (mode 0, written
 // to the buffer that does not hold the current row), or evaluate at the
 // current position (mode 1, written to buffer 0 and cur reset).
 // lanes_log2: lanes per proposal (log2, 0..6); negative = the default for the orbital count.
 // sel (nullable): only the walkers w with sel[w] == sel_value are evaluated.
+// go (nullable, mode 0): evaluate the proposals in table order (same rows, fewer table misses).
 template <typename T>
 hipError_t launch_gather(const SysParams& P, const Walkers<T>& Wk, const T* table, int mode, hipStream_t st,
-                         int lanes_log2 = -1, const uint32_t* sel = nullptr, uint32_t sel_value = 0);
+                         int lanes_log2 = -1, const uint32_t* sel = nullptr, uint32_t sel_value = 0,
+                         const GatherOrder* go = nullptr);
 // Several systems' proposals in one launch; bmap[b] = (system, first item of block b).
 template <typename T>
 hipError_t launch_gather_batched(const SysDev<T>* sd, const int2* bmap, int n_blocks, hipStream_t st);
