@@ -27,6 +27,11 @@ METRIC = "electron-moves/sec (1 GPU) mixed vs FP64; p50/p99 sweep latency served
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, GB/s
 MFMA_FP32_TFLOPS = 157.3    # MI355X dense FP32 matrix peak
 MFMA_FP64_TFLOPS = 78.6     # MI355X dense FP64 matrix peak
+VALU_FP64_TFLOPS = 78.6     # MI355X FP64 vector peak (256 CUs x 4 SIMDs x 16 FMA lanes x 2 x 2.4 GHz)
+# FP64 FLOPs of one orbital's value, gradient and Laplacian at one point: per stencil row (16 of
+# them) three z sums of 1 multiply + 3 fused multiply-adds and five accumulations in 6 fused
+# multiply-adds, i.e. 33 FLOPs (a multiply-add counts 2)
+GATHER_FLOPS_PER_ORBITAL = 16 * (3 * (1 + 2 * 3) + 2 * 6)
 BOX_CPU_SHARE = 16          # host threads a one-GPU machine grants a process
 
 
@@ -207,11 +212,15 @@ def main(argv=None) -> int:
         wl.delay_rank = r["delay_rank"]
     W, N = r["walkers"], wl.n_elec
     kt = r["kt"]
-    b = wl.coefs.dtype.itemsize
-    bytes_per_move = 64 * wl.n_orb * b
     g_ms, g_n = kt["chain"] if pdrift else kt["gather"]   # drift sweeps read the table inside the chain
     avg_gather_s = g_ms / max(g_n, 1) / 1e3
-    achieved = bytes_per_move * W * N / avg_gather_s / 1e9
+    launches = ("alone (sweep and measurement calls in turn)" if args.serial else
+                "beside the previous step's local-energy kernels (--pipelined: shared compute units)")
+    g_roof = gather_roofline(wl, W, N, avg_gather_s,
+                             ("k_chain_drift (the whole sweep: the table reads of every move's row happen "
+                              "inside the chain, which is latency-bound)") if pdrift else
+                             "k_gather_ordered (tricubic B-spline VGL of every orbital at every proposal, "
+                             "in table order) with k_propose and the bucket sort", launches)
     line = {
         "metric": METRIC,
         "value": r["value"],
@@ -235,16 +244,7 @@ def main(argv=None) -> int:
                             "+ local energy" if pdrift else "1 sweep (N moves per walker) + local energy"),
                    "steps_run": "sweep and measurement calls in turn" if args.serial else
                    "pipelined (a step's measurement beside the next step's proposals)"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None if pdrift else measured_traffic(wl),
-                     "kernel": ("k_chain_drift (the whole sweep: the table reads of every move's row "
-                                "happen inside the chain, which is latency-bound)") if pdrift else
-                     "k_gather (proposal + tricubic B-spline VGL of every orbital)",
-                     "bytes_per_launch": bytes_per_move * W * N,
-                     "avg_launch_ms": avg_gather_s * 1e3,
-                     "launches": "alone (sweep and measurement calls in turn)" if args.serial else
-                     "beside the previous step's local-energy kernels (--pipelined: shared compute "
-                     "units and HBM)"},
+        "roofline": g_roof,
         "kernels_ms_per_step": {k: v[0] / r["steps"] for k, v in kt.items()},
         "kernels_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
         "rebuilds_in_timed_steps": r["rebuilds"],
@@ -252,8 +252,12 @@ def main(argv=None) -> int:
         "sweep_only_moves_per_s": r["sweep_only_moves_per_s"],
         "mean_local_energy": r["mean_local_energy"],
     }
+    line["roofline_gather"] = g_roof
     if not ae and not pdrift:
+        # the dominant kernel of the timed steps takes the roofline entry
         line["roofline_chain"] = chain_roofline(wl, r)
+        if kt["chain"][0] > kt["gather"][0]:
+            line["roofline"] = dict(line["roofline_chain"], dominant="move chain: the longest kernel of a step")
     headline = args.workload == "mixed384" and wl.precision == "mixed" and not ae and args.j3 is None
     if headline and not args.no_compare:
         line.update(fp64_beside(wl, r, serial=args.serial))
@@ -329,6 +333,27 @@ def run_single(wl, steps: int, warmup: int, delay, lanes=None, serial: bool = Fa
             "rebuilds": {"launches": rebuild[1], "ms_per_launch": rebuild[0] / max(rebuild[1], 1)},
             "delay_rank": K, "gather_lanes_log2": lanes_log2, "acceptance": acceptance, "sweep_only_moves_per_s": moves / (sweep_ms * steps / 1e3) if sweep_ms > 0 else None,
             "mean_local_energy": float(e_host.sum(axis=1).mean()), "energies": e_host, "positions": pos_host}
+
+
+def gather_roofline(wl, W, N, avg_s, kernel, launches=None):
+    """The gather against the FP64 vector peak.  Evaluated in table order, its table reads are
+    served by the caches (the HBM fetch per launch is a small fraction of the table bytes it
+    reads), and the FP64 sums of every orbital set its pace: algorithmic FLOPs per launch =
+    GATHER_FLOPS_PER_ORBITAL x n_orb x W N.  The table bytes each launch reads (64 n_orb b per
+    proposal) are reported beside, with their rate and the measured HBM traffic."""
+    b = wl.coefs.dtype.itemsize
+    flops = float(GATHER_FLOPS_PER_ORBITAL) * wl.n_orb * W * N
+    table_bytes = 64 * wl.n_orb * b * W * N
+    achieved = flops / avg_s / 1e12 if avg_s > 0 else 0.0
+    out = {"bound": "alu", "achieved": achieved, "peak": VALU_FP64_TFLOPS, "unit": "TFLOP/s",
+           "frac": achieved / VALU_FP64_TFLOPS, "traffic": measured_traffic(wl), "kernel": kernel,
+           "flops_per_launch": flops, "avg_launch_ms": avg_s * 1e3,
+           "table_bytes_per_launch": table_bytes,
+           "table_read_rate_GBs": table_bytes / avg_s / 1e9 if avg_s > 0 else 0.0,
+           "hbm_peak_GBs": HBM_PEAK_GBS}
+    if launches:
+        out["launches"] = launches
+    return out
 
 
 def chain_roofline(wl, r):
@@ -442,10 +467,8 @@ def bench_dmc(args) -> int:
     st = stats[:args.steps].cpu().numpy()
     s.close()
     moved = pop0 + st[:-1, 2].sum()   # walkers alive at the start of each timed step
-    b = wl.coefs.dtype.itemsize
     g_ms, g_n = kt["gather"]
     avg_gather_s = g_ms / max(g_n, 1) / 1e3
-    achieved = 64 * wl.n_orb * b * W * N / avg_gather_s / 1e9
     line = {
         "metric": METRIC + "; DMC mode",
         "value": moved * N / dt,
@@ -459,10 +482,9 @@ def bench_dmc(args) -> int:
                    "tau": wl.sigma ** 2, "feedback_hartree": 1.0, "gather_lanes_log2": lanes_log2,
                    "step": "1 DMC step: drift-diffusion all-electron move of every slot (fixed node), "
                            "local energies, weights, branching and copies on the device"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(wl),
-                     "kernel": "k_gather (proposal + tricubic B-spline VGL of every orbital)",
-                     "bytes_per_launch": 64 * wl.n_orb * b * W * N, "avg_launch_ms": avg_gather_s * 1e3},
+        "roofline": gather_roofline(wl, W, N, avg_gather_s,
+                                    "k_gather_ordered (tricubic B-spline VGL of every orbital at every "
+                                    "proposal, in table order) with k_propose and the bucket sort"),
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
         "population": {"start": pop0, "min": float(st[:, 2].min()), "max": float(st[:, 2].max())},
         "mixed_estimate_last": float(st[-1, 0]),

@@ -91,14 +91,6 @@ __device__ __forceinline__ void dsync() {
   else __syncthreads();
 }
 
-// Orders this wave's LDS writes before its later LDS reads (lanes read what
-// other lanes of the same wave wrote).
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-}
-
 __device__ __forceinline__ double readlane_d(double v, int l) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)b, l);

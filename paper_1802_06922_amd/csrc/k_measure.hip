@@ -102,9 +102,10 @@ __host__ __device__ inline MeasureLayout measure_layout(int N, int np) {
   MeasureLayout L;
   L.nloc = (N + np - 1) / np;
   // partners split so that the (electron, part) items fill the workgroup about four times
-  // over, with at most 1024 items (their partial sums are kept in LDS)
+  // over, with at most 512 items: their partial sums are kept in LDS, whose size sets how many
+  // workgroups share a compute unit (three at 384 electrons)
   int parts = 1;
-  while (parts * L.nloc < 4 * kBlock && parts * 2 * L.nloc <= 1024 && parts * 2 <= N) parts *= 2;
+  while (parts * L.nloc < 4 * kBlock && parts * 2 * L.nloc <= 512 && parts * 2 <= N) parts *= 2;
   L.parts = parts;
   size_t o = 0;
   L.pos = o; o += sizeof(double) * 3 * N;

@@ -19,6 +19,14 @@ constexpr double kPi = 3.14159265358979323846;
 // under them live in scalar registers, which leaves vector registers to the arrays.
 __device__ __forceinline__ int wave_of(int tid) { return __builtin_amdgcn_readfirstlane(tid >> 6); }
 
+// Orders this wave's LDS writes before its later LDS reads (lanes read what other lanes of the
+// same wave wrote).
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 // Radial function of a Jastrow term (section "Jastrow factors").
 struct Radial {
   int kind;          // QMC_J_NONE / PADE / BSPLINE
