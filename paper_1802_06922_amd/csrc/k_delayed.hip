@@ -39,9 +39,13 @@ constexpr int kMaxWindow = 64;
 constexpr int kLdsIonsD = 256;
 
 struct DLayout {
-  size_t pos, prop, ions, red, rmag, tn, vpre, gold, gdiff, cur, acc, plist, qlist, vwin, ywin, zwin, gx, gr, grow, b,
-      total;
+  size_t pos, prop, ions, red, jtab, rmag, tn, vpre, gold, gdiff, cur, acc, plist, qlist, vwin, ywin, zwin, gx, gr,
+      grow, b, total;
 };
+
+// Intervals of a B-spline radial function's coefficient table: the M intervals below the cutoff
+// and the one at it (a distance just below rc can round to t = M).
+constexpr int kJTabInt = QMC_MAX_KNOTS + 1;
 
 __host__ __device__ inline int round16(int x) { return (x + 15) & ~15; }
 
@@ -55,6 +59,7 @@ __host__ __device__ inline DLayout dlayout(int N, int nmax, int n_ions, int ldl,
   L.prop = o; o += sizeof(double) * 4 * nmax;
   L.ions = o; o += (n_ions <= kLdsIonsD) ? sizeof(double) * 4 * n_ions : 0;
   L.red = o; o += sizeof(double) * kBlock;
+  L.jtab = o; o += sizeof(double) * 3 * kJTabInt * 4;   // same-spin, opposite-spin, electron-ion
   L.rmag = o; o += (ts == 4) ? sizeof(double) * kBlock : 0;   // mixed: |v| . |B0[:, k]| partials
   L.tn = o; o += (ts == 4) ? sizeof(double) * kBlock : 0;     // mixed: |v^T B0|^2 partials
   al(16);
@@ -96,6 +101,30 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   const int lo = __builtin_amdgcn_readlane((int)b, l);
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// The polynomial of B-spline interval i of R in f = t - i (the coefficients of radial_value),
+// rounded one operation at a time.
+__device__ __forceinline__ void bspline_interval(const Radial& R, int i, double* c) {
+#pragma clang fp contract(off)
+  const double* p = R.p + i;
+  const double p0 = p[0], p1 = p[1], p2 = p[2], p3 = p[3];
+  c[0] = (p0 + 4.0 * p1 + p2) * (1.0 / 6.0);
+  c[1] = 0.5 * (p2 - p0);
+  c[2] = 0.5 * (p0 + p2) - p1;
+  c[3] = (p3 - p0) * (1.0 / 6.0) + 0.5 * (p1 - p2);
+}
+
+// u(r) of R with a B-spline's interval polynomials read from tab (kJTabInt x 4) instead of formed
+// from the control points at every call.
+__device__ __forceinline__ double radial_tab(const Radial& R, const double* tab, double r) {
+  if (R.kind != QMC_J_BSPLINE) return radial_value(R, r);
+  const bool in = r < R.rc;
+  const double t = in ? r * R.inv_delta : 0.0;
+  const double fl = floor(t);
+  const double* c = tab + 4 * (int)fl;
+  const double f = t - fl;
+  return in ? fma(f, fma(f, fma(f, c[3], c[2]), c[1]), c[0]) : 0.0;
 }
 
 __device__ __forceinline__ double ju(const Jastrow& J, int kind, double r) {
@@ -669,6 +698,11 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
     uint32_t* dst = reinterpret_cast<uint32_t*>(&sj);
     for (int q = tid; q < (int)(sizeof(Jastrow) / 4); q += kBlock) dst[q] = src[q];
   }
+  // the radial functions' interval polynomials (read after the barriers before the first window)
+  double* jtab = reinterpret_cast<double*>(smem + lay.jtab);
+  for (int t = tid; t < 3 * kJTabInt; t += kBlock)
+    bspline_interval(t < kJTabInt ? P.jas.same : (t < 2 * kJTabInt ? P.jas.opp : P.jas.ei), t % kJTabInt,
+                     jtab + 4 * t);
   for (int j = tid; j < 3 * N; j += kBlock) spos[j] = Wk.pos[(size_t)w * 3 * N + j];
   if (ions_lds)
     for (int j = tid; j < 4 * P.n_ions; j += kBlock) sion[j] = P.ions[j];
@@ -727,18 +761,18 @@ __device__ __forceinline__ void chain_delayed_walker(const SysParams& P, const W
           const double ox = spos[3 * iq], oy = spos[3 * iq + 1], oz = spos[3 * iq + 2];
           // partner ranges with one radial function each (no divergence between lanes):
           // same-spin electrons before and after the window, the other spin block, the ions
-          auto range = [&](const Radial& R, int lo, int hi, const double* c, int stride) {
+          auto range = [&](const Radial& R, const double* tab, int lo, int hi, const double* c, int stride) {
             for (int j = lo + s; j < hi; j += tpq) {
               const double* cj = c + (size_t)stride * j;
-              part += radial_value(R, dist(px, py, pz, cj[0], cj[1], cj[2], L, invL)) -
-                      radial_value(R, dist(ox, oy, oz, cj[0], cj[1], cj[2], L, invL));
+              part += radial_tab(R, tab, dist(px, py, pz, cj[0], cj[1], cj[2], L, invL)) -
+                      radial_tab(R, tab, dist(ox, oy, oz, cj[0], cj[1], cj[2], L, invL));
             }
           };
           const int ooff = up_block ? P.n_up : 0, no = up_block ? P.n_dn : P.n_up;
-          range(sj.same, off, off + k0, spos, 3);
-          range(sj.same, off + k0 + Kw, off + n, spos, 3);
-          range(sj.opp, ooff, ooff + no, spos, 3);
-          range(sj.ei, 0, P.n_ions, ions, 4);
+          range(sj.same, jtab, off, off + k0, spos, 3);
+          range(sj.same, jtab, off + k0 + Kw, off + n, spos, 3);
+          range(sj.opp, jtab + 4 * kJTabInt, ooff, ooff + no, spos, 3);
+          range(sj.ei, jtab + 8 * kJTabInt, 0, P.n_ions, ions, 4);
           if (P.j3_on) {
             // three-body terms with partners outside the window (in-window partners are pair
             // terms below), over the ions within the cutoff of r or r'
