@@ -590,7 +590,9 @@ static int lds_budget_rebuild() {
 // goes to the scratch buffer, X to the buffer the measurement reads (binv
 // itself is not changed, so a measurement never alters the chain).
 // ---------------------------------------------------------------------------
-constexpr int kTile = 64, kChunk = 32;
+// (16-wide k chunks: the staged panels take few registers, and the refinement runs four
+// workgroups per compute unit)
+constexpr int kTile = 64, kChunk = 16;
 constexpr int kLs = kChunk + 1;    // padded LDS row strides (fewer bank conflicts)
 constexpr int kRs = kTile + 2;
 constexpr int kPerThread = kTile * kChunk / kBlock;   // panel entries each thread stages
@@ -755,7 +757,7 @@ __device__ __forceinline__ void refine_spin(const SysParams& P, const Walkers<T>
 
 // sel (nullable): only the walkers with sel[w] == sel_value are refined.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_refine(SysParams P, Walkers<T> Wk, double* scratch,
+__global__ __launch_bounds__(kBlock, 4) void k_refine(SysParams P, Walkers<T> Wk, double* scratch,
                                                    const uint32_t* sel, uint32_t sel_value) {
   if (sel && sel[blockIdx.x >> 1] != sel_value) return;
   refine_spin<T>(P, Wk, scratch, blockIdx.x >> 1, blockIdx.x & 1);
