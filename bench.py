@@ -155,13 +155,14 @@ def main(argv=None) -> int:
                     help="all-electron proposal width (default: the workload's sigma / sqrt(N))")
     ap.add_argument("--pipelined", action="store_true",
                     help="single: pipelined steps (qmc_run_steps: a step's measurement on a side "
-                         "stream beside the next step's proposals) instead of the sweep and "
-                         "measurement calls in turn; at 384 electrons the overlap gains about 1%%, "
-                         "and the gather beside the measurement falls from 0.6 to 0.36 of the HBM peak")
+                         "stream beside the next step's proposals; the default)")
     ap.add_argument("--serial", action="store_true",
-                    help="single: sweep and measurement calls in turn (the default)")
+                    help="single: the sweep and measurement calls in turn (every kernel alone; at 384 "
+                         "electrons about 2%% fewer moves/s than the pipelined steps, and the gather "
+                         "alone instead of beside the measurement)")
     args = ap.parse_args(argv)
-    args.serial = not args.pipelined
+    if args.serial and args.pipelined:
+        ap.error("--serial and --pipelined exclude each other")
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(walkers would be sharded across GPUs with one energy reduction per block).",
