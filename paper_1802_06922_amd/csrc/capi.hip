@@ -819,9 +819,9 @@ static hipError_t fallback_check(qmc_system s, hipStream_t st, bool after_rebuil
   const bool beside = s->side && st == s->side;
   if (e == hipSuccess && !after_rebuild)
     e = launch_rebuild<float>(s->P, wk, s->scratch, nullptr, st, s->fbmark, 1u, beside);
-  if (e == hipSuccess) e = launch_fb_residual(s->P, wk, s->fbmark, st);
+  if (e == hipSuccess) e = launch_fb_residual(s->P, wk, s->scratch, s->fbmark, st);
   if (e == hipSuccess) e = launch_fb_decide(s->P, wk, s->fbmark, after_rebuild ? 0 : 1, st);
-  if (e == hipSuccess && !after_rebuild) e = launch_refine<float>(s->P, wk, s->scratch, st, s->fbmark, 3u);
+  if (e == hipSuccess && !after_rebuild) e = launch_fb_adopt(s->P, wk, s->fbmark, st);
   return e;
 }
 

@@ -830,7 +830,8 @@ hipError_t launch_fb_mark(int W, const double* eta, const int* fb, uint32_t* mar
 
 // eta[w] = ||I - A fl32(B64)||_F and ||B64||_F per spin for the walkers with mark 1 or 2: the
 // error an FP32 copy of the FP64 inverse would start from (FP64 products, A = the FP64 rows).
-__global__ __launch_bounds__(kBlock) void k_fb_residual(SysParams P, Walkers<float> Wk, const uint32_t* mark) {
+__global__ __launch_bounds__(kBlock) void k_fb_residual(SysParams P, Walkers<float> Wk, double* scratch,
+                                                        const uint32_t* mark) {
   __shared__ double sL[kTile * kLs];
   __shared__ double sR[kChunk * kRs];
   __shared__ const double* arow[kMaxSpin];
@@ -843,10 +844,10 @@ __global__ __launch_bounds__(kBlock) void k_fb_residual(SysParams P, Walkers<flo
     if (tid == 0) Wk.eta[4 * w + sp] = Wk.eta[4 * w + 2 + sp] = 0.0;
     return;
   }
-  // a fresh FP32 rounding errs about evenly in every column
-  for (int k = tid; k < n; k += kBlock) Wk.ecol[(size_t)w * P.N + off + k] = 0.0f;
   const int N = P.N;
-  const double* B = Wk.binv64 + (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0);
+  const size_t boff = (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0);
+  const double* B = Wk.binv64 + boff;
+  float* E = reinterpret_cast<float*>(scratch + boff);
   for (int i = tid; i < n; i += kBlock) {
     const size_t item = (size_t)w * N + off + i;
     arow[i] = Wk.val64 + ((size_t)Wk.cur[item] * P.W * N + item) * P.S;
@@ -858,7 +859,19 @@ __global__ __launch_bounds__(kBlock) void k_fb_residual(SysParams P, Walkers<flo
          [&](int i, int k, double c) {
            const double e = (i == k ? 1.0 : 0.0) - c;
            e2 += e * e;
+           E[(size_t)i * n + k] = (float)e;
          }, sL, sR);
+  __syncthreads();   // E complete before its columns are read
+  // each column's residual norm: the guard band of the next sweep's ratios for a walker that goes
+  // on from this FP32 copy (the same numbers a refinement of it would record)
+  for (int k = tid; k < n; k += kBlock) {
+    double c2 = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double e = (double)E[(size_t)i * n + k];
+      c2 += e * e;
+    }
+    Wk.ecol[(size_t)w * N + off + k] = (float)sqrt(c2);
+  }
   for (int q = tid; q < n * n; q += kBlock) b2 += B[q] * B[q];
   e2 = block_sum(e2, red);
   b2 = block_sum(b2, red);
@@ -868,9 +881,10 @@ __global__ __launch_bounds__(kBlock) void k_fb_residual(SysParams P, Walkers<flo
   }
 }
 
-hipError_t launch_fb_residual(const SysParams& P, const Walkers<float>& Wk, const uint32_t* mark, hipStream_t st) {
-  if (P.n_up > kMaxSpin || P.n_dn > kMaxSpin || !Wk.binv64 || !Wk.eta) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_fb_residual, dim3(2 * P.W), dim3(kBlock), 0, st, P, Wk, mark);
+hipError_t launch_fb_residual(const SysParams& P, const Walkers<float>& Wk, double* scratch, const uint32_t* mark,
+                              hipStream_t st) {
+  if (P.n_up > kMaxSpin || P.n_dn > kMaxSpin || !Wk.binv64 || !Wk.eta || !Wk.ecol) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_fb_residual, dim3(2 * P.W), dim3(kBlock), 0, st, P, Wk, scratch, mark);
   return hipGetLastError();
 }
 
@@ -899,6 +913,23 @@ __global__ __launch_bounds__(kBlock) void k_fb_decide(SysParams P, Walkers<float
 
 hipError_t launch_fb_decide(const SysParams& P, const Walkers<float>& Wk, uint32_t* mark, int early, hipStream_t st) {
   hipLaunchKernelGGL(k_fb_decide, dim3(P.W), dim3(kBlock), 0, st, P, Wk, mark, early);
+  return hipGetLastError();
+}
+
+// A walker back in FP32 after a check (mark 3) goes on from binv = fl32(B64), a fresh rounding of
+// an FP64 inverse, which a refinement (itself stored in FP32) would not improve: the measurement
+// reads that copy, and k_fb_residual has recorded its residuals.
+__global__ __launch_bounds__(kBlock) void k_fb_adopt(SysParams P, Walkers<float> Wk, const uint32_t* mark) {
+  const int w = blockIdx.x;
+  if (mark[w] != 3u) return;
+  const size_t off = (size_t)w * P.bstride;
+  const int nb = P.n_up * P.n_up + P.n_dn * P.n_dn;
+  for (int q = threadIdx.x; q < nb; q += kBlock) Wk.xinv[off + q] = Wk.binv[off + q];
+}
+
+hipError_t launch_fb_adopt(const SysParams& P, const Walkers<float>& Wk, const uint32_t* mark, hipStream_t st) {
+  if (!Wk.xinv) return hipSuccess;
+  hipLaunchKernelGGL(k_fb_adopt, dim3(P.W), dim3(kBlock), 0, st, P, Wk, mark);
   return hipGetLastError();
 }
 

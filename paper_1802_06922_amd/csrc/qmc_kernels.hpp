@@ -131,11 +131,14 @@ hipError_t launch_init_positions(const SysParams& P, double* pos, hipStream_t st
 
 // Mixed precision, FP64 fallback of ill-conditioned walkers (k_linalg.hip): mark[w] from the
 // measured inverse errors (all != 0: every walker, after a full rebuild); the FP32 rounding
-// residual of binv64 for the walkers with mark 1 or 2; the decision, which copies binv =
-// fl32(binv64) for walkers returning to FP32 and leaves them mark 3 (refinement due).
+// residual of binv64 for the walkers with mark 1 or 2 (its norm and each column's, with E in
+// scratch); the decision, which copies binv = fl32(binv64) for walkers returning to FP32 and
+// leaves them mark 3; for those, the measurement's inverse xinv = binv.
 hipError_t launch_fb_mark(int W, const double* eta, const int* fb, uint32_t* mark, int all, hipStream_t st);
-hipError_t launch_fb_residual(const SysParams& P, const Walkers<float>& Wk, const uint32_t* mark, hipStream_t st);
+hipError_t launch_fb_residual(const SysParams& P, const Walkers<float>& Wk, double* scratch, const uint32_t* mark,
+                              hipStream_t st);
 hipError_t launch_fb_decide(const SysParams& P, const Walkers<float>& Wk, uint32_t* mark, int early, hipStream_t st);
+hipError_t launch_fb_adopt(const SysParams& P, const Walkers<float>& Wk, const uint32_t* mark, hipStream_t st);
 
 // Full FP64 inverse of every Slater matrix from the current value rows
 // (Gauss-Jordan with partial pivoting); scratch: W * bstride doubles.
