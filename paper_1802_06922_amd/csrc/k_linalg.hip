@@ -724,7 +724,8 @@ __device__ __forceinline__ void refine_spin(const SysParams& P, const Walkers<T>
   if (Wk.ecol)   // each column's residual norm, for the guard band of the next sweep's ratios
     for (int k = threadIdx.x; k < n; k += kBlock) {
       double c2 = 0.0;
-      for (int i = 0; i < n; ++i) {
+#pragma unroll 8
+      for (int i = 0; i < n; ++i) {   // (unrolled: eight loads in flight, the sum still in order)
         const double e = (double)E[(size_t)i * n + k];
         c2 += e * e;
       }
@@ -866,7 +867,8 @@ __global__ __launch_bounds__(kBlock) void k_fb_residual(SysParams P, Walkers<flo
   // on from this FP32 copy (the same numbers a refinement of it would record)
   for (int k = tid; k < n; k += kBlock) {
     double c2 = 0.0;
-    for (int i = 0; i < n; ++i) {
+#pragma unroll 8
+    for (int i = 0; i < n; ++i) {   // (unrolled: eight loads in flight, the sum still in order)
       const double e = (double)E[(size_t)i * n + k];
       c2 += e * e;
     }

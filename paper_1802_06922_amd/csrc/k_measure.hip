@@ -216,8 +216,26 @@ __device__ __forceinline__ void measure_part(const SysParams& P, const Walkers<T
     const T* row = Wk.vgl + ((size_t)Wk.cur[item] * P.W * N + item) * kComp * P.S;
     const T* B = (Wk.xinv ? Wk.xinv : Wk.binv) + (size_t)w * P.bstride + (sp ? (size_t)P.n_up * P.n_up : 0) + k;
     double gx = 0.0, gy = 0.0, gz = 0.0, l2 = 0.0;
-#pragma unroll 4
-    for (int l = 0; l < n; ++l) {
+    // the row read in 16-byte vectors (S and the rows are 16-byte aligned): every lane reads its
+    // own row, so each load instruction touches one line per lane whatever its width
+    constexpr int V = 16 / sizeof(T);
+    typedef T vec_t __attribute__((ext_vector_type(V)));
+    const int nv = n - n % V;
+    for (int l0 = 0; l0 < nv; l0 += V) {
+      const vec_t rx = *reinterpret_cast<const vec_t*>(row + P.S + l0);
+      const vec_t ry = *reinterpret_cast<const vec_t*>(row + 2 * P.S + l0);
+      const vec_t rz = *reinterpret_cast<const vec_t*>(row + 3 * P.S + l0);
+      const vec_t rl = *reinterpret_cast<const vec_t*>(row + 4 * P.S + l0);
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const double b = (double)B[(size_t)(l0 + e) * n];
+        gx += b * (double)rx[e];
+        gy += b * (double)ry[e];
+        gz += b * (double)rz[e];
+        l2 += b * (double)rl[e];
+      }
+    }
+    for (int l = nv; l < n; ++l) {
       const double b = (double)B[(size_t)l * n];
       gx += b * (double)row[P.S + l];
       gy += b * (double)row[2 * P.S + l];
