@@ -691,7 +691,7 @@ __device__ __forceinline__ void refine_spin(const SysParams& P, const Walkers<T>
                                             int sp) {
   __shared__ double sL[kTile * kLs];
   __shared__ double sR[kChunk * kRs];
-  __shared__ const double* arow[kMaxSpin];
+  __shared__ size_t arow[kMaxSpin];   // row offsets in val64 (not pointers: the loads stay global, not flat)
   __shared__ double red[kWaves];
   const int n = sp ? P.n_dn : P.n_up, off = sp ? P.n_up : 0;
   if (Wk.fb && Wk.fb[w]) return;   // an FP64 fallback walker is measured on its FP64 inverse
@@ -707,13 +707,13 @@ __device__ __forceinline__ void refine_spin(const SysParams& P, const Walkers<T>
   float* E = reinterpret_cast<float*>(scratch + boff);
   for (int i = threadIdx.x; i < n; i += kBlock) {
     const size_t item = (size_t)w * N + off + i;
-    arow[i] = Wk.val64 + ((size_t)Wk.cur[item] * P.W * N + item) * P.S;
+    arow[i] = ((size_t)Wk.cur[item] * P.W * N + item) * P.S;
   }
   __syncthreads();
   // E = I - A B in FP64 (A B is the identity up to ~1e-6: the difference needs FP64 products);
   // E itself is small and is kept in FP32
   double e2 = 0.0, x2 = 0.0;   // ||E||_F^2 and ||X||_F^2 partials (the guard band's inverse error)
-  gemm64(n, [&](int i, int l) { return arow[i][l]; },
+  gemm64(n, [&](int i, int l) { return Wk.val64[arow[i] + l]; },
          [&](int l, int k) { return (double)B[(size_t)l * n + k]; },
          [&](int i, int k, double c) {
            const double e = (i == k ? 1.0 : 0.0) - c;
@@ -835,7 +835,7 @@ __global__ __launch_bounds__(kBlock) void k_fb_residual(SysParams P, Walkers<flo
                                                         const uint32_t* mark) {
   __shared__ double sL[kTile * kLs];
   __shared__ double sR[kChunk * kRs];
-  __shared__ const double* arow[kMaxSpin];
+  __shared__ size_t arow[kMaxSpin];   // row offsets in val64 (not pointers: the loads stay global, not flat)
   __shared__ double red[kWaves];
   const int w = blockIdx.x >> 1, sp = blockIdx.x & 1, tid = threadIdx.x;
   if (mark[w] != 1u && mark[w] != 2u) return;
@@ -851,11 +851,11 @@ __global__ __launch_bounds__(kBlock) void k_fb_residual(SysParams P, Walkers<flo
   float* E = reinterpret_cast<float*>(scratch + boff);
   for (int i = tid; i < n; i += kBlock) {
     const size_t item = (size_t)w * N + off + i;
-    arow[i] = Wk.val64 + ((size_t)Wk.cur[item] * P.W * N + item) * P.S;
+    arow[i] = ((size_t)Wk.cur[item] * P.W * N + item) * P.S;
   }
   __syncthreads();
   double e2 = 0.0, b2 = 0.0;
-  gemm64(n, [&](int i, int l) { return arow[i][l]; },
+  gemm64(n, [&](int i, int l) { return Wk.val64[arow[i] + l]; },
          [&](int l, int k) { return (double)(float)B[(size_t)l * n + k]; },
          [&](int i, int k, double c) {
            const double e = (i == k ? 1.0 : 0.0) - c;
