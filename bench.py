@@ -63,10 +63,11 @@ def source_hash(files) -> str:
     return m.hexdigest()[:16]
 
 
-def measured_traffic(wl):
-    """HBM bytes per gather launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE runs,
-    scaled by a plain copy's counter readings; None once the kernel source has changed."""
-    path = os.path.join(ROOT, "profiles", f"gather_traffic_{wl.name}.json")
+def measured_traffic(wl, kernel: str = "gather"):
+    """HBM bytes per launch of the gather (or of the move chain, kernel="chain") from the
+    committed rocprofv3 FETCH_SIZE/WRITE_SIZE runs, scaled by a plain copy's counter readings;
+    None where none was taken or once the kernel's sources have changed."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic_{wl.name}.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
@@ -362,7 +363,8 @@ def chain_roofline(wl, r):
     launch: per walker and spin block of n electrons, the window products Y = V B0 (2 n^3 over
     a sweep) and the rank-m flushes (2 n^2 per accepted move), i.e. 2 W sum_spin n^3 (1 + a) at
     acceptance a; the inverse itself moves 2 n^2 b bytes per spin and walker when the chain
-    keeps it on chip for the sweep (read once, written once)."""
+    keeps it on chip for the sweep (read once, written once), and the proposals' value rows
+    n^2 b more."""
     kt = r["kt"]
     c_ms, c_n = kt["chain"]
     avg_s = c_ms / max(c_n, 1) / 1e3
@@ -373,10 +375,11 @@ def chain_roofline(wl, r):
     peak = MFMA_FP32_TFLOPS if b == 4 else MFMA_FP64_TFLOPS
     achieved = flops / avg_s / 1e12 if avg_s > 0 else 0.0
     return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": None,
+            "frac": achieved / peak, "traffic": measured_traffic(wl, "chain"),
             "kernel": "move chain (ratios, Jastrow, decisions, delayed-update products)",
             "flops_per_launch": flops, "avg_launch_ms": avg_s * 1e3, "delay_rank": r["delay_rank"],
             "inverse_bytes_per_launch": 2 * W * (wl.n_up ** 2 + wl.n_dn ** 2) * b,
+            "row_bytes_per_launch": W * (wl.n_up ** 2 + wl.n_dn ** 2) * b,
             "note": "sequential per walker (each move depends on the previous decision): the matrix "
                     "cores are busy only in the window products and flushes"}
 
